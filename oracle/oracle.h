@@ -1,0 +1,91 @@
+/*
+ * CPU oracle for the plateau-reduced gradient estimator (Fischer & Ritschel,
+ * "Plateau-reduced Differentiable Path Tracing", CVPR 2023).
+ *
+ * TEST INFRASTRUCTURE.  Only the test-suite, the smoke check and the CPU-baseline
+ * leg of the benchmark load this library.  It shares no code with the HIP path.
+ *
+ * Numerics: per-sample geometry and radiance are evaluated in IEEE binary32 with
+ * a fixed operation order and no contraction, because the hit tests decide which
+ * primitive a ray hits (an integer) and that decision is taken in the precision
+ * of the GPU path.  Pixel averages, image losses and the gradient combination are
+ * accumulated in binary64.
+ */
+#ifndef PRDPT_ORACLE_H
+#define PRDPT_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { ORC_DIFFUSE = 0, ORC_DIELECTRIC = 1, ORC_EMISSIVE = 2 };
+enum { ORC_BIND_SPHERE = 0, ORC_BIND_QUAD = 1, ORC_BIND_MESH = 2, ORC_BIND_PLIGHT = 3 };
+enum { ORC_EST_GAUSS = 0, ORC_EST_IS = 1, ORC_EST_IS_PERDIM = 2 };
+enum { ORC_TAG_TAU = 1, ORC_TAG_PATH = 2, ORC_TAG_REF = 3 };
+
+/* Scene as flat arrays; the oracle copies everything it needs. */
+typedef struct {
+  float eye[3], fwd[3], right[3], up[3];
+  int32_t width, height, spp, max_bounces, pixel_center;
+  float env[3];
+  int32_t n_mat;   const int32_t* mat_type; const float* mat_rgb; const float* mat_ior;
+  int32_t n_sph;   const float* sph;  const int32_t* sph_mat;      /* [n][4] cx cy cz r */
+  int32_t n_quad;  const float* quad; const int32_t* quad_mat;     /* [n][9] o e1 e2 */
+  int32_t n_mesh;  const int32_t* mesh_off; const int32_t* mesh_mat; const float* mesh_xlate;
+  int32_t n_tri;   const float* tri;                               /* [n][9] v0 v1 v2 */
+  int32_t n_plight; const float* plight;                           /* [n][6] pos rgb */
+  int32_t n_param; const int32_t* binding;                         /* [d][3] */
+} orc_scene_in;
+
+typedef struct orc_scene orc_scene;
+
+/* counter-based generator and sample transforms */
+void  orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+float orc_u01(uint32_t x);
+float orc_ln(float x);
+void  orc_sincos_2pi(float u, float* s, float* c);
+double orc_chi_mean(int d);
+
+/* perturbation draw: tau[P][d] (binary32) and pair weights c[P][d] (binary64) */
+int orc_draw_tau(int mode, int d, int P, uint64_t seed, const float* sigma,
+                 float* tau, double* c);
+/* g_j = (1/P) sum_p c[p][j] (L[2p] - L[2p+1]);  q = mean of L over 2P */
+void orc_combine(int P, int d, const double* c, const double* L, double* g, double* q);
+
+/* scene */
+orc_scene* orc_scene_new(const orc_scene_in* in);
+void orc_scene_free(orc_scene* s);
+void orc_set_brute_force(orc_scene* s, int on);
+/* closest hit of n rays (o, d): t (inf on miss) and primitive id (-1) at params X */
+void orc_trace(const orc_scene* s, const float* X, int n, const float* o, const float* d,
+               float* t_out, int32_t* id_out);
+/* render the full image at params X with stream tag/pair/seed -> img[H][W][3] */
+void orc_render(const orc_scene* s, const float* X, int tag, int pair, uint64_t seed,
+                int nthreads, float* img);
+/* render listed pixels (index y*W+x) -> out[n][3] */
+void orc_render_pixels(const orc_scene* s, const float* X, int tag, int pair, uint64_t seed,
+                       int n, const int32_t* pix, int nthreads, float* out);
+double orc_mse(const float* img, const float* ref, int npix);
+
+/* estimator: returns 0, or -1 on invalid arguments */
+int orc_grad_estimate(const orc_scene* s, const float* ref, const float* theta,
+                      const float* sigma, int N, uint64_t seed, int mode, int nthreads,
+                      double* grad, double* loss, double* losses, float* tau);
+int orc_smoothed_loss(const orc_scene* s, const float* ref, const float* theta,
+                      const float* sigma, int N, uint64_t seed, int nthreads, double* loss);
+int orc_render_perturbed(const orc_scene* s, const float* theta, const float* sigma, int N,
+                         uint64_t seed, int mode, int nthreads, float* images, float* tau);
+
+/* dielectric helper exposed for closed-form checks */
+float orc_fresnel(float cos_i, float eta_i, float eta_t);
+
+/* optimiser helpers (host-side step of the optimisation loop) */
+double orc_sigma_schedule(double sigma0, double sigma_end, int t, int T);
+void orc_adam_step(int d, double* theta, const double* g, double* m, double* v, int t,
+                   double lr, double b1, double b2, double eps);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,197 @@
+"""Pins of the oracle's path tracer: closed forms, analytic geometry, brute force,
+and the end-to-end estimator against quadrature plus finite differences."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2211_17263_amd import scenes as S
+
+
+def camera_rays_f64(sc):
+    """Pixel-centre camera rays in binary64 from the scene's binary32 camera vectors."""
+    W, H = sc.width, sc.height
+    x, y = np.meshgrid(np.arange(W) + 0.5, np.arange(H) + 0.5)
+    sx = 2.0 * x / W - 1.0
+    sy = 1.0 - 2.0 * y / H
+    f, r, u = (np.asarray(v, np.float64) for v in (sc.fwd, sc.right, sc.up))
+    d = f[None, None, :] + sx[..., None] * r[None, None, :] + sy[..., None] * u[None, None, :]
+    d /= np.linalg.norm(d, axis=-1, keepdims=True)
+    return np.asarray(sc.eye, np.float64), d
+
+
+def ray_sphere(o, d, c, r):
+    oc = o - c
+    b = (oc * d).sum(-1)
+    cc = (oc * oc).sum() - r * r
+    disc = b * b - cc
+    t = np.where(disc >= 0, -b - np.sqrt(np.maximum(disc, 0)), np.inf)
+    return t, disc
+
+
+@pytest.mark.parametrize("albedo", [0.25, 0.6, 0.9])
+def test_white_furnace(albedo):
+    # convex diffuse sphere under unit environment: sphere pixels equal the
+    # albedo, background pixels equal 1, with zero variance
+    sc = S.furnace_scene(albedo=albedo, spp=3, bounces=3)
+    sc.pixel_center = 1
+    img = O.OracleScene(sc).render([], seed=9)
+    o, d = camera_rays_f64(sc)
+    t, disc = ray_sphere(o, d, np.zeros(3), 0.8)
+    hit = disc > 1e-4
+    miss = disc < -1e-4
+    a32 = np.float32(albedo)
+    assert np.all(img[hit] == a32)
+    assert np.all(img[miss] == 1.0)
+    assert hit.sum() > 50 and miss.sum() > 50
+
+
+def test_lambertian_plane_point_light():
+    # radiance = (rho/pi) I h / r^3 for pixel-centre rays, direct lighting only
+    sc = S.plane_scene()
+    img = O.OracleScene(sc).render([])
+    o, d = camera_rays_f64(sc)
+    t = -o[2] / d[..., 2]
+    p = o[None, None, :] + t[..., None] * d
+    lpos = np.array(sc.plights[0][:3], np.float64)
+    I = sc.plights[0][3]
+    rho = sc.mat_rgb[0][0]
+    v = lpos[None, None, :] - p
+    r = np.linalg.norm(v, axis=-1)
+    L = rho / math.pi * I * lpos[2] / r**3
+    np.testing.assert_allclose(img[..., 0], L, rtol=2e-5)
+    np.testing.assert_allclose(img[..., 1], img[..., 0], rtol=0)
+
+
+def test_shadow_boundary_against_analytic_geometry():
+    # toy scene at a fixed sphere position, pixel-centre rays, direct light only:
+    # every pixel classified analytically (binary64) as sphere / lit plane /
+    # shadowed plane must agree with the render, except within a thin margin
+    sc = S.toy_scene(pixel_center=1)
+    X = np.array([0.35, -0.25], np.float32)
+    img = O.OracleScene(sc).render(X)
+    o, d = camera_rays_f64(sc)
+    c = np.array([0.35, -0.25, 0.5], np.float64)
+    r = 0.5
+    t_s, disc = ray_sphere(o, d, c, r)
+    lpos = np.array(sc.plights[0][:3], np.float64)
+    on_sphere = disc > 1e-3
+    on_plane = disc < -1e-3
+    tp = -o[2] / d[..., 2]
+    p = o[None, None, :] + tp[..., None] * d
+    # segment plane point -> light against the sphere
+    L = lpos[None, None, :] - p
+    dist = np.linalg.norm(L, axis=-1)
+    Ld = L / dist[..., None]
+    oc = p - c
+    b = (oc * Ld).sum(-1)
+    cc = (oc * oc).sum(-1) - r * r
+    disc2 = b * b - cc
+    shadowed = (disc2 > 1e-3) & (-b - np.sqrt(np.maximum(disc2, 0)) > 0)
+    lit = (disc2 < -1e-3) | ((disc2 > 1e-3) & (-b + np.sqrt(np.maximum(disc2, 0)) < 0))
+    v = img[..., 0]
+    assert np.all(v[on_plane & shadowed] == 0.0)
+    assert np.all(v[on_plane & lit] > 0.0)
+    # sphere points facing the light are lit
+    ps = o[None, None, :] + t_s[..., None] * d
+    n = (ps - c) / r
+    facing = ((lpos[None, None, :] - ps) * n).sum(-1)
+    assert np.all(v[on_sphere & (facing > 1e-3)] > 0.0)
+    assert np.all(v[on_sphere & (facing < -1e-3)] == 0.0)
+    assert (on_plane & shadowed).sum() > 20
+
+
+def test_bvh_closest_hit_equals_brute_force():
+    rng = np.random.default_rng(3)
+    sc = S.toy_scene()
+    v, f = S.random_triangles(rng, 3000, (-1, -1, 0.2), (1, 1, 1.5), 0.08)
+    m = sc.mesh(v, f, 0, translation=(0.1, -0.05, 0.0))
+    sc.bind(S.BIND_MESH, m, 2)
+    X = np.array([0.2, 0.1, 0.05], np.float32)
+    fast = O.OracleScene(sc)
+    slow = O.OracleScene(sc, brute_force=True)
+    n = 20000
+    o = np.tile(np.array([0.0, 0.0, 5.0], np.float32), (n, 1)) + rng.normal(0, 0.3, (n, 3)).astype(np.float32)
+    tgt = rng.uniform(-1.2, 1.2, (n, 3)).astype(np.float32)
+    tgt[:, 2] = rng.uniform(0, 1.5, n)
+    d = (tgt - o)
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    t1, i1 = fast.trace(X, o, d.astype(np.float32))
+    t2, i2 = slow.trace(X, o, d.astype(np.float32))
+    assert np.array_equal(i1, i2)
+    assert np.array_equal(t1, t2)
+    assert (i1 >= 3).sum() > 1000          # many triangle hits (ids after sphere and quad)
+
+
+def test_fresnel_special_values():
+    n = 1.5
+    assert abs(O.fresnel(1.0, 1.0, n) - ((n - 1) / (n + 1)) ** 2) < 1e-7          # 0.04
+    thb = math.atan(n)                                                              # Brewster
+    rs2 = ((n * n - 1) / (n * n + 1)) ** 2
+    assert abs(O.fresnel(math.cos(thb), 1.0, n) - 0.5 * rs2) < 2e-6
+    crit = math.asin(1 / n)
+    assert O.fresnel(math.cos(crit + 0.01), n, 1.0) == 1.0                          # TIR
+    assert O.fresnel(math.cos(crit - 0.05), n, 1.0) < 1.0
+    assert abs(O.fresnel(1e-6, 1.0, n) - 1.0) < 1e-4                                # grazing
+
+
+def test_glass_furnace_energy():
+    # a dielectric sphere under unit environment neither absorbs nor emits: every
+    # path that escapes within the bounce cap returns 1
+    sc = S.furnace_scene(glass=True, bounces=12, spp=32, width=24, height=24)
+    img = O.OracleScene(sc).render([], seed=4)
+    assert img.max() <= 1.0
+    assert img.mean() > 1.0 - 2e-3
+
+
+def test_render_is_deterministic_and_thread_independent():
+    pr = S.cornell_problem(width=48, height=48, spp=2, ico_level=2)
+    sc = O.OracleScene(pr["scene"])
+    a = sc.render(pr["theta0"], seed=5, nthreads=1)
+    b = sc.render(pr["theta0"], seed=5, nthreads=4)
+    assert np.array_equal(a, b)
+    c = sc.render(pr["theta0"], seed=5, pair=1)
+    assert not np.array_equal(a, c)
+    r = sc.reference(pr["theta0"], seed=5)
+    assert not np.array_equal(a, r)
+    pix = np.array([0, 17, 48 * 20 + 7, 48 * 48 - 1], np.int32)
+    np.testing.assert_array_equal(sc.render_pixels(pr["theta0"], pix, seed=5), a.reshape(-1, 3)[pix])
+
+
+def test_estimator_against_quadrature_and_finite_differences():
+    # One-parameter toy scene (sphere x), pixel-centre rays, direct light: the
+    # render is deterministic, so Q(theta) = int kappa(x - theta) L(x) dx.  Q is
+    # evaluated by a trapezoid rule on a fixed x grid, its derivative by central
+    # differences (h = 1e-3); the estimator mean must match within 4 SE plus the
+    # quadrature error.
+    sc = S.toy_scene(width=32, height=32, pixel_center=1)
+    sc.bindings = sc.bindings[:1]
+    osc = O.OracleScene(sc)
+    ref = osc.render(np.array([0.0], np.float32))
+    theta, sigma = 0.45, 0.3
+
+    def dQ(dx):
+        xs = np.arange(theta - 6 * sigma, theta + 6 * sigma + dx / 2, dx).astype(np.float32)
+        L = np.array([O.mse(osc.render(np.array([x], np.float32)), ref) for x in xs])
+        x64 = xs.astype(np.float64)
+
+        def Q(th):
+            k = np.exp(-0.5 * ((x64 - th) / sigma) ** 2) / (sigma * math.sqrt(2 * math.pi))
+            return np.trapezoid(k * L, x64)
+        h = 1e-3
+        return (Q(theta + h) - Q(theta - h)) / (2 * h)
+
+    fine, coarse = dQ(1e-3), dQ(2e-3)
+    quad_err = abs(fine - coarse)
+    sig32 = np.array([sigma], np.float32)
+    th32 = np.array([theta], np.float32)
+    for mode in (O.IS, O.GAUSS):
+        P = 3000
+        r = osc.grad_estimate(ref, th32, sig32, 2 * P, 77, mode)
+        _, c = O.draw_tau(mode, sig32, P, 77)
+        terms = c[:, 0] * (r["losses"][0::2] - r["losses"][1::2])
+        se = terms.std(ddof=1) / math.sqrt(P)
+        assert abs(r["grad"][0] - terms.mean()) < 1e-12
+        assert abs(r["grad"][0] - fine) <= 4 * se + quad_err, (mode, r["grad"], fine, se, quad_err)
+        assert abs(fine) > 6 * se     # the check has power: the gradient is not ~0
