@@ -1,0 +1,229 @@
+/*
+ * prdpt.h — C ABI of the MI355X (gfx950) plateau-reduced gradient estimator.
+ *
+ * The library evaluates, on one GPU, the Monte Carlo gradient of the
+ * kernel-smoothed inverse-rendering objective of Fischer & Ritschel,
+ * "Plateau-reduced Differentiable Path Tracing" (CVPR 2023):
+ *
+ *     Q(theta)   = integral kappa_sigma(tau) L(theta + tau) dtau            (Sec. 3.1, Eq. 6)
+ *     grad Q     ~ (1/N) sum_i dkappa/dtheta(tau_i) L(theta - tau_i)          (Sec. 3.1, Eq. 10)
+ *     L(theta)   = mean over pixels and RGB of (I_theta - R)^2               (Sec. 2.1, Eq. 2; Sec. 4.1 MSE)
+ *
+ * with a Gaussian kernel kappa = N(0, diag sigma^2) (supplement, kernel
+ * definition), antithetic pairs tau / -tau and importance sampling of the
+ * positivised kernel derivative (Sec. 3.2).  The renderer I_theta is this
+ * library's own path tracer, treated by the estimator as a black box, as the
+ * paper treats its renderer (Sec. 3.1, "if P is not differentiable").
+ *
+ * Conventions for every call:
+ *   - Status codes: PRDPT_OK (0) or a negative PRDPT_E_* value.  Nothing throws
+ *     across the ABI.  prdpt_last_error() returns a thread-local message for
+ *     the last failing call on the calling thread.
+ *   - N is the number of perturbed renders, 2 x (antithetic pairs); it must be
+ *     even and >= 2.  Perturbation index k = 2p + m: m = 0 renders theta + tau_p,
+ *     m = 1 renders theta - tau_p; both share the pair's path-sample stream.
+ *   - theta and sigma have length d = the scene's parameter count; sigma_j > 0.
+ *   - "host" pointers are ordinary CPU memory, "device" pointers are HIP device
+ *     memory of the context's device.  Outputs are owned by the caller.
+ *   - Results are a pure function of (scene description, ref, theta, sigma, N,
+ *     seed, est): they do not depend on the context, the stream, batching or
+ *     device load.
+ *   - A context binds one device and one HIP stream; calls on one context are
+ *     serialised by the library; calls on different contexts may run from
+ *     different threads.
+ */
+#ifndef PRDPT_H
+#define PRDPT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------- */
+#define PRDPT_OK 0
+#define PRDPT_E_ARG (-1)       /* null pointer, odd/small N, sigma <= 0, size 0, bad mode */
+#define PRDPT_E_NOMEM (-2)     /* device or host allocation failed */
+#define PRDPT_E_ADMISSION (-3) /* the scene does not fit the context's HBM budget */
+#define PRDPT_E_HIP (-4)       /* a HIP runtime call failed */
+#define PRDPT_E_SCENE (-5)     /* invalid scene description */
+#define PRDPT_E_CANCELLED (-6) /* request cancelled before it ran */
+#define PRDPT_E_TIMEOUT (-7)   /* request did not finish within its deadline */
+
+/* ---- estimator modes (Sec. 3.2) ------------------------------------------ */
+/* GAUSS: tau ~ kappa, pair weight z_j / (2 sigma_j); unbiased for grad Q.      */
+/* IS: importance sampling of |grad kappa|: radius chi_{d+1}, uniform direction */
+/*     (d = 1: the paper's inverse CDF sqrt(-2 sigma^2 ln xi)); pair weight     */
+/*     C_d u_j / (2 sigma_j), C_d = mean of chi_d; unbiased for grad Q.         */
+/* IS_PERDIM: independent two-sided Rayleigh per axis (literal per-dimension    */
+/*     reading); exact for d = 1, biased for non-separable objectives in d > 1. */
+#define PRDPT_EST_GAUSS 0
+#define PRDPT_EST_IS 1
+#define PRDPT_EST_IS_PERDIM 2
+
+/* ---- scene description ---------------------------------------------------- */
+#define PRDPT_MAT_DIFFUSE 0    /* rgb = albedo; Lambertian */
+#define PRDPT_MAT_DIELECTRIC 1 /* ior; smooth glass, spheres only */
+#define PRDPT_MAT_EMISSIVE 2   /* rgb = radiance; quads only (one-sided area lights) */
+
+#define PRDPT_BIND_SPHERE 0 /* sphere centre component */
+#define PRDPT_BIND_QUAD 1   /* quad origin component */
+#define PRDPT_BIND_MESH 2   /* mesh translation component */
+#define PRDPT_BIND_PLIGHT 3 /* point-light position component */
+
+/* Limits of one scene. */
+#define PRDPT_MAX_PARAMS 32
+#define PRDPT_MAX_MATERIALS 32
+#define PRDPT_MAX_SPHERES 16
+#define PRDPT_MAX_QUADS 16
+#define PRDPT_MAX_INSTANCES 8
+#define PRDPT_MAX_POINT_LIGHTS 8
+#define PRDPT_MAX_BOUNCES 64
+#define PRDPT_MAX_SIDE 4096
+
+/*
+ * All arrays are host memory, copied by prdpt_scene_create (the caller may free
+ * them on return).  Primitive ids, used to break ties between equal hit
+ * distances, are: spheres 0..S-1, quads S..S+Q-1, then triangles in array order.
+ * Camera: pinhole at eye; the unnormalised direction of image point (sx, sy) in
+ * [-1,1]^2 is fwd + sx*right + sy*up (right/up pre-scaled by the field of view;
+ * row 0 is the top, sy = +1).  A parameter binding (kind, index, component)
+ * makes that scalar field equal its base value plus theta_j (every parameter is
+ * a translation).  A mesh is an instance: rays are moved by minus its
+ * translation into its static BVH.
+ */
+typedef struct {
+  float eye[3], fwd[3], right[3], up[3];
+  int32_t width, height;      /* image size, 1..PRDPT_MAX_SIDE */
+  int32_t spp;                /* samples per pixel, >= 1 */
+  int32_t max_bounces;        /* scattering events after the primary hit, 0..64 */
+  int32_t pixel_center;       /* 1: sample pixel centres instead of jittering */
+  float env[3];               /* constant environment radiance on misses (normally 0) */
+  int32_t n_materials;
+  const int32_t* mat_type;    /* [n_materials] PRDPT_MAT_* */
+  const float* mat_rgb;       /* [n_materials][3] */
+  const float* mat_ior;       /* [n_materials] */
+  int32_t n_spheres;
+  const float* spheres;       /* [n][4] centre xyz, radius */
+  const int32_t* sphere_mat;  /* [n] */
+  int32_t n_quads;
+  const float* quads;         /* [n][9] origin, edge1, edge2 (normal = edge1 x edge2) */
+  const int32_t* quad_mat;    /* [n] */
+  int32_t n_meshes;
+  const int32_t* mesh_offset; /* [n_meshes + 1] first triangle of each mesh */
+  const int32_t* mesh_mat;    /* [n_meshes] */
+  const float* mesh_translation; /* [n_meshes][3] */
+  int32_t n_triangles;
+  const float* triangles;     /* [n_triangles][9] v0, v1, v2 */
+  int32_t n_point_lights;
+  const float* point_lights;  /* [n][6] position, intensity rgb */
+  int32_t n_params;           /* d, 1..PRDPT_MAX_PARAMS */
+  const int32_t* bindings;    /* [d][3] kind, index, component */
+} prdpt_scene_desc;
+
+typedef struct prdpt_ctx prdpt_ctx;
+typedef struct prdpt_scene prdpt_scene;
+
+/* Thread-local description of the last error on this thread ("" if none). */
+const char* prdpt_last_error(void);
+
+/*
+ * Create a context on HIP device `device`.  `stream` is the hipStream_t the
+ * context enqueues on (NULL: the device's null stream; the stream stays owned
+ * by the caller and must outlive the context).  `hbm_budget` bounds the
+ * sum of resident scene footprints in bytes (0 = unbounded): scene creation
+ * beyond it fails with PRDPT_E_ADMISSION.
+ */
+int prdpt_ctx_create(int device, void* stream, size_t hbm_budget, prdpt_ctx** out);
+/* Synchronise and release the context's own memory (scenes must be destroyed first). */
+int prdpt_ctx_destroy(prdpt_ctx* ctx);
+/* Rebind the context to another stream of the same device (NULL = null stream). */
+int prdpt_ctx_set_stream(prdpt_ctx* ctx, void* stream);
+/* Bytes currently held by resident scenes of this context. */
+int prdpt_ctx_resident_bytes(prdpt_ctx* ctx, size_t* bytes);
+
+/*
+ * Validate and copy a scene, build its BVHs on the host (binned SAH, 64-byte
+ * nodes, 48-byte triangles), upload them, and return a handle that stays
+ * resident in HBM until prdpt_scene_destroy.  *footprint_bytes (nullable)
+ * receives the device bytes held.  Errors: PRDPT_E_ARG (null), PRDPT_E_SCENE
+ * (limits, indices, material rules), PRDPT_E_ADMISSION, PRDPT_E_NOMEM.
+ */
+int prdpt_scene_create(prdpt_ctx* ctx, const prdpt_scene_desc* desc, prdpt_scene** out,
+                       size_t* footprint_bytes);
+int prdpt_scene_destroy(prdpt_scene* scene);
+/* width, height, spp, max_bounces, n_params (any may be NULL). */
+int prdpt_scene_info(const prdpt_scene* scene, int* width, int* height, int* spp,
+                     int* max_bounces, int* n_params);
+
+/*
+ * Perturbation draw only (Sec. 3.2): tau_out (host, float[P][d]) and pair weights
+ * c_out (host, double[P][d]) of `est` for P pairs.  d <= PRDPT_MAX_PARAMS.
+ */
+int prdpt_draw_tau(prdpt_ctx* ctx, int est, int d, int P, uint64_t seed, const float* sigma,
+                   float* tau_out, double* c_out);
+
+/*
+ * Render the N perturbed scenes theta +- tau_p (Eq. 6 / Eq. 10 arguments).
+ * images_out: device float[N][H][W][3] (k = 2p + m), caller-owned.
+ * tau_out: host float[N/2][d] or NULL.  Synchronous.
+ */
+int prdpt_render_perturbed(prdpt_scene* scene, const float* theta, const float* sigma, int N,
+                           uint64_t seed, int est, float* images_out, float* tau_out);
+
+/*
+ * Render one image at parameters X (host float[d]) with the reference stream
+ * (stream tag 3, pair 0) into image_out (device float[H][W][3]).  Used to build
+ * reference images R(theta_ref) for Eq. 2.  Synchronous.
+ */
+int prdpt_render_reference(prdpt_scene* scene, const float* X, uint64_t seed, float* image_out);
+
+/*
+ * Monte Carlo estimate of the smoothed objective Q (Eq. 7 read with tau ~ kappa
+ * and no extra kernel weight): the mean of the N per-image losses with GAUSS
+ * perturbations.  ref: device float[H][W][3].  loss_out: host double.
+ */
+int prdpt_smoothed_loss(prdpt_scene* scene, const float* ref, const float* theta,
+                        const float* sigma, int N, uint64_t seed, double* loss_out);
+
+/*
+ * Plateau-reduced gradient (Eq. 10 with antithetic pairs; Alg. 1 with the
+ * kernel constant made explicit):
+ *     grad_j = (1/P) sum_p c_pj (L(theta + tau_p) - L(theta - tau_p)),
+ * accumulated in binary64.  ref: device float[H][W][3].  grad_out: host
+ * double[d].  loss_out (nullable): host double, mean of the N losses.
+ * losses_out (nullable): host double[N] per-image losses.  Synchronous.
+ */
+int prdpt_grad_estimate(prdpt_scene* scene, const float* ref, const float* theta,
+                        const float* sigma, int N, uint64_t seed, int est, double* grad_out,
+                        double* loss_out, double* losses_out);
+
+/*
+ * Stream-ordered form of prdpt_grad_estimate for callers that keep everything
+ * on the device (the torch binding): theta_dev/sigma_dev device float[d];
+ * grad_dev device double[d]; loss_dev device double[1]; losses_dev (nullable)
+ * device double[N]; c_dev (nullable) device double[N/2][d] receives the pair
+ * weights.  Enqueued on the context's stream; no host synchronisation.
+ */
+int prdpt_grad_estimate_async(prdpt_scene* scene, const float* ref_dev, const float* theta_dev,
+                              const float* sigma_dev, int N, uint64_t seed, int est,
+                              double* grad_dev, double* loss_dev, double* losses_dev,
+                              double* c_dev);
+
+/*
+ * Gradient combination alone (Eq. 10 with antithetic pairs), stream-ordered:
+ *     grad_dev[j] = scale * (1/P) sum_p c_dev[p][j] (losses_dev[2p] - losses_dev[2p+1])
+ * with scale = *scale_dev (device double, NULL means 1).  All pointers device.
+ */
+int prdpt_combine_async(prdpt_ctx* ctx, int P, int d, const double* c_dev,
+                        const double* losses_dev, const double* scale_dev, double* grad_dev);
+
+/* Wait for all work enqueued on the context's stream. */
+int prdpt_ctx_synchronize(prdpt_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PRDPT_H */

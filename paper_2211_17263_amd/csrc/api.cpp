@@ -1,0 +1,562 @@
+// C ABI of the estimator: contexts, resident scenes and the estimator calls.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "prdpt.h"
+#include "prdpt_internal.h"
+
+namespace prdpt {
+BvhOut build_bvh(const float* tri9, const int32_t* tri_mat, const int32_t* list, int n,
+                 int32_t id_base, std::vector<Node>& nodes, std::vector<Tri>& tris);
+int render_tiles(int W, int H);
+hipError_t launch_tau(hipStream_t st, int est, int d, int P, uint64_t seed, const float* sigma,
+                      const float* theta, double cd, double sqrt2pi, float* tau, double* c, float* X);
+hipError_t launch_render(hipStream_t st, const DevScene& sc, int W, int H, const float* X, int nk,
+                         int d, int tag, uint64_t seed, const float* ref, float* img,
+                         float* partial, unsigned long long* counters);
+hipError_t launch_losses(hipStream_t st, const float* partial, int n_tiles, int N, int npix,
+                         double* losses);
+hipError_t launch_combine(hipStream_t st, int P, int d, const double* c, const double* L,
+                          const double* scale, double* grad, double* loss);
+}  // namespace prdpt
+
+using namespace prdpt;
+
+namespace {
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail(PRDPT_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));      \
+  } while (0)
+
+// Mean of the chi distribution with d degrees of freedom (the IS weight constant):
+// C_1 = sqrt(2/pi), C_{k+1} = k / C_k.
+double chi_mean(int d) {
+  double c = std::sqrt(2.0 / M_PI);
+  for (int k = 1; k < d; ++k) c = (double)k / c;
+  return c;
+}
+
+template <class T>
+struct DevBuf {
+  T* p = nullptr;
+  size_t n = 0;
+};
+}  // namespace
+
+struct prdpt_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  size_t budget = 0;
+  size_t resident = 0;
+  int n_scenes = 0;
+  std::mutex mu;
+  DevBuf<float> X, tau, partial, theta, sigma;
+  DevBuf<double> c, losses, grad, loss;
+  DevBuf<unsigned long long> counters;
+};
+
+struct prdpt_scene {
+  prdpt_ctx* ctx = nullptr;
+  SceneHdr hdr{};
+  SceneHdr* d_hdr = nullptr;
+  Node* d_nodes = nullptr;
+  Tri* d_tris = nullptr;
+  size_t footprint = 0;
+  int n_nodes = 0, n_tris = 0, bvh_depth = 0;
+  DevScene dev() const { return DevScene{d_hdr, d_nodes, d_tris}; }
+};
+
+namespace {
+
+template <class T>
+int ensure(prdpt_ctx* ctx, DevBuf<T>& b, size_t n) {
+  if (n == 0) n = 1;
+  if (b.n >= n) return PRDPT_OK;
+  if (b.p) {
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    HIP_TRY(hipFree(b.p));
+    b.p = nullptr;
+    b.n = 0;
+  }
+  size_t want = n + n / 2;
+  if (hipMalloc(&b.p, want * sizeof(T)) != hipSuccess) {
+    b.p = nullptr;
+    return fail(PRDPT_E_NOMEM, "device allocation of scratch failed");
+  }
+  b.n = want;
+  return PRDPT_OK;
+}
+
+int check_request(const prdpt_scene* s, const float* theta, const float* sigma, int N,
+                  bool host_vectors) {
+  if (!s) return fail(PRDPT_E_ARG, "scene is null");
+  if (!theta || !sigma) return fail(PRDPT_E_ARG, "theta/sigma is null");
+  if (N < 2 || (N & 1)) return fail(PRDPT_E_ARG, "N must be even and >= 2");
+  if (N > (1 << 20)) return fail(PRDPT_E_ARG, "N too large");
+  if (host_vectors) {
+    for (int j = 0; j < s->hdr.n_param; ++j) {
+      if (!std::isfinite(theta[j])) return fail(PRDPT_E_ARG, "theta must be finite");
+      if (!(sigma[j] > 0.0f) || !std::isfinite(sigma[j]))
+        return fail(PRDPT_E_ARG, "sigma must be positive and finite");
+    }
+  }
+  return PRDPT_OK;
+}
+
+int check_est(int est) {
+  if (est != PRDPT_EST_GAUSS && est != PRDPT_EST_IS && est != PRDPT_EST_IS_PERDIM)
+    return fail(PRDPT_E_ARG, "unknown estimator mode");
+  return PRDPT_OK;
+}
+
+// Scratch for one request with N renders; returns status.
+int prepare(prdpt_ctx* ctx, int N, int d, int n_tiles) {
+  int P = N / 2, rc;
+  if ((rc = ensure(ctx, ctx->X, (size_t)N * d))) return rc;
+  if ((rc = ensure(ctx, ctx->tau, (size_t)P * d))) return rc;
+  if ((rc = ensure(ctx, ctx->c, (size_t)P * d))) return rc;
+  if ((rc = ensure(ctx, ctx->partial, (size_t)N * n_tiles))) return rc;
+  if ((rc = ensure(ctx, ctx->losses, (size_t)N))) return rc;
+  if ((rc = ensure(ctx, ctx->grad, (size_t)d))) return rc;
+  if ((rc = ensure(ctx, ctx->loss, 1))) return rc;
+  if ((rc = ensure(ctx, ctx->theta, (size_t)d))) return rc;
+  if ((rc = ensure(ctx, ctx->sigma, (size_t)d))) return rc;
+  return PRDPT_OK;
+}
+
+// enqueue tau + fused render/loss + losses + combine on the context stream
+int enqueue_estimate(prdpt_scene* s, const float* ref, const float* theta_dev,
+                     const float* sigma_dev, int N, uint64_t seed, int est, double* grad_dev,
+                     double* loss_dev, double* losses_dev, double* c_dev) {
+  prdpt_ctx* ctx = s->ctx;
+  const SceneHdr& h = s->hdr;
+  const int d = h.n_param, P = N / 2;
+  const int n_tiles = render_tiles(h.W, h.H);
+  int rc = prepare(ctx, N, d, n_tiles);
+  if (rc) return rc;
+  double* c = c_dev ? c_dev : ctx->c.p;
+  double* L = losses_dev ? losses_dev : ctx->losses.p;
+  HIP_TRY(launch_tau(ctx->stream, est, d, P, seed, sigma_dev, theta_dev, chi_mean(d),
+                     std::sqrt(2.0 * M_PI), ctx->tau.p, c, ctx->X.p));
+  HIP_TRY(launch_render(ctx->stream, s->dev(), h.W, h.H, ctx->X.p, N, d, kTagPath, seed, ref,
+                        nullptr, ctx->partial.p, nullptr));
+  HIP_TRY(launch_losses(ctx->stream, ctx->partial.p, n_tiles, N, h.W * h.H, L));
+  HIP_TRY(launch_combine(ctx->stream, P, d, c, L, nullptr, grad_dev, loss_dev));
+  return PRDPT_OK;
+}
+
+int upload_vectors(prdpt_ctx* ctx, const float* theta, const float* sigma, int d) {
+  HIP_TRY(hipMemcpyAsync(ctx->theta.p, theta, sizeof(float) * d, hipMemcpyHostToDevice, ctx->stream));
+  HIP_TRY(hipMemcpyAsync(ctx->sigma.p, sigma, sizeof(float) * d, hipMemcpyHostToDevice, ctx->stream));
+  return PRDPT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* prdpt_last_error(void) { return g_err.c_str(); }
+
+int prdpt_ctx_create(int device, void* stream, size_t hbm_budget, prdpt_ctx** out) {
+  if (!out) return fail(PRDPT_E_ARG, "out is null");
+  *out = nullptr;
+  int n = 0;
+  HIP_TRY(hipGetDeviceCount(&n));
+  if (device < 0 || device >= n) return fail(PRDPT_E_ARG, "no such device");
+  HIP_TRY(hipSetDevice(device));
+  prdpt_ctx* ctx = new prdpt_ctx();
+  ctx->device = device;
+  ctx->budget = hbm_budget;
+  ctx->stream = (hipStream_t)stream;  // NULL: the device's null stream
+  *out = ctx;
+  return PRDPT_OK;
+}
+
+int prdpt_ctx_set_stream(prdpt_ctx* ctx, void* stream) {
+  if (!ctx) return fail(PRDPT_E_ARG, "ctx is null");
+  std::lock_guard<std::mutex> g(ctx->mu);
+  HIP_TRY(hipSetDevice(ctx->device));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  ctx->stream = (hipStream_t)stream;
+  return PRDPT_OK;
+}
+
+int prdpt_ctx_destroy(prdpt_ctx* ctx) {
+  if (!ctx) return fail(PRDPT_E_ARG, "ctx is null");
+  if (ctx->n_scenes) return fail(PRDPT_E_ARG, "destroy the context's scenes first");
+  hipSetDevice(ctx->device);
+  hipStreamSynchronize(ctx->stream);
+  void* bufs[] = {ctx->X.p, ctx->tau.p, ctx->partial.p, ctx->theta.p, ctx->sigma.p,
+                  ctx->c.p, ctx->losses.p, ctx->grad.p, ctx->loss.p, ctx->counters.p};
+  for (void* b : bufs)
+    if (b) hipFree(b);
+  delete ctx;
+  return PRDPT_OK;
+}
+
+int prdpt_ctx_resident_bytes(prdpt_ctx* ctx, size_t* bytes) {
+  if (!ctx || !bytes) return fail(PRDPT_E_ARG, "null argument");
+  std::lock_guard<std::mutex> g(ctx->mu);
+  *bytes = ctx->resident;
+  return PRDPT_OK;
+}
+
+int prdpt_ctx_synchronize(prdpt_ctx* ctx) {
+  if (!ctx) return fail(PRDPT_E_ARG, "ctx is null");
+  HIP_TRY(hipSetDevice(ctx->device));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  return PRDPT_OK;
+}
+
+int prdpt_scene_create(prdpt_ctx* ctx, const prdpt_scene_desc* D, prdpt_scene** out,
+                       size_t* footprint_bytes) {
+  if (!ctx || !D || !out) return fail(PRDPT_E_ARG, "null argument");
+  *out = nullptr;
+  // ---- validation ----
+  if (D->width < 1 || D->height < 1 || D->width > PRDPT_MAX_SIDE || D->height > PRDPT_MAX_SIDE)
+    return fail(PRDPT_E_SCENE, "image size out of range");
+  if (D->spp < 1 || D->spp > 65536) return fail(PRDPT_E_SCENE, "spp out of range");
+  if (D->max_bounces < 0 || D->max_bounces > PRDPT_MAX_BOUNCES)
+    return fail(PRDPT_E_SCENE, "max_bounces out of range");
+  if (D->n_params < 1 || D->n_params > PRDPT_MAX_PARAMS || !D->bindings)
+    return fail(PRDPT_E_SCENE, "n_params out of range");
+  if (D->n_materials < 1 || D->n_materials > PRDPT_MAX_MATERIALS || !D->mat_type || !D->mat_rgb ||
+      !D->mat_ior)
+    return fail(PRDPT_E_SCENE, "materials missing or too many");
+  if (D->n_spheres < 0 || D->n_spheres > PRDPT_MAX_SPHERES || D->n_quads < 0 ||
+      D->n_quads > PRDPT_MAX_QUADS || D->n_point_lights < 0 ||
+      D->n_point_lights > PRDPT_MAX_POINT_LIGHTS || D->n_meshes < 0 || D->n_triangles < 0)
+    return fail(PRDPT_E_SCENE, "primitive counts out of range");
+  if ((D->n_spheres && (!D->spheres || !D->sphere_mat)) || (D->n_quads && (!D->quads || !D->quad_mat)) ||
+      (D->n_point_lights && !D->point_lights) ||
+      (D->n_meshes && (!D->mesh_offset || !D->mesh_mat || !D->mesh_translation)) ||
+      (D->n_triangles && !D->triangles))
+    return fail(PRDPT_E_SCENE, "null array for a non-empty primitive list");
+  for (int i = 0; i < D->n_materials; ++i)
+    if (D->mat_type[i] < 0 || D->mat_type[i] > 2) return fail(PRDPT_E_SCENE, "bad material type");
+  auto mat_ok = [&](int m) { return m >= 0 && m < D->n_materials; };
+  for (int i = 0; i < D->n_spheres; ++i) {
+    if (!mat_ok(D->sphere_mat[i]) || D->mat_type[D->sphere_mat[i]] == PRDPT_MAT_EMISSIVE)
+      return fail(PRDPT_E_SCENE, "sphere material must be diffuse or dielectric");
+    if (!(D->spheres[4 * i + 3] > 0.0f)) return fail(PRDPT_E_SCENE, "sphere radius must be > 0");
+  }
+  for (int i = 0; i < D->n_quads; ++i)
+    if (!mat_ok(D->quad_mat[i]) || D->mat_type[D->quad_mat[i]] == PRDPT_MAT_DIELECTRIC)
+      return fail(PRDPT_E_SCENE, "quad material must be diffuse or emissive");
+  if (D->n_meshes) {
+    if (D->mesh_offset[0] != 0 || D->mesh_offset[D->n_meshes] != D->n_triangles)
+      return fail(PRDPT_E_SCENE, "mesh offsets must start at 0 and end at n_triangles");
+    for (int m = 0; m < D->n_meshes; ++m) {
+      if (D->mesh_offset[m + 1] < D->mesh_offset[m]) return fail(PRDPT_E_SCENE, "mesh offsets decrease");
+      if (!mat_ok(D->mesh_mat[m]) || D->mat_type[D->mesh_mat[m]] != PRDPT_MAT_DIFFUSE)
+        return fail(PRDPT_E_SCENE, "mesh material must be diffuse");
+    }
+  } else if (D->n_triangles) {
+    return fail(PRDPT_E_SCENE, "triangles without meshes");
+  }
+  // ---- header ----
+  prdpt_scene* s = new prdpt_scene();
+  s->ctx = ctx;
+  SceneHdr& h = s->hdr;
+  std::memcpy(h.eye, D->eye, 12);
+  std::memcpy(h.fwd, D->fwd, 12);
+  std::memcpy(h.right, D->right, 12);
+  std::memcpy(h.up, D->up, 12);
+  std::memcpy(h.env, D->env, 12);
+  h.W = D->width; h.H = D->height; h.spp = D->spp; h.B = D->max_bounces;
+  h.pixel_center = D->pixel_center ? 1 : 0;
+  h.n_mat = D->n_materials; h.n_sph = D->n_spheres; h.n_quad = D->n_quads;
+  h.n_pl = D->n_point_lights; h.n_param = D->n_params; h.n_tri = D->n_triangles;
+  h.tri_id_base = D->n_spheres + D->n_quads;
+  for (int i = 0; i < h.n_mat; ++i) {
+    h.mat_type[i] = D->mat_type[i];
+    for (int c = 0; c < 3; ++c) h.mat_rgb[i][c] = D->mat_rgb[3 * i + c];
+    h.mat_ior[i] = D->mat_ior[i];
+    if (h.mat_type[i] == PRDPT_MAT_DIELECTRIC && !(h.mat_ior[i] > 0.0f)) {
+      delete s;
+      return fail(PRDPT_E_SCENE, "dielectric ior must be > 0");
+    }
+  }
+  for (int i = 0; i < h.n_sph; ++i) {
+    for (int c = 0; c < 4; ++c) h.sph[i][c] = D->spheres[4 * i + c];
+    h.sph_mat[i] = D->sphere_mat[i];
+  }
+  h.n_area = 0;
+  for (int i = 0; i < h.n_quad; ++i) {
+    for (int c = 0; c < 9; ++c) h.quad[i][c] = D->quads[9 * i + c];
+    h.quad_mat[i] = D->quad_mat[i];
+    if (h.mat_type[h.quad_mat[i]] == PRDPT_MAT_EMISSIVE) h.area_quad[h.n_area++] = i;
+  }
+  for (int i = 0; i < h.n_pl; ++i)
+    for (int c = 0; c < 6; ++c) h.pl[i][c] = D->point_lights[6 * i + c];
+  // ---- instances: meshes with a binding or a non-zero translation get their
+  //      own BVH; all other meshes share one static BVH ----
+  std::vector<int> mesh_inst(D->n_meshes, -1);
+  std::vector<char> bound(D->n_meshes, 0);
+  for (int j = 0; j < D->n_params; ++j) {
+    const int kind = D->bindings[3 * j], idx = D->bindings[3 * j + 1], comp = D->bindings[3 * j + 2];
+    const int lim = kind == PRDPT_BIND_SPHERE ? D->n_spheres : kind == PRDPT_BIND_QUAD ? D->n_quads
+                    : kind == PRDPT_BIND_MESH ? D->n_meshes : kind == PRDPT_BIND_PLIGHT ? D->n_point_lights : -1;
+    if (lim < 0 || idx < 0 || idx >= lim || comp < 0 || comp > 2) {
+      delete s;
+      return fail(PRDPT_E_SCENE, "bad parameter binding");
+    }
+    for (int i = 0; i < j; ++i)
+      if (D->bindings[3 * i] == kind && D->bindings[3 * i + 1] == idx && D->bindings[3 * i + 2] == comp) {
+        delete s;
+        return fail(PRDPT_E_SCENE, "a field is bound twice");
+      }
+    if (kind == PRDPT_BIND_MESH) bound[idx] = 1;
+  }
+  int n_inst = 0;
+  int static_inst = -1;
+  for (int m = 0; m < D->n_meshes; ++m) {
+    const float* t = D->mesh_translation + 3 * m;
+    const bool own = bound[m] || t[0] != 0.0f || t[1] != 0.0f || t[2] != 0.0f;
+    if (own) {
+      mesh_inst[m] = n_inst++;
+    } else {
+      if (static_inst < 0) static_inst = n_inst++;
+      mesh_inst[m] = static_inst;
+    }
+  }
+  if (n_inst > PRDPT_MAX_INSTANCES) {
+    delete s;
+    return fail(PRDPT_E_SCENE, "too many mesh instances");
+  }
+  h.n_inst = n_inst;
+  for (int j = 0; j < D->n_params; ++j) {
+    h.bind_kind[j] = D->bindings[3 * j];
+    h.bind_index[j] = h.bind_kind[j] == PRDPT_BIND_MESH ? mesh_inst[D->bindings[3 * j + 1]]
+                                                        : D->bindings[3 * j + 1];
+    h.bind_comp[j] = D->bindings[3 * j + 2];
+  }
+  std::vector<int32_t> tri_mat(D->n_triangles);
+  std::vector<std::vector<int32_t>> lists(n_inst);
+  for (int m = 0; m < D->n_meshes; ++m) {
+    for (int t = D->mesh_offset[m]; t < D->mesh_offset[m + 1]; ++t) {
+      tri_mat[t] = D->mesh_mat[m];
+      lists[mesh_inst[m]].push_back(t);
+    }
+    for (int c = 0; c < 3; ++c) h.inst_xlate[mesh_inst[m]][c] = D->mesh_translation[3 * m + c];
+  }
+  std::vector<Node> nodes;
+  std::vector<Tri> tris;
+  tris.reserve(D->n_triangles);
+  for (int i = 0; i < n_inst; ++i) {
+    BvhOut b = build_bvh(D->triangles, tri_mat.data(), lists[i].data(), (int)lists[i].size(),
+                         h.tri_id_base, nodes, tris);
+    h.inst_root[i] = b.root;
+    s->bvh_depth = std::max(s->bvh_depth, b.depth);
+  }
+  if (s->bvh_depth > kStackDepth) {
+    delete s;
+    return fail(PRDPT_E_SCENE, "BVH deeper than the traversal stack");
+  }
+  s->n_nodes = (int)nodes.size();
+  s->n_tris = (int)tris.size();
+  s->footprint = sizeof(SceneHdr) + nodes.size() * sizeof(Node) + tris.size() * sizeof(Tri);
+  // ---- admission and upload ----
+  std::lock_guard<std::mutex> g(ctx->mu);
+  if (ctx->budget && ctx->resident + s->footprint > ctx->budget) {
+    delete s;
+    return fail(PRDPT_E_ADMISSION, "scene exceeds the context's HBM budget");
+  }
+  if (hipSetDevice(ctx->device) != hipSuccess) {
+    delete s;
+    return fail(PRDPT_E_HIP, "hipSetDevice failed");
+  }
+  bool ok = hipMalloc(&s->d_hdr, sizeof(SceneHdr)) == hipSuccess;
+  ok = ok && hipMalloc(&s->d_nodes, std::max<size_t>(1, nodes.size()) * sizeof(Node)) == hipSuccess;
+  ok = ok && hipMalloc(&s->d_tris, std::max<size_t>(1, tris.size()) * sizeof(Tri)) == hipSuccess;
+  if (!ok) {
+    if (s->d_hdr) hipFree(s->d_hdr);
+    if (s->d_nodes) hipFree(s->d_nodes);
+    delete s;
+    return fail(PRDPT_E_NOMEM, "device allocation of the scene failed");
+  }
+  ok = hipMemcpy(s->d_hdr, &h, sizeof(SceneHdr), hipMemcpyHostToDevice) == hipSuccess;
+  if (ok && !nodes.empty())
+    ok = hipMemcpy(s->d_nodes, nodes.data(), nodes.size() * sizeof(Node), hipMemcpyHostToDevice) == hipSuccess;
+  if (ok && !tris.empty())
+    ok = hipMemcpy(s->d_tris, tris.data(), tris.size() * sizeof(Tri), hipMemcpyHostToDevice) == hipSuccess;
+  if (!ok) {
+    hipFree(s->d_hdr);
+    hipFree(s->d_nodes);
+    hipFree(s->d_tris);
+    delete s;
+    return fail(PRDPT_E_HIP, "scene upload failed");
+  }
+  ctx->resident += s->footprint;
+  ctx->n_scenes++;
+  if (footprint_bytes) *footprint_bytes = s->footprint;
+  *out = s;
+  return PRDPT_OK;
+}
+
+int prdpt_scene_destroy(prdpt_scene* s) {
+  if (!s) return fail(PRDPT_E_ARG, "scene is null");
+  prdpt_ctx* ctx = s->ctx;
+  std::lock_guard<std::mutex> g(ctx->mu);
+  hipSetDevice(ctx->device);
+  hipStreamSynchronize(ctx->stream);
+  hipFree(s->d_hdr);
+  hipFree(s->d_nodes);
+  hipFree(s->d_tris);
+  ctx->resident -= s->footprint;
+  ctx->n_scenes--;
+  delete s;
+  return PRDPT_OK;
+}
+
+int prdpt_scene_info(const prdpt_scene* s, int* width, int* height, int* spp, int* max_bounces,
+                     int* n_params) {
+  if (!s) return fail(PRDPT_E_ARG, "scene is null");
+  if (width) *width = s->hdr.W;
+  if (height) *height = s->hdr.H;
+  if (spp) *spp = s->hdr.spp;
+  if (max_bounces) *max_bounces = s->hdr.B;
+  if (n_params) *n_params = s->hdr.n_param;
+  return PRDPT_OK;
+}
+
+int prdpt_draw_tau(prdpt_ctx* ctx, int est, int d, int P, uint64_t seed, const float* sigma,
+                   float* tau_out, double* c_out) {
+  if (!ctx || !sigma || !tau_out || !c_out) return fail(PRDPT_E_ARG, "null argument");
+  if (d < 1 || d > PRDPT_MAX_PARAMS || P < 1 || P > (1 << 20)) return fail(PRDPT_E_ARG, "bad d or P");
+  if (int rc = check_est(est)) return rc;
+  for (int j = 0; j < d; ++j)
+    if (!(sigma[j] > 0.0f) || !std::isfinite(sigma[j])) return fail(PRDPT_E_ARG, "sigma must be > 0");
+  std::lock_guard<std::mutex> g(ctx->mu);
+  HIP_TRY(hipSetDevice(ctx->device));
+  if (int rc = prepare(ctx, 2 * P, d, 1)) return rc;
+  std::vector<float> zero(d, 0.0f);
+  if (int rc = upload_vectors(ctx, zero.data(), sigma, d)) return rc;
+  HIP_TRY(launch_tau(ctx->stream, est, d, P, seed, ctx->sigma.p, ctx->theta.p, chi_mean(d),
+                     std::sqrt(2.0 * M_PI), ctx->tau.p, ctx->c.p, ctx->X.p));
+  HIP_TRY(hipMemcpyAsync(tau_out, ctx->tau.p, sizeof(float) * P * d, hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(hipMemcpyAsync(c_out, ctx->c.p, sizeof(double) * P * d, hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  return PRDPT_OK;
+}
+
+int prdpt_render_perturbed(prdpt_scene* s, const float* theta, const float* sigma, int N,
+                           uint64_t seed, int est, float* images_out, float* tau_out) {
+  if (int rc = check_request(s, theta, sigma, N, true)) return rc;
+  if (int rc = check_est(est)) return rc;
+  if (!images_out) return fail(PRDPT_E_ARG, "images_out is null");
+  prdpt_ctx* ctx = s->ctx;
+  const SceneHdr& h = s->hdr;
+  const int d = h.n_param, P = N / 2;
+  std::lock_guard<std::mutex> g(ctx->mu);
+  HIP_TRY(hipSetDevice(ctx->device));
+  if (int rc = prepare(ctx, N, d, render_tiles(h.W, h.H))) return rc;
+  if (int rc = upload_vectors(ctx, theta, sigma, d)) return rc;
+  HIP_TRY(launch_tau(ctx->stream, est, d, P, seed, ctx->sigma.p, ctx->theta.p, chi_mean(d),
+                     std::sqrt(2.0 * M_PI), ctx->tau.p, ctx->c.p, ctx->X.p));
+  HIP_TRY(launch_render(ctx->stream, s->dev(), h.W, h.H, ctx->X.p, N, d, kTagPath, seed, nullptr,
+                        images_out, nullptr, nullptr));
+  if (tau_out)
+    HIP_TRY(hipMemcpyAsync(tau_out, ctx->tau.p, sizeof(float) * P * d, hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  return PRDPT_OK;
+}
+
+int prdpt_render_reference(prdpt_scene* s, const float* X, uint64_t seed, float* image_out) {
+  if (!s || !X || !image_out) return fail(PRDPT_E_ARG, "null argument");
+  prdpt_ctx* ctx = s->ctx;
+  const SceneHdr& h = s->hdr;
+  const int d = h.n_param;
+  std::lock_guard<std::mutex> g(ctx->mu);
+  HIP_TRY(hipSetDevice(ctx->device));
+  if (int rc = prepare(ctx, 2, d, render_tiles(h.W, h.H))) return rc;
+  HIP_TRY(hipMemcpyAsync(ctx->X.p, X, sizeof(float) * d, hipMemcpyHostToDevice, ctx->stream));
+  HIP_TRY(launch_render(ctx->stream, s->dev(), h.W, h.H, ctx->X.p, 1, d, kTagRef, seed, nullptr,
+                        image_out, nullptr, nullptr));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  return PRDPT_OK;
+}
+
+int prdpt_grad_estimate(prdpt_scene* s, const float* ref, const float* theta, const float* sigma,
+                        int N, uint64_t seed, int est, double* grad_out, double* loss_out,
+                        double* losses_out) {
+  if (int rc = check_request(s, theta, sigma, N, true)) return rc;
+  if (int rc = check_est(est)) return rc;
+  if (!ref || !grad_out) return fail(PRDPT_E_ARG, "ref/grad_out is null");
+  prdpt_ctx* ctx = s->ctx;
+  const int d = s->hdr.n_param;
+  std::lock_guard<std::mutex> g(ctx->mu);
+  HIP_TRY(hipSetDevice(ctx->device));
+  if (int rc = prepare(ctx, N, d, render_tiles(s->hdr.W, s->hdr.H))) return rc;
+  if (int rc = upload_vectors(ctx, theta, sigma, d)) return rc;
+  if (int rc = enqueue_estimate(s, ref, ctx->theta.p, ctx->sigma.p, N, seed, est, ctx->grad.p,
+                                ctx->loss.p, nullptr, nullptr))
+    return rc;
+  HIP_TRY(hipMemcpyAsync(grad_out, ctx->grad.p, sizeof(double) * d, hipMemcpyDeviceToHost, ctx->stream));
+  if (loss_out)
+    HIP_TRY(hipMemcpyAsync(loss_out, ctx->loss.p, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  if (losses_out)
+    HIP_TRY(hipMemcpyAsync(losses_out, ctx->losses.p, sizeof(double) * N, hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  return PRDPT_OK;
+}
+
+int prdpt_smoothed_loss(prdpt_scene* s, const float* ref, const float* theta, const float* sigma,
+                        int N, uint64_t seed, double* loss_out) {
+  if (!loss_out) return fail(PRDPT_E_ARG, "loss_out is null");
+  if (int rc = check_request(s, theta, sigma, N, true)) return rc;
+  if (!ref) return fail(PRDPT_E_ARG, "ref is null");
+  prdpt_ctx* ctx = s->ctx;
+  const int d = s->hdr.n_param;
+  std::lock_guard<std::mutex> g(ctx->mu);
+  HIP_TRY(hipSetDevice(ctx->device));
+  if (int rc = prepare(ctx, N, d, render_tiles(s->hdr.W, s->hdr.H))) return rc;
+  if (int rc = upload_vectors(ctx, theta, sigma, d)) return rc;
+  if (int rc = enqueue_estimate(s, ref, ctx->theta.p, ctx->sigma.p, N, seed, PRDPT_EST_GAUSS,
+                                ctx->grad.p, ctx->loss.p, nullptr, nullptr))
+    return rc;
+  HIP_TRY(hipMemcpyAsync(loss_out, ctx->loss.p, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  return PRDPT_OK;
+}
+
+int prdpt_grad_estimate_async(prdpt_scene* s, const float* ref_dev, const float* theta_dev,
+                              const float* sigma_dev, int N, uint64_t seed, int est,
+                              double* grad_dev, double* loss_dev, double* losses_dev,
+                              double* c_dev) {
+  if (int rc = check_request(s, theta_dev, sigma_dev, N, false)) return rc;
+  if (int rc = check_est(est)) return rc;
+  if (!ref_dev || !grad_dev || !loss_dev) return fail(PRDPT_E_ARG, "null device pointer");
+  prdpt_ctx* ctx = s->ctx;
+  std::lock_guard<std::mutex> g(ctx->mu);
+  HIP_TRY(hipSetDevice(ctx->device));
+  return enqueue_estimate(s, ref_dev, theta_dev, sigma_dev, N, seed, est, grad_dev, loss_dev,
+                          losses_dev, c_dev);
+}
+
+int prdpt_combine_async(prdpt_ctx* ctx, int P, int d, const double* c_dev, const double* losses_dev,
+                        const double* scale_dev, double* grad_dev) {
+  if (!ctx || !c_dev || !losses_dev || !grad_dev) return fail(PRDPT_E_ARG, "null argument");
+  if (P < 1 || d < 1 || d > 64) return fail(PRDPT_E_ARG, "bad P or d");
+  std::lock_guard<std::mutex> g(ctx->mu);
+  HIP_TRY(hipSetDevice(ctx->device));
+  HIP_TRY(launch_combine(ctx->stream, P, d, c_dev, losses_dev, scale_dev, grad_dev, nullptr));
+  return PRDPT_OK;
+}
+
+}  // extern "C"

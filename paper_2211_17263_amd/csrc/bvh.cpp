@@ -1,0 +1,227 @@
+// Host BVH builder: binned surface-area heuristic (16 bins per axis), leaves of
+// at most 4 triangles, object-median splits below a depth threshold so the tree
+// never exceeds the traversal stack.  Output is appended to flat node/triangle
+// arrays in the 64-byte / 48-byte layouts the kernels read with 16-byte loads.
+#include <algorithm>
+#include <cfloat>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "prdpt_internal.h"
+
+namespace prdpt {
+
+namespace {
+
+struct Box {
+  float lo[3] = {FLT_MAX, FLT_MAX, FLT_MAX};
+  float hi[3] = {-FLT_MAX, -FLT_MAX, -FLT_MAX};
+  void grow(const Box& b) {
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = std::min(lo[a], b.lo[a]);
+      hi[a] = std::max(hi[a], b.hi[a]);
+    }
+  }
+  void grow(const float* p) {
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = std::min(lo[a], p[a]);
+      hi[a] = std::max(hi[a], p[a]);
+    }
+  }
+  double area() const {
+    if (lo[0] > hi[0]) return 0.0;
+    double dx = hi[0] - lo[0], dy = hi[1] - lo[1], dz = hi[2] - lo[2];
+    return 2.0 * (dx * dy + dy * dz + dz * dx);
+  }
+};
+
+struct Prim {
+  Box box;
+  float c[3];
+  int32_t tri;  // index into the caller's triangle array
+};
+
+constexpr int kBins = 16;
+constexpr int kLeafMax = 4;
+constexpr int kSahDepth = 22;  // below this depth: object-median splits
+
+struct Builder {
+  const float* tri9;
+  const int32_t* tri_mat;
+  int32_t id_base;
+  std::vector<Node>* nodes;
+  std::vector<Tri>* tris;
+  std::vector<Prim> prims;
+  int max_depth = 0;
+
+  // padded copy of a box, rounded outward in binary32
+  static void padded(const Box& b, float lo[3], float hi[3]) {
+    double mag = 1.0;
+    for (int a = 0; a < 3; ++a) mag = std::max({mag, (double)std::fabs(b.lo[a]), (double)std::fabs(b.hi[a])});
+    double pad = 1e-4 * mag;
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = std::nextafter((float)((double)b.lo[a] - pad), -FLT_MAX);
+      hi[a] = std::nextafter((float)((double)b.hi[a] + pad), FLT_MAX);
+    }
+  }
+
+  int emit_leaf(int begin, int end) {
+    int first = (int)tris->size();
+    for (int i = begin; i < end; ++i) {
+      int t = prims[i].tri;
+      const float* v = tri9 + 9 * (size_t)t;
+      Tri o;
+      o.v0x = v[0]; o.v0y = v[1]; o.v0z = v[2];
+      o.e1x = v[3] - v[0]; o.e1y = v[4] - v[1]; o.e1z = v[5] - v[2];
+      o.e2x = v[6] - v[0]; o.e2y = v[7] - v[1]; o.e2z = v[8] - v[2];
+      o.id = id_base + t;
+      o.mat = tri_mat[t];
+      o.pad = 0;
+      tris->push_back(o);
+    }
+    return first;
+  }
+
+  Box range_box(int begin, int end) const {
+    Box b;
+    for (int i = begin; i < end; ++i) b.grow(prims[i].box);
+    return b;
+  }
+
+  // returns (idx, cnt) reference to a subtree: cnt > 0 leaf, cnt == 0 inner
+  void build(int begin, int end, int depth, int32_t* idx, int32_t* cnt) {
+    max_depth = std::max(max_depth, depth);
+    int n = end - begin;
+    if (n <= kLeafMax) {
+      *idx = emit_leaf(begin, end);
+      *cnt = n;
+      return;
+    }
+    Box cb;
+    for (int i = begin; i < end; ++i) cb.grow(prims[i].c);
+    int axis = 0;
+    for (int a = 1; a < 3; ++a)
+      if (cb.hi[a] - cb.lo[a] > cb.hi[axis] - cb.lo[axis]) axis = a;
+    int mid = -1;
+    if (depth < kSahDepth && cb.hi[axis] > cb.lo[axis]) {
+      double best = DBL_MAX;
+      int best_axis = -1, best_bin = -1;
+      for (int a = 0; a < 3; ++a) {
+        float ext = cb.hi[a] - cb.lo[a];
+        if (!(ext > 0.0f)) continue;
+        Box bb[kBins];
+        int bc[kBins] = {0};
+        float k = kBins / ext;
+        for (int i = begin; i < end; ++i) {
+          int b = std::min(kBins - 1, (int)((prims[i].c[a] - cb.lo[a]) * k));
+          bb[b].grow(prims[i].box);
+          bc[b]++;
+        }
+        double right_area[kBins];
+        int right_cnt[kBins];
+        Box acc;
+        int cacc = 0;
+        for (int b = kBins - 1; b > 0; --b) {
+          acc.grow(bb[b]);
+          cacc += bc[b];
+          right_area[b] = acc.area();
+          right_cnt[b] = cacc;
+        }
+        Box lacc;
+        int lcnt = 0;
+        for (int b = 0; b < kBins - 1; ++b) {
+          lacc.grow(bb[b]);
+          lcnt += bc[b];
+          if (lcnt == 0 || right_cnt[b + 1] == 0) continue;
+          double cost = lacc.area() * lcnt + right_area[b + 1] * right_cnt[b + 1];
+          if (cost < best) {
+            best = cost;
+            best_axis = a;
+            best_bin = b;
+          }
+        }
+      }
+      if (best_axis >= 0) {
+        int a = best_axis;
+        float k = kBins / (cb.hi[a] - cb.lo[a]);
+        float lo = cb.lo[a];
+        auto it = std::partition(prims.begin() + begin, prims.begin() + end, [&](const Prim& p) {
+          return std::min(kBins - 1, (int)((p.c[a] - lo) * k)) <= best_bin;
+        });
+        mid = (int)(it - prims.begin());
+        if (mid == begin || mid == end) mid = -1;
+      }
+    }
+    if (mid < 0) {
+      mid = begin + n / 2;
+      std::nth_element(prims.begin() + begin, prims.begin() + mid, prims.begin() + end,
+                       [&](const Prim& p, const Prim& q) {
+                         return p.c[axis] < q.c[axis] || (p.c[axis] == q.c[axis] && p.tri < q.tri);
+                       });
+    }
+    int ni = (int)nodes->size();
+    nodes->push_back(Node{});
+    Box lb = range_box(begin, mid), rb = range_box(mid, end);
+    int32_t i0, c0, i1, c1;
+    build(begin, mid, depth + 1, &i0, &c0);
+    build(mid, end, depth + 1, &i1, &c1);
+    float llo[3], lhi[3], rlo[3], rhi[3];
+    padded(lb, llo, lhi);
+    padded(rb, rlo, rhi);
+    Node& nd = (*nodes)[ni];
+    nd.c0lox = llo[0]; nd.c0hix = lhi[0]; nd.c0loy = llo[1]; nd.c0hiy = lhi[1];
+    nd.c1lox = rlo[0]; nd.c1hix = rhi[0]; nd.c1loy = rlo[1]; nd.c1hiy = rhi[1];
+    nd.c0loz = llo[2]; nd.c0hiz = lhi[2]; nd.c1loz = rlo[2]; nd.c1hiz = rhi[2];
+    nd.idx0 = i0; nd.cnt0 = c0; nd.idx1 = i1; nd.cnt1 = c1;
+    *idx = ni;
+    *cnt = 0;
+  }
+};
+
+}  // namespace
+
+// Builds one instance BVH over triangles `list[0..n)` (indices into tri9).
+// The root is always an inner node; a missing second child has idx = -1.
+BvhOut build_bvh(const float* tri9, const int32_t* tri_mat, const int32_t* list, int n,
+                 int32_t id_base, std::vector<Node>& nodes, std::vector<Tri>& tris) {
+  Builder b;
+  b.tri9 = tri9;
+  b.tri_mat = tri_mat;
+  b.id_base = id_base;
+  b.nodes = &nodes;
+  b.tris = &tris;
+  b.prims.resize(n);
+  for (int i = 0; i < n; ++i) {
+    Prim& p = b.prims[i];
+    const float* v = tri9 + 9 * (size_t)list[i];
+    p.box.grow(v);
+    p.box.grow(v + 3);
+    p.box.grow(v + 6);
+    for (int a = 0; a < 3; ++a) p.c[a] = (p.box.lo[a] + p.box.hi[a]) * 0.5f;
+    p.tri = list[i];
+  }
+  BvhOut out{-1, 0};
+  if (n == 0) return out;
+  int32_t idx, cnt;
+  b.build(0, n, 1, &idx, &cnt);
+  if (cnt > 0) {  // a single leaf: wrap it in a root with one child
+    int ni = (int)nodes.size();
+    Node nd{};
+    float lo[3], hi[3];
+    Builder::padded(b.range_box(0, n), lo, hi);
+    nd.c0lox = lo[0]; nd.c0hix = hi[0]; nd.c0loy = lo[1]; nd.c0hiy = hi[1];
+    nd.c0loz = lo[2]; nd.c0hiz = hi[2];
+    nd.c1lox = nd.c1loy = nd.c1loz = 1.0f;
+    nd.c1hix = nd.c1hiy = nd.c1hiz = -1.0f;
+    nd.idx0 = idx; nd.cnt0 = cnt; nd.idx1 = -1; nd.cnt1 = 0;
+    nodes.push_back(nd);
+    idx = ni;
+    b.max_depth = 2;
+  }
+  out.root = idx;
+  out.depth = b.max_depth;
+  return out;
+}
+
+}  // namespace prdpt

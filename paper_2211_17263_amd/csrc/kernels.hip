@@ -1,0 +1,746 @@
+// HIP kernels for gfx950 (CDNA4): perturbation prologue, fused path-trace +
+// per-image loss, and the binary64 finalisation / gradient combination.
+//
+// Numerical contract with the CPU reference: everything that decides which
+// primitive a ray hits (camera rays, intersection tests, hit points, normals,
+// spawn offsets, sampled directions, light sample points, Fresnel choice) is
+// evaluated in binary32 in a fixed order without contraction (the library is
+// built with -ffp-contract=off and correctly rounded division and square root),
+// and the sample transforms use the library's own ln / sincos(2 pi u) built from
+// basic IEEE operations.  Per-sample paths are therefore reproducible bit for
+// bit on any IEEE-754 machine; only the pixel/loss sums differ in rounding.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "prdpt_internal.h"
+
+namespace prdpt {
+namespace {
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11) and sample transforms
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint4 philox10(uint4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
+    const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
+    c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return c;
+}
+
+// (0,1) uniform from the top 23 bits: ((x >> 9) + 1/2) 2^-23, exact in binary32
+__device__ __forceinline__ float unit_open(uint32_t x) {
+  return ((float)(x >> 9) + 0.5f) * 1.1920928955078125e-07f;
+}
+
+// ln for positive normal input: reduce to m in [sqrt(1/2), sqrt(2)], then
+// ln m = 2 atanh((m-1)/(m+1)) by the odd series through s^11, plus e ln 2 in two parts
+__device__ __forceinline__ float log_ieee(float x) {
+  uint32_t b = __float_as_uint(x);
+  int e = (int)((b >> 23) & 0xffu) - 127;
+  float m = __uint_as_float((b & 0x007fffffu) | 0x3f800000u);
+  if (m > 1.41421356f) {
+    m = m * 0.5f;
+    e = e + 1;
+  }
+  const float s = (m - 1.0f) / (m + 1.0f);
+  const float s2 = s * s;
+  float p = 1.0f / 11.0f;
+  p = 1.0f / 9.0f + s2 * p;
+  p = 1.0f / 7.0f + s2 * p;
+  p = 1.0f / 5.0f + s2 * p;
+  p = 1.0f / 3.0f + s2 * p;
+  const float at = s + s * (s2 * p);
+  const float lm = at + at;
+  const float fe = (float)e;
+  return fe * 0.693145751953125f + (lm + fe * 1.42860677e-06f);
+}
+
+// sin and cos of 2 pi u, u in [0,1): quarter-turn index plus remainder in
+// [-1/8, 1/8] (exact), Taylor series of sin through x^9 and cos through x^10
+__device__ __forceinline__ void sincos_turn(float u, float* so, float* co) {
+  const float u4 = u * 4.0f;
+  int q = (int)u4;
+  float r = u - (float)q * 0.25f;
+  if (r > 0.125f) {
+    r = r - 0.25f;
+    q = q + 1;
+  }
+  const float x = r * 6.28318530717958647692f;
+  const float x2 = x * x;
+  float ps = -1.0f / 5040.0f + x2 * (1.0f / 362880.0f);
+  ps = 1.0f / 120.0f + x2 * ps;
+  ps = -1.0f / 6.0f + x2 * ps;
+  const float sn = x + x * (x2 * ps);
+  float pc = 1.0f / 40320.0f + x2 * (-1.0f / 3628800.0f);
+  pc = -1.0f / 720.0f + x2 * pc;
+  pc = 1.0f / 24.0f + x2 * pc;
+  pc = -0.5f + x2 * pc;
+  const float cs = 1.0f + x2 * pc;
+  switch (q & 3) {
+    case 0: *so = sn; *co = cs; break;
+    case 1: *so = cs; *co = -sn; break;
+    case 2: *so = -sn; *co = -cs; break;
+    default: *so = -cs; *co = sn; break;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// binary32 vector helpers with a fixed evaluation order
+// ---------------------------------------------------------------------------
+struct V3 {
+  float x, y, z;
+};
+__device__ __forceinline__ V3 mk(float x, float y, float z) { return V3{x, y, z}; }
+__device__ __forceinline__ V3 sub(V3 a, V3 b) { return mk(a.x - b.x, a.y - b.y, a.z - b.z); }
+__device__ __forceinline__ V3 neg(V3 a) { return mk(-a.x, -a.y, -a.z); }
+__device__ __forceinline__ V3 scale(V3 a, float s) { return mk(a.x * s, a.y * s, a.z * s); }
+__device__ __forceinline__ float dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ V3 cross(V3 a, V3 b) {
+  return mk(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+__device__ __forceinline__ V3 unit(V3 a) {
+  const float len = sqrtf(dot(a, a));
+  const float inv = 1.0f / len;
+  return scale(a, inv);
+}
+__device__ __forceinline__ V3 at(V3 o, V3 d, float t) {
+  return mk(o.x + d.x * t, o.y + d.y * t, o.z + d.z * t);
+}
+__device__ __forceinline__ V3 ld3(const float* p) { return mk(p[0], p[1], p[2]); }
+
+// ---------------------------------------------------------------------------
+// primitive tests: accept t in (0, tmax)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool hit_sphere(V3 o, V3 d, const float* sp, float tmax, float* tout) {
+  const V3 oc = sub(o, ld3(sp));
+  const float r = sp[3];
+  const float a = dot(d, d);
+  const float b = dot(oc, d);
+  const float cc = dot(oc, oc) - r * r;
+  const float disc = b * b - a * cc;
+  if (disc < 0.0f) return false;
+  const float sq = sqrtf(disc);
+  const float q = (b >= 0.0f) ? -(b + sq) : -(b - sq);
+  if (q == 0.0f) return false;
+  const float t0 = q / a, t1 = cc / q;
+  const float tn = t0 < t1 ? t0 : t1;
+  const float tf = t0 < t1 ? t1 : t0;
+  const float t = tn > 0.0f ? tn : tf;
+  if (!(t > 0.0f && t < tmax)) return false;
+  *tout = t;
+  return true;
+}
+
+__device__ __forceinline__ bool hit_quad(V3 o, V3 d, const float* qd, float tmax, float* tout) {
+  const V3 qo = ld3(qd), e1 = ld3(qd + 3), e2 = ld3(qd + 6);
+  const V3 n = cross(e1, e2);
+  const float den = dot(n, d);
+  if (den == 0.0f) return false;
+  const float t = dot(n, sub(qo, o)) / den;
+  if (!(t > 0.0f && t < tmax)) return false;
+  const V3 pd = sub(at(o, d, t), qo);
+  const float nn = dot(n, n);
+  const float al = dot(cross(pd, e2), n) / nn;
+  if (al < 0.0f || al > 1.0f) return false;
+  const float be = dot(cross(e1, pd), n) / nn;
+  if (be < 0.0f || be > 1.0f) return false;
+  *tout = t;
+  return true;
+}
+
+// Moeller-Trumbore on the stored (v0, e1, e2)
+__device__ __forceinline__ bool hit_tri(V3 o, V3 d, V3 v0, V3 e1, V3 e2, float tmax, float* tout) {
+  const V3 pv = cross(d, e2);
+  const float det = dot(e1, pv);
+  if (det == 0.0f) return false;
+  const float inv = 1.0f / det;
+  const V3 tv = sub(o, v0);
+  const float u = dot(tv, pv) * inv;
+  if (u < 0.0f || u > 1.0f) return false;
+  const V3 qv = cross(tv, e1);
+  const float v = dot(d, qv) * inv;
+  if (v < 0.0f || u + v > 1.0f) return false;
+  const float t = dot(e2, qv) * inv;
+  if (!(t > 0.0f && t < tmax)) return false;
+  *tout = t;
+  return true;
+}
+
+struct Hit {
+  float t;
+  int id;     // global primitive id, -1 = miss
+  int slot;   // triangle array index for triangles
+};
+
+__device__ __forceinline__ void keep_closer(Hit& h, float t, int id, int slot) {
+  if (t < h.t || (t == h.t && id < h.id)) {
+    h.t = t;
+    h.id = id;
+    h.slot = slot;
+  }
+}
+
+struct Counters {
+  uint32_t nodes, tris;
+};
+
+// Conservative binary32 slab test of a padded child box; returns the entry
+// distance (or +inf when the box is missed or lies beyond tcull).
+__device__ __forceinline__ float slab(float lox, float hix, float loy, float hiy, float loz,
+                                      float hiz, V3 inv, V3 oi, float tcull) {
+  const float tx0 = fmaf(lox, inv.x, oi.x), tx1 = fmaf(hix, inv.x, oi.x);
+  const float ty0 = fmaf(loy, inv.y, oi.y), ty1 = fmaf(hiy, inv.y, oi.y);
+  const float tz0 = fmaf(loz, inv.z, oi.z), tz1 = fmaf(hiz, inv.z, oi.z);
+  const float tmin = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fmaxf(fminf(tz0, tz1), 0.0f));
+  const float tmax = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fminf(fmaxf(tz0, tz1), tcull));
+  return tmin <= tmax ? tmin : __builtin_huge_valf();
+}
+
+__device__ __forceinline__ float safe_inv(float x) {
+  const float ax = fabsf(x) < 1e-20f ? copysignf(1e-20f, x) : x;
+  return __builtin_amdgcn_rcpf(ax);
+}
+
+// Traverse one instance BVH.  ANY: stop at the first hit with t < tmax.
+template <bool ANY, bool COUNT>
+__device__ bool traverse(const Node* __restrict__ nodes, const Tri* __restrict__ tris, int root,
+                         V3 o, V3 d, float tmax, Hit& h, int* __restrict__ stack, int stride,
+                         Counters& cnt) {
+  const V3 inv = mk(safe_inv(d.x), safe_inv(d.y), safe_inv(d.z));
+  const V3 oi = mk(-o.x * inv.x, -o.y * inv.y, -o.z * inv.z);
+  int sp = 0;
+  int node = root;
+  while (true) {
+    const float4* np = reinterpret_cast<const float4*>(nodes + node);
+    const float4 a = np[0], b = np[1], c = np[2];
+    const int4 ix = reinterpret_cast<const int4*>(np)[3];
+    if (COUNT) cnt.nodes++;
+    const float tcull = ANY ? tmax : fminf(tmax, h.t);
+    float t0 = slab(a.x, a.y, a.z, a.w, c.x, c.y, inv, oi, tcull);
+    float t1 = ix.y >= 0 ? slab(b.x, b.y, b.z, b.w, c.z, c.w, inv, oi, tcull) : __builtin_huge_valf();
+    bool h0 = t0 < __builtin_huge_valf(), h1 = t1 < __builtin_huge_valf();
+    // leaves are intersected immediately
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      const bool hs = side == 0 ? h0 : h1;
+      const int cntl = side == 0 ? ix.z : ix.w;
+      if (hs && cntl > 0) {
+        const int first = side == 0 ? ix.x : ix.y;
+        for (int i = first; i < first + cntl; ++i) {
+          const float4* tp = reinterpret_cast<const float4*>(tris + i);
+          const float4 p0 = tp[0], p1 = tp[1], p2 = tp[2];
+          if (COUNT) cnt.tris++;
+          float t;
+          const float lim = ANY ? tmax : tmax;
+          if (hit_tri(o, d, mk(p0.x, p0.y, p0.z), mk(p0.w, p1.x, p1.y), mk(p1.z, p1.w, p2.x), lim, &t)) {
+            if (ANY) {
+              h.t = t;
+              h.id = __float_as_int(p2.y);
+              return true;
+            }
+            keep_closer(h, t, __float_as_int(p2.y), i);
+          }
+        }
+        if (side == 0) h0 = false; else h1 = false;
+      }
+    }
+    if (h0 && h1) {
+      const bool first0 = t0 <= t1;
+      stack[sp * stride] = first0 ? ix.y : ix.x;
+      ++sp;
+      node = first0 ? ix.x : ix.y;
+    } else if (h0) {
+      node = ix.x;
+    } else if (h1) {
+      node = ix.y;
+    } else {
+      if (sp == 0) break;
+      --sp;
+      node = stack[sp * stride];
+    }
+  }
+  return false;
+}
+
+// closest hit over analytic spheres, analytic quads and instanced BVHs
+template <bool COUNT>
+__device__ void closest_hit(const SceneHdr& S, const Node* nodes, const Tri* tris, V3 o, V3 d,
+                            Hit& h, int* stack, int stride, Counters& cnt) {
+  h.t = __builtin_huge_valf();
+  h.id = -1;
+  h.slot = -1;
+  const float tmax = __builtin_huge_valf();
+  for (int i = 0; i < S.n_sph; ++i) {
+    float t;
+    if (hit_sphere(o, d, S.sph[i], tmax, &t)) keep_closer(h, t, i, -1);
+  }
+  for (int i = 0; i < S.n_quad; ++i) {
+    float t;
+    if (hit_quad(o, d, S.quad[i], tmax, &t)) keep_closer(h, t, S.n_sph + i, -1);
+  }
+  for (int m = 0; m < S.n_inst; ++m) {
+    if (S.inst_root[m] < 0) continue;
+    const V3 om = mk(o.x - S.inst_xlate[m][0], o.y - S.inst_xlate[m][1], o.z - S.inst_xlate[m][2]);
+    traverse<false, COUNT>(nodes, tris, S.inst_root[m], om, d, tmax, h, stack, stride, cnt);
+  }
+}
+
+// any non-emissive primitive with t in (0, tmax)
+template <bool COUNT>
+__device__ bool occluded(const SceneHdr& S, const Node* nodes, const Tri* tris, V3 o, V3 d,
+                         float tmax, int* stack, int stride, Counters& cnt) {
+  for (int i = 0; i < S.n_sph; ++i) {
+    float t;
+    if (hit_sphere(o, d, S.sph[i], tmax, &t)) return true;
+  }
+  for (int i = 0; i < S.n_quad; ++i) {
+    if (S.mat_type[S.quad_mat[i]] == PRDPT_MAT_EMISSIVE) continue;
+    float t;
+    if (hit_quad(o, d, S.quad[i], tmax, &t)) return true;
+  }
+  Hit h;
+  h.t = __builtin_huge_valf();
+  h.id = -1;
+  h.slot = -1;
+  for (int m = 0; m < S.n_inst; ++m) {
+    if (S.inst_root[m] < 0) continue;
+    const V3 om = mk(o.x - S.inst_xlate[m][0], o.y - S.inst_xlate[m][1], o.z - S.inst_xlate[m][2]);
+    if (traverse<true, COUNT>(nodes, tris, S.inst_root[m], om, d, tmax, h, stack, stride, cnt))
+      return true;
+  }
+  return false;
+}
+
+__device__ __forceinline__ V3 offset_origin(V3 p, V3 n) {
+  const float m = fmaxf(fabsf(p.x), fmaxf(fabsf(p.y), fabsf(p.z)));
+  const float eps = 1e-4f * fmaxf(1.0f, m);
+  return mk(p.x + n.x * eps, p.y + n.y * eps, p.z + n.z * eps);
+}
+
+// orthonormal basis around a unit vector (Duff et al., JCGT 2017)
+__device__ __forceinline__ void basis(V3 n, V3* b1, V3* b2) {
+  const float sign = copysignf(1.0f, n.z);
+  const float a = -1.0f / (sign + n.z);
+  const float b = n.x * n.y * a;
+  *b1 = mk(1.0f + sign * n.x * n.x * a, sign * b, -sign * n.x);
+  *b2 = mk(b, sign + n.y * n.y * a, -n.y);
+}
+
+__device__ __forceinline__ float fresnel_dielectric(float cosi, float ei, float et) {
+  const float eta = ei / et;
+  const float sin2t = (eta * eta) * (1.0f - cosi * cosi);
+  if (sin2t >= 1.0f) return 1.0f;
+  const float cost = sqrtf(1.0f - sin2t);
+  const float rs = (ei * cosi - et * cost) / (ei * cosi + et * cost);
+  const float rp = (et * cosi - ei * cost) / (et * cosi + ei * cost);
+  return 0.5f * (rs * rs + rp * rp);
+}
+
+__device__ __forceinline__ uint4 path_words(uint32_t k0, uint32_t k1, int pix, int smp, int pair,
+                                            int tag, int slot, int sub) {
+  return philox10(make_uint4((uint32_t)pix, (uint32_t)smp, (uint32_t)pair,
+                             ((uint32_t)tag << 24) | ((uint32_t)slot << 8) | (uint32_t)sub),
+                  k0, k1);
+}
+
+constexpr float kInvPi = 0.318309886183790671538f;
+
+// One camera path (same conventions as the CPU reference).
+template <bool COUNT>
+__device__ void radiance(const SceneHdr& S, const Node* nodes, const Tri* tris, uint32_t k0,
+                         uint32_t k1, int pix, int x, int y, int smp, int pair, int tag,
+                         int* stack, int stride, Counters& cnt, float L[3]) {
+  L[0] = L[1] = L[2] = 0.0f;
+  float jx = 0.5f, jy = 0.5f;
+  if (!S.pixel_center) {
+    const uint4 w = path_words(k0, k1, pix, smp, pair, tag, 0, 0);
+    jx = unit_open(w.x);
+    jy = unit_open(w.y);
+  }
+  const float px = (float)x + jx, py = (float)y + jy;
+  const float sx = 2.0f * (px / (float)S.W) - 1.0f;
+  const float sy = 1.0f - 2.0f * (py / (float)S.H);
+  V3 o = ld3(S.eye);
+  V3 d = unit(mk(S.fwd[0] + S.right[0] * sx + S.up[0] * sy, S.fwd[1] + S.right[1] * sx + S.up[1] * sy,
+                 S.fwd[2] + S.right[2] * sx + S.up[2] * sy));
+  float beta[3] = {1.0f, 1.0f, 1.0f};
+  bool specular = true;
+  for (int v = 0; v <= S.B; ++v) {
+    Hit h;
+    closest_hit<COUNT>(S, nodes, tris, o, d, h, stack, stride, cnt);
+    if (h.id < 0) {
+      for (int c = 0; c < 3; ++c) L[c] = L[c] + beta[c] * S.env[c];
+      break;
+    }
+    const V3 p = at(o, d, h.t);
+    int mat;
+    V3 ng;
+    if (h.id < S.n_sph) {
+      mat = S.sph_mat[h.id];
+      ng = unit(sub(p, ld3(S.sph[h.id])));
+    } else if (h.id < S.tri_id_base) {
+      const int qi = h.id - S.n_sph;
+      mat = S.quad_mat[qi];
+      ng = unit(cross(ld3(S.quad[qi] + 3), ld3(S.quad[qi] + 6)));
+    } else {
+      const Tri& t = tris[h.slot];
+      mat = t.mat;
+      ng = unit(cross(mk(t.e1x, t.e1y, t.e1z), mk(t.e2x, t.e2y, t.e2z)));
+    }
+    const int mt = S.mat_type[mat];
+    if (mt == PRDPT_MAT_EMISSIVE) {
+      if (specular && dot(d, ng) < 0.0f)
+        for (int c = 0; c < 3; ++c) L[c] = L[c] + beta[c] * S.mat_rgb[mat][c];
+      break;
+    }
+    const uint4 w = path_words(k0, k1, pix, smp, pair, tag, v + 1, 0);
+    if (mt == PRDPT_MAT_DIFFUSE) {
+      const V3 n = dot(ng, d) > 0.0f ? neg(ng) : ng;
+      const float f[3] = {S.mat_rgb[mat][0] * kInvPi, S.mat_rgb[mat][1] * kInvPi,
+                          S.mat_rgb[mat][2] * kInvPi};
+      for (int l = 0; l < S.n_pl; ++l) {
+        const float* lp = S.pl[l];
+        const V3 toL = sub(ld3(lp), p);
+        const float dist2 = dot(toL, toL);
+        const float dist = sqrtf(dist2);
+        const V3 wi = scale(toL, 1.0f / dist);
+        const float cx = dot(n, wi);
+        if (!(cx > 0.0f)) continue;
+        if (occluded<COUNT>(S, nodes, tris, offset_origin(p, n), wi, dist * 0.9999f, stack, stride, cnt))
+          continue;
+        for (int c = 0; c < 3; ++c) L[c] = L[c] + beta[c] * f[c] * ((lp[3 + c] * cx) / dist2);
+      }
+      for (int ai = 0; ai < S.n_area; ++ai) {
+        const int qi = S.area_quad[ai];
+        float a, b;
+        if (ai == 0) {
+          a = unit_open(w.x);
+          b = unit_open(w.y);
+        } else {
+          const uint4 w2 = path_words(k0, k1, pix, smp, pair, tag, v + 1, ai);
+          a = unit_open(w2.x);
+          b = unit_open(w2.y);
+        }
+        const float* qd = S.quad[qi];
+        const V3 qo = ld3(qd), e1 = ld3(qd + 3), e2 = ld3(qd + 6);
+        const V3 yl = mk(qo.x + e1.x * a + e2.x * b, qo.y + e1.y * a + e2.y * b,
+                         qo.z + e1.z * a + e2.z * b);
+        const V3 nl = cross(e1, e2);
+        const float area = sqrtf(dot(nl, nl));
+        const V3 nlu = scale(nl, 1.0f / area);
+        const V3 toL = sub(yl, p);
+        const float dist2 = dot(toL, toL);
+        const float dist = sqrtf(dist2);
+        const V3 wi = scale(toL, 1.0f / dist);
+        const float cx = dot(n, wi);
+        const float cl = -dot(nlu, wi);
+        if (!(cx > 0.0f && cl > 0.0f)) continue;
+        if (occluded<COUNT>(S, nodes, tris, offset_origin(p, n), wi, dist * 0.9999f, stack, stride, cnt))
+          continue;
+        const float G = ((cx * cl) * area) / dist2;
+        const int qm = S.quad_mat[qi];
+        for (int c = 0; c < 3; ++c) L[c] = L[c] + beta[c] * f[c] * S.mat_rgb[qm][c] * G;
+      }
+      if (v == S.B) break;
+      const float u1 = unit_open(w.z), u2 = unit_open(w.w);
+      const float r = sqrtf(u1);
+      float sn, cs;
+      sincos_turn(u2, &sn, &cs);
+      const float lx = r * cs, ly = r * sn, lz = sqrtf(1.0f - u1);
+      V3 b1, b2;
+      basis(n, &b1, &b2);
+      const V3 nd = unit(mk(b1.x * lx + b2.x * ly + n.x * lz, b1.y * lx + b2.y * ly + n.y * lz,
+                            b1.z * lx + b2.z * ly + n.z * lz));
+      o = offset_origin(p, n);
+      d = nd;
+      for (int c = 0; c < 3; ++c) beta[c] = beta[c] * S.mat_rgb[mat][c];
+      specular = false;
+    } else {  // dielectric sphere
+      if (v == S.B) break;
+      const float ior = S.mat_ior[mat];
+      V3 n = ng;
+      float cosi = -dot(d, n);
+      float ei = 1.0f, et = ior;
+      if (cosi < 0.0f) {
+        n = neg(n);
+        cosi = -cosi;
+        ei = ior;
+        et = 1.0f;
+      }
+      const float F = fresnel_dielectric(cosi, ei, et);
+      const float u = unit_open(w.z);
+      V3 nd, side;
+      if (u < F) {
+        const float dn = dot(d, n);
+        nd = mk(d.x - n.x * (2.0f * dn), d.y - n.y * (2.0f * dn), d.z - n.z * (2.0f * dn));
+        side = n;
+      } else {
+        const float eta = ei / et;
+        const float sin2t = (eta * eta) * (1.0f - cosi * cosi);
+        const float cost = sqrtf(1.0f - sin2t);
+        const float kk = eta * cosi - cost;
+        nd = mk(d.x * eta + n.x * kk, d.y * eta + n.y * kk, d.z * eta + n.z * kk);
+        side = neg(n);
+      }
+      o = offset_origin(p, side);
+      d = unit(nd);
+      specular = true;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// kernels
+// ---------------------------------------------------------------------------
+constexpr int kTileW = 16, kTileH = 8, kBlock = kTileW * kTileH;  // two 8x8 waves
+
+// Load the scene constants into LDS and apply perturbation k's parameter values.
+__device__ __forceinline__ void load_state(SceneHdr& S, const SceneHdr* __restrict__ g,
+                                           const float* __restrict__ X, int d) {
+  const uint32_t* src = reinterpret_cast<const uint32_t*>(g);
+  uint32_t* dst = reinterpret_cast<uint32_t*>(&S);
+  constexpr int words = sizeof(SceneHdr) / 4;
+  for (int i = threadIdx.x; i < words; i += blockDim.x) dst[i] = src[i];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int j = 0; j < d; ++j) {
+      const int kind = S.bind_kind[j], i = S.bind_index[j], c = S.bind_comp[j];
+      const float xj = X[j];
+      if (kind == PRDPT_BIND_SPHERE) S.sph[i][c] = g->sph[i][c] + xj;
+      else if (kind == PRDPT_BIND_QUAD) S.quad[i][c] = g->quad[i][c] + xj;
+      else if (kind == PRDPT_BIND_MESH) S.inst_xlate[i][c] = g->inst_xlate[i][c] + xj;
+      else S.pl[i][c] = g->pl[i][c] + xj;
+    }
+  }
+  __syncthreads();
+}
+
+// Fused render + loss.  grid.x = pixel tiles (16x8), grid.y = perturbation k.
+// Writes partial[k][tile] = sum over the tile's pixels of sum_c (I - R)^2 when
+// ref != nullptr, and the image when img != nullptr.
+template <bool COUNT>
+__global__ __launch_bounds__(kBlock) void render_loss_kernel(
+    DevScene scene, const float* __restrict__ X, int d, int tag, uint32_t k0, uint32_t k1,
+    const float* __restrict__ ref, float* __restrict__ img, float* __restrict__ partial,
+    unsigned long long* __restrict__ counters) {
+  __shared__ SceneHdr S;
+  __shared__ int stack[kStackDepth * kBlock];
+  __shared__ float wsum[kBlock / 64];
+  const int k = blockIdx.y;
+  load_state(S, scene.hdr, X + (size_t)k * d, d);
+  const int tiles_x = (S.W + kTileW - 1) / kTileW;
+  const int tile = blockIdx.x;
+  const int t = threadIdx.x;
+  const int lx = (t & 7) + 8 * (t >> 6), ly = (t >> 3) & 7;
+  const int x = (tile % tiles_x) * kTileW + lx, y = (tile / tiles_x) * kTileH + ly;
+  float e = 0.0f;
+  Counters cnt{0u, 0u};
+  if (x < S.W && y < S.H) {
+    const int pix = y * S.W + x;
+    const int pair = k >> 1;
+    float acc[3] = {0.0f, 0.0f, 0.0f};
+    for (int s = 0; s < S.spp; ++s) {
+      float L[3];
+      radiance<COUNT>(S, scene.nodes, scene.tris, k0, k1, pix, x, y, s, pair, tag, stack + t,
+                      kBlock, cnt, L);
+      acc[0] = acc[0] + L[0];
+      acc[1] = acc[1] + L[1];
+      acc[2] = acc[2] + L[2];
+    }
+    const float inv_spp = 1.0f / (float)S.spp;
+    const float I0 = acc[0] * inv_spp, I1 = acc[1] * inv_spp, I2 = acc[2] * inv_spp;
+    const size_t npix = (size_t)S.W * S.H;
+    if (img) {
+      float* o = img + ((size_t)k * npix + pix) * 3;
+      o[0] = I0;
+      o[1] = I1;
+      o[2] = I2;
+    }
+    if (ref) {
+      const float* r = ref + (size_t)pix * 3;
+      const float d0 = I0 - r[0], d1 = I1 - r[1], d2 = I2 - r[2];
+      e = d0 * d0 + d1 * d1 + d2 * d2;
+    }
+  }
+  if (COUNT) {
+    atomicAdd(&counters[0], (unsigned long long)cnt.nodes);
+    atomicAdd(&counters[1], (unsigned long long)cnt.tris);
+  }
+  if (partial) {
+    // fixed-order butterfly within the wave, then the waves in order
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) e += __shfl_xor(e, off, 64);
+    if ((t & 63) == 0) wsum[t >> 6] = e;
+    __syncthreads();
+    if (t == 0) {
+      float s = wsum[0];
+      for (int w = 1; w < kBlock / 64; ++w) s = s + wsum[w];
+      partial[(size_t)k * gridDim.x + tile] = s;
+    }
+  }
+}
+
+// One thread per antithetic pair: tau_p, weights c_p and the two parameter rows.
+__global__ void tau_kernel(int est, int d, int P, uint32_t k0, uint32_t k1,
+                           const float* __restrict__ sigma, const float* __restrict__ theta,
+                           double cd, double sqrt2pi, float* __restrict__ tau,
+                           double* __restrict__ c, float* __restrict__ X) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  uint32_t blk = 0;
+  int used = 4;
+  uint4 w = make_uint4(0, 0, 0, 0);
+  auto word = [&]() -> uint32_t {
+    if (used == 4) {
+      w = philox10(make_uint4((uint32_t)p, blk, 0u, (uint32_t)kTagTau << 24), k0, k1);
+      ++blk;
+      used = 0;
+    }
+    const uint32_t r = used == 0 ? w.x : used == 1 ? w.y : used == 2 ? w.z : w.w;
+    ++used;
+    return r;
+  };
+  auto gauss2 = [&](float* z0, float* z1) {
+    const float u1 = unit_open(word());
+    const float u2 = unit_open(word());
+    const float rad = sqrtf(-2.0f * log_ieee(u1));
+    float sn, cs;
+    sincos_turn(u2, &sn, &cs);
+    *z0 = rad * cs;
+    *z1 = rad * sn;
+  };
+  float v[PRDPT_MAX_PARAMS];
+  float tv[PRDPT_MAX_PARAMS];
+  double cw[PRDPT_MAX_PARAMS];
+  if (est == PRDPT_EST_GAUSS) {
+    for (int j = 0; j < d; j += 2) {
+      float z0, z1;
+      gauss2(&z0, &z1);
+      v[j] = z0;
+      if (j + 1 < d) v[j + 1] = z1;
+    }
+    for (int j = 0; j < d; ++j) {
+      tv[j] = sigma[j] * v[j];
+      cw[j] = (double)v[j] / (2.0 * (double)sigma[j]);
+    }
+  } else if (est == PRDPT_EST_IS) {
+    const int m = (d + 1) / 2;
+    float acc = 0.0f;
+    for (int i = 0; i < m; ++i) acc = acc + log_ieee(unit_open(word()));
+    float rho2 = -2.0f * acc;
+    if ((d + 1) & 1) {
+      float z0, z1;
+      gauss2(&z0, &z1);
+      rho2 = rho2 + z0 * z0;
+    }
+    for (int j = 0; j < d; j += 2) {
+      float z0, z1;
+      gauss2(&z0, &z1);
+      v[j] = z0;
+      if (j + 1 < d) v[j + 1] = z1;
+    }
+    float n2 = 0.0f;
+    for (int j = 0; j < d; ++j) n2 = n2 + v[j] * v[j];
+    const float nrm = sqrtf(n2);
+    const float rho = sqrtf(rho2);
+    for (int j = 0; j < d; ++j) {
+      const float uj = v[j] / nrm;
+      tv[j] = sigma[j] * (rho * uj);
+      cw[j] = cd * (double)uj / (2.0 * (double)sigma[j]);
+    }
+  } else {
+    for (int j = 0; j < d; ++j) v[j] = sqrtf(-2.0f * log_ieee(unit_open(word())));
+    const uint32_t bits = word();
+    for (int j = 0; j < d; ++j) {
+      const float sg = ((bits >> j) & 1u) ? -1.0f : 1.0f;
+      tv[j] = sigma[j] * (sg * v[j]);
+      cw[j] = (double)sg / ((double)sigma[j] * sqrt2pi);
+    }
+  }
+  for (int j = 0; j < d; ++j) {
+    tau[(size_t)p * d + j] = tv[j];
+    c[(size_t)p * d + j] = cw[j];
+    X[(size_t)(2 * p) * d + j] = theta[j] + tv[j];
+    X[(size_t)(2 * p + 1) * d + j] = theta[j] - tv[j];
+  }
+}
+
+// Per-image losses L_k = (sum of tile partials) / (3 H W), in binary64, one wave
+// per image with a fixed summation order.
+__global__ void loss_kernel(const float* __restrict__ partial, int n_tiles, int N, double inv_den,
+                            double* __restrict__ losses) {
+  const int k = blockIdx.x;
+  const int lane = threadIdx.x;
+  double s = 0.0;
+  for (int i = lane; i < n_tiles; i += 64) s += (double)partial[(size_t)k * n_tiles + i];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if (lane == 0) losses[k] = s * inv_den;
+}
+
+// g_j = scale (1/P) sum_p c_pj (L_2p - L_2p+1) and Q = mean L, in binary64 and pair order.
+__global__ void combine_kernel(int P, int d, const double* __restrict__ c,
+                               const double* __restrict__ L, const double* __restrict__ scale,
+                               double* __restrict__ grad, double* __restrict__ loss) {
+  const int j = threadIdx.x;
+  const double sc = scale ? *scale : 1.0;
+  if (j < d) {
+    double acc = 0.0;
+    for (int p = 0; p < P; ++p) acc += c[(size_t)p * d + j] * (L[2 * p] - L[2 * p + 1]);
+    grad[j] = sc * (acc / (double)P);
+  }
+  if (j == 0 && loss) {
+    double s = 0.0;
+    for (int k = 0; k < 2 * P; ++k) s += L[k];
+    *loss = s / (double)(2 * P);
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// launchers (host)
+// ---------------------------------------------------------------------------
+int render_tiles(int W, int H) { return ((W + kTileW - 1) / kTileW) * ((H + kTileH - 1) / kTileH); }
+
+hipError_t launch_tau(hipStream_t st, int est, int d, int P, uint64_t seed, const float* sigma,
+                      const float* theta, double cd, double sqrt2pi, float* tau, double* c, float* X) {
+  const int bs = 64;
+  hipLaunchKernelGGL(tau_kernel, dim3((P + bs - 1) / bs), dim3(bs), 0, st, est, d, P,
+                     (uint32_t)seed, (uint32_t)(seed >> 32), sigma, theta, cd, sqrt2pi, tau, c, X);
+  return hipGetLastError();
+}
+
+hipError_t launch_render(hipStream_t st, const DevScene& sc, int W, int H, const float* X, int nk,
+                         int d, int tag, uint64_t seed, const float* ref, float* img,
+                         float* partial, unsigned long long* counters) {
+  dim3 grid(render_tiles(W, H), nk);
+  if (counters)
+    hipLaunchKernelGGL(render_loss_kernel<true>, grid, dim3(kBlock), 0, st, sc, X, d, tag,
+                       (uint32_t)seed, (uint32_t)(seed >> 32), ref, img, partial, counters);
+  else
+    hipLaunchKernelGGL(render_loss_kernel<false>, grid, dim3(kBlock), 0, st, sc, X, d, tag,
+                       (uint32_t)seed, (uint32_t)(seed >> 32), ref, img, partial, counters);
+  return hipGetLastError();
+}
+
+hipError_t launch_losses(hipStream_t st, const float* partial, int n_tiles, int N, int npix,
+                         double* losses) {
+  hipLaunchKernelGGL(loss_kernel, dim3(N), dim3(64), 0, st, partial, n_tiles, N,
+                     1.0 / (3.0 * (double)npix), losses);
+  return hipGetLastError();
+}
+
+hipError_t launch_combine(hipStream_t st, int P, int d, const double* c, const double* L,
+                          const double* scale, double* grad, double* loss) {
+  hipLaunchKernelGGL(combine_kernel, dim3(1), dim3(64), 0, st, P, d, c, L, scale, grad, loss);
+  return hipGetLastError();
+}
+
+}  // namespace prdpt

@@ -1,0 +1,285 @@
+"""Thin ctypes binding of libprdpt.so (argument marshalling only).
+
+Every function here has the name of the C entry point it calls.  Device buffers
+are torch tensors on the context's device (torch supplies memory and streams
+only); host vectors are numpy arrays.  The binding fails loudly if the HIP
+library is missing: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libprdpt.so")
+
+PRDPT_OK = 0
+PRDPT_E_ARG, PRDPT_E_NOMEM, PRDPT_E_ADMISSION, PRDPT_E_HIP = -1, -2, -3, -4
+PRDPT_E_SCENE, PRDPT_E_CANCELLED, PRDPT_E_TIMEOUT = -5, -6, -7
+PRDPT_EST_GAUSS, PRDPT_EST_IS, PRDPT_EST_IS_PERDIM = 0, 1, 2
+
+# every symbol declared in include/prdpt.h
+EXPORTS = [
+    "prdpt_last_error", "prdpt_ctx_create", "prdpt_ctx_destroy", "prdpt_ctx_set_stream",
+    "prdpt_ctx_resident_bytes", "prdpt_ctx_synchronize", "prdpt_scene_create",
+    "prdpt_scene_destroy", "prdpt_scene_info", "prdpt_draw_tau", "prdpt_render_perturbed",
+    "prdpt_render_reference", "prdpt_smoothed_loss", "prdpt_grad_estimate",
+    "prdpt_grad_estimate_async", "prdpt_combine_async",
+]
+
+
+class PrdptError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"prdpt error {code}: {msg}")
+        self.code = code
+
+
+class SceneDesc(C.Structure):
+    _fields_ = [("eye", C.c_float * 3), ("fwd", C.c_float * 3), ("right", C.c_float * 3),
+                ("up", C.c_float * 3),
+                ("width", C.c_int32), ("height", C.c_int32), ("spp", C.c_int32),
+                ("max_bounces", C.c_int32), ("pixel_center", C.c_int32),
+                ("env", C.c_float * 3),
+                ("n_materials", C.c_int32), ("mat_type", C.c_void_p), ("mat_rgb", C.c_void_p),
+                ("mat_ior", C.c_void_p),
+                ("n_spheres", C.c_int32), ("spheres", C.c_void_p), ("sphere_mat", C.c_void_p),
+                ("n_quads", C.c_int32), ("quads", C.c_void_p), ("quad_mat", C.c_void_p),
+                ("n_meshes", C.c_int32), ("mesh_offset", C.c_void_p), ("mesh_mat", C.c_void_p),
+                ("mesh_translation", C.c_void_p),
+                ("n_triangles", C.c_int32), ("triangles", C.c_void_p),
+                ("n_point_lights", C.c_int32), ("point_lights", C.c_void_p),
+                ("n_params", C.c_int32), ("bindings", C.c_void_p)]
+
+
+_lib = None
+
+
+def load():
+    """Load libprdpt.so (after torch, so both share one HIP runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    import torch  # noqa: F401  (HIP runtime of the process)
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          f"`python -m paper_2211_17263_amd.build` (hipcc, gfx950)")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, u64, sz = C.c_void_p, C.c_int, C.c_uint64, C.c_size_t
+    pvp = C.POINTER(C.c_void_p)
+    L.prdpt_last_error.restype = C.c_char_p
+    L.prdpt_ctx_create.argtypes = [i32, vp, sz, pvp]
+    L.prdpt_ctx_destroy.argtypes = [vp]
+    L.prdpt_ctx_set_stream.argtypes = [vp, vp]
+    L.prdpt_ctx_resident_bytes.argtypes = [vp, C.POINTER(C.c_size_t)]
+    L.prdpt_ctx_synchronize.argtypes = [vp]
+    L.prdpt_scene_create.argtypes = [vp, C.POINTER(SceneDesc), pvp, C.POINTER(C.c_size_t)]
+    L.prdpt_scene_destroy.argtypes = [vp]
+    L.prdpt_scene_info.argtypes = [vp] + [C.POINTER(C.c_int)] * 5
+    L.prdpt_draw_tau.argtypes = [vp, i32, i32, i32, u64, vp, vp, vp]
+    L.prdpt_render_perturbed.argtypes = [vp, vp, vp, i32, u64, i32, vp, vp]
+    L.prdpt_render_reference.argtypes = [vp, vp, u64, vp]
+    L.prdpt_smoothed_loss.argtypes = [vp, vp, vp, vp, i32, u64, vp]
+    L.prdpt_grad_estimate.argtypes = [vp, vp, vp, vp, i32, u64, i32, vp, vp, vp]
+    L.prdpt_grad_estimate_async.argtypes = [vp, vp, vp, vp, i32, u64, i32, vp, vp, vp, vp]
+    L.prdpt_combine_async.argtypes = [vp, i32, i32, vp, vp, vp, vp]
+    for name in EXPORTS:
+        if name != "prdpt_last_error":
+            getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+def _check(rc):
+    if rc != PRDPT_OK:
+        raise PrdptError(rc, load().prdpt_last_error().decode())
+    return rc
+
+
+def _host(a, dtype):
+    a = np.ascontiguousarray(np.asarray(a, dtype))
+    return a, a.ctypes.data_as(C.c_void_p)
+
+
+def _dev(t, dtype=None):
+    import torch
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError("expected a device tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"expected dtype {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError("device tensor must be contiguous")
+    return C.c_void_p(t.data_ptr())
+
+
+class Context:
+    """prdpt_ctx: one device, one HIP stream (default: torch's current stream)."""
+
+    def __init__(self, device=0, stream=None, hbm_budget=0):
+        import torch
+        L = load()
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.device = device
+        self.stream = stream
+        h = C.c_void_p()
+        _check(L.prdpt_ctx_create(int(device), C.c_void_p(stream.cuda_stream if stream is not None else 0),
+                                  int(hbm_budget), C.byref(h)))
+        self.h = h
+
+    def resident_bytes(self):
+        v = C.c_size_t()
+        _check(load().prdpt_ctx_resident_bytes(self.h, C.byref(v)))
+        return v.value
+
+    def synchronize(self):
+        _check(load().prdpt_ctx_synchronize(self.h))
+
+    def set_stream(self, stream):
+        _check(load().prdpt_ctx_set_stream(self.h, C.c_void_p(stream.cuda_stream if stream else 0)))
+        self.stream = stream
+
+    def close(self):
+        if getattr(self, "h", None):
+            _check(load().prdpt_ctx_destroy(self.h))
+            self.h = None
+
+
+def scene_desc(scene):
+    """Fill a prdpt_scene_desc from a generator Scene; returns (desc, keep-alive)."""
+    a = scene.arrays()
+    d = SceneDesc()
+    for nm in ("eye", "fwd", "right", "up"):
+        getattr(d, nm)[:] = [float(v) for v in getattr(scene, nm)]
+    d.env[:] = [float(v) for v in scene.env]
+    d.width, d.height, d.spp = scene.width, scene.height, scene.spp
+    d.max_bounces, d.pixel_center = scene.max_bounces, scene.pixel_center
+    ptr = lambda x: x.ctypes.data if x.size else None
+    d.n_materials = a["mat_type"].size
+    d.mat_type, d.mat_rgb, d.mat_ior = ptr(a["mat_type"]), ptr(a["mat_rgb"]), ptr(a["mat_ior"])
+    d.n_spheres = a["spheres"].shape[0]
+    d.spheres, d.sphere_mat = ptr(a["spheres"]), ptr(a["sphere_mat"])
+    d.n_quads = a["quads"].shape[0]
+    d.quads, d.quad_mat = ptr(a["quads"]), ptr(a["quad_mat"])
+    d.n_meshes = a["mesh_mat"].size
+    d.mesh_offset, d.mesh_mat, d.mesh_translation = (ptr(a["mesh_off"]), ptr(a["mesh_mat"]),
+                                                     ptr(a["mesh_xlate"]))
+    d.n_triangles = a["tris"].shape[0]
+    d.triangles = ptr(a["tris"])
+    d.n_point_lights = a["plights"].shape[0]
+    d.point_lights = ptr(a["plights"])
+    d.n_params = a["bindings"].shape[0]
+    d.bindings = ptr(a["bindings"])
+    return d, a
+
+
+class Scene:
+    """prdpt_scene: resident scene handle."""
+
+    def __init__(self, ctx, h, footprint, width, height, spp, bounces, d):
+        self.ctx, self.h, self.footprint = ctx, h, footprint
+        self.W, self.H, self.spp, self.B, self.d = width, height, spp, bounces, d
+
+    def destroy(self):
+        if getattr(self, "h", None):
+            _check(load().prdpt_scene_destroy(self.h))
+            self.h = None
+
+
+def prdpt_scene_create(ctx, scene):
+    desc, keep = scene_desc(scene)
+    h = C.c_void_p()
+    fp = C.c_size_t()
+    _check(load().prdpt_scene_create(ctx.h, C.byref(desc), C.byref(h), C.byref(fp)))
+    del keep
+    ints = [C.c_int() for _ in range(5)]
+    _check(load().prdpt_scene_info(h, *[C.byref(i) for i in ints]))
+    return Scene(ctx, h, fp.value, *[i.value for i in ints])
+
+
+def prdpt_scene_destroy(scene):
+    scene.destroy()
+
+
+def prdpt_draw_tau(ctx, est, sigma, P, seed):
+    sig, sp = _host(sigma, np.float32)
+    d = sig.size
+    tau = np.zeros((P, d), np.float32)
+    c = np.zeros((P, d), np.float64)
+    _check(load().prdpt_draw_tau(ctx.h, int(est), d, int(P), int(seed), sp,
+                                 tau.ctypes.data_as(C.c_void_p), c.ctypes.data_as(C.c_void_p)))
+    return tau, c
+
+
+def prdpt_render_perturbed(scene, theta, sigma, N, seed, est, images=None):
+    import torch
+    th, tp = _host(theta, np.float32)
+    sg, sp = _host(sigma, np.float32)
+    if th.size != scene.d or sg.size != scene.d:
+        raise ValueError("theta/sigma length must equal the scene's parameter count")
+    if images is None:
+        images = torch.empty((N, scene.H, scene.W, 3), dtype=torch.float32,
+                             device=f"cuda:{scene.ctx.device}")
+    tau = np.zeros((max(N // 2, 1), scene.d), np.float32)
+    _check(load().prdpt_render_perturbed(scene.h, tp, sp, int(N), int(seed), int(est),
+                                         _dev(images, torch.float32), tau.ctypes.data_as(C.c_void_p)))
+    return images, tau
+
+
+def prdpt_render_reference(scene, X, seed, image=None):
+    import torch
+    x, xp = _host(X, np.float32)
+    if x.size != scene.d:
+        raise ValueError("X length must equal the scene's parameter count")
+    if image is None:
+        image = torch.empty((scene.H, scene.W, 3), dtype=torch.float32,
+                            device=f"cuda:{scene.ctx.device}")
+    _check(load().prdpt_render_reference(scene.h, xp, int(seed), _dev(image, torch.float32)))
+    return image
+
+
+def prdpt_smoothed_loss(scene, ref, theta, sigma, N, seed):
+    import torch
+    th, tp = _host(theta, np.float32)
+    sg, sp = _host(sigma, np.float32)
+    if th.size != scene.d or sg.size != scene.d:
+        raise ValueError("theta/sigma length must equal the scene's parameter count")
+    out = C.c_double()
+    _check(load().prdpt_smoothed_loss(scene.h, _dev(ref, torch.float32), tp, sp, int(N), int(seed),
+                                      C.byref(out)))
+    return out.value
+
+
+def prdpt_grad_estimate(scene, ref, theta, sigma, N, seed, est):
+    """Returns dict(grad=float64[d], loss=Q estimate, losses=float64[N])."""
+    import torch
+    th, tp = _host(theta, np.float32)
+    sg, sp = _host(sigma, np.float32)
+    if th.size != scene.d or sg.size != scene.d:
+        raise ValueError("theta/sigma length must equal the scene's parameter count")
+    g = np.zeros(scene.d, np.float64)
+    q = C.c_double()
+    L = np.zeros(max(int(N), 1), np.float64)
+    _check(load().prdpt_grad_estimate(scene.h, _dev(ref, torch.float32), tp, sp, int(N), int(seed),
+                                      int(est), g.ctypes.data_as(C.c_void_p), C.byref(q),
+                                      L.ctypes.data_as(C.c_void_p)))
+    return dict(grad=g, loss=q.value, losses=L)
+
+
+def prdpt_grad_estimate_async(scene, ref, theta, sigma, N, seed, est, grad, loss, losses=None,
+                              c=None):
+    import torch
+    _check(load().prdpt_grad_estimate_async(
+        scene.h, _dev(ref, torch.float32), _dev(theta, torch.float32), _dev(sigma, torch.float32),
+        int(N), int(seed), int(est), _dev(grad, torch.float64), _dev(loss, torch.float64),
+        _dev(losses, torch.float64) if losses is not None else None,
+        _dev(c, torch.float64) if c is not None else None))
+
+
+def prdpt_combine_async(ctx, P, d, c, losses, scale, grad):
+    import torch
+    _check(load().prdpt_combine_async(ctx.h, int(P), int(d), _dev(c, torch.float64),
+                                      _dev(losses, torch.float64),
+                                      _dev(scale, torch.float64) if scale is not None else None,
+                                      _dev(grad, torch.float64)))

@@ -1,0 +1,266 @@
+"""HIP path vs CPU oracle, element by element, through the C ABI (needs a GPU).
+
+Every case prints its name, shapes and seed before touching the GPU so that a
+failing run names the case.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2211_17263_amd import scenes as S
+from tests import parity as PT
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_2211_17263_amd import native as NV
+    assert torch.cuda.is_available()
+    c = NV.Context(0)
+    yield c
+    c.synchronize()
+
+
+def gpu_scene(ctx, scene):
+    from paper_2211_17263_amd import native as NV
+    return NV.prdpt_scene_create(ctx, scene)
+
+
+def to_dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda()
+
+
+@pytest.mark.parametrize("mode", [O.GAUSS, O.IS, O.IS_PERDIM])
+@pytest.mark.parametrize("d", [1, 2, 3, 6, 12, 32])
+def test_perturbation_draw_bit_exact(ctx, mode, d):
+    from paper_2211_17263_amd import native as NV
+    say("draw_tau", mode, d)
+    sigma = np.linspace(0.05, 1.5, d).astype(np.float32)
+    tg, cg = NV.prdpt_draw_tau(ctx, mode, sigma, 777, 0x1234_5678_9ABC)
+    to, co = O.draw_tau(mode, sigma, 777, 0x1234_5678_9ABC)
+    assert np.array_equal(tg.view(np.uint32), to.view(np.uint32))
+    assert np.array_equal(cg.view(np.uint64), co.view(np.uint64))
+
+
+def _full_parity(ctx, pr, seed, what, N=None, est=None, check_images=True):
+    scene = pr["scene"]
+    N = N or pr["N"]
+    est = pr["est"] if est is None else est
+    say(what, f"{scene.width}x{scene.height} spp={scene.spp} B={scene.max_bounces}",
+        f"tris={scene.n_tris} N={N} est={est} seed={seed}")
+    from paper_2211_17263_amd import native as NV
+    osc = O.OracleScene(scene)
+    ref = osc.reference(pr["theta_ref"], seed=seed + 1)
+    gs = gpu_scene(ctx, scene)
+    try:
+        if check_images:
+            imgs, tau = NV.prdpt_render_perturbed(gs, pr["theta0"], pr["sigma"], N, seed, est)
+            oimgs, otau = osc.render_perturbed(pr["theta0"], pr["sigma"], N, seed, est)
+            assert np.array_equal(tau, otau)
+            gi = imgs.cpu().numpy()
+            for k in range(N):
+                PT.assert_images_match(gi[k], oimgs[k], f"{what} image {k}")
+        r = NV.prdpt_grad_estimate(gs, to_dev(ref), pr["theta0"], pr["sigma"], N, seed, est)
+        o = osc.grad_estimate(ref, pr["theta0"], pr["sigma"], N, seed, est)
+        _, c = O.draw_tau(est, pr["sigma"], N // 2, seed)
+        PT.assert_losses_match(r["losses"], o["losses"], what)
+        PT.assert_grad_match(r["grad"], o["grad"], c, o["losses"], what)
+        assert abs(r["loss"] - o["loss"]) <= PT.LOSS_REL * abs(o["loss"])
+        return r, o
+    finally:
+        gs.destroy()
+
+
+def test_toy_workload_full(ctx):
+    pr = S.toy_problem(seed=1)
+    r, o = _full_parity(ctx, pr, 11, "toy")
+    assert np.any(r["grad"] != 0)
+
+
+@pytest.mark.parametrize("seed", [3, 4])
+def test_toy_workload_is_mode(ctx, seed):
+    pr = S.toy_problem(seed=seed)
+    _full_parity(ctx, pr, seed, "toy-is", est=O.IS, N=8)
+
+
+def test_cornell_reduced(ctx):
+    pr = S.cornell_problem(seed=2, width=64, height=48, spp=4, ico_level=3)
+    _full_parity(ctx, pr, 5, "cornell-reduced")
+
+
+def test_caustic_reduced(ctx):
+    pr = S.caustic_problem(seed=3, width=96, height=72, spp=4, n_occluders=5000)
+    _full_parity(ctx, pr, 6, "caustic-reduced", N=8)
+
+
+def test_ragged_tiny_and_degenerate(ctx):
+    # ragged tile tail, N = 2 (one pair), d = 1, pixel-centre sampling, odd spp
+    sc = S.toy_scene(width=37, height=23, spp=3, pixel_center=0, bounces=2)
+    sc.bindings = sc.bindings[:1]
+    pr = dict(scene=sc, theta_ref=np.zeros(1, np.float32), theta0=np.array([0.4], np.float32),
+              sigma=np.array([0.25], np.float32), N=2, est=O.IS)
+    _full_parity(ctx, pr, 9, "ragged")
+    sc2 = S.toy_scene(width=1, height=1, spp=1, pixel_center=1)
+    pr2 = dict(scene=sc2, theta_ref=np.zeros(2, np.float32), theta0=np.array([0.1, 0.2], np.float32),
+               sigma=np.array([0.3, 0.3], np.float32), N=2, est=O.GAUSS)
+    _full_parity(ctx, pr2, 10, "one-pixel")
+
+
+def test_environment_and_glass(ctx):
+    from paper_2211_17263_amd import native as NV
+    for glass in (False, True):
+        sc = S.furnace_scene(glass=glass, bounces=6, spp=8, width=40, height=40)
+        sc.plight((2.0, 2.0, 2.0), (5.0, 5.0, 5.0))
+        sc.bind(S.BIND_SPHERE, 0, 0)
+        say("furnace", glass)
+        gs = gpu_scene(ctx, sc)
+        try:
+            X = np.array([0.15], np.float32)
+            img = NV.prdpt_render_reference(gs, X, 21).cpu().numpy()
+            oimg = O.OracleScene(sc).reference(X, seed=21)
+            PT.assert_images_match(img, oimg, f"furnace glass={glass}")
+        finally:
+            gs.destroy()
+
+
+def test_smoothed_loss_and_reference(ctx):
+    from paper_2211_17263_amd import native as NV
+    pr = S.cornell_problem(seed=2, width=40, height=40, spp=2, ico_level=2)
+    say("smoothed-loss")
+    osc = O.OracleScene(pr["scene"])
+    gs = gpu_scene(ctx, pr["scene"])
+    try:
+        ref_gpu = NV.prdpt_render_reference(gs, pr["theta_ref"], 4).cpu().numpy()
+        ref = osc.reference(pr["theta_ref"], seed=4)
+        PT.assert_images_match(ref_gpu, ref, "reference")
+        q = NV.prdpt_smoothed_loss(gs, to_dev(ref), pr["theta0"], pr["sigma"], 6, 12)
+        qo = osc.smoothed_loss(ref, pr["theta0"], pr["sigma"], 6, 12)
+        assert abs(q - qo) <= 1e-4 * qo
+    finally:
+        gs.destroy()
+
+
+def test_bitwise_reproducible(ctx):
+    from paper_2211_17263_amd import native as NV
+    pr = S.cornell_problem(seed=2, width=48, height=32, spp=2, ico_level=2)
+    say("reproducible")
+    ref = O.OracleScene(pr["scene"]).reference(pr["theta_ref"], seed=1)
+    gs = gpu_scene(ctx, pr["scene"])
+    try:
+        a = NV.prdpt_grad_estimate(gs, to_dev(ref), pr["theta0"], pr["sigma"], 8, 99, O.IS)
+        b = NV.prdpt_grad_estimate(gs, to_dev(ref), pr["theta0"], pr["sigma"], 8, 99, O.IS)
+        assert np.array_equal(a["grad"], b["grad"]) and np.array_equal(a["losses"], b["losses"])
+    finally:
+        gs.destroy()
+
+
+def test_async_and_combine(ctx):
+    import torch
+    from paper_2211_17263_amd import native as NV
+    pr = S.toy_problem(seed=5)
+    say("async")
+    ref = O.OracleScene(pr["scene"]).reference(pr["theta_ref"], seed=2)
+    gs = gpu_scene(ctx, pr["scene"])
+    try:
+        N, d = 6, 2
+        sync = NV.prdpt_grad_estimate(gs, to_dev(ref), pr["theta0"], pr["sigma"], N, 7, O.GAUSS)
+        g = torch.zeros(d, dtype=torch.float64, device="cuda")
+        q = torch.zeros(1, dtype=torch.float64, device="cuda")
+        L = torch.zeros(N, dtype=torch.float64, device="cuda")
+        c = torch.zeros(N // 2, d, dtype=torch.float64, device="cuda")
+        NV.prdpt_grad_estimate_async(gs, to_dev(ref), to_dev(pr["theta0"]), to_dev(pr["sigma"]),
+                                     N, 7, O.GAUSS, g, q, L, c)
+        torch.cuda.synchronize()
+        assert np.array_equal(g.cpu().numpy(), sync["grad"])
+        assert np.array_equal(L.cpu().numpy(), sync["losses"])
+        g2 = torch.zeros(d, dtype=torch.float64, device="cuda")
+        scale = torch.tensor([2.5], dtype=torch.float64, device="cuda")
+        NV.prdpt_combine_async(ctx, N // 2, d, c, L, scale, g2)
+        torch.cuda.synchronize()
+        np.testing.assert_allclose(g2.cpu().numpy(), 2.5 * sync["grad"], rtol=1e-15)
+    finally:
+        gs.destroy()
+
+
+def test_error_codes(ctx):
+    from paper_2211_17263_amd import native as NV
+    pr = S.toy_problem(seed=1)
+    say("errors")
+    gs = gpu_scene(ctx, pr["scene"])
+    ref = to_dev(np.zeros((64, 64, 3), np.float32))
+    try:
+        for N, sigma, est in [(3, pr["sigma"], 0), (0, pr["sigma"], 0),
+                              (4, np.array([0.5, 0.0], np.float32), 0), (4, pr["sigma"], 7)]:
+            with pytest.raises(NV.PrdptError) as e:
+                NV.prdpt_grad_estimate(gs, ref, pr["theta0"], sigma, N, 1, est)
+            assert e.value.code == NV.PRDPT_E_ARG
+        bad = S.toy_scene()
+        bad.bind(S.BIND_SPHERE, 5, 0)
+        with pytest.raises(NV.PrdptError) as e:
+            gpu_scene(ctx, bad)
+        assert e.value.code == NV.PRDPT_E_SCENE
+        bad2 = S.toy_scene()
+        bad2.quad_mat[0] = bad2.material(S.DIELECTRIC, ior=1.5)
+        with pytest.raises(NV.PrdptError) as e:
+            gpu_scene(ctx, bad2)
+        assert e.value.code == NV.PRDPT_E_SCENE
+    finally:
+        gs.destroy()
+
+
+def test_admission_budget():
+    from paper_2211_17263_amd import native as NV
+    say("admission")
+    small = NV.Context(0, hbm_budget=200_000)
+    pr = S.cornell_problem(seed=2, width=32, height=32, spp=1, ico_level=4)
+    with pytest.raises(NV.PrdptError) as e:
+        NV.prdpt_scene_create(small, pr["scene"])
+    assert e.value.code == NV.PRDPT_E_ADMISSION
+    ok = NV.prdpt_scene_create(small, S.toy_scene())
+    assert small.resident_bytes() == ok.footprint
+    ok.destroy()
+    assert small.resident_bytes() == 0
+    small.close()
+
+
+def test_cornell_full_size(ctx):
+    # the full global-illumination workload: 256x256, 16 spp, 4 bounces, N = 16, IS
+    pr = S.cornell_problem(seed=2)
+    _full_parity(ctx, pr, 2024, "cornell-full", check_images=False)
+
+
+def test_caustic_full_size_sampled(ctx):
+    # full caustic workload: 512x512, 64 spp, 8 bounces, 50k occluders, N = 32;
+    # the oracle re-renders 256 sampled pixels of three perturbed images
+    from paper_2211_17263_amd import native as NV
+    pr = S.caustic_problem(seed=3)
+    seed, N = 31, 32
+    say("caustic-full", "512x512 spp=64 B=8 N=32")
+    osc = O.OracleScene(pr["scene"])
+    gs = gpu_scene(ctx, pr["scene"])
+    try:
+        imgs, tau = NV.prdpt_render_perturbed(gs, pr["theta0"], pr["sigma"], N, seed, O.IS)
+        otau, _ = O.draw_tau(O.IS, pr["sigma"], N // 2, seed)
+        assert np.array_equal(tau, otau)
+        rng = np.random.default_rng(0)
+        pix = rng.choice(512 * 512, 256, replace=False).astype(np.int32)
+        for k in (0, 1, N - 1):
+            p = k // 2
+            X = (pr["theta0"] + tau[p]) if k % 2 == 0 else (pr["theta0"] - tau[p])
+            X = X.astype(np.float32)
+            ov = osc.render_pixels(X, pix, tag=O.TAG_PATH, pair=p, seed=seed)
+            gv = imgs[k].reshape(-1, 3)[pix].cpu().numpy()
+            PT.assert_images_match(gv, ov, f"caustic-full k={k}")
+    finally:
+        gs.destroy()
