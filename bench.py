@@ -1,0 +1,258 @@
+#!/usr/bin/env python3
+"""Throughput of the plateau-reduced gradient estimator on one MI355X.
+
+One step = one pass of the whole hot path over one batch of synthetic input:
+draw the antithetic perturbations, path-trace every perturbed scene, reduce each
+image's squared error against the reference, combine the losses with the kernel
+weights in binary64, then the host-side bandwidth schedule and Adam step.  The
+default workload is the global-illumination scene (256x256, 16 spp, 4 bounces,
+6 parameters, N = 16 importance-sampled perturbations).
+
+Prints one JSON line.  `value` is gradient estimates per second over the timed
+steps; `roofline` describes the fused render kernel (algorithmic node/triangle/
+reference bytes per launch over its event-timed duration, against 8 TB/s HBM);
+`cpu_baseline` is the CPU oracle timed on this host's cores on a bounded sample
+(a subset of the antithetic pairs of one estimate) of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+NODE_BYTES, TRI_BYTES, REF_BYTES_PER_PIXEL = 64, 48, 12
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_render_loss_cornell.txt")
+KERNEL_SRC = os.path.join(ROOT, "paper_2211_17263_amd", "csrc", "kernels.hip")
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def workload(name):
+    from paper_2211_17263_amd import scenes as S
+    if name == "cornell":
+        pr = S.cornell_problem(seed=2)
+        desc = "global illumination: Cornell box 12 quads + 2 x 5120-triangle jittered icospheres"
+        return pr, desc, pr["sigma"], pr["sigma"]
+    if name == "toy":
+        pr = S.toy_problem(seed=1)
+        return pr, "toy direct light: sphere over plane, point light", pr["sigma"], pr["sigma"]
+    if name == "caustic":
+        pr = S.caustic_problem(seed=3)
+        desc = "caustic: glass sphere, area light, 50000-triangle occluder"
+        return pr, desc, pr["sigma"], np.full_like(pr["sigma"], pr["sigma_end"])
+    raise SystemExit(f"unknown workload {name}")
+
+
+def traffic_from_profile():
+    """Measured HBM bytes per launch, valid only for the kernel source it was taken on."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    src_hash = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    if kv.get("kernel_source_sha256") != src_hash:
+        return None
+    try:
+        return float(kv["fetch_bytes_per_launch"]) + float(kv["write_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="cornell", choices=["cornell", "toy", "caustic"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline leg")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="CPU-oracle baseline: run whole estimates until this much time passed")
+    ap.add_argument("--seed", type=int, default=1000)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run the streaming-copy probe (1 GiB, 20 copies) and print its rate")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the estimator "
+              f"shards by antithetic pairs across GPUs, which this build does not run.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2211_17263_amd import native as NV
+
+    if args.copy_probe:
+        ctx = NV.Context(0)
+        print(json.dumps({"copy_probe_GBps": copy_rate(ctx, NV, 1 << 30, 20), "bytes": 1 << 30}))
+        ctx.close()
+        return
+
+    pr, desc, sigma0, sigma_end = workload(args.workload)
+    scene = pr["scene"]
+    N, est, d = pr["N"], pr["est"], scene.d
+    P = N // 2
+    H, W, spp = scene.height, scene.width, scene.spp
+    total_steps = args.warmup + args.steps
+
+    ctx = NV.Context(0)
+    t_build = time.perf_counter()
+    sc = NV.prdpt_scene_create(ctx, scene)
+    t_build = time.perf_counter() - t_build
+    log(f"workload {args.workload}: {W}x{H} spp={spp} N={N} d={d}, scene built in {t_build:.2f} s")
+    ref = NV.prdpt_render_reference(sc, pr["theta_ref"], args.seed + 7)
+
+    theta = pr["theta0"].astype(np.float64)
+    m = np.zeros(d)
+    v = np.zeros(d)
+    lr = float(pr.get("lr", 0.01))
+    trajectory = []
+    lat = []
+
+    def step(t):
+        s = np.array([NV.prdpt_sigma_schedule(a, b, t, total_steps) for a, b in zip(sigma0, sigma_end)],
+                     np.float32)
+        th32 = theta.astype(np.float32)
+        seed = args.seed + t
+        t0 = time.perf_counter()
+        r = NV.prdpt_grad_estimate(sc, ref, th32, s, N, seed, est)
+        NV.prdpt_adam_step(theta, r["grad"], m, v, t + 1, lr)
+        lat.append(time.perf_counter() - t0)
+        trajectory.append((th32, s, seed))
+        return r
+
+    for t in range(args.warmup):
+        step(t)
+    torch.cuda.synchronize()
+    log(f"warm-up done ({args.warmup} steps), timing {args.steps} steps")
+    lat.clear()
+    trajectory.clear()
+    NV.prdpt_ctx_read_timing(ctx)
+    NV.prdpt_ctx_set_timing(ctx, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for t in range(args.warmup, total_steps):
+        last = step(t)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    kernel_ms, launches = NV.prdpt_ctx_read_timing(ctx)
+    NV.prdpt_ctx_set_timing(ctx, False)
+    log(f"timed {args.steps} steps in {elapsed:.3f} s; counting work of the timed launches")
+
+    # algorithmic work of the timed launches, replayed with the counting kernel
+    cnt = {"nodes": 0, "tris": 0, "rays": 0, "paths": 0}
+    for th32, s, seed in trajectory:
+        c = NV.prdpt_traversal_counts(sc, th32, s, N, seed, est)
+        for k in cnt:
+            cnt[k] += c[k]
+    K = args.steps
+    per = {k: cnt[k] / K for k in cnt}
+    alg_bytes = per["nodes"] * NODE_BYTES + per["tris"] * TRI_BYTES + N * H * W * REF_BYTES_PER_PIXEL
+    kernel_avg_s = (kernel_ms / launches) / 1e3 if launches else float("nan")
+    achieved = alg_bytes / kernel_avg_s / 1e9
+    paths_per_est = N * H * W * spp
+
+    out = {
+        "metric": "gradient estimates/sec and paths/sec at 1e-4 rel. error; p50/p99 request latency",
+        "value": K / elapsed,
+        "unit": "gradient estimates/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "scene": desc, "width": W, "height": H, "spp": spp,
+                   "max_bounces": scene.max_bounces, "params": d, "N": N,
+                   "estimator": ["gauss", "is", "is_perdim"][est], "triangles": scene.n_tris},
+        "paths_per_s": paths_per_est * K / elapsed,
+        "rays_per_s": per["rays"] * K / elapsed,
+        "latency_ms": {"p50": 1e3 * float(np.percentile(lat, 50)),
+                       "p99": 1e3 * float(np.percentile(lat, 99))},
+        "kernel": {"name": "render_loss_kernel", "avg_ms": 1e3 * kernel_avg_s, "launches": launches,
+                   "share_of_step": (kernel_ms / 1e3) / elapsed},
+        "work_per_estimate": {"nodes": per["nodes"], "triangles": per["tris"], "rays": per["rays"],
+                              "paths": per["paths"]},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_profile()},
+        "scene_build_s": t_build,
+        "final_loss": last["loss"],
+    }
+
+    achievable = copy_rate(ctx, NV, 256 << 20, 10)
+    out["roofline"]["achievable_copy_GBps"] = achievable
+    out["roofline"]["frac_of_achievable"] = achieved / achievable
+    if not args.no_cpu:
+        log("CPU oracle baseline leg")
+        out["cpu_baseline"], out["parity"] = cpu_leg(sc, pr, sigma0, args, NV)
+
+    sc.destroy()
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+def copy_rate(ctx, NV, nbytes, iters):
+    """Achievable HBM bandwidth (GB/s, read + write) of the library's streaming copy."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    ms = NV.prdpt_copy_probe(ctx, src, dst, iters)
+    del src, dst
+    return 2 * nbytes / (ms / 1e3) / 1e9
+
+
+def cpu_leg(sc, pr, sigma0, args, NV):
+    """CPU oracle timed on a bounded sample of the same workload: whole estimates
+    (all antithetic pairs) with consecutive seeds until about --cpu-seconds of
+    work are done; then the GPU per-image losses are checked against the oracle's
+    on the first of those estimates (same reference, parameters and seed)."""
+    import torch
+
+    from oracle import oracle as O
+    scene = pr["scene"]
+    N, est = pr["N"], pr["est"]
+    cores = len(os.sched_getaffinity(0))
+    osc = O.OracleScene(scene)
+    ref_o = osc.reference(pr["theta_ref"], seed=args.seed + 7, nthreads=cores)
+    theta = pr["theta0"].astype(np.float32)
+    first = None
+    reps = 0
+    t0 = time.perf_counter()
+    while True:
+        o = osc.grad_estimate(ref_o, theta, sigma0, N, args.seed + reps, est, nthreads=cores)
+        first = first or o
+        reps += 1
+        dt = time.perf_counter() - t0
+        if dt >= args.cpu_seconds or reps >= 64:
+            break
+    g = NV.prdpt_grad_estimate(sc, torch.from_numpy(ref_o).cuda(), theta, sigma0, N, args.seed, est)
+    rel = np.abs(g["losses"] - first["losses"]) / np.abs(first["losses"])
+    _, c = O.draw_tau(est, sigma0, N // 2, args.seed)
+    S = (np.abs(c) * (first["losses"][0::2] + first["losses"][1::2])[:, None]).mean(axis=0)
+    gerr = np.abs(g["grad"] - first["grad"]) / S
+    paths = N * scene.width * scene.height * scene.spp
+    base = {"value": reps / dt, "unit": "gradient estimates/s", "cores": cores, "kind": "oracle",
+            "sample": f"{reps} whole estimate(s) ({reps * N} renders, {reps * paths} paths) "
+                      f"in {dt:.1f} s",
+            "paths_per_s": reps * paths / dt}
+    parity = {"checked_renders": N, "max_rel_loss_err": float(rel.max()),
+              "max_grad_err_over_scale": float(gerr.max()),
+              "pass_1e-4": bool(rel.max() <= 1e-4 and gerr.max() <= 1e-4)}
+    return base, parity
+
+
+if __name__ == "__main__":
+    main()

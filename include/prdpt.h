@@ -223,6 +223,45 @@ int prdpt_combine_async(prdpt_ctx* ctx, int P, int d, const double* c_dev,
 /* Wait for all work enqueued on the context's stream. */
 int prdpt_ctx_synchronize(prdpt_ctx* ctx);
 
+/*
+ * Measurement hooks.  With timing enabled the context records a pair of HIP
+ * events on its stream around every launch of the fused render-and-loss kernel;
+ * prdpt_ctx_read_timing waits for them and returns (then clears) the summed
+ * kernel time in milliseconds and the number of launches.
+ */
+int prdpt_ctx_set_timing(prdpt_ctx* ctx, int enable);
+int prdpt_ctx_read_timing(prdpt_ctx* ctx, double* total_ms, int64_t* launches);
+
+/*
+ * Work of one estimate, measured by an instrumented copy of the render kernel
+ * on the same rays: counts[0] BVH nodes fetched, counts[1] triangles tested,
+ * counts[2] ray queries (closest-hit and shadow), counts[3] camera paths.
+ * counts: host uint64_t[4].  Synchronous.
+ */
+int prdpt_traversal_counts(prdpt_scene* scene, const float* theta, const float* sigma, int N,
+                           uint64_t seed, int est, uint64_t* counts);
+
+/*
+ * Achievable-bandwidth probe: copies `bytes` (multiple of 16, 16-byte aligned
+ * device buffers) from src to dst `iters` times with a plain streaming kernel on
+ * the context's stream and returns the mean milliseconds per copy (each copy
+ * reads and writes `bytes`).  Also the reference dispatch for scaling memory
+ * counters.  Synchronous.
+ */
+int prdpt_copy_probe(prdpt_ctx* ctx, const void* src, void* dst, size_t bytes, int iters,
+                     double* ms_per_copy);
+
+/*
+ * Host-side step of the optimisation loop around the estimator (Sec. 3.3-3.4):
+ * linear bandwidth decay sigma_t = sigma0 + (sigma_end - sigma0) t / (T - 1)
+ * (the paper's schedule with t normalised to the run length), and one Adam
+ * step (Kingma & Ba) on theta with moments m, v (host double[d], updated in
+ * place; t counts from 1).
+ */
+double prdpt_sigma_schedule(double sigma0, double sigma_end, int t, int T);
+int prdpt_adam_step(int d, double* theta, const double* grad, double* m, double* v, int t,
+                    double lr, double beta1, double beta2, double eps);
+
 #ifdef __cplusplus
 }
 #endif

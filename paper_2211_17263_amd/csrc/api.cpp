@@ -24,6 +24,7 @@ hipError_t launch_losses(hipStream_t st, const float* partial, int n_tiles, int 
                          double* losses);
 hipError_t launch_combine(hipStream_t st, int P, int d, const double* c, const double* L,
                           const double* scale, double* grad, double* loss);
+hipError_t launch_copy(hipStream_t st, const void* src, void* dst, size_t n16);
 }  // namespace prdpt
 
 using namespace prdpt;
@@ -68,6 +69,12 @@ struct prdpt_ctx {
   DevBuf<float> X, tau, partial, theta, sigma;
   DevBuf<double> c, losses, grad, loss;
   DevBuf<unsigned long long> counters;
+  // optional timing of the fused render kernel (events on the context stream)
+  bool timing = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
+  std::vector<hipEvent_t> pool;
+  double timed_ms = 0.0;
+  int64_t timed_launches = 0;
 };
 
 struct prdpt_scene {
@@ -100,6 +107,39 @@ int ensure(prdpt_ctx* ctx, DevBuf<T>& b, size_t n) {
   }
   b.n = want;
   return PRDPT_OK;
+}
+
+hipEvent_t take_event(prdpt_ctx* ctx) {
+  if (!ctx->pool.empty()) {
+    hipEvent_t e = ctx->pool.back();
+    ctx->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// launch the fused render kernel, bracketed by timing events when enabled
+hipError_t timed_render(prdpt_ctx* ctx, const DevScene& sc, int W, int H, const float* X, int nk,
+                        int d, int tag, uint64_t seed, const float* ref, float* img, float* partial) {
+  hipEvent_t a = nullptr, b = nullptr;
+  if (ctx->timing) {
+    a = take_event(ctx);
+    b = take_event(ctx);
+    if (a && b) {
+      hipError_t e = hipEventRecord(a, ctx->stream);
+      if (e != hipSuccess) return e;
+    }
+  }
+  hipError_t e = launch_render(ctx->stream, sc, W, H, X, nk, d, tag, seed, ref, img, partial, nullptr);
+  if (e != hipSuccess) return e;
+  if (a && b) {
+    e = hipEventRecord(b, ctx->stream);
+    if (e != hipSuccess) return e;
+    ctx->pending.emplace_back(a, b);
+  }
+  return hipSuccess;
 }
 
 int check_request(const prdpt_scene* s, const float* theta, const float* sigma, int N,
@@ -153,8 +193,8 @@ int enqueue_estimate(prdpt_scene* s, const float* ref, const float* theta_dev,
   double* L = losses_dev ? losses_dev : ctx->losses.p;
   HIP_TRY(launch_tau(ctx->stream, est, d, P, seed, sigma_dev, theta_dev, chi_mean(d),
                      std::sqrt(2.0 * M_PI), ctx->tau.p, c, ctx->X.p));
-  HIP_TRY(launch_render(ctx->stream, s->dev(), h.W, h.H, ctx->X.p, N, d, kTagPath, seed, ref,
-                        nullptr, ctx->partial.p, nullptr));
+  HIP_TRY(timed_render(ctx, s->dev(), h.W, h.H, ctx->X.p, N, d, kTagPath, seed, ref, nullptr,
+                       ctx->partial.p));
   HIP_TRY(launch_losses(ctx->stream, ctx->partial.p, n_tiles, N, h.W * h.H, L));
   HIP_TRY(launch_combine(ctx->stream, P, d, c, L, nullptr, grad_dev, loss_dev));
   return PRDPT_OK;
@@ -205,6 +245,11 @@ int prdpt_ctx_destroy(prdpt_ctx* ctx) {
                   ctx->c.p, ctx->losses.p, ctx->grad.p, ctx->loss.p, ctx->counters.p};
   for (void* b : bufs)
     if (b) hipFree(b);
+  for (auto& pr : ctx->pending) {
+    hipEventDestroy(pr.first);
+    hipEventDestroy(pr.second);
+  }
+  for (hipEvent_t e : ctx->pool) hipEventDestroy(e);
   delete ctx;
   return PRDPT_OK;
 }
@@ -556,6 +601,99 @@ int prdpt_combine_async(prdpt_ctx* ctx, int P, int d, const double* c_dev, const
   std::lock_guard<std::mutex> g(ctx->mu);
   HIP_TRY(hipSetDevice(ctx->device));
   HIP_TRY(launch_combine(ctx->stream, P, d, c_dev, losses_dev, scale_dev, grad_dev, nullptr));
+  return PRDPT_OK;
+}
+
+int prdpt_ctx_set_timing(prdpt_ctx* ctx, int enable) {
+  if (!ctx) return fail(PRDPT_E_ARG, "ctx is null");
+  std::lock_guard<std::mutex> g(ctx->mu);
+  ctx->timing = enable != 0;
+  return PRDPT_OK;
+}
+
+int prdpt_ctx_read_timing(prdpt_ctx* ctx, double* total_ms, int64_t* launches) {
+  if (!ctx || !total_ms || !launches) return fail(PRDPT_E_ARG, "null argument");
+  std::lock_guard<std::mutex> g(ctx->mu);
+  HIP_TRY(hipSetDevice(ctx->device));
+  for (auto& pr : ctx->pending) {
+    HIP_TRY(hipEventSynchronize(pr.second));
+    float ms = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&ms, pr.first, pr.second));
+    ctx->timed_ms += ms;
+    ctx->timed_launches += 1;
+    ctx->pool.push_back(pr.first);
+    ctx->pool.push_back(pr.second);
+  }
+  ctx->pending.clear();
+  *total_ms = ctx->timed_ms;
+  *launches = ctx->timed_launches;
+  ctx->timed_ms = 0.0;
+  ctx->timed_launches = 0;
+  return PRDPT_OK;
+}
+
+int prdpt_traversal_counts(prdpt_scene* s, const float* theta, const float* sigma, int N,
+                           uint64_t seed, int est, uint64_t* counts) {
+  if (int rc = check_request(s, theta, sigma, N, true)) return rc;
+  if (int rc = check_est(est)) return rc;
+  if (!counts) return fail(PRDPT_E_ARG, "counts is null");
+  prdpt_ctx* ctx = s->ctx;
+  const SceneHdr& h = s->hdr;
+  const int d = h.n_param, P = N / 2;
+  std::lock_guard<std::mutex> g(ctx->mu);
+  HIP_TRY(hipSetDevice(ctx->device));
+  if (int rc = prepare(ctx, N, d, render_tiles(h.W, h.H))) return rc;
+  if (int rc = ensure(ctx, ctx->counters, 4)) return rc;
+  if (int rc = upload_vectors(ctx, theta, sigma, d)) return rc;
+  HIP_TRY(hipMemsetAsync(ctx->counters.p, 0, 4 * sizeof(unsigned long long), ctx->stream));
+  HIP_TRY(launch_tau(ctx->stream, est, d, P, seed, ctx->sigma.p, ctx->theta.p, chi_mean(d),
+                     std::sqrt(2.0 * M_PI), ctx->tau.p, ctx->c.p, ctx->X.p));
+  HIP_TRY(launch_render(ctx->stream, s->dev(), h.W, h.H, ctx->X.p, N, d, kTagPath, seed, nullptr,
+                        nullptr, nullptr, ctx->counters.p));
+  unsigned long long host[4];
+  HIP_TRY(hipMemcpyAsync(host, ctx->counters.p, sizeof(host), hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  for (int i = 0; i < 4; ++i) counts[i] = host[i];
+  return PRDPT_OK;
+}
+
+int prdpt_copy_probe(prdpt_ctx* ctx, const void* src, void* dst, size_t bytes, int iters,
+                     double* ms_per_copy) {
+  if (!ctx || !src || !dst || !ms_per_copy || iters < 1) return fail(PRDPT_E_ARG, "bad probe arguments");
+  if (bytes == 0 || bytes % 16 || ((uintptr_t)src | (uintptr_t)dst) % 16)
+    return fail(PRDPT_E_ARG, "bytes and pointers must be 16-byte aligned and non-zero");
+  std::lock_guard<std::mutex> g(ctx->mu);
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipEvent_t a, b;
+  HIP_TRY(hipEventCreate(&a));
+  HIP_TRY(hipEventCreate(&b));
+  HIP_TRY(launch_copy(ctx->stream, src, dst, bytes / 16));  // warm-up
+  HIP_TRY(hipEventRecord(a, ctx->stream));
+  for (int i = 0; i < iters; ++i) HIP_TRY(launch_copy(ctx->stream, src, dst, bytes / 16));
+  HIP_TRY(hipEventRecord(b, ctx->stream));
+  HIP_TRY(hipEventSynchronize(b));
+  float ms = 0.0f;
+  HIP_TRY(hipEventElapsedTime(&ms, a, b));
+  hipEventDestroy(a);
+  hipEventDestroy(b);
+  *ms_per_copy = (double)ms / iters;
+  return PRDPT_OK;
+}
+
+double prdpt_sigma_schedule(double sigma0, double sigma_end, int t, int T) {
+  if (T <= 1) return sigma0;
+  return sigma0 + (sigma_end - sigma0) * (double)t / (double)(T - 1);
+}
+
+int prdpt_adam_step(int d, double* theta, const double* grad, double* m, double* v, int t,
+                    double lr, double beta1, double beta2, double eps) {
+  if (d < 1 || !theta || !grad || !m || !v || t < 1) return fail(PRDPT_E_ARG, "bad Adam arguments");
+  const double c1 = 1.0 - std::pow(beta1, t), c2 = 1.0 - std::pow(beta2, t);
+  for (int j = 0; j < d; ++j) {
+    m[j] = beta1 * m[j] + (1.0 - beta1) * grad[j];
+    v[j] = beta2 * v[j] + (1.0 - beta2) * grad[j] * grad[j];
+    theta[j] -= lr * (m[j] / c1) / (std::sqrt(v[j] / c2) + eps);
+  }
   return PRDPT_OK;
 }
 

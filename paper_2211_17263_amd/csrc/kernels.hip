@@ -187,7 +187,7 @@ __device__ __forceinline__ void keep_closer(Hit& h, float t, int id, int slot) {
 }
 
 struct Counters {
-  uint32_t nodes, tris;
+  uint32_t nodes, tris, rays, paths;
 };
 
 // Conservative binary32 slab test of a padded child box; returns the entry
@@ -275,6 +275,7 @@ __device__ void closest_hit(const SceneHdr& S, const Node* nodes, const Tri* tri
   h.t = __builtin_huge_valf();
   h.id = -1;
   h.slot = -1;
+  if (COUNT) cnt.rays++;
   const float tmax = __builtin_huge_valf();
   for (int i = 0; i < S.n_sph; ++i) {
     float t;
@@ -295,6 +296,7 @@ __device__ void closest_hit(const SceneHdr& S, const Node* nodes, const Tri* tri
 template <bool COUNT>
 __device__ bool occluded(const SceneHdr& S, const Node* nodes, const Tri* tris, V3 o, V3 d,
                          float tmax, int* stack, int stride, Counters& cnt) {
+  if (COUNT) cnt.rays++;
   for (int i = 0; i < S.n_sph; ++i) {
     float t;
     if (hit_sphere(o, d, S.sph[i], tmax, &t)) return true;
@@ -357,6 +359,7 @@ __device__ void radiance(const SceneHdr& S, const Node* nodes, const Tri* tris, 
                          uint32_t k1, int pix, int x, int y, int smp, int pair, int tag,
                          int* stack, int stride, Counters& cnt, float L[3]) {
   L[0] = L[1] = L[2] = 0.0f;
+  if (COUNT) cnt.paths++;
   float jx = 0.5f, jy = 0.5f;
   if (!S.pixel_center) {
     const uint4 w = path_words(k0, k1, pix, smp, pair, tag, 0, 0);
@@ -540,7 +543,7 @@ __global__ __launch_bounds__(kBlock) void render_loss_kernel(
   const int lx = (t & 7) + 8 * (t >> 6), ly = (t >> 3) & 7;
   const int x = (tile % tiles_x) * kTileW + lx, y = (tile / tiles_x) * kTileH + ly;
   float e = 0.0f;
-  Counters cnt{0u, 0u};
+  Counters cnt{0u, 0u, 0u, 0u};
   if (x < S.W && y < S.H) {
     const int pix = y * S.W + x;
     const int pair = k >> 1;
@@ -571,6 +574,8 @@ __global__ __launch_bounds__(kBlock) void render_loss_kernel(
   if (COUNT) {
     atomicAdd(&counters[0], (unsigned long long)cnt.nodes);
     atomicAdd(&counters[1], (unsigned long long)cnt.tris);
+    atomicAdd(&counters[2], (unsigned long long)cnt.rays);
+    atomicAdd(&counters[3], (unsigned long long)cnt.paths);
   }
   if (partial) {
     // fixed-order butterfly within the wave, then the waves in order
@@ -702,6 +707,14 @@ __global__ void combine_kernel(int P, int d, const double* __restrict__ c,
   }
 }
 
+// Plain streaming copy (16-byte loads and stores, grid-stride): the reference
+// for achievable HBM bandwidth and for scaling the memory counters.
+__global__ __launch_bounds__(256) void copy_kernel(const float4* __restrict__ src,
+                                                   float4* __restrict__ dst, size_t n) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -740,6 +753,13 @@ hipError_t launch_losses(hipStream_t st, const float* partial, int n_tiles, int 
 hipError_t launch_combine(hipStream_t st, int P, int d, const double* c, const double* L,
                           const double* scale, double* grad, double* loss) {
   hipLaunchKernelGGL(combine_kernel, dim3(1), dim3(64), 0, st, P, d, c, L, scale, grad, loss);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(hipStream_t st, const void* src, void* dst, size_t n16) {
+  const int blocks = 256 * 16;  // 16 work-groups per CU
+  hipLaunchKernelGGL(copy_kernel, dim3(blocks), dim3(256), 0, st,
+                     reinterpret_cast<const float4*>(src), reinterpret_cast<float4*>(dst), n16);
   return hipGetLastError();
 }
 

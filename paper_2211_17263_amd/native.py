@@ -26,7 +26,9 @@ EXPORTS = [
     "prdpt_ctx_resident_bytes", "prdpt_ctx_synchronize", "prdpt_scene_create",
     "prdpt_scene_destroy", "prdpt_scene_info", "prdpt_draw_tau", "prdpt_render_perturbed",
     "prdpt_render_reference", "prdpt_smoothed_loss", "prdpt_grad_estimate",
-    "prdpt_grad_estimate_async", "prdpt_combine_async",
+    "prdpt_grad_estimate_async", "prdpt_combine_async", "prdpt_ctx_set_timing",
+    "prdpt_ctx_read_timing", "prdpt_traversal_counts", "prdpt_sigma_schedule", "prdpt_adam_step",
+    "prdpt_copy_probe",
 ]
 
 
@@ -84,9 +86,18 @@ def load():
     L.prdpt_grad_estimate.argtypes = [vp, vp, vp, vp, i32, u64, i32, vp, vp, vp]
     L.prdpt_grad_estimate_async.argtypes = [vp, vp, vp, vp, i32, u64, i32, vp, vp, vp, vp]
     L.prdpt_combine_async.argtypes = [vp, i32, i32, vp, vp, vp, vp]
+    L.prdpt_ctx_set_timing.argtypes = [vp, i32]
+    L.prdpt_ctx_read_timing.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+    L.prdpt_traversal_counts.argtypes = [vp, vp, vp, i32, u64, i32, vp]
+    L.prdpt_sigma_schedule.argtypes = [C.c_double, C.c_double, i32, i32]
+    dp = C.c_void_p
+    L.prdpt_adam_step.argtypes = [i32, dp, dp, dp, dp, i32, C.c_double, C.c_double, C.c_double,
+                                  C.c_double]
+    L.prdpt_copy_probe.argtypes = [vp, vp, vp, sz, i32, C.POINTER(C.c_double)]
     for name in EXPORTS:
         if name != "prdpt_last_error":
             getattr(L, name).restype = C.c_int
+    L.prdpt_sigma_schedule.restype = C.c_double
     _lib = L
     return L
 
@@ -275,6 +286,53 @@ def prdpt_grad_estimate_async(scene, ref, theta, sigma, N, seed, est, grad, loss
         int(N), int(seed), int(est), _dev(grad, torch.float64), _dev(loss, torch.float64),
         _dev(losses, torch.float64) if losses is not None else None,
         _dev(c, torch.float64) if c is not None else None))
+
+
+def prdpt_ctx_set_timing(ctx, enable):
+    _check(load().prdpt_ctx_set_timing(ctx.h, 1 if enable else 0))
+
+
+def prdpt_ctx_read_timing(ctx):
+    """(total render-kernel milliseconds, launches) since the last read."""
+    ms, n = C.c_double(), C.c_int64()
+    _check(load().prdpt_ctx_read_timing(ctx.h, C.byref(ms), C.byref(n)))
+    return ms.value, n.value
+
+
+def prdpt_traversal_counts(scene, theta, sigma, N, seed, est):
+    """dict(nodes, tris, rays, paths) of one estimate's render."""
+    th, tp = _host(theta, np.float32)
+    sg, sp = _host(sigma, np.float32)
+    out = np.zeros(4, np.uint64)
+    _check(load().prdpt_traversal_counts(scene.h, tp, sp, int(N), int(seed), int(est),
+                                         out.ctypes.data_as(C.c_void_p)))
+    return dict(zip(("nodes", "tris", "rays", "paths"), (int(x) for x in out)))
+
+
+def prdpt_copy_probe(ctx, src, dst, iters=10):
+    """Mean ms per copy of src into dst (device tensors of equal byte size)."""
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("src and dst sizes differ")
+    ms = C.c_double()
+    _check(load().prdpt_copy_probe(ctx.h, _dev(src), _dev(dst), nbytes, int(iters), C.byref(ms)))
+    return ms.value
+
+
+def prdpt_sigma_schedule(sigma0, sigma_end, t, T):
+    return load().prdpt_sigma_schedule(float(sigma0), float(sigma_end), int(t), int(T))
+
+
+def prdpt_adam_step(theta, grad, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """In-place Adam step on float64 numpy arrays."""
+    for a in (theta, m, v):
+        if a.dtype != np.float64 or not a.flags.c_contiguous:
+            raise TypeError("theta/m/v must be contiguous float64 arrays")
+    g = np.ascontiguousarray(grad, np.float64)
+    _check(load().prdpt_adam_step(theta.size, theta.ctypes.data_as(C.c_void_p),
+                                  g.ctypes.data_as(C.c_void_p), m.ctypes.data_as(C.c_void_p),
+                                  v.ctypes.data_as(C.c_void_p), int(t), float(lr), float(beta1),
+                                  float(beta2), float(eps)))
 
 
 def prdpt_combine_async(ctx, P, d, c, losses, scale, grad):

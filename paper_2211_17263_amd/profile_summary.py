@@ -1,0 +1,107 @@
+"""Summarise rocprofv3 CSV output into the short text files kept under profiles/.
+
+kernel-trace mode: per-kernel call count and mean/min/max duration from a
+``--kernel-trace --stats -f csv`` run.
+
+traffic mode: HBM bytes per dispatch of one kernel from two ``--pmc`` runs
+(FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by what the same
+counter reads for the library's streaming copy of a known size (copy probe), and
+stamped with the sha256 of the kernel source the counters were taken on.
+"""
+import argparse
+import csv
+import hashlib
+import os
+import statistics
+
+
+def _rows(path):
+    for name in os.listdir(path):
+        if name.endswith("counter_collection.csv"):
+            return list(csv.DictReader(open(os.path.join(path, name))))
+    raise SystemExit(f"no counter_collection.csv under {path}")
+
+
+def _values(path, counter, name_has, largest_grid=True):
+    rows = [r for r in _rows(path) if r["Counter_Name"] == counter and name_has in r["Kernel_Name"]]
+    if not rows:
+        raise SystemExit(f"no {counter} rows for {name_has!r} in {path}")
+    if largest_grid:
+        g = max(int(r["Grid_Size"]) for r in rows)
+        rows = [r for r in rows if int(r["Grid_Size"]) == g]
+    return [float(r["Counter_Value"]) for r in rows]
+
+
+def traffic(a):
+    fetch = _values(a.fetch, "FETCH_SIZE", a.kernel)
+    write = _values(a.write, "WRITE_SIZE", a.kernel)
+    cf = statistics.mean(_values(a.copy_fetch, "FETCH_SIZE", "copy_kernel"))
+    cw = statistics.mean(_values(a.copy_write, "WRITE_SIZE", "copy_kernel"))
+    f_scale = a.copy_bytes / (cf * 1024.0)
+    w_scale = a.copy_bytes / (cw * 1024.0)
+    fb = statistics.mean(fetch) * 1024.0 * f_scale
+    wb = statistics.mean(write) * 1024.0 * w_scale
+    sha = hashlib.sha256(open(a.source, "rb").read()).hexdigest()
+    lines = [
+        f"# HBM traffic per dispatch of {a.kernel} ({a.workload})",
+        "# commands:",
+        *[f"#   {c}" for c in a.command],
+        f"# copy probe: {a.copy_bytes} bytes read and written per dispatch; FETCH_SIZE read "
+        f"{cf:.1f} KiB, WRITE_SIZE {cw:.1f} KiB per copy dispatch",
+        f"# dispatches used: {len(fetch)} (FETCH) / {len(write)} (WRITE), largest grid only",
+        f"kernel: {a.kernel}",
+        f"kernel_source_sha256: {sha}",
+        f"fetch_kib_raw_mean: {statistics.mean(fetch):.3f}",
+        f"write_kib_raw_mean: {statistics.mean(write):.3f}",
+        f"fetch_scale: {f_scale:.5f}",
+        f"write_scale: {w_scale:.5f}",
+        f"fetch_bytes_per_launch: {fb:.0f}",
+        f"write_bytes_per_launch: {wb:.0f}",
+    ]
+    open(a.out, "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def kernel_trace(a):
+    path = a.trace
+    stats = [n for n in os.listdir(path) if n.endswith("kernel_stats.csv")]
+    rows = list(csv.DictReader(open(os.path.join(path, stats[0]))))
+    out = [f"# Kernel time summary ({a.workload})", "", "Command:", "", "```"]
+    out += a.command + ["```", "", "| kernel | calls | mean ms | min ms | max ms | share |",
+                        "|---|---|---|---|---|---|"]
+    for r in rows[: a.top]:
+        name = r["Name"].replace("(anonymous namespace)::", "")
+        name = name.split("(")[0] if "(" in name else name
+        out.append(f"| `{name[:70]}` | {r['Calls']} | {float(r['AverageNs']) / 1e6:.3f} | "
+                   f"{float(r['MinNs']) / 1e6:.3f} | {float(r['MaxNs']) / 1e6:.3f} | "
+                   f"{float(r['Percentage']):.2f} % |")
+    out += ["", *a.note]
+    open(a.out, "w").write("\n".join(out) + "\n")
+    print("\n".join(out))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    sub = ap.add_subparsers(dest="mode", required=True)
+    t = sub.add_parser("traffic")
+    for k in ("fetch", "write", "copy_fetch", "copy_write"):
+        t.add_argument("--" + k.replace("_", "-"), dest=k, required=True)
+    t.add_argument("--copy-bytes", type=float, default=float(1 << 30))
+    t.add_argument("--kernel", default="render_loss_kernel<false>")
+    t.add_argument("--source", default=os.path.join(os.path.dirname(__file__), "csrc", "kernels.hip"))
+    t.add_argument("--workload", default="")
+    t.add_argument("--command", action="append", default=[])
+    t.add_argument("--out", required=True)
+    k = sub.add_parser("trace")
+    k.add_argument("--trace", required=True)
+    k.add_argument("--workload", default="")
+    k.add_argument("--command", action="append", default=[])
+    k.add_argument("--note", action="append", default=[])
+    k.add_argument("--top", type=int, default=8)
+    k.add_argument("--out", required=True)
+    a = ap.parse_args()
+    traffic(a) if a.mode == "traffic" else kernel_trace(a)
+
+
+if __name__ == "__main__":
+    main()

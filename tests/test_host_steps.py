@@ -1,0 +1,31 @@
+"""Host-side optimiser steps of the library against the oracle (no GPU needed)."""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+
+LIB = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                   "paper_2211_17263_amd", "libprdpt.so")
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libprdpt.so not built")
+
+
+def test_sigma_schedule_matches_oracle():
+    from paper_2211_17263_amd import native as NV
+    for t in range(0, 200, 7):
+        assert NV.prdpt_sigma_schedule(1.0, 0.05, t, 200) == O.sigma_schedule(1.0, 0.05, t, 200)
+    assert NV.prdpt_sigma_schedule(1.0, 0.05, 199, 200) == pytest.approx(0.05, abs=1e-15)
+
+
+def test_adam_matches_oracle():
+    from paper_2211_17263_amd import native as NV
+    rng = np.random.default_rng(0)
+    a, b = rng.normal(size=5), None
+    b = a.copy()
+    ma, va, mb, vb = (np.zeros(5) for _ in range(4))
+    for t in range(1, 30):
+        g = rng.normal(size=5)
+        NV.prdpt_adam_step(a, g, ma, va, t, 0.01)
+        O.adam_step(b, g, mb, vb, t, 0.01)
+        np.testing.assert_allclose(a, b, rtol=1e-14, atol=1e-15)
