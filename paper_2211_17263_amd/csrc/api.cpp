@@ -409,6 +409,10 @@ int prdpt_scene_create(prdpt_ctx* ctx, const prdpt_scene_desc* D, prdpt_scene** 
     h.inst_root[i] = b.root;
     s->bvh_depth = std::max(s->bvh_depth, b.depth);
   }
+  if (nodes.size() >= (1u << 24)) {
+    delete s;
+    return fail(PRDPT_E_SCENE, "too many BVH nodes (at most 2^24)");
+  }
   if (s->bvh_depth > kStackDepth) {
     delete s;
     return fail(PRDPT_E_SCENE, "BVH deeper than the traversal stack");

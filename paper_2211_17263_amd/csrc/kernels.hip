@@ -159,9 +159,21 @@ __device__ __forceinline__ bool hit_tri(V3 o, V3 d, V3 v0, V3 e1, V3 e2, float t
   const V3 pv = cross(d, e2);
   const float det = dot(e1, pv);
   if (det == 0.0f) return false;
-  const float inv = 1.0f / det;
   const V3 tv = sub(o, v0);
-  const float u = dot(tv, pv) * inv;
+  const float un = dot(tv, pv);
+  // Rejections that skip the division yet take the same decision as the
+  // rounded test below: with 2^-60 <= |det| <= 2^60, un/det <= -2^-60 makes the
+  // binary32 u = un * (1/det) a negative normal number, and un/det above
+  // 1 + 2^-20 (less one rounding of the threshold) keeps u above 1.
+  const float adet = fabsf(det);
+  if (adet >= 0x1p-60f && adet <= 0x1p60f) {
+    const float aun = fabsf(un);
+    const bool opposite = (un < 0.0f) != (det < 0.0f);
+    if (un != 0.0f && opposite && aun >= adet * 0x1p-60f) return false;
+    if (!opposite && aun > adet * 1.00000095367431640625f) return false;
+  }
+  const float inv = 1.0f / det;
+  const float u = un * inv;
   if (u < 0.0f || u > 1.0f) return false;
   const V3 qv = cross(tv, e1);
   const float v = dot(d, qv) * inv;
@@ -186,6 +198,11 @@ __device__ __forceinline__ void keep_closer(Hit& h, float t, int id, int slot) {
   }
 }
 
+#ifndef PRDPT_LDS_STACK
+#define PRDPT_LDS_STACK 16
+#endif
+constexpr int kLdsStack = PRDPT_LDS_STACK;
+
 struct Counters {
   uint32_t nodes, tris, rays, paths;
 };
@@ -208,24 +225,78 @@ __device__ __forceinline__ float safe_inv(float x) {
 }
 
 // Traverse one instance BVH.  ANY: stop at the first hit with t < tmax.
-template <bool ANY, bool COUNT>
-__device__ bool traverse(const Node* __restrict__ nodes, const Tri* __restrict__ tris, int root,
-                         V3 o, V3 d, float tmax, Hit& h, int* __restrict__ stack, int stride,
-                         Counters& cnt) {
+// Trace one ray through the analytic primitives and every instance BVH in a
+// single loop (stack entries carry the instance in their top byte, so lanes do
+// not reconverge between instances).  any = true: shadow query, stop at the
+// first occluder with t < tmax (emissive quads are not occluders); otherwise
+// keep the closest hit by (t, primitive id).
+template <bool COUNT>
+__device__ void trace_ray(const SceneHdr& S, const Node* __restrict__ nodes,
+                          const Tri* __restrict__ tris, V3 o, V3 d, float tmax, bool any, Hit& h,
+                          int* __restrict__ stack, int stride, Counters& cnt) {
+  h.t = __builtin_huge_valf();
+  h.id = -1;
+  h.slot = -1;
+  if (COUNT) cnt.rays++;
+  for (int i = 0; i < S.n_sph; ++i) {
+    float t;
+    if (hit_sphere(o, d, S.sph[i], tmax, &t)) {
+      if (any) {
+        h.id = i;
+        return;
+      }
+      keep_closer(h, t, i, -1);
+    }
+  }
+  for (int i = 0; i < S.n_quad; ++i) {
+    if (any && S.mat_type[S.quad_mat[i]] == PRDPT_MAT_EMISSIVE) continue;
+    float t;
+    if (hit_quad(o, d, S.quad[i], tmax, &t)) {
+      if (any) {
+        h.id = S.n_sph + i;
+        return;
+      }
+      keep_closer(h, t, S.n_sph + i, -1);
+    }
+  }
   const V3 inv = mk(safe_inv(d.x), safe_inv(d.y), safe_inv(d.z));
-  const V3 oi = mk(-o.x * inv.x, -o.y * inv.y, -o.z * inv.z);
+  // short stack: the top kLdsStack entries live in LDS, deeper ones in a
+  // private overflow array (rarely touched; the builder bounds the depth)
+  int spill[kStackDepth + PRDPT_MAX_INSTANCES - kLdsStack];
   int sp = 0;
-  int node = root;
+  for (int m = S.n_inst - 1; m >= 0; --m) {
+    if (S.inst_root[m] < 0) continue;
+    const int e = (m << 24) | S.inst_root[m];
+    if (sp < kLdsStack) stack[sp * stride] = e;
+    else spill[sp - kLdsStack] = e;
+    ++sp;
+  }
+  int inst = -1;
+  int node = -1;
+  V3 om = o, oi = o;
   while (true) {
+    if (node < 0) {
+      if (sp == 0) break;
+      --sp;
+      const int e = sp < kLdsStack ? stack[sp * stride] : spill[sp - kLdsStack];
+      node = e & 0xFFFFFF;
+      const int m = e >> 24;
+      if (m != inst) {
+        // an instance: the ray moves by minus the mesh translation
+        inst = m;
+        om = mk(o.x - S.inst_xlate[m][0], o.y - S.inst_xlate[m][1], o.z - S.inst_xlate[m][2]);
+        oi = mk(-om.x * inv.x, -om.y * inv.y, -om.z * inv.z);
+      }
+    }
     const float4* np = reinterpret_cast<const float4*>(nodes + node);
     const float4 a = np[0], b = np[1], c = np[2];
     const int4 ix = reinterpret_cast<const int4*>(np)[3];
     if (COUNT) cnt.nodes++;
-    const float tcull = ANY ? tmax : fminf(tmax, h.t);
-    float t0 = slab(a.x, a.y, a.z, a.w, c.x, c.y, inv, oi, tcull);
-    float t1 = ix.y >= 0 ? slab(b.x, b.y, b.z, b.w, c.z, c.w, inv, oi, tcull) : __builtin_huge_valf();
+    const float tcull = any ? tmax : fminf(tmax, h.t);
+    const float t0 = slab(a.x, a.y, a.z, a.w, c.x, c.y, inv, oi, tcull);
+    const float t1 = ix.y >= 0 ? slab(b.x, b.y, b.z, b.w, c.z, c.w, inv, oi, tcull)
+                               : __builtin_huge_valf();
     bool h0 = t0 < __builtin_huge_valf(), h1 = t1 < __builtin_huge_valf();
-    // leaves are intersected immediately
 #pragma unroll
     for (int side = 0; side < 2; ++side) {
       const bool hs = side == 0 ? h0 : h1;
@@ -237,22 +308,25 @@ __device__ bool traverse(const Node* __restrict__ nodes, const Tri* __restrict__
           const float4 p0 = tp[0], p1 = tp[1], p2 = tp[2];
           if (COUNT) cnt.tris++;
           float t;
-          const float lim = ANY ? tmax : tmax;
-          if (hit_tri(o, d, mk(p0.x, p0.y, p0.z), mk(p0.w, p1.x, p1.y), mk(p1.z, p1.w, p2.x), lim, &t)) {
-            if (ANY) {
+          if (hit_tri(om, d, mk(p0.x, p0.y, p0.z), mk(p0.w, p1.x, p1.y), mk(p1.z, p1.w, p2.x),
+                      tmax, &t)) {
+            if (any) {
               h.t = t;
               h.id = __float_as_int(p2.y);
-              return true;
+              return;
             }
             keep_closer(h, t, __float_as_int(p2.y), i);
           }
         }
-        if (side == 0) h0 = false; else h1 = false;
+        if (side == 0) h0 = false;
+        else h1 = false;
       }
     }
     if (h0 && h1) {
       const bool first0 = t0 <= t1;
-      stack[sp * stride] = first0 ? ix.y : ix.x;
+      const int far = (inst << 24) | (first0 ? ix.y : ix.x);
+      if (sp < kLdsStack) stack[sp * stride] = far;
+      else spill[sp - kLdsStack] = far;
       ++sp;
       node = first0 ? ix.x : ix.y;
     } else if (h0) {
@@ -260,63 +334,9 @@ __device__ bool traverse(const Node* __restrict__ nodes, const Tri* __restrict__
     } else if (h1) {
       node = ix.y;
     } else {
-      if (sp == 0) break;
-      --sp;
-      node = stack[sp * stride];
+      node = -1;
     }
   }
-  return false;
-}
-
-// closest hit over analytic spheres, analytic quads and instanced BVHs
-template <bool COUNT>
-__device__ void closest_hit(const SceneHdr& S, const Node* nodes, const Tri* tris, V3 o, V3 d,
-                            Hit& h, int* stack, int stride, Counters& cnt) {
-  h.t = __builtin_huge_valf();
-  h.id = -1;
-  h.slot = -1;
-  if (COUNT) cnt.rays++;
-  const float tmax = __builtin_huge_valf();
-  for (int i = 0; i < S.n_sph; ++i) {
-    float t;
-    if (hit_sphere(o, d, S.sph[i], tmax, &t)) keep_closer(h, t, i, -1);
-  }
-  for (int i = 0; i < S.n_quad; ++i) {
-    float t;
-    if (hit_quad(o, d, S.quad[i], tmax, &t)) keep_closer(h, t, S.n_sph + i, -1);
-  }
-  for (int m = 0; m < S.n_inst; ++m) {
-    if (S.inst_root[m] < 0) continue;
-    const V3 om = mk(o.x - S.inst_xlate[m][0], o.y - S.inst_xlate[m][1], o.z - S.inst_xlate[m][2]);
-    traverse<false, COUNT>(nodes, tris, S.inst_root[m], om, d, tmax, h, stack, stride, cnt);
-  }
-}
-
-// any non-emissive primitive with t in (0, tmax)
-template <bool COUNT>
-__device__ bool occluded(const SceneHdr& S, const Node* nodes, const Tri* tris, V3 o, V3 d,
-                         float tmax, int* stack, int stride, Counters& cnt) {
-  if (COUNT) cnt.rays++;
-  for (int i = 0; i < S.n_sph; ++i) {
-    float t;
-    if (hit_sphere(o, d, S.sph[i], tmax, &t)) return true;
-  }
-  for (int i = 0; i < S.n_quad; ++i) {
-    if (S.mat_type[S.quad_mat[i]] == PRDPT_MAT_EMISSIVE) continue;
-    float t;
-    if (hit_quad(o, d, S.quad[i], tmax, &t)) return true;
-  }
-  Hit h;
-  h.t = __builtin_huge_valf();
-  h.id = -1;
-  h.slot = -1;
-  for (int m = 0; m < S.n_inst; ++m) {
-    if (S.inst_root[m] < 0) continue;
-    const V3 om = mk(o.x - S.inst_xlate[m][0], o.y - S.inst_xlate[m][1], o.z - S.inst_xlate[m][2]);
-    if (traverse<true, COUNT>(nodes, tris, S.inst_root[m], om, d, tmax, h, stack, stride, cnt))
-      return true;
-  }
-  return false;
 }
 
 __device__ __forceinline__ V3 offset_origin(V3 p, V3 n) {
@@ -353,155 +373,13 @@ __device__ __forceinline__ uint4 path_words(uint32_t k0, uint32_t k1, int pix, i
 
 constexpr float kInvPi = 0.318309886183790671538f;
 
-// One camera path (same conventions as the CPU reference).
-template <bool COUNT>
-__device__ void radiance(const SceneHdr& S, const Node* nodes, const Tri* tris, uint32_t k0,
-                         uint32_t k1, int pix, int x, int y, int smp, int pair, int tag,
-                         int* stack, int stride, Counters& cnt, float L[3]) {
-  L[0] = L[1] = L[2] = 0.0f;
-  if (COUNT) cnt.paths++;
-  float jx = 0.5f, jy = 0.5f;
-  if (!S.pixel_center) {
-    const uint4 w = path_words(k0, k1, pix, smp, pair, tag, 0, 0);
-    jx = unit_open(w.x);
-    jy = unit_open(w.y);
-  }
-  const float px = (float)x + jx, py = (float)y + jy;
-  const float sx = 2.0f * (px / (float)S.W) - 1.0f;
-  const float sy = 1.0f - 2.0f * (py / (float)S.H);
-  V3 o = ld3(S.eye);
-  V3 d = unit(mk(S.fwd[0] + S.right[0] * sx + S.up[0] * sy, S.fwd[1] + S.right[1] * sx + S.up[1] * sy,
-                 S.fwd[2] + S.right[2] * sx + S.up[2] * sy));
-  float beta[3] = {1.0f, 1.0f, 1.0f};
-  bool specular = true;
-  for (int v = 0; v <= S.B; ++v) {
-    Hit h;
-    closest_hit<COUNT>(S, nodes, tris, o, d, h, stack, stride, cnt);
-    if (h.id < 0) {
-      for (int c = 0; c < 3; ++c) L[c] = L[c] + beta[c] * S.env[c];
-      break;
-    }
-    const V3 p = at(o, d, h.t);
-    int mat;
-    V3 ng;
-    if (h.id < S.n_sph) {
-      mat = S.sph_mat[h.id];
-      ng = unit(sub(p, ld3(S.sph[h.id])));
-    } else if (h.id < S.tri_id_base) {
-      const int qi = h.id - S.n_sph;
-      mat = S.quad_mat[qi];
-      ng = unit(cross(ld3(S.quad[qi] + 3), ld3(S.quad[qi] + 6)));
-    } else {
-      const Tri& t = tris[h.slot];
-      mat = t.mat;
-      ng = unit(cross(mk(t.e1x, t.e1y, t.e1z), mk(t.e2x, t.e2y, t.e2z)));
-    }
-    const int mt = S.mat_type[mat];
-    if (mt == PRDPT_MAT_EMISSIVE) {
-      if (specular && dot(d, ng) < 0.0f)
-        for (int c = 0; c < 3; ++c) L[c] = L[c] + beta[c] * S.mat_rgb[mat][c];
-      break;
-    }
-    const uint4 w = path_words(k0, k1, pix, smp, pair, tag, v + 1, 0);
-    if (mt == PRDPT_MAT_DIFFUSE) {
-      const V3 n = dot(ng, d) > 0.0f ? neg(ng) : ng;
-      const float f[3] = {S.mat_rgb[mat][0] * kInvPi, S.mat_rgb[mat][1] * kInvPi,
-                          S.mat_rgb[mat][2] * kInvPi};
-      for (int l = 0; l < S.n_pl; ++l) {
-        const float* lp = S.pl[l];
-        const V3 toL = sub(ld3(lp), p);
-        const float dist2 = dot(toL, toL);
-        const float dist = sqrtf(dist2);
-        const V3 wi = scale(toL, 1.0f / dist);
-        const float cx = dot(n, wi);
-        if (!(cx > 0.0f)) continue;
-        if (occluded<COUNT>(S, nodes, tris, offset_origin(p, n), wi, dist * 0.9999f, stack, stride, cnt))
-          continue;
-        for (int c = 0; c < 3; ++c) L[c] = L[c] + beta[c] * f[c] * ((lp[3 + c] * cx) / dist2);
-      }
-      for (int ai = 0; ai < S.n_area; ++ai) {
-        const int qi = S.area_quad[ai];
-        float a, b;
-        if (ai == 0) {
-          a = unit_open(w.x);
-          b = unit_open(w.y);
-        } else {
-          const uint4 w2 = path_words(k0, k1, pix, smp, pair, tag, v + 1, ai);
-          a = unit_open(w2.x);
-          b = unit_open(w2.y);
-        }
-        const float* qd = S.quad[qi];
-        const V3 qo = ld3(qd), e1 = ld3(qd + 3), e2 = ld3(qd + 6);
-        const V3 yl = mk(qo.x + e1.x * a + e2.x * b, qo.y + e1.y * a + e2.y * b,
-                         qo.z + e1.z * a + e2.z * b);
-        const V3 nl = cross(e1, e2);
-        const float area = sqrtf(dot(nl, nl));
-        const V3 nlu = scale(nl, 1.0f / area);
-        const V3 toL = sub(yl, p);
-        const float dist2 = dot(toL, toL);
-        const float dist = sqrtf(dist2);
-        const V3 wi = scale(toL, 1.0f / dist);
-        const float cx = dot(n, wi);
-        const float cl = -dot(nlu, wi);
-        if (!(cx > 0.0f && cl > 0.0f)) continue;
-        if (occluded<COUNT>(S, nodes, tris, offset_origin(p, n), wi, dist * 0.9999f, stack, stride, cnt))
-          continue;
-        const float G = ((cx * cl) * area) / dist2;
-        const int qm = S.quad_mat[qi];
-        for (int c = 0; c < 3; ++c) L[c] = L[c] + beta[c] * f[c] * S.mat_rgb[qm][c] * G;
-      }
-      if (v == S.B) break;
-      const float u1 = unit_open(w.z), u2 = unit_open(w.w);
-      const float r = sqrtf(u1);
-      float sn, cs;
-      sincos_turn(u2, &sn, &cs);
-      const float lx = r * cs, ly = r * sn, lz = sqrtf(1.0f - u1);
-      V3 b1, b2;
-      basis(n, &b1, &b2);
-      const V3 nd = unit(mk(b1.x * lx + b2.x * ly + n.x * lz, b1.y * lx + b2.y * ly + n.y * lz,
-                            b1.z * lx + b2.z * ly + n.z * lz));
-      o = offset_origin(p, n);
-      d = nd;
-      for (int c = 0; c < 3; ++c) beta[c] = beta[c] * S.mat_rgb[mat][c];
-      specular = false;
-    } else {  // dielectric sphere
-      if (v == S.B) break;
-      const float ior = S.mat_ior[mat];
-      V3 n = ng;
-      float cosi = -dot(d, n);
-      float ei = 1.0f, et = ior;
-      if (cosi < 0.0f) {
-        n = neg(n);
-        cosi = -cosi;
-        ei = ior;
-        et = 1.0f;
-      }
-      const float F = fresnel_dielectric(cosi, ei, et);
-      const float u = unit_open(w.z);
-      V3 nd, side;
-      if (u < F) {
-        const float dn = dot(d, n);
-        nd = mk(d.x - n.x * (2.0f * dn), d.y - n.y * (2.0f * dn), d.z - n.z * (2.0f * dn));
-        side = n;
-      } else {
-        const float eta = ei / et;
-        const float sin2t = (eta * eta) * (1.0f - cosi * cosi);
-        const float cost = sqrtf(1.0f - sin2t);
-        const float kk = eta * cosi - cost;
-        nd = mk(d.x * eta + n.x * kk, d.y * eta + n.y * kk, d.z * eta + n.z * kk);
-        side = neg(n);
-      }
-      o = offset_origin(p, side);
-      d = unit(nd);
-      specular = true;
-    }
-  }
-}
-
 // ---------------------------------------------------------------------------
 // kernels
 // ---------------------------------------------------------------------------
 constexpr int kTileW = 16, kTileH = 8, kBlock = kTileW * kTileH;  // two 8x8 waves
+#ifndef PRDPT_MIN_WAVES_PER_EU
+#define PRDPT_MIN_WAVES_PER_EU 5
+#endif
 
 // Load the scene constants into LDS and apply perturbation k's parameter values.
 __device__ __forceinline__ void load_state(SceneHdr& S, const SceneHdr* __restrict__ g,
@@ -527,43 +405,258 @@ __device__ __forceinline__ void load_state(SceneHdr& S, const SceneHdr* __restri
 // Fused render + loss.  grid.x = pixel tiles (16x8), grid.y = perturbation k.
 // Writes partial[k][tile] = sum over the tile's pixels of sum_c (I - R)^2 when
 // ref != nullptr, and the image when img != nullptr.
+//
+// Each lane owns one pixel and runs its spp camera paths as a state machine
+// that traces exactly one ray per loop iteration: the extension ray of the
+// current vertex, or one next-event shadow ray.  A lane whose path ends starts
+// its next sample in the same iteration, so lanes never wait for the longest
+// path of the wave, and every iteration runs the same traversal code.  Per
+// sample the radiance terms are added in the same order as a recursive
+// implementation (vertex by vertex; point lights, then area lights).
 template <bool COUNT>
-__global__ __launch_bounds__(kBlock) void render_loss_kernel(
+__global__ __launch_bounds__(kBlock, PRDPT_MIN_WAVES_PER_EU) void render_loss_kernel(
     DevScene scene, const float* __restrict__ X, int d, int tag, uint32_t k0, uint32_t k1,
     const float* __restrict__ ref, float* __restrict__ img, float* __restrict__ partial,
     unsigned long long* __restrict__ counters) {
   __shared__ SceneHdr S;
-  __shared__ int stack[kStackDepth * kBlock];
+  __shared__ int stack[kLdsStack * kBlock];
   __shared__ float wsum[kBlock / 64];
   const int k = blockIdx.y;
   load_state(S, scene.hdr, X + (size_t)k * d, d);
+  const Node* __restrict__ nodes = scene.nodes;
+  const Tri* __restrict__ tris = scene.tris;
   const int tiles_x = (S.W + kTileW - 1) / kTileW;
   const int tile = blockIdx.x;
   const int t = threadIdx.x;
   const int lx = (t & 7) + 8 * (t >> 6), ly = (t >> 3) & 7;
   const int x = (tile % tiles_x) * kTileW + lx, y = (tile / tiles_x) * kTileH + ly;
-  float e = 0.0f;
+  const bool valid = x < S.W && y < S.H;
+  const int pix = y * S.W + x;
+  const int pair = k >> 1;
+  const int spp = S.spp;
+  const int n_lights = S.n_pl + S.n_area;
+  int* stk = stack + t;
   Counters cnt{0u, 0u, 0u, 0u};
-  if (x < S.W && y < S.H) {
-    const int pix = y * S.W + x;
-    const int pair = k >> 1;
-    float acc[3] = {0.0f, 0.0f, 0.0f};
-    for (int s = 0; s < S.spp; ++s) {
-      float L[3];
-      radiance<COUNT>(S, scene.nodes, scene.tris, k0, k1, pix, x, y, s, pair, tag, stack + t,
-                      kBlock, cnt, L);
-      acc[0] = acc[0] + L[0];
-      acc[1] = acc[1] + L[1];
-      acc[2] = acc[2] + L[2];
+
+  float acc0 = 0.0f, acc1 = 0.0f, acc2 = 0.0f;
+  // path state
+  V3 o = mk(0.0f, 0.0f, 0.0f), dir = o, p = o, n = o;
+  float tmax = __builtin_huge_valf();
+  bool shadow = false, specular = true;
+  float b0 = 1.0f, b1 = 1.0f, b2 = 1.0f, L0 = 0.0f, L1 = 0.0f, L2 = 0.0f;
+  float c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;  // pending next-event contribution
+  int v = 0, mat = 0, light = -1;          // light >= 0: next-event stage of a diffuse vertex
+  uint4 w = make_uint4(0u, 0u, 0u, 0u);
+
+  int s = valid ? 0 : spp;
+  bool start = s < spp;
+  while (s < spp) {
+    if (start) {  // camera ray of sample s
+      start = false;
+      if (COUNT) cnt.paths++;
+      float jx = 0.5f, jy = 0.5f;
+      if (!S.pixel_center) {
+        const uint4 wj = path_words(k0, k1, pix, s, pair, tag, 0, 0);
+        jx = unit_open(wj.x);
+        jy = unit_open(wj.y);
+      }
+      const float px = (float)x + jx, py = (float)y + jy;
+      const float sx = 2.0f * (px / (float)S.W) - 1.0f;
+      const float sy = 1.0f - 2.0f * (py / (float)S.H);
+      o = ld3(S.eye);
+      dir = unit(mk(S.fwd[0] + S.right[0] * sx + S.up[0] * sy,
+                    S.fwd[1] + S.right[1] * sx + S.up[1] * sy,
+                    S.fwd[2] + S.right[2] * sx + S.up[2] * sy));
+      tmax = __builtin_huge_valf();
+      shadow = false;
+      specular = true;
+      b0 = b1 = b2 = 1.0f;
+      L0 = L1 = L2 = 0.0f;
+      v = 0;
+      light = -1;
     }
-    const float inv_spp = 1.0f / (float)S.spp;
-    const float I0 = acc[0] * inv_spp, I1 = acc[1] * inv_spp, I2 = acc[2] * inv_spp;
+    Hit h;
+    trace_ray<COUNT>(S, nodes, tris, o, dir, tmax, shadow, h, stk, kBlock, cnt);
+    bool end_path = false;
+    if (shadow) {
+      if (h.id < 0) {
+        L0 = L0 + c0;
+        L1 = L1 + c1;
+        L2 = L2 + c2;
+      }
+      ++light;
+    } else if (h.id < 0) {
+      L0 = L0 + b0 * S.env[0];
+      L1 = L1 + b1 * S.env[1];
+      L2 = L2 + b2 * S.env[2];
+      end_path = true;
+    } else {
+      p = at(o, dir, h.t);
+      V3 ng;
+      if (h.id < S.n_sph) {
+        mat = S.sph_mat[h.id];
+        ng = unit(sub(p, ld3(S.sph[h.id])));
+      } else if (h.id < S.tri_id_base) {
+        const int qi = h.id - S.n_sph;
+        mat = S.quad_mat[qi];
+        ng = unit(cross(ld3(S.quad[qi] + 3), ld3(S.quad[qi] + 6)));
+      } else {
+        const float4* tp = reinterpret_cast<const float4*>(tris + h.slot);
+        const float4 p0 = tp[0], p1 = tp[1], p2 = tp[2];
+        mat = __float_as_int(p2.z);
+        ng = unit(cross(mk(p0.w, p1.x, p1.y), mk(p1.z, p1.w, p2.x)));
+      }
+      const int mt = S.mat_type[mat];
+      if (mt == PRDPT_MAT_EMISSIVE) {
+        if (specular && dot(dir, ng) < 0.0f) {
+          L0 = L0 + b0 * S.mat_rgb[mat][0];
+          L1 = L1 + b1 * S.mat_rgb[mat][1];
+          L2 = L2 + b2 * S.mat_rgb[mat][2];
+        }
+        end_path = true;
+      } else {
+        w = path_words(k0, k1, pix, s, pair, tag, v + 1, 0);
+        if (mt == PRDPT_MAT_DIFFUSE) {
+          n = dot(ng, dir) > 0.0f ? neg(ng) : ng;
+          light = 0;
+        } else if (v == S.B) {  // dielectric sphere, bounce budget spent
+          end_path = true;
+        } else {
+          const float ior = S.mat_ior[mat];
+          V3 nn = ng;
+          float cosi = -dot(dir, nn);
+          float ei = 1.0f, et = ior;
+          if (cosi < 0.0f) {
+            nn = neg(nn);
+            cosi = -cosi;
+            ei = ior;
+            et = 1.0f;
+          }
+          const float F = fresnel_dielectric(cosi, ei, et);
+          V3 nd, side;
+          if (unit_open(w.z) < F) {
+            const float dn = dot(dir, nn);
+            nd = mk(dir.x - nn.x * (2.0f * dn), dir.y - nn.y * (2.0f * dn), dir.z - nn.z * (2.0f * dn));
+            side = nn;
+          } else {
+            const float eta = ei / et;
+            const float sin2t = (eta * eta) * (1.0f - cosi * cosi);
+            const float cost = sqrtf(1.0f - sin2t);
+            const float kk = eta * cosi - cost;
+            nd = mk(dir.x * eta + nn.x * kk, dir.y * eta + nn.y * kk, dir.z * eta + nn.z * kk);
+            side = neg(nn);
+          }
+          o = offset_origin(p, side);
+          dir = unit(nd);
+          tmax = __builtin_huge_valf();
+          specular = true;
+          ++v;
+        }
+      }
+    }
+    if (!end_path && light >= 0) {
+      // next-event estimation at a diffuse vertex: set up the next light whose
+      // sample faces both surfaces, else continue the path
+      shadow = false;
+      const float f0 = S.mat_rgb[mat][0] * kInvPi, f1 = S.mat_rgb[mat][1] * kInvPi,
+                  f2 = S.mat_rgb[mat][2] * kInvPi;
+      for (; light < n_lights; ++light) {
+        if (light < S.n_pl) {
+          const float* lp = S.pl[light];
+          const V3 toL = sub(ld3(lp), p);
+          const float dist2 = dot(toL, toL);
+          const float dist = sqrtf(dist2);
+          const V3 wi = scale(toL, 1.0f / dist);
+          const float cx = dot(n, wi);
+          if (!(cx > 0.0f)) continue;
+          c0 = b0 * f0 * ((lp[3] * cx) / dist2);
+          c1 = b1 * f1 * ((lp[4] * cx) / dist2);
+          c2 = b2 * f2 * ((lp[5] * cx) / dist2);
+          o = offset_origin(p, n);
+          dir = wi;
+          tmax = dist * 0.9999f;
+          shadow = true;
+          break;
+        }
+        const int ai = light - S.n_pl;
+        const int qi = S.area_quad[ai];
+        float ua, ub;
+        if (ai == 0) {
+          ua = unit_open(w.x);
+          ub = unit_open(w.y);
+        } else {
+          const uint4 w2 = path_words(k0, k1, pix, s, pair, tag, v + 1, ai);
+          ua = unit_open(w2.x);
+          ub = unit_open(w2.y);
+        }
+        const float* qd = S.quad[qi];
+        const V3 qo = ld3(qd), e1 = ld3(qd + 3), e2 = ld3(qd + 6);
+        const V3 yl = mk(qo.x + e1.x * ua + e2.x * ub, qo.y + e1.y * ua + e2.y * ub,
+                         qo.z + e1.z * ua + e2.z * ub);
+        const V3 nl = cross(e1, e2);
+        const float area = sqrtf(dot(nl, nl));
+        const V3 nlu = scale(nl, 1.0f / area);
+        const V3 toL = sub(yl, p);
+        const float dist2 = dot(toL, toL);
+        const float dist = sqrtf(dist2);
+        const V3 wi = scale(toL, 1.0f / dist);
+        const float cx = dot(n, wi);
+        const float cl = -dot(nlu, wi);
+        if (!(cx > 0.0f && cl > 0.0f)) continue;
+        const float G = ((cx * cl) * area) / dist2;
+        const int qm = S.quad_mat[qi];
+        c0 = b0 * f0 * S.mat_rgb[qm][0] * G;
+        c1 = b1 * f1 * S.mat_rgb[qm][1] * G;
+        c2 = b2 * f2 * S.mat_rgb[qm][2] * G;
+        o = offset_origin(p, n);
+        dir = wi;
+        tmax = dist * 0.9999f;
+        shadow = true;
+        break;
+      }
+      if (!shadow) {  // all lights done: cosine-weighted bounce
+        light = -1;
+        if (v == S.B) {
+          end_path = true;
+        } else {
+          const float u1 = unit_open(w.z), u2 = unit_open(w.w);
+          const float r = sqrtf(u1);
+          float sn, cs;
+          sincos_turn(u2, &sn, &cs);
+          const float lx2 = r * cs, ly2 = r * sn, lz2 = sqrtf(1.0f - u1);
+          V3 e1, e2;
+          basis(n, &e1, &e2);
+          dir = unit(mk(e1.x * lx2 + e2.x * ly2 + n.x * lz2, e1.y * lx2 + e2.y * ly2 + n.y * lz2,
+                        e1.z * lx2 + e2.z * ly2 + n.z * lz2));
+          o = offset_origin(p, n);
+          tmax = __builtin_huge_valf();
+          b0 = b0 * S.mat_rgb[mat][0];
+          b1 = b1 * S.mat_rgb[mat][1];
+          b2 = b2 * S.mat_rgb[mat][2];
+          specular = false;
+          ++v;
+        }
+      }
+    }
+    if (end_path) {
+      acc0 = acc0 + L0;
+      acc1 = acc1 + L1;
+      acc2 = acc2 + L2;
+      ++s;
+      start = s < spp;
+    }
+  }
+
+  float e = 0.0f;
+  if (valid) {
+    const float inv_spp = 1.0f / (float)spp;
+    const float I0 = acc0 * inv_spp, I1 = acc1 * inv_spp, I2 = acc2 * inv_spp;
     const size_t npix = (size_t)S.W * S.H;
     if (img) {
-      float* o = img + ((size_t)k * npix + pix) * 3;
-      o[0] = I0;
-      o[1] = I1;
-      o[2] = I2;
+      float* op = img + ((size_t)k * npix + pix) * 3;
+      op[0] = I0;
+      op[1] = I1;
+      op[2] = I2;
     }
     if (ref) {
       const float* r = ref + (size_t)pix * 3;
@@ -584,9 +677,9 @@ __global__ __launch_bounds__(kBlock) void render_loss_kernel(
     if ((t & 63) == 0) wsum[t >> 6] = e;
     __syncthreads();
     if (t == 0) {
-      float s = wsum[0];
-      for (int w = 1; w < kBlock / 64; ++w) s = s + wsum[w];
-      partial[(size_t)k * gridDim.x + tile] = s;
+      float sum = wsum[0];
+      for (int wv = 1; wv < kBlock / 64; ++wv) sum = sum + wsum[wv];
+      partial[(size_t)k * gridDim.x + tile] = sum;
     }
   }
 }
