@@ -406,6 +406,10 @@ int prdpt_scene_create(prdpt_ctx* ctx, const prdpt_scene_desc* D, prdpt_scene** 
   for (int i = 0; i < n_inst; ++i) {
     BvhOut b = build_bvh(D->triangles, tri_mat.data(), lists[i].data(), (int)lists[i].size(),
                          h.tri_id_base, nodes, tris);
+    if (b.root == -2) {
+      delete s;
+      return fail(PRDPT_E_SCENE, "mesh instance too large for the BVH depth bound");
+    }
     h.inst_root[i] = b.root;
     s->bvh_depth = std::max(s->bvh_depth, b.depth);
   }
@@ -413,7 +417,7 @@ int prdpt_scene_create(prdpt_ctx* ctx, const prdpt_scene_desc* D, prdpt_scene** 
     delete s;
     return fail(PRDPT_E_SCENE, "too many BVH nodes (at most 2^24)");
   }
-  if (s->bvh_depth > kStackDepth) {
+  if (s->bvh_depth > kMaxInnerDepth) {
     delete s;
     return fail(PRDPT_E_SCENE, "BVH deeper than the traversal stack");
   }

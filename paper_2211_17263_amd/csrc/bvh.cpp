@@ -1,7 +1,9 @@
 // Host BVH builder: binned surface-area heuristic (16 bins per axis), leaves of
-// at most 4 triangles, object-median splits below a depth threshold so the tree
-// never exceeds the traversal stack.  Output is appended to flat node/triangle
-// arrays in the 64-byte / 48-byte layouts the kernels read with 16-byte loads.
+// at most 4 triangles, inner-node depth bounded by kMaxInnerDepth so a fixed
+// traversal stack always suffices: a split is admissible only if both children
+// still fit a balanced subtree in the depth that remains (else object median).
+// Output is appended to flat node/triangle arrays in the 64-byte / 48-byte
+// layouts the kernels read with 16-byte loads.
 #include <algorithm>
 #include <cfloat>
 #include <cmath>
@@ -44,7 +46,13 @@ struct Prim {
 
 constexpr int kBins = 16;
 constexpr int kLeafMax = 4;
-constexpr int kSahDepth = 22;  // below this depth: object-median splits
+
+// largest triangle count a subtree whose root inner node sits at depth D can
+// hold within the depth bound (two leaves of kLeafMax at depth kMaxInnerDepth)
+inline long long capacity(int D) {
+  const int levels = kMaxInnerDepth - D + 1;
+  return levels >= 40 ? (1LL << 50) : (long long)kLeafMax << levels;
+}
 
 struct Builder {
   const float* tri9;
@@ -90,21 +98,23 @@ struct Builder {
   }
 
   // returns (idx, cnt) reference to a subtree: cnt > 0 leaf, cnt == 0 inner
+  // node at inner-node depth `depth`
   void build(int begin, int end, int depth, int32_t* idx, int32_t* cnt) {
-    max_depth = std::max(max_depth, depth);
     int n = end - begin;
     if (n <= kLeafMax) {
       *idx = emit_leaf(begin, end);
       *cnt = n;
       return;
     }
+    max_depth = std::max(max_depth, depth);
+    const long long child_cap = capacity(depth + 1);
     Box cb;
     for (int i = begin; i < end; ++i) cb.grow(prims[i].c);
     int axis = 0;
     for (int a = 1; a < 3; ++a)
       if (cb.hi[a] - cb.lo[a] > cb.hi[axis] - cb.lo[axis]) axis = a;
     int mid = -1;
-    if (depth < kSahDepth && cb.hi[axis] > cb.lo[axis]) {
+    if (cb.hi[axis] > cb.lo[axis]) {
       double best = DBL_MAX;
       int best_axis = -1, best_bin = -1;
       for (int a = 0; a < 3; ++a) {
@@ -134,6 +144,7 @@ struct Builder {
           lacc.grow(bb[b]);
           lcnt += bc[b];
           if (lcnt == 0 || right_cnt[b + 1] == 0) continue;
+          if (lcnt > child_cap || right_cnt[b + 1] > child_cap) continue;
           double cost = lacc.area() * lcnt + right_area[b + 1] * right_cnt[b + 1];
           if (cost < best) {
             best = cost;
@@ -204,6 +215,7 @@ BvhOut build_bvh(const float* tri9, const int32_t* tri_mat, const int32_t* list,
   BvhOut out{-1, 0};
   if (n == 0) return out;
   int32_t idx, cnt;
+  if ((long long)n > capacity(1)) return BvhOut{-2, 0};
   b.build(0, n, 1, &idx, &cnt);
   if (cnt > 0) {  // a single leaf: wrap it in a root with one child
     int ni = (int)nodes.size();
@@ -217,7 +229,7 @@ BvhOut build_bvh(const float* tri9, const int32_t* tri_mat, const int32_t* list,
     nd.idx0 = idx; nd.cnt0 = cnt; nd.idx1 = -1; nd.cnt1 = 0;
     nodes.push_back(nd);
     idx = ni;
-    b.max_depth = 2;
+    b.max_depth = 1;
   }
   out.root = idx;
   out.depth = b.max_depth;

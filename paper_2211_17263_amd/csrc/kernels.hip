@@ -154,34 +154,27 @@ __device__ __forceinline__ bool hit_quad(V3 o, V3 d, const float* qd, float tmax
   return true;
 }
 
-// Moeller-Trumbore on the stored (v0, e1, e2)
+// Moeller-Trumbore on the stored (v0, e1, e2).  Every quantity is computed
+// before any decision so that the three triangle loads are consumed together;
+// the accept predicate (det != 0, 0 <= u <= 1, v >= 0, u + v <= 1,
+// 0 < t < tmax, each on the rounded binary32 values) is the one a test with
+// early returns takes.
 __device__ __forceinline__ bool hit_tri(V3 o, V3 d, V3 v0, V3 e1, V3 e2, float tmax, float* tout) {
   const V3 pv = cross(d, e2);
   const float det = dot(e1, pv);
-  if (det == 0.0f) return false;
   const V3 tv = sub(o, v0);
+  const V3 qv = cross(tv, e1);
   const float un = dot(tv, pv);
-  // Rejections that skip the division yet take the same decision as the
-  // rounded test below: with 2^-60 <= |det| <= 2^60, un/det <= -2^-60 makes the
-  // binary32 u = un * (1/det) a negative normal number, and un/det above
-  // 1 + 2^-20 (less one rounding of the threshold) keeps u above 1.
-  const float adet = fabsf(det);
-  if (adet >= 0x1p-60f && adet <= 0x1p60f) {
-    const float aun = fabsf(un);
-    const bool opposite = (un < 0.0f) != (det < 0.0f);
-    if (un != 0.0f && opposite && aun >= adet * 0x1p-60f) return false;
-    if (!opposite && aun > adet * 1.00000095367431640625f) return false;
-  }
+  const float vn = dot(d, qv);
+  const float tn = dot(e2, qv);
   const float inv = 1.0f / det;
   const float u = un * inv;
-  if (u < 0.0f || u > 1.0f) return false;
-  const V3 qv = cross(tv, e1);
-  const float v = dot(d, qv) * inv;
-  if (v < 0.0f || u + v > 1.0f) return false;
-  const float t = dot(e2, qv) * inv;
-  if (!(t > 0.0f && t < tmax)) return false;
+  const float v = vn * inv;
+  const float t = tn * inv;
+  const bool hit = det != 0.0f && !(u < 0.0f || u > 1.0f) && !(v < 0.0f || u + v > 1.0f) &&
+                   (t > 0.0f && t < tmax);
   *tout = t;
-  return true;
+  return hit;
 }
 
 struct Hit {
@@ -197,11 +190,6 @@ __device__ __forceinline__ void keep_closer(Hit& h, float t, int id, int slot) {
     h.slot = slot;
   }
 }
-
-#ifndef PRDPT_LDS_STACK
-#define PRDPT_LDS_STACK 16
-#endif
-constexpr int kLdsStack = PRDPT_LDS_STACK;
 
 struct Counters {
   uint32_t nodes, tris, rays, paths;
@@ -225,11 +213,13 @@ __device__ __forceinline__ float safe_inv(float x) {
 }
 
 // Traverse one instance BVH.  ANY: stop at the first hit with t < tmax.
-// Trace one ray through the analytic primitives and every instance BVH in a
-// single loop (stack entries carry the instance in their top byte, so lanes do
-// not reconverge between instances).  any = true: shadow query, stop at the
-// first occluder with t < tmax (emissive quads are not occluders); otherwise
-// keep the closest hit by (t, primitive id).
+// Trace one ray through the analytic primitives and every instance BVH in one
+// loop (lanes do not reconverge between instances; the instances are visited in
+// order, each to completion).  any = true: shadow query, stop at the first
+// occluder with t < tmax (emissive quads are not occluders); otherwise keep the
+// closest hit by (t, primitive id).  The stack holds kStackEntries entries in
+// LDS (stride = work-group size); the builder bounds the inner-node depth so it
+// cannot overflow.
 template <bool COUNT>
 __device__ void trace_ray(const SceneHdr& S, const Node* __restrict__ nodes,
                           const Tri* __restrict__ tris, V3 o, V3 d, float tmax, bool any, Hit& h,
@@ -260,31 +250,23 @@ __device__ void trace_ray(const SceneHdr& S, const Node* __restrict__ nodes,
     }
   }
   const V3 inv = mk(safe_inv(d.x), safe_inv(d.y), safe_inv(d.z));
-  // short stack: the top kLdsStack entries live in LDS, deeper ones in a
-  // private overflow array (rarely touched; the builder bounds the depth)
-  int spill[kStackDepth + PRDPT_MAX_INSTANCES - kLdsStack];
   int sp = 0;
-  for (int m = S.n_inst - 1; m >= 0; --m) {
-    if (S.inst_root[m] < 0) continue;
-    const int e = (m << 24) | S.inst_root[m];
-    if (sp < kLdsStack) stack[sp * stride] = e;
-    else spill[sp - kLdsStack] = e;
-    ++sp;
-  }
   int inst = -1;
   int node = -1;
   V3 om = o, oi = o;
   while (true) {
     if (node < 0) {
-      if (sp == 0) break;
-      --sp;
-      const int e = sp < kLdsStack ? stack[sp * stride] : spill[sp - kLdsStack];
-      node = e & 0xFFFFFF;
-      const int m = e >> 24;
-      if (m != inst) {
+      if (sp > 0) {
+        --sp;
+        node = stack[sp * stride];
+      } else {
+        do {
+          ++inst;
+        } while (inst < S.n_inst && S.inst_root[inst] < 0);
+        if (inst >= S.n_inst) break;
+        node = S.inst_root[inst];
         // an instance: the ray moves by minus the mesh translation
-        inst = m;
-        om = mk(o.x - S.inst_xlate[m][0], o.y - S.inst_xlate[m][1], o.z - S.inst_xlate[m][2]);
+        om = mk(o.x - S.inst_xlate[inst][0], o.y - S.inst_xlate[inst][1], o.z - S.inst_xlate[inst][2]);
         oi = mk(-om.x * inv.x, -om.y * inv.y, -om.z * inv.z);
       }
     }
@@ -294,8 +276,8 @@ __device__ void trace_ray(const SceneHdr& S, const Node* __restrict__ nodes,
     if (COUNT) cnt.nodes++;
     const float tcull = any ? tmax : fminf(tmax, h.t);
     const float t0 = slab(a.x, a.y, a.z, a.w, c.x, c.y, inv, oi, tcull);
-    const float t1 = ix.y >= 0 ? slab(b.x, b.y, b.z, b.w, c.z, c.w, inv, oi, tcull)
-                               : __builtin_huge_valf();
+    const float t1s = slab(b.x, b.y, b.z, b.w, c.z, c.w, inv, oi, tcull);
+    const float t1 = ix.y >= 0 ? t1s : __builtin_huge_valf();
     bool h0 = t0 < __builtin_huge_valf(), h1 = t1 < __builtin_huge_valf();
 #pragma unroll
     for (int side = 0; side < 2; ++side) {
@@ -324,9 +306,7 @@ __device__ void trace_ray(const SceneHdr& S, const Node* __restrict__ nodes,
     }
     if (h0 && h1) {
       const bool first0 = t0 <= t1;
-      const int far = (inst << 24) | (first0 ? ix.y : ix.x);
-      if (sp < kLdsStack) stack[sp * stride] = far;
-      else spill[sp - kLdsStack] = far;
+      stack[sp * stride] = first0 ? ix.y : ix.x;
       ++sp;
       node = first0 ? ix.x : ix.y;
     } else if (h0) {
@@ -419,7 +399,7 @@ __global__ __launch_bounds__(kBlock, PRDPT_MIN_WAVES_PER_EU) void render_loss_ke
     const float* __restrict__ ref, float* __restrict__ img, float* __restrict__ partial,
     unsigned long long* __restrict__ counters) {
   __shared__ SceneHdr S;
-  __shared__ int stack[kLdsStack * kBlock];
+  __shared__ int stack[kStackEntries * kBlock];
   __shared__ float wsum[kBlock / 64];
   const int k = blockIdx.y;
   load_state(S, scene.hdr, X + (size_t)k * d, d);

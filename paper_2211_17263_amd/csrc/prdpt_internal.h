@@ -9,7 +9,8 @@ namespace prdpt {
 constexpr int kTagTau = 1;
 constexpr int kTagPath = 2;
 constexpr int kTagRef = 3;
-constexpr int kStackDepth = 40;   // >= maximum BVH depth the builder emits
+constexpr int kMaxInnerDepth = 25;               // BVH inner-node depth bound (root = 1)
+constexpr int kStackEntries = kMaxInnerDepth - 1; // traversal stack entries per ray
 
 // Flattened BVH node: both children's boxes live in the parent (64 bytes, four
 // 16-byte loads).  cnt == 0: idx is an inner node; cnt > 0: idx is the first of
