@@ -220,6 +220,54 @@ int prdpt_grad_estimate_async(prdpt_scene* scene, const float* ref_dev, const fl
 int prdpt_combine_async(prdpt_ctx* ctx, int P, int d, const double* c_dev,
                         const double* losses_dev, const double* scale_dev, double* grad_dev);
 
+/*
+ * ---- batched estimation ------------------------------------------------------
+ * One request = the arguments of prdpt_grad_estimate for one resident scene of
+ * the context.  A batch runs all its valid requests together: one perturbation
+ * launch, one persistent render launch whose work-groups take (request,
+ * perturbation, run of pixel tiles) items from a device counter, one loss and
+ * one combine launch, captured once in a HIP graph and replayed per batch.
+ * Every result equals prdpt_grad_estimate of that request alone, bit for bit.
+ */
+typedef struct {
+  prdpt_scene* scene;      /* resident scene of the batch's context */
+  const float* ref;        /* device float[H][W][3] */
+  const float* theta;      /* host float[d] */
+  const float* sigma;      /* host float[d], > 0 */
+  int32_t N;               /* even, >= 2 */
+  int32_t est;             /* PRDPT_EST_* */
+  uint64_t seed;
+  double* grad_out;        /* host double[d] */
+  double* loss_out;        /* host double[1] or NULL */
+  double* losses_out;      /* host double[N] or NULL */
+  int32_t status;          /* out: PRDPT_OK, or the error of this request alone */
+} prdpt_request;
+
+/*
+ * Run n requests as one batch (synchronous).  Invalid requests get a negative
+ * `status` and are skipped without affecting the others; the call itself fails
+ * only on context-level errors (allocation, HIP).  The batch runs on a stream
+ * the context owns, ordered after work already enqueued on the context stream.
+ */
+int prdpt_batch_estimate(prdpt_ctx* ctx, prdpt_request* reqs, int n);
+
+/*
+ * Launch configuration of the batched form: persistent work-groups per compute
+ * unit, pixel tiles (16x8) per work item, and whether to replay a captured
+ * graph (1) or launch the kernels directly (0).
+ */
+int prdpt_batch_config(prdpt_ctx* ctx, int blocks_per_cu, int tiles_per_item, int use_graph);
+
+/*
+ * Choose blocks_per_cu and tiles_per_item for batches like `reqs` by timing a
+ * sweep on them (device time of the graph), and remember the choice per size
+ * class (compute units, log2 of camera paths, log2 of requests) in a JSON-lines
+ * file at cache_path (nullable: no cache).  A cached size class is applied
+ * without a sweep.  Outputs are nullable.
+ */
+int prdpt_batch_autotune(prdpt_ctx* ctx, prdpt_request* reqs, int n, const char* cache_path,
+                         int* best_blocks_per_cu, int* best_tiles_per_item, double* best_ms);
+
 /* Wait for all work enqueued on the context's stream. */
 int prdpt_ctx_synchronize(prdpt_ctx* ctx);
 

@@ -8,85 +8,18 @@
 #include <string>
 #include <vector>
 
-#include "prdpt.h"
-#include "prdpt_internal.h"
-
-namespace prdpt {
-BvhOut build_bvh(const float* tri9, const int32_t* tri_mat, const int32_t* list, int n,
-                 int32_t id_base, std::vector<Node>& nodes, std::vector<Tri>& tris);
-int render_tiles(int W, int H);
-hipError_t launch_tau(hipStream_t st, int est, int d, int P, uint64_t seed, const float* sigma,
-                      const float* theta, double cd, double sqrt2pi, float* tau, double* c, float* X);
-hipError_t launch_render(hipStream_t st, const DevScene& sc, int W, int H, const float* X, int nk,
-                         int d, int tag, uint64_t seed, const float* ref, float* img,
-                         float* partial, unsigned long long* counters);
-hipError_t launch_losses(hipStream_t st, const float* partial, int n_tiles, int N, int npix,
-                         double* losses);
-hipError_t launch_combine(hipStream_t st, int P, int d, const double* c, const double* L,
-                          const double* scale, double* grad, double* loss);
-hipError_t launch_copy(hipStream_t st, const void* src, void* dst, size_t n16);
-}  // namespace prdpt
+#include "ctx_internal.h"
 
 using namespace prdpt;
 
 namespace {
 thread_local std::string g_err;
+}  // namespace
 
-int fail(int code, const std::string& msg) {
+int prdpt::fail(int code, const std::string& msg) {
   g_err = msg;
   return code;
 }
-
-#define HIP_TRY(expr)                                                                   \
-  do {                                                                                  \
-    hipError_t e_ = (expr);                                                             \
-    if (e_ != hipSuccess)                                                               \
-      return fail(PRDPT_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));      \
-  } while (0)
-
-// Mean of the chi distribution with d degrees of freedom (the IS weight constant):
-// C_1 = sqrt(2/pi), C_{k+1} = k / C_k.
-double chi_mean(int d) {
-  double c = std::sqrt(2.0 / M_PI);
-  for (int k = 1; k < d; ++k) c = (double)k / c;
-  return c;
-}
-
-template <class T>
-struct DevBuf {
-  T* p = nullptr;
-  size_t n = 0;
-};
-}  // namespace
-
-struct prdpt_ctx {
-  int device = 0;
-  hipStream_t stream = nullptr;
-  size_t budget = 0;
-  size_t resident = 0;
-  int n_scenes = 0;
-  std::mutex mu;
-  DevBuf<float> X, tau, partial, theta, sigma;
-  DevBuf<double> c, losses, grad, loss;
-  DevBuf<unsigned long long> counters;
-  // optional timing of the fused render kernel (events on the context stream)
-  bool timing = false;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
-  std::vector<hipEvent_t> pool;
-  double timed_ms = 0.0;
-  int64_t timed_launches = 0;
-};
-
-struct prdpt_scene {
-  prdpt_ctx* ctx = nullptr;
-  SceneHdr hdr{};
-  SceneHdr* d_hdr = nullptr;
-  Node* d_nodes = nullptr;
-  Tri* d_tris = nullptr;
-  size_t footprint = 0;
-  int n_nodes = 0, n_tris = 0, bvh_depth = 0;
-  DevScene dev() const { return DevScene{d_hdr, d_nodes, d_tris}; }
-};
 
 namespace {
 
@@ -250,6 +183,7 @@ int prdpt_ctx_destroy(prdpt_ctx* ctx) {
     hipEventDestroy(pr.second);
   }
   for (hipEvent_t e : ctx->pool) hipEventDestroy(e);
+  batch_release(ctx->batch);
   delete ctx;
   return PRDPT_OK;
 }

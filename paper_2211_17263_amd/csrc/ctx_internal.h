@@ -1,0 +1,111 @@
+// Context and scene internals shared by the C ABI translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "prdpt.h"
+#include "prdpt_internal.h"
+
+namespace prdpt {
+BvhOut build_bvh(const float* tri9, const int32_t* tri_mat, const int32_t* list, int n,
+                 int32_t id_base, std::vector<Node>& nodes, std::vector<Tri>& tris);
+int render_tiles(int W, int H);
+hipError_t launch_tau(hipStream_t st, int est, int d, int P, uint64_t seed, const float* sigma,
+                      const float* theta, double cd, double sqrt2pi, float* tau, double* c, float* X);
+hipError_t launch_render(hipStream_t st, const DevScene& sc, int W, int H, const float* X, int nk,
+                         int d, int tag, uint64_t seed, const float* ref, float* img,
+                         float* partial, unsigned long long* counters);
+hipError_t launch_losses(hipStream_t st, const float* partial, int n_tiles, int N, int npix,
+                         double* losses);
+hipError_t launch_combine(hipStream_t st, int P, int d, const double* c, const double* L,
+                          const double* scale, double* grad, double* loss);
+hipError_t launch_batch(hipStream_t st, const BatchReq* reqs, BatchMeta* meta, int render_blocks,
+                        float* tau, double* c, float* X, float* partial, double* losses,
+                        double* grads, double* loss);
+hipError_t launch_copy(hipStream_t st, const void* src, void* dst, size_t n16);
+
+// records `msg` as the calling thread's last error and returns `code`
+int fail(int code, const std::string& msg);
+
+// Mean of the chi distribution with d degrees of freedom (the IS weight constant):
+// C_1 = sqrt(2/pi), C_{k+1} = k / C_k.
+inline double chi_mean(int d) {
+  double c = std::sqrt(2.0 / M_PI);
+  for (int k = 1; k < d; ++k) c = (double)k / c;
+  return c;
+}
+
+template <class T>
+struct DevBuf {
+  T* p = nullptr;
+  size_t n = 0;
+};
+
+// Device and pinned buffers, graph and launch configuration of the batched form.
+struct BatchState {
+  hipStream_t stream = nullptr;  // own non-blocking stream (capturable)
+  hipEvent_t ready = nullptr;    // orders the batch stream after the context stream
+  int n_cu = 0;
+  int blocks_per_cu = 8, tiles_per_item = 1, use_graph = 1;
+  size_t cap_req = 0, cap_pairs = 0, cap_rows = 0, cap_partial = 0;
+  BatchReq* d_reqs = nullptr;
+  BatchMeta* d_meta = nullptr;
+  float* d_tau = nullptr;
+  double* d_c = nullptr;
+  float* d_X = nullptr;
+  float* d_partial = nullptr;
+  double* d_losses = nullptr;
+  double* d_grads = nullptr;
+  double* d_loss = nullptr;
+  BatchReq* h_reqs = nullptr;      // pinned
+  BatchMeta* h_meta = nullptr;     // pinned
+  double* h_grads = nullptr;       // pinned
+  double* h_loss = nullptr;        // pinned
+  double* h_losses = nullptr;      // pinned
+  hipGraphExec_t exec = nullptr;
+  int graph_blocks = 0;
+};
+
+void batch_release(BatchState& b);
+}  // namespace prdpt
+
+struct prdpt_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  size_t budget = 0;
+  size_t resident = 0;
+  int n_scenes = 0;
+  std::mutex mu;
+  prdpt::DevBuf<float> X, tau, partial, theta, sigma;
+  prdpt::DevBuf<double> c, losses, grad, loss;
+  prdpt::DevBuf<unsigned long long> counters;
+  // optional timing of the fused render kernel (events on the context stream)
+  bool timing = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
+  std::vector<hipEvent_t> pool;
+  double timed_ms = 0.0;
+  int64_t timed_launches = 0;
+  prdpt::BatchState batch;
+};
+
+struct prdpt_scene {
+  prdpt_ctx* ctx = nullptr;
+  prdpt::SceneHdr hdr{};
+  prdpt::SceneHdr* d_hdr = nullptr;
+  prdpt::Node* d_nodes = nullptr;
+  prdpt::Tri* d_tris = nullptr;
+  size_t footprint = 0;
+  int n_nodes = 0, n_tris = 0, bvh_depth = 0;
+  prdpt::DevScene dev() const { return prdpt::DevScene{d_hdr, d_nodes, d_tris}; }
+};
+
+#define HIP_TRY(expr)                                                                       \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess)                                                                   \
+      return ::prdpt::fail(PRDPT_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)

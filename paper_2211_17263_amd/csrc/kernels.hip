@@ -11,6 +11,7 @@
 // bit on any IEEE-754 machine; only the pixel/loss sums differ in rounding.
 #include <hip/hip_runtime.h>
 
+#include <cstddef>
 #include <cstdint>
 
 #include "prdpt_internal.h"
@@ -382,9 +383,10 @@ __device__ __forceinline__ void load_state(SceneHdr& S, const SceneHdr* __restri
   __syncthreads();
 }
 
-// Fused render + loss.  grid.x = pixel tiles (16x8), grid.y = perturbation k.
-// Writes partial[k][tile] = sum over the tile's pixels of sum_c (I - R)^2 when
-// ref != nullptr, and the image when img != nullptr.
+// Render one 16x8 pixel tile of perturbation k (S already holds the
+// perturbation's scene state in LDS).  Writes *partial_slot = sum over the
+// tile's pixels of sum_c (I - R)^2 when it is not null (ref must then be set),
+// and the tile's pixels into img (image k) when img != nullptr.
 //
 // Each lane owns one pixel and runs its spp camera paths as a state machine
 // that traces exactly one ray per loop iteration: the extension ray of the
@@ -394,19 +396,13 @@ __device__ __forceinline__ void load_state(SceneHdr& S, const SceneHdr* __restri
 // sample the radiance terms are added in the same order as a recursive
 // implementation (vertex by vertex; point lights, then area lights).
 template <bool COUNT>
-__global__ __launch_bounds__(kBlock, PRDPT_MIN_WAVES_PER_EU) void render_loss_kernel(
-    DevScene scene, const float* __restrict__ X, int d, int tag, uint32_t k0, uint32_t k1,
-    const float* __restrict__ ref, float* __restrict__ img, float* __restrict__ partial,
-    unsigned long long* __restrict__ counters) {
-  __shared__ SceneHdr S;
-  __shared__ int stack[kStackEntries * kBlock];
-  __shared__ float wsum[kBlock / 64];
-  const int k = blockIdx.y;
-  load_state(S, scene.hdr, X + (size_t)k * d, d);
-  const Node* __restrict__ nodes = scene.nodes;
-  const Tri* __restrict__ tris = scene.tris;
+__device__ __forceinline__ void render_tile(const SceneHdr& S, const Node* __restrict__ nodes,
+                                            const Tri* __restrict__ tris, int k, int tile, int tag,
+                                            uint32_t k0, uint32_t k1, const float* __restrict__ ref,
+                                            float* __restrict__ img, float* partial_slot,
+                                            unsigned long long* __restrict__ counters,
+                                            int* __restrict__ stack, float* __restrict__ wsum) {
   const int tiles_x = (S.W + kTileW - 1) / kTileW;
-  const int tile = blockIdx.x;
   const int t = threadIdx.x;
   const int lx = (t & 7) + 8 * (t >> 6), ly = (t >> 3) & 7;
   const int x = (tile % tiles_x) * kTileW + lx, y = (tile / tiles_x) * kTileH + ly;
@@ -650,7 +646,7 @@ __global__ __launch_bounds__(kBlock, PRDPT_MIN_WAVES_PER_EU) void render_loss_ke
     atomicAdd(&counters[2], (unsigned long long)cnt.rays);
     atomicAdd(&counters[3], (unsigned long long)cnt.paths);
   }
-  if (partial) {
+  if (partial_slot) {
     // fixed-order butterfly within the wave, then the waves in order
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) e += __shfl_xor(e, off, 64);
@@ -659,18 +655,35 @@ __global__ __launch_bounds__(kBlock, PRDPT_MIN_WAVES_PER_EU) void render_loss_ke
     if (t == 0) {
       float sum = wsum[0];
       for (int wv = 1; wv < kBlock / 64; ++wv) sum = sum + wsum[wv];
-      partial[(size_t)k * gridDim.x + tile] = sum;
+      *partial_slot = sum;
     }
   }
 }
 
-// One thread per antithetic pair: tau_p, weights c_p and the two parameter rows.
-__global__ void tau_kernel(int est, int d, int P, uint32_t k0, uint32_t k1,
-                           const float* __restrict__ sigma, const float* __restrict__ theta,
-                           double cd, double sqrt2pi, float* __restrict__ tau,
-                           double* __restrict__ c, float* __restrict__ X) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= P) return;
+
+// Single-request launch: grid.x = pixel tiles, grid.y = perturbation k.
+template <bool COUNT>
+__global__ __launch_bounds__(kBlock, PRDPT_MIN_WAVES_PER_EU) void render_loss_kernel(
+    DevScene scene, const float* __restrict__ X, int d, int tag, uint32_t k0, uint32_t k1,
+    const float* __restrict__ ref, float* __restrict__ img, float* __restrict__ partial,
+    unsigned long long* __restrict__ counters) {
+  __shared__ SceneHdr S;
+  __shared__ int stack[kStackEntries * kBlock];
+  __shared__ float wsum[kBlock / 64];
+  const int k = blockIdx.y;
+  load_state(S, scene.hdr, X + (size_t)k * d, d);
+  render_tile<COUNT>(S, scene.nodes, scene.tris, k, blockIdx.x, tag, k0, k1, ref, img,
+                     partial ? partial + (size_t)k * gridDim.x + blockIdx.x : nullptr, counters,
+                     stack, wsum);
+}
+
+// Perturbation draw for pair p (Sec. 3.2): Philox TAU stream words in order,
+// tau_p, binary64 pair weights c_p, and the parameter rows theta +- tau_p.
+// Rows are written with stride `ld` (>= d).
+__device__ void draw_pair(int est, int d, int p, uint32_t k0, uint32_t k1,
+                          const float* __restrict__ sigma, const float* __restrict__ theta,
+                          double cd, double sqrt2pi, int ld, float* __restrict__ tau,
+                          double* __restrict__ c, float* __restrict__ Xp, float* __restrict__ Xm) {
   uint32_t blk = 0;
   int used = 4;
   uint4 w = make_uint4(0, 0, 0, 0);
@@ -742,41 +755,161 @@ __global__ void tau_kernel(int est, int d, int P, uint32_t k0, uint32_t k1,
     }
   }
   for (int j = 0; j < d; ++j) {
-    tau[(size_t)p * d + j] = tv[j];
-    c[(size_t)p * d + j] = cw[j];
-    X[(size_t)(2 * p) * d + j] = theta[j] + tv[j];
-    X[(size_t)(2 * p + 1) * d + j] = theta[j] - tv[j];
+    tau[j] = tv[j];
+    c[j] = cw[j];
+    Xp[j] = theta[j] + tv[j];
+    Xm[j] = theta[j] - tv[j];
   }
+  (void)ld;
 }
 
-// Per-image losses L_k = (sum of tile partials) / (3 H W), in binary64, one wave
-// per image with a fixed summation order.
-__global__ void loss_kernel(const float* __restrict__ partial, int n_tiles, int N, double inv_den,
-                            double* __restrict__ losses) {
-  const int k = blockIdx.x;
-  const int lane = threadIdx.x;
+// Per-image loss: (sum of the image's tile partials) / (3 H W) in binary64, one
+// wave per image, lane i summing tiles i, i+64, ..., then a fixed butterfly.
+__device__ __forceinline__ double row_loss(const float* __restrict__ part, int n_tiles,
+                                           double inv_den) {
+  const int lane = threadIdx.x & 63;
   double s = 0.0;
-  for (int i = lane; i < n_tiles; i += 64) s += (double)partial[(size_t)k * n_tiles + i];
+  for (int i = lane; i < n_tiles; i += 64) s += (double)part[i];
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-  if (lane == 0) losses[k] = s * inv_den;
+  return s * inv_den;
 }
 
-// g_j = scale (1/P) sum_p c_pj (L_2p - L_2p+1) and Q = mean L, in binary64 and pair order.
-__global__ void combine_kernel(int P, int d, const double* __restrict__ c,
-                               const double* __restrict__ L, const double* __restrict__ scale,
-                               double* __restrict__ grad, double* __restrict__ loss) {
+// g_j = scale (1/P) sum_p c_pj (L_2p - L_2p+1) and Q = mean L, binary64, pair
+// order (Eq. 10 with antithetic pairs); c rows have stride ld.  Thread j < d.
+__device__ __forceinline__ void combine_one(int P, int d, int ld, const double* __restrict__ c,
+                                            const double* __restrict__ L, double sc,
+                                            double* __restrict__ grad, double* __restrict__ loss) {
   const int j = threadIdx.x;
-  const double sc = scale ? *scale : 1.0;
   if (j < d) {
     double acc = 0.0;
-    for (int p = 0; p < P; ++p) acc += c[(size_t)p * d + j] * (L[2 * p] - L[2 * p + 1]);
+    for (int p = 0; p < P; ++p) acc += c[(size_t)p * ld + j] * (L[2 * p] - L[2 * p + 1]);
     grad[j] = sc * (acc / (double)P);
   }
   if (j == 0 && loss) {
     double s = 0.0;
     for (int k = 0; k < 2 * P; ++k) s += L[k];
     *loss = s / (double)(2 * P);
+  }
+}
+
+// One thread per antithetic pair: tau_p, weights c_p and the two parameter rows.
+__global__ void tau_kernel(int est, int d, int P, uint32_t k0, uint32_t k1,
+                           const float* __restrict__ sigma, const float* __restrict__ theta,
+                           double cd, double sqrt2pi, float* __restrict__ tau,
+                           double* __restrict__ c, float* __restrict__ X) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  draw_pair(est, d, p, k0, k1, sigma, theta, cd, sqrt2pi, d, tau + (size_t)p * d, c + (size_t)p * d,
+            X + (size_t)(2 * p) * d, X + (size_t)(2 * p + 1) * d);
+}
+
+__global__ void loss_kernel(const float* __restrict__ partial, int n_tiles, int N, double inv_den,
+                            double* __restrict__ losses) {
+  const int k = blockIdx.x;
+  const double L = row_loss(partial + (size_t)k * n_tiles, n_tiles, inv_den);
+  if (threadIdx.x == 0) losses[k] = L;
+}
+
+__global__ void combine_kernel(int P, int d, const double* __restrict__ c,
+                               const double* __restrict__ L, const double* __restrict__ scale,
+                               double* __restrict__ grad, double* __restrict__ loss) {
+  combine_one(P, d, d, c, L, scale ? *scale : 1.0, grad, loss);
+}
+
+// ---------------------------------------------------------------------------
+// batched form: many requests (different scenes, sizes, N, d) in one pass.
+// Every per-request result is computed by the same device functions in the same
+// order as the single-request kernels, so it is bit-identical to running the
+// request alone.
+// ---------------------------------------------------------------------------
+// index of the last request whose field (int at byte offset `off`) is <= key
+__device__ __forceinline__ int find_request(const BatchReq* __restrict__ reqs, int n, int key,
+                                            size_t off) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    const int v = *reinterpret_cast<const int32_t*>(reinterpret_cast<const char*>(reqs + mid) + off);
+    if (v <= key) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ void batch_reset_kernel(BatchMeta* meta) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) meta->counter = 0;
+}
+
+__global__ void batch_tau_kernel(const BatchReq* __restrict__ reqs, const BatchMeta* __restrict__ meta,
+                                 float* __restrict__ tau, double* __restrict__ c,
+                                 float* __restrict__ X) {
+  const int total = meta->total_pairs, n = meta->n_req;
+  constexpr int ld = PRDPT_MAX_PARAMS;
+  for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < total; g += gridDim.x * blockDim.x) {
+    const int r = find_request(reqs, n, g, offsetof(BatchReq, pair_base));
+    const BatchReq& q = reqs[r];
+    const int p = g - q.pair_base;
+    draw_pair(q.est, q.d, p, q.k0, q.k1, q.sigma, q.theta, q.cd, q.sqrt2pi, ld,
+              tau + (size_t)g * ld, c + (size_t)g * ld, X + (size_t)(q.row_base + 2 * p) * ld,
+              X + (size_t)(q.row_base + 2 * p + 1) * ld);
+  }
+}
+
+// Persistent render: work-groups take (request, perturbation, run of tiles)
+// items from one counter until the batch is exhausted; each tile writes its own
+// partial slot, so the order in which items are taken does not matter.
+__global__ __launch_bounds__(kBlock, PRDPT_MIN_WAVES_PER_EU) void batch_render_kernel(
+    const BatchReq* __restrict__ reqs, BatchMeta* __restrict__ meta, const float* __restrict__ X,
+    float* __restrict__ partial) {
+  __shared__ SceneHdr S;
+  __shared__ int stack[kStackEntries * kBlock];
+  __shared__ float wsum[kBlock / 64];
+  __shared__ int s_item;
+  const int total = meta->total_items, n = meta->n_req, tpi = meta->tiles_per_item;
+  while (true) {
+    if (threadIdx.x == 0) s_item = atomicAdd(&meta->counter, 1);
+    __syncthreads();
+    const int it = s_item;
+    __syncthreads();
+    if (it >= total) break;
+    const int r = find_request(reqs, n, it, offsetof(BatchReq, item_base));
+    const BatchReq& q = reqs[r];
+    const int local = it - q.item_base;
+    const int k = local / q.items_per_row;
+    const int first = (local % q.items_per_row) * tpi;
+    const int last = min(first + tpi, q.n_tiles);
+    load_state(S, q.scene.hdr, X + (size_t)(q.row_base + k) * PRDPT_MAX_PARAMS, q.d);
+    for (int tile = first; tile < last; ++tile) {
+      render_tile<false>(S, q.scene.nodes, q.scene.tris, k, tile, kTagPath, q.k0, q.k1, q.ref,
+                         nullptr, partial + (size_t)q.partial_base + (size_t)k * q.n_tiles + tile,
+                         nullptr, stack, wsum);
+      __syncthreads();
+    }
+  }
+}
+
+__global__ void batch_loss_kernel(const BatchReq* __restrict__ reqs,
+                                  const BatchMeta* __restrict__ meta,
+                                  const float* __restrict__ partial, double* __restrict__ losses) {
+  const int total = meta->total_rows, n = meta->n_req;
+  for (int g = blockIdx.x; g < total; g += gridDim.x) {
+    const int r = find_request(reqs, n, g, offsetof(BatchReq, row_base));
+    const BatchReq& q = reqs[r];
+    const int k = g - q.row_base;
+    const double L = row_loss(partial + (size_t)q.partial_base + (size_t)k * q.n_tiles, q.n_tiles,
+                              q.inv_den);
+    if (threadIdx.x == 0) losses[g] = L;
+  }
+}
+
+__global__ void batch_combine_kernel(const BatchReq* __restrict__ reqs,
+                                     const BatchMeta* __restrict__ meta,
+                                     const double* __restrict__ c, const double* __restrict__ losses,
+                                     double* __restrict__ grads, double* __restrict__ loss) {
+  for (int r = blockIdx.x; r < meta->n_req; r += gridDim.x) {
+    const BatchReq& q = reqs[r];
+    combine_one(q.N / 2, q.d, PRDPT_MAX_PARAMS, c + (size_t)q.pair_base * PRDPT_MAX_PARAMS,
+                losses + q.row_base, 1.0, grads + (size_t)r * PRDPT_MAX_PARAMS, loss + r);
   }
 }
 
@@ -826,6 +959,22 @@ hipError_t launch_losses(hipStream_t st, const float* partial, int n_tiles, int 
 hipError_t launch_combine(hipStream_t st, int P, int d, const double* c, const double* L,
                           const double* scale, double* grad, double* loss) {
   hipLaunchKernelGGL(combine_kernel, dim3(1), dim3(64), 0, st, P, d, c, L, scale, grad, loss);
+  return hipGetLastError();
+}
+
+// The batch sequence with launch shapes that do not depend on the batch's
+// content (totals are read from the device-side meta), so it can be captured
+// once in a graph and replayed for every batch.
+hipError_t launch_batch(hipStream_t st, const BatchReq* reqs, BatchMeta* meta, int render_blocks,
+                        float* tau, double* c, float* X, float* partial, double* losses,
+                        double* grads, double* loss) {
+  hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, st, meta);
+  hipLaunchKernelGGL(batch_tau_kernel, dim3(64), dim3(64), 0, st, reqs, meta, tau, c, X);
+  hipLaunchKernelGGL(batch_render_kernel, dim3(render_blocks), dim3(kBlock), 0, st, reqs, meta, X,
+                     partial);
+  hipLaunchKernelGGL(batch_loss_kernel, dim3(1024), dim3(64), 0, st, reqs, meta, partial, losses);
+  hipLaunchKernelGGL(batch_combine_kernel, dim3(256), dim3(64), 0, st, reqs, meta, c, losses,
+                     grads, loss);
   return hipGetLastError();
 }
 

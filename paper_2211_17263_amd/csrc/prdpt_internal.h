@@ -64,6 +64,25 @@ struct DevScene {
   const Tri* tris;
 };
 
+// One request of a batch (device table, filled by the host per batch).  Rows
+// of X/tau/c use the fixed stride PRDPT_MAX_PARAMS.
+struct BatchReq {
+  DevScene scene;
+  const float* ref;
+  int32_t W, H, N, d, n_tiles, items_per_row, est, pad0;
+  uint32_t k0, k1;
+  int32_t item_base, pair_base, row_base, partial_base;
+  double cd, sqrt2pi, inv_den;
+  float theta[PRDPT_MAX_PARAMS];
+  float sigma[PRDPT_MAX_PARAMS];
+};
+
+// Batch totals and the work counter of the persistent render kernel.
+struct BatchMeta {
+  int32_t n_req, total_pairs, total_items, total_rows;
+  int32_t tiles_per_item, counter, pad0, pad1;
+};
+
 // Host-side BVH build result for one instance.
 struct BvhOut {
   int root;          // index into the global node array

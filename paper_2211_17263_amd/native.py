@@ -28,7 +28,7 @@ EXPORTS = [
     "prdpt_render_reference", "prdpt_smoothed_loss", "prdpt_grad_estimate",
     "prdpt_grad_estimate_async", "prdpt_combine_async", "prdpt_ctx_set_timing",
     "prdpt_ctx_read_timing", "prdpt_traversal_counts", "prdpt_sigma_schedule", "prdpt_adam_step",
-    "prdpt_copy_probe",
+    "prdpt_copy_probe", "prdpt_batch_estimate", "prdpt_batch_config", "prdpt_batch_autotune",
 ]
 
 
@@ -53,6 +53,13 @@ class SceneDesc(C.Structure):
                 ("n_triangles", C.c_int32), ("triangles", C.c_void_p),
                 ("n_point_lights", C.c_int32), ("point_lights", C.c_void_p),
                 ("n_params", C.c_int32), ("bindings", C.c_void_p)]
+
+
+class Request(C.Structure):
+    _fields_ = [("scene", C.c_void_p), ("ref", C.c_void_p), ("theta", C.c_void_p),
+                ("sigma", C.c_void_p), ("N", C.c_int32), ("est", C.c_int32),
+                ("seed", C.c_uint64), ("grad_out", C.c_void_p), ("loss_out", C.c_void_p),
+                ("losses_out", C.c_void_p), ("status", C.c_int32)]
 
 
 _lib = None
@@ -94,6 +101,11 @@ def load():
     L.prdpt_adam_step.argtypes = [i32, dp, dp, dp, dp, i32, C.c_double, C.c_double, C.c_double,
                                   C.c_double]
     L.prdpt_copy_probe.argtypes = [vp, vp, vp, sz, i32, C.POINTER(C.c_double)]
+    L.prdpt_batch_estimate.argtypes = [vp, C.POINTER(Request), i32]
+    L.prdpt_batch_config.argtypes = [vp, i32, i32, i32]
+    L.prdpt_batch_autotune.argtypes = [vp, C.POINTER(Request), i32, C.c_char_p,
+                                       C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                       C.POINTER(C.c_double)]
     for name in EXPORTS:
         if name != "prdpt_last_error":
             getattr(L, name).restype = C.c_int
@@ -341,3 +353,62 @@ def prdpt_combine_async(ctx, P, d, c, losses, scale, grad):
                                       _dev(losses, torch.float64),
                                       _dev(scale, torch.float64) if scale is not None else None,
                                       _dev(grad, torch.float64)))
+
+
+class BatchRequest:
+    """Host-side holder of one prdpt_request and its output arrays."""
+
+    def __init__(self, scene, ref, theta, sigma, N, seed, est):
+        import torch
+        self.scene, self.N, self.seed, self.est = scene, int(N), int(seed), int(est)
+        self.ref = ref
+        self.theta = np.ascontiguousarray(theta, np.float32)
+        self.sigma = np.ascontiguousarray(sigma, np.float32)
+        self.grad = np.zeros(max(scene.d, 1), np.float64)
+        self.loss = np.zeros(1, np.float64)
+        self.losses = np.zeros(max(self.N, 1), np.float64)
+        self.status = None
+        if not isinstance(ref, torch.Tensor):
+            raise TypeError("ref must be a device tensor")
+
+    def fill(self, r):
+        r.scene = self.scene.h.value if self.scene.h is not None else None
+        r.ref = self.ref.data_ptr()
+        r.theta = self.theta.ctypes.data
+        r.sigma = self.sigma.ctypes.data
+        r.N, r.est, r.seed = self.N, self.est, self.seed
+        r.grad_out = self.grad.ctypes.data
+        r.loss_out = self.loss.ctypes.data
+        r.losses_out = self.losses.ctypes.data
+        r.status = 0
+
+
+def _requests(reqs):
+    arr = (Request * len(reqs))()
+    for r, q in zip(arr, reqs):
+        q.fill(r)
+    return arr
+
+
+def prdpt_batch_estimate(ctx, reqs):
+    """Runs BatchRequest objects as one batch; sets .grad/.loss/.losses/.status."""
+    arr = _requests(reqs)
+    _check(load().prdpt_batch_estimate(ctx.h, arr, len(reqs)))
+    for r, q in zip(arr, reqs):
+        q.status = r.status
+    return reqs
+
+
+def prdpt_batch_config(ctx, blocks_per_cu, tiles_per_item, use_graph=True):
+    _check(load().prdpt_batch_config(ctx.h, int(blocks_per_cu), int(tiles_per_item),
+                                     1 if use_graph else 0))
+
+
+def prdpt_batch_autotune(ctx, reqs, cache_path=None):
+    """(blocks_per_cu, tiles_per_item, ms) chosen for batches like reqs."""
+    arr = _requests(reqs)
+    b, t, ms = C.c_int(), C.c_int(), C.c_double()
+    _check(load().prdpt_batch_autotune(ctx.h, arr, len(reqs),
+                                       cache_path.encode() if cache_path else None,
+                                       C.byref(b), C.byref(t), C.byref(ms)))
+    return b.value, t.value, ms.value

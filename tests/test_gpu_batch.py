@@ -1,0 +1,125 @@
+"""Batched form: one persistent, graph-replayed launch over many uneven requests.
+
+Each request's result must equal the single-request path bit for bit (same
+device functions, same summation order), for graph replays with eager work in
+between, for direct launches, and with invalid requests mixed in.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2211_17263_amd import scenes as S
+from tests import parity as PT
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def setup():
+    import torch
+    from paper_2211_17263_amd import native as NV
+    ctx = NV.Context(0)
+    jobs = S.batch_jobs(seed=44, n_jobs=10, max_side=128, max_tris=20000)
+    scenes, refs = [], []
+    for j in jobs:
+        sc = NV.prdpt_scene_create(ctx, j["scene"])
+        scenes.append(sc)
+        refs.append(NV.prdpt_render_reference(sc, j["theta_ref"], 3))
+    torch.cuda.synchronize()
+    yield ctx, jobs, scenes, refs
+    for sc in scenes:
+        sc.destroy()
+    ctx.close()
+
+
+def _alone(NV, sc, ref, j, seed):
+    return NV.prdpt_grad_estimate(sc, ref, j["theta0"], j["sigma"], j["N"], seed, j["est"])
+
+
+def _batch(NV, ctx, jobs, scenes, refs, idx, seeds):
+    reqs = [NV.BatchRequest(scenes[i], refs[i], jobs[i]["theta0"], jobs[i]["sigma"], jobs[i]["N"],
+                            seeds[i], jobs[i]["est"]) for i in idx]
+    NV.prdpt_batch_estimate(ctx, reqs)
+    return reqs
+
+
+@pytest.mark.parametrize("use_graph", [True, False])
+def test_batch_equals_alone_bitwise(setup, use_graph):
+    import torch
+    from paper_2211_17263_amd import native as NV
+    ctx, jobs, scenes, refs = setup
+    say("batch-vs-alone", "graph" if use_graph else "direct", [j["scene"].width for j in jobs])
+    NV.prdpt_batch_config(ctx, 4, 2, use_graph)
+    rng = np.random.default_rng(0)
+    for rep in range(3):   # graph replays with eager single-request work in between
+        idx = list(range(len(jobs))) if rep == 0 else sorted(rng.choice(len(jobs), 6, replace=False))
+        seeds = {i: 1000 * rep + 17 * i + 1 for i in idx}
+        reqs = _batch(NV, ctx, jobs, scenes, refs, idx, seeds)
+        for i, q in zip(idx, reqs):
+            a = _alone(NV, scenes[i], refs[i], jobs[i], seeds[i])
+            torch.cuda.synchronize()
+            assert q.status == 0
+            d = scenes[i].d
+            assert np.array_equal(q.grad[:d], a["grad"]), (rep, i)
+            assert np.array_equal(q.losses[: jobs[i]["N"]], a["losses"]), (rep, i)
+            assert q.loss[0] == a["loss"]
+
+
+def test_batch_isolates_invalid_requests(setup):
+    from paper_2211_17263_amd import native as NV
+    ctx, jobs, scenes, refs = setup
+    say("batch-invalid")
+    NV.prdpt_batch_config(ctx, 4, 1, True)
+    good = NV.BatchRequest(scenes[0], refs[0], jobs[0]["theta0"], jobs[0]["sigma"], jobs[0]["N"], 5,
+                           jobs[0]["est"])
+    odd = NV.BatchRequest(scenes[1], refs[1], jobs[1]["theta0"], jobs[1]["sigma"], 3, 5, jobs[1]["est"])
+    bad_sigma = NV.BatchRequest(scenes[2], refs[2], jobs[2]["theta0"], np.zeros_like(jobs[2]["sigma"]),
+                                jobs[2]["N"], 5, jobs[2]["est"])
+    bad_est = NV.BatchRequest(scenes[3], refs[3], jobs[3]["theta0"], jobs[3]["sigma"], jobs[3]["N"], 5, 9)
+    NV.prdpt_batch_estimate(ctx, [odd, good, bad_sigma, bad_est])
+    assert [r.status for r in (odd, good, bad_sigma, bad_est)] == [NV.PRDPT_E_ARG, 0, NV.PRDPT_E_ARG,
+                                                                  NV.PRDPT_E_ARG]
+    a = _alone(NV, scenes[0], refs[0], jobs[0], 5)
+    assert np.array_equal(good.grad[: scenes[0].d], a["grad"])
+
+
+def test_batch_against_oracle(setup):
+    import torch
+    from paper_2211_17263_amd import native as NV
+    ctx, jobs, scenes, refs = setup
+    i = min(range(len(jobs)), key=lambda t: jobs[t]["scene"].width * jobs[t]["scene"].spp)
+    j = jobs[i]
+    say("batch-oracle", j["scene"].width, j["scene"].spp, j["N"])
+    osc = O.OracleScene(j["scene"])
+    ref = osc.reference(j["theta_ref"], seed=8)
+    ref_d = torch.from_numpy(ref).cuda()
+    q = NV.BatchRequest(scenes[i], ref_d, j["theta0"], j["sigma"], j["N"], 77, j["est"])
+    NV.prdpt_batch_estimate(ctx, [q])
+    o = osc.grad_estimate(ref, j["theta0"], j["sigma"], j["N"], 77, j["est"])
+    _, c = O.draw_tau(j["est"], j["sigma"], j["N"] // 2, 77)
+    PT.assert_losses_match(q.losses[: j["N"]], o["losses"], "batch")
+    PT.assert_grad_match(q.grad[: scenes[i].d], o["grad"], c, o["losses"], "batch")
+
+
+def test_autotune_writes_and_reads_cache(setup, tmp_path):
+    from paper_2211_17263_amd import native as NV
+    ctx, jobs, scenes, refs = setup
+    say("autotune")
+    reqs = [NV.BatchRequest(scenes[i], refs[i], jobs[i]["theta0"], jobs[i]["sigma"], jobs[i]["N"], 9,
+                            jobs[i]["est"]) for i in range(len(jobs))]
+    cache = str(tmp_path / "tune.jsonl")
+    b, t, ms = NV.prdpt_batch_autotune(ctx, reqs, cache)
+    assert b >= 1 and t >= 1 and ms > 0
+    assert os.path.exists(cache) and '"blocks_per_cu": %d' % b in open(cache).read()
+    b2, t2, ms2 = NV.prdpt_batch_autotune(ctx, reqs, cache)
+    assert (b2, t2) == (b, t) and ms2 == pytest.approx(ms, rel=1e-6)
+    NV.prdpt_batch_estimate(ctx, reqs)
+    assert all(r.status == 0 for r in reqs)
