@@ -75,7 +75,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="cornell", choices=["cornell", "toy", "caustic"])
+    ap.add_argument("--workload", default="cornell",
+                    choices=["cornell", "toy", "caustic", "batch", "serve"])
+    ap.add_argument("--serve-seconds", type=float, default=20.0,
+                    help="serve workload: length of each arrival phase")
+    ap.add_argument("--serve-rate", type=float, default=200.0,
+                    help="serve workload: offered Poisson arrival rate (requests/s)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline leg")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="CPU-oracle baseline: run whole estimates until this much time passed")
@@ -97,6 +102,11 @@ def main():
         print(json.dumps({"copy_probe_GBps": copy_rate(ctx, NV, 1 << 30, 20), "bytes": 1 << 30}))
         ctx.close()
         return
+
+    if args.workload == "batch":
+        return bench_batch(args, NV)
+    if args.workload == "serve":
+        return bench_serve(args, NV)
 
     pr, desc, sigma0, sigma_end = workload(args.workload)
     scene = pr["scene"]
@@ -201,6 +211,170 @@ def main():
 
     sc.destroy()
     ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+def tune_cache_path():
+    d = os.path.join(ROOT, "gpurun_out")
+    return os.path.join(d if os.path.isdir(d) else "/tmp", "prdpt_autotune.jsonl")
+
+
+def bench_batch(args, NV):
+    """64 uneven jobs (sides 64..512, 1k..200k triangles, d 2..12, N 4..32): the
+    batched persistent graph launch against the plain per-request loop."""
+    import torch
+    from paper_2211_17263_amd import scenes as S
+    jobs = S.batch_jobs(seed=4)
+    ctx = NV.Context(0)
+    t0 = time.perf_counter()
+    scs = [NV.prdpt_scene_create(ctx, j["scene"]) for j in jobs]
+    t_build = time.perf_counter() - t0
+    refs = [NV.prdpt_render_reference(sc, j["theta_ref"], args.seed + 3) for sc, j in zip(scs, jobs)]
+    torch.cuda.synchronize()
+    log(f"batch: {len(jobs)} scenes built in {t_build:.1f} s, "
+        f"{sum(j['scene'].n_tris for j in jobs)} triangles")
+    reqs = [NV.BatchRequest(sc, r, j["theta0"], j["sigma"], j["N"], j["seed"], j["est"])
+            for sc, r, j in zip(scs, refs, jobs)]
+    bpc, tpi, tune_ms = NV.prdpt_batch_autotune(ctx, reqs, tune_cache_path())
+    log(f"autotuned: {bpc} work-groups per CU, {tpi} tiles per item ({tune_ms:.1f} ms)")
+    K = max(1, args.steps // 4)
+    for _ in range(args.warmup):
+        NV.prdpt_batch_estimate(ctx, reqs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(K):
+        NV.prdpt_batch_estimate(ctx, reqs)
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / K
+    assert all(r.status == 0 for r in reqs)
+    for sc, r, j in zip(scs, refs, jobs):       # warm the plain path
+        NV.prdpt_grad_estimate(sc, r, j["theta0"], j["sigma"], j["N"], j["seed"], j["est"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(K):
+        for sc, r, j in zip(scs, refs, jobs):
+            NV.prdpt_grad_estimate(sc, r, j["theta0"], j["sigma"], j["N"], j["seed"], j["est"])
+    torch.cuda.synchronize()
+    t_plain = (time.perf_counter() - t0) / K
+    same = all(np.array_equal(q.grad[:sc.d], NV.prdpt_grad_estimate(
+        sc, r, j["theta0"], j["sigma"], j["N"], j["seed"], j["est"])["grad"])
+        for q, sc, r, j in zip(reqs, scs, refs, jobs))
+    paths = sum(j["N"] * j["scene"].width * j["scene"].height * j["scene"].spp for j in jobs)
+    out = {"metric": "gradient estimates/sec and paths/sec at 1e-4 rel. error; p50/p99 request latency",
+           "value": len(jobs) / t_batch, "unit": "gradient estimates/s", "n_gpus": 1, "steps": K,
+           "warmup": args.warmup, "ms_per_step": 1e3 * t_batch, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "batch", "jobs": len(jobs), "paths_per_batch": paths,
+                      "blocks_per_cu": bpc, "tiles_per_item": tpi, "graph": True},
+           "paths_per_s": paths / t_batch,
+           "plain_per_request": {"value": len(jobs) / t_plain, "ms_per_batch_of_requests": 1e3 * t_plain},
+           "speedup_vs_plain": t_plain / t_batch, "bitwise_equal_to_plain": bool(same),
+           "scene_build_s": t_build}
+    for sc in scs:
+        sc.destroy()
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+def serve_phase(NV, ctx, jobs, refs, rate, seconds, max_batch, max_inflight, budget, seed):
+    """Open-loop Poisson arrivals at `rate` for `seconds`; returns completion stats.
+    Requests still queued at the end are cancelled and reported as not completed."""
+    rng = np.random.default_rng(seed)
+    sv = NV.Server(ctx, hbm_budget=budget, max_batch=max_batch, max_inflight=max_inflight)
+    t_add = time.perf_counter()
+    ids = [sv.add_job(j["scene"], r) for j, r in zip(jobs, refs)]
+    log(f"serve phase rate={rate:.1f}: {len(ids)} jobs registered in {time.perf_counter() - t_add:.1f} s")
+    # warm: every job once (admission, graph capture)
+    warm = [sv.submit(ids[i], jobs[i]["theta0"], jobs[i]["sigma"], jobs[i]["N"], 1, jobs[i]["est"])
+            for i in range(0, len(jobs), max(1, len(jobs) // 16))]
+    got = 0
+    while got < len(warm):
+        got += len(sv.poll(timeout_ms=200))
+    done, submitted = [], {}
+    t0 = time.perf_counter()
+    t_next = t0
+    while True:
+        now = time.perf_counter()
+        if now - t0 >= seconds:
+            break
+        while t_next <= now:
+            k = int(rng.integers(len(jobs)))
+            j = jobs[k]
+            th = (j["theta0"] + rng.normal(0, 0.02, j["scene"].d)).astype(np.float32)
+            tk = sv.submit(ids[k], th, j["sigma"], j["N"], int(rng.integers(1, 2**62)), j["est"])
+            submitted[tk] = now
+            t_next += rng.exponential(1.0 / rate)
+        done += sv.poll(timeout_ms=1)
+    left = set(submitted) - {c["ticket"] for c in done}
+    for tk in left:
+        sv.cancel(tk)
+    drain_t = time.perf_counter()
+    while len(done) < len(submitted) and time.perf_counter() - drain_t < 60:
+        done += sv.poll(timeout_ms=100)
+    st = sv.stats()
+    sv.stop()
+    ok = [c for c in done if c["status"] == 0 and c["ticket"] in submitted]
+    lat = np.array([c["t_done"] - c["t_submit"] for c in ok])
+    # the arrival window on the server's clock: first to last submission
+    w0 = min(c["t_submit"] for c in done if c["ticket"] in submitted) if done else 0.0
+    w1 = max(c["t_submit"] for c in done if c["ticket"] in submitted) if done else 0.0
+    span = max(w1 - w0, 1e-9)
+    window_done = [c for c in ok if w0 <= c["t_done"] <= w1]
+    paths = sum(jobs[c["job"]]["N"] * jobs[c["job"]]["scene"].width * jobs[c["job"]]["scene"].height
+                * jobs[c["job"]]["scene"].spp for c in window_done)
+    return {"offered_rate": rate, "seconds": span, "submitted": len(submitted),
+            "completed_in_window": len(window_done), "completed_total": len(ok),
+            "cancelled_at_end": len(left), "throughput_req_s": len(window_done) / span,
+            "paths_per_s": paths / span,
+            "latency_p50_s": float(np.percentile(lat, 50)) if lat.size else None,
+            "latency_p99_s": float(np.percentile(lat, 99)) if lat.size else None,
+            "epochs": st["epochs"], "admissions": st["admissions"], "evictions": st["evictions"]}
+
+
+def bench_serve(args, NV):
+    """256 jobs drawn like the batched workload; Poisson arrivals; the continuous-
+    batching server against the plain per-request estimator (FIFO, one request at
+    a time), at the offered rate and at a sustainable rate."""
+    import torch
+    from paper_2211_17263_amd import scenes as S
+    jobs = S.batch_jobs(seed=5, n_jobs=256)
+    ctx = NV.Context(0)
+    refs = []
+    t0 = time.perf_counter()
+    for i, j in enumerate(jobs):
+        sc = NV.prdpt_scene_create(ctx, j["scene"])
+        refs.append(NV.prdpt_render_reference(sc, j["theta_ref"], args.seed + 3).cpu().numpy())
+        sc.destroy()
+        if i % 32 == 31:
+            log(f"serve: {i + 1} references rendered")
+    log(f"serve: {len(jobs)} references rendered in {time.perf_counter() - t0:.1f} s")
+    budget = 512 << 20          # below the 256 jobs' total footprint: admission binds
+    res = {}
+    res["served"] = serve_phase(NV, ctx, jobs, refs, args.serve_rate, args.serve_seconds, 64, 2,
+                                budget, 11)
+    log("served at offered rate:", res["served"])
+    res["plain"] = serve_phase(NV, ctx, jobs, refs, args.serve_rate, args.serve_seconds, 1, 1,
+                               budget, 11)
+    log("plain at offered rate:", res["plain"])
+    sustain = 0.7 * res["served"]["throughput_req_s"]
+    res["served_sustainable"] = serve_phase(NV, ctx, jobs, refs, sustain, args.serve_seconds, 64, 2,
+                                            budget, 12)
+    log("served at 70% of its throughput:", res["served_sustainable"])
+    sustain_plain = 0.7 * res["plain"]["throughput_req_s"]
+    res["plain_sustainable"] = serve_phase(NV, ctx, jobs, refs, sustain_plain, args.serve_seconds, 1,
+                                           1, budget, 12)
+    log("plain at 70% of its throughput:", res["plain_sustainable"])
+    ctx.close()
+    s = res["served"]
+    out = {"metric": "gradient estimates/sec and paths/sec at 1e-4 rel. error; p50/p99 request latency",
+           "value": s["throughput_req_s"], "unit": "gradient estimates/s", "n_gpus": 1,
+           "steps": s["completed_in_window"], "warmup": 0, "ms_per_step": 1e3 / max(s["throughput_req_s"], 1e-9),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": "serve", "jobs": len(jobs), "offered_rate": args.serve_rate,
+                      "hbm_budget": budget, "max_batch": 64, "epochs_in_flight": 2},
+           "latency_s": {"p50": s["latency_p50_s"], "p99": s["latency_p99_s"]},
+           "phases": res}
     print(json.dumps(out), flush=True)
 
 

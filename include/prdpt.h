@@ -268,6 +268,57 @@ int prdpt_batch_config(prdpt_ctx* ctx, int blocks_per_cu, int tiles_per_item, in
 int prdpt_batch_autotune(prdpt_ctx* ctx, prdpt_request* reqs, int n, const char* cache_path,
                          int* best_blocks_per_cu, int* best_tiles_per_item, double* best_ms);
 
+/*
+ * ---- serving ------------------------------------------------------------------
+ * A request loop for many concurrent inverse-rendering jobs.  Jobs register a
+ * scene description and a reference image; their BVHs are built on the host
+ * once and kept there.  A server thread forms batch epochs (prdpt_batch_*
+ * semantics) from the FIFO of pending requests: a request joins an epoch if its
+ * job is resident in HBM or can be admitted within hbm_budget (idle jobs are
+ * evicted least recently used first), otherwise it waits for a later epoch.  Up
+ * to two epochs run at once on separate streams: requests that arrive while an
+ * epoch runs are admitted as slots and memory free up, and overlap it on the
+ * device.  Each result equals the request run alone.
+ */
+typedef struct prdpt_server prdpt_server;
+
+typedef struct {
+  size_t hbm_budget;     /* bytes of resident scenes + references (0 = unbounded) */
+  int32_t max_batch;     /* requests per epoch (<= 0: 64) */
+  int32_t max_inflight;  /* epochs running at once, 1 or 2 (<= 0: 2) */
+} prdpt_server_config;
+
+typedef struct {
+  int64_t ticket;                 /* from prdpt_server_submit */
+  int32_t job;
+  int32_t status;                 /* PRDPT_OK, PRDPT_E_CANCELLED, PRDPT_E_ADMISSION, ... */
+  double loss;                    /* Q estimate (mean per-image loss) */
+  double grad[PRDPT_MAX_PARAMS];  /* first d entries valid */
+  double t_submit, t_start, t_done;  /* seconds on the server's steady clock */
+} prdpt_completion;
+
+typedef struct {
+  int64_t submitted, completed, failed, epochs, admissions, evictions, pending, resident_bytes;
+  double paths;                   /* camera paths of completed requests */
+} prdpt_server_stats;
+
+/* Start the server thread on ctx (which must outlive the server). */
+int prdpt_server_start(prdpt_ctx* ctx, const prdpt_server_config* cfg, prdpt_server** out);
+/* Register a job: the description is validated and its BVHs built now (host);
+ * ref_host is host float[H][W][3], copied.  *job_id receives the job's id. */
+int prdpt_server_add_job(prdpt_server* sv, const prdpt_scene_desc* desc, const float* ref_host,
+                         int* job_id);
+/* Queue one gradient estimate of job `job_id` (theta, sigma: host float[d], copied). */
+int prdpt_server_submit(prdpt_server* sv, int job_id, const float* theta, const float* sigma, int N,
+                        uint64_t seed, int est, int64_t* ticket);
+/* Cancel a queued request (it completes with PRDPT_E_CANCELLED unless already running). */
+int prdpt_server_cancel(prdpt_server* sv, int64_t ticket);
+/* Take up to max completion records, waiting up to timeout_ms for the first. */
+int prdpt_server_poll(prdpt_server* sv, prdpt_completion* out, int max, int timeout_ms, int* n_out);
+int prdpt_server_get_stats(prdpt_server* sv, prdpt_server_stats* stats);
+/* Finish all queued and running requests, then release everything. */
+int prdpt_server_stop(prdpt_server* sv);
+
 /* Wait for all work enqueued on the context's stream. */
 int prdpt_ctx_synchronize(prdpt_ctx* ctx);
 

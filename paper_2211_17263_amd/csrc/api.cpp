@@ -202,10 +202,11 @@ int prdpt_ctx_synchronize(prdpt_ctx* ctx) {
   return PRDPT_OK;
 }
 
-int prdpt_scene_create(prdpt_ctx* ctx, const prdpt_scene_desc* D, prdpt_scene** out,
-                       size_t* footprint_bytes) {
-  if (!ctx || !D || !out) return fail(PRDPT_E_ARG, "null argument");
-  *out = nullptr;
+}  // extern "C"
+
+// Validate a scene description, build its header and BVHs on the host.
+int prdpt::build_host_scene(const prdpt_scene_desc* D, HostScene& hs) {
+  if (!D) return fail(PRDPT_E_ARG, "null argument");
   // ---- validation ----
   if (D->width < 1 || D->height < 1 || D->width > PRDPT_MAX_SIDE || D->height > PRDPT_MAX_SIDE)
     return fail(PRDPT_E_SCENE, "image size out of range");
@@ -249,9 +250,8 @@ int prdpt_scene_create(prdpt_ctx* ctx, const prdpt_scene_desc* D, prdpt_scene** 
     return fail(PRDPT_E_SCENE, "triangles without meshes");
   }
   // ---- header ----
-  prdpt_scene* s = new prdpt_scene();
-  s->ctx = ctx;
-  SceneHdr& h = s->hdr;
+  hs = HostScene{};
+  SceneHdr& h = hs.hdr;
   std::memcpy(h.eye, D->eye, 12);
   std::memcpy(h.fwd, D->fwd, 12);
   std::memcpy(h.right, D->right, 12);
@@ -267,7 +267,6 @@ int prdpt_scene_create(prdpt_ctx* ctx, const prdpt_scene_desc* D, prdpt_scene** 
     for (int c = 0; c < 3; ++c) h.mat_rgb[i][c] = D->mat_rgb[3 * i + c];
     h.mat_ior[i] = D->mat_ior[i];
     if (h.mat_type[i] == PRDPT_MAT_DIELECTRIC && !(h.mat_ior[i] > 0.0f)) {
-      delete s;
       return fail(PRDPT_E_SCENE, "dielectric ior must be > 0");
     }
   }
@@ -292,12 +291,10 @@ int prdpt_scene_create(prdpt_ctx* ctx, const prdpt_scene_desc* D, prdpt_scene** 
     const int lim = kind == PRDPT_BIND_SPHERE ? D->n_spheres : kind == PRDPT_BIND_QUAD ? D->n_quads
                     : kind == PRDPT_BIND_MESH ? D->n_meshes : kind == PRDPT_BIND_PLIGHT ? D->n_point_lights : -1;
     if (lim < 0 || idx < 0 || idx >= lim || comp < 0 || comp > 2) {
-      delete s;
       return fail(PRDPT_E_SCENE, "bad parameter binding");
     }
     for (int i = 0; i < j; ++i)
       if (D->bindings[3 * i] == kind && D->bindings[3 * i + 1] == idx && D->bindings[3 * i + 2] == comp) {
-        delete s;
         return fail(PRDPT_E_SCENE, "a field is bound twice");
       }
     if (kind == PRDPT_BIND_MESH) bound[idx] = 1;
@@ -315,7 +312,6 @@ int prdpt_scene_create(prdpt_ctx* ctx, const prdpt_scene_desc* D, prdpt_scene** 
     }
   }
   if (n_inst > PRDPT_MAX_INSTANCES) {
-    delete s;
     return fail(PRDPT_E_SCENE, "too many mesh instances");
   }
   h.n_inst = n_inst;
@@ -334,30 +330,40 @@ int prdpt_scene_create(prdpt_ctx* ctx, const prdpt_scene_desc* D, prdpt_scene** 
     }
     for (int c = 0; c < 3; ++c) h.inst_xlate[mesh_inst[m]][c] = D->mesh_translation[3 * m + c];
   }
-  std::vector<Node> nodes;
-  std::vector<Tri> tris;
+  std::vector<Node>& nodes = hs.nodes;
+  std::vector<Tri>& tris = hs.tris;
   tris.reserve(D->n_triangles);
   for (int i = 0; i < n_inst; ++i) {
     BvhOut b = build_bvh(D->triangles, tri_mat.data(), lists[i].data(), (int)lists[i].size(),
                          h.tri_id_base, nodes, tris);
     if (b.root == -2) {
-      delete s;
       return fail(PRDPT_E_SCENE, "mesh instance too large for the BVH depth bound");
     }
     h.inst_root[i] = b.root;
-    s->bvh_depth = std::max(s->bvh_depth, b.depth);
+    hs.bvh_depth = std::max(hs.bvh_depth, b.depth);
   }
   if (nodes.size() >= (1u << 24)) {
-    delete s;
     return fail(PRDPT_E_SCENE, "too many BVH nodes (at most 2^24)");
   }
-  if (s->bvh_depth > kMaxInnerDepth) {
-    delete s;
+  if (hs.bvh_depth > kMaxInnerDepth) {
     return fail(PRDPT_E_SCENE, "BVH deeper than the traversal stack");
   }
-  s->n_nodes = (int)nodes.size();
-  s->n_tris = (int)tris.size();
-  s->footprint = sizeof(SceneHdr) + nodes.size() * sizeof(Node) + tris.size() * sizeof(Tri);
+  hs.footprint = sizeof(SceneHdr) + nodes.size() * sizeof(Node) + tris.size() * sizeof(Tri);
+  return PRDPT_OK;
+}
+
+// Admit (context HBM budget) and upload a host-built scene.
+int prdpt::upload_scene(prdpt_ctx* ctx, const HostScene& hs, prdpt_scene** out) {
+  prdpt_scene* s = new prdpt_scene();
+  s->ctx = ctx;
+  s->hdr = hs.hdr;
+  s->bvh_depth = hs.bvh_depth;
+  s->n_nodes = (int)hs.nodes.size();
+  s->n_tris = (int)hs.tris.size();
+  s->footprint = hs.footprint;
+  const SceneHdr& h = hs.hdr;
+  const std::vector<Node>& nodes = hs.nodes;
+  const std::vector<Tri>& tris = hs.tris;
   // ---- admission and upload ----
   std::lock_guard<std::mutex> g(ctx->mu);
   if (ctx->budget && ctx->resident + s->footprint > ctx->budget) {
@@ -391,8 +397,20 @@ int prdpt_scene_create(prdpt_ctx* ctx, const prdpt_scene_desc* D, prdpt_scene** 
   }
   ctx->resident += s->footprint;
   ctx->n_scenes++;
-  if (footprint_bytes) *footprint_bytes = s->footprint;
   *out = s;
+  return PRDPT_OK;
+}
+
+extern "C" {
+
+int prdpt_scene_create(prdpt_ctx* ctx, const prdpt_scene_desc* D, prdpt_scene** out,
+                       size_t* footprint_bytes) {
+  if (!ctx || !D || !out) return fail(PRDPT_E_ARG, "null argument");
+  *out = nullptr;
+  HostScene hs;
+  if (int rc = build_host_scene(D, hs)) return rc;
+  if (int rc = upload_scene(ctx, hs, out)) return rc;
+  if (footprint_bytes) *footprint_bytes = (*out)->footprint;
   return PRDPT_OK;
 }
 

@@ -60,8 +60,12 @@ int grow_host(T*& p, size_t n) {
   return PRDPT_OK;
 }
 
-int ensure_batch(prdpt_ctx* ctx, size_t n_req, size_t pairs, size_t rows, size_t partial) {
-  BatchState& b = ctx->batch;
+}  // namespace
+
+// Create the batch stream on first use and grow device/pinned buffers to the
+// given capacities (a capacity change invalidates the captured graph).
+int ensure_batch(prdpt_ctx* ctx, BatchState& b, size_t n_req, size_t pairs, size_t rows,
+                 size_t partial) {
   if (!b.stream) {
     HIP_TRY(hipStreamCreateWithFlags(&b.stream, hipStreamNonBlocking));
     HIP_TRY(hipEventCreateWithFlags(&b.ready, hipEventDisableTiming));
@@ -115,6 +119,8 @@ int ensure_batch(prdpt_ctx* ctx, size_t n_req, size_t pairs, size_t rows, size_t
   return PRDPT_OK;
 }
 
+namespace {
+
 int check_one(prdpt_ctx* ctx, const prdpt_request& r) {
   const prdpt_scene* s = r.scene;
   if (!s || s->ctx != ctx) return PRDPT_E_ARG;
@@ -128,17 +134,22 @@ int check_one(prdpt_ctx* ctx, const prdpt_request& r) {
   return PRDPT_OK;
 }
 
-int launch_sequence(prdpt_ctx* ctx, int render_blocks) {
-  BatchState& b = ctx->batch;
+int launch_sequence(BatchState& b, int render_blocks) {
   HIP_TRY(launch_batch(b.stream, b.d_reqs, b.d_meta, render_blocks, b.d_tau, b.d_c, b.d_X,
                        b.d_partial, b.d_losses, b.d_grads, b.d_loss));
   return PRDPT_OK;
 }
 
-// Runs the valid requests of `reqs`; per-request status in reqs[i].status.
-int run_batch(prdpt_ctx* ctx, prdpt_request* reqs, int n, double* device_ms) {
-  BatchState& b = ctx->batch;
-  std::vector<int> ok;
+}  // namespace
+
+// Enqueue the valid requests of `reqs` as one batch on b's stream (tables,
+// graph replay or direct launches, asynchronous copies of the results into
+// pinned memory).  Per-request status in reqs[i].status; `ok` receives the
+// indices of the requests that run, in table order.  If `t0`/`t1` are given,
+// events bracket the device work.
+int batch_enqueue(prdpt_ctx* ctx, BatchState& b, prdpt_request* reqs, int n, std::vector<int>& ok,
+                  hipEvent_t t0, hipEvent_t t1) {
+  ok.clear();
   for (int i = 0; i < n; ++i) {
     reqs[i].status = check_one(ctx, reqs[i]);
     if (reqs[i].status == PRDPT_OK) ok.push_back(i);
@@ -161,7 +172,7 @@ int run_batch(prdpt_ctx* ctx, prdpt_request* reqs, int n, double* device_ms) {
     items += (size_t)reqs[i].N * ((nt + tpi - 1) / tpi);
   }
   if (items >= (1u << 31) || partial >= (1u << 31)) return fail(PRDPT_E_ARG, "batch too large");
-  if (int rc = ensure_batch(ctx, ok.size(), pairs, rows, partial)) return rc;
+  if (int rc = ensure_batch(ctx, b, ok.size(), pairs, rows, partial)) return rc;
   // request table
   int item_base = 0, pair_base = 0, row_base = 0, partial_base = 0;
   for (size_t q = 0; q < ok.size(); ++q) {
@@ -209,12 +220,7 @@ int run_batch(prdpt_ctx* ctx, prdpt_request* reqs, int n, double* device_ms) {
   HIP_TRY(hipStreamWaitEvent(b.stream, b.ready, 0));
   HIP_TRY(hipMemcpyAsync(b.d_reqs, b.h_reqs, sizeof(BatchReq) * ok.size(), hipMemcpyHostToDevice, b.stream));
   HIP_TRY(hipMemcpyAsync(b.d_meta, b.h_meta, sizeof(BatchMeta), hipMemcpyHostToDevice, b.stream));
-  hipEvent_t t0 = nullptr, t1 = nullptr;
-  if (device_ms) {
-    HIP_TRY(hipEventCreate(&t0));
-    HIP_TRY(hipEventCreate(&t1));
-    HIP_TRY(hipEventRecord(t0, b.stream));
-  }
+  if (t0) HIP_TRY(hipEventRecord(t0, b.stream));
   if (b.use_graph) {
     if (b.exec && b.graph_blocks != render_blocks) {
       HIP_TRY(hipGraphExecDestroy(b.exec));
@@ -223,7 +229,7 @@ int run_batch(prdpt_ctx* ctx, prdpt_request* reqs, int n, double* device_ms) {
     if (!b.exec) {
       hipGraph_t g = nullptr;
       HIP_TRY(hipStreamBeginCapture(b.stream, hipStreamCaptureModeThreadLocal));
-      const int rc = launch_sequence(ctx, render_blocks);
+      const int rc = launch_sequence(b, render_blocks);
       hipError_t e = hipStreamEndCapture(b.stream, &g);
       if (rc) return rc;
       if (e != hipSuccess) return fail(PRDPT_E_HIP, std::string("graph capture: ") + hipGetErrorString(e));
@@ -237,21 +243,18 @@ int run_batch(prdpt_ctx* ctx, prdpt_request* reqs, int n, double* device_ms) {
     }
     HIP_TRY(hipGraphLaunch(b.exec, b.stream));
   } else {
-    if (int rc = launch_sequence(ctx, render_blocks)) return rc;
+    if (int rc = launch_sequence(b, render_blocks)) return rc;
   }
-  if (device_ms) HIP_TRY(hipEventRecord(t1, b.stream));
+  if (t1) HIP_TRY(hipEventRecord(t1, b.stream));
   HIP_TRY(hipMemcpyAsync(b.h_grads, b.d_grads, sizeof(double) * PRDPT_MAX_PARAMS * ok.size(),
                          hipMemcpyDeviceToHost, b.stream));
   HIP_TRY(hipMemcpyAsync(b.h_loss, b.d_loss, sizeof(double) * ok.size(), hipMemcpyDeviceToHost, b.stream));
   HIP_TRY(hipMemcpyAsync(b.h_losses, b.d_losses, sizeof(double) * rows, hipMemcpyDeviceToHost, b.stream));
-  HIP_TRY(hipStreamSynchronize(b.stream));
-  if (device_ms) {
-    float ms = 0.0f;
-    HIP_TRY(hipEventElapsedTime(&ms, t0, t1));
-    *device_ms = ms;
-    hipEventDestroy(t0);
-    hipEventDestroy(t1);
-  }
+  return PRDPT_OK;
+}
+
+// Scatter the results of a finished batch (b's stream complete) to the requests.
+void batch_collect(BatchState& b, prdpt_request* reqs, const std::vector<int>& ok) {
   for (size_t q = 0; q < ok.size(); ++q) {
     prdpt_request& r = reqs[ok[q]];
     const BatchReq& t = b.h_reqs[q];
@@ -259,7 +262,33 @@ int run_batch(prdpt_ctx* ctx, prdpt_request* reqs, int n, double* device_ms) {
     if (r.loss_out) *r.loss_out = b.h_loss[q];
     if (r.losses_out) std::memcpy(r.losses_out, b.h_losses + t.row_base, sizeof(double) * r.N);
   }
-  return PRDPT_OK;
+}
+
+namespace {
+
+// Runs the valid requests of `reqs` on the context's batch state, synchronously.
+int run_batch(prdpt_ctx* ctx, prdpt_request* reqs, int n, double* device_ms) {
+  BatchState& b = ctx->batch;
+  if (int rc = ensure_batch(ctx, b, 1, 1, 1, 1)) return rc;
+  std::vector<int> ok;
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  if (device_ms) {
+    HIP_TRY(hipEventCreate(&t0));
+    HIP_TRY(hipEventCreate(&t1));
+  }
+  int rc = batch_enqueue(ctx, b, reqs, n, ok, t0, t1);
+  if (rc == PRDPT_OK && !ok.empty()) {
+    hipError_t e = hipStreamSynchronize(b.stream);
+    if (e != hipSuccess) rc = fail(PRDPT_E_HIP, std::string("batch: ") + hipGetErrorString(e));
+  }
+  if (rc == PRDPT_OK && device_ms) {
+    float ms = 0.0f;
+    if (!ok.empty() && hipEventElapsedTime(&ms, t0, t1) == hipSuccess) *device_ms = ms;
+  }
+  if (t0) hipEventDestroy(t0);
+  if (t1) hipEventDestroy(t1);
+  if (rc == PRDPT_OK) batch_collect(b, reqs, ok);
+  return rc;
 }
 
 // size class of a batch for the autotuner cache: CU count, log2 of the camera
@@ -360,7 +389,7 @@ int prdpt_batch_autotune(prdpt_ctx* ctx, prdpt_request* reqs, int n, const char*
   std::lock_guard<std::mutex> g(ctx->mu);
   HIP_TRY(hipSetDevice(ctx->device));
   BatchState& b = ctx->batch;
-  if (int rc = ensure_batch(ctx, 1, 1, 1, 1)) return rc;
+  if (int rc = ensure_batch(ctx, b, 1, 1, 1, 1)) return rc;
   const std::string key = size_key(ctx, reqs, n);
   int bpc = 0, tpi = 0;
   double ms = 0.0;

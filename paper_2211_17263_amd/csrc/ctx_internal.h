@@ -71,6 +71,27 @@ struct BatchState {
 };
 
 void batch_release(BatchState& b);
+
+// A scene validated and built on the host (header, BVH nodes, triangles).
+struct HostScene {
+  SceneHdr hdr{};
+  std::vector<Node> nodes;
+  std::vector<Tri> tris;
+  int bvh_depth = 0;
+  size_t footprint = 0;
+};
+}  // namespace prdpt
+
+struct prdpt_ctx;
+struct prdpt_scene;
+namespace prdpt {
+int build_host_scene(const prdpt_scene_desc* D, HostScene& hs);
+int upload_scene(prdpt_ctx* ctx, const HostScene& hs, prdpt_scene** out);
+int ensure_batch(prdpt_ctx* ctx, BatchState& b, size_t n_req, size_t pairs, size_t rows,
+                 size_t partial);
+int batch_enqueue(prdpt_ctx* ctx, BatchState& b, prdpt_request* reqs, int n, std::vector<int>& ok,
+                  hipEvent_t t0, hipEvent_t t1);
+void batch_collect(BatchState& b, prdpt_request* reqs, const std::vector<int>& ok);
 }  // namespace prdpt
 
 struct prdpt_ctx {

@@ -29,6 +29,8 @@ EXPORTS = [
     "prdpt_grad_estimate_async", "prdpt_combine_async", "prdpt_ctx_set_timing",
     "prdpt_ctx_read_timing", "prdpt_traversal_counts", "prdpt_sigma_schedule", "prdpt_adam_step",
     "prdpt_copy_probe", "prdpt_batch_estimate", "prdpt_batch_config", "prdpt_batch_autotune",
+    "prdpt_server_start", "prdpt_server_add_job", "prdpt_server_submit", "prdpt_server_cancel",
+    "prdpt_server_poll", "prdpt_server_get_stats", "prdpt_server_stop",
 ]
 
 
@@ -60,6 +62,22 @@ class Request(C.Structure):
                 ("sigma", C.c_void_p), ("N", C.c_int32), ("est", C.c_int32),
                 ("seed", C.c_uint64), ("grad_out", C.c_void_p), ("loss_out", C.c_void_p),
                 ("losses_out", C.c_void_p), ("status", C.c_int32)]
+
+
+class ServerConfig(C.Structure):
+    _fields_ = [("hbm_budget", C.c_size_t), ("max_batch", C.c_int32), ("max_inflight", C.c_int32)]
+
+
+class Completion(C.Structure):
+    _fields_ = [("ticket", C.c_int64), ("job", C.c_int32), ("status", C.c_int32),
+                ("loss", C.c_double), ("grad", C.c_double * 32), ("t_submit", C.c_double),
+                ("t_start", C.c_double), ("t_done", C.c_double)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [(n, C.c_int64) for n in ("submitted", "completed", "failed", "epochs",
+                                          "admissions", "evictions", "pending",
+                                          "resident_bytes")] + [("paths", C.c_double)]
 
 
 _lib = None
@@ -106,6 +124,13 @@ def load():
     L.prdpt_batch_autotune.argtypes = [vp, C.POINTER(Request), i32, C.c_char_p,
                                        C.POINTER(C.c_int), C.POINTER(C.c_int),
                                        C.POINTER(C.c_double)]
+    L.prdpt_server_start.argtypes = [vp, C.POINTER(ServerConfig), pvp]
+    L.prdpt_server_add_job.argtypes = [vp, C.POINTER(SceneDesc), vp, C.POINTER(C.c_int)]
+    L.prdpt_server_submit.argtypes = [vp, i32, vp, vp, i32, u64, i32, C.POINTER(C.c_int64)]
+    L.prdpt_server_cancel.argtypes = [vp, C.c_int64]
+    L.prdpt_server_poll.argtypes = [vp, C.POINTER(Completion), i32, i32, C.POINTER(C.c_int)]
+    L.prdpt_server_get_stats.argtypes = [vp, C.POINTER(ServerStats)]
+    L.prdpt_server_stop.argtypes = [vp]
     for name in EXPORTS:
         if name != "prdpt_last_error":
             getattr(L, name).restype = C.c_int
@@ -412,3 +437,61 @@ def prdpt_batch_autotune(ctx, reqs, cache_path=None):
                                        cache_path.encode() if cache_path else None,
                                        C.byref(b), C.byref(t), C.byref(ms)))
     return b.value, t.value, ms.value
+
+
+class Server:
+    """prdpt_server: continuous-batching request loop on one context."""
+
+    def __init__(self, ctx, hbm_budget=0, max_batch=64, max_inflight=2):
+        cfg = ServerConfig(int(hbm_budget), int(max_batch), int(max_inflight))
+        h = C.c_void_p()
+        _check(load().prdpt_server_start(ctx.h, C.byref(cfg), C.byref(h)))
+        self.h, self.ctx = h, ctx
+        self.d = {}
+        self._buf = (Completion * 256)()
+
+    def add_job(self, scene, ref):
+        """Register a generator Scene and its reference image (host float32 [H, W, 3])."""
+        desc, keep = scene_desc(scene)
+        r, rp = _host(ref, np.float32)
+        jid = C.c_int()
+        _check(load().prdpt_server_add_job(self.h, C.byref(desc), rp, C.byref(jid)))
+        del keep
+        self.d[jid.value] = scene.d
+        return jid.value
+
+    def submit(self, job, theta, sigma, N, seed, est):
+        th, tp = _host(theta, np.float32)
+        sg, sp = _host(sigma, np.float32)
+        if th.size != self.d[job] or sg.size != self.d[job]:
+            raise ValueError("theta/sigma length must equal the job's parameter count")
+        t = C.c_int64()
+        _check(load().prdpt_server_submit(self.h, int(job), tp, sp, int(N), int(seed), int(est),
+                                          C.byref(t)))
+        return t.value
+
+    def cancel(self, ticket):
+        _check(load().prdpt_server_cancel(self.h, int(ticket)))
+
+    def poll(self, timeout_ms=0):
+        """List of completion dicts (ticket, job, status, loss, grad, t_submit, t_start, t_done)."""
+        n = C.c_int()
+        _check(load().prdpt_server_poll(self.h, self._buf, len(self._buf), int(timeout_ms),
+                                        C.byref(n)))
+        out = []
+        for c in self._buf[: n.value]:
+            d = self.d.get(c.job, 0)
+            out.append(dict(ticket=c.ticket, job=c.job, status=c.status, loss=c.loss,
+                            grad=np.array(c.grad[:d]), t_submit=c.t_submit, t_start=c.t_start,
+                            t_done=c.t_done))
+        return out
+
+    def stats(self):
+        st = ServerStats()
+        _check(load().prdpt_server_get_stats(self.h, C.byref(st)))
+        return {n: getattr(st, n) for n, _ in ServerStats._fields_}
+
+    def stop(self):
+        if getattr(self, "h", None):
+            _check(load().prdpt_server_stop(self.h))
+            self.h = None
