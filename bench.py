@@ -160,7 +160,8 @@ def main():
     log(f"timed {args.steps} steps in {elapsed:.3f} s; counting work of the timed launches")
 
     # algorithmic work of the timed launches, replayed with the counting kernel
-    cnt = {"nodes": 0, "tris": 0, "rays": 0, "paths": 0}
+    cnt = {"nodes": 0, "tris": 0, "rays": 0, "paths": 0, "wave_node_iters": 0,
+           "wave_tri_iters": 0, "wave_ray_iters": 0}
     for th32, s, seed in trajectory:
         c = NV.prdpt_traversal_counts(sc, th32, s, N, seed, est)
         for k in cnt:
@@ -196,6 +197,10 @@ def main():
                    "share_of_step": (kernel_ms / 1e3) / elapsed},
         "work_per_estimate": {"nodes": per["nodes"], "triangles": per["tris"], "rays": per["rays"],
                               "paths": per["paths"]},
+        "simd_efficiency": {
+            "node_loop": per["nodes"] / max(64 * per["wave_node_iters"], 1),
+            "triangle_loop": per["tris"] / max(64 * per["wave_tri_iters"], 1),
+            "ray_loop": per["rays"] / max(64 * per["wave_ray_iters"], 1)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_profile()},
         "scene_build_s": t_build,

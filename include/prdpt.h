@@ -334,8 +334,10 @@ int prdpt_ctx_read_timing(prdpt_ctx* ctx, double* total_ms, int64_t* launches);
 /*
  * Work of one estimate, measured by an instrumented copy of the render kernel
  * on the same rays: counts[0] BVH nodes fetched, counts[1] triangles tested,
- * counts[2] ray queries (closest-hit and shadow), counts[3] camera paths.
- * counts: host uint64_t[4].  Synchronous.
+ * counts[2] ray queries (closest-hit and shadow), counts[3] camera paths,
+ * counts[4..6] iterations of the node loop, the triangle loop and the ray loop
+ * executed per wavefront (summed over wavefronts; lane work / (64 x iterations)
+ * is each loop's SIMD efficiency).  counts: host uint64_t[7].  Synchronous.
  */
 int prdpt_traversal_counts(prdpt_scene* scene, const float* theta, const float* sigma, int N,
                            uint64_t seed, int est, uint64_t* counts);

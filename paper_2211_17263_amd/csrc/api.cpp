@@ -603,17 +603,17 @@ int prdpt_traversal_counts(prdpt_scene* s, const float* theta, const float* sigm
   std::lock_guard<std::mutex> g(ctx->mu);
   HIP_TRY(hipSetDevice(ctx->device));
   if (int rc = prepare(ctx, N, d, render_tiles(h.W, h.H))) return rc;
-  if (int rc = ensure(ctx, ctx->counters, 4)) return rc;
+  if (int rc = ensure(ctx, ctx->counters, 7)) return rc;
   if (int rc = upload_vectors(ctx, theta, sigma, d)) return rc;
-  HIP_TRY(hipMemsetAsync(ctx->counters.p, 0, 4 * sizeof(unsigned long long), ctx->stream));
+  HIP_TRY(hipMemsetAsync(ctx->counters.p, 0, 7 * sizeof(unsigned long long), ctx->stream));
   HIP_TRY(launch_tau(ctx->stream, est, d, P, seed, ctx->sigma.p, ctx->theta.p, chi_mean(d),
                      std::sqrt(2.0 * M_PI), ctx->tau.p, ctx->c.p, ctx->X.p));
   HIP_TRY(launch_render(ctx->stream, s->dev(), h.W, h.H, ctx->X.p, N, d, kTagPath, seed, nullptr,
                         nullptr, nullptr, ctx->counters.p));
-  unsigned long long host[4];
+  unsigned long long host[7];
   HIP_TRY(hipMemcpyAsync(host, ctx->counters.p, sizeof(host), hipMemcpyDeviceToHost, ctx->stream));
   HIP_TRY(hipStreamSynchronize(ctx->stream));
-  for (int i = 0; i < 4; ++i) counts[i] = host[i];
+  for (int i = 0; i < 7; ++i) counts[i] = host[i];
   return PRDPT_OK;
 }
 

@@ -192,9 +192,18 @@ __device__ __forceinline__ void keep_closer(Hit& h, float t, int id, int slot) {
   }
 }
 
+// Work counters of the instrumented kernel copy: lane-level work (nodes,
+// triangles, rays, paths) and wave-level loop iterations (counted once per wave
+// by its first active lane), whose ratio is the SIMD efficiency of each loop.
 struct Counters {
   uint32_t nodes, tris, rays, paths;
+  uint32_t wave_node_iters, wave_tri_iters, wave_outer_iters, pad;
 };
+
+__device__ __forceinline__ bool first_active_lane() {
+  const unsigned long long m = __ballot(1);
+  return (int)__lane_id() == __ffsll((long long)m) - 1;
+}
 
 // Conservative binary32 slab test of a padded child box; returns the entry
 // distance (or +inf when the box is missed or lies beyond tcull).
@@ -218,9 +227,18 @@ __device__ __forceinline__ float safe_inv(float x) {
 // loop (lanes do not reconverge between instances; the instances are visited in
 // order, each to completion).  any = true: shadow query, stop at the first
 // occluder with t < tmax (emissive quads are not occluders); otherwise keep the
-// closest hit by (t, primitive id).  The stack holds kStackEntries entries in
-// LDS (stride = work-group size); the builder bounds the inner-node depth so it
-// cannot overflow.
+// closest hit by (t, primitive id).
+//
+// Traversal is "while-while" with postponed leaves: the node loop visits inner
+// nodes, and a hit leaf child becomes the lane's pending leaf (or is pushed if
+// one is already pending); lanes holding a leaf keep descending speculatively.
+// The wave leaves the node loop once every lane holds a leaf or has no work
+// left, and then tests all pending leaves together, so the triangle loop runs
+// with most lanes active.  Stack entries: >= 0 inner node, < 0 leaf encoded as
+// ~(first << 3 | (count - 1)).  The stack holds kStackEntries entries in LDS
+// (stride = work-group size); the builder bounds the inner-node depth, every
+// inner node on the current path holds at most one stack entry and the last
+// visited one at most two, so it cannot overflow.
 template <bool COUNT>
 __device__ void trace_ray(const SceneHdr& S, const Node* __restrict__ nodes,
                           const Tri* __restrict__ tris, V3 o, V3 d, float tmax, bool any, Hit& h,
@@ -253,70 +271,103 @@ __device__ void trace_ray(const SceneHdr& S, const Node* __restrict__ nodes,
   const V3 inv = mk(safe_inv(d.x), safe_inv(d.y), safe_inv(d.z));
   int sp = 0;
   int inst = -1;
-  int node = -1;
+  int node = -1;   // inner node being visited, -1: none
+  int leaf = 0;    // pending leaf (encoded < 0), 0: none
+  bool done = false;
   V3 om = o, oi = o;
-  while (true) {
-    if (node < 0) {
-      if (sp > 0) {
-        --sp;
-        node = stack[sp * stride];
-      } else {
-        do {
-          ++inst;
-        } while (inst < S.n_inst && S.inst_root[inst] < 0);
-        if (inst >= S.n_inst) break;
-        node = S.inst_root[inst];
-        // an instance: the ray moves by minus the mesh translation
-        om = mk(o.x - S.inst_xlate[inst][0], o.y - S.inst_xlate[inst][1], o.z - S.inst_xlate[inst][2]);
-        oi = mk(-om.x * inv.x, -om.y * inv.y, -om.z * inv.z);
-      }
+  // first instance
+  auto next_instance = [&]() {
+    do {
+      ++inst;
+    } while (inst < S.n_inst && S.inst_root[inst] < 0);
+    if (inst >= S.n_inst) {
+      done = true;
+      return;
     }
-    const float4* np = reinterpret_cast<const float4*>(nodes + node);
-    const float4 a = np[0], b = np[1], c = np[2];
-    const int4 ix = reinterpret_cast<const int4*>(np)[3];
-    if (COUNT) cnt.nodes++;
-    const float tcull = any ? tmax : fminf(tmax, h.t);
-    const float t0 = slab(a.x, a.y, a.z, a.w, c.x, c.y, inv, oi, tcull);
-    const float t1s = slab(b.x, b.y, b.z, b.w, c.z, c.w, inv, oi, tcull);
-    const float t1 = ix.y >= 0 ? t1s : __builtin_huge_valf();
-    bool h0 = t0 < __builtin_huge_valf(), h1 = t1 < __builtin_huge_valf();
-#pragma unroll
-    for (int side = 0; side < 2; ++side) {
-      const bool hs = side == 0 ? h0 : h1;
-      const int cntl = side == 0 ? ix.z : ix.w;
-      if (hs && cntl > 0) {
-        const int first = side == 0 ? ix.x : ix.y;
-        for (int i = first; i < first + cntl; ++i) {
-          const float4* tp = reinterpret_cast<const float4*>(tris + i);
-          const float4 p0 = tp[0], p1 = tp[1], p2 = tp[2];
-          if (COUNT) cnt.tris++;
-          float t;
-          if (hit_tri(om, d, mk(p0.x, p0.y, p0.z), mk(p0.w, p1.x, p1.y), mk(p1.z, p1.w, p2.x),
-                      tmax, &t)) {
-            if (any) {
-              h.t = t;
-              h.id = __float_as_int(p2.y);
-              return;
-            }
-            keep_closer(h, t, __float_as_int(p2.y), i);
-          }
+    node = S.inst_root[inst];
+    // an instance: the ray moves by minus the mesh translation
+    om = mk(o.x - S.inst_xlate[inst][0], o.y - S.inst_xlate[inst][1], o.z - S.inst_xlate[inst][2]);
+    oi = mk(-om.x * inv.x, -om.y * inv.y, -om.z * inv.z);
+  };
+  next_instance();
+  while (!done) {
+    // ---- node loop: descend until every lane holds a leaf or is out of work
+    while (true) {
+      if (node < 0 && leaf == 0) {
+        if (sp > 0) {
+          --sp;
+          const int e = stack[sp * stride];
+          if (e < 0) leaf = e;
+          else node = e;
         }
-        if (side == 0) h0 = false;
-        else h1 = false;
+      }
+      const bool ready = leaf != 0 || (node < 0 && sp == 0);
+      if (__ballot(!ready) == 0ull) break;
+      if (node >= 0) {
+        const float4* np = reinterpret_cast<const float4*>(nodes + node);
+        const float4 a = np[0], b = np[1], c = np[2];
+        const int4 ix = reinterpret_cast<const int4*>(np)[3];
+        if (COUNT) {
+          cnt.nodes++;
+          if (first_active_lane()) cnt.wave_node_iters++;
+        }
+        const float tcull = any ? tmax : fminf(tmax, h.t);
+        const float t0 = slab(a.x, a.y, a.z, a.w, c.x, c.y, inv, oi, tcull);
+        const float t1s = slab(b.x, b.y, b.z, b.w, c.z, c.w, inv, oi, tcull);
+        const float t1 = ix.y >= 0 ? t1s : __builtin_huge_valf();
+        const bool h0 = t0 < __builtin_huge_valf(), h1 = t1 < __builtin_huge_valf();
+        const bool l0 = ix.z > 0, l1 = ix.w > 0;
+        const int e0 = l0 ? ~((ix.x << 3) | (ix.z - 1)) : ix.x;
+        const int e1 = l1 ? ~((ix.y << 3) | (ix.w - 1)) : ix.y;
+        // leaf children: the first becomes the pending leaf if none is, the
+        // rest go on the stack
+        if (h0 && l0) {
+          if (leaf == 0) leaf = e0;
+          else stack[(sp++) * stride] = e0;
+        }
+        if (h1 && l1) {
+          if (leaf == 0) leaf = e1;
+          else stack[(sp++) * stride] = e1;
+        }
+        const bool i0 = h0 && !l0, i1 = h1 && !l1;
+        if (i0 && i1) {
+          const bool first0 = t0 <= t1;
+          stack[(sp++) * stride] = first0 ? e1 : e0;
+          node = first0 ? e0 : e1;
+        } else if (i0) {
+          node = e0;
+        } else if (i1) {
+          node = e1;
+        } else {
+          node = -1;
+        }
       }
     }
-    if (h0 && h1) {
-      const bool first0 = t0 <= t1;
-      stack[sp * stride] = first0 ? ix.y : ix.x;
-      ++sp;
-      node = first0 ? ix.x : ix.y;
-    } else if (h0) {
-      node = ix.x;
-    } else if (h1) {
-      node = ix.y;
-    } else {
-      node = -1;
+    // ---- leaf loop: all pending leaves together
+    if (leaf != 0) {
+      const int code = ~leaf;
+      const int first = code >> 3, count = (code & 7) + 1;
+      leaf = 0;
+      for (int i = first; i < first + count; ++i) {
+        const float4* tp = reinterpret_cast<const float4*>(tris + i);
+        const float4 p0 = tp[0], p1 = tp[1], p2 = tp[2];
+        if (COUNT) {
+          cnt.tris++;
+          if (first_active_lane()) cnt.wave_tri_iters++;
+        }
+        float t;
+        if (hit_tri(om, d, mk(p0.x, p0.y, p0.z), mk(p0.w, p1.x, p1.y), mk(p1.z, p1.w, p2.x), tmax,
+                    &t)) {
+          if (any) {
+            h.t = t;
+            h.id = __float_as_int(p2.y);
+            return;
+          }
+          keep_closer(h, t, __float_as_int(p2.y), i);
+        }
+      }
     }
+    if (node < 0 && leaf == 0 && sp == 0) next_instance();
   }
 }
 
@@ -412,7 +463,7 @@ __device__ __forceinline__ void render_tile(const SceneHdr& S, const Node* __res
   const int spp = S.spp;
   const int n_lights = S.n_pl + S.n_area;
   int* stk = stack + t;
-  Counters cnt{0u, 0u, 0u, 0u};
+  Counters cnt{0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
 
   float acc0 = 0.0f, acc1 = 0.0f, acc2 = 0.0f;
   // path state
@@ -452,6 +503,7 @@ __device__ __forceinline__ void render_tile(const SceneHdr& S, const Node* __res
       light = -1;
     }
     Hit h;
+    if (COUNT && first_active_lane()) cnt.wave_outer_iters++;
     trace_ray<COUNT>(S, nodes, tris, o, dir, tmax, shadow, h, stk, kBlock, cnt);
     bool end_path = false;
     if (shadow) {
@@ -645,6 +697,9 @@ __device__ __forceinline__ void render_tile(const SceneHdr& S, const Node* __res
     atomicAdd(&counters[1], (unsigned long long)cnt.tris);
     atomicAdd(&counters[2], (unsigned long long)cnt.rays);
     atomicAdd(&counters[3], (unsigned long long)cnt.paths);
+    atomicAdd(&counters[4], (unsigned long long)cnt.wave_node_iters);
+    atomicAdd(&counters[5], (unsigned long long)cnt.wave_tri_iters);
+    atomicAdd(&counters[6], (unsigned long long)cnt.wave_outer_iters);
   }
   if (partial_slot) {
     // fixed-order butterfly within the wave, then the waves in order

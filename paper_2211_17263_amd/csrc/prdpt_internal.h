@@ -10,7 +10,10 @@ constexpr int kTagTau = 1;
 constexpr int kTagPath = 2;
 constexpr int kTagRef = 3;
 constexpr int kMaxInnerDepth = 25;               // BVH inner-node depth bound (root = 1)
-constexpr int kStackEntries = kMaxInnerDepth - 1; // traversal stack entries per ray
+// Traversal stack entries per ray: each inner node on the current path keeps at
+// most one child on the stack, and the last one visited at most two (both
+// children leaves while a leaf is already pending), so depth + 1 suffice.
+constexpr int kStackEntries = kMaxInnerDepth + 1;
 
 // Flattened BVH node: both children's boxes live in the parent (64 bytes, four
 // 16-byte loads).  cnt == 0: idx is an inner node; cnt > 0: idx is the first of

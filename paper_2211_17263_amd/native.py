@@ -340,10 +340,11 @@ def prdpt_traversal_counts(scene, theta, sigma, N, seed, est):
     """dict(nodes, tris, rays, paths) of one estimate's render."""
     th, tp = _host(theta, np.float32)
     sg, sp = _host(sigma, np.float32)
-    out = np.zeros(4, np.uint64)
+    out = np.zeros(7, np.uint64)
     _check(load().prdpt_traversal_counts(scene.h, tp, sp, int(N), int(seed), int(est),
                                          out.ctypes.data_as(C.c_void_p)))
-    return dict(zip(("nodes", "tris", "rays", "paths"), (int(x) for x in out)))
+    return dict(zip(("nodes", "tris", "rays", "paths", "wave_node_iters", "wave_tri_iters",
+                     "wave_ray_iters"), (int(x) for x in out)))
 
 
 def prdpt_copy_probe(ctx, src, dst, iters=10):
