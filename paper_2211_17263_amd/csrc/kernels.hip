@@ -233,12 +233,16 @@ __device__ __forceinline__ float safe_inv(float x) {
 // nodes, and a hit leaf child becomes the lane's pending leaf (or is pushed if
 // one is already pending); lanes holding a leaf keep descending speculatively.
 // The wave leaves the node loop once every lane holds a leaf or has no work
-// left, and then tests all pending leaves together, so the triangle loop runs
-// with most lanes active.  Stack entries: >= 0 inner node, < 0 leaf encoded as
+// left, or once at least PRDPT_LEAF_QUORUM percent of its active lanes hold
+// one, and then tests the pending leaves together, so the triangle loop runs
+// with many lanes active and one long descent does not stall the rest.  Stack entries: >= 0 inner node, < 0 leaf encoded as
 // ~(first << 3 | (count - 1)).  The stack holds kStackEntries entries in LDS
 // (stride = work-group size); the builder bounds the inner-node depth, every
 // inner node on the current path holds at most one stack entry and the last
 // visited one at most two, so it cannot overflow.
+#ifndef PRDPT_LEAF_QUORUM
+#define PRDPT_LEAF_QUORUM 50
+#endif
 template <bool COUNT>
 __device__ void trace_ray(const SceneHdr& S, const Node* __restrict__ nodes,
                           const Tri* __restrict__ tris, V3 o, V3 d, float tmax, bool any, Hit& h,
@@ -303,6 +307,9 @@ __device__ void trace_ray(const SceneHdr& S, const Node* __restrict__ nodes,
       }
       const bool ready = leaf != 0 || (node < 0 && sp == 0);
       if (__ballot(!ready) == 0ull) break;
+#if PRDPT_LEAF_QUORUM < 100
+      if (__popcll(__ballot(leaf != 0)) * 100 >= __popcll(__ballot(1)) * PRDPT_LEAF_QUORUM) break;
+#endif
       if (node >= 0) {
         const float4* np = reinterpret_cast<const float4*>(nodes + node);
         const float4 a = np[0], b = np[1], c = np[2];
