@@ -1,7 +1,9 @@
-// Host BVH builder: binned surface-area heuristic (16 bins per axis), leaves of
-// at most 4 triangles, inner-node depth bounded by kMaxInnerDepth so a fixed
-// traversal stack always suffices: a split is admissible only if both children
-// still fit a balanced subtree in the depth that remains (else object median).
+// Host BVH builder: surface-area heuristic (16 bins per axis, an exact sweep
+// over sorted centroids for small ranges), leaves of at most 4 triangles, a
+// range of at most 4 kept as a leaf only when no split is cheaper under the
+// SAH, and inner-node depth bounded by kMaxInnerDepth so a fixed traversal
+// stack always suffices: a split is admissible only if both children still fit
+// a balanced subtree in the depth that remains (else object median).
 // Output is appended to flat node/triangle arrays in the 64-byte / 48-byte
 // layouts the kernels read with 16-byte loads.
 #include <algorithm>
@@ -46,6 +48,17 @@ struct Prim {
 
 constexpr int kBins = 16;
 constexpr int kLeafMax = 4;
+constexpr int kSweepMax = 32;   // ranges up to this size use the exact sweep
+
+// SAH costs: one node visit (both child boxes) and one triangle test
+#ifndef PRDPT_SAH_NODE
+#define PRDPT_SAH_NODE 2.0
+#endif
+#ifndef PRDPT_SAH_TRI
+#define PRDPT_SAH_TRI 1.0
+#endif
+constexpr double kCostNode = PRDPT_SAH_NODE;
+constexpr double kCostTri = PRDPT_SAH_TRI;
 
 // largest triangle count a subtree whose root inner node sits at depth D can
 // hold within the depth bound (two leaves of kLeafMax at depth kMaxInnerDepth)
@@ -97,25 +110,64 @@ struct Builder {
     return b;
   }
 
+  // exact SAH sweep over the centroids sorted along each axis; returns the
+  // best cost (sum of child area x count) and sets axis/position, or DBL_MAX
+  double sweep(int begin, int end, long long child_cap, int* best_axis, int* best_mid) {
+    const int n = end - begin;
+    double best = DBL_MAX;
+    std::vector<double> right(n);
+    for (int a = 0; a < 3; ++a) {
+      std::sort(prims.begin() + begin, prims.begin() + end, [&](const Prim& p, const Prim& q) {
+        return p.c[a] < q.c[a] || (p.c[a] == q.c[a] && p.tri < q.tri);
+      });
+      Box acc;
+      for (int i = n - 1; i > 0; --i) {
+        acc.grow(prims[begin + i].box);
+        right[i] = acc.area();
+      }
+      Box lacc;
+      for (int i = 1; i < n; ++i) {
+        lacc.grow(prims[begin + i - 1].box);
+        if (i > child_cap || n - i > child_cap) continue;
+        const double cost = lacc.area() * i + right[i] * (n - i);
+        if (cost < best) {
+          best = cost;
+          *best_axis = a;
+          *best_mid = i;
+        }
+      }
+    }
+    if (best < DBL_MAX) {
+      const int a = *best_axis;
+      std::sort(prims.begin() + begin, prims.begin() + end, [&](const Prim& p, const Prim& q) {
+        return p.c[a] < q.c[a] || (p.c[a] == q.c[a] && p.tri < q.tri);
+      });
+    }
+    return best;
+  }
+
   // returns (idx, cnt) reference to a subtree: cnt > 0 leaf, cnt == 0 inner
   // node at inner-node depth `depth`
   void build(int begin, int end, int depth, int32_t* idx, int32_t* cnt) {
     int n = end - begin;
-    if (n <= kLeafMax) {
+    const long long child_cap = capacity(depth + 1);
+    if (n == 1) {
       *idx = emit_leaf(begin, end);
       *cnt = n;
       return;
     }
-    max_depth = std::max(max_depth, depth);
-    const long long child_cap = capacity(depth + 1);
     Box cb;
     for (int i = begin; i < end; ++i) cb.grow(prims[i].c);
     int axis = 0;
     for (int a = 1; a < 3; ++a)
       if (cb.hi[a] - cb.lo[a] > cb.hi[axis] - cb.lo[axis]) axis = a;
     int mid = -1;
-    if (cb.hi[axis] > cb.lo[axis]) {
-      double best = DBL_MAX;
+    double best = DBL_MAX;
+    if (n <= kSweepMax) {
+      int ba = -1, bm = -1;
+      best = sweep(begin, end, child_cap, &ba, &bm);
+      if (best < DBL_MAX) mid = begin + bm;
+    } else if (cb.hi[axis] > cb.lo[axis]) {
       int best_axis = -1, best_bin = -1;
       for (int a = 0; a < 3; ++a) {
         float ext = cb.hi[a] - cb.lo[a];
@@ -164,6 +216,20 @@ struct Builder {
         if (mid == begin || mid == end) mid = -1;
       }
     }
+    if (n <= kLeafMax) {
+      // keep a leaf unless splitting is cheaper: node visit + expected tests
+      const double parent = range_box(begin, end).area();
+      // (an inner node here must still respect the depth bound)
+      const double split = mid < 0 || !(parent > 0.0) || depth > kMaxInnerDepth
+                               ? DBL_MAX
+                               : kCostNode + kCostTri * best / parent;
+      if (kCostTri * n <= split) {
+        *idx = emit_leaf(begin, end);
+        *cnt = n;
+        return;
+      }
+    }
+    max_depth = std::max(max_depth, depth);
     if (mid < 0) {
       mid = begin + n / 2;
       std::nth_element(prims.begin() + begin, prims.begin() + mid, prims.begin() + end,

@@ -222,12 +222,18 @@ __device__ __forceinline__ float safe_inv(float x) {
   return __builtin_amdgcn_rcpf(ax);
 }
 
-// Traverse one instance BVH.  ANY: stop at the first hit with t < tmax.
-// Trace one ray through the analytic primitives and every instance BVH in one
-// loop (lanes do not reconverge between instances; the instances are visited in
-// order, each to completion).  any = true: shadow query, stop at the first
-// occluder with t < tmax (emissive quads are not occluders); otherwise keep the
-// closest hit by (t, primitive id).
+// Ray queries over the analytic primitives and every instance BVH.  any =
+// true: shadow query, stop at the first occluder with t < tmax (emissive quads
+// are not occluders); otherwise keep the closest hit by (t, primitive id), a
+// result that does not depend on the order in which primitives are visited.
+//
+// A query is resumable: begin_trace tests the analytic primitives and queues
+// the first instance's root; continue_trace then traverses until the query is
+// answered or the wave has spent `budget` node-loop iterations in this call, so
+// lanes whose ray is done can shade and start their next ray while long
+// traversals go on.  The suspended state is the best hit so far, the stack
+// pointer and the instance (Trav); the node being visited is pushed back on the
+// lane's stack and the instance-space ray is rebuilt on resumption.
 //
 // Traversal is "while-while" with postponed leaves: the node loop visits inner
 // nodes, and a hit leaf child becomes the lane's pending leaf (or is pushed if
@@ -235,18 +241,41 @@ __device__ __forceinline__ float safe_inv(float x) {
 // The wave leaves the node loop once every lane holds a leaf or has no work
 // left, or once at least PRDPT_LEAF_QUORUM percent of its active lanes hold
 // one, and then tests the pending leaves together, so the triangle loop runs
-// with many lanes active and one long descent does not stall the rest.  Stack entries: >= 0 inner node, < 0 leaf encoded as
-// ~(first << 3 | (count - 1)).  The stack holds kStackEntries entries in LDS
-// (stride = work-group size); the builder bounds the inner-node depth, every
-// inner node on the current path holds at most one stack entry and the last
-// visited one at most two, so it cannot overflow.
+// with many lanes active and one long descent does not stall the rest.
+// Instances are visited in order, each to completion.
+//
+// Stack entries: >= 0 inner node, < 0 leaf encoded as ~(first << 3 |
+// (count - 1)).  The stack holds kStackEntries entries in LDS (stride =
+// work-group size); the builder bounds the inner-node depth, every inner node
+// on the current path holds at most one stack entry and the last visited one at
+// most two, and a suspended node takes the place of its own path entry, so it
+// cannot overflow.
 #ifndef PRDPT_LEAF_QUORUM
 #define PRDPT_LEAF_QUORUM 50
 #endif
+#ifndef PRDPT_TRACE_BUDGET
+#define PRDPT_TRACE_BUDGET 16
+#endif
+
+struct Trav {
+  Hit h;
+  int sp;    // stack entries in use
+  int inst;  // instance being traversed
+};
+
+// first instance at or after i with a BVH, or n_inst
+__device__ __forceinline__ int next_inst(const SceneHdr& S, int i) {
+  while (i < S.n_inst && S.inst_root[i] < 0) ++i;
+  return i;
+}
+
+// Starts a query: analytic primitives, then the first instance's root on the
+// stack.  Returns true when the query is already answered (a shadow ray
+// blocked by an analytic primitive, or nothing left to traverse).
 template <bool COUNT>
-__device__ void trace_ray(const SceneHdr& S, const Node* __restrict__ nodes,
-                          const Tri* __restrict__ tris, V3 o, V3 d, float tmax, bool any, Hit& h,
-                          int* __restrict__ stack, int stride, Counters& cnt) {
+__device__ __forceinline__ bool begin_trace(const SceneHdr& S, V3 o, V3 d, float tmax, bool any,
+                                            Trav& tr, int* __restrict__ stack, Counters& cnt) {
+  Hit& h = tr.h;
   h.t = __builtin_huge_valf();
   h.id = -1;
   h.slot = -1;
@@ -256,7 +285,7 @@ __device__ void trace_ray(const SceneHdr& S, const Node* __restrict__ nodes,
     if (hit_sphere(o, d, S.sph[i], tmax, &t)) {
       if (any) {
         h.id = i;
-        return;
+        return true;
       }
       keep_closer(h, t, i, -1);
     }
@@ -267,35 +296,36 @@ __device__ void trace_ray(const SceneHdr& S, const Node* __restrict__ nodes,
     if (hit_quad(o, d, S.quad[i], tmax, &t)) {
       if (any) {
         h.id = S.n_sph + i;
-        return;
+        return true;
       }
       keep_closer(h, t, S.n_sph + i, -1);
     }
   }
+  tr.inst = next_inst(S, 0);
+  if (tr.inst >= S.n_inst) return true;
+  stack[0] = S.inst_root[tr.inst];
+  tr.sp = 1;
+  return false;
+}
+
+// Continues a query; returns true when it is answered (tr.h holds the result).
+template <bool COUNT>
+__device__ bool continue_trace(const SceneHdr& S, const Node* __restrict__ nodes,
+                               const Tri* __restrict__ tris, V3 o, V3 d, float tmax, bool any,
+                               Trav& tr, int* __restrict__ stack, int stride, int budget,
+                               Counters& cnt) {
+  Hit& h = tr.h;
+  int sp = tr.sp;
+  int inst = tr.inst;
   const V3 inv = mk(safe_inv(d.x), safe_inv(d.y), safe_inv(d.z));
-  int sp = 0;
-  int inst = -1;
+  // an instance: the ray moves by minus the mesh translation
+  V3 om = mk(o.x - S.inst_xlate[inst][0], o.y - S.inst_xlate[inst][1], o.z - S.inst_xlate[inst][2]);
+  V3 oi = mk(-om.x * inv.x, -om.y * inv.y, -om.z * inv.z);
   int node = -1;   // inner node being visited, -1: none
   int leaf = 0;    // pending leaf (encoded < 0), 0: none
-  bool done = false;
-  V3 om = o, oi = o;
-  // first instance
-  auto next_instance = [&]() {
-    do {
-      ++inst;
-    } while (inst < S.n_inst && S.inst_root[inst] < 0);
-    if (inst >= S.n_inst) {
-      done = true;
-      return;
-    }
-    node = S.inst_root[inst];
-    // an instance: the ray moves by minus the mesh translation
-    om = mk(o.x - S.inst_xlate[inst][0], o.y - S.inst_xlate[inst][1], o.z - S.inst_xlate[inst][2]);
-    oi = mk(-om.x * inv.x, -om.y * inv.y, -om.z * inv.z);
-  };
-  next_instance();
-  while (!done) {
-    // ---- node loop: descend until every lane holds a leaf or is out of work
+  int iters = 0;
+  while (true) {
+    // ---- node loop: descend until enough lanes hold a leaf
     while (true) {
       if (node < 0 && leaf == 0) {
         if (sp > 0) {
@@ -310,6 +340,7 @@ __device__ void trace_ray(const SceneHdr& S, const Node* __restrict__ nodes,
 #if PRDPT_LEAF_QUORUM < 100
       if (__popcll(__ballot(leaf != 0)) * 100 >= __popcll(__ballot(1)) * PRDPT_LEAF_QUORUM) break;
 #endif
+      ++iters;
       if (node >= 0) {
         const float4* np = reinterpret_cast<const float4*>(nodes + node);
         const float4 a = np[0], b = np[1], c = np[2];
@@ -350,7 +381,7 @@ __device__ void trace_ray(const SceneHdr& S, const Node* __restrict__ nodes,
         }
       }
     }
-    // ---- leaf loop: all pending leaves together
+    // ---- leaf loop: the pending leaves together
     if (leaf != 0) {
       const int code = ~leaf;
       const int first = code >> 3, count = (code & 7) + 1;
@@ -368,13 +399,26 @@ __device__ void trace_ray(const SceneHdr& S, const Node* __restrict__ nodes,
           if (any) {
             h.t = t;
             h.id = __float_as_int(p2.y);
-            return;
+            return true;
           }
           keep_closer(h, t, __float_as_int(p2.y), i);
         }
       }
     }
-    if (node < 0 && leaf == 0 && sp == 0) next_instance();
+    if (node < 0 && sp == 0) {  // instance done: next one, or the query is answered
+      inst = next_inst(S, inst + 1);
+      if (inst >= S.n_inst) return true;
+      om = mk(o.x - S.inst_xlate[inst][0], o.y - S.inst_xlate[inst][1], o.z - S.inst_xlate[inst][2]);
+      oi = mk(-om.x * inv.x, -om.y * inv.y, -om.z * inv.z);
+      stack[0] = S.inst_root[inst];
+      sp = 1;
+    }
+    if (iters >= budget) {  // suspend: the current node goes back on the stack
+      if (node >= 0) stack[(sp++) * stride] = node;
+      tr.sp = sp;
+      tr.inst = inst;
+      return false;
+    }
   }
 }
 
@@ -484,202 +528,218 @@ __device__ __forceinline__ void render_tile(const SceneHdr& S, const Node* __res
 
   int s = valid ? 0 : spp;
   bool start = s < spp;
+  bool tracing = false;   // a query is in flight (possibly suspended)
+  bool answered = false;  // the last query's result (tr.h) is still to be used
+  Trav tr;
   while (s < spp) {
-    if (start) {  // camera ray of sample s
-      start = false;
-      if (COUNT) cnt.paths++;
-      float jx = 0.5f, jy = 0.5f;
-      if (!S.pixel_center) {
-        const uint4 wj = path_words(k0, k1, pix, s, pair, tag, 0, 0);
-        jx = unit_open(wj.x);
-        jy = unit_open(wj.y);
-      }
-      const float px = (float)x + jx, py = (float)y + jy;
-      const float sx = 2.0f * (px / (float)S.W) - 1.0f;
-      const float sy = 1.0f - 2.0f * (py / (float)S.H);
-      o = ld3(S.eye);
-      dir = unit(mk(S.fwd[0] + S.right[0] * sx + S.up[0] * sy,
-                    S.fwd[1] + S.right[1] * sx + S.up[1] * sy,
-                    S.fwd[2] + S.right[2] * sx + S.up[2] * sy));
-      tmax = __builtin_huge_valf();
-      shadow = false;
-      specular = true;
-      b0 = b1 = b2 = 1.0f;
-      L0 = L1 = L2 = 0.0f;
-      v = 0;
-      light = -1;
-    }
-    Hit h;
-    if (COUNT && first_active_lane()) cnt.wave_outer_iters++;
-    trace_ray<COUNT>(S, nodes, tris, o, dir, tmax, shadow, h, stk, kBlock, cnt);
-    bool end_path = false;
-    if (shadow) {
-      if (h.id < 0) {
-        L0 = L0 + c0;
-        L1 = L1 + c1;
-        L2 = L2 + c2;
-      }
-      ++light;
-    } else if (h.id < 0) {
-      L0 = L0 + b0 * S.env[0];
-      L1 = L1 + b1 * S.env[1];
-      L2 = L2 + b2 * S.env[2];
-      end_path = true;
-    } else {
-      p = at(o, dir, h.t);
-      V3 ng;
-      if (h.id < S.n_sph) {
-        mat = S.sph_mat[h.id];
-        ng = unit(sub(p, ld3(S.sph[h.id])));
-      } else if (h.id < S.tri_id_base) {
-        const int qi = h.id - S.n_sph;
-        mat = S.quad_mat[qi];
-        ng = unit(cross(ld3(S.quad[qi] + 3), ld3(S.quad[qi] + 6)));
-      } else {
-        const float4* tp = reinterpret_cast<const float4*>(tris + h.slot);
-        const float4 p0 = tp[0], p1 = tp[1], p2 = tp[2];
-        mat = __float_as_int(p2.z);
-        ng = unit(cross(mk(p0.w, p1.x, p1.y), mk(p1.z, p1.w, p2.x)));
-      }
-      const int mt = S.mat_type[mat];
-      if (mt == PRDPT_MAT_EMISSIVE) {
-        if (specular && dot(dir, ng) < 0.0f) {
-          L0 = L0 + b0 * S.mat_rgb[mat][0];
-          L1 = L1 + b1 * S.mat_rgb[mat][1];
-          L2 = L2 + b2 * S.mat_rgb[mat][2];
-        }
-        end_path = true;
-      } else {
-        w = path_words(k0, k1, pix, s, pair, tag, v + 1, 0);
-        if (mt == PRDPT_MAT_DIFFUSE) {
-          n = dot(ng, dir) > 0.0f ? neg(ng) : ng;
-          light = 0;
-        } else if (v == S.B) {  // dielectric sphere, bounce budget spent
+    if (!tracing) {
+      if (answered) {
+        answered = false;
+        const Hit h = tr.h;
+        bool end_path = false;
+        if (shadow) {
+          if (h.id < 0) {
+            L0 = L0 + c0;
+            L1 = L1 + c1;
+            L2 = L2 + c2;
+          }
+          ++light;
+        } else if (h.id < 0) {
+          L0 = L0 + b0 * S.env[0];
+          L1 = L1 + b1 * S.env[1];
+          L2 = L2 + b2 * S.env[2];
           end_path = true;
         } else {
-          const float ior = S.mat_ior[mat];
-          V3 nn = ng;
-          float cosi = -dot(dir, nn);
-          float ei = 1.0f, et = ior;
-          if (cosi < 0.0f) {
-            nn = neg(nn);
-            cosi = -cosi;
-            ei = ior;
-            et = 1.0f;
-          }
-          const float F = fresnel_dielectric(cosi, ei, et);
-          V3 nd, side;
-          if (unit_open(w.z) < F) {
-            const float dn = dot(dir, nn);
-            nd = mk(dir.x - nn.x * (2.0f * dn), dir.y - nn.y * (2.0f * dn), dir.z - nn.z * (2.0f * dn));
-            side = nn;
+          p = at(o, dir, h.t);
+          V3 ng;
+          if (h.id < S.n_sph) {
+            mat = S.sph_mat[h.id];
+            ng = unit(sub(p, ld3(S.sph[h.id])));
+          } else if (h.id < S.tri_id_base) {
+            const int qi = h.id - S.n_sph;
+            mat = S.quad_mat[qi];
+            ng = unit(cross(ld3(S.quad[qi] + 3), ld3(S.quad[qi] + 6)));
           } else {
-            const float eta = ei / et;
-            const float sin2t = (eta * eta) * (1.0f - cosi * cosi);
-            const float cost = sqrtf(1.0f - sin2t);
-            const float kk = eta * cosi - cost;
-            nd = mk(dir.x * eta + nn.x * kk, dir.y * eta + nn.y * kk, dir.z * eta + nn.z * kk);
-            side = neg(nn);
+            const float4* tp = reinterpret_cast<const float4*>(tris + h.slot);
+            const float4 p0 = tp[0], p1 = tp[1], p2 = tp[2];
+            mat = __float_as_int(p2.z);
+            ng = unit(cross(mk(p0.w, p1.x, p1.y), mk(p1.z, p1.w, p2.x)));
           }
-          o = offset_origin(p, side);
-          dir = unit(nd);
-          tmax = __builtin_huge_valf();
-          specular = true;
-          ++v;
+          const int mt = S.mat_type[mat];
+          if (mt == PRDPT_MAT_EMISSIVE) {
+            if (specular && dot(dir, ng) < 0.0f) {
+              L0 = L0 + b0 * S.mat_rgb[mat][0];
+              L1 = L1 + b1 * S.mat_rgb[mat][1];
+              L2 = L2 + b2 * S.mat_rgb[mat][2];
+            }
+            end_path = true;
+          } else {
+            w = path_words(k0, k1, pix, s, pair, tag, v + 1, 0);
+            if (mt == PRDPT_MAT_DIFFUSE) {
+              n = dot(ng, dir) > 0.0f ? neg(ng) : ng;
+              light = 0;
+            } else if (v == S.B) {  // dielectric sphere, bounce budget spent
+              end_path = true;
+            } else {
+              const float ior = S.mat_ior[mat];
+              V3 nn = ng;
+              float cosi = -dot(dir, nn);
+              float ei = 1.0f, et = ior;
+              if (cosi < 0.0f) {
+                nn = neg(nn);
+                cosi = -cosi;
+                ei = ior;
+                et = 1.0f;
+              }
+              const float F = fresnel_dielectric(cosi, ei, et);
+              V3 nd, side;
+              if (unit_open(w.z) < F) {
+                const float dn = dot(dir, nn);
+                nd = mk(dir.x - nn.x * (2.0f * dn), dir.y - nn.y * (2.0f * dn), dir.z - nn.z * (2.0f * dn));
+                side = nn;
+              } else {
+                const float eta = ei / et;
+                const float sin2t = (eta * eta) * (1.0f - cosi * cosi);
+                const float cost = sqrtf(1.0f - sin2t);
+                const float kk = eta * cosi - cost;
+                nd = mk(dir.x * eta + nn.x * kk, dir.y * eta + nn.y * kk, dir.z * eta + nn.z * kk);
+                side = neg(nn);
+              }
+              o = offset_origin(p, side);
+              dir = unit(nd);
+              tmax = __builtin_huge_valf();
+              specular = true;
+              ++v;
+            }
+          }
         }
+        if (!end_path && light >= 0) {
+          // next-event estimation at a diffuse vertex: set up the next light whose
+          // sample faces both surfaces, else continue the path
+          shadow = false;
+          const float f0 = S.mat_rgb[mat][0] * kInvPi, f1 = S.mat_rgb[mat][1] * kInvPi,
+                      f2 = S.mat_rgb[mat][2] * kInvPi;
+          for (; light < n_lights; ++light) {
+            if (light < S.n_pl) {
+              const float* lp = S.pl[light];
+              const V3 toL = sub(ld3(lp), p);
+              const float dist2 = dot(toL, toL);
+              const float dist = sqrtf(dist2);
+              const V3 wi = scale(toL, 1.0f / dist);
+              const float cx = dot(n, wi);
+              if (!(cx > 0.0f)) continue;
+              c0 = b0 * f0 * ((lp[3] * cx) / dist2);
+              c1 = b1 * f1 * ((lp[4] * cx) / dist2);
+              c2 = b2 * f2 * ((lp[5] * cx) / dist2);
+              o = offset_origin(p, n);
+              dir = wi;
+              tmax = dist * 0.9999f;
+              shadow = true;
+              break;
+            }
+            const int ai = light - S.n_pl;
+            const int qi = S.area_quad[ai];
+            float ua, ub;
+            if (ai == 0) {
+              ua = unit_open(w.x);
+              ub = unit_open(w.y);
+            } else {
+              const uint4 w2 = path_words(k0, k1, pix, s, pair, tag, v + 1, ai);
+              ua = unit_open(w2.x);
+              ub = unit_open(w2.y);
+            }
+            const float* qd = S.quad[qi];
+            const V3 qo = ld3(qd), e1 = ld3(qd + 3), e2 = ld3(qd + 6);
+            const V3 yl = mk(qo.x + e1.x * ua + e2.x * ub, qo.y + e1.y * ua + e2.y * ub,
+                             qo.z + e1.z * ua + e2.z * ub);
+            const V3 nl = cross(e1, e2);
+            const float area = sqrtf(dot(nl, nl));
+            const V3 nlu = scale(nl, 1.0f / area);
+            const V3 toL = sub(yl, p);
+            const float dist2 = dot(toL, toL);
+            const float dist = sqrtf(dist2);
+            const V3 wi = scale(toL, 1.0f / dist);
+            const float cx = dot(n, wi);
+            const float cl = -dot(nlu, wi);
+            if (!(cx > 0.0f && cl > 0.0f)) continue;
+            const float G = ((cx * cl) * area) / dist2;
+            const int qm = S.quad_mat[qi];
+            c0 = b0 * f0 * S.mat_rgb[qm][0] * G;
+            c1 = b1 * f1 * S.mat_rgb[qm][1] * G;
+            c2 = b2 * f2 * S.mat_rgb[qm][2] * G;
+            o = offset_origin(p, n);
+            dir = wi;
+            tmax = dist * 0.9999f;
+            shadow = true;
+            break;
+          }
+          if (!shadow) {  // all lights done: cosine-weighted bounce
+            light = -1;
+            if (v == S.B) {
+              end_path = true;
+            } else {
+              const float u1 = unit_open(w.z), u2 = unit_open(w.w);
+              const float r = sqrtf(u1);
+              float sn, cs;
+              sincos_turn(u2, &sn, &cs);
+              const float lx2 = r * cs, ly2 = r * sn, lz2 = sqrtf(1.0f - u1);
+              V3 e1, e2;
+              basis(n, &e1, &e2);
+              dir = unit(mk(e1.x * lx2 + e2.x * ly2 + n.x * lz2, e1.y * lx2 + e2.y * ly2 + n.y * lz2,
+                            e1.z * lx2 + e2.z * ly2 + n.z * lz2));
+              o = offset_origin(p, n);
+              tmax = __builtin_huge_valf();
+              b0 = b0 * S.mat_rgb[mat][0];
+              b1 = b1 * S.mat_rgb[mat][1];
+              b2 = b2 * S.mat_rgb[mat][2];
+              specular = false;
+              ++v;
+            }
+          }
+        }
+        if (end_path) {
+          acc0 = acc0 + L0;
+          acc1 = acc1 + L1;
+          acc2 = acc2 + L2;
+          ++s;
+          start = s < spp;
+        }
+        if (s >= spp) break;
       }
-    }
-    if (!end_path && light >= 0) {
-      // next-event estimation at a diffuse vertex: set up the next light whose
-      // sample faces both surfaces, else continue the path
-      shadow = false;
-      const float f0 = S.mat_rgb[mat][0] * kInvPi, f1 = S.mat_rgb[mat][1] * kInvPi,
-                  f2 = S.mat_rgb[mat][2] * kInvPi;
-      for (; light < n_lights; ++light) {
-        if (light < S.n_pl) {
-          const float* lp = S.pl[light];
-          const V3 toL = sub(ld3(lp), p);
-          const float dist2 = dot(toL, toL);
-          const float dist = sqrtf(dist2);
-          const V3 wi = scale(toL, 1.0f / dist);
-          const float cx = dot(n, wi);
-          if (!(cx > 0.0f)) continue;
-          c0 = b0 * f0 * ((lp[3] * cx) / dist2);
-          c1 = b1 * f1 * ((lp[4] * cx) / dist2);
-          c2 = b2 * f2 * ((lp[5] * cx) / dist2);
-          o = offset_origin(p, n);
-          dir = wi;
-          tmax = dist * 0.9999f;
-          shadow = true;
-          break;
+      if (start) {  // camera ray of sample s
+        start = false;
+        if (COUNT) cnt.paths++;
+        float jx = 0.5f, jy = 0.5f;
+        if (!S.pixel_center) {
+          const uint4 wj = path_words(k0, k1, pix, s, pair, tag, 0, 0);
+          jx = unit_open(wj.x);
+          jy = unit_open(wj.y);
         }
-        const int ai = light - S.n_pl;
-        const int qi = S.area_quad[ai];
-        float ua, ub;
-        if (ai == 0) {
-          ua = unit_open(w.x);
-          ub = unit_open(w.y);
-        } else {
-          const uint4 w2 = path_words(k0, k1, pix, s, pair, tag, v + 1, ai);
-          ua = unit_open(w2.x);
-          ub = unit_open(w2.y);
-        }
-        const float* qd = S.quad[qi];
-        const V3 qo = ld3(qd), e1 = ld3(qd + 3), e2 = ld3(qd + 6);
-        const V3 yl = mk(qo.x + e1.x * ua + e2.x * ub, qo.y + e1.y * ua + e2.y * ub,
-                         qo.z + e1.z * ua + e2.z * ub);
-        const V3 nl = cross(e1, e2);
-        const float area = sqrtf(dot(nl, nl));
-        const V3 nlu = scale(nl, 1.0f / area);
-        const V3 toL = sub(yl, p);
-        const float dist2 = dot(toL, toL);
-        const float dist = sqrtf(dist2);
-        const V3 wi = scale(toL, 1.0f / dist);
-        const float cx = dot(n, wi);
-        const float cl = -dot(nlu, wi);
-        if (!(cx > 0.0f && cl > 0.0f)) continue;
-        const float G = ((cx * cl) * area) / dist2;
-        const int qm = S.quad_mat[qi];
-        c0 = b0 * f0 * S.mat_rgb[qm][0] * G;
-        c1 = b1 * f1 * S.mat_rgb[qm][1] * G;
-        c2 = b2 * f2 * S.mat_rgb[qm][2] * G;
-        o = offset_origin(p, n);
-        dir = wi;
-        tmax = dist * 0.9999f;
-        shadow = true;
-        break;
-      }
-      if (!shadow) {  // all lights done: cosine-weighted bounce
+        const float px = (float)x + jx, py = (float)y + jy;
+        const float sx = 2.0f * (px / (float)S.W) - 1.0f;
+        const float sy = 1.0f - 2.0f * (py / (float)S.H);
+        o = ld3(S.eye);
+        dir = unit(mk(S.fwd[0] + S.right[0] * sx + S.up[0] * sy,
+                      S.fwd[1] + S.right[1] * sx + S.up[1] * sy,
+                      S.fwd[2] + S.right[2] * sx + S.up[2] * sy));
+        tmax = __builtin_huge_valf();
+        shadow = false;
+        specular = true;
+        b0 = b1 = b2 = 1.0f;
+        L0 = L1 = L2 = 0.0f;
+        v = 0;
         light = -1;
-        if (v == S.B) {
-          end_path = true;
-        } else {
-          const float u1 = unit_open(w.z), u2 = unit_open(w.w);
-          const float r = sqrtf(u1);
-          float sn, cs;
-          sincos_turn(u2, &sn, &cs);
-          const float lx2 = r * cs, ly2 = r * sn, lz2 = sqrtf(1.0f - u1);
-          V3 e1, e2;
-          basis(n, &e1, &e2);
-          dir = unit(mk(e1.x * lx2 + e2.x * ly2 + n.x * lz2, e1.y * lx2 + e2.y * ly2 + n.y * lz2,
-                        e1.z * lx2 + e2.z * ly2 + n.z * lz2));
-          o = offset_origin(p, n);
-          tmax = __builtin_huge_valf();
-          b0 = b0 * S.mat_rgb[mat][0];
-          b1 = b1 * S.mat_rgb[mat][1];
-          b2 = b2 * S.mat_rgb[mat][2];
-          specular = false;
-          ++v;
-        }
+      }
+      tracing = !begin_trace<COUNT>(S, o, dir, tmax, shadow, tr, stk, cnt);
+      if (!tracing) {
+        answered = true;
+        continue;
       }
     }
-    if (end_path) {
-      acc0 = acc0 + L0;
-      acc1 = acc1 + L1;
-      acc2 = acc2 + L2;
-      ++s;
-      start = s < spp;
-    }
+    if (COUNT && first_active_lane()) cnt.wave_outer_iters++;
+    tracing = !continue_trace<COUNT>(S, nodes, tris, o, dir, tmax, shadow, tr, stk, kBlock,
+                                     PRDPT_TRACE_BUDGET, cnt);
+    answered = !tracing;
   }
 
   float e = 0.0f;

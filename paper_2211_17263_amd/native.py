@@ -337,7 +337,8 @@ def prdpt_ctx_read_timing(ctx):
 
 
 def prdpt_traversal_counts(scene, theta, sigma, N, seed, est):
-    """dict(nodes, tris, rays, paths) of one estimate's render."""
+    """Work counts of one estimate's render: per-lane nodes, tris, rays, paths and
+    wave-level iterations of the node, triangle and ray loops."""
     th, tp = _host(theta, np.float32)
     sg, sp = _host(sigma, np.float32)
     out = np.zeros(7, np.uint64)
