@@ -343,6 +343,7 @@ void write_cache(const char* path, const std::string& key, int bpc, int tpi, dou
       if (!line.empty() && line.find(tag) == std::string::npos) keep.push_back(line);
   }
   std::ostringstream os;
+  os.precision(17);  // the stored time reads back exactly
   os << "{\"key\": \"" << key << "\", \"blocks_per_cu\": " << bpc << ", \"tiles_per_item\": " << tpi
      << ", \"ms\": " << ms << "}";
   keep.push_back(os.str());

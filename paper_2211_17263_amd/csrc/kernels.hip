@@ -461,7 +461,7 @@ constexpr float kInvPi = 0.318309886183790671538f;
 // ---------------------------------------------------------------------------
 constexpr int kTileW = 16, kTileH = 8, kBlock = kTileW * kTileH;  // two 8x8 waves
 #ifndef PRDPT_MIN_WAVES_PER_EU
-#define PRDPT_MIN_WAVES_PER_EU 5
+#define PRDPT_MIN_WAVES_PER_EU 4
 #endif
 
 // Load the scene constants into LDS and apply perturbation k's parameter values.
