@@ -28,7 +28,6 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 NODE_BYTES, TRI_BYTES, REF_BYTES_PER_PIXEL = 64, 48, 12
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_render_loss_cornell.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_2211_17263_amd", "csrc", "kernels.hip")
 
 
@@ -52,12 +51,14 @@ def workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def traffic_from_profile():
-    """Measured HBM bytes per launch, valid only for the kernel source it was taken on."""
-    if not os.path.exists(TRAFFIC_FILE):
+def traffic_from_profile(workload):
+    """Measured HBM bytes per launch of the render kernel on this workload, valid
+    only for the kernel source the counters were taken on."""
+    path = os.path.join(ROOT, "profiles", f"traffic_render_loss_{workload}.txt")
+    if not os.path.exists(path):
         return None
     kv = {}
-    for line in open(TRAFFIC_FILE):
+    for line in open(path):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
@@ -202,7 +203,7 @@ def main():
             "triangle_loop": per["tris"] / max(64 * per["wave_tri_iters"], 1),
             "ray_loop": per["rays"] / max(64 * per["wave_ray_iters"], 1)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_profile()},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_profile(args.workload)},
         "scene_build_s": t_build,
         "final_loss": last["loss"],
     }

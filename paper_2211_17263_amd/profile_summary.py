@@ -75,6 +75,17 @@ def kernel_trace(a):
         out.append(f"| `{name[:70]}` | {r['Calls']} | {float(r['AverageNs']) / 1e6:.3f} | "
                    f"{float(r['MinNs']) / 1e6:.3f} | {float(r['MaxNs']) / 1e6:.3f} | "
                    f"{float(r['Percentage']):.2f} % |")
+    traces = [n for n in os.listdir(path) if n.endswith("kernel_trace.csv")]
+    if traces and a.kernel:
+        rows = [r for r in csv.DictReader(open(os.path.join(path, traces[0])))
+                if a.kernel in r["Kernel_Name"]]
+        if rows:
+            def grid(r):
+                return int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"])
+            g = max(grid(r) for r in rows)
+            ms = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6 for r in rows if grid(r) == g]
+            out += ["", f"`{a.kernel}` dispatches with the largest grid ({g} work-items): {len(ms)}, "
+                    f"mean {statistics.mean(ms):.3f} ms, min {min(ms):.3f} ms, max {max(ms):.3f} ms"]
     out += ["", *a.note]
     open(a.out, "w").write("\n".join(out) + "\n")
     print("\n".join(out))
@@ -98,6 +109,8 @@ def main():
     k.add_argument("--command", action="append", default=[])
     k.add_argument("--note", action="append", default=[])
     k.add_argument("--top", type=int, default=8)
+    k.add_argument("--kernel", default="render_loss_kernel<false>",
+                   help="also summarise this kernel's largest-grid dispatches")
     k.add_argument("--out", required=True)
     a = ap.parse_args()
     traffic(a) if a.mode == "traffic" else kernel_trace(a)
