@@ -231,7 +231,8 @@ __device__ __forceinline__ float safe_inv(float x) {
 //
 // A query is resumable: begin_trace tests the analytic primitives and queues
 // the first instance's root; continue_trace then traverses until the query is
-// answered or the wave has spent `budget` node-loop iterations in this call, so
+// answered, the wave has spent `budget` node-loop iterations in this call, or
+// at least half of the lanes that entered the call have their answer, so
 // lanes whose ray is done can shade and start their next ray while long
 // traversals go on.  The suspended state is the best hit so far, the stack
 // pointer and the instance (Trav); the node being visited is pushed back on the
@@ -256,7 +257,10 @@ __device__ __forceinline__ float safe_inv(float x) {
 #define PRDPT_LEAF_QUORUM 50
 #endif
 #ifndef PRDPT_TRACE_BUDGET
-#define PRDPT_TRACE_BUDGET 16
+#define PRDPT_TRACE_BUDGET 32
+#endif
+#ifndef PRDPT_TRACE_QUORUM
+#define PRDPT_TRACE_QUORUM 50
 #endif
 
 struct Trav {
@@ -326,6 +330,7 @@ __device__ bool continue_trace(const SceneHdr& S, const Node* __restrict__ nodes
   int node = -1;   // inner node being visited, -1: none
   int leaf = 0;    // pending leaf (encoded < 0), 0: none
   int iters = 0;
+  const int entered = __popcll(__ballot(1));
   while (true) {
     // ---- node loop: descend until enough lanes hold a leaf
     while (true) {
@@ -415,7 +420,10 @@ __device__ bool continue_trace(const SceneHdr& S, const Node* __restrict__ nodes
       stack[0] = S.inst_root[inst];
       sp = 1;
     }
-    if (iters >= budget) {  // suspend: the current node goes back on the stack
+    // suspend once the budget is spent or at most PRDPT_TRACE_QUORUM percent of
+    // the lanes that entered are still tracing: the current node goes back on
+    // the stack
+    if (iters >= budget || __popcll(__ballot(1)) * 100 <= entered * PRDPT_TRACE_QUORUM) {
       if (node >= 0) stack[(sp++) * stride] = node;
       tr.sp = sp;
       tr.inst = inst;
