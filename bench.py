@@ -27,7 +27,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-NODE_BYTES, TRI_BYTES, REF_BYTES_PER_PIXEL = 64, 48, 12
+NODE_BYTES, TRI_BYTES, REF_BYTES_PER_PIXEL = 128, 48, 12
 KERNEL_SRC = os.path.join(ROOT, "paper_2211_17263_amd", "csrc", "kernels.hip")
 
 

@@ -65,7 +65,8 @@ hipError_t timed_render(prdpt_ctx* ctx, const DevScene& sc, int W, int H, const 
       if (e != hipSuccess) return e;
     }
   }
-  hipError_t e = launch_render(ctx->stream, sc, W, H, X, nk, d, tag, seed, ref, img, partial, nullptr);
+  hipError_t e = launch_render(ctx->stream, sc, W, H, X, nk, d, tag, seed, ref, img, partial, nullptr,
+                               ctx->work.p);
   if (e != hipSuccess) return e;
   if (a && b) {
     e = hipEventRecord(b, ctx->stream);
@@ -109,6 +110,7 @@ int prepare(prdpt_ctx* ctx, int N, int d, int n_tiles) {
   if ((rc = ensure(ctx, ctx->loss, 1))) return rc;
   if ((rc = ensure(ctx, ctx->theta, (size_t)d))) return rc;
   if ((rc = ensure(ctx, ctx->sigma, (size_t)d))) return rc;
+  if ((rc = ensure(ctx, ctx->work, 1))) return rc;
   return PRDPT_OK;
 }
 
@@ -175,7 +177,7 @@ int prdpt_ctx_destroy(prdpt_ctx* ctx) {
   hipSetDevice(ctx->device);
   hipStreamSynchronize(ctx->stream);
   void* bufs[] = {ctx->X.p, ctx->tau.p, ctx->partial.p, ctx->theta.p, ctx->sigma.p,
-                  ctx->c.p, ctx->losses.p, ctx->grad.p, ctx->loss.p, ctx->counters.p};
+                  ctx->c.p, ctx->losses.p, ctx->grad.p, ctx->loss.p, ctx->counters.p, ctx->work.p};
   for (void* b : bufs)
     if (b) hipFree(b);
   for (auto& pr : ctx->pending) {
@@ -345,7 +347,7 @@ int prdpt::build_host_scene(const prdpt_scene_desc* D, HostScene& hs) {
   if (nodes.size() >= (1u << 24)) {
     return fail(PRDPT_E_SCENE, "too many BVH nodes (at most 2^24)");
   }
-  if (hs.bvh_depth > kMaxInnerDepth) {
+  if (hs.bvh_depth > kMaxDepth4) {
     return fail(PRDPT_E_SCENE, "BVH deeper than the traversal stack");
   }
   hs.footprint = sizeof(SceneHdr) + nodes.size() * sizeof(Node) + tris.size() * sizeof(Tri);
@@ -475,7 +477,7 @@ int prdpt_render_perturbed(prdpt_scene* s, const float* theta, const float* sigm
   HIP_TRY(launch_tau(ctx->stream, est, d, P, seed, ctx->sigma.p, ctx->theta.p, chi_mean(d),
                      std::sqrt(2.0 * M_PI), ctx->tau.p, ctx->c.p, ctx->X.p));
   HIP_TRY(launch_render(ctx->stream, s->dev(), h.W, h.H, ctx->X.p, N, d, kTagPath, seed, nullptr,
-                        images_out, nullptr, nullptr));
+                        images_out, nullptr, nullptr, ctx->work.p));
   if (tau_out)
     HIP_TRY(hipMemcpyAsync(tau_out, ctx->tau.p, sizeof(float) * P * d, hipMemcpyDeviceToHost, ctx->stream));
   HIP_TRY(hipStreamSynchronize(ctx->stream));
@@ -492,7 +494,7 @@ int prdpt_render_reference(prdpt_scene* s, const float* X, uint64_t seed, float*
   if (int rc = prepare(ctx, 2, d, render_tiles(h.W, h.H))) return rc;
   HIP_TRY(hipMemcpyAsync(ctx->X.p, X, sizeof(float) * d, hipMemcpyHostToDevice, ctx->stream));
   HIP_TRY(launch_render(ctx->stream, s->dev(), h.W, h.H, ctx->X.p, 1, d, kTagRef, seed, nullptr,
-                        image_out, nullptr, nullptr));
+                        image_out, nullptr, nullptr, ctx->work.p));
   HIP_TRY(hipStreamSynchronize(ctx->stream));
   return PRDPT_OK;
 }
@@ -609,7 +611,7 @@ int prdpt_traversal_counts(prdpt_scene* s, const float* theta, const float* sigm
   HIP_TRY(launch_tau(ctx->stream, est, d, P, seed, ctx->sigma.p, ctx->theta.p, chi_mean(d),
                      std::sqrt(2.0 * M_PI), ctx->tau.p, ctx->c.p, ctx->X.p));
   HIP_TRY(launch_render(ctx->stream, s->dev(), h.W, h.H, ctx->X.p, N, d, kTagPath, seed, nullptr,
-                        nullptr, nullptr, ctx->counters.p));
+                        nullptr, nullptr, ctx->counters.p, ctx->work.p));
   unsigned long long host[7];
   HIP_TRY(hipMemcpyAsync(host, ctx->counters.p, sizeof(host), hipMemcpyDeviceToHost, ctx->stream));
   HIP_TRY(hipStreamSynchronize(ctx->stream));

@@ -1,11 +1,13 @@
 // Host BVH builder: surface-area heuristic (16 bins per axis, an exact sweep
 // over sorted centroids for small ranges), leaves of at most 4 triangles, a
 // range of at most 4 kept as a leaf only when no split is cheaper under the
-// SAH, and inner-node depth bounded by kMaxInnerDepth so a fixed traversal
-// stack always suffices: a split is admissible only if both children still fit
-// a balanced subtree in the depth that remains (else object median).
-// Output is appended to flat node/triangle arrays in the 64-byte / 48-byte
-// layouts the kernels read with 16-byte loads.
+// SAH, and inner-node depth bounded by kMaxInnerDepth: a split is admissible
+// only if both children still fit a balanced subtree in the depth that remains
+// (else object median).  The binary tree is then collapsed into the 4-wide
+// device layout (each node takes its grandchildren, or a child that is a leaf,
+// as its up to four children), so the device depth is at most kMaxDepth4 and
+// the traversal stack bound holds.  Output is appended to flat node/triangle
+// arrays in the 128-byte / 48-byte layouts the kernels read with 16-byte loads.
 #include <algorithm>
 #include <cfloat>
 #include <cmath>
@@ -40,6 +42,13 @@ struct Box {
   }
 };
 
+// binary node of the build (host only): both children's padded boxes, child
+// index and leaf count (cnt > 0: idx is the first of cnt triangles)
+struct Node2 {
+  float lo[2][3], hi[2][3];
+  int32_t idx[2], cnt[2];
+};
+
 struct Prim {
   Box box;
   float c[3];
@@ -71,7 +80,7 @@ struct Builder {
   const float* tri9;
   const int32_t* tri_mat;
   int32_t id_base;
-  std::vector<Node>* nodes;
+  std::vector<Node2>* nodes;
   std::vector<Tri>* tris;
   std::vector<Prim> prims;
   int max_depth = 0;
@@ -238,7 +247,7 @@ struct Builder {
                        });
     }
     int ni = (int)nodes->size();
-    nodes->push_back(Node{});
+    nodes->push_back(Node2{});
     Box lb = range_box(begin, mid), rb = range_box(mid, end);
     int32_t i0, c0, i1, c1;
     build(begin, mid, depth + 1, &i0, &c0);
@@ -246,27 +255,79 @@ struct Builder {
     float llo[3], lhi[3], rlo[3], rhi[3];
     padded(lb, llo, lhi);
     padded(rb, rlo, rhi);
-    Node& nd = (*nodes)[ni];
-    nd.c0lox = llo[0]; nd.c0hix = lhi[0]; nd.c0loy = llo[1]; nd.c0hiy = lhi[1];
-    nd.c1lox = rlo[0]; nd.c1hix = rhi[0]; nd.c1loy = rlo[1]; nd.c1hiy = rhi[1];
-    nd.c0loz = llo[2]; nd.c0hiz = lhi[2]; nd.c1loz = rlo[2]; nd.c1hiz = rhi[2];
-    nd.idx0 = i0; nd.cnt0 = c0; nd.idx1 = i1; nd.cnt1 = c1;
+    Node2& nd = (*nodes)[ni];
+    for (int a = 0; a < 3; ++a) {
+      nd.lo[0][a] = llo[a];
+      nd.hi[0][a] = lhi[a];
+      nd.lo[1][a] = rlo[a];
+      nd.hi[1][a] = rhi[a];
+    }
+    nd.idx[0] = i0; nd.cnt[0] = c0; nd.idx[1] = i1; nd.cnt[1] = c1;
     *idx = ni;
     *cnt = 0;
   }
 };
 
+// Appends the 4-wide node for binary inner node i (and, depth first, its
+// subtree) to out; returns its index.
+int32_t collapse(const std::vector<Node2>& n2, int i, std::vector<Node>& out) {
+  struct Child {
+    const float* lo;
+    const float* hi;
+    int32_t idx, cnt;  // cnt > 0: leaf; cnt == 0: binary inner node idx
+  };
+  Child ch[4];
+  int nc = 0;
+  const Node2& b = n2[i];
+  for (int s = 0; s < 2; ++s) {
+    if (b.idx[s] < 0) continue;  // the missing second child of a wrapped leaf
+    if (b.cnt[s] > 0) {
+      ch[nc++] = Child{b.lo[s], b.hi[s], b.idx[s], b.cnt[s]};
+    } else {
+      const Node2& g = n2[b.idx[s]];
+      for (int t = 0; t < 2; ++t)
+        if (g.idx[t] >= 0) ch[nc++] = Child{g.lo[t], g.hi[t], g.idx[t], g.cnt[t]};
+    }
+  }
+  const int32_t me = (int32_t)out.size();
+  out.push_back(Node{});
+  int32_t ref[4];
+  for (int c = 0; c < 4; ++c) {
+    if (c >= nc) {
+      ref[c] = kEmptyChild;
+    } else if (ch[c].cnt > 0) {
+      ref[c] = ~((ch[c].idx << 3) | (ch[c].cnt - 1));
+    } else {
+      ref[c] = collapse(n2, ch[c].idx, out);
+    }
+  }
+  Node& nd = out[me];
+  for (int c = 0; c < 4; ++c) {
+    const bool use = c < nc;
+    nd.lox[c] = use ? ch[c].lo[0] : 0.0f;
+    nd.loy[c] = use ? ch[c].lo[1] : 0.0f;
+    nd.loz[c] = use ? ch[c].lo[2] : 0.0f;
+    nd.hix[c] = use ? ch[c].hi[0] : 0.0f;
+    nd.hiy[c] = use ? ch[c].hi[1] : 0.0f;
+    nd.hiz[c] = use ? ch[c].hi[2] : 0.0f;
+    nd.ref[c] = ref[c];
+    nd.pad[c] = 0;
+  }
+  return me;
+}
+
 }  // namespace
 
 // Builds one instance BVH over triangles `list[0..n)` (indices into tri9).
-// The root is always an inner node; a missing second child has idx = -1.
+// The root is always an inner node; depth is that of the 4-wide tree.
 BvhOut build_bvh(const float* tri9, const int32_t* tri_mat, const int32_t* list, int n,
                  int32_t id_base, std::vector<Node>& nodes, std::vector<Tri>& tris) {
+  std::vector<Node2> n2;
   Builder b;
   b.tri9 = tri9;
   b.tri_mat = tri_mat;
   b.id_base = id_base;
-  b.nodes = &nodes;
+  b.nodes = &n2;
   b.tris = &tris;
   b.prims.resize(n);
   for (int i = 0; i < n; ++i) {
@@ -284,21 +345,21 @@ BvhOut build_bvh(const float* tri9, const int32_t* tri_mat, const int32_t* list,
   if ((long long)n > capacity(1)) return BvhOut{-2, 0};
   b.build(0, n, 1, &idx, &cnt);
   if (cnt > 0) {  // a single leaf: wrap it in a root with one child
-    int ni = (int)nodes.size();
-    Node nd{};
+    int ni = (int)n2.size();
+    Node2 nd{};
     float lo[3], hi[3];
     Builder::padded(b.range_box(0, n), lo, hi);
-    nd.c0lox = lo[0]; nd.c0hix = hi[0]; nd.c0loy = lo[1]; nd.c0hiy = hi[1];
-    nd.c0loz = lo[2]; nd.c0hiz = hi[2];
-    nd.c1lox = nd.c1loy = nd.c1loz = 1.0f;
-    nd.c1hix = nd.c1hiy = nd.c1hiz = -1.0f;
-    nd.idx0 = idx; nd.cnt0 = cnt; nd.idx1 = -1; nd.cnt1 = 0;
-    nodes.push_back(nd);
+    for (int a = 0; a < 3; ++a) {
+      nd.lo[0][a] = lo[a];
+      nd.hi[0][a] = hi[a];
+    }
+    nd.idx[0] = idx; nd.cnt[0] = cnt; nd.idx[1] = -1; nd.cnt[1] = 0;
+    n2.push_back(nd);
     idx = ni;
     b.max_depth = 1;
   }
-  out.root = idx;
-  out.depth = b.max_depth;
+  out.root = collapse(n2, idx, nodes);
+  out.depth = (b.max_depth + 1) / 2;
   return out;
 }
 

@@ -18,7 +18,7 @@ hipError_t launch_tau(hipStream_t st, int est, int d, int P, uint64_t seed, cons
                       const float* theta, double cd, double sqrt2pi, float* tau, double* c, float* X);
 hipError_t launch_render(hipStream_t st, const DevScene& sc, int W, int H, const float* X, int nk,
                          int d, int tag, uint64_t seed, const float* ref, float* img,
-                         float* partial, unsigned long long* counters);
+                         float* partial, unsigned long long* counters, int* work);
 hipError_t launch_losses(hipStream_t st, const float* partial, int n_tiles, int N, int npix,
                          double* losses);
 hipError_t launch_combine(hipStream_t st, int P, int d, const double* c, const double* L,
@@ -104,6 +104,7 @@ struct prdpt_ctx {
   prdpt::DevBuf<float> X, tau, partial, theta, sigma;
   prdpt::DevBuf<double> c, losses, grad, loss;
   prdpt::DevBuf<unsigned long long> counters;
+  prdpt::DevBuf<int> work;  // work counter of the persistent render kernel
   // optional timing of the fused render kernel (events on the context stream)
   bool timing = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;

@@ -11,6 +11,7 @@
 // bit on any IEEE-754 machine; only the pixel/loss sums differ in rounding.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstddef>
 #include <cstdint>
 
@@ -263,6 +264,41 @@ __device__ __forceinline__ float safe_inv(float x) {
 #define PRDPT_TRACE_QUORUM 50
 #endif
 
+// Per-lane traversal stack: entries [0, kStackEntries) in LDS (stride = the
+// work-group size), deeper ones in the lane's private overflow array.
+__device__ __forceinline__ void push(int* __restrict__ lds, int stride, int* __restrict__ ovf,
+                                     int& sp, int e) {
+  if (sp < kStackEntries) {
+    lds[sp * stride] = e;
+  } else {
+    ovf[sp - kStackEntries] = e;
+  }
+  ++sp;
+}
+
+__device__ __forceinline__ int pop(const int* __restrict__ lds, int stride,
+                                   const int* __restrict__ ovf, int& sp) {
+  --sp;
+  // the LDS read is always in bounds; the private entry replaces it when the
+  // top lies beyond the LDS part
+  int e = lds[min(sp, kStackEntries - 1) * stride];
+  // (volatile: keeps this a private-memory load of its own rather than one
+  // generic load whose address selects between LDS and private memory)
+  if (sp >= kStackEntries) e = *(const volatile int*)&ovf[sp - kStackEntries];
+  return e;
+}
+
+// orders two (distance, reference) pairs by distance
+__device__ __forceinline__ void order2(float& ta, int& ra, float& tb, int& rb) {
+  const bool sw = tb < ta;
+  const float t = sw ? tb : ta;
+  const int r = sw ? rb : ra;
+  tb = sw ? ta : tb;
+  rb = sw ? ra : rb;
+  ta = t;
+  ra = r;
+}
+
 struct Trav {
   Hit h;
   int sp;    // stack entries in use
@@ -318,8 +354,8 @@ __device__ __forceinline__ bool begin_trace(const SceneHdr& S, V3 o, V3 d, float
 template <bool COUNT>
 __device__ bool continue_trace(const SceneHdr& S, const Node* __restrict__ nodes,
                                const Tri* __restrict__ tris, V3 o, V3 d, float tmax, bool any,
-                               Trav& tr, int* __restrict__ stack, int stride, int budget,
-                               Counters& cnt) {
+                               Trav& tr, int* __restrict__ stack, int stride,
+                               int* __restrict__ ovf, int budget, Counters& cnt) {
   Hit& h = tr.h;
   int sp = tr.sp;
   int inst = tr.inst;
@@ -336,8 +372,7 @@ __device__ bool continue_trace(const SceneHdr& S, const Node* __restrict__ nodes
     while (true) {
       if (node < 0 && leaf == 0) {
         if (sp > 0) {
-          --sp;
-          const int e = stack[sp * stride];
+          const int e = pop(stack, stride, ovf, sp);
           if (e < 0) leaf = e;
           else node = e;
         }
@@ -350,42 +385,69 @@ __device__ bool continue_trace(const SceneHdr& S, const Node* __restrict__ nodes
       ++iters;
       if (node >= 0) {
         const float4* np = reinterpret_cast<const float4*>(nodes + node);
-        const float4 a = np[0], b = np[1], c = np[2];
-        const int4 ix = reinterpret_cast<const int4*>(np)[3];
+        const float4 lx = np[0], hx = np[1], ly = np[2], hy = np[3], lz = np[4], hz = np[5];
+        const int4 rf = reinterpret_cast<const int4*>(np)[6];
         if (COUNT) {
           cnt.nodes++;
           if (first_active_lane()) cnt.wave_node_iters++;
         }
         const float tcull = any ? tmax : fminf(tmax, h.t);
-        const float t0 = slab(a.x, a.y, a.z, a.w, c.x, c.y, inv, oi, tcull);
-        const float t1s = slab(b.x, b.y, b.z, b.w, c.z, c.w, inv, oi, tcull);
-        const float t1 = ix.y >= 0 ? t1s : __builtin_huge_valf();
-        const bool h0 = t0 < __builtin_huge_valf(), h1 = t1 < __builtin_huge_valf();
-        const bool l0 = ix.z > 0, l1 = ix.w > 0;
-        const int e0 = l0 ? ~((ix.x << 3) | (ix.z - 1)) : ix.x;
-        const int e1 = l1 ? ~((ix.y << 3) | (ix.w - 1)) : ix.y;
-        // leaf children: the first becomes the pending leaf if none is, the
-        // rest go on the stack
-        if (h0 && l0) {
-          if (leaf == 0) leaf = e0;
-          else stack[(sp++) * stride] = e0;
+        const float inf = __builtin_huge_valf();
+        float t0 = slab(lx.x, hx.x, ly.x, hy.x, lz.x, hz.x, inv, oi, tcull);
+        float t1 = slab(lx.y, hx.y, ly.y, hy.y, lz.y, hz.y, inv, oi, tcull);
+        float t2 = slab(lx.z, hx.z, ly.z, hy.z, lz.z, hz.z, inv, oi, tcull);
+        float t3 = slab(lx.w, hx.w, ly.w, hy.w, lz.w, hz.w, inv, oi, tcull);
+        int r0 = rf.x, r1 = rf.y, r2 = rf.z, r3 = rf.w;
+        t0 = r0 != kEmptyChild ? t0 : inf;
+        t1 = r1 != kEmptyChild ? t1 : inf;
+        t2 = r2 != kEmptyChild ? t2 : inf;
+        t3 = r3 != kEmptyChild ? t3 : inf;
+        // nearest first (misses last)
+        order2(t0, r0, t1, r1);
+        order2(t2, r2, t3, r3);
+        order2(t0, r0, t2, r2);
+        order2(t1, r1, t3, r3);
+        order2(t1, r1, t2, r2);
+        // far to near: the nearest inner child is visited next and the nearest
+        // leaf becomes the pending leaf if none is; the others are pushed so
+        // that nearer ones are popped first
+        int next = -1, near_leaf = 0;
+        if (t3 < inf) {
+          if (r3 >= 0) next = r3;
+          else near_leaf = r3;
         }
-        if (h1 && l1) {
-          if (leaf == 0) leaf = e1;
-          else stack[(sp++) * stride] = e1;
+        if (t2 < inf) {
+          if (r2 >= 0) {
+            if (next >= 0) push(stack, stride, ovf, sp, next);
+            next = r2;
+          } else {
+            if (near_leaf != 0) push(stack, stride, ovf, sp, near_leaf);
+            near_leaf = r2;
+          }
         }
-        const bool i0 = h0 && !l0, i1 = h1 && !l1;
-        if (i0 && i1) {
-          const bool first0 = t0 <= t1;
-          stack[(sp++) * stride] = first0 ? e1 : e0;
-          node = first0 ? e0 : e1;
-        } else if (i0) {
-          node = e0;
-        } else if (i1) {
-          node = e1;
-        } else {
-          node = -1;
+        if (t1 < inf) {
+          if (r1 >= 0) {
+            if (next >= 0) push(stack, stride, ovf, sp, next);
+            next = r1;
+          } else {
+            if (near_leaf != 0) push(stack, stride, ovf, sp, near_leaf);
+            near_leaf = r1;
+          }
         }
+        if (t0 < inf) {
+          if (r0 >= 0) {
+            if (next >= 0) push(stack, stride, ovf, sp, next);
+            next = r0;
+          } else {
+            if (near_leaf != 0) push(stack, stride, ovf, sp, near_leaf);
+            near_leaf = r0;
+          }
+        }
+        if (near_leaf != 0) {
+          if (leaf == 0) leaf = near_leaf;
+          else push(stack, stride, ovf, sp, near_leaf);
+        }
+        node = next;
       }
     }
     // ---- leaf loop: the pending leaves together
@@ -424,7 +486,7 @@ __device__ bool continue_trace(const SceneHdr& S, const Node* __restrict__ nodes
     // the lanes that entered are still tracing: the current node goes back on
     // the stack
     if (iters >= budget || __popcll(__ballot(1)) * 100 <= entered * PRDPT_TRACE_QUORUM) {
-      if (node >= 0) stack[(sp++) * stride] = node;
+      if (node >= 0) push(stack, stride, ovf, sp, node);
       tr.sp = sp;
       tr.inst = inst;
       return false;
@@ -524,6 +586,7 @@ __device__ __forceinline__ void render_tile(const SceneHdr& S, const Node* __res
   const int spp = S.spp;
   const int n_lights = S.n_pl + S.n_area;
   int* stk = stack + t;
+  int ovf[kStackOverflow];  // stack entries beyond the LDS part (deep descents only)
   Counters cnt{0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
 
   float acc0 = 0.0f, acc1 = 0.0f, acc2 = 0.0f;
@@ -747,7 +810,7 @@ __device__ __forceinline__ void render_tile(const SceneHdr& S, const Node* __res
       }
     }
     if (COUNT && first_active_lane()) cnt.wave_outer_iters++;
-    tracing = !continue_trace<COUNT>(S, nodes, tris, o, dir, tmax, shadow, tr, stk, kBlock,
+    tracing = !continue_trace<COUNT>(S, nodes, tris, o, dir, tmax, shadow, tr, stk, kBlock, ovf,
                                      PRDPT_TRACE_BUDGET, cnt);
     answered = !tracing;
   }
@@ -793,20 +856,42 @@ __device__ __forceinline__ void render_tile(const SceneHdr& S, const Node* __res
 }
 
 
-// Single-request launch: grid.x = pixel tiles, grid.y = perturbation k.
+// Single-request launch, persistent: a grid of at most the resident work-group
+// count whose work-groups take (perturbation k, tile) items in order from the
+// counter *work (zeroed by reset_work_kernel before the launch) until all
+// n_tiles * nk items are done.  Dynamic assignment keeps every CU busy when
+// tiles differ widely in cost, where a one-work-group-per-tile grid leaves
+// CUs idle waiting on the hardware dispatcher.
 template <bool COUNT>
 __global__ __launch_bounds__(kBlock, PRDPT_MIN_WAVES_PER_EU) void render_loss_kernel(
     DevScene scene, const float* __restrict__ X, int d, int tag, uint32_t k0, uint32_t k1,
     const float* __restrict__ ref, float* __restrict__ img, float* __restrict__ partial,
-    unsigned long long* __restrict__ counters) {
+    unsigned long long* __restrict__ counters, int n_tiles, int n_items, int* __restrict__ work) {
   __shared__ SceneHdr S;
   __shared__ int stack[kStackEntries * kBlock];
   __shared__ float wsum[kBlock / 64];
-  const int k = blockIdx.y;
-  load_state(S, scene.hdr, X + (size_t)k * d, d);
-  render_tile<COUNT>(S, scene.nodes, scene.tris, k, blockIdx.x, tag, k0, k1, ref, img,
-                     partial ? partial + (size_t)k * gridDim.x + blockIdx.x : nullptr, counters,
-                     stack, wsum);
+  __shared__ int s_item;
+  int cur = -1;
+  while (true) {
+    if (threadIdx.x == 0) s_item = atomicAdd(work, 1);
+    __syncthreads();
+    const int it = s_item;
+    __syncthreads();
+    if (it >= n_items) break;
+    const int k = it / n_tiles, tile = it - k * n_tiles;
+    if (k != cur) {  // the scene state of perturbation k (after the previous tile's last use)
+      load_state(S, scene.hdr, X + (size_t)k * d, d);
+      cur = k;
+    }
+    render_tile<COUNT>(S, scene.nodes, scene.tris, k, tile, tag, k0, k1, ref, img,
+                       partial ? partial + (size_t)k * n_tiles + tile : nullptr, counters, stack,
+                       wsum);
+    __syncthreads();
+  }
+}
+
+__global__ void reset_work_kernel(int* __restrict__ work) {
+  if (threadIdx.x == 0) work[0] = 0;
 }
 
 // Perturbation draw for pair p (Sec. 3.2): Philox TAU stream words in order,
@@ -1068,16 +1153,38 @@ hipError_t launch_tau(hipStream_t st, int est, int d, int P, uint64_t seed, cons
   return hipGetLastError();
 }
 
+// resident work-groups of the render kernel on the current device (cached)
+int render_grid_limit() {
+  static int cached[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+  if (cached[dev] > 0) return cached[dev];
+  int n_cu = 0, per_cu = 0;
+  if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, render_loss_kernel<false>, kBlock, 0) !=
+      hipSuccess)
+    return 0;
+  cached[dev] = std::max(1, n_cu * std::max(1, per_cu));
+  return cached[dev];
+}
+
 hipError_t launch_render(hipStream_t st, const DevScene& sc, int W, int H, const float* X, int nk,
                          int d, int tag, uint64_t seed, const float* ref, float* img,
-                         float* partial, unsigned long long* counters) {
-  dim3 grid(render_tiles(W, H), nk);
+                         float* partial, unsigned long long* counters, int* work) {
+  const int n_tiles = render_tiles(W, H);
+  const int n_items = n_tiles * nk;
+  const int limit = render_grid_limit();
+  if (limit <= 0) return hipErrorInvalidDevice;
+  const int blocks = std::min(n_items, limit);
+  hipLaunchKernelGGL(reset_work_kernel, dim3(1), dim3(64), 0, st, work);
   if (counters)
-    hipLaunchKernelGGL(render_loss_kernel<true>, grid, dim3(kBlock), 0, st, sc, X, d, tag,
-                       (uint32_t)seed, (uint32_t)(seed >> 32), ref, img, partial, counters);
+    hipLaunchKernelGGL(render_loss_kernel<true>, dim3(blocks), dim3(kBlock), 0, st, sc, X, d, tag,
+                       (uint32_t)seed, (uint32_t)(seed >> 32), ref, img, partial, counters,
+                       n_tiles, n_items, work);
   else
-    hipLaunchKernelGGL(render_loss_kernel<false>, grid, dim3(kBlock), 0, st, sc, X, d, tag,
-                       (uint32_t)seed, (uint32_t)(seed >> 32), ref, img, partial, counters);
+    hipLaunchKernelGGL(render_loss_kernel<false>, dim3(blocks), dim3(kBlock), 0, st, sc, X, d, tag,
+                       (uint32_t)seed, (uint32_t)(seed >> 32), ref, img, partial, counters,
+                       n_tiles, n_items, work);
   return hipGetLastError();
 }
 

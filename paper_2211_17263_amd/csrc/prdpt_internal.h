@@ -9,23 +9,33 @@ namespace prdpt {
 constexpr int kTagTau = 1;
 constexpr int kTagPath = 2;
 constexpr int kTagRef = 3;
-constexpr int kMaxInnerDepth = 25;               // BVH inner-node depth bound (root = 1)
-// Traversal stack entries per ray: each inner node on the current path keeps at
-// most one child on the stack, and the last one visited at most two (both
-// children leaves while a leaf is already pending), so depth + 1 suffice.
-constexpr int kStackEntries = kMaxInnerDepth + 1;
+constexpr int kMaxInnerDepth = 25;  // depth bound of the binary tree the builder makes (root = 1)
+// The device BVH is 4-wide: each node opens two levels of the binary tree, so
+// its depth is at most (kMaxInnerDepth + 1) / 2.
+constexpr int kMaxDepth4 = (kMaxInnerDepth + 1) / 2;
+// Traversal stack entries per ray: every node on the current path keeps at
+// most three of its children on the stack and the last one visited at most
+// four (all four children leaves while a leaf is already pending); a suspended
+// node adds one entry for itself.  kStackEntries live in LDS, the rest in a
+// small per-lane private array that only unusually deep descents reach.
+constexpr int kStackBound = 3 * kMaxDepth4 + 1;
+constexpr int kStackEntries = 26;
+constexpr int kStackOverflow = kStackBound - kStackEntries;
+// child reference of an empty slot of a 4-wide node
+constexpr int32_t kEmptyChild = INT32_MIN;
 
-// Flattened BVH node: both children's boxes live in the parent (64 bytes, four
-// 16-byte loads).  cnt == 0: idx is an inner node; cnt > 0: idx is the first of
-// cnt triangles.  Boxes are padded outward so the binary32 slab test is
-// conservative for every binary32 triangle hit inside them.
+// Flattened 4-wide BVH node (128 bytes, seven 16-byte loads): the padded boxes
+// of its children as six 4-vectors (one per box face coordinate) and the child
+// references.  A reference >= 0 is an inner node, < 0 a leaf of triangles
+// encoded as ~(first << 3 | (count - 1)), kEmptyChild an unused slot.  Boxes
+// are padded outward so the binary32 slab test is conservative for every
+// binary32 triangle hit inside them.
 struct alignas(16) Node {
-  float c0lox, c0hix, c0loy, c0hiy;
-  float c1lox, c1hix, c1loy, c1hiy;
-  float c0loz, c0hiz, c1loz, c1hiz;
-  int32_t idx0, idx1, cnt0, cnt1;
+  float lox[4], hix[4], loy[4], hiy[4], loz[4], hiz[4];
+  int32_t ref[4];
+  int32_t pad[4];
 };
-static_assert(sizeof(Node) == 64, "node layout");
+static_assert(sizeof(Node) == 128, "node layout");
 
 // Triangle: v0, e1 = v1 - v0, e2 = v2 - v0 (binary32, computed on the host),
 // global primitive id and material (48 bytes, three 16-byte loads).
