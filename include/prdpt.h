@@ -253,7 +253,7 @@ int prdpt_batch_estimate(prdpt_ctx* ctx, prdpt_request* reqs, int n);
 
 /*
  * Launch configuration of the batched form: persistent work-groups per compute
- * unit, pixel tiles (16x8) per work item, and whether to replay a captured
+ * unit, pixel tiles (8x8) per work item, and whether to replay a captured
  * graph (1) or launch the kernels directly (0).
  */
 int prdpt_batch_config(prdpt_ctx* ctx, int blocks_per_cu, int tiles_per_item, int use_graph);

@@ -395,7 +395,7 @@ int prdpt_batch_autotune(prdpt_ctx* ctx, prdpt_request* reqs, int n, const char*
   int bpc = 0, tpi = 0;
   double ms = 0.0;
   if (!read_cache(cache_path, key, &bpc, &tpi, &ms)) {
-    const int cand_bpc[] = {2, 4, 6, 8, 10, 12};
+    const int cand_bpc[] = {4, 8, 12, 16, 20, 24};
     const int cand_tpi[] = {1, 2, 4};
     double best = 1e300;
     for (int cb : cand_bpc)

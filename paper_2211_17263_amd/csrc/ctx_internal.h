@@ -50,7 +50,7 @@ struct BatchState {
   hipStream_t stream = nullptr;  // own non-blocking stream (capturable)
   hipEvent_t ready = nullptr;    // orders the batch stream after the context stream
   int n_cu = 0;
-  int blocks_per_cu = 8, tiles_per_item = 1, use_graph = 1;
+  int blocks_per_cu = 16, tiles_per_item = 1, use_graph = 1;
   size_t cap_req = 0, cap_pairs = 0, cap_rows = 0, cap_partial = 0;
   BatchReq* d_reqs = nullptr;
   BatchMeta* d_meta = nullptr;

@@ -531,7 +531,7 @@ constexpr float kInvPi = 0.318309886183790671538f;
 // ---------------------------------------------------------------------------
 // kernels
 // ---------------------------------------------------------------------------
-constexpr int kTileW = 16, kTileH = 8, kBlock = kTileW * kTileH;  // two 8x8 waves
+constexpr int kTileW = 8, kTileH = 8, kBlock = kTileW * kTileH;  // one wave per 8x8 tile
 #ifndef PRDPT_MIN_WAVES_PER_EU
 #define PRDPT_MIN_WAVES_PER_EU 4
 #endif
@@ -557,7 +557,7 @@ __device__ __forceinline__ void load_state(SceneHdr& S, const SceneHdr* __restri
   __syncthreads();
 }
 
-// Render one 16x8 pixel tile of perturbation k (S already holds the
+// Render one 8x8 pixel tile of perturbation k (S already holds the
 // perturbation's scene state in LDS).  Writes *partial_slot = sum over the
 // tile's pixels of sum_c (I - R)^2 when it is not null (ref must then be set),
 // and the tile's pixels into img (image k) when img != nullptr.
