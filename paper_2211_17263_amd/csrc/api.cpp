@@ -54,8 +54,10 @@ hipEvent_t take_event(prdpt_ctx* ctx) {
 }
 
 // launch the fused render kernel, bracketed by timing events when enabled
-hipError_t timed_render(prdpt_ctx* ctx, const DevScene& sc, int W, int H, const float* X, int nk,
-                        int d, int tag, uint64_t seed, const float* ref, float* img, float* partial) {
+hipError_t timed_render(prdpt_ctx* ctx, const prdpt_scene* s, const float* X, int nk, int d, int tag,
+                        uint64_t seed, const float* ref, float* img, float* partial) {
+  const DevScene sc = s->dev();
+  const int W = s->hdr.W, H = s->hdr.H;
   hipEvent_t a = nullptr, b = nullptr;
   if (ctx->timing) {
     a = take_event(ctx);
@@ -66,14 +68,15 @@ hipError_t timed_render(prdpt_ctx* ctx, const DevScene& sc, int W, int H, const 
     }
   }
   hipError_t e = launch_render(ctx->stream, sc, W, H, X, nk, d, tag, seed, ref, img, partial, nullptr,
-                               ctx->work.p);
+                               ctx->work.p, s->d_tile_order, s->d_tile_cost);
   if (e != hipSuccess) return e;
   if (a && b) {
     e = hipEventRecord(b, ctx->stream);
     if (e != hipSuccess) return e;
     ctx->pending.emplace_back(a, b);
   }
-  return hipSuccess;
+  // the next render of this scene takes its costliest tiles first
+  return launch_tile_order(ctx->stream, s->d_tile_cost, s->d_tile_order, s->n_tiles);
 }
 
 int check_request(const prdpt_scene* s, const float* theta, const float* sigma, int N,
@@ -128,8 +131,7 @@ int enqueue_estimate(prdpt_scene* s, const float* ref, const float* theta_dev,
   double* L = losses_dev ? losses_dev : ctx->losses.p;
   HIP_TRY(launch_tau(ctx->stream, est, d, P, seed, sigma_dev, theta_dev, chi_mean(d),
                      std::sqrt(2.0 * M_PI), ctx->tau.p, c, ctx->X.p));
-  HIP_TRY(timed_render(ctx, s->dev(), h.W, h.H, ctx->X.p, N, d, kTagPath, seed, ref, nullptr,
-                       ctx->partial.p));
+  HIP_TRY(timed_render(ctx, s, ctx->X.p, N, d, kTagPath, seed, ref, nullptr, ctx->partial.p));
   HIP_TRY(launch_losses(ctx->stream, ctx->partial.p, n_tiles, N, h.W * h.H, L));
   HIP_TRY(launch_combine(ctx->stream, P, d, c, L, nullptr, grad_dev, loss_dev));
   return PRDPT_OK;
@@ -350,7 +352,8 @@ int prdpt::build_host_scene(const prdpt_scene_desc* D, HostScene& hs) {
   if (hs.bvh_depth > kMaxDepth4) {
     return fail(PRDPT_E_SCENE, "BVH deeper than the traversal stack");
   }
-  hs.footprint = sizeof(SceneHdr) + nodes.size() * sizeof(Node) + tris.size() * sizeof(Tri);
+  hs.footprint = sizeof(SceneHdr) + nodes.size() * sizeof(Node) + tris.size() * sizeof(Tri) +
+                 (size_t)render_tiles(h.W, h.H) * (sizeof(float) + sizeof(int));
   return PRDPT_OK;
 }
 
@@ -376,25 +379,38 @@ int prdpt::upload_scene(prdpt_ctx* ctx, const HostScene& hs, prdpt_scene** out) 
     delete s;
     return fail(PRDPT_E_HIP, "hipSetDevice failed");
   }
+  s->n_tiles = render_tiles(h.W, h.H);
+  auto release = [&]() {
+    if (s->d_hdr) hipFree(s->d_hdr);
+    if (s->d_nodes) hipFree(s->d_nodes);
+    if (s->d_tris) hipFree(s->d_tris);
+    if (s->d_tile_cost) hipFree(s->d_tile_cost);
+    if (s->d_tile_order) hipFree(s->d_tile_order);
+    delete s;
+  };
   bool ok = hipMalloc(&s->d_hdr, sizeof(SceneHdr)) == hipSuccess;
   ok = ok && hipMalloc(&s->d_nodes, std::max<size_t>(1, nodes.size()) * sizeof(Node)) == hipSuccess;
   ok = ok && hipMalloc(&s->d_tris, std::max<size_t>(1, tris.size()) * sizeof(Tri)) == hipSuccess;
+  ok = ok && hipMalloc(&s->d_tile_cost, s->n_tiles * sizeof(float)) == hipSuccess;
+  ok = ok && hipMalloc(&s->d_tile_order, s->n_tiles * sizeof(int)) == hipSuccess;
   if (!ok) {
-    if (s->d_hdr) hipFree(s->d_hdr);
-    if (s->d_nodes) hipFree(s->d_nodes);
-    delete s;
+    release();
     return fail(PRDPT_E_NOMEM, "device allocation of the scene failed");
   }
+  std::vector<int> order(s->n_tiles);
+  for (int i = 0; i < s->n_tiles; ++i) order[i] = i;
+  const std::vector<float> cost(s->n_tiles, 0.0f);
   ok = hipMemcpy(s->d_hdr, &h, sizeof(SceneHdr), hipMemcpyHostToDevice) == hipSuccess;
   if (ok && !nodes.empty())
     ok = hipMemcpy(s->d_nodes, nodes.data(), nodes.size() * sizeof(Node), hipMemcpyHostToDevice) == hipSuccess;
   if (ok && !tris.empty())
     ok = hipMemcpy(s->d_tris, tris.data(), tris.size() * sizeof(Tri), hipMemcpyHostToDevice) == hipSuccess;
+  ok = ok && hipMemcpy(s->d_tile_order, order.data(), s->n_tiles * sizeof(int), hipMemcpyHostToDevice) ==
+                 hipSuccess;
+  ok = ok && hipMemcpy(s->d_tile_cost, cost.data(), s->n_tiles * sizeof(float), hipMemcpyHostToDevice) ==
+                 hipSuccess;
   if (!ok) {
-    hipFree(s->d_hdr);
-    hipFree(s->d_nodes);
-    hipFree(s->d_tris);
-    delete s;
+    release();
     return fail(PRDPT_E_HIP, "scene upload failed");
   }
   ctx->resident += s->footprint;
@@ -425,6 +441,8 @@ int prdpt_scene_destroy(prdpt_scene* s) {
   hipFree(s->d_hdr);
   hipFree(s->d_nodes);
   hipFree(s->d_tris);
+  hipFree(s->d_tile_cost);
+  hipFree(s->d_tile_order);
   ctx->resident -= s->footprint;
   ctx->n_scenes--;
   delete s;
@@ -477,7 +495,8 @@ int prdpt_render_perturbed(prdpt_scene* s, const float* theta, const float* sigm
   HIP_TRY(launch_tau(ctx->stream, est, d, P, seed, ctx->sigma.p, ctx->theta.p, chi_mean(d),
                      std::sqrt(2.0 * M_PI), ctx->tau.p, ctx->c.p, ctx->X.p));
   HIP_TRY(launch_render(ctx->stream, s->dev(), h.W, h.H, ctx->X.p, N, d, kTagPath, seed, nullptr,
-                        images_out, nullptr, nullptr, ctx->work.p));
+                        images_out, nullptr, nullptr, ctx->work.p, s->d_tile_order,
+                        s->d_tile_cost));
   if (tau_out)
     HIP_TRY(hipMemcpyAsync(tau_out, ctx->tau.p, sizeof(float) * P * d, hipMemcpyDeviceToHost, ctx->stream));
   HIP_TRY(hipStreamSynchronize(ctx->stream));
@@ -494,7 +513,8 @@ int prdpt_render_reference(prdpt_scene* s, const float* X, uint64_t seed, float*
   if (int rc = prepare(ctx, 2, d, render_tiles(h.W, h.H))) return rc;
   HIP_TRY(hipMemcpyAsync(ctx->X.p, X, sizeof(float) * d, hipMemcpyHostToDevice, ctx->stream));
   HIP_TRY(launch_render(ctx->stream, s->dev(), h.W, h.H, ctx->X.p, 1, d, kTagRef, seed, nullptr,
-                        image_out, nullptr, nullptr, ctx->work.p));
+                        image_out, nullptr, nullptr, ctx->work.p, s->d_tile_order,
+                        s->d_tile_cost));
   HIP_TRY(hipStreamSynchronize(ctx->stream));
   return PRDPT_OK;
 }
@@ -611,7 +631,8 @@ int prdpt_traversal_counts(prdpt_scene* s, const float* theta, const float* sigm
   HIP_TRY(launch_tau(ctx->stream, est, d, P, seed, ctx->sigma.p, ctx->theta.p, chi_mean(d),
                      std::sqrt(2.0 * M_PI), ctx->tau.p, ctx->c.p, ctx->X.p));
   HIP_TRY(launch_render(ctx->stream, s->dev(), h.W, h.H, ctx->X.p, N, d, kTagPath, seed, nullptr,
-                        nullptr, nullptr, ctx->counters.p, ctx->work.p));
+                        nullptr, nullptr, ctx->counters.p, ctx->work.p, s->d_tile_order,
+                        nullptr));
   unsigned long long host[7];
   HIP_TRY(hipMemcpyAsync(host, ctx->counters.p, sizeof(host), hipMemcpyDeviceToHost, ctx->stream));
   HIP_TRY(hipStreamSynchronize(ctx->stream));

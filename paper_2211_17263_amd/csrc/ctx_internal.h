@@ -18,7 +18,10 @@ hipError_t launch_tau(hipStream_t st, int est, int d, int P, uint64_t seed, cons
                       const float* theta, double cd, double sqrt2pi, float* tau, double* c, float* X);
 hipError_t launch_render(hipStream_t st, const DevScene& sc, int W, int H, const float* X, int nk,
                          int d, int tag, uint64_t seed, const float* ref, float* img,
-                         float* partial, unsigned long long* counters, int* work);
+                         float* partial, unsigned long long* counters, int* work,
+                         const int* order, float* cost);
+// tiles by descending measured render time (no-op for more than 4096 tiles)
+hipError_t launch_tile_order(hipStream_t st, const float* cost, int* order, int n_tiles);
 hipError_t launch_losses(hipStream_t st, const float* partial, int n_tiles, int N, int npix,
                          double* losses);
 hipError_t launch_combine(hipStream_t st, int P, int d, const double* c, const double* L,
@@ -120,6 +123,9 @@ struct prdpt_scene {
   prdpt::SceneHdr* d_hdr = nullptr;
   prdpt::Node* d_nodes = nullptr;
   prdpt::Tri* d_tris = nullptr;
+  float* d_tile_cost = nullptr;  // last measured render time per pixel tile
+  int* d_tile_order = nullptr;   // tiles by descending cost (render order)
+  int n_tiles = 0;
   size_t footprint = 0;
   int n_nodes = 0, n_tris = 0, bvh_depth = 0;
   prdpt::DevScene dev() const { return prdpt::DevScene{d_hdr, d_nodes, d_tris}; }

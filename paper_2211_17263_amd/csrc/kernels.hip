@@ -255,7 +255,7 @@ __device__ __forceinline__ float safe_inv(float x) {
 // most two, and a suspended node takes the place of its own path entry, so it
 // cannot overflow.
 #ifndef PRDPT_LEAF_QUORUM
-#define PRDPT_LEAF_QUORUM 50
+#define PRDPT_LEAF_QUORUM 35
 #endif
 #ifndef PRDPT_TRACE_BUDGET
 #define PRDPT_TRACE_BUDGET 32
@@ -861,12 +861,18 @@ __device__ __forceinline__ void render_tile(const SceneHdr& S, const Node* __res
 // counter *work (zeroed by reset_work_kernel before the launch) until all
 // n_tiles * nk items are done.  Dynamic assignment keeps every CU busy when
 // tiles differ widely in cost, where a one-work-group-per-tile grid leaves
-// CUs idle waiting on the hardware dispatcher.
+// CUs idle waiting on the hardware dispatcher.  Within each perturbation the
+// tiles are taken in the order order[] (null: index order), and each tile's
+// render time is stored in cost[tile] (when not null), so that sorting the
+// tiles by cost for the next launch puts the cheapest tiles last and shortens
+// the tail where few work-groups are still busy.  Outputs do not depend on
+// the order.
 template <bool COUNT>
 __global__ __launch_bounds__(kBlock, PRDPT_MIN_WAVES_PER_EU) void render_loss_kernel(
     DevScene scene, const float* __restrict__ X, int d, int tag, uint32_t k0, uint32_t k1,
     const float* __restrict__ ref, float* __restrict__ img, float* __restrict__ partial,
-    unsigned long long* __restrict__ counters, int n_tiles, int n_items, int* __restrict__ work) {
+    unsigned long long* __restrict__ counters, int n_tiles, int n_items, int* __restrict__ work,
+    const int* __restrict__ order, float* __restrict__ cost) {
   __shared__ SceneHdr S;
   __shared__ int stack[kStackEntries * kBlock];
   __shared__ float wsum[kBlock / 64];
@@ -878,20 +884,61 @@ __global__ __launch_bounds__(kBlock, PRDPT_MIN_WAVES_PER_EU) void render_loss_ke
     const int it = s_item;
     __syncthreads();
     if (it >= n_items) break;
-    const int k = it / n_tiles, tile = it - k * n_tiles;
+    const int k = it / n_tiles, j = it - k * n_tiles;
+    int tile = order ? order[j] : j;
+    if ((unsigned)tile >= (unsigned)n_tiles) tile = j;  // a permutation by construction
     if (k != cur) {  // the scene state of perturbation k (after the previous tile's last use)
       load_state(S, scene.hdr, X + (size_t)k * d, d);
       cur = k;
     }
+    unsigned long long t0 = 0;
+    if (cost && threadIdx.x == 0) t0 = wall_clock64();
     render_tile<COUNT>(S, scene.nodes, scene.tris, k, tile, tag, k0, k1, ref, img,
                        partial ? partial + (size_t)k * n_tiles + tile : nullptr, counters, stack,
                        wsum);
+    if (cost && threadIdx.x == 0) cost[tile] = (float)(wall_clock64() - t0);
     __syncthreads();
   }
 }
 
 __global__ void reset_work_kernel(int* __restrict__ work) {
   if (threadIdx.x == 0) work[0] = 0;
+}
+
+// order[0..n) = tile indices by descending cost (bitonic sort of at most
+// kOrderMax keys in LDS by one work-group; ties in an arbitrary fixed order)
+constexpr int kOrderMax = 4096;
+__global__ __launch_bounds__(1024) void tile_order_kernel(const float* __restrict__ cost,
+                                                          int* __restrict__ order, int n) {
+  __shared__ float key[kOrderMax];
+  __shared__ int val[kOrderMax];
+  int m = 1;
+  while (m < n) m <<= 1;
+  for (int i = threadIdx.x; i < m; i += blockDim.x) {
+    key[i] = i < n ? cost[i] : -1.0f;  // costs are >= 0: padding sorts last
+    val[i] = i;
+  }
+  __syncthreads();
+  for (int size = 2; size <= m; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int i = threadIdx.x; i < m; i += blockDim.x) {
+        const int jx = i ^ stride;
+        if (jx > i) {
+          const bool down = (i & size) == 0;  // blocks alternate; the last merge is descending
+          const float ki = key[i], kj = key[jx];
+          if (down ? (ki < kj) : (ki > kj)) {
+            key[i] = kj;
+            key[jx] = ki;
+            const int t = val[i];
+            val[i] = val[jx];
+            val[jx] = t;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int i = threadIdx.x; i < n; i += blockDim.x) order[i] = val[i];
 }
 
 // Perturbation draw for pair p (Sec. 3.2): Philox TAU stream words in order,
@@ -1170,7 +1217,8 @@ int render_grid_limit() {
 
 hipError_t launch_render(hipStream_t st, const DevScene& sc, int W, int H, const float* X, int nk,
                          int d, int tag, uint64_t seed, const float* ref, float* img,
-                         float* partial, unsigned long long* counters, int* work) {
+                         float* partial, unsigned long long* counters, int* work,
+                         const int* order, float* cost) {
   const int n_tiles = render_tiles(W, H);
   const int n_items = n_tiles * nk;
   const int limit = render_grid_limit();
@@ -1180,11 +1228,17 @@ hipError_t launch_render(hipStream_t st, const DevScene& sc, int W, int H, const
   if (counters)
     hipLaunchKernelGGL(render_loss_kernel<true>, dim3(blocks), dim3(kBlock), 0, st, sc, X, d, tag,
                        (uint32_t)seed, (uint32_t)(seed >> 32), ref, img, partial, counters,
-                       n_tiles, n_items, work);
+                       n_tiles, n_items, work, order, cost);
   else
     hipLaunchKernelGGL(render_loss_kernel<false>, dim3(blocks), dim3(kBlock), 0, st, sc, X, d, tag,
                        (uint32_t)seed, (uint32_t)(seed >> 32), ref, img, partial, counters,
-                       n_tiles, n_items, work);
+                       n_tiles, n_items, work, order, cost);
+  return hipGetLastError();
+}
+
+hipError_t launch_tile_order(hipStream_t st, const float* cost, int* order, int n_tiles) {
+  if (!cost || !order || n_tiles < 1 || n_tiles > kOrderMax) return hipSuccess;
+  hipLaunchKernelGGL(tile_order_kernel, dim3(1), dim3(1024), 0, st, cost, order, n_tiles);
   return hipGetLastError();
 }
 
