@@ -161,14 +161,17 @@ def main():
     log(f"timed {args.steps} steps in {elapsed:.3f} s; counting work of the timed launches")
 
     # algorithmic work of the timed launches, replayed with the counting kernel
+    # (at most 8 evenly spaced timed steps; the per-estimate mean stands for all)
     cnt = {"nodes": 0, "tris": 0, "rays": 0, "paths": 0, "wave_node_iters": 0,
            "wave_tri_iters": 0, "wave_ray_iters": 0}
-    for th32, s, seed in trajectory:
+    counted = sorted(set(np.linspace(0, len(trajectory) - 1, min(8, len(trajectory))).round().astype(int)))
+    for i in counted:
+        th32, s, seed = trajectory[i]
         c = NV.prdpt_traversal_counts(sc, th32, s, N, seed, est)
         for k in cnt:
             cnt[k] += c[k]
     K = args.steps
-    per = {k: cnt[k] / K for k in cnt}
+    per = {k: cnt[k] / len(counted) for k in cnt}
     alg_bytes = per["nodes"] * NODE_BYTES + per["tris"] * TRI_BYTES + N * H * W * REF_BYTES_PER_PIXEL
     kernel_avg_s = (kernel_ms / launches) / 1e3 if launches else float("nan")
     achieved = alg_bytes / kernel_avg_s / 1e9
@@ -197,7 +200,9 @@ def main():
         "kernel": {"name": "render_loss_kernel", "avg_ms": 1e3 * kernel_avg_s, "launches": launches,
                    "share_of_step": (kernel_ms / 1e3) / elapsed},
         "work_per_estimate": {"nodes": per["nodes"], "triangles": per["tris"], "rays": per["rays"],
-                              "paths": per["paths"]},
+                              "paths": per["paths"], "counted_steps": len(counted)},
+        "step_ms_by_sigma": {f"{float(trajectory[i][1][0]):.4g}": 1e3 * lat[i] for i in
+                             sorted({0, len(lat) // 2, len(lat) - 1})},
         "simd_efficiency": {
             "node_loop": per["nodes"] / max(64 * per["wave_node_iters"], 1),
             "triangle_loop": per["tris"] / max(64 * per["wave_tri_iters"], 1),

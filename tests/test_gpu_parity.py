@@ -240,18 +240,22 @@ def test_cornell_full_size(ctx):
     _full_parity(ctx, pr, 2024, "cornell-full", check_images=False)
 
 
-def test_caustic_full_size_sampled(ctx):
-    # full caustic workload: 512x512, 64 spp, 8 bounces, 50k occluders, N = 32;
-    # the oracle re-renders 256 sampled pixels of three perturbed images
+@pytest.mark.parametrize("step", [0, 100, 199])
+def test_caustic_full_size_sampled(ctx, step):
+    # full caustic workload: 512x512, 64 spp, 8 bounces, 50k occluders, N = 32,
+    # at the bandwidth of annealing steps 0, 100 and 199 of 200 (sigma 1.0 ->
+    # 0.05); the oracle re-renders 256 sampled pixels of three perturbed images
     from paper_2211_17263_amd import native as NV
     pr = S.caustic_problem(seed=3)
-    seed, N = 31, 32
-    say("caustic-full", "512x512 spp=64 B=8 N=32")
+    sigma = np.array([O.sigma_schedule(a, b, step, 200) for a, b in
+                      zip(pr["sigma"], np.full_like(pr["sigma"], pr["sigma_end"]))], np.float32)
+    seed, N = 31 + step, 32
+    say("caustic-full", "512x512 spp=64 B=8 N=32 step", step, "sigma", float(sigma[0]))
     osc = O.OracleScene(pr["scene"])
     gs = gpu_scene(ctx, pr["scene"])
     try:
-        imgs, tau = NV.prdpt_render_perturbed(gs, pr["theta0"], pr["sigma"], N, seed, O.IS)
-        otau, _ = O.draw_tau(O.IS, pr["sigma"], N // 2, seed)
+        imgs, tau = NV.prdpt_render_perturbed(gs, pr["theta0"], sigma, N, seed, O.IS)
+        otau, _ = O.draw_tau(O.IS, sigma, N // 2, seed)
         assert np.array_equal(tau, otau)
         rng = np.random.default_rng(0)
         pix = rng.choice(512 * 512, 256, replace=False).astype(np.int32)
