@@ -22,19 +22,22 @@ def _rows(path):
     raise SystemExit(f"no counter_collection.csv under {path}")
 
 
-def _values(path, counter, name_has, largest_grid=True):
+def _values(path, counter, name_has, largest_grid=True, last=0):
     rows = [r for r in _rows(path) if r["Counter_Name"] == counter and name_has in r["Kernel_Name"]]
     if not rows:
         raise SystemExit(f"no {counter} rows for {name_has!r} in {path}")
     if largest_grid:
         g = max(int(r["Grid_Size"]) for r in rows)
         rows = [r for r in rows if int(r["Grid_Size"]) == g]
+    rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+    if last:
+        rows = rows[-last:]
     return [float(r["Counter_Value"]) for r in rows]
 
 
 def traffic(a):
-    fetch = _values(a.fetch, "FETCH_SIZE", a.kernel)
-    write = _values(a.write, "WRITE_SIZE", a.kernel)
+    fetch = _values(a.fetch, "FETCH_SIZE", a.kernel, last=a.last)
+    write = _values(a.write, "WRITE_SIZE", a.kernel, last=a.last)
     cf = statistics.mean(_values(a.copy_fetch, "FETCH_SIZE", "copy_kernel"))
     cw = statistics.mean(_values(a.copy_write, "WRITE_SIZE", "copy_kernel"))
     f_scale = a.copy_bytes / (cf * 1024.0)
@@ -48,7 +51,8 @@ def traffic(a):
         *[f"#   {c}" for c in a.command],
         f"# copy probe: {a.copy_bytes} bytes read and written per dispatch; FETCH_SIZE read "
         f"{cf:.1f} KiB, WRITE_SIZE {cw:.1f} KiB per copy dispatch",
-        f"# dispatches used: {len(fetch)} (FETCH) / {len(write)} (WRITE), largest grid only",
+        f"# dispatches used: {len(fetch)} (FETCH) / {len(write)} (WRITE), largest grid only"
+        + (f", the last {a.last} (the timed estimates)" if a.last else ""),
         f"kernel: {a.kernel}",
         f"kernel_source_sha256: {sha}",
         f"fetch_kib_raw_mean: {statistics.mean(fetch):.3f}",
@@ -83,9 +87,14 @@ def kernel_trace(a):
             def grid(r):
                 return int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"])
             g = max(grid(r) for r in rows)
-            ms = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6 for r in rows if grid(r) == g]
-            out += ["", f"`{a.kernel}` dispatches with the largest grid ({g} work-items): {len(ms)}, "
-                    f"mean {statistics.mean(ms):.3f} ms, min {min(ms):.3f} ms, max {max(ms):.3f} ms"]
+            big = sorted((r for r in rows if grid(r) == g), key=lambda r: int(r["Start_Timestamp"]))
+            if a.last:
+                big = big[-a.last:]
+            ms = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6 for r in big]
+            which = f"the last {a.last} " if a.last else ""
+            out += ["", f"`{a.kernel}`, {which}dispatches with the largest grid ({g} work-items): "
+                    f"{len(ms)}, mean {statistics.mean(ms):.3f} ms, min {min(ms):.3f} ms, "
+                    f"max {max(ms):.3f} ms"]
     out += ["", *a.note]
     open(a.out, "w").write("\n".join(out) + "\n")
     print("\n".join(out))
@@ -102,6 +111,8 @@ def main():
     t.add_argument("--source", default=os.path.join(os.path.dirname(__file__), "csrc", "kernels.hip"))
     t.add_argument("--workload", default="")
     t.add_argument("--command", action="append", default=[])
+    t.add_argument("--last", type=int, default=0,
+                   help="only the last N largest-grid dispatches (the timed ones)")
     t.add_argument("--out", required=True)
     k = sub.add_parser("trace")
     k.add_argument("--trace", required=True)
@@ -111,6 +122,8 @@ def main():
     k.add_argument("--top", type=int, default=8)
     k.add_argument("--kernel", default="render_loss_kernel<false>",
                    help="also summarise this kernel's largest-grid dispatches")
+    k.add_argument("--last", type=int, default=0,
+                   help="only the last N of those dispatches (the timed ones)")
     k.add_argument("--out", required=True)
     a = ap.parse_args()
     traffic(a) if a.mode == "traffic" else kernel_trace(a)
