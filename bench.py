@@ -77,7 +77,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="cornell",
-                    choices=["cornell", "toy", "caustic", "batch", "serve"])
+                    choices=["cornell", "toy", "caustic", "batch", "serve", "inverse"])
     ap.add_argument("--serve-seconds", type=float, default=20.0,
                     help="serve workload: length of each arrival phase")
     ap.add_argument("--serve-rate", type=float, default=200.0,
@@ -108,6 +108,8 @@ def main():
         return bench_batch(args, NV)
     if args.workload == "serve":
         return bench_serve(args, NV)
+    if args.workload == "inverse":
+        return bench_inverse(args, NV)
 
     pr, desc, sigma0, sigma_end = workload(args.workload)
     scene = pr["scene"]
@@ -220,6 +222,70 @@ def main():
         log("CPU oracle baseline leg")
         out["cpu_baseline"], out["parity"] = cpu_leg(sc, pr, sigma0, args, NV)
 
+    sc.destroy()
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+def bench_inverse(args, NV):
+    """End-to-end inverse rendering with the driver (Adam + warm-started sigma
+    schedule): the plateau demonstration (black sphere, no silhouette overlap at
+    the start) for GAUSS, IS and sigma -> 0, sweeps of N and sigma_0 on it, and
+    the global-illumination workload's 6 parameters."""
+    import torch
+    from paper_2211_17263_amd import optimize as OP
+    from paper_2211_17263_amd import scenes as S
+    ctx = NV.Context(0)
+    out = {"metric": "inverse rendering: final parameter MSE (plateau and GI workloads)",
+           "n_gpus": 1, "data": "synthetic", "dtype": "f32", "config": {"workload": "inverse"}}
+    # plateau
+    sc = NV.prdpt_scene_create(ctx, S.plateau_scene())
+    tref = np.zeros(2, np.float32)
+    th0 = np.array([0.9, 0.9], np.float32)
+    ref = NV.prdpt_render_reference(sc, tref, 5)
+    seeds = (100, 1100, 2100)
+
+    def final(s0, N, est, sm=0.01):
+        r = [OP.optimize(sc, ref, th0, s0, 300, 0.02, N, est=est, seed=sd, sigma_min=sm,
+                         theta_ref=tref).param_mse[-1] for sd in seeds]
+        return float(np.median(r))
+    log("inverse: plateau demonstration")
+    out["plateau"] = {"start_param_mse": float(np.mean(th0 ** 2)), "steps": 300, "lr": 0.02,
+                      "N": 4, "sigma0": 0.5, "median_of_seeds": len(seeds),
+                      "gauss": final(0.5, 4, NV.PRDPT_EST_GAUSS),
+                      "is": final(0.5, 4, NV.PRDPT_EST_IS),
+                      "sigma_to_zero_1e-6": final(1e-6, 4, NV.PRDPT_EST_IS, sm=1e-6)}
+    log("inverse: N and sigma_0 sweeps")
+    out["n_sweep_is_sigma0.5"] = {str(N): final(0.5, N, NV.PRDPT_EST_IS) for N in (2, 4, 8, 16)}
+    out["sigma0_sweep_is_N4"] = {str(s0): final(s0, 4, NV.PRDPT_EST_IS)
+                                 for s0 in (0.05, 0.1, 0.2, 0.35, 0.5, 0.75, 1.0)}
+    sc.destroy()
+    # global illumination
+    log("inverse: global-illumination workload")
+    pr = S.cornell_problem(seed=2)
+    sc = NV.prdpt_scene_create(ctx, pr["scene"])
+    ref = NV.prdpt_render_reference(sc, pr["theta_ref"], args.seed + 7)
+    # the paper's GI bandwidth (sigma_0 = 0.125) with N = 16 renders and lr 0.01
+    steps, lr, s0 = 400, 0.01, 0.125
+    out["gi"] = {"steps": steps, "lr": lr, "N": pr["N"], "sigma0": s0, "sigma_min": 0.01,
+                 "warm_start": 0.5, "runs": []}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for seed in (args.seed, args.seed + 4000):
+        tr = OP.optimize(sc, ref, pr["theta0"], s0, steps, lr, pr["N"], est=pr["est"], seed=seed,
+                         theta_ref=pr["theta_ref"], eval_every=100)
+        out["gi"]["runs"].append({
+            "seed": seed,
+            "param_mse": {str(t): tr.param_mse[t] for t in range(0, steps + 1, 100)},
+            "image_mse": {str(t): v for t, v in tr.image_mse},
+            "ms_per_step": float(np.mean(tr.step_ms))})
+    el = time.perf_counter() - t0
+    noise = OP.image_mse(sc, ref, pr["theta_ref"], 12345)
+    out["gi"]["image_mse_at_theta_ref"] = noise     # the Monte Carlo noise floor
+    out["gi"]["wall_s"] = el
+    out["value"] = 2 * steps / el
+    out["unit"] = "GI optimisation steps/s (estimate + Adam + periodic image-MSE renders)"
+    out["higher_is_better"] = True
     sc.destroy()
     ctx.close()
     print(json.dumps(out), flush=True)

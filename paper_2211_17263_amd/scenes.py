@@ -224,6 +224,23 @@ def toy_scene(width=64, height=64, spp=1, light=(1.5, 1.5, 3.0), pixel_center=0,
     return s
 
 
+def plateau_scene(width=64, height=64, spp=1, fov=60.0):
+    """The circle-position plateau of Sec. 2.1: the toy camera and sphere
+    (theta = sphere (x, y)), no ground and no lights, so the sphere renders
+    black over a constant unit environment and its appearance does not depend
+    on its position.  Moving it without overlapping its reference position
+    leaves the image loss unchanged.  The 60 degree field of view is the wider
+    view the paper's bandwidth study uses so that perturbed positions stay in
+    the frame (with 40 degrees, leaving the frame also lowers the loss)."""
+    s = _new_scene("plateau", width, height, spp, 0, eye=(0, 0, 5), look=(0, 0, 0),
+                   up=(0, 1, 0), fov=fov, env=np.ones(3, np.float32))
+    dark = s.material(DIFFUSE, (0.8, 0.3, 0.2))
+    sph = s.sphere((0.0, 0.0, 0.5), 0.5, dark)
+    s.bind(BIND_SPHERE, sph, 0)
+    s.bind(BIND_SPHERE, sph, 1)
+    return s
+
+
 def toy_problem(seed=1, **kw):
     """Toy workload: theta = sphere (x, y); theta_ref = (0, 0); theta_0 ~ U[-1,1]^2."""
     rng = np.random.default_rng(seed)

@@ -1,0 +1,100 @@
+"""Inverse-rendering driver: trajectory against an oracle-driven loop, and the
+plateau demonstration of Sec. 2.1 / Sec. 4 (a black sphere over a constant
+background whose silhouette does not overlap its reference position: the loss
+of the plain render is flat there, the smoothed objective is not)."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2211_17263_amd import scenes as S
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def oracle_sigma(s0, sm, t, steps, warm):
+    first = int(round(warm * (steps - 1)))
+    if t <= first:
+        return np.float32(s0)
+    return np.float32(O.sigma_schedule(s0, sm, t - first, steps - first))
+
+
+def test_driver_matches_oracle_loop():
+    import torch
+    from paper_2211_17263_amd import native as NV
+    from paper_2211_17263_amd import optimize as OP
+    pr = S.toy_problem(seed=1)
+    steps, lr, N, seed = 6, 0.05, 4, 900
+    say("driver-vs-oracle", steps, "steps")
+    osc = O.OracleScene(pr["scene"])
+    ref = osc.reference(pr["theta_ref"], seed=5)
+    ctx = NV.Context(0)
+    sc = NV.prdpt_scene_create(ctx, pr["scene"])
+    try:
+        tr = OP.optimize(sc, torch.from_numpy(ref).cuda(), pr["theta0"], 0.5, steps, lr, N,
+                         est=NV.PRDPT_EST_IS, seed=seed, sigma_min=0.05, warm_start=0.5,
+                         theta_ref=pr["theta_ref"])
+        theta = pr["theta0"].astype(np.float64).copy()
+        m, v = np.zeros(2), np.zeros(2)
+        for t in range(steps):
+            sig = np.full(2, oracle_sigma(0.5, 0.05, t, steps, 0.5), np.float32)
+            assert np.array_equal(sig, tr.sigma[t]), t
+            assert np.allclose(theta, tr.theta[t], rtol=0, atol=1e-5), (t, theta, tr.theta[t])
+            o = osc.grad_estimate(ref, theta.astype(np.float32), sig, N, seed + t, O.IS)
+            O.adam_step(theta, o["grad"], m, v, t + 1, lr)
+        assert np.allclose(theta, tr.final_theta, rtol=0, atol=1e-5)
+    finally:
+        sc.destroy()
+        ctx.close()
+
+
+@pytest.fixture(scope="module")
+def plateau():
+    from paper_2211_17263_amd import native as NV
+    theta_ref = np.zeros(2, np.float32)
+    theta0 = np.array([0.9, 0.9], np.float32)   # silhouettes 1.27 apart, radii 0.5
+    ctx = NV.Context(0)
+    sc = NV.prdpt_scene_create(ctx, S.plateau_scene())
+    ref = NV.prdpt_render_reference(sc, theta_ref, 5)
+    yield sc, ref, theta0, theta_ref
+    sc.destroy()
+    ctx.close()
+
+
+def test_plateau_gradient_zero_without_smoothing(plateau):
+    # on the plateau the antithetic renders at sigma -> 0 almost never differ
+    # (only when a jittered sample crosses the silhouette: about 40 silhouette
+    # pixels x 4 renders x 1e-5 pixel of motion each here), while the smoothed
+    # gradient points away from the reference, so descent moves towards it
+    from paper_2211_17263_amd import native as NV
+    sc, ref, theta0, theta_ref = plateau
+    say("plateau-gradient")
+    zero, uphill = [], []
+    for seed in range(20):
+        g0 = NV.prdpt_grad_estimate(sc, ref, theta0, np.full(2, 1e-6, np.float32), 4, seed,
+                                    NV.PRDPT_EST_IS)["grad"]
+        zero.append(bool(np.all(g0 == 0.0)))
+        for est in (NV.PRDPT_EST_GAUSS, NV.PRDPT_EST_IS):
+            g = NV.prdpt_grad_estimate(sc, ref, theta0, np.full(2, 0.5, np.float32), 16, seed,
+                                       est)["grad"]
+            uphill.append(float(np.dot(g, theta0 - theta_ref)) > 0.0)
+    assert np.mean(zero) >= 0.9, zero
+    assert np.mean(uphill) >= 0.9, uphill
+
+
+@pytest.mark.parametrize("est", [0, 1])
+def test_plateau_escape(plateau, est):
+    from paper_2211_17263_amd import optimize as OP
+    sc, ref, theta0, theta_ref = plateau
+    start = float(np.mean((theta0 - theta_ref) ** 2))
+    for seed in (100, 1100):
+        say("plateau-escape est", est, "seed", seed)
+        tr = OP.optimize(sc, ref, theta0, 0.5, 300, 0.02, 4, est=est, seed=seed,
+                         theta_ref=theta_ref)
+        assert tr.param_mse[-1] < 0.01 * start, (est, seed, tr.param_mse[-1], start)

@@ -29,3 +29,19 @@ def test_adam_matches_oracle():
         NV.prdpt_adam_step(a, g, ma, va, t, 0.01)
         O.adam_step(b, g, mb, vb, t, 0.01)
         np.testing.assert_allclose(a, b, rtol=1e-14, atol=1e-15)
+
+
+def test_warm_started_schedule():
+    # constant sigma_0 until half of the iterations, then linear to sigma_min at
+    # the last one (Sec. 3.3 with the supplement's warm start)
+    from paper_2211_17263_amd import optimize as OP
+    steps = 101
+    for t in range(steps):
+        got = OP.sigma_at([0.5, 0.25], 0.01, t, steps, warm_start=0.5)
+        first = 50
+        want = [s0 if t <= first else O.sigma_schedule(s0, 0.01, t - first, steps - first)
+                for s0 in (0.5, 0.25)]
+        assert np.array_equal(got, np.array(want, np.float32)), t
+    assert OP.sigma_at(0.5, 0.01, steps - 1, steps)[0] == np.float32(0.01)
+    assert OP.sigma_at(1.0, 0.05, 0, 200, warm_start=0.0)[0] == np.float32(1.0)
+    assert OP.sigma_at(1.0, 0.05, 199, 200, warm_start=0.0)[0] == np.float32(0.05)

@@ -190,3 +190,26 @@ def test_sigma_schedule_and_adam():
         before = th.copy()
         O.adam_step(th, g, m, v, t, 0.01)
         np.testing.assert_allclose(before - th, 0.01 * g / (np.abs(g) + 1e-8), rtol=1e-9)
+
+
+def test_plateau_loss_is_flat_without_overlap():
+    # Sec. 2.1: a black sphere over a constant background; while its silhouette
+    # does not overlap the reference one, small moves leave the point-sampled
+    # image loss exactly unchanged (the plateau: zero gradient almost
+    # everywhere, level up to the disk's pixel coverage), and it drops once
+    # they overlap
+    from paper_2211_17263_amd import scenes as S
+    osc = O.OracleScene(S.plateau_scene())
+    ref = osc.reference(np.zeros(2, np.float32), seed=5)
+
+    def loss(th):
+        img = osc.reference(np.array(th, np.float32), seed=5)
+        return float(((img - ref) ** 2).mean())
+
+    here = loss((0.9, 0.9))
+    assert here > 0 and loss((0.9001, 0.9)) == here and loss((0.9, 0.9001)) == here
+    flat = [loss(th) for th in ((0.9, 0.9), (0.95, 0.9), (-1.2, 0.3), (0.2, -1.3))]
+    assert max(flat) / min(flat) - 1.0 < 0.05
+    assert loss((0.5, 0.5)) < 0.9 * min(flat)
+    assert loss((0.3, 0.3)) < loss((0.5, 0.5))
+    assert loss((0.0, 0.0)) == 0.0
