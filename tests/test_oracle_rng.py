@@ -94,3 +94,55 @@ def test_chi_mean_closed_form(d):
 def test_chi_mean_special_values():
     assert abs(O.chi_mean(1) - math.sqrt(2 / math.pi)) < 1e-15
     assert abs(O.chi_mean(2) - math.sqrt(math.pi / 2)) < 1e-15
+
+
+_ROCRAND_PROBE = r"""
+#include <hip/hip_runtime.h>
+#include <rocrand/rocrand_philox4x32_10.h>
+#include <cstdio>
+// reads lines "c0 c1 c2 c3 k0 k1", prints Philox4x32-10(c, k) via rocRAND's engine
+int main() {
+  unsigned c[4], k[2];
+  while (std::scanf("%u %u %u %u %u %u", &c[0], &c[1], &c[2], &c[3], &k[0], &k[1]) == 6) {
+    const unsigned long long seed = ((unsigned long long)k[1] << 32) | k[0];
+    const unsigned long long subseq = ((unsigned long long)c[3] << 32) | c[2];
+    const unsigned long long offset = 4ull * (((unsigned long long)c[1] << 32) | c[0]);
+    rocrand_device::philox4x32_10_engine e(seed, subseq, offset);
+    const uint4 r = e.next4();
+    std::printf("%u %u %u %u\n", r.x, r.y, r.z, r.w);
+  }
+  return 0;
+}
+"""
+
+
+def test_philox_matches_rocrand(tmp_path):
+    # rocRAND's Philox4x32-10 as an independent implementation: its engine,
+    # seeded with the key, subsequence (c2, c3) and offset 4 (c0, c1), yields
+    # Philox(c, key) as its first four outputs (the upper counter words stay
+    # below 2^30 so the 4x offset does not carry out of 64 bits)
+    import shutil
+    import subprocess
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(hipcc) or not os.path.exists("/opt/rocm/include/rocrand/rocrand_philox4x32_10.h"):
+        pytest.skip("hipcc or rocRAND headers not available")
+    src = tmp_path / "probe.cpp"
+    exe = tmp_path / "probe"
+    src.write_text(_ROCRAND_PROBE)
+    subprocess.run([hipcc, "-x", "c++", "-D__HIP_PLATFORM_AMD__", "-I", "/opt/rocm/include", "-O1",
+                    "-o", str(exe), str(src)],
+                   check=True, capture_output=True, timeout=300)
+    rng = np.random.default_rng(7)
+    cases = rng.integers(0, 2**32, size=(300, 6), dtype=np.uint64)
+    cases[:, 1] %= 2**30
+    cases[:5, :4] = 0
+    cases[5] = [0xFFFFFFFF, 0x3FFFFFFF, 0xFFFFFFFF, 0xFFFFFFFF, 0xFFFFFFFF, 0xFFFFFFFF]
+    inp = "\n".join(" ".join(str(int(v)) for v in row) for row in cases) + "\n"
+    res = subprocess.run([str(exe)], input=inp, capture_output=True, text=True, check=True,
+                         timeout=60)
+    got = np.array([[int(x) for x in line.split()] for line in res.stdout.strip().splitlines()],
+                   np.uint64)
+    assert got.shape == (len(cases), 4)
+    for row, g in zip(cases, got):
+        want = O.philox(row[:4].astype(np.uint32), row[4:].astype(np.uint32))
+        assert np.array_equal(want.astype(np.uint64), g), (row, want, g)
