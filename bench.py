@@ -499,8 +499,13 @@ def cpu_leg(sc, pr, sigma0, args, NV):
             "sample": f"{reps} whole estimate(s) ({reps * N} renders, {reps * paths} paths) "
                       f"in {dt:.1f} s",
             "paths_per_s": reps * paths / dt}
+    sig = np.abs(first["grad"]) >= 0.1 * S          # components well above the cancellation scale
+    grel = np.abs(g["grad"] - first["grad"])[sig] / np.abs(first["grad"])[sig]
     parity = {"checked_renders": N, "max_rel_loss_err": float(rel.max()),
               "max_grad_err_over_scale": float(gerr.max()),
+              "max_rel_grad_err_significant": float(grel.max()) if grel.size else None,
+              "significant_components": int(sig.sum()),
+              "q_hat_gpu": float(g["loss"]), "q_hat_oracle": float(first["loss"]),
               "pass_1e-4": bool(rel.max() <= 1e-4 and gerr.max() <= 1e-4)}
     return base, parity
 
