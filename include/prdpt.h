@@ -22,6 +22,7 @@
  *   - N is the number of perturbed renders, 2 x (antithetic pairs); it must be
  *     even and >= 2.  Perturbation index k = 2p + m: m = 0 renders theta + tau_p,
  *     m = 1 renders theta - tau_p; both share the pair's path-sample stream.
+ *     (With PRDPT_EST_INDEPENDENT: render k is theta + tau_k, stream k.)
  *   - theta and sigma have length d = the scene's parameter count; sigma_j > 0.
  *   - "host" pointers are ordinary CPU memory, "device" pointers are HIP device
  *     memory of the context's device.  Outputs are owned by the caller.
@@ -62,6 +63,13 @@ extern "C" {
 #define PRDPT_EST_GAUSS 0
 #define PRDPT_EST_IS 1
 #define PRDPT_EST_IS_PERDIM 2
+/* Flag or-ed into a mode: independent perturbations without the antithetic
+ * partner (the paper's noAT ablation, Sec. 5.3): the N renders are theta +
+ * tau_i for N independent draws, each with its own path-sample stream, and
+ *     grad_j = (1/N) sum_i c_ij L(theta + tau_i)
+ * with the single-sample weights c_ij (twice the pair weights).  Accepted by
+ * the single-request calls; the batched and served forms reject it. */
+#define PRDPT_EST_INDEPENDENT 0x100
 
 /* ---- scene description ---------------------------------------------------- */
 #define PRDPT_MAT_DIFFUSE 0    /* rgb = albedo; Lambertian */
@@ -160,7 +168,8 @@ int prdpt_scene_info(const prdpt_scene* scene, int* width, int* height, int* spp
 
 /*
  * Perturbation draw only (Sec. 3.2): tau_out (host, float[P][d]) and pair weights
- * c_out (host, double[P][d]) of `est` for P pairs.  d <= PRDPT_MAX_PARAMS.
+ * c_out (host, double[P][d]) of `est` for P pairs (P independent draws and
+ * their single-sample weights with PRDPT_EST_INDEPENDENT).  d <= PRDPT_MAX_PARAMS.
  */
 int prdpt_draw_tau(prdpt_ctx* ctx, int est, int d, int P, uint64_t seed, const float* sigma,
                    float* tau_out, double* c_out);
@@ -168,7 +177,8 @@ int prdpt_draw_tau(prdpt_ctx* ctx, int est, int d, int P, uint64_t seed, const f
 /*
  * Render the N perturbed scenes theta +- tau_p (Eq. 6 / Eq. 10 arguments).
  * images_out: device float[N][H][W][3] (k = 2p + m), caller-owned.
- * tau_out: host float[N/2][d] or NULL.  Synchronous.
+ * tau_out: host float[N/2][d] (float[N][d] with PRDPT_EST_INDEPENDENT) or
+ * NULL.  Synchronous.
  */
 int prdpt_render_perturbed(prdpt_scene* scene, const float* theta, const float* sigma, int N,
                            uint64_t seed, int est, float* images_out, float* tau_out);
@@ -205,7 +215,9 @@ int prdpt_grad_estimate(prdpt_scene* scene, const float* ref, const float* theta
  * on the device (the torch binding): theta_dev/sigma_dev device float[d];
  * grad_dev device double[d]; loss_dev device double[1]; losses_dev (nullable)
  * device double[N]; c_dev (nullable) device double[N/2][d] receives the pair
- * weights.  Enqueued on the context's stream; no host synchronisation.
+ * weights (double[N][d], the single-sample weights, with
+ * PRDPT_EST_INDEPENDENT).  Enqueued on the context's stream; no host
+ * synchronisation.
  */
 int prdpt_grad_estimate_async(prdpt_scene* scene, const float* ref_dev, const float* theta_dev,
                               const float* sigma_dev, int N, uint64_t seed, int est,
@@ -213,12 +225,17 @@ int prdpt_grad_estimate_async(prdpt_scene* scene, const float* ref_dev, const fl
                               double* c_dev);
 
 /*
- * Gradient combination alone (Eq. 10 with antithetic pairs), stream-ordered:
+ * Gradient combination alone (Eq. 10), stream-ordered, for the weights of an
+ * estimate made with estimator flags `est`:
  *     grad_dev[j] = scale * (1/P) sum_p c_dev[p][j] (losses_dev[2p] - losses_dev[2p+1])
- * with scale = *scale_dev (device double, NULL means 1).  All pointers device.
+ * with rows = P pairs, or, with PRDPT_EST_INDEPENDENT in est,
+ *     grad_dev[j] = scale * (1/N) sum_i c_dev[i][j] losses_dev[i]
+ * with rows = N draws; scale = *scale_dev (device double, NULL means 1).  All
+ * pointers device.
  */
-int prdpt_combine_async(prdpt_ctx* ctx, int P, int d, const double* c_dev,
-                        const double* losses_dev, const double* scale_dev, double* grad_dev);
+int prdpt_combine_async(prdpt_ctx* ctx, int rows, int d, const double* c_dev,
+                        const double* losses_dev, const double* scale_dev, double* grad_dev,
+                        int est);
 
 /*
  * ---- batched estimation ------------------------------------------------------
@@ -235,7 +252,7 @@ typedef struct {
   const float* theta;      /* host float[d] */
   const float* sigma;      /* host float[d], > 0 */
   int32_t N;               /* even, >= 2 */
-  int32_t est;             /* PRDPT_EST_* */
+  int32_t est;             /* PRDPT_EST_GAUSS / _IS / _IS_PERDIM (antithetic only) */
   uint64_t seed;
   double* grad_out;        /* host double[d] */
   double* loss_out;        /* host double[1] or NULL */

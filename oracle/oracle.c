@@ -170,6 +170,11 @@ static void normal_pair(tau_stream* st, float* z0, float* z1) {
 int orc_draw_tau(int mode, int d, int P, uint64_t seed, const float* sigma, float* tau,
                  double* c) {
   if (d < 1 || d > 32 || P < 1) return -1;
+  /* independent draws: the same samplers; the weight is the single-sample score
+   * weight (its expectation over the draw is the gradient by itself), written
+   * below directly: v_j / sigma_j, C_d u_j / sigma_j, s_j 2 / (sigma_j sqrt(2 pi)) */
+  const int indep = (mode & ORC_EST_INDEPENDENT) != 0;
+  mode &= ~ORC_EST_INDEPENDENT;
   double cd = orc_chi_mean(d);
   const double sqrt2pi = sqrt(2.0 * ORC_PI);
   float v[32], z[32];
@@ -190,7 +195,8 @@ int orc_draw_tau(int mode, int d, int P, uint64_t seed, const float* sigma, floa
       }
       for (int j = 0; j < d; ++j) {
         tau[p * d + j] = sigma[j] * v[j];
-        c[p * d + j] = (double)v[j] / (2.0 * (double)sigma[j]);
+        c[p * d + j] = indep ? (double)v[j] / (double)sigma[j]
+                             : (double)v[j] / (2.0 * (double)sigma[j]);
       }
     } else if (mode == ORC_EST_IS) {
       /* importance sampling of the kernel derivative: radius rho ~ chi_{d+1}
@@ -218,7 +224,8 @@ int orc_draw_tau(int mode, int d, int P, uint64_t seed, const float* sigma, floa
       for (int j = 0; j < d; ++j) {
         float uj = z[j] / nrm;
         tau[p * d + j] = sigma[j] * (rho * uj);
-        c[p * d + j] = cd * (double)uj / (2.0 * (double)sigma[j]);
+        c[p * d + j] = indep ? cd * (double)uj / (double)sigma[j]
+                             : cd * (double)uj / (2.0 * (double)sigma[j]);
       }
     } else if (mode == ORC_EST_IS_PERDIM) {
       /* literal per-dimension reading: independent two-sided Rayleigh per axis */
@@ -227,7 +234,8 @@ int orc_draw_tau(int mode, int d, int P, uint64_t seed, const float* sigma, floa
       for (int j = 0; j < d; ++j) {
         float sgn = ((bits >> j) & 1u) ? -1.0f : 1.0f;
         tau[p * d + j] = sigma[j] * (sgn * v[j]);
-        c[p * d + j] = (double)sgn / ((double)sigma[j] * sqrt2pi);
+        c[p * d + j] = indep ? 2.0 * (double)sgn / ((double)sigma[j] * sqrt2pi)
+                             : (double)sgn / ((double)sigma[j] * sqrt2pi);
       }
     } else {
       return -1;
@@ -247,6 +255,22 @@ void orc_combine(int P, int d, const double* c, const double* L, double* g, doub
     double s = 0.0;
     for (int k = 0; k < 2 * P; ++k) s += L[k];
     *q = s / (double)(2 * P);
+  }
+}
+
+/* Without antithetic partners: g_j = (1/N) sum_i c_ij L(theta+tau_i) (Eq. 10
+ * as a plain Monte Carlo mean of score-weighted losses), Q = mean L */
+void orc_combine_independent(int N, int d, const double* c, const double* L, double* g,
+                             double* q) {
+  for (int j = 0; j < d; ++j) {
+    double acc = 0.0;
+    for (int i = 0; i < N; ++i) acc += c[i * d + j] * L[i];
+    g[j] = acc / (double)N;
+  }
+  if (q) {
+    double s = 0.0;
+    for (int i = 0; i < N; ++i) s += L[i];
+    *q = s / (double)N;
   }
 }
 
@@ -906,11 +930,29 @@ static void perturbed_losses(const orc_scene* s, const float* ref, const float* 
   free(img);
 }
 
+/* independent draws: renders theta + tau_i, each with its own path stream i */
+static void independent_losses(const orc_scene* s, const float* ref, const float* theta,
+                               const float* tau, int N, uint64_t seed, int nthreads,
+                               double* L, float* images) {
+  int d = s->n_param;
+  size_t npix = (size_t)s->W * (size_t)s->H;
+  float* img = images ? NULL : (float*)malloc(sizeof(float) * 3 * npix);
+  float X[32];
+  for (int i = 0; i < N; ++i) {
+    for (int j = 0; j < d; ++j) X[j] = theta[j] + tau[i * d + j];
+    float* out = images ? images + (size_t)i * 3 * npix : img;
+    orc_render(s, X, ORC_TAG_PATH, i, seed, nthreads, out);
+    if (L) L[i] = orc_mse(out, ref, (int)npix);
+  }
+  free(img);
+}
+
 int orc_grad_estimate(const orc_scene* s, const float* ref, const float* theta,
                       const float* sigma, int N, uint64_t seed, int mode, int nthreads,
                       double* grad, double* loss, double* losses, float* tau_out) {
   if (check_args(s, sigma, N)) return -1;
-  int P = N / 2, d = s->n_param;
+  const int indep = (mode & ORC_EST_INDEPENDENT) != 0;
+  int P = indep ? N : N / 2, d = s->n_param;
   float* tau = (float*)malloc(sizeof(float) * (size_t)(P * d));
   double* c = (double*)malloc(sizeof(double) * (size_t)(P * d));
   double* L = (double*)malloc(sizeof(double) * (size_t)N);
@@ -918,9 +960,14 @@ int orc_grad_estimate(const orc_scene* s, const float* ref, const float* theta,
     free(tau); free(c); free(L);
     return -1;
   }
-  perturbed_losses(s, ref, theta, tau, P, seed, nthreads, L, NULL);
   double q;
-  orc_combine(P, d, c, L, grad, &q);
+  if (indep) {
+    independent_losses(s, ref, theta, tau, N, seed, nthreads, L, NULL);
+    orc_combine_independent(N, d, c, L, grad, &q);
+  } else {
+    perturbed_losses(s, ref, theta, tau, P, seed, nthreads, L, NULL);
+    orc_combine(P, d, c, L, grad, &q);
+  }
   if (loss) *loss = q;
   if (losses) memcpy(losses, L, sizeof(double) * (size_t)N);
   if (tau_out) memcpy(tau_out, tau, sizeof(float) * (size_t)(P * d));
@@ -941,14 +988,18 @@ int orc_smoothed_loss(const orc_scene* s, const float* ref, const float* theta,
 int orc_render_perturbed(const orc_scene* s, const float* theta, const float* sigma, int N,
                          uint64_t seed, int mode, int nthreads, float* images, float* tau_out) {
   if (check_args(s, sigma, N)) return -1;
-  int P = N / 2, d = s->n_param;
+  const int indep = (mode & ORC_EST_INDEPENDENT) != 0;
+  int P = indep ? N : N / 2, d = s->n_param;
   float* tau = (float*)malloc(sizeof(float) * (size_t)(P * d));
   double* c = (double*)malloc(sizeof(double) * (size_t)(P * d));
   if (orc_draw_tau(mode, d, P, seed, sigma, tau, c)) {
     free(tau); free(c);
     return -1;
   }
-  perturbed_losses(s, NULL, theta, tau, P, seed, nthreads, NULL, images);
+  if (indep)
+    independent_losses(s, NULL, theta, tau, N, seed, nthreads, NULL, images);
+  else
+    perturbed_losses(s, NULL, theta, tau, P, seed, nthreads, NULL, images);
   if (tau_out) memcpy(tau_out, tau, sizeof(float) * (size_t)(P * d));
   free(tau); free(c);
   return 0;

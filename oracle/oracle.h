@@ -22,6 +22,10 @@ extern "C" {
 enum { ORC_DIFFUSE = 0, ORC_DIELECTRIC = 1, ORC_EMISSIVE = 2 };
 enum { ORC_BIND_SPHERE = 0, ORC_BIND_QUAD = 1, ORC_BIND_MESH = 2, ORC_BIND_PLIGHT = 3 };
 enum { ORC_EST_GAUSS = 0, ORC_EST_IS = 1, ORC_EST_IS_PERDIM = 2 };
+/* flag or-ed into a mode: independent perturbations without the antithetic
+ * partner (the paper's noAT ablation, Sec. 5.3): N draws, one render each at
+ * theta + tau_i with its own path stream, single-sample score weights */
+enum { ORC_EST_INDEPENDENT = 0x100 };
 enum { ORC_TAG_TAU = 1, ORC_TAG_PATH = 2, ORC_TAG_REF = 3 };
 
 /* Scene as flat arrays; the oracle copies everything it needs. */
@@ -52,6 +56,9 @@ int orc_draw_tau(int mode, int d, int P, uint64_t seed, const float* sigma,
                  float* tau, double* c);
 /* g_j = (1/P) sum_p c[p][j] (L[2p] - L[2p+1]);  q = mean of L over 2P */
 void orc_combine(int P, int d, const double* c, const double* L, double* g, double* q);
+/* independent draws: g_j = (1/N) sum_i c_ij L_i, q = mean L */
+void orc_combine_independent(int N, int d, const double* c, const double* L, double* g,
+                             double* q);
 
 /* scene */
 orc_scene* orc_scene_new(const orc_scene_in* in);

@@ -16,6 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
 
 GAUSS, IS, IS_PERDIM = 0, 1, 2
+INDEPENDENT = 0x100          # or-ed into a mode: no antithetic partners (noAT)
 TAG_TAU, TAG_PATH, TAG_REF = 1, 2, 3
 
 _lib = None
@@ -66,6 +67,8 @@ def _declare(L):
     L.orc_chi_mean.restype = C.c_double
     L.orc_draw_tau.argtypes = [C.c_int, C.c_int, C.c_int, C.c_uint64, _f32p, _f32p, _f64p]
     L.orc_combine.argtypes = [C.c_int, C.c_int, _f64p, _f64p, _f64p, C.POINTER(C.c_double)]
+    L.orc_combine_independent.argtypes = [C.c_int, C.c_int, _f64p, _f64p, _f64p,
+                                          C.POINTER(C.c_double)]
     L.orc_scene_new.argtypes = [C.POINTER(SceneIn)]
     L.orc_scene_new.restype = C.c_void_p
     L.orc_scene_free.argtypes = [C.c_void_p]
@@ -145,6 +148,16 @@ def combine(c, L):
     g = np.zeros(d, np.float64)
     q = C.c_double()
     lib().orc_combine(P, d, c, L, g, C.byref(q))
+    return g, q.value
+
+
+def combine_independent(c, L):
+    c = np.ascontiguousarray(c, np.float64)
+    L = np.ascontiguousarray(L, np.float64)
+    N, d = c.shape
+    g = np.zeros(d, np.float64)
+    q = C.c_double()
+    lib().orc_combine_independent(N, d, c, L, g, C.byref(q))
     return g, q.value
 
 
@@ -229,7 +242,7 @@ class OracleScene:
         g = np.zeros(d, np.float64)
         q = C.c_double()
         L = np.zeros(N, np.float64)
-        tau = np.zeros((N // 2, d), np.float32)
+        tau = np.zeros((N if int(mode) & INDEPENDENT else N // 2, d), np.float32)
         rc = lib().orc_grad_estimate(self.h, _f32(ref), _f32(theta, d), _f32(sigma, d), int(N),
                                      int(seed), int(mode), nthreads, g, C.byref(q), L, tau)
         if rc:
@@ -246,7 +259,7 @@ class OracleScene:
 
     def render_perturbed(self, theta, sigma, N, seed, mode, nthreads=0):
         imgs = np.zeros((N, self.H, self.W, 3), np.float32)
-        tau = np.zeros((N // 2, self.d), np.float32)
+        tau = np.zeros((N if int(mode) & INDEPENDENT else N // 2, self.d), np.float32)
         rc = lib().orc_render_perturbed(self.h, _f32(theta, self.d), _f32(sigma, self.d), int(N),
                                         int(seed), int(mode), nthreads, imgs, tau)
         if rc:

@@ -32,7 +32,8 @@ class PrdptSmoothedLoss(torch.autograd.Function):
             sigma = torch.tensor(sigma, dtype=torch.float32, device=dev)
         sigma = sigma.to(device=dev, dtype=torch.float32).contiguous()
         th = theta.detach().to(torch.float32).contiguous()
-        d, P = scene.d, N // 2
+        d = scene.d
+        rows = N if int(est) & NV.PRDPT_EST_INDEPENDENT else N // 2   # weight rows
         if th.numel() != d or sigma.numel() != d:
             raise ValueError("theta/sigma length must equal the scene's parameter count")
         stream = torch.cuda.current_stream(dev)
@@ -41,21 +42,22 @@ class PrdptSmoothedLoss(torch.autograd.Function):
         grad = torch.empty(d, dtype=torch.float64, device=dev)
         loss = torch.empty(1, dtype=torch.float64, device=dev)
         losses = torch.empty(N, dtype=torch.float64, device=dev)
-        c = torch.empty(P, d, dtype=torch.float64, device=dev)
+        c = torch.empty(rows, d, dtype=torch.float64, device=dev)
         NV.prdpt_grad_estimate_async(scene, ref.contiguous(), th, sigma, N, seed, est, grad, loss,
                                      losses, c)
         ctx.save_for_backward(losses, c)
         ctx.scene = scene
+        ctx.est = int(est)
         ctx.theta_dtype = theta.dtype
         return loss[0].to(theta.dtype)
 
     @staticmethod
     def backward(ctx, grad_out):
         losses, c = ctx.saved_tensors
-        P, d = c.shape
+        rows, d = c.shape
         scale = grad_out.detach().reshape(1).to(torch.float64).contiguous()
         g = torch.empty(d, dtype=torch.float64, device=c.device)
-        NV.prdpt_combine_async(ctx.scene.ctx, P, d, c, losses, scale, g)
+        NV.prdpt_combine_async(ctx.scene.ctx, rows, d, c, losses, scale, g, ctx.est)
         return g.to(ctx.theta_dtype), None, None, None, None, None, None
 
 

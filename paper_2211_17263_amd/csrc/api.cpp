@@ -55,7 +55,7 @@ hipEvent_t take_event(prdpt_ctx* ctx) {
 
 // launch the fused render kernel, bracketed by timing events when enabled
 hipError_t timed_render(prdpt_ctx* ctx, const prdpt_scene* s, const float* X, int nk, int d, int tag,
-                        uint64_t seed, const float* ref, float* img, float* partial) {
+                        uint64_t seed, const float* ref, float* img, float* partial, int crn) {
   const DevScene sc = s->dev();
   const int W = s->hdr.W, H = s->hdr.H;
   hipEvent_t a = nullptr, b = nullptr;
@@ -68,7 +68,7 @@ hipError_t timed_render(prdpt_ctx* ctx, const prdpt_scene* s, const float* X, in
     }
   }
   hipError_t e = launch_render(ctx->stream, sc, W, H, X, nk, d, tag, seed, ref, img, partial, nullptr,
-                               ctx->work.p, s->d_tile_order, s->d_tile_cost);
+                               ctx->work.p, s->d_tile_order, s->d_tile_cost, crn);
   if (e != hipSuccess) return e;
   if (a && b) {
     e = hipEventRecord(b, ctx->stream);
@@ -96,17 +96,22 @@ int check_request(const prdpt_scene* s, const float* theta, const float* sigma, 
 }
 
 int check_est(int est) {
-  if (est != PRDPT_EST_GAUSS && est != PRDPT_EST_IS && est != PRDPT_EST_IS_PERDIM)
+  const int mode = est & ~PRDPT_EST_INDEPENDENT;
+  if (mode != PRDPT_EST_GAUSS && mode != PRDPT_EST_IS && mode != PRDPT_EST_IS_PERDIM)
     return fail(PRDPT_E_ARG, "unknown estimator mode");
   return PRDPT_OK;
 }
+
+// perturbation draws of an estimate with N renders: pairs, or N independent draws
+int n_draws(int est, int N) { return (est & PRDPT_EST_INDEPENDENT) ? N : N / 2; }
 
 // Scratch for one request with N renders; returns status.
 int prepare(prdpt_ctx* ctx, int N, int d, int n_tiles) {
   int P = N / 2, rc;
   if ((rc = ensure(ctx, ctx->X, (size_t)N * d))) return rc;
-  if ((rc = ensure(ctx, ctx->tau, (size_t)P * d))) return rc;
-  if ((rc = ensure(ctx, ctx->c, (size_t)P * d))) return rc;
+  (void)P;  // tau and c hold up to N rows (independent draws)
+  if ((rc = ensure(ctx, ctx->tau, (size_t)N * d))) return rc;
+  if ((rc = ensure(ctx, ctx->c, (size_t)N * d))) return rc;
   if ((rc = ensure(ctx, ctx->partial, (size_t)N * n_tiles))) return rc;
   if ((rc = ensure(ctx, ctx->losses, (size_t)N))) return rc;
   if ((rc = ensure(ctx, ctx->grad, (size_t)d))) return rc;
@@ -123,17 +128,20 @@ int enqueue_estimate(prdpt_scene* s, const float* ref, const float* theta_dev,
                      double* loss_dev, double* losses_dev, double* c_dev) {
   prdpt_ctx* ctx = s->ctx;
   const SceneHdr& h = s->hdr;
-  const int d = h.n_param, P = N / 2;
+  const int d = h.n_param;
+  const int indep = (est & PRDPT_EST_INDEPENDENT) != 0;
+  const int rows = n_draws(est, N);
   const int n_tiles = render_tiles(h.W, h.H);
   int rc = prepare(ctx, N, d, n_tiles);
   if (rc) return rc;
   double* c = c_dev ? c_dev : ctx->c.p;
   double* L = losses_dev ? losses_dev : ctx->losses.p;
-  HIP_TRY(launch_tau(ctx->stream, est, d, P, seed, sigma_dev, theta_dev, chi_mean(d),
+  HIP_TRY(launch_tau(ctx->stream, est, d, rows, seed, sigma_dev, theta_dev, chi_mean(d),
                      std::sqrt(2.0 * M_PI), ctx->tau.p, c, ctx->X.p));
-  HIP_TRY(timed_render(ctx, s, ctx->X.p, N, d, kTagPath, seed, ref, nullptr, ctx->partial.p));
+  HIP_TRY(timed_render(ctx, s, ctx->X.p, N, d, kTagPath, seed, ref, nullptr, ctx->partial.p,
+                       indep ? 0 : 1));
   HIP_TRY(launch_losses(ctx->stream, ctx->partial.p, n_tiles, N, h.W * h.H, L));
-  HIP_TRY(launch_combine(ctx->stream, P, d, c, L, nullptr, grad_dev, loss_dev));
+  HIP_TRY(launch_combine(ctx->stream, rows, d, indep, c, L, nullptr, grad_dev, loss_dev));
   return PRDPT_OK;
 }
 
@@ -487,18 +495,19 @@ int prdpt_render_perturbed(prdpt_scene* s, const float* theta, const float* sigm
   if (!images_out) return fail(PRDPT_E_ARG, "images_out is null");
   prdpt_ctx* ctx = s->ctx;
   const SceneHdr& h = s->hdr;
-  const int d = h.n_param, P = N / 2;
+  const int d = h.n_param, rows = n_draws(est, N);
   std::lock_guard<std::mutex> g(ctx->mu);
   HIP_TRY(hipSetDevice(ctx->device));
   if (int rc = prepare(ctx, N, d, render_tiles(h.W, h.H))) return rc;
   if (int rc = upload_vectors(ctx, theta, sigma, d)) return rc;
-  HIP_TRY(launch_tau(ctx->stream, est, d, P, seed, ctx->sigma.p, ctx->theta.p, chi_mean(d),
+  HIP_TRY(launch_tau(ctx->stream, est, d, rows, seed, ctx->sigma.p, ctx->theta.p, chi_mean(d),
                      std::sqrt(2.0 * M_PI), ctx->tau.p, ctx->c.p, ctx->X.p));
   HIP_TRY(launch_render(ctx->stream, s->dev(), h.W, h.H, ctx->X.p, N, d, kTagPath, seed, nullptr,
                         images_out, nullptr, nullptr, ctx->work.p, s->d_tile_order,
-                        s->d_tile_cost));
+                        s->d_tile_cost, (est & PRDPT_EST_INDEPENDENT) ? 0 : 1));
   if (tau_out)
-    HIP_TRY(hipMemcpyAsync(tau_out, ctx->tau.p, sizeof(float) * P * d, hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipMemcpyAsync(tau_out, ctx->tau.p, sizeof(float) * rows * d, hipMemcpyDeviceToHost,
+                           ctx->stream));
   HIP_TRY(hipStreamSynchronize(ctx->stream));
   return PRDPT_OK;
 }
@@ -514,7 +523,7 @@ int prdpt_render_reference(prdpt_scene* s, const float* X, uint64_t seed, float*
   HIP_TRY(hipMemcpyAsync(ctx->X.p, X, sizeof(float) * d, hipMemcpyHostToDevice, ctx->stream));
   HIP_TRY(launch_render(ctx->stream, s->dev(), h.W, h.H, ctx->X.p, 1, d, kTagRef, seed, nullptr,
                         image_out, nullptr, nullptr, ctx->work.p, s->d_tile_order,
-                        s->d_tile_cost));
+                        s->d_tile_cost, 1));
   HIP_TRY(hipStreamSynchronize(ctx->stream));
   return PRDPT_OK;
 }
@@ -576,13 +585,16 @@ int prdpt_grad_estimate_async(prdpt_scene* s, const float* ref_dev, const float*
                           losses_dev, c_dev);
 }
 
-int prdpt_combine_async(prdpt_ctx* ctx, int P, int d, const double* c_dev, const double* losses_dev,
-                        const double* scale_dev, double* grad_dev) {
+int prdpt_combine_async(prdpt_ctx* ctx, int rows, int d, const double* c_dev,
+                        const double* losses_dev, const double* scale_dev, double* grad_dev,
+                        int est) {
   if (!ctx || !c_dev || !losses_dev || !grad_dev) return fail(PRDPT_E_ARG, "null argument");
-  if (P < 1 || d < 1 || d > 64) return fail(PRDPT_E_ARG, "bad P or d");
+  if (rows < 1 || d < 1 || d > 64) return fail(PRDPT_E_ARG, "bad row count or d");
+  if (int rc = check_est(est)) return rc;
   std::lock_guard<std::mutex> g(ctx->mu);
   HIP_TRY(hipSetDevice(ctx->device));
-  HIP_TRY(launch_combine(ctx->stream, P, d, c_dev, losses_dev, scale_dev, grad_dev, nullptr));
+  HIP_TRY(launch_combine(ctx->stream, rows, d, (est & PRDPT_EST_INDEPENDENT) ? 1 : 0, c_dev,
+                         losses_dev, scale_dev, grad_dev, nullptr));
   return PRDPT_OK;
 }
 
@@ -621,18 +633,18 @@ int prdpt_traversal_counts(prdpt_scene* s, const float* theta, const float* sigm
   if (!counts) return fail(PRDPT_E_ARG, "counts is null");
   prdpt_ctx* ctx = s->ctx;
   const SceneHdr& h = s->hdr;
-  const int d = h.n_param, P = N / 2;
+  const int d = h.n_param, rows = n_draws(est, N);
   std::lock_guard<std::mutex> g(ctx->mu);
   HIP_TRY(hipSetDevice(ctx->device));
   if (int rc = prepare(ctx, N, d, render_tiles(h.W, h.H))) return rc;
   if (int rc = ensure(ctx, ctx->counters, 7)) return rc;
   if (int rc = upload_vectors(ctx, theta, sigma, d)) return rc;
   HIP_TRY(hipMemsetAsync(ctx->counters.p, 0, 7 * sizeof(unsigned long long), ctx->stream));
-  HIP_TRY(launch_tau(ctx->stream, est, d, P, seed, ctx->sigma.p, ctx->theta.p, chi_mean(d),
+  HIP_TRY(launch_tau(ctx->stream, est, d, rows, seed, ctx->sigma.p, ctx->theta.p, chi_mean(d),
                      std::sqrt(2.0 * M_PI), ctx->tau.p, ctx->c.p, ctx->X.p));
   HIP_TRY(launch_render(ctx->stream, s->dev(), h.W, h.H, ctx->X.p, N, d, kTagPath, seed, nullptr,
                         nullptr, nullptr, ctx->counters.p, ctx->work.p, s->d_tile_order,
-                        nullptr));
+                        nullptr, (est & PRDPT_EST_INDEPENDENT) ? 0 : 1));
   unsigned long long host[7];
   HIP_TRY(hipMemcpyAsync(host, ctx->counters.p, sizeof(host), hipMemcpyDeviceToHost, ctx->stream));
   HIP_TRY(hipStreamSynchronize(ctx->stream));

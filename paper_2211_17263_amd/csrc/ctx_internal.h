@@ -19,13 +19,14 @@ hipError_t launch_tau(hipStream_t st, int est, int d, int P, uint64_t seed, cons
 hipError_t launch_render(hipStream_t st, const DevScene& sc, int W, int H, const float* X, int nk,
                          int d, int tag, uint64_t seed, const float* ref, float* img,
                          float* partial, unsigned long long* counters, int* work,
-                         const int* order, float* cost);
+                         const int* order, float* cost, int crn);
 // tiles by descending measured render time (no-op for more than 4096 tiles)
 hipError_t launch_tile_order(hipStream_t st, const float* cost, int* order, int n_tiles);
 hipError_t launch_losses(hipStream_t st, const float* partial, int n_tiles, int N, int npix,
                          double* losses);
-hipError_t launch_combine(hipStream_t st, int P, int d, const double* c, const double* L,
-                          const double* scale, double* grad, double* loss);
+// rows = pairs (antithetic) or draws (independent != 0)
+hipError_t launch_combine(hipStream_t st, int rows, int d, int independent, const double* c,
+                          const double* L, const double* scale, double* grad, double* loss);
 hipError_t launch_batch(hipStream_t st, const BatchReq* reqs, BatchMeta* meta, int render_blocks,
                         float* tau, double* c, float* X, float* partial, double* losses,
                         double* grads, double* loss);

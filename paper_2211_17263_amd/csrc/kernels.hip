@@ -575,14 +575,17 @@ __device__ __forceinline__ void render_tile(const SceneHdr& S, const Node* __res
                                             uint32_t k0, uint32_t k1, const float* __restrict__ ref,
                                             float* __restrict__ img, float* partial_slot,
                                             unsigned long long* __restrict__ counters,
-                                            int* __restrict__ stack, float* __restrict__ wsum) {
+                                            int* __restrict__ stack, float* __restrict__ wsum,
+                                            int crn) {
   const int tiles_x = (S.W + kTileW - 1) / kTileW;
   const int t = threadIdx.x;
   const int lx = (t & 7) + 8 * (t >> 6), ly = (t >> 3) & 7;
   const int x = (tile % tiles_x) * kTileW + lx, y = (tile / tiles_x) * kTileH + ly;
   const bool valid = x < S.W && y < S.H;
   const int pix = y * S.W + x;
-  const int pair = k >> 1;
+  // path streams: the two renders of an antithetic pair share stream k / 2
+  // (common random numbers); independent renders (crn = 0) use stream k
+  const int pair = crn ? k >> 1 : k;
   const int spp = S.spp;
   const int n_lights = S.n_pl + S.n_area;
   int* stk = stack + t;
@@ -872,7 +875,7 @@ __global__ __launch_bounds__(kBlock, PRDPT_MIN_WAVES_PER_EU) void render_loss_ke
     DevScene scene, const float* __restrict__ X, int d, int tag, uint32_t k0, uint32_t k1,
     const float* __restrict__ ref, float* __restrict__ img, float* __restrict__ partial,
     unsigned long long* __restrict__ counters, int n_tiles, int n_items, int* __restrict__ work,
-    const int* __restrict__ order, float* __restrict__ cost) {
+    const int* __restrict__ order, float* __restrict__ cost, int crn) {
   __shared__ SceneHdr S;
   __shared__ int stack[kStackEntries * kBlock];
   __shared__ float wsum[kBlock / 64];
@@ -895,7 +898,7 @@ __global__ __launch_bounds__(kBlock, PRDPT_MIN_WAVES_PER_EU) void render_loss_ke
     if (cost && threadIdx.x == 0) t0 = wall_clock64();
     render_tile<COUNT>(S, scene.nodes, scene.tris, k, tile, tag, k0, k1, ref, img,
                        partial ? partial + (size_t)k * n_tiles + tile : nullptr, counters, stack,
-                       wsum);
+                       wsum, crn);
     if (cost && threadIdx.x == 0) cost[tile] = (float)(wall_clock64() - t0);
     __syncthreads();
   }
@@ -942,7 +945,8 @@ __global__ __launch_bounds__(1024) void tile_order_kernel(const float* __restric
 }
 
 // Perturbation draw for pair p (Sec. 3.2): Philox TAU stream words in order,
-// tau_p, binary64 pair weights c_p, and the parameter rows theta +- tau_p.
+// tau_p, binary64 pair weights c_p, and the parameter rows theta +- tau_p
+// (Xm null: draw p of independent perturbations, row theta + tau_p only).
 // Rows are written with stride `ld` (>= d).
 __device__ void draw_pair(int est, int d, int p, uint32_t k0, uint32_t k1,
                           const float* __restrict__ sigma, const float* __restrict__ theta,
@@ -973,6 +977,10 @@ __device__ void draw_pair(int est, int d, int p, uint32_t k0, uint32_t k1,
   float v[PRDPT_MAX_PARAMS];
   float tv[PRDPT_MAX_PARAMS];
   double cw[PRDPT_MAX_PARAMS];
+  // without antithetic partners each draw carries the single-sample score
+  // weight, twice the pair weight (exact in binary64)
+  const double wscale = (est & PRDPT_EST_INDEPENDENT) ? 2.0 : 1.0;
+  est &= ~PRDPT_EST_INDEPENDENT;
   if (est == PRDPT_EST_GAUSS) {
     for (int j = 0; j < d; j += 2) {
       float z0, z1;
@@ -1020,9 +1028,9 @@ __device__ void draw_pair(int est, int d, int p, uint32_t k0, uint32_t k1,
   }
   for (int j = 0; j < d; ++j) {
     tau[j] = tv[j];
-    c[j] = cw[j];
+    c[j] = wscale * cw[j];
     Xp[j] = theta[j] + tv[j];
-    Xm[j] = theta[j] - tv[j];
+    if (Xm) Xm[j] = theta[j] - tv[j];
   }
   (void)ld;
 }
@@ -1057,15 +1065,38 @@ __device__ __forceinline__ void combine_one(int P, int d, int ld, const double* 
   }
 }
 
-// One thread per antithetic pair: tau_p, weights c_p and the two parameter rows.
+// Independent perturbations: g_j = scale (1/N) sum_i c_ij L_i, Q = mean L.
+__device__ __forceinline__ void combine_independent(int N, int d, const double* __restrict__ c,
+                                                    const double* __restrict__ L, double sc,
+                                                    double* __restrict__ grad,
+                                                    double* __restrict__ loss) {
+  const int j = threadIdx.x;
+  if (j < d) {
+    double acc = 0.0;
+    for (int i = 0; i < N; ++i) acc += c[(size_t)i * d + j] * L[i];
+    grad[j] = sc * (acc / (double)N);
+  }
+  if (j == 0 && loss) {
+    double s = 0.0;
+    for (int i = 0; i < N; ++i) s += L[i];
+    *loss = s / (double)N;
+  }
+}
+
+// One thread per antithetic pair: tau_p, weights c_p and the two parameter rows
+// (or, with PRDPT_EST_INDEPENDENT, one thread per independent draw).
 __global__ void tau_kernel(int est, int d, int P, uint32_t k0, uint32_t k1,
                            const float* __restrict__ sigma, const float* __restrict__ theta,
                            double cd, double sqrt2pi, float* __restrict__ tau,
                            double* __restrict__ c, float* __restrict__ X) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= P) return;
-  draw_pair(est, d, p, k0, k1, sigma, theta, cd, sqrt2pi, d, tau + (size_t)p * d, c + (size_t)p * d,
-            X + (size_t)(2 * p) * d, X + (size_t)(2 * p + 1) * d);
+  if (est & PRDPT_EST_INDEPENDENT)  // P independent draws, one parameter row each
+    draw_pair(est, d, p, k0, k1, sigma, theta, cd, sqrt2pi, d, tau + (size_t)p * d,
+              c + (size_t)p * d, X + (size_t)p * d, nullptr);
+  else
+    draw_pair(est, d, p, k0, k1, sigma, theta, cd, sqrt2pi, d, tau + (size_t)p * d,
+              c + (size_t)p * d, X + (size_t)(2 * p) * d, X + (size_t)(2 * p + 1) * d);
 }
 
 __global__ void loss_kernel(const float* __restrict__ partial, int n_tiles, int N, double inv_den,
@@ -1075,10 +1106,13 @@ __global__ void loss_kernel(const float* __restrict__ partial, int n_tiles, int 
   if (threadIdx.x == 0) losses[k] = L;
 }
 
-__global__ void combine_kernel(int P, int d, const double* __restrict__ c,
+__global__ void combine_kernel(int rows, int d, int independent, const double* __restrict__ c,
                                const double* __restrict__ L, const double* __restrict__ scale,
                                double* __restrict__ grad, double* __restrict__ loss) {
-  combine_one(P, d, d, c, L, scale ? *scale : 1.0, grad, loss);
+  if (independent)
+    combine_independent(rows, d, c, L, scale ? *scale : 1.0, grad, loss);
+  else
+    combine_one(rows, d, d, c, L, scale ? *scale : 1.0, grad, loss);
 }
 
 // ---------------------------------------------------------------------------
@@ -1146,7 +1180,7 @@ __global__ __launch_bounds__(kBlock, PRDPT_MIN_WAVES_PER_EU) void batch_render_k
     for (int tile = first; tile < last; ++tile) {
       render_tile<false>(S, q.scene.nodes, q.scene.tris, k, tile, kTagPath, q.k0, q.k1, q.ref,
                          nullptr, partial + (size_t)q.partial_base + (size_t)k * q.n_tiles + tile,
-                         nullptr, stack, wsum);
+                         nullptr, stack, wsum, 1);
       __syncthreads();
     }
   }
@@ -1218,7 +1252,7 @@ int render_grid_limit() {
 hipError_t launch_render(hipStream_t st, const DevScene& sc, int W, int H, const float* X, int nk,
                          int d, int tag, uint64_t seed, const float* ref, float* img,
                          float* partial, unsigned long long* counters, int* work,
-                         const int* order, float* cost) {
+                         const int* order, float* cost, int crn) {
   const int n_tiles = render_tiles(W, H);
   const int n_items = n_tiles * nk;
   const int limit = render_grid_limit();
@@ -1228,11 +1262,11 @@ hipError_t launch_render(hipStream_t st, const DevScene& sc, int W, int H, const
   if (counters)
     hipLaunchKernelGGL(render_loss_kernel<true>, dim3(blocks), dim3(kBlock), 0, st, sc, X, d, tag,
                        (uint32_t)seed, (uint32_t)(seed >> 32), ref, img, partial, counters,
-                       n_tiles, n_items, work, order, cost);
+                       n_tiles, n_items, work, order, cost, crn);
   else
     hipLaunchKernelGGL(render_loss_kernel<false>, dim3(blocks), dim3(kBlock), 0, st, sc, X, d, tag,
                        (uint32_t)seed, (uint32_t)(seed >> 32), ref, img, partial, counters,
-                       n_tiles, n_items, work, order, cost);
+                       n_tiles, n_items, work, order, cost, crn);
   return hipGetLastError();
 }
 
@@ -1249,9 +1283,10 @@ hipError_t launch_losses(hipStream_t st, const float* partial, int n_tiles, int 
   return hipGetLastError();
 }
 
-hipError_t launch_combine(hipStream_t st, int P, int d, const double* c, const double* L,
-                          const double* scale, double* grad, double* loss) {
-  hipLaunchKernelGGL(combine_kernel, dim3(1), dim3(64), 0, st, P, d, c, L, scale, grad, loss);
+hipError_t launch_combine(hipStream_t st, int rows, int d, int independent, const double* c,
+                          const double* L, const double* scale, double* grad, double* loss) {
+  hipLaunchKernelGGL(combine_kernel, dim3(1), dim3(64), 0, st, rows, d, independent, c, L, scale,
+                     grad, loss);
   return hipGetLastError();
 }
 

@@ -19,6 +19,7 @@ PRDPT_OK = 0
 PRDPT_E_ARG, PRDPT_E_NOMEM, PRDPT_E_ADMISSION, PRDPT_E_HIP = -1, -2, -3, -4
 PRDPT_E_SCENE, PRDPT_E_CANCELLED, PRDPT_E_TIMEOUT = -5, -6, -7
 PRDPT_EST_GAUSS, PRDPT_EST_IS, PRDPT_EST_IS_PERDIM = 0, 1, 2
+PRDPT_EST_INDEPENDENT = 0x100   # or-ed into a mode: no antithetic partners (noAT)
 
 # every symbol declared in include/prdpt.h
 EXPORTS = [
@@ -110,7 +111,7 @@ def load():
     L.prdpt_smoothed_loss.argtypes = [vp, vp, vp, vp, i32, u64, vp]
     L.prdpt_grad_estimate.argtypes = [vp, vp, vp, vp, i32, u64, i32, vp, vp, vp]
     L.prdpt_grad_estimate_async.argtypes = [vp, vp, vp, vp, i32, u64, i32, vp, vp, vp, vp]
-    L.prdpt_combine_async.argtypes = [vp, i32, i32, vp, vp, vp, vp]
+    L.prdpt_combine_async.argtypes = [vp, i32, i32, vp, vp, vp, vp, i32]
     L.prdpt_ctx_set_timing.argtypes = [vp, i32]
     L.prdpt_ctx_read_timing.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
     L.prdpt_traversal_counts.argtypes = [vp, vp, vp, i32, u64, i32, vp]
@@ -269,7 +270,8 @@ def prdpt_render_perturbed(scene, theta, sigma, N, seed, est, images=None):
     if images is None:
         images = torch.empty((N, scene.H, scene.W, 3), dtype=torch.float32,
                              device=f"cuda:{scene.ctx.device}")
-    tau = np.zeros((max(N // 2, 1), scene.d), np.float32)
+    rows = N if int(est) & PRDPT_EST_INDEPENDENT else N // 2
+    tau = np.zeros((max(rows, 1), scene.d), np.float32)
     _check(load().prdpt_render_perturbed(scene.h, tp, sp, int(N), int(seed), int(est),
                                          _dev(images, torch.float32), tau.ctypes.data_as(C.c_void_p)))
     return images, tau
@@ -374,12 +376,13 @@ def prdpt_adam_step(theta, grad, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
                                   float(beta2), float(eps)))
 
 
-def prdpt_combine_async(ctx, P, d, c, losses, scale, grad):
+def prdpt_combine_async(ctx, rows, d, c, losses, scale, grad, est=PRDPT_EST_IS):
+    """rows = pairs (antithetic) or draws (est with PRDPT_EST_INDEPENDENT)."""
     import torch
-    _check(load().prdpt_combine_async(ctx.h, int(P), int(d), _dev(c, torch.float64),
+    _check(load().prdpt_combine_async(ctx.h, int(rows), int(d), _dev(c, torch.float64),
                                       _dev(losses, torch.float64),
                                       _dev(scale, torch.float64) if scale is not None else None,
-                                      _dev(grad, torch.float64)))
+                                      _dev(grad, torch.float64), int(est)))
 
 
 class BatchRequest:

@@ -37,8 +37,12 @@ def assert_images_match(gpu, orc, what=""):
 
 
 def grad_scale(c, L):
+    """S_j = (1/P) sum_p |c_pj| (L_2p + L_2p+1) for antithetic pair weights, or
+    (1/N) sum_i |c_ij| L_i for independent draws (one weight row per loss)."""
     c = np.asarray(c, np.float64)
     L = np.asarray(L, np.float64)
+    if c.shape[0] == L.shape[0]:
+        return (np.abs(c) * L[:, None]).mean(axis=0)
     return (np.abs(c) * (L[0::2] + L[1::2])[:, None]).mean(axis=0)
 
 

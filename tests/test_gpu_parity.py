@@ -41,7 +41,8 @@ def to_dev(a):
     return torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda()
 
 
-@pytest.mark.parametrize("mode", [O.GAUSS, O.IS, O.IS_PERDIM])
+@pytest.mark.parametrize("mode", [O.GAUSS, O.IS, O.IS_PERDIM, O.IS | O.INDEPENDENT,
+                                  O.GAUSS | O.INDEPENDENT])
 @pytest.mark.parametrize("d", [1, 2, 3, 6, 12, 32])
 def test_perturbation_draw_bit_exact(ctx, mode, d):
     from paper_2211_17263_amd import native as NV
@@ -73,7 +74,7 @@ def _full_parity(ctx, pr, seed, what, N=None, est=None, check_images=True):
                 PT.assert_images_match(gi[k], oimgs[k], f"{what} image {k}")
         r = NV.prdpt_grad_estimate(gs, to_dev(ref), pr["theta0"], pr["sigma"], N, seed, est)
         o = osc.grad_estimate(ref, pr["theta0"], pr["sigma"], N, seed, est)
-        _, c = O.draw_tau(est, pr["sigma"], N // 2, seed)
+        _, c = O.draw_tau(est, pr["sigma"], N if est & O.INDEPENDENT else N // 2, seed)
         PT.assert_losses_match(r["losses"], o["losses"], what)
         PT.assert_grad_match(r["grad"], o["grad"], c, o["losses"], what)
         assert abs(r["loss"] - o["loss"]) <= PT.LOSS_REL * abs(o["loss"])
@@ -92,6 +93,19 @@ def test_toy_workload_full(ctx):
 def test_toy_workload_is_mode(ctx, seed):
     pr = S.toy_problem(seed=seed)
     _full_parity(ctx, pr, seed, "toy-is", est=O.IS, N=8)
+
+
+@pytest.mark.parametrize("est", [O.GAUSS | O.INDEPENDENT, O.IS | O.INDEPENDENT])
+def test_independent_perturbations_toy(ctx, est):
+    # the noAT arm: N independent draws, one render each with its own paths
+    pr = S.toy_problem(seed=2)
+    r, o = _full_parity(ctx, pr, 13, "toy-independent", est=est, N=6)
+    assert np.any(r["grad"] != 0)
+
+
+def test_independent_perturbations_cornell_reduced(ctx):
+    pr = S.cornell_problem(seed=2, width=64, height=48, spp=4, ico_level=3)
+    _full_parity(ctx, pr, 8, "cornell-reduced-independent", est=O.IS | O.INDEPENDENT, N=6)
 
 
 def test_cornell_reduced(ctx):
@@ -186,7 +200,18 @@ def test_async_and_combine(ctx):
         assert np.array_equal(L.cpu().numpy(), sync["losses"])
         g2 = torch.zeros(d, dtype=torch.float64, device="cuda")
         scale = torch.tensor([2.5], dtype=torch.float64, device="cuda")
-        NV.prdpt_combine_async(ctx, N // 2, d, c, L, scale, g2)
+        NV.prdpt_combine_async(ctx, N // 2, d, c, L, scale, g2, O.GAUSS)
+        torch.cuda.synchronize()
+        np.testing.assert_allclose(g2.cpu().numpy(), 2.5 * sync["grad"], rtol=1e-15)
+        # the same with independent perturbations (one weight row per render)
+        est = O.GAUSS | O.INDEPENDENT
+        sync = NV.prdpt_grad_estimate(gs, to_dev(ref), pr["theta0"], pr["sigma"], N, 9, est)
+        c = torch.zeros(N, d, dtype=torch.float64, device="cuda")
+        NV.prdpt_grad_estimate_async(gs, to_dev(ref), to_dev(pr["theta0"]), to_dev(pr["sigma"]),
+                                     N, 9, est, g, q, L, c)
+        torch.cuda.synchronize()
+        assert np.array_equal(g.cpu().numpy(), sync["grad"])
+        NV.prdpt_combine_async(ctx, N, d, c, L, scale, g2, est)
         torch.cuda.synchronize()
         np.testing.assert_allclose(g2.cpu().numpy(), 2.5 * sync["grad"], rtol=1e-15)
     finally:

@@ -213,3 +213,60 @@ def test_plateau_loss_is_flat_without_overlap():
     assert loss((0.5, 0.5)) < 0.9 * min(flat)
     assert loss((0.3, 0.3)) < loss((0.5, 0.5))
     assert loss((0.0, 0.0)) == 0.0
+
+
+def estimate_independent(mode, theta, sigma, N, seed, Lfun):
+    """Independent draws (no antithetic partner): g = mean of c_i L(theta + tau_i)."""
+    theta = np.asarray(theta, np.float32)
+    sigma = np.asarray(sigma, np.float32)
+    tau, c = O.draw_tau(mode | O.INDEPENDENT, sigma, N, seed)
+    X = (theta[None, :] + tau).astype(np.float32)
+    L = Lfun(X.astype(np.float64))
+    g, q = O.combine_independent(c, L)
+    terms = c * L[:, None]
+    se = terms.std(axis=0, ddof=1) / math.sqrt(N)
+    return g, q, se, terms
+
+
+@pytest.mark.parametrize("mode", [O.GAUSS, O.IS])
+@pytest.mark.parametrize("theta,a,sigma", [(0.3, 0.0, 0.5), (-0.7, 0.2, 0.25)])
+def test_independent_erf_step_1d(mode, theta, a, sigma):
+    # without antithetic partners the estimator stays unbiased (Sec. 5.3's noAT arm)
+    g, q, se, _ = estimate_independent(mode, [theta], [sigma], 80000, 23, step(a))
+    truth = phi((theta - a) / sigma) / sigma
+    assert abs(g[0] - truth) <= 4 * se[0], (g, truth, se)
+
+
+@pytest.mark.parametrize("mode", [O.GAUSS, O.IS])
+def test_independent_product_of_steps_and_quadratic(mode):
+    theta = np.array([0.2, -0.1])
+    a = np.array([0.5, -0.3])
+    sigma = np.array([0.3, 0.5])
+    L = lambda X: ((X[:, 0] > a[0]) & (X[:, 1] > a[1])).astype(np.float64)
+    g, q, se, _ = estimate_independent(mode, theta, sigma, 120000, 31, L)
+    z = (theta - a) / sigma
+    truth = np.array([phi(z[0]) / sigma[0] * Phi(z[1]), phi(z[1]) / sigma[1] * Phi(z[0])])
+    assert np.all(np.abs(g - truth) <= 4 * se), (g, truth, se)
+    rng = np.random.default_rng(3)
+    d = 6
+    th = rng.uniform(-1, 1, d).astype(np.float32)
+    cc = rng.uniform(-1, 1, d)
+    sg = rng.uniform(0.1, 0.6, d).astype(np.float32)
+    Lq = lambda X: ((X - cc[None, :]) ** 2).sum(axis=1)
+    g, q, se, _ = estimate_independent(mode, th, sg, 200000, 5, Lq)
+    truth = 2.0 * (th.astype(np.float64) - cc)
+    assert np.all(np.abs(g - truth) <= 4 * se), (g, truth, se)
+
+
+def test_independent_weights_are_twice_the_pair_weights_and_lose_zero_variance():
+    # same draws; single-sample score weights = 2 x antithetic pair weights; at the
+    # step (theta = a) the antithetic estimate has zero variance, the
+    # independent one does not
+    for mode in (O.GAUSS, O.IS, O.IS_PERDIM):
+        t1, c1 = O.draw_tau(mode, [0.5, 0.3, 0.2], 64, 9)
+        t2, c2 = O.draw_tau(mode | O.INDEPENDENT, [0.5, 0.3, 0.2], 64, 9)
+        assert np.array_equal(t1, t2) and np.array_equal(2.0 * c1, c2)
+    *_, terms_at, _, _ = estimate(O.IS, [0.0], [0.5], 2000, 3, step(0.0))
+    _, _, _, terms_ind = estimate_independent(O.IS, [0.0], [0.5], 2000, 3, step(0.0))
+    assert np.ptp(terms_at) == 0.0
+    assert terms_ind.std() > 0.5 * np.abs(terms_ind.mean())
