@@ -77,7 +77,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="cornell",
-                    choices=["cornell", "toy", "caustic", "batch", "serve", "inverse"])
+                    choices=["cornell", "toy", "caustic", "batch", "serve", "inverse", "ablation"])
     ap.add_argument("--serve-seconds", type=float, default=20.0,
                     help="serve workload: length of each arrival phase")
     ap.add_argument("--serve-rate", type=float, default=200.0,
@@ -110,6 +110,8 @@ def main():
         return bench_serve(args, NV)
     if args.workload == "inverse":
         return bench_inverse(args, NV)
+    if args.workload == "ablation":
+        return bench_ablation(args, NV)
 
     pr, desc, sigma0, sigma_end = workload(args.workload)
     scene = pr["scene"]
@@ -288,6 +290,90 @@ def bench_inverse(args, NV):
     out["higher_is_better"] = True
     sc.destroy()
     ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+def bench_ablation(args, NV):
+    """Estimator ablation (Sec. 5.3: noIS, noAP, noAT) and variance study: per
+    estimator arm, the per-render gradient variance and bias against a
+    high-precision reference gradient on the global-illumination workload and
+    on the plateau scene, the renders needed for 10 % relative RMS error, and
+    the final parameter MSE of the optimisation with each component removed."""
+    import torch
+    from paper_2211_17263_amd import optimize as OP
+    from paper_2211_17263_amd import scenes as S
+    I = NV.PRDPT_EST_INDEPENDENT
+    arms = {"is (full)": NV.PRDPT_EST_IS, "gauss (noIS)": NV.PRDPT_EST_GAUSS,
+            "is, independent (noAT)": NV.PRDPT_EST_IS | I,
+            "gauss, independent (noIS+noAT)": NV.PRDPT_EST_GAUSS | I,
+            "is per-dimension": NV.PRDPT_EST_IS_PERDIM}
+    ctx = NV.Context(0)
+    out = {"metric": "estimator variance per render and ablated optimisation", "n_gpus": 1,
+           "data": "synthetic", "dtype": "f32", "config": {"workload": "ablation"}}
+
+    def study(sc, ref, theta, sigma, N, K, K_ref):
+        rg = np.array([NV.prdpt_grad_estimate(sc, ref, theta, sigma, N, 50000 + i,
+                                              NV.PRDPT_EST_IS)["grad"] for i in range(K_ref)])
+        refg, ref_var = rg.mean(0), rg.var(0, ddof=1) / K_ref
+        res = {"reference_grad": refg.tolist(), "N": N, "estimates_per_arm": K,
+               "reference_estimates": K_ref}
+        norm2 = float(np.dot(refg, refg))
+        for name, est in arms.items():
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            gs = np.array([NV.prdpt_grad_estimate(sc, ref, theta, sigma, N, 1000 + i, est)["grad"]
+                           for i in range(K)])
+            ms = 1e3 * (time.perf_counter() - t0) / K
+            mean, var = gs.mean(0), gs.var(0, ddof=1)
+            per_render = float(N * var.sum() / norm2)        # relative, summed over components
+            se = np.sqrt(var / K + ref_var) + 1e-300     # arm mean minus reference mean
+            res[name] = {"variance_per_render_rel": per_render,
+                         "max_bias_in_se": float(np.max(np.abs(mean - refg) / se)),
+                         "rel_bias": float(np.linalg.norm(mean - refg) / np.sqrt(norm2)),
+                         "renders_for_10pct_rms": per_render / 0.01,
+                         "ms_per_estimate": ms}
+        return res
+    log("ablation: variance on the global-illumination workload")
+    pr = S.cornell_problem(seed=2)
+    sc = NV.prdpt_scene_create(ctx, pr["scene"])
+    ref = NV.prdpt_render_reference(sc, pr["theta_ref"], args.seed + 7)
+    # at the workload's start the light is 0.06 below the ceiling and sigma =
+    # 0.3, so many perturbations lift it through the ceiling and black out the
+    # image: a heavy-tailed estimate; the second point keeps crossings rare
+    out["variance_gi"] = study(sc, ref, pr["theta0"], pr["sigma"], 16, 96, 384)
+    th_low = pr["theta0"].copy()
+    th_low[1] = -0.3
+    out["variance_gi_light_low"] = study(sc, ref, th_low, np.full(6, 0.1, np.float32), 16, 96, 384)
+    out["variance_gi_light_low"]["theta"] = th_low.tolist()
+    log("ablation: optimisation on the global-illumination workload")
+    gi = {}
+    for name, est, warm in (("full", NV.PRDPT_EST_IS, 0.5), ("noIS", NV.PRDPT_EST_GAUSS, 0.5),
+                            ("noAP", NV.PRDPT_EST_IS, 1.0), ("noAT", NV.PRDPT_EST_IS | I, 0.5)):
+        tr = OP.optimize(sc, ref, pr["theta0"], 0.125, 400, 0.01, 16, est=est, seed=args.seed,
+                         warm_start=warm, theta_ref=pr["theta_ref"], eval_every=400)
+        gi[name] = {"param_mse": tr.param_mse[-1], "image_mse": tr.image_mse[-1][1]}
+    out["optimisation_gi"] = dict(gi, steps=400, N=16, sigma0=0.125, lr=0.01,
+                                  start_param_mse=tr.param_mse[0])
+    sc.destroy()
+    log("ablation: plateau scene")
+    sc = NV.prdpt_scene_create(ctx, S.plateau_scene())
+    tref = np.zeros(2, np.float32)
+    th0 = np.array([0.9, 0.9], np.float32)
+    ref = NV.prdpt_render_reference(sc, tref, 5)
+    out["variance_plateau"] = study(sc, ref, th0, np.full(2, 0.5, np.float32), 4, 400, 4000)
+    pl = {}
+    for name, est, warm in (("full", NV.PRDPT_EST_IS, 0.5), ("noIS", NV.PRDPT_EST_GAUSS, 0.5),
+                            ("noAP", NV.PRDPT_EST_IS, 1.0), ("noAT", NV.PRDPT_EST_IS | I, 0.5)):
+        r = [OP.optimize(sc, ref, th0, 0.5, 300, 0.02, 4, est=est, seed=sd, warm_start=warm,
+                         theta_ref=tref).param_mse[-1] for sd in (100, 1100, 2100)]
+        pl[name] = float(np.median(r))
+    out["optimisation_plateau"] = dict(pl, steps=300, N=4, sigma0=0.5, lr=0.02,
+                                       start_param_mse=float(np.mean(th0 ** 2)), median_of_seeds=3)
+    sc.destroy()
+    ctx.close()
+    out["value"] = out["variance_gi"]["is (full)"]["variance_per_render_rel"]
+    out["unit"] = "relative gradient variance per render (IS, GI workload)"
+    out["higher_is_better"] = False
     print(json.dumps(out), flush=True)
 
 
