@@ -80,6 +80,8 @@ extern "C" {
 #define PRDPT_BIND_QUAD 1   /* quad origin component */
 #define PRDPT_BIND_MESH 2   /* mesh translation component */
 #define PRDPT_BIND_PLIGHT 3 /* point-light position component */
+#define PRDPT_BIND_ALBEDO 4 /* material colour channel: albedo of a diffuse material,
+                               radiance of an emissive one */
 
 /* Limits of one scene. */
 #define PRDPT_MAX_PARAMS 32

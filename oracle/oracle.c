@@ -469,6 +469,7 @@ typedef struct {
   float* quad;
   float* xlate;
   float* pl;
+  float* rgb;   /* material colours */
 } kstate;
 
 static void kstate_init(const orc_scene* s, const float* X, kstate* k) {
@@ -476,17 +477,19 @@ static void kstate_init(const orc_scene* s, const float* X, kstate* k) {
   DUP(k->quad, s->quad, 9 * s->n_quad, float);
   DUP(k->xlate, s->mesh_xlate, 3 * s->n_mesh, float);
   DUP(k->pl, s->pl, 6 * s->n_pl, float);
+  DUP(k->rgb, s->mat_rgb, 3 * s->n_mat, float);
   for (int j = 0; j < s->n_param; ++j) {
     int kind = s->binding[3 * j], i = s->binding[3 * j + 1], c = s->binding[3 * j + 2];
     if (kind == ORC_BIND_SPHERE) k->sph[4 * i + c] = s->sph[4 * i + c] + X[j];
     else if (kind == ORC_BIND_QUAD) k->quad[9 * i + c] = s->quad[9 * i + c] + X[j];
     else if (kind == ORC_BIND_MESH) k->xlate[3 * i + c] = s->mesh_xlate[3 * i + c] + X[j];
     else if (kind == ORC_BIND_PLIGHT) k->pl[6 * i + c] = s->pl[6 * i + c] + X[j];
+    else if (kind == ORC_BIND_ALBEDO) k->rgb[3 * i + c] = s->mat_rgb[3 * i + c] + X[j];
   }
 }
 
 static void kstate_free(kstate* k) {
-  free(k->sph); free(k->quad); free(k->xlate); free(k->pl);
+  free(k->sph); free(k->quad); free(k->xlate); free(k->pl); free(k->rgb);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -738,7 +741,7 @@ static void trace_path(const orc_scene* s, const kstate* k, const uint32_t key[2
     v3 ng;
     prim_info(s, k, h.id, p, &mat, &ng);
     int mt = s->mat_type[mat];
-    const float* rgb = s->mat_rgb + 3 * mat;
+    const float* rgb = k->rgb + 3 * mat;
     if (mt == ORC_EMISSIVE) {
       if (specular && vdot(d, ng) < 0.0f)
         for (int c = 0; c < 3; ++c) L[c] = L[c] + beta[c] * rgb[c];
@@ -794,7 +797,7 @@ static void trace_path(const orc_scene* s, const kstate* k, const uint32_t key[2
         closest(s, k, spawn(p, n), wi, dist * 0.9999f, 1, &hs);
         if (hs.id >= 0) continue;
         float G = ((cx * cl) * area) / dist2;
-        const float* le = s->mat_rgb + 3 * qm;
+        const float* le = k->rgb + 3 * qm;
         for (int c = 0; c < 3; ++c) L[c] = L[c] + beta[c] * f[c] * le[c] * G;
       }
       if (v == s->B) break;

@@ -20,7 +20,8 @@ extern "C" {
 #endif
 
 enum { ORC_DIFFUSE = 0, ORC_DIELECTRIC = 1, ORC_EMISSIVE = 2 };
-enum { ORC_BIND_SPHERE = 0, ORC_BIND_QUAD = 1, ORC_BIND_MESH = 2, ORC_BIND_PLIGHT = 3 };
+enum { ORC_BIND_SPHERE = 0, ORC_BIND_QUAD = 1, ORC_BIND_MESH = 2, ORC_BIND_PLIGHT = 3,
+       ORC_BIND_ALBEDO = 4 /* material colour channel: albedo (diffuse) or radiance (emissive) */ };
 enum { ORC_EST_GAUSS = 0, ORC_EST_IS = 1, ORC_EST_IS_PERDIM = 2 };
 /* flag or-ed into a mode: independent perturbations without the antithetic
  * partner (the paper's noAT ablation, Sec. 5.3): N draws, one render each at

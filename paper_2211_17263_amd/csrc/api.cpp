@@ -301,7 +301,8 @@ int prdpt::build_host_scene(const prdpt_scene_desc* D, HostScene& hs) {
   for (int j = 0; j < D->n_params; ++j) {
     const int kind = D->bindings[3 * j], idx = D->bindings[3 * j + 1], comp = D->bindings[3 * j + 2];
     const int lim = kind == PRDPT_BIND_SPHERE ? D->n_spheres : kind == PRDPT_BIND_QUAD ? D->n_quads
-                    : kind == PRDPT_BIND_MESH ? D->n_meshes : kind == PRDPT_BIND_PLIGHT ? D->n_point_lights : -1;
+                    : kind == PRDPT_BIND_MESH ? D->n_meshes : kind == PRDPT_BIND_PLIGHT ? D->n_point_lights
+                    : kind == PRDPT_BIND_ALBEDO ? D->n_materials : -1;
     if (lim < 0 || idx < 0 || idx >= lim || comp < 0 || comp > 2) {
       return fail(PRDPT_E_SCENE, "bad parameter binding");
     }
@@ -309,6 +310,9 @@ int prdpt::build_host_scene(const prdpt_scene_desc* D, HostScene& hs) {
       if (D->bindings[3 * i] == kind && D->bindings[3 * i + 1] == idx && D->bindings[3 * i + 2] == comp) {
         return fail(PRDPT_E_SCENE, "a field is bound twice");
       }
+    if (kind == PRDPT_BIND_ALBEDO && D->mat_type[idx] == PRDPT_MAT_DIELECTRIC) {
+      return fail(PRDPT_E_SCENE, "a dielectric material has no colour to bind");
+    }
     if (kind == PRDPT_BIND_MESH) bound[idx] = 1;
   }
   int n_inst = 0;

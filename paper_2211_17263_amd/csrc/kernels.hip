@@ -551,7 +551,8 @@ __device__ __forceinline__ void load_state(SceneHdr& S, const SceneHdr* __restri
       if (kind == PRDPT_BIND_SPHERE) S.sph[i][c] = g->sph[i][c] + xj;
       else if (kind == PRDPT_BIND_QUAD) S.quad[i][c] = g->quad[i][c] + xj;
       else if (kind == PRDPT_BIND_MESH) S.inst_xlate[i][c] = g->inst_xlate[i][c] + xj;
-      else S.pl[i][c] = g->pl[i][c] + xj;
+      else if (kind == PRDPT_BIND_PLIGHT) S.pl[i][c] = g->pl[i][c] + xj;
+      else if (kind == PRDPT_BIND_ALBEDO) S.mat_rgb[i][c] = g->mat_rgb[i][c] + xj;
     }
   }
   __syncthreads();

@@ -29,7 +29,7 @@ from typing import List
 import numpy as np
 
 DIFFUSE, DIELECTRIC, EMISSIVE = 0, 1, 2
-BIND_SPHERE, BIND_QUAD, BIND_MESH, BIND_PLIGHT = 0, 1, 2, 3
+BIND_SPHERE, BIND_QUAD, BIND_MESH, BIND_PLIGHT, BIND_ALBEDO = 0, 1, 2, 3, 4
 EST_GAUSS, EST_IS, EST_IS_PERDIM = 0, 1, 2
 
 
@@ -252,7 +252,9 @@ def toy_problem(seed=1, **kw):
 # ---------------------------------------------------------------------------
 # workload 2: Cornell-style box, movable area light + two jittered icospheres
 # ---------------------------------------------------------------------------
-def cornell_scene(seed=2, width=256, height=256, spp=16, bounces=4, ico_level=4):
+def cornell_scene(seed=2, width=256, height=256, spp=16, bounces=4, ico_level=4, colour=False):
+    """Cornell box; binds the area light's position (3) and the yellow sphere's
+    translation (3), and with colour=True also the left wall's albedo (3)."""
     rng = np.random.default_rng(seed)
     s = _new_scene("cornell", width, height, spp, bounces, eye=(0, 0, 3.4), look=(0, 0, 0))
     white = s.material(DIFFUSE, (0.73, 0.73, 0.73))
@@ -281,19 +283,30 @@ def cornell_scene(seed=2, width=256, height=256, spp=16, bounces=4, ico_level=4)
         s.bind(BIND_QUAD, lq, c)
     for c in range(3):
         s.bind(BIND_MESH, mesh_a, c)
+    if colour:
+        for c in range(3):
+            s.bind(BIND_ALBEDO, red, c)
     return s
 
 
-def cornell_problem(seed=2, **kw):
+def cornell_problem(seed=2, colour=False, **kw):
+    """Geometry (light position, sphere translation) and, with colour=True, the
+    left wall's colour as offsets from its initial albedo, which is theta_0's."""
     rng = np.random.default_rng(seed + 1000)
-    scene = cornell_scene(seed=seed, **kw)
+    scene = cornell_scene(seed=seed, colour=colour, **kw)
     theta_ref = np.array([rng.uniform(-0.3, 0.3), -0.02, rng.uniform(-0.3, 0.3),
                           rng.uniform(-0.2, 0.2), 0.0, rng.uniform(-0.2, 0.2)], np.float32)
     offs = rng.uniform(-0.5, 0.5, 6)
     offs[1] = -abs(offs[1]) * 0.6      # keep the light below the ceiling at theta_0
     theta0 = (theta_ref + offs).astype(np.float32)
-    return dict(scene=scene, theta_ref=theta_ref, theta0=theta0,
-                sigma=np.full(6, 0.3, np.float32), N=16, est=EST_IS)
+    sigma = np.full(6, 0.3, np.float32)
+    if colour:
+        base = np.array(scene.mat_rgb[1], np.float64)       # the red wall
+        target = rng.uniform(0.1, 0.9, 3)
+        theta_ref = np.concatenate([theta_ref, target - base]).astype(np.float32)
+        theta0 = np.concatenate([theta0, np.zeros(3)]).astype(np.float32)
+        sigma = np.concatenate([sigma, np.full(3, 0.2)]).astype(np.float32)
+    return dict(scene=scene, theta_ref=theta_ref, theta0=theta0, sigma=sigma, N=16, est=EST_IS)
 
 
 # ---------------------------------------------------------------------------

@@ -108,6 +108,29 @@ def test_independent_perturbations_cornell_reduced(ctx):
     _full_parity(ctx, pr, 8, "cornell-reduced-independent", est=O.IS | O.INDEPENDENT, N=6)
 
 
+def test_colour_bindings_cornell_reduced(ctx):
+    # light position, sphere translation and the left wall's albedo (d = 9)
+    pr = S.cornell_problem(seed=2, colour=True, width=64, height=48, spp=4, ico_level=3)
+    r, o = _full_parity(ctx, pr, 7, "cornell-reduced-colour")
+    assert np.all(r["grad"][6:] != 0)
+
+
+@pytest.mark.parametrize("est", [O.GAUSS, O.IS_PERDIM])
+def test_emission_and_albedo_bindings(ctx, est):
+    # the area light's radiance (emissive branch) and one wall channel
+    sc = S.cornell_scene(width=40, height=36, spp=3, bounces=3, ico_level=2)
+    sc.bindings = []
+    light = [i for i, t in enumerate(sc.mat_type) if t == S.EMISSIVE][0]
+    for c in range(3):
+        sc.bind(S.BIND_ALBEDO, light, c)
+    sc.bind(S.BIND_ALBEDO, 1, 0)
+    pr = dict(scene=sc, theta_ref=np.array([-3.0, 2.0, 0.0, 0.2], np.float32),
+              theta0=np.zeros(4, np.float32), sigma=np.array([2.0, 2.0, 2.0, 0.2], np.float32),
+              N=8, est=est)
+    r, o = _full_parity(ctx, pr, 12, "emission-albedo")
+    assert np.any(r["grad"] != 0)
+
+
 def test_cornell_reduced(ctx):
     pr = S.cornell_problem(seed=2, width=64, height=48, spp=4, ico_level=3)
     _full_parity(ctx, pr, 5, "cornell-reduced")
@@ -240,6 +263,15 @@ def test_error_codes(ctx):
         with pytest.raises(NV.PrdptError) as e:
             gpu_scene(ctx, bad2)
         assert e.value.code == NV.PRDPT_E_SCENE
+        # colour bindings: material index in range, and no dielectric
+        for idx in (len(S.toy_scene().mat_type), None):
+            bad3 = S.toy_scene()
+            if idx is None:
+                idx = bad3.material(S.DIELECTRIC, ior=1.5)
+            bad3.bind(S.BIND_ALBEDO, idx, 0)
+            with pytest.raises(NV.PrdptError) as e:
+                gpu_scene(ctx, bad3)
+            assert e.value.code == NV.PRDPT_E_SCENE
     finally:
         gs.destroy()
 

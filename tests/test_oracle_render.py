@@ -64,6 +64,81 @@ def test_lambertian_plane_point_light():
     np.testing.assert_allclose(img[..., 1], img[..., 0], rtol=0)
 
 
+def plane_irradiance_over_pi(sc):
+    """I h / (pi r^3) at each pixel-centre hit of the plane scene (binary64)."""
+    o, d = camera_rays_f64(sc)
+    t = -o[2] / d[..., 2]
+    p = o[None, None, :] + t[..., None] * d
+    lpos = np.array(sc.plights[0][:3], np.float64)
+    r = np.linalg.norm(lpos[None, None, :] - p, axis=-1)
+    return sc.plights[0][3] / math.pi * lpos[2] / r**3
+
+
+def test_albedo_binding_plane_closed_form():
+    # a colour binding offsets one channel of the material's albedo, which the
+    # Lambertian shading multiplies: channel c reads (rho_c + x_c) I h / (pi r^3)
+    sc = S.plane_scene()
+    sc.bind(S.BIND_ALBEDO, 0, 0)
+    sc.bind(S.BIND_ALBEDO, 0, 2)
+    img = O.OracleScene(sc).render(np.array([0.25, -0.125], np.float32))
+    A = plane_irradiance_over_pi(sc)
+    rho = sc.mat_rgb[0][0]
+    np.testing.assert_allclose(img[..., 0], (rho + 0.25) * A, rtol=2e-5)
+    np.testing.assert_allclose(img[..., 1], rho * A, rtol=2e-5)
+    np.testing.assert_allclose(img[..., 2], (rho - 0.125) * A, rtol=2e-5)
+
+
+@pytest.mark.parametrize("mode", [O.GAUSS, O.IS, O.GAUSS | O.INDEPENDENT])
+def test_albedo_gradient_of_quadratic_loss(mode):
+    # with albedo offsets x the plane's image is (rho + x) A per channel, so the
+    # loss is a quadratic in x: an antithetic difference is exactly 2 grad L . tau,
+    # and an independent draw's loss is L(theta) + grad L . tau + tau^T H tau / 2
+    sc = S.plane_scene()
+    sc.bind(S.BIND_ALBEDO, 0, 0)
+    sc.bind(S.BIND_ALBEDO, 0, 2)
+    osc = O.OracleScene(sc)
+    x_ref = np.array([0.1, -0.05], np.float32)
+    ref = osc.reference(x_ref)
+    theta = np.zeros(2, np.float32)
+    sigma = np.array([0.05, 0.08], np.float32)
+    N, seed = 8, 21
+    r = osc.grad_estimate(ref, theta, sigma, N, seed, mode)
+    A2 = (plane_irradiance_over_pi(sc) ** 2).mean()
+    grad = 2.0 / 3.0 * A2 * (theta - x_ref.astype(np.float64))   # mean over 3 channels
+    H = 2.0 / 3.0 * A2
+    tau = r["tau"].astype(np.float64)
+    if mode & O.INDEPENDENT:
+        # single-sample Gaussian weight tau / sigma^2 on L(theta + tau)
+        L0 = (2.0 / 3.0) * A2 * 0.5 * float(((theta - x_ref) ** 2).sum())
+        Li = L0 + tau @ grad + 0.5 * H * (tau ** 2).sum(1)
+        np.testing.assert_allclose(r["losses"], Li, rtol=1e-4)
+        want = ((tau / sigma.astype(np.float64) ** 2) * Li[:, None]).mean(0)
+    else:
+        if mode == O.GAUSS:
+            c = tau / (2.0 * sigma.astype(np.float64) ** 2)
+        else:
+            _, c = O.draw_tau(mode, sigma, N // 2, seed)
+        want = (c * (2.0 * (tau @ grad))[:, None]).mean(0)
+    np.testing.assert_allclose(r["grad"], want, rtol=2e-4)
+
+
+def test_emission_binding_is_linear_in_radiance():
+    # every contribution of a path carries one emitted radiance, and sampling
+    # does not depend on it: with the light's channel bound, that channel of
+    # the image scales by (Le + x) / Le at a fixed seed, the others are unchanged
+    sc = S.cornell_scene(width=24, height=20, spp=2, bounces=3, ico_level=1)
+    sc.bindings = []
+    light = [i for i, t in enumerate(sc.mat_type) if t == S.EMISSIVE][0]
+    sc.bind(S.BIND_ALBEDO, light, 1)
+    osc = O.OracleScene(sc)
+    a = osc.render(np.zeros(1, np.float32), seed=4)
+    b = osc.render(np.array([-6.0], np.float32), seed=4)
+    le = sc.mat_rgb[light][1]
+    np.testing.assert_array_equal(a[..., [0, 2]], b[..., [0, 2]])
+    np.testing.assert_allclose(b[..., 1], a[..., 1] * (le - 6.0) / le, rtol=1e-5, atol=1e-7)
+    assert a[..., 1].mean() > 0.05
+
+
 def test_shadow_boundary_against_analytic_geometry():
     # toy scene at a fixed sphere position, pixel-centre rays, direct light only:
     # every pixel classified analytically (binary64) as sphere / lit plane /
