@@ -82,6 +82,7 @@ extern "C" {
 #define PRDPT_BIND_PLIGHT 3 /* point-light position component */
 #define PRDPT_BIND_ALBEDO 4 /* material colour channel: albedo of a diffuse material,
                                radiance of an emissive one */
+#define PRDPT_BIND_MESH_ROT 5 /* mesh rotation angle (radians) about the x, y or z axis */
 
 /* Limits of one scene. */
 #define PRDPT_MAX_PARAMS 32
@@ -100,9 +101,12 @@ extern "C" {
  * Camera: pinhole at eye; the unnormalised direction of image point (sx, sy) in
  * [-1,1]^2 is fwd + sx*right + sy*up (right/up pre-scaled by the field of view;
  * row 0 is the top, sy = +1).  A parameter binding (kind, index, component)
- * makes that scalar field equal its base value plus theta_j (every parameter is
- * a translation).  A mesh is an instance: rays are moved by minus its
- * translation into its static BVH.
+ * makes that scalar field equal its base value plus theta_j.  A mesh is an
+ * instance: its vertex x is placed at R x + t, with t its translation and
+ * R = Rz(c) Ry(b) Rx(a) for its rotation angles (a, b, c) (rotations about the
+ * fixed x, y, z axes through the mesh's origin, applied in that order, formed
+ * in binary64 and rounded to binary32); rays are taken into the mesh's static
+ * BVH by R^T (o - t) and R^T d.
  */
 typedef struct {
   float eye[3], fwd[3], right[3], up[3];
@@ -131,6 +135,7 @@ typedef struct {
   const float* point_lights;  /* [n][6] position, intensity rgb */
   int32_t n_params;           /* d, 1..PRDPT_MAX_PARAMS */
   const int32_t* bindings;    /* [d][3] kind, index, component */
+  const float* mesh_rotation; /* [n_meshes][3] angles (a, b, c) in radians, or NULL (zero) */
 } prdpt_scene_desc;
 
 typedef struct prdpt_ctx prdpt_ctx;

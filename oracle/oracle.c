@@ -316,7 +316,7 @@ struct orc_scene {
   int32_t* mat_type; float* mat_rgb; float* mat_ior;
   float* sph; int32_t* sph_mat;
   float* quad; int32_t* quad_mat;
-  int32_t* mesh_off; int32_t* mesh_mat; float* mesh_xlate;
+  int32_t* mesh_off; int32_t* mesh_mat; float* mesh_xlate; float* mesh_rot;
   float* tri;
   float* pl;
   int32_t* binding;
@@ -429,6 +429,8 @@ orc_scene* orc_scene_new(const orc_scene_in* in) {
   DUP(s->mesh_off, in->mesh_off, in->n_mesh + 1, int32_t);
   DUP(s->mesh_mat, in->mesh_mat, in->n_mesh, int32_t);
   DUP(s->mesh_xlate, in->mesh_xlate, 3 * in->n_mesh, float);
+  s->mesh_rot = (float*)calloc((size_t)(in->n_mesh > 0 ? 3 * in->n_mesh : 1), sizeof(float));
+  if (in->mesh_rot) memcpy(s->mesh_rot, in->mesh_rot, sizeof(float) * 3 * (size_t)in->n_mesh);
   DUP(s->tri, in->tri, 9 * in->n_tri, float);
   DUP(s->pl, in->plight, 6 * in->n_plight, float);
   DUP(s->binding, in->binding, 3 * in->n_param, int32_t);
@@ -456,7 +458,7 @@ void orc_scene_free(orc_scene* s) {
   free(s->bvh);
   free(s->mat_type); free(s->mat_rgb); free(s->mat_ior);
   free(s->sph); free(s->sph_mat); free(s->quad); free(s->quad_mat);
-  free(s->mesh_off); free(s->mesh_mat); free(s->mesh_xlate);
+  free(s->mesh_off); free(s->mesh_mat); free(s->mesh_xlate); free(s->mesh_rot);
   free(s->tri); free(s->pl); free(s->binding);
   free(s);
 }
@@ -470,7 +472,37 @@ typedef struct {
   float* xlate;
   float* pl;
   float* rgb;   /* material colours */
+  float* ang;   /* mesh rotation angles */
+  float* rot;   /* [n_mesh][3][3] row-major rotation of each mesh (binary32) */
 } kstate;
+
+/* Rotation by the angles (a, b, c) about the fixed x, y and z axes, applied in
+ * that order: R = Rz(c) Ry(b) Rx(a), formed as a product of the three axis
+ * rotations in binary64 and rounded to binary32. */
+static void euler_matrix(const float ang[3], float R[9]) {
+  double A[3][3][3];
+  for (int ax = 0; ax < 3; ++ax) {
+    const double cs = cos((double)ang[ax]), sn = sin((double)ang[ax]);
+    const int u = (ax + 1) % 3, w = (ax + 2) % 3;  /* the plane the axis rotates */
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) A[ax][r][c] = r == c ? 1.0 : 0.0;
+    A[ax][u][u] = cs; A[ax][u][w] = -sn;
+    A[ax][w][u] = sn; A[ax][w][w] = cs;
+  }
+  double T[3][3], M[3][3];
+  for (int r = 0; r < 3; ++r)       /* T = Ry Rx */
+    for (int c = 0; c < 3; ++c) {
+      T[r][c] = 0.0;
+      for (int i = 0; i < 3; ++i) T[r][c] += A[1][r][i] * A[0][i][c];
+    }
+  for (int r = 0; r < 3; ++r)       /* M = Rz T */
+    for (int c = 0; c < 3; ++c) {
+      M[r][c] = 0.0;
+      for (int i = 0; i < 3; ++i) M[r][c] += A[2][r][i] * T[i][c];
+    }
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c) R[3 * r + c] = (float)M[r][c];
+}
 
 static void kstate_init(const orc_scene* s, const float* X, kstate* k) {
   DUP(k->sph, s->sph, 4 * s->n_sph, float);
@@ -478,6 +510,7 @@ static void kstate_init(const orc_scene* s, const float* X, kstate* k) {
   DUP(k->xlate, s->mesh_xlate, 3 * s->n_mesh, float);
   DUP(k->pl, s->pl, 6 * s->n_pl, float);
   DUP(k->rgb, s->mat_rgb, 3 * s->n_mat, float);
+  DUP(k->ang, s->mesh_rot, 3 * s->n_mesh, float);
   for (int j = 0; j < s->n_param; ++j) {
     int kind = s->binding[3 * j], i = s->binding[3 * j + 1], c = s->binding[3 * j + 2];
     if (kind == ORC_BIND_SPHERE) k->sph[4 * i + c] = s->sph[4 * i + c] + X[j];
@@ -485,11 +518,15 @@ static void kstate_init(const orc_scene* s, const float* X, kstate* k) {
     else if (kind == ORC_BIND_MESH) k->xlate[3 * i + c] = s->mesh_xlate[3 * i + c] + X[j];
     else if (kind == ORC_BIND_PLIGHT) k->pl[6 * i + c] = s->pl[6 * i + c] + X[j];
     else if (kind == ORC_BIND_ALBEDO) k->rgb[3 * i + c] = s->mat_rgb[3 * i + c] + X[j];
+    else if (kind == ORC_BIND_MESH_ROT) k->ang[3 * i + c] = s->mesh_rot[3 * i + c] + X[j];
   }
+  k->rot = (float*)malloc(sizeof(float) * 9 * (size_t)(s->n_mesh > 0 ? s->n_mesh : 1));
+  for (int m = 0; m < s->n_mesh; ++m) euler_matrix(k->ang + 3 * m, k->rot + 9 * m);
 }
 
 static void kstate_free(kstate* k) {
   free(k->sph); free(k->quad); free(k->xlate); free(k->pl); free(k->rgb);
+  free(k->ang); free(k->rot);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -631,9 +668,16 @@ static void closest(const orc_scene* s, const kstate* k, v3 o, v3 d, float tmax,
   }
   int tri_base = s->n_sph + s->n_quad;
   for (int m = 0; m < s->n_mesh; ++m) {
-    /* a mesh is an instance: the ray moves by minus the mesh translation */
-    v3 om = V(o.x - k->xlate[3 * m], o.y - k->xlate[3 * m + 1], o.z - k->xlate[3 * m + 2]);
-    mesh_hit(s, m, om, d, tmax, tri_base, h);
+    /* a mesh is an instance: the ray goes into the mesh's own frame by the
+     * inverse transform, R^T (o - translation) and R^T d (R orthonormal keeps
+     * the ray parameter t of a hit) */
+    const float* R = k->rot + 9 * m;
+    v3 q = V(o.x - k->xlate[3 * m], o.y - k->xlate[3 * m + 1], o.z - k->xlate[3 * m + 2]);
+    v3 om = V(R[0] * q.x + R[3] * q.y + R[6] * q.z, R[1] * q.x + R[4] * q.y + R[7] * q.z,
+              R[2] * q.x + R[5] * q.y + R[8] * q.z);
+    v3 dm = V(R[0] * d.x + R[3] * d.y + R[6] * d.z, R[1] * d.x + R[4] * d.y + R[7] * d.z,
+              R[2] * d.x + R[5] * d.y + R[8] * d.z);
+    mesh_hit(s, m, om, dm, tmax, tri_base, h);
   }
 }
 
@@ -669,7 +713,10 @@ static void prim_info(const orc_scene* s, const kstate* k, int id, v3 p, int* ma
   *mat = s->mesh_mat[m];
   const float* tv = s->tri + 9 * (size_t)id;
   v3 v0 = vld(tv);
-  *ng = vnorm(vcross(vsub(vld(tv + 3), v0), vsub(vld(tv + 6), v0)));
+  v3 nl = vcross(vsub(vld(tv + 3), v0), vsub(vld(tv + 6), v0));  /* mesh frame */
+  const float* R = k->rot + 9 * m;
+  *ng = vnorm(V(R[0] * nl.x + R[1] * nl.y + R[2] * nl.z, R[3] * nl.x + R[4] * nl.y + R[5] * nl.z,
+                R[6] * nl.x + R[7] * nl.y + R[8] * nl.z));
 }
 
 /* origin moved off the surface along n by 1e-4 max(1, |p|_inf) */

@@ -21,7 +21,8 @@ extern "C" {
 
 enum { ORC_DIFFUSE = 0, ORC_DIELECTRIC = 1, ORC_EMISSIVE = 2 };
 enum { ORC_BIND_SPHERE = 0, ORC_BIND_QUAD = 1, ORC_BIND_MESH = 2, ORC_BIND_PLIGHT = 3,
-       ORC_BIND_ALBEDO = 4 /* material colour channel: albedo (diffuse) or radiance (emissive) */ };
+       ORC_BIND_ALBEDO = 4, /* material colour channel: albedo (diffuse) or radiance (emissive) */
+       ORC_BIND_MESH_ROT = 5 /* mesh rotation angle (radians) about the x, y or z axis */ };
 enum { ORC_EST_GAUSS = 0, ORC_EST_IS = 1, ORC_EST_IS_PERDIM = 2 };
 /* flag or-ed into a mode: independent perturbations without the antithetic
  * partner (the paper's noAT ablation, Sec. 5.3): N draws, one render each at
@@ -41,6 +42,8 @@ typedef struct {
   int32_t n_tri;   const float* tri;                               /* [n][9] v0 v1 v2 */
   int32_t n_plight; const float* plight;                           /* [n][6] pos rgb */
   int32_t n_param; const int32_t* binding;                         /* [d][3] */
+  const float* mesh_rot;   /* [n_mesh][3] angles (a, b, c) or NULL (all zero): a mesh's
+                              vertex x maps to R x + translation, R = Rz(c) Ry(b) Rx(a) */
 } orc_scene_in;
 
 typedef struct orc_scene orc_scene;

@@ -53,7 +53,7 @@ class SceneIn(C.Structure):
                 ("mesh_xlate", C.c_void_p),
                 ("n_tri", C.c_int32), ("tri", C.c_void_p),
                 ("n_plight", C.c_int32), ("plight", C.c_void_p),
-                ("n_param", C.c_int32), ("binding", C.c_void_p)]
+                ("n_param", C.c_int32), ("binding", C.c_void_p), ("mesh_rot", C.c_void_p)]
 
 
 def _declare(L):
@@ -200,6 +200,7 @@ class OracleScene:
         st.plight = ptr(a["plights"])
         st.n_param = a["bindings"].shape[0]
         st.binding = ptr(a["bindings"])
+        st.mesh_rot = ptr(a["mesh_rot"])
         self.h = lib().orc_scene_new(C.byref(st))
         lib().orc_set_brute_force(self.h, 1 if brute_force else 0)
         self.d = st.n_param

@@ -68,7 +68,7 @@ hipError_t timed_render(prdpt_ctx* ctx, const prdpt_scene* s, const float* X, in
     }
   }
   hipError_t e = launch_render(ctx->stream, sc, W, H, X, nk, d, tag, seed, ref, img, partial, nullptr,
-                               ctx->work.p, s->d_tile_order, s->d_tile_cost, crn);
+                               ctx->work.p, s->d_tile_order, s->d_tile_cost, crn, s->hdr.has_rot);
   if (e != hipSuccess) return e;
   if (a && b) {
     e = hipEventRecord(b, ctx->stream);
@@ -294,15 +294,19 @@ int prdpt::build_host_scene(const prdpt_scene_desc* D, HostScene& hs) {
   }
   for (int i = 0; i < h.n_pl; ++i)
     for (int c = 0; c < 6; ++c) h.pl[i][c] = D->point_lights[6 * i + c];
-  // ---- instances: meshes with a binding or a non-zero translation get their
-  //      own BVH; all other meshes share one static BVH ----
+  if (D->mesh_rotation)
+    for (int i = 0; i < 3 * D->n_meshes; ++i)
+      if (!std::isfinite(D->mesh_rotation[i])) return fail(PRDPT_E_SCENE, "mesh rotation not finite");
+  // ---- instances: meshes with a binding, a non-zero translation or a non-zero
+  //      rotation get their own BVH; all other meshes share one static BVH ----
   std::vector<int> mesh_inst(D->n_meshes, -1);
   std::vector<char> bound(D->n_meshes, 0);
   for (int j = 0; j < D->n_params; ++j) {
     const int kind = D->bindings[3 * j], idx = D->bindings[3 * j + 1], comp = D->bindings[3 * j + 2];
     const int lim = kind == PRDPT_BIND_SPHERE ? D->n_spheres : kind == PRDPT_BIND_QUAD ? D->n_quads
                     : kind == PRDPT_BIND_MESH ? D->n_meshes : kind == PRDPT_BIND_PLIGHT ? D->n_point_lights
-                    : kind == PRDPT_BIND_ALBEDO ? D->n_materials : -1;
+                    : kind == PRDPT_BIND_ALBEDO ? D->n_materials
+                    : kind == PRDPT_BIND_MESH_ROT ? D->n_meshes : -1;
     if (lim < 0 || idx < 0 || idx >= lim || comp < 0 || comp > 2) {
       return fail(PRDPT_E_SCENE, "bad parameter binding");
     }
@@ -313,13 +317,17 @@ int prdpt::build_host_scene(const prdpt_scene_desc* D, HostScene& hs) {
     if (kind == PRDPT_BIND_ALBEDO && D->mat_type[idx] == PRDPT_MAT_DIELECTRIC) {
       return fail(PRDPT_E_SCENE, "a dielectric material has no colour to bind");
     }
-    if (kind == PRDPT_BIND_MESH) bound[idx] = 1;
+    if (kind == PRDPT_BIND_MESH || kind == PRDPT_BIND_MESH_ROT) bound[idx] = 1;
+    if (kind == PRDPT_BIND_MESH_ROT) h.has_rot = 1;
   }
   int n_inst = 0;
   int static_inst = -1;
   for (int m = 0; m < D->n_meshes; ++m) {
     const float* t = D->mesh_translation + 3 * m;
-    const bool own = bound[m] || t[0] != 0.0f || t[1] != 0.0f || t[2] != 0.0f;
+    const float* a = D->mesh_rotation ? D->mesh_rotation + 3 * m : nullptr;
+    const bool rotated = a && (a[0] != 0.0f || a[1] != 0.0f || a[2] != 0.0f);
+    if (rotated) h.has_rot = 1;
+    const bool own = bound[m] || rotated || t[0] != 0.0f || t[1] != 0.0f || t[2] != 0.0f;
     if (own) {
       mesh_inst[m] = n_inst++;
     } else {
@@ -333,8 +341,8 @@ int prdpt::build_host_scene(const prdpt_scene_desc* D, HostScene& hs) {
   h.n_inst = n_inst;
   for (int j = 0; j < D->n_params; ++j) {
     h.bind_kind[j] = D->bindings[3 * j];
-    h.bind_index[j] = h.bind_kind[j] == PRDPT_BIND_MESH ? mesh_inst[D->bindings[3 * j + 1]]
-                                                        : D->bindings[3 * j + 1];
+    const bool on_mesh = h.bind_kind[j] == PRDPT_BIND_MESH || h.bind_kind[j] == PRDPT_BIND_MESH_ROT;
+    h.bind_index[j] = on_mesh ? mesh_inst[D->bindings[3 * j + 1]] : D->bindings[3 * j + 1];
     h.bind_comp[j] = D->bindings[3 * j + 2];
   }
   std::vector<int32_t> tri_mat(D->n_triangles);
@@ -344,14 +352,20 @@ int prdpt::build_host_scene(const prdpt_scene_desc* D, HostScene& hs) {
       tri_mat[t] = D->mesh_mat[m];
       lists[mesh_inst[m]].push_back(t);
     }
-    for (int c = 0; c < 3; ++c) h.inst_xlate[mesh_inst[m]][c] = D->mesh_translation[3 * m + c];
+    for (int c = 0; c < 3; ++c) {
+      h.inst_xlate[mesh_inst[m]][c] = D->mesh_translation[3 * m + c];
+      h.inst_ang[mesh_inst[m]][c] = D->mesh_rotation ? D->mesh_rotation[3 * m + c] : 0.0f;
+    }
   }
+  for (int i = 0; i < PRDPT_MAX_INSTANCES; ++i) euler_rotation_host(h.inst_ang[i], h.inst_rot[i]);
   std::vector<Node>& nodes = hs.nodes;
   std::vector<Tri>& tris = hs.tris;
   tris.reserve(D->n_triangles);
   for (int i = 0; i < n_inst; ++i) {
+    const size_t tri_begin = tris.size();
     BvhOut b = build_bvh(D->triangles, tri_mat.data(), lists[i].data(), (int)lists[i].size(),
                          h.tri_id_base, nodes, tris);
+    for (size_t t = tri_begin; t < tris.size(); ++t) tris[t].inst = i;
     if (b.root == -2) {
       return fail(PRDPT_E_SCENE, "mesh instance too large for the BVH depth bound");
     }
@@ -508,7 +522,7 @@ int prdpt_render_perturbed(prdpt_scene* s, const float* theta, const float* sigm
                      std::sqrt(2.0 * M_PI), ctx->tau.p, ctx->c.p, ctx->X.p));
   HIP_TRY(launch_render(ctx->stream, s->dev(), h.W, h.H, ctx->X.p, N, d, kTagPath, seed, nullptr,
                         images_out, nullptr, nullptr, ctx->work.p, s->d_tile_order,
-                        s->d_tile_cost, (est & PRDPT_EST_INDEPENDENT) ? 0 : 1));
+                        s->d_tile_cost, (est & PRDPT_EST_INDEPENDENT) ? 0 : 1, h.has_rot));
   if (tau_out)
     HIP_TRY(hipMemcpyAsync(tau_out, ctx->tau.p, sizeof(float) * rows * d, hipMemcpyDeviceToHost,
                            ctx->stream));
@@ -527,7 +541,7 @@ int prdpt_render_reference(prdpt_scene* s, const float* X, uint64_t seed, float*
   HIP_TRY(hipMemcpyAsync(ctx->X.p, X, sizeof(float) * d, hipMemcpyHostToDevice, ctx->stream));
   HIP_TRY(launch_render(ctx->stream, s->dev(), h.W, h.H, ctx->X.p, 1, d, kTagRef, seed, nullptr,
                         image_out, nullptr, nullptr, ctx->work.p, s->d_tile_order,
-                        s->d_tile_cost, 1));
+                        s->d_tile_cost, 1, h.has_rot));
   HIP_TRY(hipStreamSynchronize(ctx->stream));
   return PRDPT_OK;
 }
@@ -648,7 +662,7 @@ int prdpt_traversal_counts(prdpt_scene* s, const float* theta, const float* sigm
                      std::sqrt(2.0 * M_PI), ctx->tau.p, ctx->c.p, ctx->X.p));
   HIP_TRY(launch_render(ctx->stream, s->dev(), h.W, h.H, ctx->X.p, N, d, kTagPath, seed, nullptr,
                         nullptr, nullptr, ctx->counters.p, ctx->work.p, s->d_tile_order,
-                        nullptr, (est & PRDPT_EST_INDEPENDENT) ? 0 : 1));
+                        nullptr, (est & PRDPT_EST_INDEPENDENT) ? 0 : 1, s->hdr.has_rot));
   unsigned long long host[7];
   HIP_TRY(hipMemcpyAsync(host, ctx->counters.p, sizeof(host), hipMemcpyDeviceToHost, ctx->stream));
   HIP_TRY(hipStreamSynchronize(ctx->stream));

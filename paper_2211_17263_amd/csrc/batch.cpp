@@ -134,8 +134,8 @@ int check_one(prdpt_ctx* ctx, const prdpt_request& r) {
   return PRDPT_OK;
 }
 
-int launch_sequence(BatchState& b, int render_blocks) {
-  HIP_TRY(launch_batch(b.stream, b.d_reqs, b.d_meta, render_blocks, b.d_tau, b.d_c, b.d_X,
+int launch_sequence(BatchState& b, int render_blocks, int rot) {
+  HIP_TRY(launch_batch(b.stream, b.d_reqs, b.d_meta, render_blocks, rot, b.d_tau, b.d_c, b.d_X,
                        b.d_partial, b.d_losses, b.d_grads, b.d_loss));
   return PRDPT_OK;
 }
@@ -215,6 +215,8 @@ int batch_enqueue(prdpt_ctx* ctx, BatchState& b, prdpt_request* reqs, int n, std
   m.total_rows = row_base;
   m.tiles_per_item = tpi;
   const int render_blocks = std::max(1, b.n_cu * b.blocks_per_cu);
+  int rot = 0;  // the render variant that applies instance rotations
+  for (int i : ok) rot |= reqs[i].scene->hdr.has_rot;
   // order after earlier work on the context stream (e.g. reference uploads)
   HIP_TRY(hipEventRecord(b.ready, ctx->stream));
   HIP_TRY(hipStreamWaitEvent(b.stream, b.ready, 0));
@@ -222,14 +224,14 @@ int batch_enqueue(prdpt_ctx* ctx, BatchState& b, prdpt_request* reqs, int n, std
   HIP_TRY(hipMemcpyAsync(b.d_meta, b.h_meta, sizeof(BatchMeta), hipMemcpyHostToDevice, b.stream));
   if (t0) HIP_TRY(hipEventRecord(t0, b.stream));
   if (b.use_graph) {
-    if (b.exec && b.graph_blocks != render_blocks) {
+    if (b.exec && (b.graph_blocks != render_blocks || b.graph_rot != rot)) {
       HIP_TRY(hipGraphExecDestroy(b.exec));
       b.exec = nullptr;
     }
     if (!b.exec) {
       hipGraph_t g = nullptr;
       HIP_TRY(hipStreamBeginCapture(b.stream, hipStreamCaptureModeThreadLocal));
-      const int rc = launch_sequence(b, render_blocks);
+      const int rc = launch_sequence(b, render_blocks, rot);
       hipError_t e = hipStreamEndCapture(b.stream, &g);
       if (rc) return rc;
       if (e != hipSuccess) return fail(PRDPT_E_HIP, std::string("graph capture: ") + hipGetErrorString(e));
@@ -240,10 +242,11 @@ int batch_enqueue(prdpt_ctx* ctx, BatchState& b, prdpt_request* reqs, int n, std
         return fail(PRDPT_E_HIP, std::string("graph instantiate: ") + hipGetErrorString(e));
       }
       b.graph_blocks = render_blocks;
+      b.graph_rot = rot;
     }
     HIP_TRY(hipGraphLaunch(b.exec, b.stream));
   } else {
-    if (int rc = launch_sequence(b, render_blocks)) return rc;
+    if (int rc = launch_sequence(b, render_blocks, rot)) return rc;
   }
   if (t1) HIP_TRY(hipEventRecord(t1, b.stream));
   HIP_TRY(hipMemcpyAsync(b.h_grads, b.d_grads, sizeof(double) * PRDPT_MAX_PARAMS * ok.size(),

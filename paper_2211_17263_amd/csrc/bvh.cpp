@@ -107,7 +107,7 @@ struct Builder {
       o.e2x = v[6] - v[0]; o.e2y = v[7] - v[1]; o.e2z = v[8] - v[2];
       o.id = id_base + t;
       o.mat = tri_mat[t];
-      o.pad = 0;
+      o.inst = 0;  // set by the caller, which knows the instance
       tris->push_back(o);
     }
     return first;

@@ -19,7 +19,9 @@ hipError_t launch_tau(hipStream_t st, int est, int d, int P, uint64_t seed, cons
 hipError_t launch_render(hipStream_t st, const DevScene& sc, int W, int H, const float* X, int nk,
                          int d, int tag, uint64_t seed, const float* ref, float* img,
                          float* partial, unsigned long long* counters, int* work,
-                         const int* order, float* cost, int crn);
+                         const int* order, float* cost, int crn, int rot);
+// Rz(c) Ry(b) Rx(a) of the angles (a, b, c), row-major (the kernels' own formula)
+void euler_rotation_host(const float* ang, float* R);
 // tiles by descending measured render time (no-op for more than 4096 tiles)
 hipError_t launch_tile_order(hipStream_t st, const float* cost, int* order, int n_tiles);
 hipError_t launch_losses(hipStream_t st, const float* partial, int n_tiles, int N, int npix,
@@ -27,8 +29,9 @@ hipError_t launch_losses(hipStream_t st, const float* partial, int n_tiles, int 
 // rows = pairs (antithetic) or draws (independent != 0)
 hipError_t launch_combine(hipStream_t st, int rows, int d, int independent, const double* c,
                           const double* L, const double* scale, double* grad, double* loss);
+// rot != 0: some request's scene has rotated instances
 hipError_t launch_batch(hipStream_t st, const BatchReq* reqs, BatchMeta* meta, int render_blocks,
-                        float* tau, double* c, float* X, float* partial, double* losses,
+                        int rot, float* tau, double* c, float* X, float* partial, double* losses,
                         double* grads, double* loss);
 hipError_t launch_copy(hipStream_t st, const void* src, void* dst, size_t n16);
 
@@ -72,6 +75,7 @@ struct BatchState {
   double* h_losses = nullptr;      // pinned
   hipGraphExec_t exec = nullptr;
   int graph_blocks = 0;
+  int graph_rot = 0;  // render variant captured in the graph
 };
 
 void batch_release(BatchState& b);

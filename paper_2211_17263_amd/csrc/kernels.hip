@@ -299,6 +299,44 @@ __device__ __forceinline__ void order2(float& ta, int& ra, float& tb, int& rb) {
   ra = r;
 }
 
+// Rz(c) Ry(b) Rx(a) for the angles (a, b, c) = ang (rotations about the fixed
+// x, y, z axes, applied in that order), row-major; entries are formed in
+// binary64 and rounded to binary32, so zero angles give the identity exactly.
+__host__ __device__ inline void euler_rotation(const float* ang, float* R) {
+  const double ca = cos((double)ang[0]), sa = sin((double)ang[0]);
+  const double cb = cos((double)ang[1]), sb = sin((double)ang[1]);
+  const double cc = cos((double)ang[2]), sc = sin((double)ang[2]);
+  R[0] = (float)(cc * cb);
+  R[1] = (float)(cc * sb * sa - sc * ca);
+  R[2] = (float)(cc * sb * ca + sc * sa);
+  R[3] = (float)(sc * cb);
+  R[4] = (float)(sc * sb * sa + cc * ca);
+  R[5] = (float)(sc * sb * ca - cc * sa);
+  R[6] = (float)(-sb);
+  R[7] = (float)(cb * sa);
+  R[8] = (float)(cb * ca);
+}
+
+// The ray (o, d) in the frame of instance `inst`: R^T (o - t) and R^T d
+// (without rotations, ROT = false: o - t and d).  R is orthonormal, so the ray
+// parameter of a hit is the same in both frames.
+template <bool ROT>
+__device__ __forceinline__ void to_instance(const SceneHdr& S, int inst, V3 o, V3 d, V3& om,
+                                            V3& dm) {
+  const V3 q = mk(o.x - S.inst_xlate[inst][0], o.y - S.inst_xlate[inst][1],
+                  o.z - S.inst_xlate[inst][2]);
+  if (ROT) {
+    const float* R = S.inst_rot[inst];
+    om = mk(R[0] * q.x + R[3] * q.y + R[6] * q.z, R[1] * q.x + R[4] * q.y + R[7] * q.z,
+            R[2] * q.x + R[5] * q.y + R[8] * q.z);
+    dm = mk(R[0] * d.x + R[3] * d.y + R[6] * d.z, R[1] * d.x + R[4] * d.y + R[7] * d.z,
+            R[2] * d.x + R[5] * d.y + R[8] * d.z);
+  } else {
+    om = q;
+    dm = d;
+  }
+}
+
 struct Trav {
   Hit h;
   int sp;    // stack entries in use
@@ -351,7 +389,7 @@ __device__ __forceinline__ bool begin_trace(const SceneHdr& S, V3 o, V3 d, float
 }
 
 // Continues a query; returns true when it is answered (tr.h holds the result).
-template <bool COUNT>
+template <bool COUNT, bool ROT>
 __device__ bool continue_trace(const SceneHdr& S, const Node* __restrict__ nodes,
                                const Tri* __restrict__ tris, V3 o, V3 d, float tmax, bool any,
                                Trav& tr, int* __restrict__ stack, int stride,
@@ -359,9 +397,10 @@ __device__ bool continue_trace(const SceneHdr& S, const Node* __restrict__ nodes
   Hit& h = tr.h;
   int sp = tr.sp;
   int inst = tr.inst;
-  const V3 inv = mk(safe_inv(d.x), safe_inv(d.y), safe_inv(d.z));
-  // an instance: the ray moves by minus the mesh translation
-  V3 om = mk(o.x - S.inst_xlate[inst][0], o.y - S.inst_xlate[inst][1], o.z - S.inst_xlate[inst][2]);
+  // an instance: the ray in the mesh's own frame
+  V3 om, dm;
+  to_instance<ROT>(S, inst, o, d, om, dm);
+  V3 inv = mk(safe_inv(dm.x), safe_inv(dm.y), safe_inv(dm.z));
   V3 oi = mk(-om.x * inv.x, -om.y * inv.y, -om.z * inv.z);
   int node = -1;   // inner node being visited, -1: none
   int leaf = 0;    // pending leaf (encoded < 0), 0: none
@@ -463,7 +502,7 @@ __device__ bool continue_trace(const SceneHdr& S, const Node* __restrict__ nodes
           if (first_active_lane()) cnt.wave_tri_iters++;
         }
         float t;
-        if (hit_tri(om, d, mk(p0.x, p0.y, p0.z), mk(p0.w, p1.x, p1.y), mk(p1.z, p1.w, p2.x), tmax,
+        if (hit_tri(om, dm, mk(p0.x, p0.y, p0.z), mk(p0.w, p1.x, p1.y), mk(p1.z, p1.w, p2.x), tmax,
                     &t)) {
           if (any) {
             h.t = t;
@@ -477,7 +516,8 @@ __device__ bool continue_trace(const SceneHdr& S, const Node* __restrict__ nodes
     if (node < 0 && sp == 0) {  // instance done: next one, or the query is answered
       inst = next_inst(S, inst + 1);
       if (inst >= S.n_inst) return true;
-      om = mk(o.x - S.inst_xlate[inst][0], o.y - S.inst_xlate[inst][1], o.z - S.inst_xlate[inst][2]);
+      to_instance<ROT>(S, inst, o, d, om, dm);
+      if (ROT) inv = mk(safe_inv(dm.x), safe_inv(dm.y), safe_inv(dm.z));
       oi = mk(-om.x * inv.x, -om.y * inv.y, -om.z * inv.z);
       stack[0] = S.inst_root[inst];
       sp = 1;
@@ -553,7 +593,12 @@ __device__ __forceinline__ void load_state(SceneHdr& S, const SceneHdr* __restri
       else if (kind == PRDPT_BIND_MESH) S.inst_xlate[i][c] = g->inst_xlate[i][c] + xj;
       else if (kind == PRDPT_BIND_PLIGHT) S.pl[i][c] = g->pl[i][c] + xj;
       else if (kind == PRDPT_BIND_ALBEDO) S.mat_rgb[i][c] = g->mat_rgb[i][c] + xj;
+      else if (kind == PRDPT_BIND_MESH_ROT) S.inst_ang[i][c] = g->inst_ang[i][c] + xj;
     }
+  }
+  if (S.has_rot) {  // uniform: every work-group of the launch reads the same header
+    __syncthreads();
+    if ((int)threadIdx.x < S.n_inst) euler_rotation(S.inst_ang[threadIdx.x], S.inst_rot[threadIdx.x]);
   }
   __syncthreads();
 }
@@ -570,7 +615,7 @@ __device__ __forceinline__ void load_state(SceneHdr& S, const SceneHdr* __restri
 // path of the wave, and every iteration runs the same traversal code.  Per
 // sample the radiance terms are added in the same order as a recursive
 // implementation (vertex by vertex; point lights, then area lights).
-template <bool COUNT>
+template <bool COUNT, bool ROT>
 __device__ __forceinline__ void render_tile(const SceneHdr& S, const Node* __restrict__ nodes,
                                             const Tri* __restrict__ tris, int k, int tile, int tag,
                                             uint32_t k0, uint32_t k1, const float* __restrict__ ref,
@@ -640,7 +685,13 @@ __device__ __forceinline__ void render_tile(const SceneHdr& S, const Node* __res
             const float4* tp = reinterpret_cast<const float4*>(tris + h.slot);
             const float4 p0 = tp[0], p1 = tp[1], p2 = tp[2];
             mat = __float_as_int(p2.z);
-            ng = unit(cross(mk(p0.w, p1.x, p1.y), mk(p1.z, p1.w, p2.x)));
+            ng = cross(mk(p0.w, p1.x, p1.y), mk(p1.z, p1.w, p2.x));  // the mesh's frame
+            if (ROT) {
+              const float* R = S.inst_rot[__float_as_int(p2.w)];
+              ng = mk(R[0] * ng.x + R[1] * ng.y + R[2] * ng.z, R[3] * ng.x + R[4] * ng.y + R[5] * ng.z,
+                      R[6] * ng.x + R[7] * ng.y + R[8] * ng.z);
+            }
+            ng = unit(ng);
           }
           const int mt = S.mat_type[mat];
           if (mt == PRDPT_MAT_EMISSIVE) {
@@ -814,8 +865,8 @@ __device__ __forceinline__ void render_tile(const SceneHdr& S, const Node* __res
       }
     }
     if (COUNT && first_active_lane()) cnt.wave_outer_iters++;
-    tracing = !continue_trace<COUNT>(S, nodes, tris, o, dir, tmax, shadow, tr, stk, kBlock, ovf,
-                                     PRDPT_TRACE_BUDGET, cnt);
+    tracing = !continue_trace<COUNT, ROT>(S, nodes, tris, o, dir, tmax, shadow, tr, stk, kBlock,
+                                          ovf, PRDPT_TRACE_BUDGET, cnt);
     answered = !tracing;
   }
 
@@ -871,7 +922,7 @@ __device__ __forceinline__ void render_tile(const SceneHdr& S, const Node* __res
 // tiles by cost for the next launch puts the cheapest tiles last and shortens
 // the tail where few work-groups are still busy.  Outputs do not depend on
 // the order.
-template <bool COUNT>
+template <bool COUNT, bool ROT>
 __global__ __launch_bounds__(kBlock, PRDPT_MIN_WAVES_PER_EU) void render_loss_kernel(
     DevScene scene, const float* __restrict__ X, int d, int tag, uint32_t k0, uint32_t k1,
     const float* __restrict__ ref, float* __restrict__ img, float* __restrict__ partial,
@@ -897,7 +948,7 @@ __global__ __launch_bounds__(kBlock, PRDPT_MIN_WAVES_PER_EU) void render_loss_ke
     }
     unsigned long long t0 = 0;
     if (cost && threadIdx.x == 0) t0 = wall_clock64();
-    render_tile<COUNT>(S, scene.nodes, scene.tris, k, tile, tag, k0, k1, ref, img,
+    render_tile<COUNT, ROT>(S, scene.nodes, scene.tris, k, tile, tag, k0, k1, ref, img,
                        partial ? partial + (size_t)k * n_tiles + tile : nullptr, counters, stack,
                        wsum, crn);
     if (cost && threadIdx.x == 0) cost[tile] = (float)(wall_clock64() - t0);
@@ -1157,6 +1208,7 @@ __global__ void batch_tau_kernel(const BatchReq* __restrict__ reqs, const BatchM
 // Persistent render: work-groups take (request, perturbation, run of tiles)
 // items from one counter until the batch is exhausted; each tile writes its own
 // partial slot, so the order in which items are taken does not matter.
+template <bool ROT>
 __global__ __launch_bounds__(kBlock, PRDPT_MIN_WAVES_PER_EU) void batch_render_kernel(
     const BatchReq* __restrict__ reqs, BatchMeta* __restrict__ meta, const float* __restrict__ X,
     float* __restrict__ partial) {
@@ -1179,7 +1231,7 @@ __global__ __launch_bounds__(kBlock, PRDPT_MIN_WAVES_PER_EU) void batch_render_k
     const int last = min(first + tpi, q.n_tiles);
     load_state(S, q.scene.hdr, X + (size_t)(q.row_base + k) * PRDPT_MAX_PARAMS, q.d);
     for (int tile = first; tile < last; ++tile) {
-      render_tile<false>(S, q.scene.nodes, q.scene.tris, k, tile, kTagPath, q.k0, q.k1, q.ref,
+      render_tile<false, ROT>(S, q.scene.nodes, q.scene.tris, k, tile, kTagPath, q.k0, q.k1, q.ref,
                          nullptr, partial + (size_t)q.partial_base + (size_t)k * q.n_tiles + tile,
                          nullptr, stack, wsum, 1);
       __syncthreads();
@@ -1235,39 +1287,49 @@ hipError_t launch_tau(hipStream_t st, int est, int d, int P, uint64_t seed, cons
   return hipGetLastError();
 }
 
-// resident work-groups of the render kernel on the current device (cached)
-int render_grid_limit() {
-  static int cached[64];
+// resident work-groups of the render kernel on the current device (cached per
+// device and variant)
+int render_grid_limit(int rot) {
+  static int cached[64][2];
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
-  if (cached[dev] > 0) return cached[dev];
+  rot = rot ? 1 : 0;
+  if (cached[dev][rot] > 0) return cached[dev][rot];
   int n_cu = 0, per_cu = 0;
   if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, render_loss_kernel<false>, kBlock, 0) !=
-      hipSuccess)
-    return 0;
-  cached[dev] = std::max(1, n_cu * std::max(1, per_cu));
-  return cached[dev];
+  const hipError_t e = rot ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                                 &per_cu, render_loss_kernel<false, true>, kBlock, 0)
+                           : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                                 &per_cu, render_loss_kernel<false, false>, kBlock, 0);
+  if (e != hipSuccess) return 0;
+  cached[dev][rot] = std::max(1, n_cu * std::max(1, per_cu));
+  return cached[dev][rot];
 }
+
+void euler_rotation_host(const float* ang, float* R) { euler_rotation(ang, R); }
 
 hipError_t launch_render(hipStream_t st, const DevScene& sc, int W, int H, const float* X, int nk,
                          int d, int tag, uint64_t seed, const float* ref, float* img,
                          float* partial, unsigned long long* counters, int* work,
-                         const int* order, float* cost, int crn) {
+                         const int* order, float* cost, int crn, int rot) {
   const int n_tiles = render_tiles(W, H);
   const int n_items = n_tiles * nk;
-  const int limit = render_grid_limit();
+  const int limit = render_grid_limit(rot);
   if (limit <= 0) return hipErrorInvalidDevice;
   const int blocks = std::min(n_items, limit);
   hipLaunchKernelGGL(reset_work_kernel, dim3(1), dim3(64), 0, st, work);
-  if (counters)
-    hipLaunchKernelGGL(render_loss_kernel<true>, dim3(blocks), dim3(kBlock), 0, st, sc, X, d, tag,
-                       (uint32_t)seed, (uint32_t)(seed >> 32), ref, img, partial, counters,
-                       n_tiles, n_items, work, order, cost, crn);
-  else
-    hipLaunchKernelGGL(render_loss_kernel<false>, dim3(blocks), dim3(kBlock), 0, st, sc, X, d, tag,
-                       (uint32_t)seed, (uint32_t)(seed >> 32), ref, img, partial, counters,
-                       n_tiles, n_items, work, order, cost, crn);
+  const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+#define PRDPT_RENDER(C, R)                                                                      \
+  hipLaunchKernelGGL((render_loss_kernel<C, R>), dim3(blocks), dim3(kBlock), 0, st, sc, X, d, tag, \
+                     k0, k1, ref, img, partial, counters, n_tiles, n_items, work, order, cost, crn)
+  if (counters) {
+    if (rot) PRDPT_RENDER(true, true);
+    else PRDPT_RENDER(true, false);
+  } else {
+    if (rot) PRDPT_RENDER(false, true);
+    else PRDPT_RENDER(false, false);
+  }
+#undef PRDPT_RENDER
   return hipGetLastError();
 }
 
@@ -1295,12 +1357,16 @@ hipError_t launch_combine(hipStream_t st, int rows, int d, int independent, cons
 // content (totals are read from the device-side meta), so it can be captured
 // once in a graph and replayed for every batch.
 hipError_t launch_batch(hipStream_t st, const BatchReq* reqs, BatchMeta* meta, int render_blocks,
-                        float* tau, double* c, float* X, float* partial, double* losses,
+                        int rot, float* tau, double* c, float* X, float* partial, double* losses,
                         double* grads, double* loss) {
   hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, st, meta);
   hipLaunchKernelGGL(batch_tau_kernel, dim3(64), dim3(64), 0, st, reqs, meta, tau, c, X);
-  hipLaunchKernelGGL(batch_render_kernel, dim3(render_blocks), dim3(kBlock), 0, st, reqs, meta, X,
-                     partial);
+  if (rot)
+    hipLaunchKernelGGL(batch_render_kernel<true>, dim3(render_blocks), dim3(kBlock), 0, st, reqs,
+                       meta, X, partial);
+  else
+    hipLaunchKernelGGL(batch_render_kernel<false>, dim3(render_blocks), dim3(kBlock), 0, st, reqs,
+                       meta, X, partial);
   hipLaunchKernelGGL(batch_loss_kernel, dim3(1024), dim3(64), 0, st, reqs, meta, partial, losses);
   hipLaunchKernelGGL(batch_combine_kernel, dim3(256), dim3(64), 0, st, reqs, meta, c, losses,
                      grads, loss);

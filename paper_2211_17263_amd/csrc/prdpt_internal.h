@@ -38,12 +38,12 @@ struct alignas(16) Node {
 static_assert(sizeof(Node) == 128, "node layout");
 
 // Triangle: v0, e1 = v1 - v0, e2 = v2 - v0 (binary32, computed on the host),
-// global primitive id and material (48 bytes, three 16-byte loads).
+// global primitive id, material and instance (48 bytes, three 16-byte loads).
 struct alignas(16) Tri {
   float v0x, v0y, v0z, e1x;
   float e1y, e1z, e2x, e2y;
   float e2z;
-  int32_t id, mat, pad;
+  int32_t id, mat, inst;  // instance index (its rotation turns the normal into the world)
 };
 static_assert(sizeof(Tri) == 48, "triangle layout");
 
@@ -64,6 +64,9 @@ struct SceneHdr {
   int32_t area_quad[PRDPT_MAX_QUADS];        // emissive quads in index order
   int32_t inst_root[PRDPT_MAX_INSTANCES];    // root node of each instance BVH (-1: empty)
   float inst_xlate[PRDPT_MAX_INSTANCES][3];
+  float inst_ang[PRDPT_MAX_INSTANCES][3];    // rotation angles (a, b, c)
+  float inst_rot[PRDPT_MAX_INSTANCES][9];    // Rz(c) Ry(b) Rx(a), row-major
+  int32_t has_rot;                           // some instance is rotated or has a bound angle
   float pl[PRDPT_MAX_POINT_LIGHTS][6];
   int32_t bind_kind[PRDPT_MAX_PARAMS];
   int32_t bind_index[PRDPT_MAX_PARAMS];      // instance index for meshes

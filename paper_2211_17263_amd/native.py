@@ -55,7 +55,8 @@ class SceneDesc(C.Structure):
                 ("mesh_translation", C.c_void_p),
                 ("n_triangles", C.c_int32), ("triangles", C.c_void_p),
                 ("n_point_lights", C.c_int32), ("point_lights", C.c_void_p),
-                ("n_params", C.c_int32), ("bindings", C.c_void_p)]
+                ("n_params", C.c_int32), ("bindings", C.c_void_p),
+                ("mesh_rotation", C.c_void_p)]
 
 
 class Request(C.Structure):
@@ -220,6 +221,7 @@ def scene_desc(scene):
     d.point_lights = ptr(a["plights"])
     d.n_params = a["bindings"].shape[0]
     d.bindings = ptr(a["bindings"])
+    d.mesh_rotation = ptr(a["mesh_rot"])
     return d, a
 
 

@@ -18,7 +18,10 @@ Conventions shared by every consumer of a scene:
     pre-scaled by tan(fov/2)*aspect and tan(fov/2)
   * parameter binding (kind, index, component): the bound field equals its base
     value plus the parameter value.  kinds: 0 sphere centre, 1 quad origin,
-    2 mesh translation, 3 point-light position
+    2 mesh translation, 3 point-light position, 4 material colour channel,
+    5 mesh rotation angle about the x, y or z axis (radians)
+  * a mesh's vertex x is placed at Rz(c) Ry(b) Rx(a) x + translation, with
+    (a, b, c) its rotation angles
 """
 from __future__ import annotations
 
@@ -29,7 +32,7 @@ from typing import List
 import numpy as np
 
 DIFFUSE, DIELECTRIC, EMISSIVE = 0, 1, 2
-BIND_SPHERE, BIND_QUAD, BIND_MESH, BIND_PLIGHT, BIND_ALBEDO = 0, 1, 2, 3, 4
+BIND_SPHERE, BIND_QUAD, BIND_MESH, BIND_PLIGHT, BIND_ALBEDO, BIND_MESH_ROT = 0, 1, 2, 3, 4, 5
 EST_GAUSS, EST_IS, EST_IS_PERDIM = 0, 1, 2
 
 
@@ -39,6 +42,7 @@ class Mesh:
     faces: np.ndarray        # int32 [T][3]
     material: int
     translation: np.ndarray  # float32 [3]
+    rotation: np.ndarray     # float32 [3] angles (a, b, c): x -> Rz(c) Ry(b) Rx(a) x + translation
 
 
 @dataclasses.dataclass
@@ -82,10 +86,11 @@ class Scene:
         self.quad_mat.append(int(mat))
         return len(self.quads) - 1
 
-    def mesh(self, verts, faces, mat, translation=(0.0, 0.0, 0.0)) -> int:
+    def mesh(self, verts, faces, mat, translation=(0.0, 0.0, 0.0), rotation=(0.0, 0.0, 0.0)) -> int:
         self.meshes.append(Mesh(np.ascontiguousarray(verts, np.float32),
                                 np.ascontiguousarray(faces, np.int32), int(mat),
-                                np.asarray(translation, np.float32)))
+                                np.asarray(translation, np.float32),
+                                np.asarray(rotation, np.float32)))
         return len(self.meshes) - 1
 
     def plight(self, pos, intensity) -> int:
@@ -123,6 +128,7 @@ class Scene:
             mesh_off=np.asarray(off, np.int32),
             mesh_mat=i32([m.material for m in self.meshes], 1).ravel(),
             mesh_xlate=f32([m.translation for m in self.meshes], 3),
+            mesh_rot=f32([m.rotation for m in self.meshes], 3),
             plights=f32(self.plights, 6), bindings=i32(self.bindings, 3),
         )
 
@@ -252,9 +258,12 @@ def toy_problem(seed=1, **kw):
 # ---------------------------------------------------------------------------
 # workload 2: Cornell-style box, movable area light + two jittered icospheres
 # ---------------------------------------------------------------------------
-def cornell_scene(seed=2, width=256, height=256, spp=16, bounces=4, ico_level=4, colour=False):
+def cornell_scene(seed=2, width=256, height=256, spp=16, bounces=4, ico_level=4, colour=False,
+                  rotation=False):
     """Cornell box; binds the area light's position (3) and the yellow sphere's
-    translation (3), and with colour=True also the left wall's albedo (3)."""
+    translation (3), with colour=True also the left wall's albedo (3), and with
+    rotation=True the tall box's turn about the vertical axis (1; the box is
+    then an instance built around its own centre)."""
     rng = np.random.default_rng(seed)
     s = _new_scene("cornell", width, height, spp, bounces, eye=(0, 0, 3.4), look=(0, 0, 0))
     white = s.material(DIFFUSE, (0.73, 0.73, 0.73))
@@ -273,8 +282,13 @@ def cornell_scene(seed=2, width=256, height=256, spp=16, bounces=4, ico_level=4,
     for o, e1, e2, m in walls:
         v, f = quad_tris(o, e1, e2)
         s.mesh(v, f, m)
-    v, f = box_tris((0.35, -0.7, 0.25), (0.55, 0.6, 0.55), 18.0)
-    s.mesh(v, f, white)
+    if rotation:
+        v, f = box_tris((0.0, 0.0, 0.0), (0.55, 0.6, 0.55), 0.0)
+        box = s.mesh(v, f, white, translation=(0.35, -0.7, 0.25),
+                     rotation=(0.0, math.radians(18.0), 0.0))
+    else:
+        v, f = box_tris((0.35, -0.7, 0.25), (0.55, 0.6, 0.55), 18.0)
+        s.mesh(v, f, white)
     va, fa = jittered_icosphere(rng, ico_level, 0.2, (-0.45, -0.55, -0.15))
     mesh_a = s.mesh(va, fa, yellow)
     vb, fb = jittered_icosphere(rng, ico_level, 0.2, (0.35, -0.15, 0.25))
@@ -286,14 +300,17 @@ def cornell_scene(seed=2, width=256, height=256, spp=16, bounces=4, ico_level=4,
     if colour:
         for c in range(3):
             s.bind(BIND_ALBEDO, red, c)
+    if rotation:
+        s.bind(BIND_MESH_ROT, box, 1)
     return s
 
 
-def cornell_problem(seed=2, colour=False, **kw):
-    """Geometry (light position, sphere translation) and, with colour=True, the
-    left wall's colour as offsets from its initial albedo, which is theta_0's."""
+def cornell_problem(seed=2, colour=False, rotation=False, **kw):
+    """Geometry (light position, sphere translation); with colour=True the left
+    wall's colour as offsets from its initial albedo (theta_0's); with
+    rotation=True the tall box's turn (radians) about the vertical axis."""
     rng = np.random.default_rng(seed + 1000)
-    scene = cornell_scene(seed=seed, colour=colour, **kw)
+    scene = cornell_scene(seed=seed, colour=colour, rotation=rotation, **kw)
     theta_ref = np.array([rng.uniform(-0.3, 0.3), -0.02, rng.uniform(-0.3, 0.3),
                           rng.uniform(-0.2, 0.2), 0.0, rng.uniform(-0.2, 0.2)], np.float32)
     offs = rng.uniform(-0.5, 0.5, 6)
@@ -306,6 +323,10 @@ def cornell_problem(seed=2, colour=False, **kw):
         theta_ref = np.concatenate([theta_ref, target - base]).astype(np.float32)
         theta0 = np.concatenate([theta0, np.zeros(3)]).astype(np.float32)
         sigma = np.concatenate([sigma, np.full(3, 0.2)]).astype(np.float32)
+    if rotation:
+        theta_ref = np.append(theta_ref, rng.uniform(-0.5, 0.5)).astype(np.float32)
+        theta0 = np.append(theta0, 0.0).astype(np.float32)
+        sigma = np.append(sigma, 0.3).astype(np.float32)
     return dict(scene=scene, theta_ref=theta_ref, theta0=theta0, sigma=sigma, N=16, est=EST_IS)
 
 

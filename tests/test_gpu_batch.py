@@ -73,6 +73,35 @@ def test_batch_equals_alone_bitwise(setup, use_graph):
             assert q.loss[0] == a["loss"]
 
 
+def test_batch_with_rotated_instances(setup):
+    # a scene with a rotated, rotation-bound box next to scenes without
+    # rotations: the batch takes the rotating variant of the render when any
+    # request needs it (the captured graph is replaced when that changes), and
+    # every request still equals its single-request result bit for bit
+    import torch
+    from paper_2211_17263_amd import native as NV
+    ctx, jobs, scenes, refs = setup
+    pr = S.cornell_problem(seed=2, rotation=True, width=48, height=40, spp=2, ico_level=2)
+    say("batch-rotation")
+    rs = NV.prdpt_scene_create(ctx, pr["scene"])
+    try:
+        rjob = dict(theta0=pr["theta0"], sigma=pr["sigma"], N=8, est=NV.PRDPT_EST_IS)
+        js, ss = [jobs[0], jobs[1], rjob], [scenes[0], scenes[1], rs]
+        rf = [refs[0], refs[1], NV.prdpt_render_reference(rs, pr["theta_ref"], 3)]
+        NV.prdpt_batch_config(ctx, 4, 2, True)
+        for rep, idx in enumerate([[2, 0], [0, 1], [1, 2], [2]]):
+            seeds = {i: 500 * rep + 3 * i + 1 for i in idx}
+            reqs = _batch(NV, ctx, js, ss, rf, idx, seeds)
+            for i, q in zip(idx, reqs):
+                a = _alone(NV, ss[i], rf[i], js[i], seeds[i])
+                torch.cuda.synchronize()
+                assert q.status == 0
+                assert np.array_equal(q.grad[: ss[i].d], a["grad"]), (rep, i)
+                assert np.array_equal(q.losses[: js[i]["N"]], a["losses"]), (rep, i)
+    finally:
+        rs.destroy()
+
+
 def test_batch_isolates_invalid_requests(setup):
     from paper_2211_17263_amd import native as NV
     ctx, jobs, scenes, refs = setup

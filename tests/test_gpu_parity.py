@@ -131,6 +131,36 @@ def test_emission_and_albedo_bindings(ctx, est):
     assert np.any(r["grad"] != 0)
 
 
+def test_rotation_bindings_cornell_reduced(ctx):
+    # light position, sphere translation, wall colour and the tall box's turn
+    # about the vertical axis (d = 10)
+    pr = S.cornell_problem(seed=2, colour=True, rotation=True, width=64, height=48, spp=4,
+                           ico_level=3)
+    r, o = _full_parity(ctx, pr, 15, "cornell-reduced-rotation")
+    assert r["grad"][9] != 0
+
+
+@pytest.mark.parametrize("est", [O.GAUSS, O.IS])
+def test_rotation_all_axes(ctx, est):
+    # a random-triangle cloud turned about all three axes and moved, beside a
+    # rotated mesh whose angles are not bound
+    rng = np.random.default_rng(21)
+    sc = S.toy_scene(width=48, height=40, spp=2, bounces=2)
+    sc.bindings = []
+    v, f = S.random_triangles(rng, 3000, (-0.5, -0.5, -0.3), (0.5, 0.5, 0.3), 0.08)
+    m = sc.mesh(v, f, 0, translation=(0.2, 0.1, 0.6), rotation=(0.3, -0.2, 0.8))
+    vb, fb = S.box_tris((0.0, 0.0, 0.0), (0.4, 0.3, 0.2), 0.0)
+    sc.mesh(vb, fb, 0, translation=(-0.8, -0.6, 0.2), rotation=(0.0, 0.4, 1.0))
+    for c in range(3):
+        sc.bind(S.BIND_MESH_ROT, m, c)
+    sc.bind(S.BIND_MESH, m, 0)
+    pr = dict(scene=sc, theta_ref=np.array([0.1, 0.2, -0.3, 0.05], np.float32),
+              theta0=np.array([-0.2, 0.1, 0.2, -0.1], np.float32),
+              sigma=np.full(4, 0.2, np.float32), N=8, est=est)
+    r, o = _full_parity(ctx, pr, 16, "rotation-all-axes")
+    assert np.all(r["grad"] != 0)
+
+
 def test_cornell_reduced(ctx):
     pr = S.cornell_problem(seed=2, width=64, height=48, spp=4, ico_level=3)
     _full_parity(ctx, pr, 5, "cornell-reduced")
@@ -262,6 +292,18 @@ def test_error_codes(ctx):
         bad2.quad_mat[0] = bad2.material(S.DIELECTRIC, ior=1.5)
         with pytest.raises(NV.PrdptError) as e:
             gpu_scene(ctx, bad2)
+        assert e.value.code == NV.PRDPT_E_SCENE
+        # rotation bindings: mesh index in range; angles finite
+        bad4 = S.toy_scene()
+        bad4.bind(S.BIND_MESH_ROT, 0, 1)          # the toy scene has no mesh
+        with pytest.raises(NV.PrdptError) as e:
+            gpu_scene(ctx, bad4)
+        assert e.value.code == NV.PRDPT_E_SCENE
+        bad5 = S.toy_scene()
+        vb, fb = S.box_tris((0.0, 0.0, 0.0), (0.4, 0.3, 0.2), 0.0)
+        bad5.mesh(vb, fb, 0, rotation=(0.0, float("nan"), 0.0))
+        with pytest.raises(NV.PrdptError) as e:
+            gpu_scene(ctx, bad5)
         assert e.value.code == NV.PRDPT_E_SCENE
         # colour bindings: material index in range, and no dielectric
         for idx in (len(S.toy_scene().mat_type), None):

@@ -199,6 +199,71 @@ def test_bvh_closest_hit_equals_brute_force():
     assert (i1 >= 3).sum() > 1000          # many triangle hits (ids after sphere and quad)
 
 
+def _euler_scipy(a, b, c):
+    # extrinsic rotations about x, then y, then z: Rz(c) Ry(b) Rx(a)
+    from scipy.spatial.transform import Rotation
+    return Rotation.from_euler("xyz", [a, b, c]).as_matrix()
+
+
+@pytest.mark.parametrize("angles", [(0.0, 0.0, math.pi / 2), (0.4, -0.7, 1.1), (-2.5, 0.3, 0.05)])
+def test_mesh_rotation_equals_rotated_vertices(angles):
+    # an instance rotated by (a, b, c) and translated by t must hit what the
+    # static mesh with vertices R x + t (binary64, then rounded) hits; part of
+    # each angle comes from a rotation binding
+    rng = np.random.default_rng(7)
+    v, f = S.random_triangles(rng, 400, (-0.6, -0.6, -0.6), (0.6, 0.6, 0.6), 0.15)
+    t = np.array([0.2, -0.1, 0.3])
+    base = np.array(angles, np.float32) - np.float32(0.25)
+    X = np.full(3, 0.25, np.float32)
+    ang = (base + X).astype(np.float64)       # the binary32 sums the renderer forms
+    inst = S.toy_scene()
+    inst.bindings = []
+    m = inst.mesh(v, f, 0, translation=t, rotation=base)
+    for c in range(3):
+        inst.bind(S.BIND_MESH_ROT, m, c)
+    R = _euler_scipy(*ang)
+    flat = S.toy_scene()
+    flat.bindings = []
+    flat.mesh((v.astype(np.float64) @ R.T + t).astype(np.float32), f, 0)
+    n = 20000
+    o = np.tile(np.array([0.3, 0.2, 5.0], np.float32), (n, 1)) + rng.normal(0, 0.2, (n, 3)).astype(np.float32)
+    tgt = rng.uniform(-0.9, 0.9, (n, 3)) + t
+    d = tgt - o
+    d = (d / np.linalg.norm(d, axis=1, keepdims=True)).astype(np.float32)
+    t1, i1 = O.OracleScene(inst).trace(X, o, d)
+    t2, i2 = O.OracleScene(flat).trace(np.zeros(0, np.float32), o, d)
+    same = i1 == i2
+    assert same.mean() > 0.995, same.mean()      # ids differ only for rays grazing an edge
+    hit = same & (i1 >= 2)
+    assert hit.sum() > 3000
+    np.testing.assert_allclose(t1[hit], t2[hit], rtol=2e-5)
+
+
+def test_rotated_plane_lambertian_closed_form():
+    # a mesh square in its own z = 0 plane, rotated by a about x (through a
+    # binding): the plane is n . x = 0 with n = (0, -sin a, cos a), and the
+    # direct radiance is (rho / pi) I |n . (l - p)| / |l - p|^3
+    sc = S.plane_scene()
+    sc.quads, sc.quad_mat = [], []
+    v, f = S.quad_tris((-50.0, -50.0, 0.0), (100.0, 0.0, 0.0), (0.0, 100.0, 0.0))
+    m = sc.mesh(v, f, 0, rotation=(0.2, 0.0, 0.0))
+    sc.bind(S.BIND_MESH_ROT, m, 0)
+    X = np.array([0.15], np.float32)
+    a = float(np.float32(0.2) + X[0])
+    img = O.OracleScene(sc).render(X)
+    o, d = camera_rays_f64(sc)
+    nrm = np.array([0.0, -math.sin(a), math.cos(a)])
+    tt = -(o @ nrm) / (d @ nrm)
+    p = o[None, None, :] + tt[..., None] * d
+    lpos = np.array(sc.plights[0][:3], np.float64)
+    lv = lpos[None, None, :] - p
+    r = np.linalg.norm(lv, axis=-1)
+    L = sc.mat_rgb[0][0] / math.pi * sc.plights[0][3] * np.abs(lv @ nrm) / r**3
+    np.testing.assert_allclose(img[..., 0], L, rtol=5e-5)
+    # the same plane without the rotation is lit differently
+    assert np.abs(img[..., 0] - O.OracleScene(S.plane_scene()).render([])[..., 0]).max() > 1e-2
+
+
 def test_fresnel_special_values():
     n = 1.5
     assert abs(O.fresnel(1.0, 1.0, n) - ((n - 1) / (n + 1)) ** 2) < 1e-7          # 0.04
@@ -234,17 +299,30 @@ def test_render_is_deterministic_and_thread_independent():
     np.testing.assert_array_equal(sc.render_pixels(pr["theta0"], pix, seed=5), a.reshape(-1, 3)[pix])
 
 
-def test_estimator_against_quadrature_and_finite_differences():
-    # One-parameter toy scene (sphere x), pixel-centre rays, direct light: the
-    # render is deterministic, so Q(theta) = int kappa(x - theta) L(x) dx.  Q is
-    # evaluated by a trapezoid rule on a fixed x grid, its derivative by central
-    # differences (h = 1e-3); the estimator mean must match within 4 SE plus the
-    # quadrature error.
+def _one_parameter_scene(kind):
     sc = S.toy_scene(width=32, height=32, pixel_center=1)
-    sc.bindings = sc.bindings[:1]
+    if kind == "sphere-x":
+        sc.bindings = sc.bindings[:1]
+        return sc, 0.45, 0.3
+    # the sphere replaced by a box turning about the viewing axis
+    sc.bindings = []
+    sc.spheres, sc.sphere_mat = [], []
+    v, f = S.box_tris((0.0, 0.0, 0.0), (1.2, 0.5, 0.5), 0.0)
+    m = sc.mesh(v, f, 0, translation=(0.0, 0.0, 0.35), rotation=(0.0, 0.0, 0.3))
+    sc.bind(S.BIND_MESH_ROT, m, 2)
+    return sc, 0.5, 0.35
+
+
+@pytest.mark.parametrize("kind", ["sphere-x", "box-rotation-z"])
+def test_estimator_against_quadrature_and_finite_differences(kind):
+    # One-parameter toy scene (sphere x, or a box's rotation angle), pixel-centre
+    # rays, direct light: the render is deterministic, so
+    # Q(theta) = int kappa(x - theta) L(x) dx.  Q is evaluated by a trapezoid
+    # rule on a fixed x grid, its derivative by central differences (h = 1e-3);
+    # the estimator mean must match within 4 SE plus the quadrature error.
+    sc, theta, sigma = _one_parameter_scene(kind)
     osc = O.OracleScene(sc)
     ref = osc.render(np.array([0.0], np.float32))
-    theta, sigma = 0.45, 0.3
 
     def dQ(dx):
         xs = np.arange(theta - 6 * sigma, theta + 6 * sigma + dx / 2, dx).astype(np.float32)
