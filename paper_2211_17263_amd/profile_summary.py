@@ -107,7 +107,7 @@ def main():
     for k in ("fetch", "write", "copy_fetch", "copy_write"):
         t.add_argument("--" + k.replace("_", "-"), dest=k, required=True)
     t.add_argument("--copy-bytes", type=float, default=float(1 << 30))
-    t.add_argument("--kernel", default="render_loss_kernel<false>")
+    t.add_argument("--kernel", default="render_loss_kernel<false, false>")
     t.add_argument("--source", default=os.path.join(os.path.dirname(__file__), "csrc", "kernels.hip"))
     t.add_argument("--workload", default="")
     t.add_argument("--command", action="append", default=[])
@@ -120,7 +120,7 @@ def main():
     k.add_argument("--command", action="append", default=[])
     k.add_argument("--note", action="append", default=[])
     k.add_argument("--top", type=int, default=8)
-    k.add_argument("--kernel", default="render_loss_kernel<false>",
+    k.add_argument("--kernel", default="render_loss_kernel<false, false>",
                    help="also summarise this kernel's largest-grid dispatches")
     k.add_argument("--last", type=int, default=0,
                    help="only the last N of those dispatches (the timed ones)")
