@@ -60,6 +60,7 @@ extern "C" {
 /*     C_d u_j / (2 sigma_j), C_d = mean of chi_d; unbiased for grad Q.         */
 /* IS_PERDIM: independent two-sided Rayleigh per axis (literal per-dimension    */
 /*     reading); exact for d = 1, biased for non-separable objectives in d > 1. */
+/*     Axis j takes its sign from bit j mod 32 of sign word j / 32.             */
 #define PRDPT_EST_GAUSS 0
 #define PRDPT_EST_IS 1
 #define PRDPT_EST_IS_PERDIM 2
@@ -85,9 +86,10 @@ extern "C" {
 #define PRDPT_BIND_MESH_ROT 5 /* mesh rotation angle (radians) about the x, y or z axis */
 
 /* Limits of one scene. */
-#define PRDPT_MAX_PARAMS 32
+#define PRDPT_MAX_PARAMS 256
+#define PRDPT_BATCH_MAX_PARAMS 32 /* d limit of the batched and served forms */
 #define PRDPT_MAX_MATERIALS 32
-#define PRDPT_MAX_SPHERES 16
+#define PRDPT_MAX_SPHERES 128
 #define PRDPT_MAX_QUADS 16
 #define PRDPT_MAX_INSTANCES 8
 #define PRDPT_MAX_POINT_LIGHTS 8
@@ -252,6 +254,8 @@ int prdpt_combine_async(prdpt_ctx* ctx, int rows, int d, const double* c_dev,
  * perturbation, run of pixel tiles) items from a device counter, one loss and
  * one combine launch, captured once in a HIP graph and replayed per batch.
  * Every result equals prdpt_grad_estimate of that request alone, bit for bit.
+ * A request's scene may have at most PRDPT_BATCH_MAX_PARAMS parameters (larger
+ * d: PRDPT_E_ARG for that request; use the single-request calls).
  */
 typedef struct {
   prdpt_scene* scene;      /* resident scene of the batch's context */
@@ -317,7 +321,7 @@ typedef struct {
   int32_t job;
   int32_t status;                 /* PRDPT_OK, PRDPT_E_CANCELLED, PRDPT_E_ADMISSION, ... */
   double loss;                    /* Q estimate (mean per-image loss) */
-  double grad[PRDPT_MAX_PARAMS];  /* first d entries valid */
+  double grad[PRDPT_BATCH_MAX_PARAMS];  /* first d entries valid */
   double t_submit, t_start, t_done;  /* seconds on the server's steady clock */
 } prdpt_completion;
 
@@ -329,7 +333,9 @@ typedef struct {
 /* Start the server thread on ctx (which must outlive the server). */
 int prdpt_server_start(prdpt_ctx* ctx, const prdpt_server_config* cfg, prdpt_server** out);
 /* Register a job: the description is validated and its BVHs built now (host);
- * ref_host is host float[H][W][3], copied.  *job_id receives the job's id. */
+ * ref_host is host float[H][W][3], copied.  *job_id receives the job's id.
+ * A job's scene has at most PRDPT_BATCH_MAX_PARAMS parameters (else
+ * PRDPT_E_SCENE). */
 int prdpt_server_add_job(prdpt_server* sv, const prdpt_scene_desc* desc, const float* ref_host,
                          int* job_id);
 /* Queue one gradient estimate of job `job_id` (theta, sigma: host float[d], copied). */

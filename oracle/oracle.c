@@ -169,7 +169,7 @@ static void normal_pair(tau_stream* st, float* z0, float* z1) {
 
 int orc_draw_tau(int mode, int d, int P, uint64_t seed, const float* sigma, float* tau,
                  double* c) {
-  if (d < 1 || d > 32 || P < 1) return -1;
+  if (d < 1 || d > ORC_MAX_PARAMS || P < 1) return -1;
   /* independent draws: the same samplers; the weight is the single-sample score
    * weight (its expectation over the draw is the gradient by itself), written
    * below directly: v_j / sigma_j, C_d u_j / sigma_j, s_j 2 / (sigma_j sqrt(2 pi)) */
@@ -177,7 +177,7 @@ int orc_draw_tau(int mode, int d, int P, uint64_t seed, const float* sigma, floa
   mode &= ~ORC_EST_INDEPENDENT;
   double cd = orc_chi_mean(d);
   const double sqrt2pi = sqrt(2.0 * ORC_PI);
-  float v[32], z[32];
+  float v[ORC_MAX_PARAMS], z[ORC_MAX_PARAMS];
   for (int p = 0; p < P; ++p) {
     tau_stream st;
     seed_key(seed, st.key);
@@ -228,11 +228,13 @@ int orc_draw_tau(int mode, int d, int P, uint64_t seed, const float* sigma, floa
                              : cd * (double)uj / (2.0 * (double)sigma[j]);
       }
     } else if (mode == ORC_EST_IS_PERDIM) {
-      /* literal per-dimension reading: independent two-sided Rayleigh per axis */
+      /* literal per-dimension reading: independent two-sided Rayleigh per axis;
+       * the signs come after the radii, one word per 32 axes (bit j mod 32) */
       for (int j = 0; j < d; ++j) v[j] = sqrtf(-2.0f * orc_ln(orc_u01(tau_word(&st))));
-      uint32_t bits = tau_word(&st);
+      uint32_t bits = 0;
       for (int j = 0; j < d; ++j) {
-        float sgn = ((bits >> j) & 1u) ? -1.0f : 1.0f;
+        if (j % 32 == 0) bits = tau_word(&st);
+        float sgn = ((bits >> (j % 32)) & 1u) ? -1.0f : 1.0f;
         tau[p * d + j] = sigma[j] * (sgn * v[j]);
         c[p * d + j] = indep ? 2.0 * (double)sgn / ((double)sigma[j] * sqrt2pi)
                              : (double)sgn / ((double)sigma[j] * sqrt2pi);
@@ -954,7 +956,7 @@ double orc_mse(const float* img, const float* ref, int npix) {
 
 static int check_args(const orc_scene* s, const float* sigma, int N) {
   if (N < 2 || (N & 1)) return -1;
-  if (s->n_param < 1 || s->n_param > 32) return -1;
+  if (s->n_param < 1 || s->n_param > ORC_MAX_PARAMS) return -1;
   for (int j = 0; j < s->n_param; ++j)
     if (!(sigma[j] > 0.0f) || !isfinite(sigma[j])) return -1;
   return 0;
@@ -968,7 +970,7 @@ static void perturbed_losses(const orc_scene* s, const float* ref, const float* 
   int d = s->n_param;
   size_t npix = (size_t)s->W * (size_t)s->H;
   float* img = images ? NULL : (float*)malloc(sizeof(float) * 3 * npix);
-  float X[32];
+  float X[ORC_MAX_PARAMS];
   for (int p = 0; p < P; ++p)
     for (int m = 0; m < 2; ++m) {
       for (int j = 0; j < d; ++j)
@@ -987,7 +989,7 @@ static void independent_losses(const orc_scene* s, const float* ref, const float
   int d = s->n_param;
   size_t npix = (size_t)s->W * (size_t)s->H;
   float* img = images ? NULL : (float*)malloc(sizeof(float) * 3 * npix);
-  float X[32];
+  float X[ORC_MAX_PARAMS];
   for (int i = 0; i < N; ++i) {
     for (int j = 0; j < d; ++j) X[j] = theta[j] + tau[i * d + j];
     float* out = images ? images + (size_t)i * 3 * npix : img;

@@ -20,6 +20,8 @@ extern "C" {
 #endif
 
 enum { ORC_DIFFUSE = 0, ORC_DIELECTRIC = 1, ORC_EMISSIVE = 2 };
+#define ORC_MAX_PARAMS 256
+
 enum { ORC_BIND_SPHERE = 0, ORC_BIND_QUAD = 1, ORC_BIND_MESH = 2, ORC_BIND_PLIGHT = 3,
        ORC_BIND_ALBEDO = 4, /* material colour channel: albedo (diffuse) or radiance (emissive) */
        ORC_BIND_MESH_ROT = 5 /* mesh rotation angle (radians) about the x, y or z axis */ };

@@ -68,7 +68,8 @@ hipError_t timed_render(prdpt_ctx* ctx, const prdpt_scene* s, const float* X, in
     }
   }
   hipError_t e = launch_render(ctx->stream, sc, W, H, X, nk, d, tag, seed, ref, img, partial, nullptr,
-                               ctx->work.p, s->d_tile_order, s->d_tile_cost, crn, s->hdr.has_rot);
+                               ctx->work.p, s->d_tile_order, s->d_tile_cost, crn, s->hdr.has_rot,
+                               s->hdr.n_sph);
   if (e != hipSuccess) return e;
   if (a && b) {
     e = hipEventRecord(b, ctx->stream);
@@ -522,7 +523,8 @@ int prdpt_render_perturbed(prdpt_scene* s, const float* theta, const float* sigm
                      std::sqrt(2.0 * M_PI), ctx->tau.p, ctx->c.p, ctx->X.p));
   HIP_TRY(launch_render(ctx->stream, s->dev(), h.W, h.H, ctx->X.p, N, d, kTagPath, seed, nullptr,
                         images_out, nullptr, nullptr, ctx->work.p, s->d_tile_order,
-                        s->d_tile_cost, (est & PRDPT_EST_INDEPENDENT) ? 0 : 1, h.has_rot));
+                        s->d_tile_cost, (est & PRDPT_EST_INDEPENDENT) ? 0 : 1, h.has_rot,
+                        h.n_sph));
   if (tau_out)
     HIP_TRY(hipMemcpyAsync(tau_out, ctx->tau.p, sizeof(float) * rows * d, hipMemcpyDeviceToHost,
                            ctx->stream));
@@ -541,7 +543,7 @@ int prdpt_render_reference(prdpt_scene* s, const float* X, uint64_t seed, float*
   HIP_TRY(hipMemcpyAsync(ctx->X.p, X, sizeof(float) * d, hipMemcpyHostToDevice, ctx->stream));
   HIP_TRY(launch_render(ctx->stream, s->dev(), h.W, h.H, ctx->X.p, 1, d, kTagRef, seed, nullptr,
                         image_out, nullptr, nullptr, ctx->work.p, s->d_tile_order,
-                        s->d_tile_cost, 1, h.has_rot));
+                        s->d_tile_cost, 1, h.has_rot, h.n_sph));
   HIP_TRY(hipStreamSynchronize(ctx->stream));
   return PRDPT_OK;
 }
@@ -662,7 +664,8 @@ int prdpt_traversal_counts(prdpt_scene* s, const float* theta, const float* sigm
                      std::sqrt(2.0 * M_PI), ctx->tau.p, ctx->c.p, ctx->X.p));
   HIP_TRY(launch_render(ctx->stream, s->dev(), h.W, h.H, ctx->X.p, N, d, kTagPath, seed, nullptr,
                         nullptr, nullptr, ctx->counters.p, ctx->work.p, s->d_tile_order,
-                        nullptr, (est & PRDPT_EST_INDEPENDENT) ? 0 : 1, s->hdr.has_rot));
+                        nullptr, (est & PRDPT_EST_INDEPENDENT) ? 0 : 1, s->hdr.has_rot,
+                        s->hdr.n_sph));
   unsigned long long host[7];
   HIP_TRY(hipMemcpyAsync(host, ctx->counters.p, sizeof(host), hipMemcpyDeviceToHost, ctx->stream));
   HIP_TRY(hipStreamSynchronize(ctx->stream));

@@ -83,24 +83,24 @@ int ensure_batch(prdpt_ctx* ctx, BatchState& b, size_t n_req, size_t pairs, size
   auto want = [](size_t need, size_t have) { return need > have ? std::max(need, have + have / 2) : 0; };
   if (size_t w = want(n_req, b.cap_req)) {
     HIP_TRY(hipStreamSynchronize(b.stream));
-    if ((rc = grow_dev(b.d_reqs, dummy, w)) || (rc = grow_dev(b.d_grads, dummy, w * PRDPT_MAX_PARAMS)) ||
+    if ((rc = grow_dev(b.d_reqs, dummy, w)) || (rc = grow_dev(b.d_grads, dummy, w * PRDPT_BATCH_MAX_PARAMS)) ||
         (rc = grow_dev(b.d_loss, dummy, w)) || (rc = grow_host(b.h_reqs, w)) ||
-        (rc = grow_host(b.h_grads, w * PRDPT_MAX_PARAMS)) || (rc = grow_host(b.h_loss, w)))
+        (rc = grow_host(b.h_grads, w * PRDPT_BATCH_MAX_PARAMS)) || (rc = grow_host(b.h_loss, w)))
       return rc;
     b.cap_req = w;
     changed = true;
   }
   if (size_t w = want(pairs, b.cap_pairs)) {
     HIP_TRY(hipStreamSynchronize(b.stream));
-    if ((rc = grow_dev(b.d_tau, dummy, w * PRDPT_MAX_PARAMS)) ||
-        (rc = grow_dev(b.d_c, dummy, w * PRDPT_MAX_PARAMS)))
+    if ((rc = grow_dev(b.d_tau, dummy, w * PRDPT_BATCH_MAX_PARAMS)) ||
+        (rc = grow_dev(b.d_c, dummy, w * PRDPT_BATCH_MAX_PARAMS)))
       return rc;
     b.cap_pairs = w;
     changed = true;
   }
   if (size_t w = want(rows, b.cap_rows)) {
     HIP_TRY(hipStreamSynchronize(b.stream));
-    if ((rc = grow_dev(b.d_X, dummy, w * PRDPT_MAX_PARAMS)) || (rc = grow_dev(b.d_losses, dummy, w)) ||
+    if ((rc = grow_dev(b.d_X, dummy, w * PRDPT_BATCH_MAX_PARAMS)) || (rc = grow_dev(b.d_losses, dummy, w)) ||
         (rc = grow_host(b.h_losses, w)))
       return rc;
     b.cap_rows = w;
@@ -127,6 +127,7 @@ int check_one(prdpt_ctx* ctx, const prdpt_request& r) {
   if (!r.ref || !r.theta || !r.sigma || !r.grad_out) return PRDPT_E_ARG;
   if (r.N < 2 || (r.N & 1) || r.N > (1 << 20)) return PRDPT_E_ARG;
   if (r.est < PRDPT_EST_GAUSS || r.est > PRDPT_EST_IS_PERDIM) return PRDPT_E_ARG;
+  if (s->hdr.n_param > PRDPT_BATCH_MAX_PARAMS) return PRDPT_E_ARG;
   for (int j = 0; j < s->hdr.n_param; ++j) {
     if (!std::isfinite(r.theta[j])) return PRDPT_E_ARG;
     if (!(r.sigma[j] > 0.0f) || !std::isfinite(r.sigma[j])) return PRDPT_E_ARG;
@@ -134,8 +135,8 @@ int check_one(prdpt_ctx* ctx, const prdpt_request& r) {
   return PRDPT_OK;
 }
 
-int launch_sequence(BatchState& b, int render_blocks, int rot) {
-  HIP_TRY(launch_batch(b.stream, b.d_reqs, b.d_meta, render_blocks, rot, b.d_tau, b.d_c, b.d_X,
+int launch_sequence(BatchState& b, int render_blocks, int rot, int max_sph) {
+  HIP_TRY(launch_batch(b.stream, b.d_reqs, b.d_meta, render_blocks, rot, max_sph, b.d_tau, b.d_c, b.d_X,
                        b.d_partial, b.d_losses, b.d_grads, b.d_loss));
   return PRDPT_OK;
 }
@@ -216,7 +217,11 @@ int batch_enqueue(prdpt_ctx* ctx, BatchState& b, prdpt_request* reqs, int n, std
   m.tiles_per_item = tpi;
   const int render_blocks = std::max(1, b.n_cu * b.blocks_per_cu);
   int rot = 0;  // the render variant that applies instance rotations
-  for (int i : ok) rot |= reqs[i].scene->hdr.has_rot;
+  int max_sph = 0;
+  for (int i : ok) {
+    rot |= reqs[i].scene->hdr.has_rot;
+    max_sph = std::max(max_sph, reqs[i].scene->hdr.n_sph);
+  }
   // order after earlier work on the context stream (e.g. reference uploads)
   HIP_TRY(hipEventRecord(b.ready, ctx->stream));
   HIP_TRY(hipStreamWaitEvent(b.stream, b.ready, 0));
@@ -224,14 +229,14 @@ int batch_enqueue(prdpt_ctx* ctx, BatchState& b, prdpt_request* reqs, int n, std
   HIP_TRY(hipMemcpyAsync(b.d_meta, b.h_meta, sizeof(BatchMeta), hipMemcpyHostToDevice, b.stream));
   if (t0) HIP_TRY(hipEventRecord(t0, b.stream));
   if (b.use_graph) {
-    if (b.exec && (b.graph_blocks != render_blocks || b.graph_rot != rot)) {
+    if (b.exec && (b.graph_blocks != render_blocks || b.graph_rot != rot || b.graph_sph != max_sph)) {
       HIP_TRY(hipGraphExecDestroy(b.exec));
       b.exec = nullptr;
     }
     if (!b.exec) {
       hipGraph_t g = nullptr;
       HIP_TRY(hipStreamBeginCapture(b.stream, hipStreamCaptureModeThreadLocal));
-      const int rc = launch_sequence(b, render_blocks, rot);
+      const int rc = launch_sequence(b, render_blocks, rot, max_sph);
       hipError_t e = hipStreamEndCapture(b.stream, &g);
       if (rc) return rc;
       if (e != hipSuccess) return fail(PRDPT_E_HIP, std::string("graph capture: ") + hipGetErrorString(e));
@@ -243,13 +248,14 @@ int batch_enqueue(prdpt_ctx* ctx, BatchState& b, prdpt_request* reqs, int n, std
       }
       b.graph_blocks = render_blocks;
       b.graph_rot = rot;
+      b.graph_sph = max_sph;
     }
     HIP_TRY(hipGraphLaunch(b.exec, b.stream));
   } else {
-    if (int rc = launch_sequence(b, render_blocks, rot)) return rc;
+    if (int rc = launch_sequence(b, render_blocks, rot, max_sph)) return rc;
   }
   if (t1) HIP_TRY(hipEventRecord(t1, b.stream));
-  HIP_TRY(hipMemcpyAsync(b.h_grads, b.d_grads, sizeof(double) * PRDPT_MAX_PARAMS * ok.size(),
+  HIP_TRY(hipMemcpyAsync(b.h_grads, b.d_grads, sizeof(double) * PRDPT_BATCH_MAX_PARAMS * ok.size(),
                          hipMemcpyDeviceToHost, b.stream));
   HIP_TRY(hipMemcpyAsync(b.h_loss, b.d_loss, sizeof(double) * ok.size(), hipMemcpyDeviceToHost, b.stream));
   HIP_TRY(hipMemcpyAsync(b.h_losses, b.d_losses, sizeof(double) * rows, hipMemcpyDeviceToHost, b.stream));
@@ -261,7 +267,7 @@ void batch_collect(BatchState& b, prdpt_request* reqs, const std::vector<int>& o
   for (size_t q = 0; q < ok.size(); ++q) {
     prdpt_request& r = reqs[ok[q]];
     const BatchReq& t = b.h_reqs[q];
-    std::memcpy(r.grad_out, b.h_grads + q * PRDPT_MAX_PARAMS, sizeof(double) * t.d);
+    std::memcpy(r.grad_out, b.h_grads + q * PRDPT_BATCH_MAX_PARAMS, sizeof(double) * t.d);
     if (r.loss_out) *r.loss_out = b.h_loss[q];
     if (r.losses_out) std::memcpy(r.losses_out, b.h_losses + t.row_base, sizeof(double) * r.N);
   }

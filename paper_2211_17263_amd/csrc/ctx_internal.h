@@ -19,7 +19,7 @@ hipError_t launch_tau(hipStream_t st, int est, int d, int P, uint64_t seed, cons
 hipError_t launch_render(hipStream_t st, const DevScene& sc, int W, int H, const float* X, int nk,
                          int d, int tag, uint64_t seed, const float* ref, float* img,
                          float* partial, unsigned long long* counters, int* work,
-                         const int* order, float* cost, int crn, int rot);
+                         const int* order, float* cost, int crn, int rot, int n_sph);
 // Rz(c) Ry(b) Rx(a) of the angles (a, b, c), row-major (the kernels' own formula)
 void euler_rotation_host(const float* ang, float* R);
 // tiles by descending measured render time (no-op for more than 4096 tiles)
@@ -29,10 +29,11 @@ hipError_t launch_losses(hipStream_t st, const float* partial, int n_tiles, int 
 // rows = pairs (antithetic) or draws (independent != 0)
 hipError_t launch_combine(hipStream_t st, int rows, int d, int independent, const double* c,
                           const double* L, const double* scale, double* grad, double* loss);
-// rot != 0: some request's scene has rotated instances
+// rot != 0: some request's scene has rotated instances; max_sph: the largest
+// sphere count of the batch's scenes (sizes the render kernel's dynamic LDS)
 hipError_t launch_batch(hipStream_t st, const BatchReq* reqs, BatchMeta* meta, int render_blocks,
-                        int rot, float* tau, double* c, float* X, float* partial, double* losses,
-                        double* grads, double* loss);
+                        int rot, int max_sph, float* tau, double* c, float* X, float* partial,
+                        double* losses, double* grads, double* loss);
 hipError_t launch_copy(hipStream_t st, const void* src, void* dst, size_t n16);
 
 // records `msg` as the calling thread's last error and returns `code`
@@ -76,6 +77,7 @@ struct BatchState {
   hipGraphExec_t exec = nullptr;
   int graph_blocks = 0;
   int graph_rot = 0;  // render variant captured in the graph
+  int graph_sph = 0;  // sphere count its dynamic LDS was sized for
 };
 
 void batch_release(BatchState& b);

@@ -321,7 +321,7 @@ __host__ __device__ inline void euler_rotation(const float* ang, float* R) {
 // (without rotations, ROT = false: o - t and d).  R is orthonormal, so the ray
 // parameter of a hit is the same in both frames.
 template <bool ROT>
-__device__ __forceinline__ void to_instance(const SceneHdr& S, int inst, V3 o, V3 d, V3& om,
+__device__ __forceinline__ void to_instance(const SceneLds& S, int inst, V3 o, V3 d, V3& om,
                                             V3& dm) {
   const V3 q = mk(o.x - S.inst_xlate[inst][0], o.y - S.inst_xlate[inst][1],
                   o.z - S.inst_xlate[inst][2]);
@@ -344,7 +344,7 @@ struct Trav {
 };
 
 // first instance at or after i with a BVH, or n_inst
-__device__ __forceinline__ int next_inst(const SceneHdr& S, int i) {
+__device__ __forceinline__ int next_inst(const SceneLds& S, int i) {
   while (i < S.n_inst && S.inst_root[i] < 0) ++i;
   return i;
 }
@@ -353,8 +353,9 @@ __device__ __forceinline__ int next_inst(const SceneHdr& S, int i) {
 // stack.  Returns true when the query is already answered (a shadow ray
 // blocked by an analytic primitive, or nothing left to traverse).
 template <bool COUNT>
-__device__ __forceinline__ bool begin_trace(const SceneHdr& S, V3 o, V3 d, float tmax, bool any,
-                                            Trav& tr, int* __restrict__ stack, Counters& cnt) {
+__device__ __forceinline__ bool begin_trace(const SceneLds& S, const float* __restrict__ sph,
+                                            V3 o, V3 d, float tmax, bool any, Trav& tr,
+                                            int* __restrict__ stack, Counters& cnt) {
   Hit& h = tr.h;
   h.t = __builtin_huge_valf();
   h.id = -1;
@@ -362,7 +363,7 @@ __device__ __forceinline__ bool begin_trace(const SceneHdr& S, V3 o, V3 d, float
   if (COUNT) cnt.rays++;
   for (int i = 0; i < S.n_sph; ++i) {
     float t;
-    if (hit_sphere(o, d, S.sph[i], tmax, &t)) {
+    if (hit_sphere(o, d, sph + 4 * i, tmax, &t)) {
       if (any) {
         h.id = i;
         return true;
@@ -390,7 +391,7 @@ __device__ __forceinline__ bool begin_trace(const SceneHdr& S, V3 o, V3 d, float
 
 // Continues a query; returns true when it is answered (tr.h holds the result).
 template <bool COUNT, bool ROT>
-__device__ bool continue_trace(const SceneHdr& S, const Node* __restrict__ nodes,
+__device__ bool continue_trace(const SceneLds& S, const Node* __restrict__ nodes,
                                const Tri* __restrict__ tris, V3 o, V3 d, float tmax, bool any,
                                Trav& tr, int* __restrict__ stack, int stride,
                                int* __restrict__ ovf, int budget, Counters& cnt) {
@@ -576,27 +577,31 @@ constexpr int kTileW = 8, kTileH = 8, kBlock = kTileW * kTileH;  // one wave per
 #define PRDPT_MIN_WAVES_PER_EU 4
 #endif
 
-// Load the scene constants into LDS and apply perturbation k's parameter values.
-__device__ __forceinline__ void load_state(SceneHdr& S, const SceneHdr* __restrict__ g,
+// Load the scene constants and the spheres into LDS and apply perturbation k's
+// parameter values (one binding per thread; no two bindings share a field).
+__device__ __forceinline__ void load_state(SceneLds& S, float* __restrict__ sph,
+                                           int* __restrict__ sph_mat,
+                                           const SceneHdr* __restrict__ g,
                                            const float* __restrict__ X, int d) {
-  const uint32_t* src = reinterpret_cast<const uint32_t*>(g);
+  const uint32_t* src = reinterpret_cast<const uint32_t*>(static_cast<const SceneLds*>(g));
   uint32_t* dst = reinterpret_cast<uint32_t*>(&S);
-  constexpr int words = sizeof(SceneHdr) / 4;
+  constexpr int words = sizeof(SceneLds) / 4;
   for (int i = threadIdx.x; i < words; i += blockDim.x) dst[i] = src[i];
+  const int n_sph = g->n_sph;
+  for (int i = threadIdx.x; i < 4 * n_sph; i += blockDim.x) sph[i] = g->sph[i >> 2][i & 3];
+  for (int i = threadIdx.x; i < n_sph; i += blockDim.x) sph_mat[i] = g->sph_mat[i];
   __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int j = 0; j < d; ++j) {
-      const int kind = S.bind_kind[j], i = S.bind_index[j], c = S.bind_comp[j];
-      const float xj = X[j];
-      if (kind == PRDPT_BIND_SPHERE) S.sph[i][c] = g->sph[i][c] + xj;
-      else if (kind == PRDPT_BIND_QUAD) S.quad[i][c] = g->quad[i][c] + xj;
-      else if (kind == PRDPT_BIND_MESH) S.inst_xlate[i][c] = g->inst_xlate[i][c] + xj;
-      else if (kind == PRDPT_BIND_PLIGHT) S.pl[i][c] = g->pl[i][c] + xj;
-      else if (kind == PRDPT_BIND_ALBEDO) S.mat_rgb[i][c] = g->mat_rgb[i][c] + xj;
-      else if (kind == PRDPT_BIND_MESH_ROT) S.inst_ang[i][c] = g->inst_ang[i][c] + xj;
-    }
+  for (int j = threadIdx.x; j < d; j += blockDim.x) {
+    const int kind = g->bind_kind[j], i = g->bind_index[j], c = g->bind_comp[j];
+    const float xj = X[j];
+    if (kind == PRDPT_BIND_SPHERE) sph[4 * i + c] = g->sph[i][c] + xj;
+    else if (kind == PRDPT_BIND_QUAD) S.quad[i][c] = g->quad[i][c] + xj;
+    else if (kind == PRDPT_BIND_MESH) S.inst_xlate[i][c] = g->inst_xlate[i][c] + xj;
+    else if (kind == PRDPT_BIND_PLIGHT) S.pl[i][c] = g->pl[i][c] + xj;
+    else if (kind == PRDPT_BIND_ALBEDO) S.mat_rgb[i][c] = g->mat_rgb[i][c] + xj;
+    else if (kind == PRDPT_BIND_MESH_ROT) S.inst_ang[i][c] = g->inst_ang[i][c] + xj;
   }
-  if (S.has_rot) {  // uniform: every work-group of the launch reads the same header
+  if (g->has_rot) {  // uniform: every thread reads the same header
     __syncthreads();
     if ((int)threadIdx.x < S.n_inst) euler_rotation(S.inst_ang[threadIdx.x], S.inst_rot[threadIdx.x]);
   }
@@ -616,7 +621,9 @@ __device__ __forceinline__ void load_state(SceneHdr& S, const SceneHdr* __restri
 // sample the radiance terms are added in the same order as a recursive
 // implementation (vertex by vertex; point lights, then area lights).
 template <bool COUNT, bool ROT>
-__device__ __forceinline__ void render_tile(const SceneHdr& S, const Node* __restrict__ nodes,
+__device__ __forceinline__ void render_tile(const SceneLds& S, const float* __restrict__ sph,
+                                            const int* __restrict__ sph_mat,
+                                            const Node* __restrict__ nodes,
                                             const Tri* __restrict__ tris, int k, int tile, int tag,
                                             uint32_t k0, uint32_t k1, const float* __restrict__ ref,
                                             float* __restrict__ img, float* partial_slot,
@@ -675,8 +682,8 @@ __device__ __forceinline__ void render_tile(const SceneHdr& S, const Node* __res
           p = at(o, dir, h.t);
           V3 ng;
           if (h.id < S.n_sph) {
-            mat = S.sph_mat[h.id];
-            ng = unit(sub(p, ld3(S.sph[h.id])));
+            mat = sph_mat[h.id];
+            ng = unit(sub(p, ld3(sph + 4 * h.id)));
           } else if (h.id < S.tri_id_base) {
             const int qi = h.id - S.n_sph;
             mat = S.quad_mat[qi];
@@ -858,7 +865,7 @@ __device__ __forceinline__ void render_tile(const SceneHdr& S, const Node* __res
         v = 0;
         light = -1;
       }
-      tracing = !begin_trace<COUNT>(S, o, dir, tmax, shadow, tr, stk, cnt);
+      tracing = !begin_trace<COUNT>(S, sph, o, dir, tmax, shadow, tr, stk, cnt);
       if (!tracing) {
         answered = true;
         continue;
@@ -928,10 +935,12 @@ __global__ __launch_bounds__(kBlock, PRDPT_MIN_WAVES_PER_EU) void render_loss_ke
     const float* __restrict__ ref, float* __restrict__ img, float* __restrict__ partial,
     unsigned long long* __restrict__ counters, int n_tiles, int n_items, int* __restrict__ work,
     const int* __restrict__ order, float* __restrict__ cost, int crn) {
-  __shared__ SceneHdr S;
+  __shared__ SceneLds S;
   __shared__ int stack[kStackEntries * kBlock];
   __shared__ float wsum[kBlock / 64];
   __shared__ int s_item;
+  extern __shared__ float sph[];  // sphere_lds_bytes(n_sph) at launch
+  int* sph_mat = reinterpret_cast<int*>(sph + 4 * scene.hdr->n_sph);
   int cur = -1;
   while (true) {
     if (threadIdx.x == 0) s_item = atomicAdd(work, 1);
@@ -943,12 +952,12 @@ __global__ __launch_bounds__(kBlock, PRDPT_MIN_WAVES_PER_EU) void render_loss_ke
     int tile = order ? order[j] : j;
     if ((unsigned)tile >= (unsigned)n_tiles) tile = j;  // a permutation by construction
     if (k != cur) {  // the scene state of perturbation k (after the previous tile's last use)
-      load_state(S, scene.hdr, X + (size_t)k * d, d);
+      load_state(S, sph, sph_mat, scene.hdr, X + (size_t)k * d, d);
       cur = k;
     }
     unsigned long long t0 = 0;
     if (cost && threadIdx.x == 0) t0 = wall_clock64();
-    render_tile<COUNT, ROT>(S, scene.nodes, scene.tris, k, tile, tag, k0, k1, ref, img,
+    render_tile<COUNT, ROT>(S, sph, sph_mat, scene.nodes, scene.tris, k, tile, tag, k0, k1, ref, img,
                        partial ? partial + (size_t)k * n_tiles + tile : nullptr, counters, stack,
                        wsum, crn);
     if (cost && threadIdx.x == 0) cost[tile] = (float)(wall_clock64() - t0);
@@ -1026,23 +1035,22 @@ __device__ void draw_pair(int est, int d, int p, uint32_t k0, uint32_t k1,
     *z0 = rad * cs;
     *z1 = rad * sn;
   };
-  float v[PRDPT_MAX_PARAMS];
-  float tv[PRDPT_MAX_PARAMS];
-  double cw[PRDPT_MAX_PARAMS];
   // without antithetic partners each draw carries the single-sample score
-  // weight, twice the pair weight (exact in binary64)
+  // weight, twice the pair weight (exact in binary64).  The row tau holds the
+  // normal or radius draws until their final values replace them.
   const double wscale = (est & PRDPT_EST_INDEPENDENT) ? 2.0 : 1.0;
   est &= ~PRDPT_EST_INDEPENDENT;
   if (est == PRDPT_EST_GAUSS) {
     for (int j = 0; j < d; j += 2) {
       float z0, z1;
       gauss2(&z0, &z1);
-      v[j] = z0;
-      if (j + 1 < d) v[j + 1] = z1;
+      tau[j] = z0;
+      if (j + 1 < d) tau[j + 1] = z1;
     }
     for (int j = 0; j < d; ++j) {
-      tv[j] = sigma[j] * v[j];
-      cw[j] = (double)v[j] / (2.0 * (double)sigma[j]);
+      const float v = tau[j];
+      tau[j] = sigma[j] * v;
+      c[j] = wscale * ((double)v / (2.0 * (double)sigma[j]));
     }
   } else if (est == PRDPT_EST_IS) {
     const int m = (d + 1) / 2;
@@ -1057,32 +1065,31 @@ __device__ void draw_pair(int est, int d, int p, uint32_t k0, uint32_t k1,
     for (int j = 0; j < d; j += 2) {
       float z0, z1;
       gauss2(&z0, &z1);
-      v[j] = z0;
-      if (j + 1 < d) v[j + 1] = z1;
+      tau[j] = z0;
+      if (j + 1 < d) tau[j + 1] = z1;
     }
     float n2 = 0.0f;
-    for (int j = 0; j < d; ++j) n2 = n2 + v[j] * v[j];
+    for (int j = 0; j < d; ++j) n2 = n2 + tau[j] * tau[j];
     const float nrm = sqrtf(n2);
     const float rho = sqrtf(rho2);
     for (int j = 0; j < d; ++j) {
-      const float uj = v[j] / nrm;
-      tv[j] = sigma[j] * (rho * uj);
-      cw[j] = cd * (double)uj / (2.0 * (double)sigma[j]);
+      const float uj = tau[j] / nrm;
+      tau[j] = sigma[j] * (rho * uj);
+      c[j] = wscale * (cd * (double)uj / (2.0 * (double)sigma[j]));
     }
   } else {
-    for (int j = 0; j < d; ++j) v[j] = sqrtf(-2.0f * log_ieee(unit_open(word())));
-    const uint32_t bits = word();
-    for (int j = 0; j < d; ++j) {
-      const float sg = ((bits >> j) & 1u) ? -1.0f : 1.0f;
-      tv[j] = sigma[j] * (sg * v[j]);
-      cw[j] = (double)sg / ((double)sigma[j] * sqrt2pi);
+    for (int j = 0; j < d; ++j) tau[j] = sqrtf(-2.0f * log_ieee(unit_open(word())));
+    uint32_t bits = 0;
+    for (int j = 0; j < d; ++j) {  // one sign word per 32 axes, after the radii
+      if ((j & 31) == 0) bits = word();
+      const float sg = ((bits >> (j & 31)) & 1u) ? -1.0f : 1.0f;
+      tau[j] = sigma[j] * (sg * tau[j]);
+      c[j] = wscale * ((double)sg / ((double)sigma[j] * sqrt2pi));
     }
   }
   for (int j = 0; j < d; ++j) {
-    tau[j] = tv[j];
-    c[j] = wscale * cw[j];
-    Xp[j] = theta[j] + tv[j];
-    if (Xm) Xm[j] = theta[j] - tv[j];
+    Xp[j] = theta[j] + tau[j];
+    if (Xm) Xm[j] = theta[j] - tau[j];
   }
   (void)ld;
 }
@@ -1100,17 +1107,17 @@ __device__ __forceinline__ double row_loss(const float* __restrict__ part, int n
 }
 
 // g_j = scale (1/P) sum_p c_pj (L_2p - L_2p+1) and Q = mean L, binary64, pair
-// order (Eq. 10 with antithetic pairs); c rows have stride ld.  Thread j < d.
+// order (Eq. 10 with antithetic pairs); c rows have stride ld.  Thread t takes
+// the components t, t + blockDim.x, ...
 __device__ __forceinline__ void combine_one(int P, int d, int ld, const double* __restrict__ c,
                                             const double* __restrict__ L, double sc,
                                             double* __restrict__ grad, double* __restrict__ loss) {
-  const int j = threadIdx.x;
-  if (j < d) {
+  for (int j = threadIdx.x; j < d; j += blockDim.x) {
     double acc = 0.0;
     for (int p = 0; p < P; ++p) acc += c[(size_t)p * ld + j] * (L[2 * p] - L[2 * p + 1]);
     grad[j] = sc * (acc / (double)P);
   }
-  if (j == 0 && loss) {
+  if (threadIdx.x == 0 && loss) {
     double s = 0.0;
     for (int k = 0; k < 2 * P; ++k) s += L[k];
     *loss = s / (double)(2 * P);
@@ -1122,13 +1129,12 @@ __device__ __forceinline__ void combine_independent(int N, int d, const double* 
                                                     const double* __restrict__ L, double sc,
                                                     double* __restrict__ grad,
                                                     double* __restrict__ loss) {
-  const int j = threadIdx.x;
-  if (j < d) {
+  for (int j = threadIdx.x; j < d; j += blockDim.x) {
     double acc = 0.0;
     for (int i = 0; i < N; ++i) acc += c[(size_t)i * d + j] * L[i];
     grad[j] = sc * (acc / (double)N);
   }
-  if (j == 0 && loss) {
+  if (threadIdx.x == 0 && loss) {
     double s = 0.0;
     for (int i = 0; i < N; ++i) s += L[i];
     *loss = s / (double)N;
@@ -1194,7 +1200,7 @@ __global__ void batch_tau_kernel(const BatchReq* __restrict__ reqs, const BatchM
                                  float* __restrict__ tau, double* __restrict__ c,
                                  float* __restrict__ X) {
   const int total = meta->total_pairs, n = meta->n_req;
-  constexpr int ld = PRDPT_MAX_PARAMS;
+  constexpr int ld = PRDPT_BATCH_MAX_PARAMS;
   for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < total; g += gridDim.x * blockDim.x) {
     const int r = find_request(reqs, n, g, offsetof(BatchReq, pair_base));
     const BatchReq& q = reqs[r];
@@ -1212,10 +1218,11 @@ template <bool ROT>
 __global__ __launch_bounds__(kBlock, PRDPT_MIN_WAVES_PER_EU) void batch_render_kernel(
     const BatchReq* __restrict__ reqs, BatchMeta* __restrict__ meta, const float* __restrict__ X,
     float* __restrict__ partial) {
-  __shared__ SceneHdr S;
+  __shared__ SceneLds S;
   __shared__ int stack[kStackEntries * kBlock];
   __shared__ float wsum[kBlock / 64];
   __shared__ int s_item;
+  extern __shared__ float sph[];  // sphere_lds_bytes(largest n_sph of the batch) at launch
   const int total = meta->total_items, n = meta->n_req, tpi = meta->tiles_per_item;
   while (true) {
     if (threadIdx.x == 0) s_item = atomicAdd(&meta->counter, 1);
@@ -1229,9 +1236,11 @@ __global__ __launch_bounds__(kBlock, PRDPT_MIN_WAVES_PER_EU) void batch_render_k
     const int k = local / q.items_per_row;
     const int first = (local % q.items_per_row) * tpi;
     const int last = min(first + tpi, q.n_tiles);
-    load_state(S, q.scene.hdr, X + (size_t)(q.row_base + k) * PRDPT_MAX_PARAMS, q.d);
+    int* sph_mat = reinterpret_cast<int*>(sph + 4 * q.scene.hdr->n_sph);
+    load_state(S, sph, sph_mat, q.scene.hdr, X + (size_t)(q.row_base + k) * PRDPT_BATCH_MAX_PARAMS,
+               q.d);
     for (int tile = first; tile < last; ++tile) {
-      render_tile<false, ROT>(S, q.scene.nodes, q.scene.tris, k, tile, kTagPath, q.k0, q.k1, q.ref,
+      render_tile<false, ROT>(S, sph, sph_mat, q.scene.nodes, q.scene.tris, k, tile, kTagPath, q.k0, q.k1, q.ref,
                          nullptr, partial + (size_t)q.partial_base + (size_t)k * q.n_tiles + tile,
                          nullptr, stack, wsum, 1);
       __syncthreads();
@@ -1259,8 +1268,9 @@ __global__ void batch_combine_kernel(const BatchReq* __restrict__ reqs,
                                      double* __restrict__ grads, double* __restrict__ loss) {
   for (int r = blockIdx.x; r < meta->n_req; r += gridDim.x) {
     const BatchReq& q = reqs[r];
-    combine_one(q.N / 2, q.d, PRDPT_MAX_PARAMS, c + (size_t)q.pair_base * PRDPT_MAX_PARAMS,
-                losses + q.row_base, 1.0, grads + (size_t)r * PRDPT_MAX_PARAMS, loss + r);
+    combine_one(q.N / 2, q.d, PRDPT_BATCH_MAX_PARAMS,
+                c + (size_t)q.pair_base * PRDPT_BATCH_MAX_PARAMS, losses + q.row_base, 1.0,
+                grads + (size_t)r * PRDPT_BATCH_MAX_PARAMS, loss + r);
   }
 }
 
@@ -1287,23 +1297,26 @@ hipError_t launch_tau(hipStream_t st, int est, int d, int P, uint64_t seed, cons
   return hipGetLastError();
 }
 
-// resident work-groups of the render kernel on the current device (cached per
-// device and variant)
-int render_grid_limit(int rot) {
-  static int cached[64][2];
+// resident work-groups of the render kernel on the current device for the
+// variant and the dynamic LDS of n_sph spheres (cached)
+int render_grid_limit(int rot, int n_sph) {
+  static int cached[64][2][PRDPT_MAX_SPHERES + 1];
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+  if (n_sph < 0 || n_sph > PRDPT_MAX_SPHERES) return 0;
   rot = rot ? 1 : 0;
-  if (cached[dev][rot] > 0) return cached[dev][rot];
+  int& slot = cached[dev][rot][n_sph];
+  if (slot > 0) return slot;
   int n_cu = 0, per_cu = 0;
   if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  const size_t lds = (size_t)sphere_lds_bytes(n_sph);
   const hipError_t e = rot ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                                 &per_cu, render_loss_kernel<false, true>, kBlock, 0)
+                                 &per_cu, render_loss_kernel<false, true>, kBlock, lds)
                            : hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                                 &per_cu, render_loss_kernel<false, false>, kBlock, 0);
+                                 &per_cu, render_loss_kernel<false, false>, kBlock, lds);
   if (e != hipSuccess) return 0;
-  cached[dev][rot] = std::max(1, n_cu * std::max(1, per_cu));
-  return cached[dev][rot];
+  slot = std::max(1, n_cu * std::max(1, per_cu));
+  return slot;
 }
 
 void euler_rotation_host(const float* ang, float* R) { euler_rotation(ang, R); }
@@ -1311,16 +1324,17 @@ void euler_rotation_host(const float* ang, float* R) { euler_rotation(ang, R); }
 hipError_t launch_render(hipStream_t st, const DevScene& sc, int W, int H, const float* X, int nk,
                          int d, int tag, uint64_t seed, const float* ref, float* img,
                          float* partial, unsigned long long* counters, int* work,
-                         const int* order, float* cost, int crn, int rot) {
+                         const int* order, float* cost, int crn, int rot, int n_sph) {
   const int n_tiles = render_tiles(W, H);
   const int n_items = n_tiles * nk;
-  const int limit = render_grid_limit(rot);
+  const int limit = render_grid_limit(rot, n_sph);
   if (limit <= 0) return hipErrorInvalidDevice;
+  const size_t lds = (size_t)sphere_lds_bytes(n_sph);
   const int blocks = std::min(n_items, limit);
   hipLaunchKernelGGL(reset_work_kernel, dim3(1), dim3(64), 0, st, work);
   const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
 #define PRDPT_RENDER(C, R)                                                                      \
-  hipLaunchKernelGGL((render_loss_kernel<C, R>), dim3(blocks), dim3(kBlock), 0, st, sc, X, d, tag, \
+  hipLaunchKernelGGL((render_loss_kernel<C, R>), dim3(blocks), dim3(kBlock), lds, st, sc, X, d, tag, \
                      k0, k1, ref, img, partial, counters, n_tiles, n_items, work, order, cost, crn)
   if (counters) {
     if (rot) PRDPT_RENDER(true, true);
@@ -1357,16 +1371,17 @@ hipError_t launch_combine(hipStream_t st, int rows, int d, int independent, cons
 // content (totals are read from the device-side meta), so it can be captured
 // once in a graph and replayed for every batch.
 hipError_t launch_batch(hipStream_t st, const BatchReq* reqs, BatchMeta* meta, int render_blocks,
-                        int rot, float* tau, double* c, float* X, float* partial, double* losses,
-                        double* grads, double* loss) {
+                        int rot, int max_sph, float* tau, double* c, float* X, float* partial,
+                        double* losses, double* grads, double* loss) {
+  const size_t lds = (size_t)sphere_lds_bytes(max_sph);
   hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, st, meta);
   hipLaunchKernelGGL(batch_tau_kernel, dim3(64), dim3(64), 0, st, reqs, meta, tau, c, X);
   if (rot)
-    hipLaunchKernelGGL(batch_render_kernel<true>, dim3(render_blocks), dim3(kBlock), 0, st, reqs,
+    hipLaunchKernelGGL(batch_render_kernel<true>, dim3(render_blocks), dim3(kBlock), lds, st, reqs,
                        meta, X, partial);
   else
-    hipLaunchKernelGGL(batch_render_kernel<false>, dim3(render_blocks), dim3(kBlock), 0, st, reqs,
-                       meta, X, partial);
+    hipLaunchKernelGGL(batch_render_kernel<false>, dim3(render_blocks), dim3(kBlock), lds, st,
+                       reqs, meta, X, partial);
   hipLaunchKernelGGL(batch_loss_kernel, dim3(1024), dim3(64), 0, st, reqs, meta, partial, losses);
   hipLaunchKernelGGL(batch_combine_kernel, dim3(256), dim3(64), 0, st, reqs, meta, c, losses,
                      grads, loss);

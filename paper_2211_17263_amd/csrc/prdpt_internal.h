@@ -47,9 +47,9 @@ struct alignas(16) Tri {
 };
 static_assert(sizeof(Tri) == 48, "triangle layout");
 
-// Small per-scene constants; each work-group copies this to LDS and applies its
-// perturbation's parameter values.
-struct SceneHdr {
+// Small per-scene constants; each work-group copies this part to LDS and
+// applies its perturbation's parameter values.
+struct SceneLds {
   float eye[3], fwd[3], right[3], up[3], env[3];
   int32_t W, H, spp, B, pixel_center;
   int32_t n_mat, n_sph, n_quad, n_inst, n_pl, n_param, n_area, n_tri;
@@ -57,8 +57,6 @@ struct SceneHdr {
   int32_t mat_type[PRDPT_MAX_MATERIALS];
   float mat_rgb[PRDPT_MAX_MATERIALS][3];
   float mat_ior[PRDPT_MAX_MATERIALS];
-  float sph[PRDPT_MAX_SPHERES][4];
-  int32_t sph_mat[PRDPT_MAX_SPHERES];
   float quad[PRDPT_MAX_QUADS][9];
   int32_t quad_mat[PRDPT_MAX_QUADS];
   int32_t area_quad[PRDPT_MAX_QUADS];        // emissive quads in index order
@@ -68,10 +66,23 @@ struct SceneHdr {
   float inst_rot[PRDPT_MAX_INSTANCES][9];    // Rz(c) Ry(b) Rx(a), row-major
   int32_t has_rot;                           // some instance is rotated or has a bound angle
   float pl[PRDPT_MAX_POINT_LIGHTS][6];
+};
+
+// The whole scene header in device memory: the LDS part, then the spheres
+// (copied to a dynamically sized LDS array of n_sph entries, so that scenes
+// with few spheres keep the LDS of many resident work-groups) and the
+// parameter bindings (read from device memory when a perturbation is applied).
+struct SceneHdr : SceneLds {
+  float sph[PRDPT_MAX_SPHERES][4];
+  int32_t sph_mat[PRDPT_MAX_SPHERES];
   int32_t bind_kind[PRDPT_MAX_PARAMS];
   int32_t bind_index[PRDPT_MAX_PARAMS];      // instance index for meshes
   int32_t bind_comp[PRDPT_MAX_PARAMS];
 };
+
+// Dynamic LDS of a render work-group: n_sph spheres (centre, radius) and their
+// materials.
+inline int sphere_lds_bytes(int n_sph) { return n_sph * (4 * 4 + 4); }
 
 // Device-side view of a resident scene.
 struct DevScene {
@@ -81,7 +92,7 @@ struct DevScene {
 };
 
 // One request of a batch (device table, filled by the host per batch).  Rows
-// of X/tau/c use the fixed stride PRDPT_MAX_PARAMS.
+// of X/tau/c use the fixed stride PRDPT_BATCH_MAX_PARAMS.
 struct BatchReq {
   DevScene scene;
   const float* ref;
@@ -89,8 +100,8 @@ struct BatchReq {
   uint32_t k0, k1;
   int32_t item_base, pair_base, row_base, partial_base;
   double cd, sqrt2pi, inv_den;
-  float theta[PRDPT_MAX_PARAMS];
-  float sigma[PRDPT_MAX_PARAMS];
+  float theta[PRDPT_BATCH_MAX_PARAMS];
+  float sigma[PRDPT_BATCH_MAX_PARAMS];
 };
 
 // Batch totals and the work counter of the persistent render kernel.

@@ -44,8 +44,8 @@ struct Job {
 struct Pending {
   int64_t ticket = 0;
   int job = 0;
-  float theta[PRDPT_MAX_PARAMS];
-  float sigma[PRDPT_MAX_PARAMS];
+  float theta[PRDPT_BATCH_MAX_PARAMS];
+  float sigma[PRDPT_BATCH_MAX_PARAMS];
   int N = 0, est = 0;
   uint64_t seed = 0;
   double t_submit = 0.0;
@@ -205,7 +205,7 @@ bool launch_epoch(prdpt_server* sv, Slot& s) {
   if (s.items.empty()) return false;
   const size_t n = s.items.size();
   s.reqs.assign(n, prdpt_request{});
-  s.grads.assign(n, std::vector<double>(PRDPT_MAX_PARAMS, 0.0));
+  s.grads.assign(n, std::vector<double>(PRDPT_BATCH_MAX_PARAMS, 0.0));
   s.loss.assign(n, 0.0);
   for (size_t i = 0; i < n; ++i) {
     Pending& p = s.items[i];
@@ -301,6 +301,8 @@ int prdpt_server_add_job(prdpt_server* sv, const prdpt_scene_desc* desc, const f
   if (!sv || !desc || !ref_host || !job_id) return fail(PRDPT_E_ARG, "null argument");
   auto j = std::make_unique<Job>();
   if (int rc = build_host_scene(desc, j->host)) return rc;
+  if (j->host.hdr.n_param > PRDPT_BATCH_MAX_PARAMS)
+    return fail(PRDPT_E_SCENE, "served jobs take at most PRDPT_BATCH_MAX_PARAMS parameters");
   const size_t n = (size_t)desc->width * desc->height * 3;
   j->ref_host.assign(ref_host, ref_host + n);
   std::lock_guard<std::mutex> g(sv->mu);

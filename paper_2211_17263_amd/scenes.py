@@ -374,6 +374,47 @@ def caustic_problem(seed=3, **kw):
 
 
 # ---------------------------------------------------------------------------
+# many objects: Sort-like stand-in (75 objects, two coordinates each)
+# ---------------------------------------------------------------------------
+def sort_scene(n_objects=75, width=128, height=128, spp=4, bounces=2, radius=0.1, spacing=0.33,
+               n_colours=15, seed=5):
+    """n_objects coloured diffuse spheres on a floor on a square grid, lit by an
+    area light, seen from above at an angle; binds each sphere's x and z (the
+    floor-plane coordinates), so d = 2 n_objects (150 for the default 75)."""
+    rng = np.random.default_rng(seed)
+    s = _new_scene("sort", width, height, spp, bounces, eye=(0.0, 4.2, 2.6), look=(0, 0, 0),
+                   fov=45.0)
+    floor = s.material(DIFFUSE, (0.7, 0.7, 0.7))
+    light = s.material(EMISSIVE, (12.0, 12.0, 12.0))
+    colours = [s.material(DIFFUSE, tuple(rng.uniform(0.1, 0.9, 3))) for _ in range(n_colours)]
+    s.quad((-4.0, 0.0, -4.0), (0.0, 0.0, 8.0), (8.0, 0.0, 0.0), floor)
+    s.quad((-0.75, 3.0, -0.75), (1.5, 0.0, 0.0), (0.0, 0.0, 1.5), light)
+    side = int(math.ceil(math.sqrt(n_objects)))
+    spheres = []
+    for i in range(n_objects):
+        gx, gz = i % side, i // side
+        x = (gx - 0.5 * (side - 1)) * spacing
+        z = (gz - 0.5 * (side - 1)) * spacing
+        spheres.append(s.sphere((x, radius, z), radius, colours[i % n_colours]))
+    for i in spheres:
+        s.bind(BIND_SPHERE, i, 0)
+        s.bind(BIND_SPHERE, i, 2)
+    return s
+
+
+def sort_problem(seed=5, n_objects=75, offset=0.12, **kw):
+    """Recover every object's floor position from offsets of up to `offset` in
+    each coordinate (d = 2 n_objects)."""
+    rng = np.random.default_rng(seed + 1000)
+    scene = sort_scene(n_objects=n_objects, seed=seed, **kw)
+    d = scene.d
+    theta_ref = np.zeros(d, np.float32)
+    theta0 = rng.uniform(-offset, offset, d).astype(np.float32)
+    return dict(scene=scene, theta_ref=theta_ref, theta0=theta0,
+                sigma=np.full(d, 0.05, np.float32), N=16, est=EST_IS)
+
+
+# ---------------------------------------------------------------------------
 # workload 4: many uneven scenes (batched estimation)
 # ---------------------------------------------------------------------------
 def random_job_scene(rng, side, n_tris, spp, bounces):

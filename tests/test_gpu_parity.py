@@ -43,7 +43,7 @@ def to_dev(a):
 
 @pytest.mark.parametrize("mode", [O.GAUSS, O.IS, O.IS_PERDIM, O.IS | O.INDEPENDENT,
                                   O.GAUSS | O.INDEPENDENT])
-@pytest.mark.parametrize("d", [1, 2, 3, 6, 12, 32])
+@pytest.mark.parametrize("d", [1, 2, 3, 6, 12, 32, 33, 150, 256])
 def test_perturbation_draw_bit_exact(ctx, mode, d):
     from paper_2211_17263_amd import native as NV
     say("draw_tau", mode, d)
@@ -159,6 +159,14 @@ def test_rotation_all_axes(ctx, est):
               sigma=np.full(4, 0.2, np.float32), N=8, est=est)
     r, o = _full_parity(ctx, pr, 16, "rotation-all-axes")
     assert np.all(r["grad"] != 0)
+
+
+@pytest.mark.parametrize("est", [O.IS, O.GAUSS, O.IS_PERDIM])
+def test_many_objects_reduced(ctx, est):
+    # 75 spheres, each moved in x and z: d = 150
+    pr = S.sort_problem(width=48, height=40, spp=2)
+    r, o = _full_parity(ctx, pr, 17, "sort-reduced", est=est, N=8)
+    assert np.count_nonzero(r["grad"]) > 100
 
 
 def test_cornell_reduced(ctx):
@@ -292,6 +300,12 @@ def test_error_codes(ctx):
         bad2.quad_mat[0] = bad2.material(S.DIELECTRIC, ior=1.5)
         with pytest.raises(NV.PrdptError) as e:
             gpu_scene(ctx, bad2)
+        assert e.value.code == NV.PRDPT_E_SCENE
+        # at most PRDPT_MAX_PARAMS parameters
+        many = S.sort_scene(n_objects=128)       # 128 spheres (the most), 256 parameters
+        many.bind(S.BIND_QUAD, 0, 1)
+        with pytest.raises(NV.PrdptError) as e:
+            gpu_scene(ctx, many)
         assert e.value.code == NV.PRDPT_E_SCENE
         # rotation bindings: mesh index in range; angles finite
         bad4 = S.toy_scene()

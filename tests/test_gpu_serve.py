@@ -91,6 +91,15 @@ def test_admission_refusal_and_cancel():
     finally:
         sv.stop()
     assert res[t_refused]["status"] == NV.PRDPT_E_ADMISSION
+    # served jobs take at most PRDPT_BATCH_MAX_PARAMS parameters
+    sv2 = NV.Server(ctx)
+    try:
+        srt = S.sort_problem(width=16, height=16, spp=1)
+        with pytest.raises(NV.PrdptError) as e:
+            sv2.add_job(srt["scene"], np.zeros((16, 16, 3), np.float32))
+        assert e.value.code == NV.PRDPT_E_SCENE
+    finally:
+        sv2.stop()
     assert res[tickets[-1]]["status"] == NV.PRDPT_E_CANCELLED
     assert all(res[t]["status"] == 0 for t in tickets[:-1])
     ctx.close()

@@ -101,7 +101,7 @@ def test_per_dimension_reading_is_biased_in_2d():
 
 
 @pytest.mark.parametrize("mode", [O.GAUSS, O.IS])
-@pytest.mark.parametrize("d", [6, 12])
+@pytest.mark.parametrize("d", [6, 12, 150, 256])
 def test_quadratic(mode, d):
     # L = |x - c|^2: Q = |theta - c|^2 + sum sigma^2, grad Q = 2 (theta - c)
     rng = np.random.default_rng(d)
@@ -147,7 +147,7 @@ def test_rayleigh_magnitude_matches_supplement_cdf():
     assert stats.kstest(O.draw_tau(O.IS_PERDIM, [sigma], 50000, 43)[0][:, 0], F).pvalue > 1e-3
 
 
-@pytest.mark.parametrize("d", [2, 3, 6, 12])
+@pytest.mark.parametrize("d", [2, 3, 6, 12, 150, 256])
 def test_radial_sampler_is_chi_d_plus_1(d):
     sigma = np.full(d, 0.5, np.float32)
     tau, c = O.draw_tau(O.IS, sigma, 20000, 100 + d)
@@ -167,6 +167,20 @@ def test_gauss_sampler_is_normal(d):
     for j in range(d):
         assert stats.kstest(tau[:, j] / 0.3, stats.norm.cdf).pvalue > 1e-3
     np.testing.assert_allclose(c, tau.astype(np.float64) / 0.3 / (2 * 0.3), rtol=1e-6)
+
+
+@pytest.mark.parametrize("d", [32, 33, 70])
+def test_per_axis_signs_past_32_axes(d):
+    # one sign word per 32 axes: every axis is balanced, and axes 32 apart do
+    # not share their signs; the radii are Rayleigh on every axis
+    P = 20000
+    tau, c = O.draw_tau(O.IS_PERDIM, np.full(d, 0.5, np.float32), P, 300 + d)
+    sg = tau > 0
+    assert np.all(np.abs(sg.mean(0) - 0.5) < 4 * 0.5 / math.sqrt(P))
+    for j in range(d - 32):
+        assert abs((sg[:, j] == sg[:, j + 32]).mean() - 0.5) < 4 * 0.5 / math.sqrt(P)
+    assert stats.kstest(np.abs(tau[:, d - 1]) / 0.5, stats.rayleigh.cdf).pvalue > 1e-3
+    np.testing.assert_array_equal(np.sign(c), np.sign(tau))
 
 
 def test_draw_is_a_function_of_seed_and_pair_only():

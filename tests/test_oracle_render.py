@@ -199,6 +199,44 @@ def test_bvh_closest_hit_equals_brute_force():
     assert (i1 >= 3).sum() > 1000          # many triangle hits (ids after sphere and quad)
 
 
+def test_many_spheres_closest_hit_analytic():
+    # 75 bound spheres, each moved by its two parameters: the closest hit of a
+    # ray is the nearest intersected sphere in binary64 (rays whose two nearest
+    # candidates are within 1e-4 of each other, or that graze a sphere, are
+    # left out)
+    pr = S.sort_problem(width=8, height=8, spp=1)
+    sc = pr["scene"]
+    X = pr["theta0"]
+    rng = np.random.default_rng(12)
+    n = 20000
+    o = np.tile(np.array(sc.eye, np.float32), (n, 1))
+    tgt = np.stack([rng.uniform(-1.6, 1.6, n), np.full(n, 0.1), rng.uniform(-1.6, 1.6, n)], 1)
+    d = tgt - o
+    d = (d / np.linalg.norm(d, axis=1, keepdims=True)).astype(np.float32)
+    t, ids = O.OracleScene(sc).trace(X, o, d)
+    cen = np.array([s[:3] for s in sc.spheres], np.float64)
+    for j, (kind, idx, comp) in enumerate(sc.bindings):
+        cen[idx, comp] = np.float32(np.float32(sc.spheres[idx][comp]) + X[j])
+    r = np.array([s[3] for s in sc.spheres], np.float64)
+    oc = o[:, None, :].astype(np.float64) - cen[None]
+    dd = d.astype(np.float64)
+    b = (oc * dd[:, None, :]).sum(-1)
+    disc = b * b - ((oc * oc).sum(-1) - r[None] ** 2)
+    th = np.where(disc > 0, -b - np.sqrt(np.maximum(disc, 0)), np.inf)
+    srt = np.sort(th, axis=1)
+    gap = np.where(np.isfinite(srt[:, 1]), srt[:, 1] - np.where(np.isfinite(srt[:, 0]), srt[:, 0], 0),
+                   np.inf)
+    clear = (np.abs(disc) > 1e-4).all(1) & (gap > 1e-4)
+    want = np.where(np.isfinite(srt[:, 0]), np.argmin(th, axis=1), -1)
+    sph_hit = want >= 0
+    assert (clear & sph_hit).sum() > 2000
+    assert np.array_equal(ids[clear & sph_hit], want[clear & sph_hit])
+    # (binary32 intersection: the error grows as a ray nears grazing)
+    np.testing.assert_allclose(t[clear & sph_hit], srt[clear & sph_hit, 0], rtol=2e-4)
+    assert (clear & ~sph_hit).sum() > 2000
+    assert np.all(ids[clear & ~sph_hit] >= len(sc.spheres))    # the floor, or a miss
+
+
 def _euler_scipy(a, b, c):
     # extrinsic rotations about x, then y, then z: Rz(c) Ry(b) Rx(a)
     from scipy.spatial.transform import Rotation
