@@ -98,3 +98,22 @@ def test_plateau_escape(plateau, est):
         tr = OP.optimize(sc, ref, theta0, 0.5, 300, 0.02, 4, est=est, seed=seed,
                          theta_ref=theta_ref)
         assert tr.param_mse[-1] < 0.01 * start, (est, seed, tr.param_mse[-1], start)
+
+
+def test_many_objects_optimisation():
+    # 75 spheres, 150 coordinates: the estimator-driven Adam loop recovers the
+    # positions (parameter MSE at least 5x below the start)
+    from paper_2211_17263_amd import native as NV
+    from paper_2211_17263_amd import optimize as OP
+    pr = S.sort_problem(seed=5)
+    say("sort-150d optimisation")
+    ctx = NV.Context(0)
+    sc = NV.prdpt_scene_create(ctx, pr["scene"])
+    try:
+        ref = NV.prdpt_render_reference(sc, pr["theta_ref"], 7)
+        tr = OP.optimize(sc, ref, pr["theta0"], 0.05, 600, 0.002, 16, est=NV.PRDPT_EST_IS, seed=3,
+                         theta_ref=pr["theta_ref"])
+        assert tr.param_mse[-1] < 0.2 * tr.param_mse[0], (tr.param_mse[0], tr.param_mse[-1])
+    finally:
+        sc.destroy()
+        ctx.close()
