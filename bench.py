@@ -505,10 +505,41 @@ def bench_batch(args, NV):
            "plain_per_request": {"value": len(jobs) / t_plain, "ms_per_batch_of_requests": 1e3 * t_plain},
            "speedup_vs_plain": t_plain / t_batch, "bitwise_equal_to_plain": bool(same),
            "scene_build_s": t_build}
+    # the roofline on the batch's largest scene (the least cacheable BVH)
+    i = max(range(len(jobs)), key=lambda t: jobs[t]["scene"].n_tris)
+    out["largest_scene_roofline"] = scene_roofline(NV, ctx, scs[i], refs[i], jobs[i], args.seed)
     for sc in scs:
         sc.destroy()
     ctx.close()
     print(json.dumps(out), flush=True)
+
+
+def scene_roofline(NV, ctx, sc, ref, job, seed, K=5):
+    """Single-request render-kernel roofline of one scene: algorithmic bytes of
+    an estimate (counting kernel) over the mean HIP-event render time of K
+    estimates (events on the library's stream)."""
+    import torch
+    scene, N, est = job["scene"], job["N"], job["est"]
+    for t in range(2):
+        NV.prdpt_grad_estimate(sc, ref, job["theta0"], job["sigma"], N, seed + t, est)
+    torch.cuda.synchronize()
+    NV.prdpt_ctx_read_timing(ctx)
+    NV.prdpt_ctx_set_timing(ctx, True)
+    for t in range(K):
+        NV.prdpt_grad_estimate(sc, ref, job["theta0"], job["sigma"], N, seed + t, est)
+    torch.cuda.synchronize()
+    kernel_ms, launches = NV.prdpt_ctx_read_timing(ctx)
+    NV.prdpt_ctx_set_timing(ctx, False)
+    c = NV.prdpt_traversal_counts(sc, job["theta0"], job["sigma"], N, seed, est)
+    H, W = scene.height, scene.width
+    alg = c["nodes"] * NODE_BYTES + c["tris"] * TRI_BYTES + N * H * W * REF_BYTES_PER_PIXEL
+    avg_s = kernel_ms / launches / 1e3
+    achieved = alg / avg_s / 1e9
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "kernel_avg_ms": 1e3 * avg_s,
+            "algorithmic_bytes_per_launch": alg,
+            "scene": {"width": W, "height": H, "spp": scene.spp, "max_bounces": scene.max_bounces,
+                      "triangles": scene.n_tris, "N": N, "d": scene.d}}
 
 
 def serve_phase(NV, ctx, jobs, refs, rate, seconds, max_batch, max_inflight, budget, seed):
@@ -653,10 +684,24 @@ def cpu_leg(sc, pr, sigma0, args, NV):
     S = (np.abs(c) * (first["losses"][0::2] + first["losses"][1::2])[:, None]).mean(axis=0)
     gerr = np.abs(g["grad"] - first["grad"]) / S
     paths = N * scene.width * scene.height * scene.spp
+    # about 4096 evenly spread pixels of one render on one thread: the
+    # single-thread rate beside the all-core one
+    npix = scene.width * scene.height
+    pix = np.arange(0, npix, max(1, npix // 4096), dtype=np.int32)
+    t1 = time.perf_counter()
+    osc.render_pixels(theta, pix, seed=args.seed, nthreads=1)
+    single = time.perf_counter() - t1
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
     base = {"value": reps / dt, "unit": "gradient estimates/s", "cores": cores, "kind": "oracle",
             "sample": f"{reps} whole estimate(s) ({reps * N} renders, {reps * paths} paths) "
                       f"in {dt:.1f} s",
-            "paths_per_s": reps * paths / dt}
+            "paths_per_s": reps * paths / dt, "cpu_model": model,
+            "single_thread_paths_per_s": pix.size * scene.spp / single}
     sig = np.abs(first["grad"]) >= 0.1 * S          # components well above the cancellation scale
     grel = np.abs(g["grad"] - first["grad"])[sig] / np.abs(first["grad"])[sig]
     parity = {"checked_renders": N, "max_rel_loss_err": float(rel.max()),
