@@ -28,6 +28,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 NODE_BYTES, TRI_BYTES, REF_BYTES_PER_PIXEL = 128, 48, 12
+FP32_PEAK_TFLOPS = 157.3
 KERNEL_SRC = os.path.join(ROOT, "paper_2211_17263_amd", "csrc", "kernels.hip")
 
 
@@ -67,6 +68,30 @@ def traffic_from_profile(workload):
         return None
     try:
         return float(kv["fetch_bytes_per_launch"]) + float(kv["write_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def valu_from_profile(workload, kernel_s):
+    """VALU issue utilisation and FP32 rate of the render kernel from the
+    committed issue counters (profiles/counters_render_loss_<workload>.txt),
+    valid only for the kernel source they were taken on."""
+    path = os.path.join(ROOT, "profiles", f"counters_render_loss_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    src_hash = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    if kv.get("kernel_source_sha256") != src_hash:
+        return None
+    try:
+        return {"valu_issue_utilisation": float(kv["valu_issue_utilisation"]),
+                "fp32_arith_share_of_valu": float(kv["fp32_arith_share_of_valu"]),
+                "fp32_tflops_upper_bound": float(kv["fp32_flop_upper_bound_per_dispatch"]) / kernel_s / 1e12,
+                "fp32_peak_tflops": FP32_PEAK_TFLOPS}
     except (KeyError, ValueError):
         return None
 
@@ -216,6 +241,7 @@ def main():
             "ray_loop": per["rays"] / max(64 * per["wave_ray_iters"], 1)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_profile(args.workload)},
+        "valu": valu_from_profile(args.workload, kernel_avg_s),
         "scene_build_s": t_build,
         "final_loss": last["loss"],
     }

@@ -3,6 +3,13 @@
 kernel-trace mode: per-kernel call count and mean/min/max duration from a
 ``--kernel-trace --stats -f csv`` run.
 
+counters mode: issue-level counters of one kernel (mean per dispatch over the
+last dispatches with the largest grid) from any number of ``--pmc`` runs, and
+the VALU issue utilisation they imply: wave-level VALU instructions x 4 cycles
+(a wave64 instruction occupies a 16-lane SIMD for 4 cycles) over the SIMD-cycles
+of the dispatch (GRBM_GUI_ACTIVE, summed over the 8 XCDs, over 8, times 1024
+SIMDs).
+
 traffic mode: HBM bytes per dispatch of one kernel from two ``--pmc`` runs
 (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by what the same
 counter reads for the library's streaming copy of a known size (copy probe), and
@@ -66,6 +73,36 @@ def traffic(a):
     print("\n".join(lines))
 
 
+def counters(a):
+    vals = {}
+    for path in a.runs:
+        names = sorted({r["Counter_Name"] for r in _rows(path)})
+        for n in names:
+            v = _values(path, n, a.kernel, last=a.last)
+            vals[n] = statistics.mean(v)
+    lines = [f"# Issue counters per dispatch of {a.kernel} ({a.workload})", "# commands:",
+             *[f"#   {c}" for c in a.command],
+             f"# mean over the last {a.last} largest-grid dispatches (the timed estimates)",
+             f"kernel: {a.kernel}",
+             f"kernel_source_sha256: {hashlib.sha256(open(a.source, 'rb').read()).hexdigest()}"]
+    lines += [f"{n}: {vals[n]:.6g}" for n in sorted(vals)]
+    if "GRBM_GUI_ACTIVE" in vals and "SQ_INSTS_VALU" in vals:
+        cycles = vals["GRBM_GUI_ACTIVE"] / a.xcds
+        cap = cycles * a.simds
+        lines += [f"dispatch_cycles: {cycles:.6g}",
+                  f"valu_issue_utilisation: {4.0 * vals['SQ_INSTS_VALU'] / cap:.4f}"]
+        if "SQ_ACTIVE_INST_VALU" in vals:
+            lines.append(f"valu_active_utilisation: {4.0 * vals['SQ_ACTIVE_INST_VALU'] / cap:.4f}")
+        f32 = [vals.get(k) for k in ("SQ_INSTS_VALU_FMA_F32", "SQ_INSTS_VALU_ADD_F32",
+                                     "SQ_INSTS_VALU_MUL_F32")]
+        if all(x is not None for x in f32):
+            flops = 64.0 * (2.0 * f32[0] + f32[1] + f32[2])   # at most: every lane active
+            lines.append(f"fp32_flop_upper_bound_per_dispatch: {flops:.6g}")
+            lines.append(f"fp32_arith_share_of_valu: {sum(f32) / vals['SQ_INSTS_VALU']:.4f}")
+    open(a.out, "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def kernel_trace(a):
     path = a.trace
     stats = [n for n in os.listdir(path) if n.endswith("kernel_stats.csv")]
@@ -114,6 +151,16 @@ def main():
     t.add_argument("--last", type=int, default=0,
                    help="only the last N largest-grid dispatches (the timed ones)")
     t.add_argument("--out", required=True)
+    c = sub.add_parser("counters")
+    c.add_argument("--runs", nargs="+", required=True)
+    c.add_argument("--kernel", default="render_loss_kernel<false, false>")
+    c.add_argument("--workload", default="")
+    c.add_argument("--command", action="append", default=[])
+    c.add_argument("--last", type=int, default=2)
+    c.add_argument("--xcds", type=int, default=8)
+    c.add_argument("--simds", type=int, default=1024)
+    c.add_argument("--source", default=os.path.join(os.path.dirname(__file__), "csrc", "kernels.hip"))
+    c.add_argument("--out", required=True)
     k = sub.add_parser("trace")
     k.add_argument("--trace", required=True)
     k.add_argument("--workload", default="")
@@ -126,7 +173,7 @@ def main():
                    help="only the last N of those dispatches (the timed ones)")
     k.add_argument("--out", required=True)
     a = ap.parse_args()
-    traffic(a) if a.mode == "traffic" else kernel_trace(a)
+    {"traffic": traffic, "counters": counters, "trace": kernel_trace}[a.mode](a)
 
 
 if __name__ == "__main__":
