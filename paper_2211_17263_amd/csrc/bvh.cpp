@@ -12,6 +12,7 @@
 #include <cfloat>
 #include <cmath>
 #include <cstring>
+#include <limits>
 #include <vector>
 
 #include "prdpt_internal.h"
@@ -302,14 +303,17 @@ int32_t collapse(const std::vector<Node2>& n2, int i, std::vector<Node>& out) {
     }
   }
   Node& nd = out[me];
+  // an empty slot gets the inverted box lo = +inf, hi = -inf: every slab
+  // test misses it, whatever the ray
+  const float inf = std::numeric_limits<float>::infinity();
   for (int c = 0; c < 4; ++c) {
     const bool use = c < nc;
-    nd.lox[c] = use ? ch[c].lo[0] : 0.0f;
-    nd.loy[c] = use ? ch[c].lo[1] : 0.0f;
-    nd.loz[c] = use ? ch[c].lo[2] : 0.0f;
-    nd.hix[c] = use ? ch[c].hi[0] : 0.0f;
-    nd.hiy[c] = use ? ch[c].hi[1] : 0.0f;
-    nd.hiz[c] = use ? ch[c].hi[2] : 0.0f;
+    nd.lox[c] = use ? ch[c].lo[0] : inf;
+    nd.loy[c] = use ? ch[c].lo[1] : inf;
+    nd.loz[c] = use ? ch[c].lo[2] : inf;
+    nd.hix[c] = use ? ch[c].hi[0] : -inf;
+    nd.hiy[c] = use ? ch[c].hi[1] : -inf;
+    nd.hiz[c] = use ? ch[c].hi[2] : -inf;
     nd.ref[c] = ref[c];
     nd.pad[c] = 0;
   }

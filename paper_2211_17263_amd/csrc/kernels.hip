@@ -208,16 +208,27 @@ __device__ __forceinline__ bool first_active_lane() {
   return (int)__lane_id() == __ffsll((long long)m) - 1;
 }
 
-// Conservative binary32 slab test of a padded child box; returns the entry
-// distance (or +inf when the box is missed or lies beyond tcull).
-__device__ __forceinline__ float slab(float lox, float hix, float loy, float hiy, float loz,
-                                      float hiz, V3 inv, V3 oi, float tcull) {
-  const float tx0 = fmaf(lox, inv.x, oi.x), tx1 = fmaf(hix, inv.x, oi.x);
-  const float ty0 = fmaf(loy, inv.y, oi.y), ty1 = fmaf(hiy, inv.y, oi.y);
-  const float tz0 = fmaf(loz, inv.z, oi.z), tz1 = fmaf(hiz, inv.z, oi.z);
-  const float tmin = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fmaxf(fminf(tz0, tz1), 0.0f));
-  const float tmax = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fminf(fmaxf(tz0, tz1), tcull));
+// Conservative binary32 slab test of a padded child box, given per axis the
+// plane the ray meets first (near) and last (far); returns the entry distance
+// (or +inf when the box is missed or lies beyond tcull).  With the planes
+// picked by the sign of the inverse direction, fma(near, inv, oi) is the
+// smaller of the two plane distances of the axis (the rounded fma is monotone
+// in the plane coordinate), so this equals the min/max form of the test.  An
+// empty child slot has lo = +inf and hi = -inf on every axis and is missed.
+__device__ __forceinline__ float slab(float nx, float fx, float ny, float fy, float nz, float fz,
+                                      V3 inv, V3 oi, float tcull) {
+  const float tmin = fmaxf(fmaxf(fmaf(nx, inv.x, oi.x), fmaf(ny, inv.y, oi.y)),
+                           fmaxf(fmaf(nz, inv.z, oi.z), 0.0f));
+  const float tmax = fminf(fminf(fmaf(fx, inv.x, oi.x), fmaf(fy, inv.y, oi.y)),
+                           fminf(fmaf(fz, inv.z, oi.z), tcull));
   return tmin <= tmax ? tmin : __builtin_huge_valf();
+}
+
+// Byte offset within a node of the four near planes of each axis: lo (x at
+// 0, y at 32, z at 64) where the inverse direction is positive, hi (16 bytes
+// further) where it is negative; the far planes are at offset ^ 16.
+__device__ __forceinline__ uint32_t near_planes(float inv_axis, uint32_t lo_offset) {
+  return lo_offset | ((__float_as_uint(inv_axis) >> 27) & 16u);
 }
 
 __device__ __forceinline__ float safe_inv(float x) {
@@ -424,24 +435,28 @@ __device__ bool continue_trace(const SceneLds& S, const Node* __restrict__ nodes
 #endif
       ++iters;
       if (node >= 0) {
-        const float4* np = reinterpret_cast<const float4*>(nodes + node);
-        const float4 lx = np[0], hx = np[1], ly = np[2], hy = np[3], lz = np[4], hz = np[5];
-        const int4 rf = reinterpret_cast<const int4*>(np)[6];
+        const char* nb = reinterpret_cast<const char*>(nodes);
+        const uint32_t at = (uint32_t)node << 7;  // 128-byte nodes
+        const uint32_t ax = near_planes(inv.x, at), ay = near_planes(inv.y, at | 32u),
+                       az = near_planes(inv.z, at | 64u);
+        const float4 nx = *reinterpret_cast<const float4*>(nb + ax);
+        const float4 fx = *reinterpret_cast<const float4*>(nb + (ax ^ 16u));
+        const float4 ny = *reinterpret_cast<const float4*>(nb + ay);
+        const float4 fy = *reinterpret_cast<const float4*>(nb + (ay ^ 16u));
+        const float4 nz = *reinterpret_cast<const float4*>(nb + az);
+        const float4 fz = *reinterpret_cast<const float4*>(nb + (az ^ 16u));
+        const int4 rf = *reinterpret_cast<const int4*>(nb + (at | 96u));
         if (COUNT) {
           cnt.nodes++;
           if (first_active_lane()) cnt.wave_node_iters++;
         }
         const float tcull = any ? tmax : fminf(tmax, h.t);
         const float inf = __builtin_huge_valf();
-        float t0 = slab(lx.x, hx.x, ly.x, hy.x, lz.x, hz.x, inv, oi, tcull);
-        float t1 = slab(lx.y, hx.y, ly.y, hy.y, lz.y, hz.y, inv, oi, tcull);
-        float t2 = slab(lx.z, hx.z, ly.z, hy.z, lz.z, hz.z, inv, oi, tcull);
-        float t3 = slab(lx.w, hx.w, ly.w, hy.w, lz.w, hz.w, inv, oi, tcull);
-        int r0 = rf.x, r1 = rf.y, r2 = rf.z, r3 = rf.w;
-        t0 = r0 != kEmptyChild ? t0 : inf;
-        t1 = r1 != kEmptyChild ? t1 : inf;
-        t2 = r2 != kEmptyChild ? t2 : inf;
-        t3 = r3 != kEmptyChild ? t3 : inf;
+        float t0 = slab(nx.x, fx.x, ny.x, fy.x, nz.x, fz.x, inv, oi, tcull);
+        float t1 = slab(nx.y, fx.y, ny.y, fy.y, nz.y, fz.y, inv, oi, tcull);
+        float t2 = slab(nx.z, fx.z, ny.z, fy.z, nz.z, fz.z, inv, oi, tcull);
+        float t3 = slab(nx.w, fx.w, ny.w, fy.w, nz.w, fz.w, inv, oi, tcull);
+        int r0 = rf.x, r1 = rf.y, r2 = rf.z, r3 = rf.w;  // empty slots: t = inf
         // nearest first (misses last)
         order2(t0, r0, t1, r1);
         order2(t2, r2, t3, r3);

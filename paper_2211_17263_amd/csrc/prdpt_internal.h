@@ -27,9 +27,11 @@ constexpr int32_t kEmptyChild = INT32_MIN;
 // Flattened 4-wide BVH node (128 bytes, seven 16-byte loads): the padded boxes
 // of its children as six 4-vectors (one per box face coordinate) and the child
 // references.  A reference >= 0 is an inner node, < 0 a leaf of triangles
-// encoded as ~(first << 3 | (count - 1)), kEmptyChild an unused slot.  Boxes
-// are padded outward so the binary32 slab test is conservative for every
-// binary32 triangle hit inside them.
+// encoded as ~(first << 3 | (count - 1)), kEmptyChild an unused slot (whose box
+// is inverted, lo = +inf and hi = -inf, so that no ray hits it).  Boxes are
+// padded outward so the binary32 slab test is conservative for every binary32
+// triangle hit inside them.  Each axis keeps lo and hi 16 bytes apart, which
+// lets the traversal load a ray's near and far planes directly.
 struct alignas(16) Node {
   float lox[4], hix[4], loy[4], hiy[4], loz[4], hiz[4];
   int32_t ref[4];
