@@ -290,6 +290,7 @@ int prdpt::build_host_scene(const prdpt_scene_desc* D, HostScene& hs) {
   h.n_area = 0;
   for (int i = 0; i < h.n_quad; ++i) {
     for (int c = 0; c < 9; ++c) h.quad[i][c] = D->quads[9 * i + c];
+    quad_frame_host(h.quad[i], h.quad_n[i], h.quad_nu[i]);
     h.quad_mat[i] = D->quad_mat[i];
     if (h.mat_type[h.quad_mat[i]] == PRDPT_MAT_EMISSIVE) h.area_quad[h.n_area++] = i;
   }

@@ -22,6 +22,9 @@ hipError_t launch_render(hipStream_t st, const DevScene& sc, int W, int H, const
                          const int* order, float* cost, int crn, int rot, int n_sph);
 // Rz(c) Ry(b) Rx(a) of the angles (a, b, c), row-major (the kernels' own formula)
 void euler_rotation_host(const float* ang, float* R);
+// normal and squared length, unit normal and area of a quad [origin, edge1,
+// edge2] (the kernels' operation order)
+void quad_frame_host(const float* q, float* n, float* nu);
 // tiles by descending measured render time (no-op for more than 4096 tiles)
 hipError_t launch_tile_order(hipStream_t st, const float* cost, int* order, int n_tiles);
 hipError_t launch_losses(hipStream_t st, const float* partial, int n_tiles, int N, int npix,

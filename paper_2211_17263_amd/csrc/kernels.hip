@@ -141,15 +141,17 @@ __device__ __forceinline__ bool hit_sphere(V3 o, V3 d, const float* sp, float tm
   return true;
 }
 
-__device__ __forceinline__ bool hit_quad(V3 o, V3 d, const float* qd, float tmax, float* tout) {
+// qn: the quad's edge1 x edge2 and its squared length (per-scene constants)
+__device__ __forceinline__ bool hit_quad(V3 o, V3 d, const float* qd, const float* qn, float tmax,
+                                         float* tout) {
   const V3 qo = ld3(qd), e1 = ld3(qd + 3), e2 = ld3(qd + 6);
-  const V3 n = cross(e1, e2);
+  const V3 n = ld3(qn);
   const float den = dot(n, d);
   if (den == 0.0f) return false;
   const float t = dot(n, sub(qo, o)) / den;
   if (!(t > 0.0f && t < tmax)) return false;
   const V3 pd = sub(at(o, d, t), qo);
-  const float nn = dot(n, n);
+  const float nn = qn[3];
   const float al = dot(cross(pd, e2), n) / nn;
   if (al < 0.0f || al > 1.0f) return false;
   const float be = dot(cross(e1, pd), n) / nn;
@@ -385,7 +387,7 @@ __device__ __forceinline__ bool begin_trace(const SceneLds& S, const float* __re
   for (int i = 0; i < S.n_quad; ++i) {
     if (any && S.mat_type[S.quad_mat[i]] == PRDPT_MAT_EMISSIVE) continue;
     float t;
-    if (hit_quad(o, d, S.quad[i], tmax, &t)) {
+    if (hit_quad(o, d, S.quad[i], S.quad_n[i], tmax, &t)) {
       if (any) {
         h.id = S.n_sph + i;
         return true;
@@ -702,7 +704,7 @@ __device__ __forceinline__ void render_tile(const SceneLds& S, const float* __re
           } else if (h.id < S.tri_id_base) {
             const int qi = h.id - S.n_sph;
             mat = S.quad_mat[qi];
-            ng = unit(cross(ld3(S.quad[qi] + 3), ld3(S.quad[qi] + 6)));
+            ng = ld3(S.quad_nu[qi]);
           } else {
             const float4* tp = reinterpret_cast<const float4*>(tris + h.slot);
             const float4 p0 = tp[0], p1 = tp[1], p2 = tp[2];
@@ -802,9 +804,8 @@ __device__ __forceinline__ void render_tile(const SceneLds& S, const float* __re
             const V3 qo = ld3(qd), e1 = ld3(qd + 3), e2 = ld3(qd + 6);
             const V3 yl = mk(qo.x + e1.x * ua + e2.x * ub, qo.y + e1.y * ua + e2.y * ub,
                              qo.z + e1.z * ua + e2.z * ub);
-            const V3 nl = cross(e1, e2);
-            const float area = sqrtf(dot(nl, nl));
-            const V3 nlu = scale(nl, 1.0f / area);
+            const V3 nlu = ld3(S.quad_nu[qi]);
+            const float area = S.quad_nu[qi][3];
             const V3 toL = sub(yl, p);
             const float dist2 = dot(toL, toL);
             const float dist = sqrtf(dist2);
@@ -1335,6 +1336,26 @@ int render_grid_limit(int rot, int n_sph) {
 }
 
 void euler_rotation_host(const float* ang, float* R) { euler_rotation(ang, R); }
+
+// Normal n = edge1 x edge2 of a quad with its squared length, and the unit
+// normal with the area, in the operation order of the intersection and the
+// shading: cross product, squared length, its sqrt, one reciprocal, three
+// products.
+void quad_frame_host(const float* q, float* n, float* nu) {
+  const float ax = q[3], ay = q[4], az = q[5], bx = q[6], by = q[7], bz = q[8];
+  const float nx = ay * bz - az * by, ny = az * bx - ax * bz, nz = ax * by - ay * bx;
+  const float nn = nx * nx + ny * ny + nz * nz;
+  const float area = sqrtf(nn);
+  const float inv = 1.0f / area;
+  n[0] = nx;
+  n[1] = ny;
+  n[2] = nz;
+  n[3] = nn;
+  nu[0] = nx * inv;
+  nu[1] = ny * inv;
+  nu[2] = nz * inv;
+  nu[3] = area;
+}
 
 hipError_t launch_render(hipStream_t st, const DevScene& sc, int W, int H, const float* X, int nk,
                          int d, int tag, uint64_t seed, const float* ref, float* img,

@@ -62,6 +62,8 @@ struct SceneLds {
   float quad[PRDPT_MAX_QUADS][9];
   int32_t quad_mat[PRDPT_MAX_QUADS];
   int32_t area_quad[PRDPT_MAX_QUADS];        // emissive quads in index order
+  float quad_n[PRDPT_MAX_QUADS][4];          // edge1 x edge2 and its squared length
+  float quad_nu[PRDPT_MAX_QUADS][4];         // unit normal and area (edges are never bound)
   int32_t inst_root[PRDPT_MAX_INSTANCES];    // root node of each instance BVH (-1: empty)
   float inst_xlate[PRDPT_MAX_INSTANCES][3];
   float inst_ang[PRDPT_MAX_INSTANCES][3];    // rotation angles (a, b, c)
