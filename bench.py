@@ -195,7 +195,7 @@ def main():
     # algorithmic work of the timed launches, replayed with the counting kernel
     # (at most 8 evenly spaced timed steps; the per-estimate mean stands for all)
     cnt = {"nodes": 0, "tris": 0, "rays": 0, "paths": 0, "wave_node_iters": 0,
-           "wave_tri_iters": 0, "wave_ray_iters": 0}
+           "wave_tri_iters": 0, "wave_ray_iters": 0, "idle_lane_iters": 0}
     counted = sorted(set(np.linspace(0, len(trajectory) - 1, min(8, len(trajectory))).round().astype(int)))
     for i in counted:
         th32, s, seed = trajectory[i]
@@ -238,7 +238,8 @@ def main():
         "simd_efficiency": {
             "node_loop": per["nodes"] / max(64 * per["wave_node_iters"], 1),
             "triangle_loop": per["tris"] / max(64 * per["wave_tri_iters"], 1),
-            "ray_loop": per["rays"] / max(64 * per["wave_ray_iters"], 1)},
+            "ray_loop": per["rays"] / max(64 * per["wave_ray_iters"], 1),
+            "ray_loop_lanes_idle_done": per["idle_lane_iters"] / max(64 * per["wave_ray_iters"], 1)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_profile(args.workload)},
         "valu": valu_from_profile(args.workload, kernel_avg_s),

@@ -367,7 +367,9 @@ int prdpt_ctx_read_timing(prdpt_ctx* ctx, double* total_ms, int64_t* launches);
  * counts[2] ray queries (closest-hit and shadow), counts[3] camera paths,
  * counts[4..6] iterations of the node loop, the triangle loop and the ray loop
  * executed per wavefront (summed over wavefronts; lane work / (64 x iterations)
- * is each loop's SIMD efficiency).  counts: host uint64_t[7].  Synchronous.
+ * is each loop's SIMD efficiency), counts[7] lanes idle in ray-loop iterations
+ * because their pixel's samples are done or the tile has no pixel for them
+ * (summed over iterations).  counts: host uint64_t[8].  Synchronous.
  */
 int prdpt_traversal_counts(prdpt_scene* scene, const float* theta, const float* sigma, int N,
                            uint64_t seed, int est, uint64_t* counts);

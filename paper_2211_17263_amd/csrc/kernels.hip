@@ -202,7 +202,8 @@ __device__ __forceinline__ void keep_closer(Hit& h, float t, int id, int slot) {
 // by its first active lane), whose ratio is the SIMD efficiency of each loop.
 struct Counters {
   uint32_t nodes, tris, rays, paths;
-  uint32_t wave_node_iters, wave_tri_iters, wave_outer_iters, pad;
+  uint32_t wave_node_iters, wave_tri_iters, wave_outer_iters;
+  uint32_t idle_lane_iters;  // ray-loop iterations x lanes whose pixel is done (or absent)
 };
 
 __device__ __forceinline__ bool first_active_lane() {
@@ -637,7 +638,7 @@ __device__ __forceinline__ void load_state(SceneLds& S, float* __restrict__ sph,
 // path of the wave, and every iteration runs the same traversal code.  Per
 // sample the radiance terms are added in the same order as a recursive
 // implementation (vertex by vertex; point lights, then area lights).
-template <bool COUNT, bool ROT>
+template <bool COUNT, bool ROT, bool CHUNKED>
 __device__ __forceinline__ void render_tile(const SceneLds& S, const float* __restrict__ sph,
                                             const int* __restrict__ sph_mat,
                                             const Node* __restrict__ nodes,
@@ -646,13 +647,18 @@ __device__ __forceinline__ void render_tile(const SceneLds& S, const float* __re
                                             float* __restrict__ img, float* partial_slot,
                                             unsigned long long* __restrict__ counters,
                                             int* __restrict__ stack, float* __restrict__ wsum,
-                                            int crn) {
+                                            int crn, float* __restrict__ pbuf,
+                                            volatile int* __restrict__ next_job) {
   const int tiles_x = (S.W + kTileW - 1) / kTileW;
   const int t = threadIdx.x;
-  const int lx = (t & 7) + 8 * (t >> 6), ly = (t >> 3) & 7;
-  const int x = (tile % tiles_x) * kTileW + lx, y = (tile / tiles_x) * kTileH + ly;
+  const int tx0 = (tile % tiles_x) * kTileW, ty0 = (tile / tiles_x) * kTileH;
+  const int lx = t & 7, ly = t >> 3;  // lane t owns pixel (lx, ly) of the tile
+  const int x = tx0 + lx, y = ty0 + ly;
   const bool valid = x < S.W && y < S.H;
   const int pix = y * S.W + x;
+  // the tile's valid pixels (tw x th) and its jobs: pixel q, sample c + j / nv
+  const int tw = min(kTileW, S.W - tx0), th = min(kTileH, S.H - ty0);
+  const int nv = tw * th;
   // path streams: the two renders of an antithetic pair share stream k / 2
   // (common random numbers); independent renders (crn = 0) use stream k
   const int pair = crn ? k >> 1 : k;
@@ -672,12 +678,26 @@ __device__ __forceinline__ void render_tile(const SceneLds& S, const float* __re
   int v = 0, mat = 0, light = -1;          // light >= 0: next-event stage of a diffuse vertex
   uint4 w = make_uint4(0u, 0u, 0u, 0u);
 
-  int s = valid ? 0 : spp;
-  bool start = s < spp;
+  // the path in flight, as its slot in the chunk's buffer: sample
+  // c_first + (jslot >> 6) of the tile pixel (jslot & 7, (jslot >> 3) & 7);
+  // -1 when the lane has none
+  int jslot = -1;
   bool tracing = false;   // a query is in flight (possibly suspended)
   bool answered = false;  // the last query's result (tr.h) is still to be used
   Trav tr;
-  while (s < spp) {
+  // chunks of samples [c_first, c_first + n_chunk) of the tile's pixels (one
+  // chunk of all spp samples unless CHUNKED)
+  const int n_chunks = CHUNKED ? (spp + kSampleChunk - 1) / kSampleChunk : 1;
+  for (int ci = 0; ci < n_chunks; ++ci) {
+  const int c_first = CHUNKED ? ci * kSampleChunk : 0;
+  const int n_chunk = CHUNKED ? min(spp - c_first, kSampleChunk) : spp;
+  // image pixel index and sample of the path in flight
+  auto path_pix = [&]() { return (ty0 + ((jslot >> 3) & 7)) * S.W + tx0 + (jslot & 7); };
+  auto path_smp = [&]() { return c_first + (jslot >> 6); };
+  const int n_jobs = nv * n_chunk;
+  if (t == 0) *next_job = 0;
+  __syncthreads();
+  while (true) {
     if (!tracing) {
       if (answered) {
         answered = false;
@@ -726,7 +746,7 @@ __device__ __forceinline__ void render_tile(const SceneLds& S, const float* __re
             }
             end_path = true;
           } else {
-            w = path_words(k0, k1, pix, s, pair, tag, v + 1, 0);
+            w = path_words(k0, k1, path_pix(), path_smp(), pair, tag, v + 1, 0);
             if (mt == PRDPT_MAT_DIFFUSE) {
               n = dot(ng, dir) > 0.0f ? neg(ng) : ng;
               light = 0;
@@ -796,7 +816,7 @@ __device__ __forceinline__ void render_tile(const SceneLds& S, const float* __re
               ua = unit_open(w.x);
               ub = unit_open(w.y);
             } else {
-              const uint4 w2 = path_words(k0, k1, pix, s, pair, tag, v + 1, ai);
+              const uint4 w2 = path_words(k0, k1, path_pix(), path_smp(), pair, tag, v + 1, ai);
               ua = unit_open(w2.x);
               ub = unit_open(w2.y);
             }
@@ -849,24 +869,35 @@ __device__ __forceinline__ void render_tile(const SceneLds& S, const float* __re
           }
         }
         if (end_path) {
-          acc0 = acc0 + L0;
-          acc1 = acc1 + L1;
-          acc2 = acc2 + L2;
-          ++s;
-          start = s < spp;
+          float* slot = pbuf + (size_t)jslot * 3;
+          slot[0] = L0;
+          slot[1] = L1;
+          slot[2] = L2;
+          jslot = -1;
         }
-        if (s >= spp) break;
       }
-      if (start) {  // camera ray of sample s
-        start = false;
+      if (jslot < 0) {  // the lanes without a path take the chunk's next jobs in order
+        const unsigned long long m = __ballot(1);
+        const int rank = (int)__builtin_amdgcn_mbcnt_hi(
+            (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+        const int base = *next_job;
+        const int j = base + rank;
+        if (rank == 0) *next_job = base + __popcll(m);
+        if (j >= n_jobs) break;  // this lane is done with the chunk
+        const int q = nv == kBlock ? (j & (kBlock - 1)) : j % nv;
+        const int sj = nv == kBlock ? (j >> 6) : j / nv;
+        const int qx = tw == kTileW ? (q & (kTileW - 1)) : q % tw;
+        const int qy = tw == kTileW ? (q >> 3) : q / tw;
+        jslot = sj * kBlock + qx + kTileW * qy;
+        // camera ray of the path
         if (COUNT) cnt.paths++;
-        float jx = 0.5f, jy = 0.5f;
+        float jxo = 0.5f, jyo = 0.5f;
         if (!S.pixel_center) {
-          const uint4 wj = path_words(k0, k1, pix, s, pair, tag, 0, 0);
-          jx = unit_open(wj.x);
-          jy = unit_open(wj.y);
+          const uint4 wj = path_words(k0, k1, path_pix(), path_smp(), pair, tag, 0, 0);
+          jxo = unit_open(wj.x);
+          jyo = unit_open(wj.y);
         }
-        const float px = (float)x + jx, py = (float)y + jy;
+        const float px = (float)(tx0 + qx) + jxo, py = (float)(ty0 + qy) + jyo;
         const float sx = 2.0f * (px / (float)S.W) - 1.0f;
         const float sy = 1.0f - 2.0f * (py / (float)S.H);
         o = ld3(S.eye);
@@ -887,10 +918,29 @@ __device__ __forceinline__ void render_tile(const SceneLds& S, const float* __re
         continue;
       }
     }
-    if (COUNT && first_active_lane()) cnt.wave_outer_iters++;
+    if (COUNT) {
+      const int active = __popcll(__ballot(1));
+      if (first_active_lane()) {
+        cnt.wave_outer_iters++;
+        cnt.idle_lane_iters += 64 - active;
+      }
+    }
     tracing = !continue_trace<COUNT, ROT>(S, nodes, tris, o, dir, tmax, shadow, tr, stk, kBlock,
                                           ovf, PRDPT_TRACE_BUDGET, cnt);
     answered = !tracing;
+  }
+  // every path of the chunk is done: each lane adds its pixel's samples in
+  // sample order
+  __syncthreads();
+  if (valid) {
+    for (int sj = 0; sj < n_chunk; ++sj) {
+      const float* slot = pbuf + (size_t)(sj * kBlock + t) * 3;
+      acc0 = acc0 + slot[0];
+      acc1 = acc1 + slot[1];
+      acc2 = acc2 + slot[2];
+    }
+  }
+  __syncthreads();
   }
 
   float e = 0.0f;
@@ -918,6 +968,7 @@ __device__ __forceinline__ void render_tile(const SceneLds& S, const float* __re
     atomicAdd(&counters[4], (unsigned long long)cnt.wave_node_iters);
     atomicAdd(&counters[5], (unsigned long long)cnt.wave_tri_iters);
     atomicAdd(&counters[6], (unsigned long long)cnt.wave_outer_iters);
+    atomicAdd(&counters[7], (unsigned long long)cnt.idle_lane_iters);
   }
   if (partial_slot) {
     // fixed-order butterfly within the wave, then the waves in order
@@ -945,16 +996,18 @@ __device__ __forceinline__ void render_tile(const SceneLds& S, const float* __re
 // tiles by cost for the next launch puts the cheapest tiles last and shortens
 // the tail where few work-groups are still busy.  Outputs do not depend on
 // the order.
-template <bool COUNT, bool ROT>
+template <bool COUNT, bool ROT, bool CHUNKED>
 __global__ __launch_bounds__(kBlock, PRDPT_MIN_WAVES_PER_EU) void render_loss_kernel(
     DevScene scene, const float* __restrict__ X, int d, int tag, uint32_t k0, uint32_t k1,
     const float* __restrict__ ref, float* __restrict__ img, float* __restrict__ partial,
     unsigned long long* __restrict__ counters, int n_tiles, int n_items, int* __restrict__ work,
-    const int* __restrict__ order, float* __restrict__ cost, int crn) {
+    const int* __restrict__ order, float* __restrict__ cost, int crn, float* __restrict__ pbuf) {
   __shared__ SceneLds S;
   __shared__ int stack[kStackEntries * kBlock];
   __shared__ float wsum[kBlock / 64];
   __shared__ int s_item;
+  __shared__ int s_job;
+  float* const my_paths = pbuf + (size_t)blockIdx.x * kPathBufFloats;
   extern __shared__ float sph[];  // sphere_lds_bytes(n_sph) at launch
   int* sph_mat = reinterpret_cast<int*>(sph + 4 * scene.hdr->n_sph);
   int cur = -1;
@@ -973,9 +1026,9 @@ __global__ __launch_bounds__(kBlock, PRDPT_MIN_WAVES_PER_EU) void render_loss_ke
     }
     unsigned long long t0 = 0;
     if (cost && threadIdx.x == 0) t0 = wall_clock64();
-    render_tile<COUNT, ROT>(S, sph, sph_mat, scene.nodes, scene.tris, k, tile, tag, k0, k1, ref, img,
+    render_tile<COUNT, ROT, CHUNKED>(S, sph, sph_mat, scene.nodes, scene.tris, k, tile, tag, k0, k1, ref, img,
                        partial ? partial + (size_t)k * n_tiles + tile : nullptr, counters, stack,
-                       wsum, crn);
+                       wsum, crn, my_paths, &s_job);
     if (cost && threadIdx.x == 0) cost[tile] = (float)(wall_clock64() - t0);
     __syncthreads();
   }
@@ -1230,14 +1283,16 @@ __global__ void batch_tau_kernel(const BatchReq* __restrict__ reqs, const BatchM
 // Persistent render: work-groups take (request, perturbation, run of tiles)
 // items from one counter until the batch is exhausted; each tile writes its own
 // partial slot, so the order in which items are taken does not matter.
-template <bool ROT>
+template <bool ROT, bool CHUNKED>
 __global__ __launch_bounds__(kBlock, PRDPT_MIN_WAVES_PER_EU) void batch_render_kernel(
     const BatchReq* __restrict__ reqs, BatchMeta* __restrict__ meta, const float* __restrict__ X,
-    float* __restrict__ partial) {
+    float* __restrict__ partial, float* __restrict__ pbuf) {
   __shared__ SceneLds S;
   __shared__ int stack[kStackEntries * kBlock];
   __shared__ float wsum[kBlock / 64];
   __shared__ int s_item;
+  __shared__ int s_job;
+  float* const my_paths = pbuf + (size_t)blockIdx.x * kPathBufFloats;
   extern __shared__ float sph[];  // sphere_lds_bytes(largest n_sph of the batch) at launch
   const int total = meta->total_items, n = meta->n_req, tpi = meta->tiles_per_item;
   while (true) {
@@ -1256,9 +1311,9 @@ __global__ __launch_bounds__(kBlock, PRDPT_MIN_WAVES_PER_EU) void batch_render_k
     load_state(S, sph, sph_mat, q.scene.hdr, X + (size_t)(q.row_base + k) * PRDPT_BATCH_MAX_PARAMS,
                q.d);
     for (int tile = first; tile < last; ++tile) {
-      render_tile<false, ROT>(S, sph, sph_mat, q.scene.nodes, q.scene.tris, k, tile, kTagPath, q.k0, q.k1, q.ref,
+      render_tile<false, ROT, CHUNKED>(S, sph, sph_mat, q.scene.nodes, q.scene.tris, k, tile, kTagPath, q.k0, q.k1, q.ref,
                          nullptr, partial + (size_t)q.partial_base + (size_t)k * q.n_tiles + tile,
-                         nullptr, stack, wsum, 1);
+                         nullptr, stack, wsum, 1, my_paths, &s_job);
       __syncthreads();
     }
   }
@@ -1327,9 +1382,9 @@ int render_grid_limit(int rot, int n_sph) {
   if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
   const size_t lds = (size_t)sphere_lds_bytes(n_sph);
   const hipError_t e = rot ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                                 &per_cu, render_loss_kernel<false, true>, kBlock, lds)
+                                 &per_cu, render_loss_kernel<false, true, false>, kBlock, lds)
                            : hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                                 &per_cu, render_loss_kernel<false, false>, kBlock, lds);
+                                 &per_cu, render_loss_kernel<false, false, false>, kBlock, lds);
   if (e != hipSuccess) return 0;
   slot = std::max(1, n_cu * std::max(1, per_cu));
   return slot;
@@ -1360,24 +1415,37 @@ void quad_frame_host(const float* q, float* n, float* nu) {
 hipError_t launch_render(hipStream_t st, const DevScene& sc, int W, int H, const float* X, int nk,
                          int d, int tag, uint64_t seed, const float* ref, float* img,
                          float* partial, unsigned long long* counters, int* work,
-                         const int* order, float* cost, int crn, int rot, int n_sph) {
+                         const int* order, float* cost, int crn, int rot, int n_sph,
+                         int spp, float* pbuf, int pbuf_blocks) {
   const int n_tiles = render_tiles(W, H);
   const int n_items = n_tiles * nk;
   const int limit = render_grid_limit(rot, n_sph);
-  if (limit <= 0) return hipErrorInvalidDevice;
+  if (limit <= 0 || pbuf_blocks <= 0) return hipErrorInvalidDevice;
   const size_t lds = (size_t)sphere_lds_bytes(n_sph);
-  const int blocks = std::min(n_items, limit);
+  const int blocks = std::min(std::min(n_items, limit), pbuf_blocks);
   hipLaunchKernelGGL(reset_work_kernel, dim3(1), dim3(64), 0, st, work);
   const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
-#define PRDPT_RENDER(C, R)                                                                      \
-  hipLaunchKernelGGL((render_loss_kernel<C, R>), dim3(blocks), dim3(kBlock), lds, st, sc, X, d, tag, \
-                     k0, k1, ref, img, partial, counters, n_tiles, n_items, work, order, cost, crn)
+#define PRDPT_RENDER(C, R, K)                                                                    \
+  hipLaunchKernelGGL((render_loss_kernel<C, R, K>), dim3(blocks), dim3(kBlock), lds, st, sc, X, d,  \
+                     tag, k0, k1, ref, img, partial, counters, n_tiles, n_items, work, order, cost,  \
+                     crn, pbuf)
+  const bool chunked = spp > kSampleChunk;
   if (counters) {
-    if (rot) PRDPT_RENDER(true, true);
-    else PRDPT_RENDER(true, false);
+    if (rot) {
+      if (chunked) PRDPT_RENDER(true, true, true);
+      else PRDPT_RENDER(true, true, false);
+    } else {
+      if (chunked) PRDPT_RENDER(true, false, true);
+      else PRDPT_RENDER(true, false, false);
+    }
   } else {
-    if (rot) PRDPT_RENDER(false, true);
-    else PRDPT_RENDER(false, false);
+    if (rot) {
+      if (chunked) PRDPT_RENDER(false, true, true);
+      else PRDPT_RENDER(false, true, false);
+    } else {
+      if (chunked) PRDPT_RENDER(false, false, true);
+      else PRDPT_RENDER(false, false, false);
+    }
   }
 #undef PRDPT_RENDER
   return hipGetLastError();
@@ -1407,17 +1475,23 @@ hipError_t launch_combine(hipStream_t st, int rows, int d, int independent, cons
 // content (totals are read from the device-side meta), so it can be captured
 // once in a graph and replayed for every batch.
 hipError_t launch_batch(hipStream_t st, const BatchReq* reqs, BatchMeta* meta, int render_blocks,
-                        int rot, int max_sph, float* tau, double* c, float* X, float* partial,
-                        double* losses, double* grads, double* loss) {
+                        int rot, int max_sph, int max_spp, float* tau, double* c, float* X,
+                        float* partial, double* losses, double* grads, double* loss, float* pbuf) {
   const size_t lds = (size_t)sphere_lds_bytes(max_sph);
   hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, st, meta);
   hipLaunchKernelGGL(batch_tau_kernel, dim3(64), dim3(64), 0, st, reqs, meta, tau, c, X);
-  if (rot)
-    hipLaunchKernelGGL(batch_render_kernel<true>, dim3(render_blocks), dim3(kBlock), lds, st, reqs,
-                       meta, X, partial);
-  else
-    hipLaunchKernelGGL(batch_render_kernel<false>, dim3(render_blocks), dim3(kBlock), lds, st,
-                       reqs, meta, X, partial);
+#define PRDPT_BATCH_RENDER(R, K)                                                                \
+  hipLaunchKernelGGL((batch_render_kernel<R, K>), dim3(render_blocks), dim3(kBlock), lds, st, reqs, \
+                     meta, X, partial, pbuf)
+  const bool chunked = max_spp > kSampleChunk;
+  if (rot) {
+    if (chunked) PRDPT_BATCH_RENDER(true, true);
+    else PRDPT_BATCH_RENDER(true, false);
+  } else {
+    if (chunked) PRDPT_BATCH_RENDER(false, true);
+    else PRDPT_BATCH_RENDER(false, false);
+  }
+#undef PRDPT_BATCH_RENDER
   hipLaunchKernelGGL(batch_loss_kernel, dim3(1024), dim3(64), 0, st, reqs, meta, partial, losses);
   hipLaunchKernelGGL(batch_combine_kernel, dim3(256), dim3(64), 0, st, reqs, meta, c, losses,
                      grads, loss);

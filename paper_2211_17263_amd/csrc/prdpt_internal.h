@@ -84,6 +84,13 @@ struct SceneHdr : SceneLds {
   int32_t bind_comp[PRDPT_MAX_PARAMS];
 };
 
+// Paths of a tile are rendered in chunks of kSampleChunk samples per pixel;
+// each render work-group keeps the radiance of its chunk's paths in its own
+// region of kPathBufFloats floats ([sample][pixel][rgb]) until the pixels add
+// them up in sample order.
+constexpr int kSampleChunk = 64;
+constexpr int kPathBufFloats = 64 * kSampleChunk * 3;
+
 // Dynamic LDS of a render work-group: n_sph spheres (centre, radius) and their
 // materials.
 inline int sphere_lds_bytes(int n_sph) { return n_sph * (4 * 4 + 4); }

@@ -341,15 +341,16 @@ def prdpt_ctx_read_timing(ctx):
 
 
 def prdpt_traversal_counts(scene, theta, sigma, N, seed, est):
-    """Work counts of one estimate's render: per-lane nodes, tris, rays, paths and
-    wave-level iterations of the node, triangle and ray loops."""
+    """Work counts of one estimate's render: per-lane nodes, tris, rays, paths,
+    wave-level iterations of the node, triangle and ray loops, and lanes idle in
+    ray-loop iterations because their pixel is done."""
     th, tp = _host(theta, np.float32)
     sg, sp = _host(sigma, np.float32)
-    out = np.zeros(7, np.uint64)
+    out = np.zeros(8, np.uint64)
     _check(load().prdpt_traversal_counts(scene.h, tp, sp, int(N), int(seed), int(est),
                                          out.ctypes.data_as(C.c_void_p)))
     return dict(zip(("nodes", "tris", "rays", "paths", "wave_node_iters", "wave_tri_iters",
-                     "wave_ray_iters"), (int(x) for x in out)))
+                     "wave_ray_iters", "idle_lane_iters"), (int(x) for x in out)))
 
 
 def prdpt_copy_probe(ctx, src, dst, iters=10):

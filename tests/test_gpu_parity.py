@@ -192,6 +192,15 @@ def test_ragged_tiny_and_degenerate(ctx):
     _full_parity(ctx, pr2, 10, "one-pixel")
 
 
+def test_more_samples_than_one_chunk(ctx):
+    # spp above the per-work-group path buffer's chunk (64 samples): the tile's
+    # paths run in two chunks, each pixel adding its samples in order
+    sc = S.toy_scene(width=21, height=13, spp=80, bounces=1)
+    pr = dict(scene=sc, theta_ref=np.zeros(2, np.float32), theta0=np.array([0.3, -0.2], np.float32),
+              sigma=np.full(2, 0.3, np.float32), N=4, est=O.IS)
+    _full_parity(ctx, pr, 19, "two-chunks")
+
+
 def test_environment_and_glass(ctx):
     from paper_2211_17263_amd import native as NV
     for glass in (False, True):
