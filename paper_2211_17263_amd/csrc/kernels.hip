@@ -631,13 +631,18 @@ __device__ __forceinline__ void load_state(SceneLds& S, float* __restrict__ sph,
 // tile's pixels of sum_c (I - R)^2 when it is not null (ref must then be set),
 // and the tile's pixels into img (image k) when img != nullptr.
 //
-// Each lane owns one pixel and runs its spp camera paths as a state machine
-// that traces exactly one ray per loop iteration: the extension ray of the
-// current vertex, or one next-event shadow ray.  A lane whose path ends starts
-// its next sample in the same iteration, so lanes never wait for the longest
-// path of the wave, and every iteration runs the same traversal code.  Per
-// sample the radiance terms are added in the same order as a recursive
-// implementation (vertex by vertex; point lights, then area lights).
+// The tile's paths (valid pixels x samples) are jobs that the lanes take in
+// order whenever they are free; each lane runs its current path as a state
+// machine that traces exactly one ray per loop iteration: the extension ray of
+// the current vertex, or one next-event shadow ray.  A lane whose path ends
+// takes the next job in the same iteration, so lanes neither wait for the
+// longest path of the wave nor for the slowest pixel of the tile, and every
+// iteration runs the same traversal code.  A path's radiance goes to its slot
+// of the work-group's path buffer pbuf ([sample][pixel][rgb], kSampleChunk
+// samples at a time); at the end of a chunk lane t adds pixel t's samples in
+// sample order.  Per sample the radiance terms are added in the same order as
+// a recursive implementation (vertex by vertex; point lights, then area
+// lights).
 template <bool COUNT, bool ROT, bool CHUNKED>
 __device__ __forceinline__ void render_tile(const SceneLds& S, const float* __restrict__ sph,
                                             const int* __restrict__ sph_mat,
