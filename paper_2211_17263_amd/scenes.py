@@ -468,6 +468,59 @@ def batch_jobs(seed=4, n_jobs=64, max_side=512, max_tris=200000):
 
 
 # ---------------------------------------------------------------------------
+# randomised small scenes (every primitive, material and parameter kind)
+# ---------------------------------------------------------------------------
+def random_scene(seed):
+    """A small scene drawn from seed: a floor, 0-3 spheres (diffuse or glass),
+    0-1 area light, 0-2 point lights, 1-2 meshes (triangle cloud or box, turned
+    and moved), a random environment, and 1-8 parameters of random kinds
+    (sphere centre, quad origin, mesh translation, mesh angle, point-light
+    position, material colour).  Returns (scene, theta_ref, theta0, sigma)."""
+    rng = np.random.default_rng(seed)
+    W, H = int(rng.integers(5, 41)), int(rng.integers(5, 41))
+    s = _new_scene("random", W, H, int(rng.integers(1, 5)), int(rng.integers(0, 4)),
+                   eye=(0.3, 1.6, 3.2), look=(0.0, 0.2, 0.0), fov=float(rng.uniform(35, 60)),
+                   pixel_center=int(rng.integers(0, 2)))
+    s.env = np.asarray(rng.uniform(0.0, 0.3, 3), np.float32)
+    floor = s.material(DIFFUSE, tuple(rng.uniform(0.2, 0.9, 3)))
+    s.quad((-3.0, 0.0, -3.0), (0.0, 0.0, 6.0), (6.0, 0.0, 0.0), floor)
+    fields = []
+    for _ in range(int(rng.integers(0, 4))):
+        glass = rng.random() < 0.3
+        m = s.material(DIELECTRIC, ior=1.5) if glass else s.material(DIFFUSE, tuple(rng.uniform(0.1, 0.9, 3)))
+        i = s.sphere(tuple(rng.uniform([-1.0, 0.2, -1.0], [1.0, 0.8, 1.0])), float(rng.uniform(0.1, 0.4)), m)
+        fields += [(BIND_SPHERE, i, c) for c in range(3)]
+        if not glass:
+            fields.append((BIND_ALBEDO, m, int(rng.integers(0, 3))))
+    if rng.random() < 0.7:
+        lm = s.material(EMISSIVE, tuple(rng.uniform(5.0, 20.0, 3)))
+        lq = s.quad((-0.4, 2.2, -0.4), (0.8, 0.0, 0.0), (0.0, 0.0, 0.8), lm)
+        fields += [(BIND_QUAD, lq, c) for c in range(3)] + [(BIND_ALBEDO, lm, 1)]
+    for _ in range(int(rng.integers(0, 3))):
+        pl = s.plight(tuple(rng.uniform([-1.5, 1.0, -1.5], [1.5, 2.5, 1.5])), tuple(rng.uniform(2.0, 8.0, 3)))
+        fields += [(BIND_PLIGHT, pl, c) for c in range(3)]
+    for _ in range(int(rng.integers(1, 3))):
+        mm = s.material(DIFFUSE, tuple(rng.uniform(0.1, 0.9, 3)))
+        if rng.random() < 0.5:
+            v, f = random_triangles(rng, int(rng.integers(20, 400)), (-0.4, -0.3, -0.4), (0.4, 0.3, 0.4), 0.08)
+        else:
+            v, f = box_tris((0.0, 0.0, 0.0), tuple(rng.uniform(0.2, 0.6, 3)), 0.0)
+        mesh = s.mesh(v, f, mm, translation=tuple(rng.uniform([-1.0, 0.3, -1.0], [1.0, 0.7, 1.0])),
+                      rotation=tuple(rng.uniform(-1.0, 1.0, 3)) if rng.random() < 0.6 else (0.0, 0.0, 0.0))
+        fields += [(BIND_MESH, mesh, c) for c in range(3)] + [(BIND_MESH_ROT, mesh, c) for c in range(3)]
+    if not fields:
+        fields.append((BIND_ALBEDO, floor, 0))
+    order = rng.permutation(len(fields))[: int(rng.integers(1, min(8, len(fields)) + 1))]
+    for idx in order:
+        s.bind(*fields[idx])
+    d = s.d
+    theta_ref = np.zeros(d, np.float32)
+    theta0 = rng.uniform(-0.15, 0.15, d).astype(np.float32)
+    sigma = rng.uniform(0.05, 0.3, d).astype(np.float32)
+    return s, theta_ref, theta0, sigma
+
+
+# ---------------------------------------------------------------------------
 # scenes used by closed-form checks
 # ---------------------------------------------------------------------------
 def furnace_scene(albedo=0.6, width=32, height=32, spp=4, bounces=2, glass=False):

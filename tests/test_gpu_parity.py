@@ -201,6 +201,33 @@ def test_more_samples_than_one_chunk(ctx):
     _full_parity(ctx, pr, 19, "two-chunks")
 
 
+@pytest.mark.parametrize("seed", range(16))
+def test_random_scenes(ctx, seed):
+    # small scenes mixing every primitive, material and parameter kind
+    sc, theta_ref, theta0, sigma = S.random_scene(seed)
+    est = [O.IS, O.GAUSS, O.IS_PERDIM, O.IS | O.INDEPENDENT][seed % 4]
+    pr = dict(scene=sc, theta_ref=theta_ref, theta0=theta0, sigma=sigma, N=4, est=est)
+    _full_parity(ctx, pr, 40 + seed, f"random-{seed}")
+
+
+def test_work_counts(ctx):
+    # the counting kernel sees every camera path once and whole loops
+    from paper_2211_17263_amd import native as NV
+    pr = S.cornell_problem(seed=2, width=40, height=24, spp=3, ico_level=2)
+    sc = pr["scene"]
+    say("work-counts")
+    gs = gpu_scene(ctx, sc)
+    try:
+        c = NV.prdpt_traversal_counts(gs, pr["theta0"], pr["sigma"], 8, 3, O.IS)
+    finally:
+        gs.destroy()
+    assert c["paths"] == 8 * sc.width * sc.height * sc.spp
+    assert c["rays"] >= c["paths"]
+    for loop, work in (("wave_node_iters", "nodes"), ("wave_tri_iters", "tris"), ("wave_ray_iters", "rays")):
+        assert 0 < c[work] <= 64 * c[loop]
+    assert 0 <= c["idle_lane_iters"] <= 64 * c["wave_ray_iters"]
+
+
 def test_environment_and_glass(ctx):
     from paper_2211_17263_amd import native as NV
     for glass in (False, True):
