@@ -151,7 +151,10 @@ const char* prdpt_last_error(void);
  * context enqueues on (NULL: the device's null stream; the stream stays owned
  * by the caller and must outlive the context).  `hbm_budget` bounds the
  * sum of resident scene footprints in bytes (0 = unbounded): scene creation
- * beyond it fails with PRDPT_E_ADMISSION.
+ * beyond it fails with PRDPT_E_ADMISSION.  Scratch that the context allocates
+ * on first use and keeps until it is destroyed is not counted: per-estimate
+ * arrays (O(N d + N tiles)) and a path buffer of 48 KB per resident render
+ * work-group (~200 MB on a 256-CU device, allocated with 50 % slack).
  */
 int prdpt_ctx_create(int device, void* stream, size_t hbm_budget, prdpt_ctx** out);
 /* Synchronise and release the context's own memory (scenes must be destroyed first). */
