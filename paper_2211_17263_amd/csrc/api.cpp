@@ -151,6 +151,24 @@ int enqueue_estimate(prdpt_scene* s, const float* ref, const float* theta_dev,
   return PRDPT_OK;
 }
 
+// pinned host staging of at least n elements (hipHostMalloc; grows only)
+template <class T>
+int ensure_pinned(prdpt_ctx* ctx, T*& p, size_t& cap, size_t n) {
+  if (cap >= n) return PRDPT_OK;
+  if (p) {
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    HIP_TRY(hipHostFree(p));
+    p = nullptr;
+    cap = 0;
+  }
+  if (hipHostMalloc((void**)&p, n * sizeof(T), hipHostMallocDefault) != hipSuccess) {
+    p = nullptr;
+    return fail(PRDPT_E_NOMEM, "pinned host allocation failed");
+  }
+  cap = n;
+  return PRDPT_OK;
+}
+
 int upload_vectors(prdpt_ctx* ctx, const float* theta, const float* sigma, int d) {
   HIP_TRY(hipMemcpyAsync(ctx->theta.p, theta, sizeof(float) * d, hipMemcpyHostToDevice, ctx->stream));
   HIP_TRY(hipMemcpyAsync(ctx->sigma.p, sigma, sizeof(float) * d, hipMemcpyHostToDevice, ctx->stream));
@@ -194,9 +212,11 @@ int prdpt_ctx_destroy(prdpt_ctx* ctx) {
   hipStreamSynchronize(ctx->stream);
   void* bufs[] = {ctx->X.p, ctx->tau.p, ctx->partial.p, ctx->theta.p, ctx->sigma.p,
                   ctx->c.p, ctx->losses.p, ctx->grad.p, ctx->loss.p, ctx->counters.p, ctx->work.p,
-                  ctx->paths.p};
+                  ctx->paths.p, ctx->vin.p, ctx->vout.p};
   for (void* b : bufs)
     if (b) hipFree(b);
+  if (ctx->h_vin) hipHostFree(ctx->h_vin);
+  if (ctx->h_vout) hipHostFree(ctx->h_vout);
   for (auto& pr : ctx->pending) {
     hipEventDestroy(pr.first);
     hipEventDestroy(pr.second);
@@ -566,16 +586,27 @@ int prdpt_grad_estimate(prdpt_scene* s, const float* ref, const float* theta, co
   std::lock_guard<std::mutex> g(ctx->mu);
   HIP_TRY(hipSetDevice(ctx->device));
   if (int rc = prepare(ctx, N, d, render_tiles(s->hdr.W, s->hdr.H))) return rc;
-  if (int rc = upload_vectors(ctx, theta, sigma, d)) return rc;
-  if (int rc = enqueue_estimate(s, ref, ctx->theta.p, ctx->sigma.p, N, seed, est, ctx->grad.p,
-                                ctx->loss.p, nullptr, nullptr))
+  // one pinned upload of [theta | sigma], one pinned download of
+  // [grad | loss | losses]
+  const size_t n_in = 2 * (size_t)d, n_out = (size_t)d + 1 + (size_t)N;
+  if (int rc = ensure(ctx, ctx->vin, n_in)) return rc;
+  if (int rc = ensure(ctx, ctx->vout, n_out)) return rc;
+  if (int rc = ensure_pinned(ctx, ctx->h_vin, ctx->h_vin_n, n_in)) return rc;
+  if (int rc = ensure_pinned(ctx, ctx->h_vout, ctx->h_vout_n, n_out)) return rc;
+  std::memcpy(ctx->h_vin, theta, sizeof(float) * d);
+  std::memcpy(ctx->h_vin + d, sigma, sizeof(float) * d);
+  HIP_TRY(hipMemcpyAsync(ctx->vin.p, ctx->h_vin, sizeof(float) * n_in, hipMemcpyHostToDevice,
+                         ctx->stream));
+  double* out = ctx->vout.p;
+  if (int rc = enqueue_estimate(s, ref, ctx->vin.p, ctx->vin.p + d, N, seed, est, out, out + d,
+                                out + d + 1, nullptr))
     return rc;
-  HIP_TRY(hipMemcpyAsync(grad_out, ctx->grad.p, sizeof(double) * d, hipMemcpyDeviceToHost, ctx->stream));
-  if (loss_out)
-    HIP_TRY(hipMemcpyAsync(loss_out, ctx->loss.p, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
-  if (losses_out)
-    HIP_TRY(hipMemcpyAsync(losses_out, ctx->losses.p, sizeof(double) * N, hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(hipMemcpyAsync(ctx->h_vout, out, sizeof(double) * n_out, hipMemcpyDeviceToHost,
+                         ctx->stream));
   HIP_TRY(hipStreamSynchronize(ctx->stream));
+  std::memcpy(grad_out, ctx->h_vout, sizeof(double) * d);
+  if (loss_out) *loss_out = ctx->h_vout[d];
+  if (losses_out) std::memcpy(losses_out, ctx->h_vout + d + 1, sizeof(double) * N);
   return PRDPT_OK;
 }
 

@@ -126,6 +126,13 @@ struct prdpt_ctx {
   prdpt::DevBuf<int> work;  // work counter of the persistent render kernel
   prdpt::DevBuf<float> paths;  // per-work-group path radiance of a sample chunk
   int path_blocks = 0;         // work-group regions in `paths`
+  // the synchronous estimate's inputs [theta | sigma] and outputs
+  // [grad | loss | losses], each moved by one copy through pinned host memory
+  prdpt::DevBuf<float> vin;
+  prdpt::DevBuf<double> vout;
+  float* h_vin = nullptr;   // pinned
+  double* h_vout = nullptr; // pinned
+  size_t h_vin_n = 0, h_vout_n = 0;
   // optional timing of the fused render kernel (events on the context stream)
   bool timing = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
