@@ -102,6 +102,34 @@ def test_batch_with_rotated_instances(setup):
         rs.destroy()
 
 
+def test_batch_with_many_samples(setup):
+    # a scene with more samples per pixel than one chunk (the chunked render)
+    # beside the setup's scenes, bit-equal to the single-request path
+    import torch
+    from paper_2211_17263_amd import native as NV
+    ctx, jobs, scenes, refs = setup
+    say("batch-two-chunks")
+    sc = S.toy_scene(width=27, height=19, spp=80, bounces=1)
+    gs = NV.prdpt_scene_create(ctx, sc)
+    try:
+        job = dict(theta0=np.array([0.2, -0.1], np.float32), sigma=np.full(2, 0.3, np.float32),
+                   N=4, est=NV.PRDPT_EST_IS)
+        js, ss = [job, jobs[0]], [gs, scenes[0]]
+        rf = [NV.prdpt_render_reference(gs, np.zeros(2, np.float32), 3), refs[0]]
+        NV.prdpt_batch_config(ctx, 4, 2, True)
+        for rep in range(2):
+            seeds = {0: 11 + rep, 1: 23 + rep}
+            reqs = _batch(NV, ctx, js, ss, rf, [0, 1], seeds)
+            for i, q in zip([0, 1], reqs):
+                a = _alone(NV, ss[i], rf[i], js[i], seeds[i])
+                torch.cuda.synchronize()
+                assert q.status == 0
+                assert np.array_equal(q.grad[: ss[i].d], a["grad"]), (rep, i)
+                assert np.array_equal(q.losses[: js[i]["N"]], a["losses"]), (rep, i)
+    finally:
+        gs.destroy()
+
+
 def test_batch_isolates_invalid_requests(setup):
     from paper_2211_17263_amd import native as NV
     ctx, jobs, scenes, refs = setup
