@@ -117,7 +117,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the estimator "
-              f"shards by antithetic pairs across GPUs, which this build does not run.",
+              f"would shard by antithetic pairs across GPUs, which is not implemented.",
               file=sys.stderr)
         sys.exit(2)
 
