@@ -406,7 +406,17 @@ int prdpt::build_host_scene(const prdpt_scene_desc* D, HostScene& hs) {
   if (hs.bvh_depth > kMaxDepth4) {
     return fail(PRDPT_E_SCENE, "BVH deeper than the traversal stack");
   }
+  // every scene triangle lands in exactly one leaf: a permutation
+  hs.tri_slot.assign(tris.size(), -1);
+  for (size_t t = 0; t < tris.size(); ++t) {
+    const int64_t i = (int64_t)tris[t].id - h.tri_id_base;
+    if (i < 0 || i >= (int64_t)tris.size() || hs.tri_slot[i] >= 0) {
+      return fail(PRDPT_E_SCENE, "BVH triangles are not a permutation of the scene's");
+    }
+    hs.tri_slot[i] = (int32_t)t;
+  }
   hs.footprint = sizeof(SceneHdr) + nodes.size() * sizeof(Node) + tris.size() * sizeof(Tri) +
+                 tris.size() * sizeof(int32_t) +
                  (size_t)render_tiles(h.W, h.H) * (sizeof(float) + sizeof(int));
   return PRDPT_OK;
 }
@@ -438,6 +448,7 @@ int prdpt::upload_scene(prdpt_ctx* ctx, const HostScene& hs, prdpt_scene** out) 
     if (s->d_hdr) hipFree(s->d_hdr);
     if (s->d_nodes) hipFree(s->d_nodes);
     if (s->d_tris) hipFree(s->d_tris);
+    if (s->d_tri_slot) hipFree(s->d_tri_slot);
     if (s->d_tile_cost) hipFree(s->d_tile_cost);
     if (s->d_tile_order) hipFree(s->d_tile_order);
     delete s;
@@ -445,6 +456,7 @@ int prdpt::upload_scene(prdpt_ctx* ctx, const HostScene& hs, prdpt_scene** out) 
   bool ok = hipMalloc(&s->d_hdr, sizeof(SceneHdr)) == hipSuccess;
   ok = ok && hipMalloc(&s->d_nodes, std::max<size_t>(1, nodes.size()) * sizeof(Node)) == hipSuccess;
   ok = ok && hipMalloc(&s->d_tris, std::max<size_t>(1, tris.size()) * sizeof(Tri)) == hipSuccess;
+  ok = ok && hipMalloc(&s->d_tri_slot, std::max<size_t>(1, tris.size()) * sizeof(int32_t)) == hipSuccess;
   ok = ok && hipMalloc(&s->d_tile_cost, s->n_tiles * sizeof(float)) == hipSuccess;
   ok = ok && hipMalloc(&s->d_tile_order, s->n_tiles * sizeof(int)) == hipSuccess;
   if (!ok) {
@@ -459,6 +471,9 @@ int prdpt::upload_scene(prdpt_ctx* ctx, const HostScene& hs, prdpt_scene** out) 
     ok = hipMemcpy(s->d_nodes, nodes.data(), nodes.size() * sizeof(Node), hipMemcpyHostToDevice) == hipSuccess;
   if (ok && !tris.empty())
     ok = hipMemcpy(s->d_tris, tris.data(), tris.size() * sizeof(Tri), hipMemcpyHostToDevice) == hipSuccess;
+  if (ok && !tris.empty())
+    ok = hipMemcpy(s->d_tri_slot, hs.tri_slot.data(), tris.size() * sizeof(int32_t),
+                   hipMemcpyHostToDevice) == hipSuccess;
   ok = ok && hipMemcpy(s->d_tile_order, order.data(), s->n_tiles * sizeof(int), hipMemcpyHostToDevice) ==
                  hipSuccess;
   ok = ok && hipMemcpy(s->d_tile_cost, cost.data(), s->n_tiles * sizeof(float), hipMemcpyHostToDevice) ==
@@ -495,6 +510,7 @@ int prdpt_scene_destroy(prdpt_scene* s) {
   hipFree(s->d_hdr);
   hipFree(s->d_nodes);
   hipFree(s->d_tris);
+  hipFree(s->d_tri_slot);
   hipFree(s->d_tile_cost);
   hipFree(s->d_tile_order);
   ctx->resident -= s->footprint;

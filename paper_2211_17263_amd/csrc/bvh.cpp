@@ -57,7 +57,6 @@ struct Prim {
 };
 
 constexpr int kBins = 16;
-constexpr int kLeafMax = 4;
 constexpr int kSweepMax = 32;   // ranges up to this size use the exact sweep
 
 // SAH costs: one node visit (both child boxes) and one triangle test

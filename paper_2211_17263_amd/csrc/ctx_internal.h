@@ -96,6 +96,7 @@ struct HostScene {
   SceneHdr hdr{};
   std::vector<Node> nodes;
   std::vector<Tri> tris;
+  std::vector<int32_t> tri_slot;  // index in tris of each scene triangle
   int bvh_depth = 0;
   size_t footprint = 0;
 };
@@ -148,12 +149,13 @@ struct prdpt_scene {
   prdpt::SceneHdr* d_hdr = nullptr;
   prdpt::Node* d_nodes = nullptr;
   prdpt::Tri* d_tris = nullptr;
+  int32_t* d_tri_slot = nullptr;
   float* d_tile_cost = nullptr;  // last measured render time per pixel tile
   int* d_tile_order = nullptr;   // tiles by descending cost (render order)
   int n_tiles = 0;
   size_t footprint = 0;
   int n_nodes = 0, n_tris = 0, bvh_depth = 0;
-  prdpt::DevScene dev() const { return prdpt::DevScene{d_hdr, d_nodes, d_tris}; }
+  prdpt::DevScene dev() const { return prdpt::DevScene{d_hdr, d_nodes, d_tris, d_tri_slot}; }
 };
 
 #define HIP_TRY(expr)                                                                       \

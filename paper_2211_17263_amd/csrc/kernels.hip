@@ -183,19 +183,35 @@ __device__ __forceinline__ bool hit_tri(V3 o, V3 d, V3 v0, V3 e1, V3 e2, float t
   return hit;
 }
 
+constexpr int kTileW = 8, kTileH = 8, kBlock = kTileW * kTileH;  // one wave per 8x8 tile
+
 struct Hit {
   float t;
   int id;     // global primitive id, -1 = miss
-  int slot;   // triangle array index for triangles
 };
 
-__device__ __forceinline__ void keep_closer(Hit& h, float t, int id, int slot) {
+__device__ __forceinline__ void keep_closer(Hit& h, float t, int id) {
   if (t < h.t || (t == h.t && id < h.id)) {
     h.t = t;
     h.id = id;
-    h.slot = slot;
   }
 }
+
+// A hit as one 64-bit key whose unsigned order is the (t, primitive id) order
+// of keep_closer: t > 0, so its bits order like the value; a miss is
+// (inf, all ones), above every hit.
+__device__ __forceinline__ unsigned long long hit_key(float t, int id) {
+  return ((unsigned long long)__float_as_uint(t) << 32) | (uint32_t)id;
+}
+
+// LDS of the leaf phase: the wave's pending (lane, triangle) pairs in lane
+// order, as the owning lane of each, and each lane's best hit as a key.
+struct LeafLds {
+  unsigned long long key[kBlock];
+  uint8_t owner[kBlock * kLeafMax];
+};
+static_assert(kBlock == 64, "the leaf phase spreads pairs over one wave");
+static_assert(kLeafMax <= 7, "leaf counts are added up from three ballots");
 
 // Work counters of the instrumented kernel copy: lane-level work (nodes,
 // triangles, rays, paths) and wave-level loop iterations (counted once per wave
@@ -258,9 +274,13 @@ __device__ __forceinline__ float safe_inv(float x) {
 // one is already pending); lanes holding a leaf keep descending speculatively.
 // The wave leaves the node loop once every lane holds a leaf or has no work
 // left, or once at least PRDPT_LEAF_QUORUM percent of its active lanes hold
-// one, and then tests the pending leaves together, so the triangle loop runs
-// with many lanes active and one long descent does not stall the rest.
-// Instances are visited in order, each to completion.
+// one.  The leaf phase then lists the (lane, triangle) pairs of all pending
+// leaves and deals them out to every active lane, a pair per lane per round:
+// the lane fetches the owner's ray with cross-lane permutes, tests the
+// triangle and folds the hit into the owner's best-hit key in LDS with an
+// atomic minimum.  Lanes without a leaf of their own thus test triangles too,
+// and a wave spends ceil(pairs / active lanes) rounds instead of the largest
+// leaf's count.  Instances are visited in order, each to completion.
 //
 // Stack entries: >= 0 inner node, < 0 leaf encoded as ~(first << 3 |
 // (count - 1)).  The stack holds kStackEntries entries in LDS (stride =
@@ -269,7 +289,7 @@ __device__ __forceinline__ float safe_inv(float x) {
 // most two, and a suspended node takes the place of its own path entry, so it
 // cannot overflow.
 #ifndef PRDPT_LEAF_QUORUM
-#define PRDPT_LEAF_QUORUM 35
+#define PRDPT_LEAF_QUORUM 25
 #endif
 #ifndef PRDPT_TRACE_BUDGET
 #define PRDPT_TRACE_BUDGET 32
@@ -277,6 +297,16 @@ __device__ __forceinline__ float safe_inv(float x) {
 #ifndef PRDPT_TRACE_QUORUM
 #define PRDPT_TRACE_QUORUM 50
 #endif
+
+// popcount of the mask's bits below this lane
+__device__ __forceinline__ uint32_t mbcnt64(unsigned long long m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// the value of x in the lane whose index is addr / 4
+__device__ __forceinline__ float bperm(int addr, float x) {
+  return __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(x)));
+}
 
 // Per-lane traversal stack: entries [0, kStackEntries) in LDS (stride = the
 // work-group size), deeper ones in the lane's private overflow array.
@@ -373,7 +403,6 @@ __device__ __forceinline__ bool begin_trace(const SceneLds& S, const float* __re
   Hit& h = tr.h;
   h.t = __builtin_huge_valf();
   h.id = -1;
-  h.slot = -1;
   if (COUNT) cnt.rays++;
   for (int i = 0; i < S.n_sph; ++i) {
     float t;
@@ -382,7 +411,7 @@ __device__ __forceinline__ bool begin_trace(const SceneLds& S, const float* __re
         h.id = i;
         return true;
       }
-      keep_closer(h, t, i, -1);
+      keep_closer(h, t, i);
     }
   }
   for (int i = 0; i < S.n_quad; ++i) {
@@ -393,7 +422,7 @@ __device__ __forceinline__ bool begin_trace(const SceneLds& S, const float* __re
         h.id = S.n_sph + i;
         return true;
       }
-      keep_closer(h, t, S.n_sph + i, -1);
+      keep_closer(h, t, S.n_sph + i);
     }
   }
   tr.inst = next_inst(S, 0);
@@ -408,7 +437,8 @@ template <bool COUNT, bool ROT>
 __device__ bool continue_trace(const SceneLds& S, const Node* __restrict__ nodes,
                                const Tri* __restrict__ tris, V3 o, V3 d, float tmax, bool any,
                                Trav& tr, int* __restrict__ stack, int stride,
-                               int* __restrict__ ovf, int budget, Counters& cnt) {
+                               int* __restrict__ ovf, LeafLds* __restrict__ lf, int budget,
+                               Counters& cnt) {
   Hit& h = tr.h;
   int sp = tr.sp;
   int inst = tr.inst;
@@ -508,27 +538,73 @@ __device__ bool continue_trace(const SceneLds& S, const Node* __restrict__ nodes
         node = next;
       }
     }
-    // ---- leaf loop: the pending leaves together
-    if (leaf != 0) {
-      const int code = ~leaf;
-      const int first = code >> 3, count = (code & 7) + 1;
-      leaf = 0;
-      for (int i = first; i < first + count; ++i) {
+    // ---- leaf phase: the pending leaves' (lane, triangle) pairs, spread over
+    // the active lanes in lane order; each owner keeps the least hit key of its
+    // pairs (the same hit as testing them one by one with keep_closer)
+    if (__ballot(leaf != 0) != 0ull) {
+      const int lane = (int)__lane_id();
+      int n_own = 0, first = 0;
+      if (leaf != 0) {
+        const int code = ~leaf;
+        first = code >> 3;
+        n_own = (code & 7) + 1;
+        leaf = 0;
+      }
+      // exclusive prefix sum of the counts over the lanes, and their total
+      const unsigned long long c1 = __ballot(n_own & 1), c2 = __ballot(n_own & 2),
+                               c4 = __ballot(n_own & 4);
+      const int excl = (int)mbcnt64(c1) + 2 * (int)mbcnt64(c2) + 4 * (int)mbcnt64(c4);
+      const int total = __popcll(c1) + 2 * __popcll(c2) + 4 * __popcll(c4);
+      const unsigned long long miss = hit_key(__builtin_huge_valf(), -1);
+      unsigned long long mine = miss;
+      if (n_own > 0) {
+        if (!any && h.id >= 0) mine = hit_key(h.t, h.id);
+        lf->key[lane] = mine;
+#pragma unroll
+        for (int j = 0; j < kLeafMax; ++j)
+          if (j < n_own) lf->owner[excl + j] = (uint8_t)lane;
+      }
+      // pair p of this lane is triangle first + p - excl
+      const int tri_base = first - excl;
+      const float tlim = tmax;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      const unsigned long long act = __ballot(1);
+      const int n_act = __popcll(act), rank = (int)mbcnt64(act);
+      for (int p0 = 0; p0 < total; p0 += n_act) {
+        const int p = p0 + rank;
+        if (COUNT && first_active_lane()) cnt.wave_tri_iters++;
+        // every active lane takes part in the permutes (a lane outside the
+        // exec mask supplies no data, and an owner may have no pair of its own
+        // this round), and a lane past the last pair repeats the last one, so
+        // the triangle loads are issued before the ray permutes they overlap
+        const int pc = min(p, total - 1);
+        const int src = (int)lf->owner[pc] << 2;  // owner's permute address
+        const int i = __builtin_amdgcn_ds_bpermute(src, tri_base) + pc;
         const float4* tp = reinterpret_cast<const float4*>(tris + i);
-        const float4 p0 = tp[0], p1 = tp[1], p2 = tp[2];
-        if (COUNT) {
-          cnt.tris++;
-          if (first_active_lane()) cnt.wave_tri_iters++;
+        const float4 p0v = tp[0], p1v = tp[1];
+        const float2 p2v = *reinterpret_cast<const float2*>(tp + 2);
+        const V3 qo = mk(bperm(src, om.x), bperm(src, om.y), bperm(src, om.z));
+        const V3 qd = mk(bperm(src, dm.x), bperm(src, dm.y), bperm(src, dm.z));
+        const float qt = bperm(src, tlim);
+        if (p < total) {
+          if (COUNT) cnt.tris++;
+          float t;
+          const bool hit = hit_tri(qo, qd, mk(p0v.x, p0v.y, p0v.z), mk(p0v.w, p1v.x, p1v.y),
+                                   mk(p1v.z, p1v.w, p2v.x), qt, &t);
+          atomicMin(&lf->key[src >> 2], hit ? hit_key(t, __float_as_int(p2v.y)) : miss);
         }
-        float t;
-        if (hit_tri(om, dm, mk(p0.x, p0.y, p0.z), mk(p0.w, p1.x, p1.y), mk(p1.z, p1.w, p2.x), tmax,
-                    &t)) {
-          if (any) {
-            h.t = t;
-            h.id = __float_as_int(p2.y);
-            return true;
-          }
-          keep_closer(h, t, __float_as_int(p2.y), i);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      if (n_own > 0) {
+        const unsigned long long best = lf->key[lane];
+        if (best != mine) {
+          h.t = __uint_as_float((uint32_t)(best >> 32));
+          h.id = (int)(uint32_t)best;
+          if (any) return true;
         }
       }
     }
@@ -590,7 +666,6 @@ constexpr float kInvPi = 0.318309886183790671538f;
 // ---------------------------------------------------------------------------
 // kernels
 // ---------------------------------------------------------------------------
-constexpr int kTileW = 8, kTileH = 8, kBlock = kTileW * kTileH;  // one wave per 8x8 tile
 #ifndef PRDPT_MIN_WAVES_PER_EU
 #define PRDPT_MIN_WAVES_PER_EU 4
 #endif
@@ -647,13 +722,16 @@ template <bool COUNT, bool ROT, bool CHUNKED>
 __device__ __forceinline__ void render_tile(const SceneLds& S, const float* __restrict__ sph,
                                             const int* __restrict__ sph_mat,
                                             const Node* __restrict__ nodes,
-                                            const Tri* __restrict__ tris, int k, int tile, int tag,
+                                            const Tri* __restrict__ tris,
+                                            const int32_t* __restrict__ tri_slot, int k, int tile,
+                                            int tag,
                                             uint32_t k0, uint32_t k1, const float* __restrict__ ref,
                                             float* __restrict__ img, float* partial_slot,
                                             unsigned long long* __restrict__ counters,
                                             int* __restrict__ stack, float* __restrict__ wsum,
                                             int crn, float* __restrict__ pbuf,
-                                            volatile int* __restrict__ next_job) {
+                                            volatile int* __restrict__ next_job,
+                                            LeafLds* __restrict__ lf) {
   const int tiles_x = (S.W + kTileW - 1) / kTileW;
   const int t = threadIdx.x;
   const int tx0 = (tile % tiles_x) * kTileW, ty0 = (tile / tiles_x) * kTileH;
@@ -731,7 +809,8 @@ __device__ __forceinline__ void render_tile(const SceneLds& S, const float* __re
             mat = S.quad_mat[qi];
             ng = ld3(S.quad_nu[qi]);
           } else {
-            const float4* tp = reinterpret_cast<const float4*>(tris + h.slot);
+            const float4* tp =
+                reinterpret_cast<const float4*>(tris + tri_slot[h.id - S.tri_id_base]);
             const float4 p0 = tp[0], p1 = tp[1], p2 = tp[2];
             mat = __float_as_int(p2.z);
             ng = cross(mk(p0.w, p1.x, p1.y), mk(p1.z, p1.w, p2.x));  // the mesh's frame
@@ -931,7 +1010,7 @@ __device__ __forceinline__ void render_tile(const SceneLds& S, const float* __re
       }
     }
     tracing = !continue_trace<COUNT, ROT>(S, nodes, tris, o, dir, tmax, shadow, tr, stk, kBlock,
-                                          ovf, PRDPT_TRACE_BUDGET, cnt);
+                                          ovf, lf, PRDPT_TRACE_BUDGET, cnt);
     answered = !tracing;
   }
   // every path of the chunk is done: each lane adds its pixel's samples in
@@ -1012,6 +1091,7 @@ __global__ __launch_bounds__(kBlock, PRDPT_MIN_WAVES_PER_EU) void render_loss_ke
   __shared__ float wsum[kBlock / 64];
   __shared__ int s_item;
   __shared__ int s_job;
+  __shared__ LeafLds s_leaf;
   float* const my_paths = pbuf + (size_t)blockIdx.x * kPathBufFloats;
   extern __shared__ float sph[];  // sphere_lds_bytes(n_sph) at launch
   int* sph_mat = reinterpret_cast<int*>(sph + 4 * scene.hdr->n_sph);
@@ -1031,9 +1111,10 @@ __global__ __launch_bounds__(kBlock, PRDPT_MIN_WAVES_PER_EU) void render_loss_ke
     }
     unsigned long long t0 = 0;
     if (cost && threadIdx.x == 0) t0 = wall_clock64();
-    render_tile<COUNT, ROT, CHUNKED>(S, sph, sph_mat, scene.nodes, scene.tris, k, tile, tag, k0, k1, ref, img,
+    render_tile<COUNT, ROT, CHUNKED>(S, sph, sph_mat, scene.nodes, scene.tris, scene.tri_slot, k, tile,
+                       tag, k0, k1, ref, img,
                        partial ? partial + (size_t)k * n_tiles + tile : nullptr, counters, stack,
-                       wsum, crn, my_paths, &s_job);
+                       wsum, crn, my_paths, &s_job, &s_leaf);
     if (cost && threadIdx.x == 0) cost[tile] = (float)(wall_clock64() - t0);
     __syncthreads();
   }
@@ -1297,6 +1378,7 @@ __global__ __launch_bounds__(kBlock, PRDPT_MIN_WAVES_PER_EU) void batch_render_k
   __shared__ float wsum[kBlock / 64];
   __shared__ int s_item;
   __shared__ int s_job;
+  __shared__ LeafLds s_leaf;
   float* const my_paths = pbuf + (size_t)blockIdx.x * kPathBufFloats;
   extern __shared__ float sph[];  // sphere_lds_bytes(largest n_sph of the batch) at launch
   const int total = meta->total_items, n = meta->n_req, tpi = meta->tiles_per_item;
@@ -1316,9 +1398,10 @@ __global__ __launch_bounds__(kBlock, PRDPT_MIN_WAVES_PER_EU) void batch_render_k
     load_state(S, sph, sph_mat, q.scene.hdr, X + (size_t)(q.row_base + k) * PRDPT_BATCH_MAX_PARAMS,
                q.d);
     for (int tile = first; tile < last; ++tile) {
-      render_tile<false, ROT, CHUNKED>(S, sph, sph_mat, q.scene.nodes, q.scene.tris, k, tile, kTagPath, q.k0, q.k1, q.ref,
+      render_tile<false, ROT, CHUNKED>(S, sph, sph_mat, q.scene.nodes, q.scene.tris, q.scene.tri_slot, k,
+                         tile, kTagPath, q.k0, q.k1, q.ref,
                          nullptr, partial + (size_t)q.partial_base + (size_t)k * q.n_tiles + tile,
-                         nullptr, stack, wsum, 1, my_paths, &s_job);
+                         nullptr, stack, wsum, 1, my_paths, &s_job, &s_leaf);
       __syncthreads();
     }
   }

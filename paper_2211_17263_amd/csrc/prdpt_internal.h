@@ -23,6 +23,12 @@ constexpr int kStackEntries = 26;
 constexpr int kStackOverflow = kStackBound - kStackEntries;
 // child reference of an empty slot of a 4-wide node
 constexpr int32_t kEmptyChild = INT32_MIN;
+// most triangles in a BVH leaf (the traversal spreads a wave's pending leaves
+// over its lanes in a table of kLeafMax entries per lane)
+#ifndef PRDPT_LEAF_MAX
+#define PRDPT_LEAF_MAX 4
+#endif
+constexpr int kLeafMax = PRDPT_LEAF_MAX;
 
 // Flattened 4-wide BVH node (128 bytes, seven 16-byte loads): the padded boxes
 // of its children as six 4-vectors (one per box face coordinate) and the child
@@ -100,6 +106,7 @@ struct DevScene {
   const SceneHdr* hdr;
   const Node* nodes;
   const Tri* tris;
+  const int32_t* tri_slot;  // index in tris of the triangle with id tri_id_base + i, by i
 };
 
 // One request of a batch (device table, filled by the host per batch).  Rows
