@@ -165,9 +165,10 @@ int prdpt_ctx_set_stream(prdpt_ctx* ctx, void* stream);
 int prdpt_ctx_resident_bytes(prdpt_ctx* ctx, size_t* bytes);
 
 /*
- * Validate and copy a scene, build its BVHs on the host (binned SAH, 64-byte
- * nodes, 48-byte triangles), upload them, and return a handle that stays
- * resident in HBM until prdpt_scene_destroy.  *footprint_bytes (nullable)
+ * Validate and copy a scene, build its BVHs on the host (binned SAH, 4-wide
+ * 128-byte nodes, 48-byte triangles and a 4-byte id-to-position entry per
+ * triangle), upload them, and return a handle that stays resident in HBM until
+ * prdpt_scene_destroy.  *footprint_bytes (nullable)
  * receives the device bytes held.  Errors: PRDPT_E_ARG (null), PRDPT_E_SCENE
  * (limits, indices, material rules), PRDPT_E_ADMISSION, PRDPT_E_NOMEM.
  */
