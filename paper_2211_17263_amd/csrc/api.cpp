@@ -406,6 +406,14 @@ int prdpt::build_host_scene(const prdpt_scene_desc* D, HostScene& hs) {
   if (hs.bvh_depth > kMaxDepth4) {
     return fail(PRDPT_E_SCENE, "BVH deeper than the traversal stack");
   }
+  // the traversal's leaf phase holds at most kLeafMax triangles per lane
+  for (const Node& nd : nodes)
+    for (int c = 0; c < 4; ++c) {
+      const int32_t r = nd.ref[c];
+      if (r < 0 && r != kEmptyChild && (~r & 7) + 1 > kLeafMax) {
+        return fail(PRDPT_E_SCENE, "BVH leaf larger than the traversal's leaf bound");
+      }
+    }
   // every scene triangle lands in exactly one leaf: a permutation
   hs.tri_slot.assign(tris.size(), -1);
   for (size_t t = 0; t < tris.size(); ++t) {

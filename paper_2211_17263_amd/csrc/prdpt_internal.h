@@ -19,7 +19,10 @@ constexpr int kMaxDepth4 = (kMaxInnerDepth + 1) / 2;
 // node adds one entry for itself.  kStackEntries live in LDS, the rest in a
 // small per-lane private array that only unusually deep descents reach.
 constexpr int kStackBound = 3 * kMaxDepth4 + 1;
-constexpr int kStackEntries = 26;
+#ifndef PRDPT_STACK_LDS
+#define PRDPT_STACK_LDS 26
+#endif
+constexpr int kStackEntries = PRDPT_STACK_LDS;
 constexpr int kStackOverflow = kStackBound - kStackEntries;
 // child reference of an empty slot of a 4-wide node
 constexpr int32_t kEmptyChild = INT32_MIN;
