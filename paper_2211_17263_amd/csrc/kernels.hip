@@ -284,10 +284,11 @@ __device__ __forceinline__ float safe_inv(float x) {
 //
 // Stack entries: >= 0 inner node, < 0 leaf encoded as ~(first << 3 |
 // (count - 1)).  The stack holds kStackEntries entries in LDS (stride =
-// work-group size); the builder bounds the inner-node depth, every inner node
-// on the current path holds at most one stack entry and the last visited one at
-// most two, and a suspended node takes the place of its own path entry, so it
-// cannot overflow.
+// work-group size) and the rest in the lane's private overflow array; the
+// builder bounds the 4-wide depth, every node on the current path keeps at
+// most three of its children on the stack and the last visited one at most
+// four, and a suspended node adds one entry for itself, so the two parts
+// together (kStackBound entries) cannot overflow.
 #ifndef PRDPT_LEAF_QUORUM
 #define PRDPT_LEAF_QUORUM 25
 #endif
