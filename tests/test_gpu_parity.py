@@ -201,6 +201,27 @@ def test_more_samples_than_one_chunk(ctx):
     _full_parity(ctx, pr, 19, "two-chunks")
 
 
+def test_exact_ties_take_the_smaller_id(ctx):
+    # two identical static icospheres (one BVH): every hit on them is an exact
+    # tie in t between a triangle and its twin, which the closest-hit rule
+    # breaks by the smaller primitive id, i.e. the first (green) copy; shadow
+    # rays meet the same twin occluders
+    sc = S.toy_scene(width=40, height=32, spp=2, bounces=2)
+    green = sc.material(S.DIFFUSE, (0.1, 0.8, 0.1))
+    blue = sc.material(S.DIFFUSE, (0.1, 0.1, 0.8))
+    v, f = S.icosphere(2)
+    v = (v * 0.45 + np.array([-0.9, 0.3, 0.6])).astype(np.float32)
+    sc.mesh(v, f, green)
+    sc.mesh(v.copy(), f.copy(), blue)
+    pr = dict(scene=sc, theta_ref=np.zeros(2, np.float32), theta0=np.array([0.2, -0.1], np.float32),
+              sigma=np.full(2, 0.3, np.float32), N=4, est=O.IS)
+    _full_parity(ctx, pr, 23, "exact-ties")
+    img = O.OracleScene(sc).reference(pr["theta_ref"], seed=5)
+    g, b = img[..., 1], img[..., 2]
+    assert np.count_nonzero(g > 2.0 * b + 1e-3) > 20   # the green copy is what shows
+    assert np.count_nonzero(b > 2.0 * g + 1e-3) == 0
+
+
 @pytest.mark.parametrize("seed", range(16))
 def test_random_scenes(ctx, seed):
     # small scenes mixing every primitive, material and parameter kind

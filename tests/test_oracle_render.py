@@ -199,6 +199,43 @@ def test_bvh_closest_hit_equals_brute_force():
     assert (i1 >= 3).sum() > 1000          # many triangle hits (ids after sphere and quad)
 
 
+def _twin_scenes():
+    sc = S.toy_scene(width=40, height=32, spp=2, bounces=2)
+    green = sc.material(S.DIFFUSE, (0.1, 0.8, 0.1))
+    blue = sc.material(S.DIFFUSE, (0.1, 0.1, 0.8))
+    v, f = S.icosphere(2)
+    v = (v * 0.45 + np.array([-0.9, 0.3, 0.6])).astype(np.float32)
+    single = S.toy_scene(width=40, height=32, spp=2, bounces=2)
+    single.material(S.DIFFUSE, (0.1, 0.8, 0.1))
+    single.material(S.DIFFUSE, (0.1, 0.1, 0.8))
+    sc.mesh(v, f, green)
+    sc.mesh(v.copy(), f.copy(), blue)
+    single.mesh(v.copy(), f.copy(), green)
+    return sc, single, len(f)
+
+
+def test_exact_ties_resolve_to_the_smaller_id():
+    # a mesh and its exact twin: every hit on them ties in t, and the closest-hit
+    # rule (t, then primitive id) must take the first copy, in the BVH and by
+    # brute force alike; the rendered image is then the twin-free scene's
+    sc, single, nf = _twin_scenes()
+    rng = np.random.default_rng(8)
+    X = np.zeros(2, np.float32)
+    n = 4000
+    o = np.tile(np.array([0.0, 0.0, 5.0], np.float32), (n, 1))
+    tgt = np.array([-0.9, 0.3, 0.6]) + rng.uniform(-0.5, 0.5, (n, 3))
+    d = (tgt - o) / np.linalg.norm(tgt - o, axis=1, keepdims=True)
+    first = 1 + 1  # ids: the sphere, the ground quad, then the triangles
+    for brute in (False, True):
+        t, i = O.OracleScene(sc, brute_force=brute).trace(X, o, d.astype(np.float32))
+        assert np.count_nonzero((i >= first) & (i < first + nf)) > 1000
+        assert np.count_nonzero(i >= first + nf) == 0
+    theta = np.array([0.2, -0.1], np.float32)
+    a = O.OracleScene(sc).reference(theta, seed=5)
+    b = O.OracleScene(single).reference(theta, seed=5)
+    assert np.array_equal(a, b)
+
+
 def test_many_spheres_closest_hit_analytic():
     # 75 bound spheres, each moved by its two parameters: the closest hit of a
     # ray is the nearest intersected sphere in binary64 (rays whose two nearest
