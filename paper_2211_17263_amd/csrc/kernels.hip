@@ -346,20 +346,22 @@ __device__ __forceinline__ void order2(float& ta, int& ra, float& tb, int& rb) {
 
 // Rz(c) Ry(b) Rx(a) for the angles (a, b, c) = ang (rotations about the fixed
 // x, y, z axes, applied in that order), row-major; entries are formed in
-// binary64 and rounded to binary32, so zero angles give the identity exactly.
+// binary64 and rounded to binary32, so zero angles give the identity exactly,
+// and an entry that is zero is +0 (adding +0 clears a negative zero), as in
+// the product of the three axis matrices summed from zero.
 __host__ __device__ inline void euler_rotation(const float* ang, float* R) {
   const double ca = cos((double)ang[0]), sa = sin((double)ang[0]);
   const double cb = cos((double)ang[1]), sb = sin((double)ang[1]);
   const double cc = cos((double)ang[2]), sc = sin((double)ang[2]);
-  R[0] = (float)(cc * cb);
-  R[1] = (float)(cc * sb * sa - sc * ca);
-  R[2] = (float)(cc * sb * ca + sc * sa);
-  R[3] = (float)(sc * cb);
-  R[4] = (float)(sc * sb * sa + cc * ca);
-  R[5] = (float)(sc * sb * ca - cc * sa);
-  R[6] = (float)(-sb);
-  R[7] = (float)(cb * sa);
-  R[8] = (float)(cb * ca);
+  R[0] = (float)(cc * cb + 0.0);
+  R[1] = (float)(cc * sb * sa - sc * ca + 0.0);
+  R[2] = (float)(cc * sb * ca + sc * sa + 0.0);
+  R[3] = (float)(sc * cb + 0.0);
+  R[4] = (float)(sc * sb * sa + cc * ca + 0.0);
+  R[5] = (float)(sc * sb * ca - cc * sa + 0.0);
+  R[6] = (float)(-sb + 0.0);
+  R[7] = (float)(cb * sa + 0.0);
+  R[8] = (float)(cb * ca + 0.0);
 }
 
 // The ray (o, d) in the frame of instance `inst`: R^T (o - t) and R^T d
@@ -815,10 +817,17 @@ __device__ __forceinline__ void render_tile(const SceneLds& S, const float* __re
             const float4 p0 = tp[0], p1 = tp[1], p2 = tp[2];
             mat = __float_as_int(p2.z);
             ng = cross(mk(p0.w, p1.x, p1.y), mk(p1.z, p1.w, p2.x));  // the mesh's frame
+            // into the world by the instance's rotation; without rotations it
+            // is the zero-angle matrix, still applied: its zero entries decide
+            // the sign of a zero normal component, and that sign picks the
+            // tangent frame of the bounce
             if (ROT) {
               const float* R = S.inst_rot[__float_as_int(p2.w)];
               ng = mk(R[0] * ng.x + R[1] * ng.y + R[2] * ng.z, R[3] * ng.x + R[4] * ng.y + R[5] * ng.z,
                       R[6] * ng.x + R[7] * ng.y + R[8] * ng.z);
+            } else {
+              ng = mk(ng.x + 0.0f * ng.y + 0.0f * ng.z, 0.0f * ng.x + ng.y + 0.0f * ng.z,
+                      0.0f * ng.x + 0.0f * ng.y + ng.z);
             }
             ng = unit(ng);
           }

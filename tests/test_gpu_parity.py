@@ -222,6 +222,24 @@ def test_exact_ties_take_the_smaller_id(ctx):
     assert np.count_nonzero(b > 2.0 * g + 1e-3) == 0
 
 
+def test_zero_normal_component_picks_the_same_frame(ctx):
+    # an icosphere has faces whose edge cross product has a z component of
+    # -0; the world normal (the zero-angle rotation applied to it) has +0
+    # there, and the sign of that zero selects the tangent frame of a bounce,
+    # so both sides must carry it the same way (camera paths reach such faces)
+    sc = S.toy_scene(width=40, height=32, spp=2, bounces=2)
+    green = sc.material(S.DIFFUSE, (0.1, 0.8, 0.1))
+    v, f = S.icosphere(2)
+    v = (v * 0.45 + np.array([-0.9, 0.3, 0.6])).astype(np.float32)
+    e1, e2 = v[f[:, 1]] - v[f[:, 0]], v[f[:, 2]] - v[f[:, 0]]
+    nz = e1[:, 0] * e2[:, 1] - e1[:, 1] * e2[:, 0]
+    assert np.any((nz == 0) & np.signbit(nz))
+    sc.mesh(v, f, green)
+    pr = dict(scene=sc, theta_ref=np.zeros(2, np.float32), theta0=np.array([0.2, -0.1], np.float32),
+              sigma=np.full(2, 0.3, np.float32), N=4, est=O.IS)
+    _full_parity(ctx, pr, 23, "zero-normal-component")
+
+
 @pytest.mark.parametrize("seed", range(16))
 def test_random_scenes(ctx, seed):
     # small scenes mixing every primitive, material and parameter kind
