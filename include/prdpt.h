@@ -369,11 +369,11 @@ int prdpt_ctx_read_timing(prdpt_ctx* ctx, double* total_ms, int64_t* launches);
  * Work of one estimate, measured by an instrumented copy of the render kernel
  * on the same rays: counts[0] BVH nodes fetched, counts[1] triangles tested,
  * counts[2] ray queries (closest-hit and shadow), counts[3] camera paths,
- * counts[4..6] iterations of the node loop, the triangle loop and the ray loop
- * executed per wavefront (summed over wavefronts; lane work / (64 x iterations)
- * is each loop's SIMD efficiency), counts[7] lanes idle in ray-loop iterations
- * because their pixel's samples are done or the tile has no pixel for them
- * (summed over iterations).  counts: host uint64_t[8].  Synchronous.
+ * counts[4..6] iterations of the node loop, the rounds of triangle tests and
+ * iterations of the ray loop executed per wavefront (summed over wavefronts;
+ * lane work / (64 x iterations) is each loop's SIMD efficiency), counts[7]
+ * lanes idle in ray-loop iterations because their tile has no path left for
+ * them (summed over iterations).  counts: host uint64_t[8].  Synchronous.
  */
 int prdpt_traversal_counts(prdpt_scene* scene, const float* theta, const float* sigma, int N,
                            uint64_t seed, int est, uint64_t* counts);
