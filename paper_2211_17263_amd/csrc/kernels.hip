@@ -7,8 +7,12 @@
 // evaluated in binary32 in a fixed order without contraction (the library is
 // built with -ffp-contract=off and correctly rounded division and square root),
 // and the sample transforms use the library's own ln / sincos(2 pi u) built from
-// basic IEEE operations.  Per-sample paths are therefore reproducible bit for
-// bit on any IEEE-754 machine; only the pixel/loss sums differ in rounding.
+// basic IEEE operations.  Signed zeros count too: the sign of a zero normal
+// component picks the tangent frame of a bounce, so a triangle's world normal
+// is always the instance rotation applied to its mesh-frame normal, even where
+// that rotation is the identity.  Per-sample paths are therefore reproducible
+// bit for bit on any IEEE-754 machine; only the pixel/loss sums differ in
+// rounding.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -219,7 +223,7 @@ static_assert(kLeafMax <= 7, "leaf counts are added up from three ballots");
 struct Counters {
   uint32_t nodes, tris, rays, paths;
   uint32_t wave_node_iters, wave_tri_iters, wave_outer_iters;
-  uint32_t idle_lane_iters;  // ray-loop iterations x lanes whose pixel is done (or absent)
+  uint32_t idle_lane_iters;  // ray-loop iterations x lanes with no path of the tile left
 };
 
 __device__ __forceinline__ bool first_active_lane() {
@@ -738,7 +742,7 @@ __device__ __forceinline__ void render_tile(const SceneLds& S, const float* __re
   const int tiles_x = (S.W + kTileW - 1) / kTileW;
   const int t = threadIdx.x;
   const int tx0 = (tile % tiles_x) * kTileW, ty0 = (tile / tiles_x) * kTileH;
-  const int lx = t & 7, ly = t >> 3;  // lane t owns pixel (lx, ly) of the tile
+  const int lx = t & 7, ly = t >> 3;  // lane t sums and writes pixel (lx, ly) of the tile
   const int x = tx0 + lx, y = ty0 + ly;
   const bool valid = x < S.W && y < S.H;
   const int pix = y * S.W + x;
