@@ -10,7 +10,9 @@ default workload is the global-illumination scene (256x256, 16 spp, 4 bounces,
 
 Prints one JSON line.  `value` is gradient estimates per second over the timed
 steps; `roofline` describes the fused render kernel (algorithmic node/triangle/
-reference bytes per launch over its event-timed duration, against 8 TB/s HBM);
+reference bytes per launch over its event-timed duration, against 8 TB/s HBM),
+`roofline_alu` the same kernel's algorithmic binary32 arithmetic against the
+157.3 TFLOP/s vector peak, and `valu` its measured VALU issue utilisation;
 `cpu_baseline` is the CPU oracle timed on this host's cores on a bounded sample
 (a subset of the antithetic pairs of one estimate) of the same workload.
 """
@@ -28,6 +30,11 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 NODE_BYTES, TRI_BYTES, REF_BYTES_PER_PIXEL = 128, 48, 12
+# algorithmic binary32 arithmetic per unit of work (fma = 2): a 4-wide node
+# visit is four slab tests of 6 fma + 6 min/max; a Moeller-Trumbore test is two
+# cross products, four dot products, one difference, one division, three
+# products and one sum; shading per ray query is an estimate (100-200)
+NODE_FLOPS, TRI_FLOPS, SHADE_FLOPS_PER_RAY = 4 * 18, 46, 150
 FP32_PEAK_TFLOPS = 157.3
 KERNEL_SRC = os.path.join(ROOT, "paper_2211_17263_amd", "csrc", "kernels.hip")
 
@@ -70,6 +77,17 @@ def traffic_from_profile(workload):
         return float(kv["fetch_bytes_per_launch"]) + float(kv["write_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
+
+
+def alu_roofline(per, kernel_s):
+    """The render kernel against the binary32 vector peak: algorithmic FP32
+    operations of its node visits, triangle tests and shading per launch (from
+    the counting copy's work on the same rays) over the event-timed duration."""
+    flops = (per["nodes"] * NODE_FLOPS + per["tris"] * TRI_FLOPS +
+             per["rays"] * SHADE_FLOPS_PER_RAY)
+    achieved = flops / kernel_s / 1e12
+    return {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / FP32_PEAK_TFLOPS, "flops_per_launch": flops}
 
 
 def valu_from_profile(workload, kernel_s):
@@ -243,6 +261,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_profile(args.workload)},
         "valu": valu_from_profile(args.workload, kernel_avg_s),
+        "roofline_alu": alu_roofline(per, kernel_avg_s),
         "scene_build_s": t_build,
         "final_loss": last["loss"],
     }
