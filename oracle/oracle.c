@@ -144,6 +144,7 @@ typedef struct {
   uint32_t pair, block;
   uint32_t w[4];
   int used;
+  int strata;  /* > 0: the draw's first uniform lies in stratum `pair` of this many */
 } tau_stream;
 
 static uint32_t tau_word(tau_stream* st) {
@@ -156,10 +157,21 @@ static uint32_t tau_word(tau_stream* st) {
   return st->w[st->used++];
 }
 
+/* the next uniform of the draw; with strata, the first one is (i + u) / P for
+ * draw i of P (binary32, kept below 1) */
+static float tau_uniform(tau_stream* st) {
+  float u = orc_u01(tau_word(st));
+  if (st->strata > 0) {
+    u = fminf(((float)st->pair + u) / (float)st->strata, 0x1.fffffep-1f);
+    st->strata = 0;
+  }
+  return u;
+}
+
 /* one Box-Muller pair of standard normals from two uniforms */
 static void normal_pair(tau_stream* st, float* z0, float* z1) {
-  float u1 = orc_u01(tau_word(st));
-  float u2 = orc_u01(tau_word(st));
+  float u1 = tau_uniform(st);
+  float u2 = tau_uniform(st);
   float rad = sqrtf(-2.0f * orc_ln(u1));
   float sn, cs;
   orc_sincos_2pi(u2, &sn, &cs);
@@ -174,7 +186,9 @@ int orc_draw_tau(int mode, int d, int P, uint64_t seed, const float* sigma, floa
    * weight (its expectation over the draw is the gradient by itself), written
    * below directly: v_j / sigma_j, C_d u_j / sigma_j, s_j 2 / (sigma_j sqrt(2 pi)) */
   const int indep = (mode & ORC_EST_INDEPENDENT) != 0;
-  mode &= ~ORC_EST_INDEPENDENT;
+  const int strat = (mode & ORC_EST_STRATIFIED) != 0;
+  if (strat && !indep) return -1;  /* strata replace the antithetic partner */
+  mode &= ~(ORC_EST_INDEPENDENT | ORC_EST_STRATIFIED);
   double cd = orc_chi_mean(d);
   const double sqrt2pi = sqrt(2.0 * ORC_PI);
   float v[ORC_MAX_PARAMS], z[ORC_MAX_PARAMS];
@@ -184,6 +198,7 @@ int orc_draw_tau(int mode, int d, int P, uint64_t seed, const float* sigma, floa
     st.pair = (uint32_t)p;
     st.block = 0;
     st.used = 4;
+    st.strata = strat ? P : 0;
     if (mode == ORC_EST_GAUSS) {
       /* tau ~ kappa: v standard normal; pair weight v_j / (2 sigma_j) is the
        * antithetic average of the score (tau_j / sigma_j^2) (Eq. 10, 11). */
@@ -204,7 +219,7 @@ int orc_draw_tau(int mode, int d, int P, uint64_t seed, const float* sigma, floa
        * uniform; pair weight C_d u_j / (2 sigma_j). */
       int m = (d + 1) / 2;
       float acc = 0.0f;
-      for (int i = 0; i < m; ++i) acc = acc + orc_ln(orc_u01(tau_word(&st)));
+      for (int i = 0; i < m; ++i) acc = acc + orc_ln(tau_uniform(&st));
       float rho2 = -2.0f * acc;
       if ((d + 1) & 1) {
         float z0, z1;
@@ -230,7 +245,7 @@ int orc_draw_tau(int mode, int d, int P, uint64_t seed, const float* sigma, floa
     } else if (mode == ORC_EST_IS_PERDIM) {
       /* literal per-dimension reading: independent two-sided Rayleigh per axis;
        * the signs come after the radii, one word per 32 axes (bit j mod 32) */
-      for (int j = 0; j < d; ++j) v[j] = sqrtf(-2.0f * orc_ln(orc_u01(tau_word(&st))));
+      for (int j = 0; j < d; ++j) v[j] = sqrtf(-2.0f * orc_ln(tau_uniform(&st)));
       uint32_t bits = 0;
       for (int j = 0; j < d; ++j) {
         if (j % 32 == 0) bits = tau_word(&st);

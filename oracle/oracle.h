@@ -30,6 +30,10 @@ enum { ORC_EST_GAUSS = 0, ORC_EST_IS = 1, ORC_EST_IS_PERDIM = 2 };
  * partner (the paper's noAT ablation, Sec. 5.3): N draws, one render each at
  * theta + tau_i with its own path stream, single-sample score weights */
 enum { ORC_EST_INDEPENDENT = 0x100 };
+/* flag or-ed into an independent mode: stratified draws, the alternative to
+ * antithetic pairs that Sec. 3.2 mentions; the first uniform of draw i of P is
+ * moved into stratum i, (i + u) / P, so the P draws cover [0, 1) once each */
+enum { ORC_EST_STRATIFIED = 0x200 };
 enum { ORC_TAG_TAU = 1, ORC_TAG_PATH = 2, ORC_TAG_REF = 3 };
 
 /* Scene as flat arrays; the oracle copies everything it needs. */

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "liboracle.so")
 
 GAUSS, IS, IS_PERDIM = 0, 1, 2
 INDEPENDENT = 0x100          # or-ed into a mode: no antithetic partners (noAT)
+STRATIFIED = 0x200           # or-ed into an independent mode: stratified first uniforms
 TAG_TAU, TAG_PATH, TAG_REF = 1, 2, 3
 
 _lib = None

@@ -284,3 +284,53 @@ def test_independent_weights_are_twice_the_pair_weights_and_lose_zero_variance()
     _, _, _, terms_ind = estimate_independent(O.IS, [0.0], [0.5], 2000, 3, step(0.0))
     assert np.ptp(terms_at) == 0.0
     assert terms_ind.std() > 0.5 * np.abs(terms_ind.mean())
+
+
+# ---- stratified draws (the alternative to antithetic pairs of Sec. 3.2) ----
+
+@pytest.mark.parametrize("mode", [O.IS, O.IS_PERDIM])
+@pytest.mark.parametrize("N", [2, 7, 64])
+def test_stratified_draws_cover_each_stratum_once(mode, N):
+    # d = 1: |v_i| = sqrt(-2 ln xi_i), so xi_i = exp(-v_i^2 / 2) recovers the
+    # draw's first uniform, which must lie in stratum i of N
+    sigma = 0.4
+    tau, c = O.draw_tau(mode | O.INDEPENDENT | O.STRATIFIED, [sigma], N, 17)
+    xi = np.exp(-0.5 * (tau[:, 0].astype(np.float64) / sigma) ** 2)
+    pos = xi * N - np.arange(N)
+    assert np.all(pos > -1e-4) and np.all(pos < 1.0 + 1e-4), pos
+    # the plain independent draws of the same seed are not stratified
+    t2, _ = O.draw_tau(mode | O.INDEPENDENT, [sigma], N, 17)
+    if N == 64:
+        x2 = np.exp(-0.5 * (t2[:, 0].astype(np.float64) / sigma) ** 2)
+        assert np.any(np.abs(x2 * N - np.arange(N) - 0.5) > 1.0)
+
+
+def test_stratified_needs_independent_draws():
+    with pytest.raises(ValueError):
+        O.draw_tau(O.IS | O.STRATIFIED, [0.3], 4, 1)
+
+
+def stratified_estimates(mode, theta, sigma, N, seeds, Lfun):
+    out = []
+    for s in seeds:
+        tau, c = O.draw_tau(mode, np.asarray(sigma, np.float32), N, s)
+        X = (np.asarray(theta, np.float32)[None, :] + tau).astype(np.float64)
+        g, _ = O.combine_independent(c, Lfun(X))
+        out.append(g)
+    return np.array(out)
+
+
+@pytest.mark.parametrize("mode", [O.GAUSS, O.IS])
+def test_stratified_erf_step_1d_unbiased_and_less_variable(mode):
+    # each stratum is sampled from its own conditional law, so the mean over
+    # seeds is grad Q exactly as for plain independent draws; stratifying the
+    # radius (IS) or the Box-Muller radius (GAUSS) lowers the variance here
+    theta, a, sigma, N = 0.3, 0.0, 0.5, 16
+    truth = phi((theta - a) / sigma) / sigma
+    seeds = range(3000)
+    gs = stratified_estimates(mode | O.INDEPENDENT | O.STRATIFIED, [theta], [sigma], N, seeds,
+                              step(a))[:, 0]
+    gi = stratified_estimates(mode | O.INDEPENDENT, [theta], [sigma], N, seeds, step(a))[:, 0]
+    se = gs.std(ddof=1) / math.sqrt(len(gs))
+    assert abs(gs.mean() - truth) <= 4 * se, (gs.mean(), truth, se)
+    assert gs.var() < gi.var(), (gs.var(), gi.var())
