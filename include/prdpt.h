@@ -71,6 +71,14 @@ extern "C" {
  * with the single-sample weights c_ij (twice the pair weights).  Accepted by
  * the single-request calls; the batched and served forms reject it. */
 #define PRDPT_EST_INDEPENDENT 0x100
+/* Flag or-ed into an independent mode (PRDPT_EST_INDEPENDENT must be set):
+ * stratified draws, the alternative to antithetic pairs that Sec. 3.2
+ * mentions.  The first uniform of draw i of the N draws is moved into stratum
+ * i, (i + u) / N (binary32, kept below 1), which stratifies the radius of the
+ * IS and IS_PERDIM samplers and the first Box-Muller radius of GAUSS; weights
+ * and renders are those of the independent draws.  Accepted by the
+ * single-request calls; the batched and served forms reject it. */
+#define PRDPT_EST_STRATIFIED 0x200
 
 /* ---- scene description ---------------------------------------------------- */
 #define PRDPT_MAT_DIFFUSE 0    /* rgb = albedo; Lambertian */

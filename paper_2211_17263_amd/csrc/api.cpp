@@ -97,9 +97,11 @@ int check_request(const prdpt_scene* s, const float* theta, const float* sigma, 
 }
 
 int check_est(int est) {
-  const int mode = est & ~PRDPT_EST_INDEPENDENT;
+  const int mode = est & ~(PRDPT_EST_INDEPENDENT | PRDPT_EST_STRATIFIED);
   if (mode != PRDPT_EST_GAUSS && mode != PRDPT_EST_IS && mode != PRDPT_EST_IS_PERDIM)
     return fail(PRDPT_E_ARG, "unknown estimator mode");
+  if ((est & PRDPT_EST_STRATIFIED) && !(est & PRDPT_EST_INDEPENDENT))
+    return fail(PRDPT_E_ARG, "stratified draws need PRDPT_EST_INDEPENDENT");
   return PRDPT_OK;
 }
 

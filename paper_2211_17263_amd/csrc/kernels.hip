@@ -1181,7 +1181,8 @@ __global__ __launch_bounds__(1024) void tile_order_kernel(const float* __restric
 __device__ void draw_pair(int est, int d, int p, uint32_t k0, uint32_t k1,
                           const float* __restrict__ sigma, const float* __restrict__ theta,
                           double cd, double sqrt2pi, int ld, float* __restrict__ tau,
-                          double* __restrict__ c, float* __restrict__ Xp, float* __restrict__ Xm) {
+                          double* __restrict__ c, float* __restrict__ Xp, float* __restrict__ Xm,
+                          int strata) {
   uint32_t blk = 0;
   int used = 4;
   uint4 w = make_uint4(0, 0, 0, 0);
@@ -1195,9 +1196,20 @@ __device__ void draw_pair(int est, int d, int p, uint32_t k0, uint32_t k1,
     ++used;
     return r;
   };
+  // the draw's next uniform; with strata > 0 the first one is moved into
+  // stratum p of strata, (p + u) / strata, kept below 1
+  bool to_stratify = strata > 0;
+  auto uniform = [&]() -> float {
+    float u = unit_open(word());
+    if (to_stratify) {
+      u = fminf(((float)p + u) / (float)strata, 0x1.fffffep-1f);
+      to_stratify = false;
+    }
+    return u;
+  };
   auto gauss2 = [&](float* z0, float* z1) {
-    const float u1 = unit_open(word());
-    const float u2 = unit_open(word());
+    const float u1 = uniform();
+    const float u2 = uniform();
     const float rad = sqrtf(-2.0f * log_ieee(u1));
     float sn, cs;
     sincos_turn(u2, &sn, &cs);
@@ -1208,7 +1220,7 @@ __device__ void draw_pair(int est, int d, int p, uint32_t k0, uint32_t k1,
   // weight, twice the pair weight (exact in binary64).  The row tau holds the
   // normal or radius draws until their final values replace them.
   const double wscale = (est & PRDPT_EST_INDEPENDENT) ? 2.0 : 1.0;
-  est &= ~PRDPT_EST_INDEPENDENT;
+  est &= ~(PRDPT_EST_INDEPENDENT | PRDPT_EST_STRATIFIED);
   if (est == PRDPT_EST_GAUSS) {
     for (int j = 0; j < d; j += 2) {
       float z0, z1;
@@ -1224,7 +1236,7 @@ __device__ void draw_pair(int est, int d, int p, uint32_t k0, uint32_t k1,
   } else if (est == PRDPT_EST_IS) {
     const int m = (d + 1) / 2;
     float acc = 0.0f;
-    for (int i = 0; i < m; ++i) acc = acc + log_ieee(unit_open(word()));
+    for (int i = 0; i < m; ++i) acc = acc + log_ieee(uniform());
     float rho2 = -2.0f * acc;
     if ((d + 1) & 1) {
       float z0, z1;
@@ -1247,7 +1259,7 @@ __device__ void draw_pair(int est, int d, int p, uint32_t k0, uint32_t k1,
       c[j] = wscale * (cd * (double)uj / (2.0 * (double)sigma[j]));
     }
   } else {
-    for (int j = 0; j < d; ++j) tau[j] = sqrtf(-2.0f * log_ieee(unit_open(word())));
+    for (int j = 0; j < d; ++j) tau[j] = sqrtf(-2.0f * log_ieee(uniform()));
     uint32_t bits = 0;
     for (int j = 0; j < d; ++j) {  // one sign word per 32 axes, after the radii
       if ((j & 31) == 0) bits = word();
@@ -1311,7 +1323,8 @@ __device__ __forceinline__ void combine_independent(int N, int d, const double* 
 }
 
 // One thread per antithetic pair: tau_p, weights c_p and the two parameter rows
-// (or, with PRDPT_EST_INDEPENDENT, one thread per independent draw).
+// (or, with PRDPT_EST_INDEPENDENT, one thread per independent draw, whose first
+// uniforms are stratified over the P draws with PRDPT_EST_STRATIFIED).
 __global__ void tau_kernel(int est, int d, int P, uint32_t k0, uint32_t k1,
                            const float* __restrict__ sigma, const float* __restrict__ theta,
                            double cd, double sqrt2pi, float* __restrict__ tau,
@@ -1320,10 +1333,11 @@ __global__ void tau_kernel(int est, int d, int P, uint32_t k0, uint32_t k1,
   if (p >= P) return;
   if (est & PRDPT_EST_INDEPENDENT)  // P independent draws, one parameter row each
     draw_pair(est, d, p, k0, k1, sigma, theta, cd, sqrt2pi, d, tau + (size_t)p * d,
-              c + (size_t)p * d, X + (size_t)p * d, nullptr);
+              c + (size_t)p * d, X + (size_t)p * d, nullptr,
+              (est & PRDPT_EST_STRATIFIED) ? P : 0);
   else
     draw_pair(est, d, p, k0, k1, sigma, theta, cd, sqrt2pi, d, tau + (size_t)p * d,
-              c + (size_t)p * d, X + (size_t)(2 * p) * d, X + (size_t)(2 * p + 1) * d);
+              c + (size_t)p * d, X + (size_t)(2 * p) * d, X + (size_t)(2 * p + 1) * d, 0);
 }
 
 __global__ void loss_kernel(const float* __restrict__ partial, int n_tiles, int N, double inv_den,
@@ -1376,7 +1390,7 @@ __global__ void batch_tau_kernel(const BatchReq* __restrict__ reqs, const BatchM
     const int p = g - q.pair_base;
     draw_pair(q.est, q.d, p, q.k0, q.k1, q.sigma, q.theta, q.cd, q.sqrt2pi, ld,
               tau + (size_t)g * ld, c + (size_t)g * ld, X + (size_t)(q.row_base + 2 * p) * ld,
-              X + (size_t)(q.row_base + 2 * p + 1) * ld);
+              X + (size_t)(q.row_base + 2 * p + 1) * ld, 0);
   }
 }
 

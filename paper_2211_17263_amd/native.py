@@ -20,6 +20,7 @@ PRDPT_E_ARG, PRDPT_E_NOMEM, PRDPT_E_ADMISSION, PRDPT_E_HIP = -1, -2, -3, -4
 PRDPT_E_SCENE, PRDPT_E_CANCELLED, PRDPT_E_TIMEOUT = -5, -6, -7
 PRDPT_EST_GAUSS, PRDPT_EST_IS, PRDPT_EST_IS_PERDIM = 0, 1, 2
 PRDPT_EST_INDEPENDENT = 0x100   # or-ed into a mode: no antithetic partners (noAT)
+PRDPT_EST_STRATIFIED = 0x200    # or-ed into an independent mode: stratified first uniforms
 
 # every symbol declared in include/prdpt.h
 EXPORTS = [

@@ -42,7 +42,10 @@ def to_dev(a):
 
 
 @pytest.mark.parametrize("mode", [O.GAUSS, O.IS, O.IS_PERDIM, O.IS | O.INDEPENDENT,
-                                  O.GAUSS | O.INDEPENDENT])
+                                  O.GAUSS | O.INDEPENDENT,
+                                  O.IS | O.INDEPENDENT | O.STRATIFIED,
+                                  O.GAUSS | O.INDEPENDENT | O.STRATIFIED,
+                                  O.IS_PERDIM | O.INDEPENDENT | O.STRATIFIED])
 @pytest.mark.parametrize("d", [1, 2, 3, 6, 12, 32, 33, 150, 256])
 def test_perturbation_draw_bit_exact(ctx, mode, d):
     from paper_2211_17263_amd import native as NV
@@ -95,7 +98,8 @@ def test_toy_workload_is_mode(ctx, seed):
     _full_parity(ctx, pr, seed, "toy-is", est=O.IS, N=8)
 
 
-@pytest.mark.parametrize("est", [O.GAUSS | O.INDEPENDENT, O.IS | O.INDEPENDENT])
+@pytest.mark.parametrize("est", [O.GAUSS | O.INDEPENDENT, O.IS | O.INDEPENDENT,
+                                 O.IS | O.INDEPENDENT | O.STRATIFIED])
 def test_independent_perturbations_toy(ctx, est):
     # the noAT arm: N independent draws, one render each with its own paths
     pr = S.toy_problem(seed=2)
@@ -362,7 +366,8 @@ def test_error_codes(ctx):
     ref = to_dev(np.zeros((64, 64, 3), np.float32))
     try:
         for N, sigma, est in [(3, pr["sigma"], 0), (0, pr["sigma"], 0),
-                              (4, np.array([0.5, 0.0], np.float32), 0), (4, pr["sigma"], 7)]:
+                              (4, np.array([0.5, 0.0], np.float32), 0), (4, pr["sigma"], 7),
+                              (4, pr["sigma"], NV.PRDPT_EST_IS | NV.PRDPT_EST_STRATIFIED)]:
             with pytest.raises(NV.PrdptError) as e:
                 NV.prdpt_grad_estimate(gs, ref, pr["theta0"], sigma, N, 1, est)
             assert e.value.code == NV.PRDPT_E_ARG
