@@ -343,7 +343,8 @@ def bench_inverse(args, NV):
 
 
 def bench_ablation(args, NV):
-    """Estimator ablation (Sec. 5.3: noIS, noAP, noAT) and variance study: per
+    """Estimator ablation (Sec. 5.3: noIS, noAP, noAT; stratified draws instead
+    of antithetic pairs, Sec. 3.2) and variance study: per
     estimator arm, the per-render gradient variance and bias against a
     high-precision reference gradient on the global-illumination workload and
     on the plateau scene, the renders needed for 10 % relative RMS error, and
@@ -352,8 +353,10 @@ def bench_ablation(args, NV):
     from paper_2211_17263_amd import optimize as OP
     from paper_2211_17263_amd import scenes as S
     I = NV.PRDPT_EST_INDEPENDENT
+    ST = NV.PRDPT_EST_INDEPENDENT | NV.PRDPT_EST_STRATIFIED
     arms = {"is (full)": NV.PRDPT_EST_IS, "gauss (noIS)": NV.PRDPT_EST_GAUSS,
             "is, independent (noAT)": NV.PRDPT_EST_IS | I,
+            "is, stratified instead of antithetic": NV.PRDPT_EST_IS | ST,
             "gauss, independent (noIS+noAT)": NV.PRDPT_EST_GAUSS | I,
             "is per-dimension": NV.PRDPT_EST_IS_PERDIM}
     ctx = NV.Context(0)
@@ -397,7 +400,8 @@ def bench_ablation(args, NV):
     log("ablation: optimisation on the global-illumination workload")
     gi = {}
     for name, est, warm in (("full", NV.PRDPT_EST_IS, 0.5), ("noIS", NV.PRDPT_EST_GAUSS, 0.5),
-                            ("noAP", NV.PRDPT_EST_IS, 1.0), ("noAT", NV.PRDPT_EST_IS | I, 0.5)):
+                            ("noAP", NV.PRDPT_EST_IS, 1.0), ("noAT", NV.PRDPT_EST_IS | I, 0.5),
+                            ("stratified", NV.PRDPT_EST_IS | ST, 0.5)):
         tr = OP.optimize(sc, ref, pr["theta0"], 0.125, 400, 0.01, 16, est=est, seed=args.seed,
                          warm_start=warm, theta_ref=pr["theta_ref"], eval_every=400)
         gi[name] = {"param_mse": tr.param_mse[-1], "image_mse": tr.image_mse[-1][1]}
@@ -412,7 +416,8 @@ def bench_ablation(args, NV):
     out["variance_plateau"] = study(sc, ref, th0, np.full(2, 0.5, np.float32), 4, 400, 4000)
     pl = {}
     for name, est, warm in (("full", NV.PRDPT_EST_IS, 0.5), ("noIS", NV.PRDPT_EST_GAUSS, 0.5),
-                            ("noAP", NV.PRDPT_EST_IS, 1.0), ("noAT", NV.PRDPT_EST_IS | I, 0.5)):
+                            ("noAP", NV.PRDPT_EST_IS, 1.0), ("noAT", NV.PRDPT_EST_IS | I, 0.5),
+                            ("stratified", NV.PRDPT_EST_IS | ST, 0.5)):
         r = [OP.optimize(sc, ref, th0, 0.5, 300, 0.02, 4, est=est, seed=sd, warm_start=warm,
                          theta_ref=tref).param_mse[-1] for sd in (100, 1100, 2100)]
         pl[name] = float(np.median(r))
