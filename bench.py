@@ -343,7 +343,7 @@ def bench_inverse(args, NV):
 
 
 def bench_ablation(args, NV):
-    """Estimator ablation (Sec. 5.3: noIS, noAP, noAT; stratified draws instead
+    """Estimator ablation (Sec. 4.4, Tab. 4: noIS, noAP, noAT; stratified draws instead
     of antithetic pairs, Sec. 3.2) and variance study: per
     estimator arm, the per-render gradient variance and bias against a
     high-precision reference gradient on the global-illumination workload and

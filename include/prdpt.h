@@ -65,7 +65,7 @@ extern "C" {
 #define PRDPT_EST_IS 1
 #define PRDPT_EST_IS_PERDIM 2
 /* Flag or-ed into a mode: independent perturbations without the antithetic
- * partner (the paper's noAT ablation, Sec. 5.3): the N renders are theta +
+ * partner (the paper's noAT ablation, Sec. 4.4, Tab. 4): the N renders are theta +
  * tau_i for N independent draws, each with its own path-sample stream, and
  *     grad_j = (1/N) sum_i c_ij L(theta + tau_i)
  * with the single-sample weights c_ij (twice the pair weights).  Accepted by

@@ -762,6 +762,64 @@ float orc_fresnel(float cosi, float ei, float et) {
   return 0.5f * (rs * rs + rp * rp);
 }
 
+/* Cosine-weighted direction about the unit normal n (density cos(theta)/pi on
+ * the hemisphere of n): a uniform point of the unit disc, radius sqrt(u1) and
+ * angle 2 pi u2, lifted to the hemisphere, z = sqrt(1 - u1), expressed in the
+ * orthonormal basis of n and normalised. */
+void orc_cosine_direction(const float nin[3], float u1, float u2, float out[3]) {
+  v3 n = V(nin[0], nin[1], nin[2]);
+  float r = sqrtf(u1);
+  float sn, cs;
+  orc_sincos_2pi(u2, &sn, &cs);
+  float lx = r * cs, ly = r * sn, lz = sqrtf(1.0f - u1);
+  v3 b1, b2;
+  onb(n, &b1, &b2);
+  v3 nd = vnorm(V(b1.x * lx + b2.x * ly + n.x * lz, b1.y * lx + b2.y * ly + n.y * lz,
+                  b1.z * lx + b2.z * ly + n.z * lz));
+  out[0] = nd.x; out[1] = nd.y; out[2] = nd.z;
+}
+
+/* Smooth dielectric interface of index ior (outside index 1): the ray of unit
+ * direction d meets a surface with unit geometric normal ng (pointing out of
+ * the body).  The normal is turned against d and the indices swapped when the
+ * ray leaves the body.  With probability F (exact unpolarised Fresnel; F = 1
+ * under total internal reflection), chosen by u < F, the ray is mirrored and
+ * the new origin goes to the incident side; otherwise it is refracted by
+ * Snell's law, eta_i sin(theta_i) = eta_t sin(theta_t), written in vector form
+ * t = eta d + (eta cos_i - cos_t) n with eta = eta_i / eta_t, and the origin
+ * goes to the far side.  out: the unit new direction; side: the unit normal
+ * of the side the new origin is offset to. */
+void orc_dielectric_scatter(const float din[3], const float ngin[3], float ior, float u,
+                            float out[3], float side_out[3]) {
+  v3 d = V(din[0], din[1], din[2]);
+  v3 n = V(ngin[0], ngin[1], ngin[2]);
+  float cosi = -vdot(d, n);
+  float ei = 1.0f, et = ior;
+  if (cosi < 0.0f) {
+    n = vneg(n);
+    cosi = -cosi;
+    ei = ior;
+    et = 1.0f;
+  }
+  float F = orc_fresnel(cosi, ei, et);
+  v3 nd, side;
+  if (u < F) {
+    float dn = vdot(d, n);
+    nd = V(d.x - n.x * (2.0f * dn), d.y - n.y * (2.0f * dn), d.z - n.z * (2.0f * dn));
+    side = n;
+  } else {
+    float rel = ei / et;
+    float sin2t = (rel * rel) * (1.0f - cosi * cosi);
+    float cost = sqrtf(1.0f - sin2t);
+    float kk = rel * cosi - cost;
+    nd = V(d.x * rel + n.x * kk, d.y * rel + n.y * kk, d.z * rel + n.z * kk);
+    side = vneg(n);
+  }
+  nd = vnorm(nd);
+  out[0] = nd.x; out[1] = nd.y; out[2] = nd.z;
+  side_out[0] = side.x; side_out[1] = side.y; side_out[2] = side.z;
+}
+
 static void philox_path(const uint32_t key[2], int pix, int smp, int pair, int tag, int slot,
                         int sub, uint32_t w[4]) {
   uint32_t ctr[4] = {(uint32_t)pix, (uint32_t)smp, (uint32_t)pair,
@@ -865,48 +923,18 @@ static void trace_path(const orc_scene* s, const kstate* k, const uint32_t key[2
         for (int c = 0; c < 3; ++c) L[c] = L[c] + beta[c] * f[c] * le[c] * G;
       }
       if (v == s->B) break;
-      float u1 = orc_u01(w[2]), u2 = orc_u01(w[3]);
-      float r = sqrtf(u1);
-      float sn, cs;
-      orc_sincos_2pi(u2, &sn, &cs);
-      float lx = r * cs, ly = r * sn, lz = sqrtf(1.0f - u1);
-      v3 b1, b2;
-      onb(n, &b1, &b2);
-      v3 nd = vnorm(V(b1.x * lx + b2.x * ly + n.x * lz, b1.y * lx + b2.y * ly + n.y * lz,
-                      b1.z * lx + b2.z * ly + n.z * lz));
+      float nin[3] = {n.x, n.y, n.z}, nd[3];
+      orc_cosine_direction(nin, orc_u01(w[2]), orc_u01(w[3]), nd);
       o = spawn(p, n);
-      d = nd;
+      d = V(nd[0], nd[1], nd[2]);
       for (int c = 0; c < 3; ++c) beta[c] = beta[c] * rgb[c];
       specular = 0;
     } else { /* dielectric sphere */
       if (v == s->B) break;
-      float ior = s->mat_ior[mat];
-      v3 n = ng;
-      float cosi = -vdot(d, n);
-      float ei = 1.0f, et = ior;
-      if (cosi < 0.0f) {
-        n = vneg(n);
-        cosi = -cosi;
-        ei = ior;
-        et = 1.0f;
-      }
-      float F = orc_fresnel(cosi, ei, et);
-      float u = orc_u01(w[2]);
-      v3 nd, side;
-      if (u < F) {
-        float dn = vdot(d, n);
-        nd = V(d.x - n.x * (2.0f * dn), d.y - n.y * (2.0f * dn), d.z - n.z * (2.0f * dn));
-        side = n;
-      } else {
-        float eta = ei / et;
-        float sin2t = (eta * eta) * (1.0f - cosi * cosi);
-        float cost = sqrtf(1.0f - sin2t);
-        float kk = eta * cosi - cost;
-        nd = V(d.x * eta + n.x * kk, d.y * eta + n.y * kk, d.z * eta + n.z * kk);
-        side = vneg(n);
-      }
-      o = spawn(p, side);
-      d = vnorm(nd);
+      float din[3] = {d.x, d.y, d.z}, nin[3] = {ng.x, ng.y, ng.z}, nd[3], side[3];
+      orc_dielectric_scatter(din, nin, s->mat_ior[mat], orc_u01(w[2]), nd, side);
+      o = spawn(p, V(side[0], side[1], side[2]));
+      d = V(nd[0], nd[1], nd[2]);
       specular = 1;
     }
   }

@@ -27,7 +27,7 @@ enum { ORC_BIND_SPHERE = 0, ORC_BIND_QUAD = 1, ORC_BIND_MESH = 2, ORC_BIND_PLIGH
        ORC_BIND_MESH_ROT = 5 /* mesh rotation angle (radians) about the x, y or z axis */ };
 enum { ORC_EST_GAUSS = 0, ORC_EST_IS = 1, ORC_EST_IS_PERDIM = 2 };
 /* flag or-ed into a mode: independent perturbations without the antithetic
- * partner (the paper's noAT ablation, Sec. 5.3): N draws, one render each at
+ * partner (the paper's noAT ablation, Sec. 4.4, Tab. 4): N draws, one render each at
  * theta + tau_i with its own path stream, single-sample score weights */
 enum { ORC_EST_INDEPENDENT = 0x100 };
 /* flag or-ed into an independent mode: stratified draws, the alternative to
@@ -94,8 +94,15 @@ int orc_smoothed_loss(const orc_scene* s, const float* ref, const float* theta,
 int orc_render_perturbed(const orc_scene* s, const float* theta, const float* sigma, int N,
                          uint64_t seed, int mode, int nthreads, float* images, float* tau);
 
-/* dielectric helper exposed for closed-form checks */
+/* scattering steps of the path tracer, exposed for closed-form checks:
+ * unpolarised Fresnel reflectance; the cosine-weighted diffuse direction about
+ * a unit normal from two uniforms; the dielectric interface (reflect with
+ * probability F chosen by u, else refract by Snell's law), returning the unit
+ * new direction and the normal of the side the next origin is offset to */
 float orc_fresnel(float cos_i, float eta_i, float eta_t);
+void orc_cosine_direction(const float n[3], float u1, float u2, float out[3]);
+void orc_dielectric_scatter(const float d[3], const float ng[3], float ior, float u,
+                            float out[3], float side[3]);
 
 /* optimiser helpers (host-side step of the optimisation loop) */
 double orc_sigma_schedule(double sigma0, double sigma_end, int t, int T);

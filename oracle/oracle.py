@@ -13,7 +13,9 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liboracle.so")
+# PRDPT_ORACLE_LIB names another build of oracle.c (the mutation checks of the
+# pins load deliberately broken copies this way, each in its own process)
+LIB_PATH = os.environ.get("PRDPT_ORACLE_LIB") or os.path.join(HERE, "liboracle.so")
 
 GAUSS, IS, IS_PERDIM = 0, 1, 2
 INDEPENDENT = 0x100          # or-ed into a mode: no antithetic partners (noAT)
@@ -89,6 +91,8 @@ def _declare(L):
                                        C.c_int, _f32p, _f32p]
     L.orc_fresnel.argtypes = [C.c_float, C.c_float, C.c_float]
     L.orc_fresnel.restype = C.c_float
+    L.orc_cosine_direction.argtypes = [_f32p, C.c_float, C.c_float, _f32p]
+    L.orc_dielectric_scatter.argtypes = [_f32p, _f32p, C.c_float, C.c_float, _f32p, _f32p]
     L.orc_sigma_schedule.argtypes = [C.c_double, C.c_double, C.c_int, C.c_int]
     L.orc_sigma_schedule.restype = C.c_double
     L.orc_adam_step.argtypes = [C.c_int, _f64p, _f64p, _f64p, _f64p, C.c_int, C.c_double,
@@ -129,6 +133,21 @@ def chi_mean(d):
 
 def fresnel(cos_i, eta_i, eta_t):
     return lib().orc_fresnel(float(cos_i), float(eta_i), float(eta_t))
+
+
+def cosine_direction(n, u1, u2):
+    """The renderer's cosine-weighted bounce direction about unit normal n."""
+    out = np.zeros(3, np.float32)
+    lib().orc_cosine_direction(_f32(n, 3), float(u1), float(u2), out)
+    return out
+
+
+def dielectric_scatter(d, ng, ior, u):
+    """The renderer's dielectric interface step: (new direction, offset side)."""
+    out = np.zeros(3, np.float32)
+    side = np.zeros(3, np.float32)
+    lib().orc_dielectric_scatter(_f32(d, 3), _f32(ng, 3), float(ior), float(u), out, side)
+    return out, side
 
 
 def draw_tau(mode, sigma, P, seed):

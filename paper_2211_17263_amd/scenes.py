@@ -540,3 +540,40 @@ def plane_scene(width=32, height=32, light=(0.3, -0.2, 2.0), intensity=7.0, albe
     s.quad((-50.0, -50.0, 0.0), (100.0, 0.0, 0.0), (0.0, 100.0, 0.0), m)
     s.plight(light, (intensity,) * 3)
     return s
+
+
+def area_light_plane_scene(width=8, height=8, spp=256, albedo=0.7, radiance=5.0,
+                           light=((0.9, -0.3, 1.2), (0.0, 0.6, 0.1), (0.5, 0.0, 0.2))):
+    """Lambertian plane z=0 lit by one tilted parallelogram emitter (origin,
+    edge1, edge2; it emits along edge1 x edge2, downwards) outside the camera's
+    view; pixel-centre rays, direct lighting only."""
+    s = _new_scene("area-plane", width, height, spp, 0, eye=(0.0, 0.0, 3.0), look=(0, 0, 0),
+                   pixel_center=1)
+    m = s.material(DIFFUSE, (albedo,) * 3)
+    s.quad((-10.0, -10.0, 0.0), (20.0, 0.0, 0.0), (0.0, 20.0, 0.0), m)
+    e = s.material(EMISSIVE, (radiance,) * 3)
+    s.quad(light[0], light[1], light[2], e)
+    return s
+
+
+def occluded_sky_scene(width=8, height=8, spp=2048, albedo=0.6,
+                       blocker=((-0.3, -0.8, 1.0), (1.1, 0.0, 0.0), (0.0, 1.3, 0.0))):
+    """Lambertian plane z=0 under a constant unit environment with a black
+    (albedo 0) rectangle above it; one bounce, no lights.  A camera below the
+    rectangle looks straight down, so a pixel-centre path returns the albedo
+    when its bounce escapes and 0 when the bounce meets the rectangle."""
+    s = _new_scene("occluded-sky", width, height, spp, 1, eye=(0.0, 0.0, 0.6), look=(0, 0, 0),
+                   fov=30.0, pixel_center=1, env=np.ones(3, np.float32))
+    m = s.material(DIFFUSE, (albedo,) * 3)
+    s.quad((-10.0, -10.0, 0.0), (20.0, 0.0, 0.0), (0.0, 20.0, 0.0), m)
+    k = s.material(DIFFUSE, (0.0, 0.0, 0.0))
+    s.quad(blocker[0], blocker[1], blocker[2], k)
+    return s
+
+
+def lens_scene(ior=1.5, radius=0.5):
+    """A glass sphere at the origin (for tracing rays through it)."""
+    s = _new_scene("lens", 8, 8, 1, 8, eye=(0.0, 0.0, 3.0), look=(0, 0, 0))
+    m = s.material(DIELECTRIC, ior=ior)
+    s.sphere((0.0, 0.0, 0.0), radius, m)
+    return s

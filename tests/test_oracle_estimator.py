@@ -245,7 +245,7 @@ def estimate_independent(mode, theta, sigma, N, seed, Lfun):
 @pytest.mark.parametrize("mode", [O.GAUSS, O.IS])
 @pytest.mark.parametrize("theta,a,sigma", [(0.3, 0.0, 0.5), (-0.7, 0.2, 0.25)])
 def test_independent_erf_step_1d(mode, theta, a, sigma):
-    # without antithetic partners the estimator stays unbiased (Sec. 5.3's noAT arm)
+    # without antithetic partners the estimator stays unbiased (the noAT arm of Sec. 4.4, Tab. 4)
     g, q, se, _ = estimate_independent(mode, [theta], [sigma], 80000, 23, step(a))
     truth = phi((theta - a) / sigma) / sigma
     assert abs(g[0] - truth) <= 4 * se[0], (g, truth, se)

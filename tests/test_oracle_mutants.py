@@ -1,0 +1,50 @@
+"""The renderer pins must catch plausible mistakes.  Each case below builds a
+copy of the oracle with one deliberate error (a dropped cosine, a wrong area
+factor, a wrong disc radius or height of the cosine-weighted bounce, an
+inverted index ratio or a flipped sign in the refracted direction), loads it in
+a child process and checks that the pin aimed at that step fails there.  The
+broken copies live in a temporary directory and are never used elsewhere."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+ORACLE_C = os.path.join(ROOT, "oracle", "oracle.c")
+
+MUTANTS = {
+    # next-event estimation of an area light
+    "area_light_no_cos_l": ("float G = ((cx * cl) * area) / dist2;", "float G = (cx * area) / dist2;",
+                            "tests/test_oracle_scatter.py::test_area_light_form_factor"),
+    "area_light_no_area": ("float G = ((cx * cl) * area) / dist2;", "float G = (cx * cl) / dist2;",
+                           "tests/test_oracle_scatter.py::test_area_light_form_factor"),
+    # cosine-weighted bounce
+    "bounce_disc_radius": ("float r = sqrtf(u1);", "float r = u1;",
+                           "tests/test_oracle_scatter.py::test_cosine_bounce_form_factor"),
+    "bounce_height": ("lz = sqrtf(1.0f - u1);", "lz = 1.0f - u1;",
+                      "tests/test_oracle_scatter.py::test_cosine_bounce_distribution"),
+    # refraction
+    "refract_inverted_eta": ("float rel = ei / et;", "float rel = et / ei;",
+                             "tests/test_oracle_scatter.py::test_refraction_obeys_snell"),
+    "refract_sign": ("float kk = rel * cosi - cost;", "float kk = rel * cosi + cost;",
+                     "tests/test_oracle_scatter.py::test_ball_lens_paraxial_focus"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pin_catches_mutant(name, tmp_path):
+    from oracle import build as OB
+    old, new, pin = MUTANTS[name]
+    src = open(ORACLE_C).read()
+    assert src.count(old) == 1, f"mutation site of {name} not found once"
+    mutant_c = tmp_path / "oracle_mutant.c"
+    mutant_c.write_text(src.replace(old, new))
+    lib = tmp_path / "liboracle_mutant.so"
+    subprocess.run(["gcc", *OB.FLAGS, "-I", os.path.join(ROOT, "oracle"), "-o", str(lib),
+                    str(mutant_c), "-lm"], check=True)
+    env = dict(os.environ, PRDPT_ORACLE_LIB=str(lib))
+    r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
+                        pin], cwd=ROOT, env=env, capture_output=True, text=True, timeout=300)
+    assert r.returncode == 1, f"pin {pin} did not fail on mutant {name}:\n{r.stdout[-2000:]}"
+    assert "failed" in r.stdout
