@@ -69,7 +69,7 @@ hipError_t timed_render(prdpt_ctx* ctx, const prdpt_scene* s, const float* X, in
   }
   hipError_t e = launch_render(ctx->stream, sc, W, H, X, nk, d, tag, seed, ref, img, partial, nullptr,
                                ctx->work.p, s->d_tile_order, s->d_tile_cost, crn, s->hdr.has_rot,
-                               s->hdr.n_sph, s->hdr.spp, ctx->paths.p, ctx->path_blocks);
+                               s->hdr.n_sph);
   if (e != hipSuccess) return e;
   if (a && b) {
     e = hipEventRecord(b, ctx->stream);
@@ -122,11 +122,6 @@ int prepare(prdpt_ctx* ctx, int N, int d, int n_tiles) {
   if ((rc = ensure(ctx, ctx->theta, (size_t)d))) return rc;
   if ((rc = ensure(ctx, ctx->sigma, (size_t)d))) return rc;
   if ((rc = ensure(ctx, ctx->work, 1))) return rc;
-  // one path region per resident render work-group (no spheres: the most)
-  const int blocks = render_grid_limit(0, 0);
-  if (blocks <= 0) return fail(PRDPT_E_HIP, "occupancy query failed");
-  if ((rc = ensure(ctx, ctx->paths, (size_t)blocks * kPathBufFloats))) return rc;
-  ctx->path_blocks = blocks;
   return PRDPT_OK;
 }
 
@@ -214,7 +209,7 @@ int prdpt_ctx_destroy(prdpt_ctx* ctx) {
   hipStreamSynchronize(ctx->stream);
   void* bufs[] = {ctx->X.p, ctx->tau.p, ctx->partial.p, ctx->theta.p, ctx->sigma.p,
                   ctx->c.p, ctx->losses.p, ctx->grad.p, ctx->loss.p, ctx->counters.p, ctx->work.p,
-                  ctx->paths.p, ctx->vin.p, ctx->vout.p};
+                  ctx->vin.p, ctx->vout.p};
   for (void* b : bufs)
     if (b) hipFree(b);
   if (ctx->h_vin) hipHostFree(ctx->h_vin);
@@ -577,7 +572,7 @@ int prdpt_render_perturbed(prdpt_scene* s, const float* theta, const float* sigm
   HIP_TRY(launch_render(ctx->stream, s->dev(), h.W, h.H, ctx->X.p, N, d, kTagPath, seed, nullptr,
                         images_out, nullptr, nullptr, ctx->work.p, s->d_tile_order,
                         s->d_tile_cost, (est & PRDPT_EST_INDEPENDENT) ? 0 : 1, h.has_rot,
-                        h.n_sph, h.spp, ctx->paths.p, ctx->path_blocks));
+                        h.n_sph));
   if (tau_out)
     HIP_TRY(hipMemcpyAsync(tau_out, ctx->tau.p, sizeof(float) * rows * d, hipMemcpyDeviceToHost,
                            ctx->stream));
@@ -596,7 +591,7 @@ int prdpt_render_reference(prdpt_scene* s, const float* X, uint64_t seed, float*
   HIP_TRY(hipMemcpyAsync(ctx->X.p, X, sizeof(float) * d, hipMemcpyHostToDevice, ctx->stream));
   HIP_TRY(launch_render(ctx->stream, s->dev(), h.W, h.H, ctx->X.p, 1, d, kTagRef, seed, nullptr,
                         image_out, nullptr, nullptr, ctx->work.p, s->d_tile_order,
-                        s->d_tile_cost, 1, h.has_rot, h.n_sph, h.spp, ctx->paths.p, ctx->path_blocks));
+                        s->d_tile_cost, 1, h.has_rot, h.n_sph));
   HIP_TRY(hipStreamSynchronize(ctx->stream));
   return PRDPT_OK;
 }
@@ -729,7 +724,7 @@ int prdpt_traversal_counts(prdpt_scene* s, const float* theta, const float* sigm
   HIP_TRY(launch_render(ctx->stream, s->dev(), h.W, h.H, ctx->X.p, N, d, kTagPath, seed, nullptr,
                         nullptr, nullptr, ctx->counters.p, ctx->work.p, s->d_tile_order,
                         nullptr, (est & PRDPT_EST_INDEPENDENT) ? 0 : 1, s->hdr.has_rot,
-                        s->hdr.n_sph, s->hdr.spp, ctx->paths.p, ctx->path_blocks));
+                        s->hdr.n_sph));
   unsigned long long host[8];
   HIP_TRY(hipMemcpyAsync(host, ctx->counters.p, sizeof(host), hipMemcpyDeviceToHost, ctx->stream));
   HIP_TRY(hipStreamSynchronize(ctx->stream));

@@ -20,8 +20,8 @@ namespace prdpt {
 
 void batch_release(BatchState& b) {
   if (b.exec) hipGraphExecDestroy(b.exec);
-  void* dev[] = {b.d_reqs,  b.d_meta,   b.d_tau,    b.d_c,     b.d_X,
-                 b.d_partial, b.d_paths, b.d_losses, b.d_grads, b.d_loss};
+  void* dev[] = {b.d_reqs,    b.d_meta,   b.d_tau,   b.d_c,   b.d_X,
+                 b.d_partial, b.d_losses, b.d_grads, b.d_loss};
   for (void* p : dev)
     if (p) hipFree(p);
   void* host[] = {b.h_reqs, b.h_meta, b.h_grads, b.h_loss, b.h_losses};
@@ -136,9 +136,9 @@ int check_one(prdpt_ctx* ctx, const prdpt_request& r) {
   return PRDPT_OK;
 }
 
-int launch_sequence(BatchState& b, int render_blocks, int rot, int max_sph, int max_spp) {
-  HIP_TRY(launch_batch(b.stream, b.d_reqs, b.d_meta, render_blocks, rot, max_sph, max_spp, b.d_tau,
-                       b.d_c, b.d_X, b.d_partial, b.d_losses, b.d_grads, b.d_loss, b.d_paths));
+int launch_sequence(BatchState& b, int render_blocks, int rot, int max_sph) {
+  HIP_TRY(launch_batch(b.stream, b.d_reqs, b.d_meta, render_blocks, rot, max_sph, b.d_tau,
+                       b.d_c, b.d_X, b.d_partial, b.d_losses, b.d_grads, b.d_loss));
   return PRDPT_OK;
 }
 
@@ -217,24 +217,12 @@ int batch_enqueue(prdpt_ctx* ctx, BatchState& b, prdpt_request* reqs, int n, std
   m.total_rows = row_base;
   m.tiles_per_item = tpi;
   const int render_blocks = std::max(1, b.n_cu * b.blocks_per_cu);
-  if ((size_t)render_blocks > b.cap_path_blocks) {  // one path region per work-group
-    HIP_TRY(hipStreamSynchronize(b.stream));
-    size_t dummy = 0;
-    if (int rc = grow_dev(b.d_paths, dummy, (size_t)render_blocks * kPathBufFloats)) return rc;
-    b.cap_path_blocks = (size_t)render_blocks;
-    if (b.exec) {
-      HIP_TRY(hipGraphExecDestroy(b.exec));
-      b.exec = nullptr;
-    }
-  }
   int rot = 0;  // the render variant that applies instance rotations
-  int max_sph = 0, max_spp = 0;
+  int max_sph = 0;
   for (int i : ok) {
     rot |= reqs[i].scene->hdr.has_rot;
     max_sph = std::max(max_sph, reqs[i].scene->hdr.n_sph);
-    max_spp = std::max(max_spp, reqs[i].scene->hdr.spp);
   }
-  const int chunked = max_spp > kSampleChunk ? 1 : 0;
   // order after earlier work on the context stream (e.g. reference uploads)
   HIP_TRY(hipEventRecord(b.ready, ctx->stream));
   HIP_TRY(hipStreamWaitEvent(b.stream, b.ready, 0));
@@ -242,15 +230,14 @@ int batch_enqueue(prdpt_ctx* ctx, BatchState& b, prdpt_request* reqs, int n, std
   HIP_TRY(hipMemcpyAsync(b.d_meta, b.h_meta, sizeof(BatchMeta), hipMemcpyHostToDevice, b.stream));
   if (t0) HIP_TRY(hipEventRecord(t0, b.stream));
   if (b.use_graph) {
-    if (b.exec && (b.graph_blocks != render_blocks || b.graph_rot != rot || b.graph_sph != max_sph ||
-                   b.graph_chunked != chunked)) {
+    if (b.exec && (b.graph_blocks != render_blocks || b.graph_rot != rot || b.graph_sph != max_sph)) {
       HIP_TRY(hipGraphExecDestroy(b.exec));
       b.exec = nullptr;
     }
     if (!b.exec) {
       hipGraph_t g = nullptr;
       HIP_TRY(hipStreamBeginCapture(b.stream, hipStreamCaptureModeThreadLocal));
-      const int rc = launch_sequence(b, render_blocks, rot, max_sph, max_spp);
+      const int rc = launch_sequence(b, render_blocks, rot, max_sph);
       hipError_t e = hipStreamEndCapture(b.stream, &g);
       if (rc) return rc;
       if (e != hipSuccess) return fail(PRDPT_E_HIP, std::string("graph capture: ") + hipGetErrorString(e));
@@ -263,11 +250,10 @@ int batch_enqueue(prdpt_ctx* ctx, BatchState& b, prdpt_request* reqs, int n, std
       b.graph_blocks = render_blocks;
       b.graph_rot = rot;
       b.graph_sph = max_sph;
-      b.graph_chunked = chunked;
     }
     HIP_TRY(hipGraphLaunch(b.exec, b.stream));
   } else {
-    if (int rc = launch_sequence(b, render_blocks, rot, max_sph, max_spp)) return rc;
+    if (int rc = launch_sequence(b, render_blocks, rot, max_sph)) return rc;
   }
   if (t1) HIP_TRY(hipEventRecord(t1, b.stream));
   HIP_TRY(hipMemcpyAsync(b.h_grads, b.d_grads, sizeof(double) * PRDPT_BATCH_MAX_PARAMS * ok.size(),

@@ -19,8 +19,7 @@ hipError_t launch_tau(hipStream_t st, int est, int d, int P, uint64_t seed, cons
 hipError_t launch_render(hipStream_t st, const DevScene& sc, int W, int H, const float* X, int nk,
                          int d, int tag, uint64_t seed, const float* ref, float* img,
                          float* partial, unsigned long long* counters, int* work,
-                         const int* order, float* cost, int crn, int rot, int n_sph, int spp,
-                         float* pbuf, int pbuf_blocks);
+                         const int* order, float* cost, int crn, int rot, int n_sph);
 // resident render work-groups for a variant and sphere count (the grid bound)
 int render_grid_limit(int rot, int n_sph);
 // Rz(c) Ry(b) Rx(a) of the angles (a, b, c), row-major (the kernels' own formula)
@@ -38,8 +37,8 @@ hipError_t launch_combine(hipStream_t st, int rows, int d, int independent, cons
 // rot != 0: some request's scene has rotated instances; max_sph: the largest
 // sphere count of the batch's scenes (sizes the render kernel's dynamic LDS)
 hipError_t launch_batch(hipStream_t st, const BatchReq* reqs, BatchMeta* meta, int render_blocks,
-                        int rot, int max_sph, int max_spp, float* tau, double* c, float* X,
-                        float* partial, double* losses, double* grads, double* loss, float* pbuf);
+                        int rot, int max_sph, float* tau, double* c, float* X,
+                        float* partial, double* losses, double* grads, double* loss);
 hipError_t launch_copy(hipStream_t st, const void* src, void* dst, size_t n16);
 
 // records `msg` as the calling thread's last error and returns `code`
@@ -72,8 +71,6 @@ struct BatchState {
   double* d_c = nullptr;
   float* d_X = nullptr;
   float* d_partial = nullptr;
-  float* d_paths = nullptr;        // per-work-group path radiance (kPathBufFloats each)
-  size_t cap_path_blocks = 0;
   double* d_losses = nullptr;
   double* d_grads = nullptr;
   double* d_loss = nullptr;
@@ -86,7 +83,6 @@ struct BatchState {
   int graph_blocks = 0;
   int graph_rot = 0;  // render variant captured in the graph
   int graph_sph = 0;  // sphere count its dynamic LDS was sized for
-  int graph_chunked = 0;  // samples rendered in chunks (spp above kSampleChunk)
 };
 
 void batch_release(BatchState& b);
@@ -125,8 +121,6 @@ struct prdpt_ctx {
   prdpt::DevBuf<double> c, losses, grad, loss;
   prdpt::DevBuf<unsigned long long> counters;
   prdpt::DevBuf<int> work;  // work counter of the persistent render kernel
-  prdpt::DevBuf<float> paths;  // per-work-group path radiance of a sample chunk
-  int path_blocks = 0;         // work-group regions in `paths`
   // the synchronous estimate's inputs [theta | sigma] and outputs
   // [grad | loss | losses], each moved by one copy through pinned host memory
   prdpt::DevBuf<float> vin;

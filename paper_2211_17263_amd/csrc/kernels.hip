@@ -215,6 +215,14 @@ struct LeafLds {
   uint8_t owner[kBlock * kLeafMax];
 };
 static_assert(kBlock == 64, "the leaf phase spreads pairs over one wave");
+static_assert(sizeof(uint8_t) * kBlock * kLeafMax >= sizeof(uint32_t) * kBlock,
+              "the deposit claims reuse the leaf phase's owner table");
+
+// LDS of a tile's pixel sums: the radiance of each finished path is added to
+// its pixel's entry (tile pixel slot q = x + 8 y).
+struct PixLds {
+  float rgb[3][kBlock];
+};
 static_assert(kLeafMax <= 7, "leaf counts are added up from three ballots");
 
 // Work counters of the instrumented kernel copy: lane-level work (nodes,
@@ -719,13 +727,15 @@ __device__ __forceinline__ void load_state(SceneLds& S, float* __restrict__ sph,
 // the current vertex, or one next-event shadow ray.  A lane whose path ends
 // takes the next job in the same iteration, so lanes neither wait for the
 // longest path of the wave nor for the slowest pixel of the tile, and every
-// iteration runs the same traversal code.  A path's radiance goes to its slot
-// of the work-group's path buffer pbuf ([sample][pixel][rgb], kSampleChunk
-// samples at a time); at the end of a chunk lane t adds pixel t's samples in
-// sample order.  Per sample the radiance terms are added in the same order as
-// a recursive implementation (vertex by vertex; point lights, then area
-// lights).
-template <bool COUNT, bool ROT, bool CHUNKED>
+// iteration runs the same traversal code.  A finished path adds its radiance
+// to its pixel's sum in LDS (pix); when several lanes finish paths of the same
+// pixel in one iteration, the lowest lane adds first (each round, an atomic
+// minimum over the lane ids elects one lane per pixel).  The wave's execution
+// is a function of its inputs alone, so the order of every pixel's additions,
+// and the sum, are reproducible, and nothing per path goes to device memory.
+// Per sample the radiance terms are added in the same order as a recursive
+// implementation (vertex by vertex; point lights, then area lights).
+template <bool COUNT, bool ROT>
 __device__ __forceinline__ void render_tile(const SceneLds& S, const float* __restrict__ sph,
                                             const int* __restrict__ sph_mat,
                                             const Node* __restrict__ nodes,
@@ -736,9 +746,8 @@ __device__ __forceinline__ void render_tile(const SceneLds& S, const float* __re
                                             float* __restrict__ img, float* partial_slot,
                                             unsigned long long* __restrict__ counters,
                                             int* __restrict__ stack, float* __restrict__ wsum,
-                                            int crn, float* __restrict__ pbuf,
-                                            volatile int* __restrict__ next_job,
-                                            LeafLds* __restrict__ lf) {
+                                            int crn, volatile int* __restrict__ next_job,
+                                            LeafLds* __restrict__ lf, PixLds* __restrict__ pix_sum) {
   const int tiles_x = (S.W + kTileW - 1) / kTileW;
   const int t = threadIdx.x;
   const int tx0 = (tile % tiles_x) * kTileW, ty0 = (tile / tiles_x) * kTileH;
@@ -758,7 +767,6 @@ __device__ __forceinline__ void render_tile(const SceneLds& S, const float* __re
   int ovf[kStackOverflow];  // stack entries beyond the LDS part (deep descents only)
   Counters cnt{0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
 
-  float acc0 = 0.0f, acc1 = 0.0f, acc2 = 0.0f;
   // path state
   V3 o = mk(0.0f, 0.0f, 0.0f), dir = o, p = o, n = o;
   float tmax = __builtin_huge_valf();
@@ -768,23 +776,21 @@ __device__ __forceinline__ void render_tile(const SceneLds& S, const float* __re
   int v = 0, mat = 0, light = -1;          // light >= 0: next-event stage of a diffuse vertex
   uint4 w = make_uint4(0u, 0u, 0u, 0u);
 
-  // the path in flight, as its slot in the chunk's buffer: sample
-  // c_first + (jslot >> 6) of the tile pixel (jslot & 7, (jslot >> 3) & 7);
-  // -1 when the lane has none
+  // the path in flight: sample jslot >> 6 of the tile pixel (jslot & 7,
+  // (jslot >> 3) & 7), whose sum is pix_sum entry jslot & 63; -1 when the lane
+  // has none
   int jslot = -1;
   bool tracing = false;   // a query is in flight (possibly suspended)
   bool answered = false;  // the last query's result (tr.h) is still to be used
   Trav tr;
-  // chunks of samples [c_first, c_first + n_chunk) of the tile's pixels (one
-  // chunk of all spp samples unless CHUNKED)
-  const int n_chunks = CHUNKED ? (spp + kSampleChunk - 1) / kSampleChunk : 1;
-  for (int ci = 0; ci < n_chunks; ++ci) {
-  const int c_first = CHUNKED ? ci * kSampleChunk : 0;
-  const int n_chunk = CHUNKED ? min(spp - c_first, kSampleChunk) : spp;
   // image pixel index and sample of the path in flight
   auto path_pix = [&]() { return (ty0 + ((jslot >> 3) & 7)) * S.W + tx0 + (jslot & 7); };
-  auto path_smp = [&]() { return c_first + (jslot >> 6); };
-  const int n_jobs = nv * n_chunk;
+  auto path_smp = [&]() { return jslot >> 6; };
+  const int n_jobs = nv * spp;
+  uint32_t* const claim = reinterpret_cast<uint32_t*>(lf->owner);
+  pix_sum->rgb[0][t] = 0.0f;
+  pix_sum->rgb[1][t] = 0.0f;
+  pix_sum->rgb[2][t] = 0.0f;
   if (t == 0) *next_job = 0;
   __syncthreads();
   while (true) {
@@ -966,22 +972,39 @@ __device__ __forceinline__ void render_tile(const SceneLds& S, const float* __re
             }
           }
         }
-        if (end_path) {
-          float* slot = pbuf + (size_t)jslot * 3;
-          slot[0] = L0;
-          slot[1] = L1;
-          slot[2] = L2;
-          jslot = -1;
+        // finished paths add their radiance to their pixels' sums; lanes with
+        // the same pixel take turns, lowest lane first
+        const int q = jslot & (kBlock - 1);
+        bool deposit = end_path;
+        while (__ballot(deposit) != 0ull) {
+          if (deposit) claim[q] = 0xffffffffu;
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+          if (deposit) atomicMin(&claim[q], (uint32_t)t);
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+          if (deposit && claim[q] == (uint32_t)t) {
+            pix_sum->rgb[0][q] = pix_sum->rgb[0][q] + L0;
+            pix_sum->rgb[1][q] = pix_sum->rgb[1][q] + L1;
+            pix_sum->rgb[2][q] = pix_sum->rgb[2][q] + L2;
+            deposit = false;
+          }
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
+        if (end_path) jslot = -1;
       }
-      if (jslot < 0) {  // the lanes without a path take the chunk's next jobs in order
+      if (jslot < 0) {  // the lanes without a path take the tile's next jobs in order
         const unsigned long long m = __ballot(1);
         const int rank = (int)__builtin_amdgcn_mbcnt_hi(
             (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
         const int base = *next_job;
         const int j = base + rank;
         if (rank == 0) *next_job = base + __popcll(m);
-        if (j >= n_jobs) break;  // this lane is done with the chunk
+        if (j >= n_jobs) break;  // this lane is done with the tile
         const int q = nv == kBlock ? (j & (kBlock - 1)) : j % nv;
         const int sj = nv == kBlock ? (j >> 6) : j / nv;
         const int qx = tw == kTileW ? (q & (kTileW - 1)) : q % tw;
@@ -1027,24 +1050,13 @@ __device__ __forceinline__ void render_tile(const SceneLds& S, const float* __re
                                           ovf, lf, PRDPT_TRACE_BUDGET, cnt);
     answered = !tracing;
   }
-  // every path of the chunk is done: each lane adds its pixel's samples in
-  // sample order
+  // every path of the tile is done: lane t reads pixel t's sum
   __syncthreads();
-  if (valid) {
-    for (int sj = 0; sj < n_chunk; ++sj) {
-      const float* slot = pbuf + (size_t)(sj * kBlock + t) * 3;
-      acc0 = acc0 + slot[0];
-      acc1 = acc1 + slot[1];
-      acc2 = acc2 + slot[2];
-    }
-  }
-  __syncthreads();
-  }
-
   float e = 0.0f;
   if (valid) {
     const float inv_spp = 1.0f / (float)spp;
-    const float I0 = acc0 * inv_spp, I1 = acc1 * inv_spp, I2 = acc2 * inv_spp;
+    const float I0 = pix_sum->rgb[0][t] * inv_spp, I1 = pix_sum->rgb[1][t] * inv_spp,
+                I2 = pix_sum->rgb[2][t] * inv_spp;
     const size_t npix = (size_t)S.W * S.H;
     if (img) {
       float* op = img + ((size_t)k * npix + pix) * 3;
@@ -1094,19 +1106,19 @@ __device__ __forceinline__ void render_tile(const SceneLds& S, const float* __re
 // tiles by cost for the next launch puts the cheapest tiles last and shortens
 // the tail where few work-groups are still busy.  Outputs do not depend on
 // the order.
-template <bool COUNT, bool ROT, bool CHUNKED>
+template <bool COUNT, bool ROT>
 __global__ __launch_bounds__(kBlock, PRDPT_MIN_WAVES_PER_EU) void render_loss_kernel(
     DevScene scene, const float* __restrict__ X, int d, int tag, uint32_t k0, uint32_t k1,
     const float* __restrict__ ref, float* __restrict__ img, float* __restrict__ partial,
     unsigned long long* __restrict__ counters, int n_tiles, int n_items, int* __restrict__ work,
-    const int* __restrict__ order, float* __restrict__ cost, int crn, float* __restrict__ pbuf) {
+    const int* __restrict__ order, float* __restrict__ cost, int crn) {
   __shared__ SceneLds S;
   __shared__ int stack[kStackEntries * kBlock];
   __shared__ float wsum[kBlock / 64];
   __shared__ int s_item;
   __shared__ int s_job;
   __shared__ LeafLds s_leaf;
-  float* const my_paths = pbuf + (size_t)blockIdx.x * kPathBufFloats;
+  __shared__ PixLds s_pix;
   extern __shared__ float sph[];  // sphere_lds_bytes(n_sph) at launch
   int* sph_mat = reinterpret_cast<int*>(sph + 4 * scene.hdr->n_sph);
   int cur = -1;
@@ -1125,10 +1137,10 @@ __global__ __launch_bounds__(kBlock, PRDPT_MIN_WAVES_PER_EU) void render_loss_ke
     }
     unsigned long long t0 = 0;
     if (cost && threadIdx.x == 0) t0 = wall_clock64();
-    render_tile<COUNT, ROT, CHUNKED>(S, sph, sph_mat, scene.nodes, scene.tris, scene.tri_slot, k, tile,
+    render_tile<COUNT, ROT>(S, sph, sph_mat, scene.nodes, scene.tris, scene.tri_slot, k, tile,
                        tag, k0, k1, ref, img,
                        partial ? partial + (size_t)k * n_tiles + tile : nullptr, counters, stack,
-                       wsum, crn, my_paths, &s_job, &s_leaf);
+                       wsum, crn, &s_job, &s_leaf, &s_pix);
     if (cost && threadIdx.x == 0) cost[tile] = (float)(wall_clock64() - t0);
     __syncthreads();
   }
@@ -1397,17 +1409,17 @@ __global__ void batch_tau_kernel(const BatchReq* __restrict__ reqs, const BatchM
 // Persistent render: work-groups take (request, perturbation, run of tiles)
 // items from one counter until the batch is exhausted; each tile writes its own
 // partial slot, so the order in which items are taken does not matter.
-template <bool ROT, bool CHUNKED>
+template <bool ROT>
 __global__ __launch_bounds__(kBlock, PRDPT_MIN_WAVES_PER_EU) void batch_render_kernel(
     const BatchReq* __restrict__ reqs, BatchMeta* __restrict__ meta, const float* __restrict__ X,
-    float* __restrict__ partial, float* __restrict__ pbuf) {
+    float* __restrict__ partial) {
   __shared__ SceneLds S;
   __shared__ int stack[kStackEntries * kBlock];
   __shared__ float wsum[kBlock / 64];
   __shared__ int s_item;
   __shared__ int s_job;
   __shared__ LeafLds s_leaf;
-  float* const my_paths = pbuf + (size_t)blockIdx.x * kPathBufFloats;
+  __shared__ PixLds s_pix;
   extern __shared__ float sph[];  // sphere_lds_bytes(largest n_sph of the batch) at launch
   const int total = meta->total_items, n = meta->n_req, tpi = meta->tiles_per_item;
   while (true) {
@@ -1426,10 +1438,10 @@ __global__ __launch_bounds__(kBlock, PRDPT_MIN_WAVES_PER_EU) void batch_render_k
     load_state(S, sph, sph_mat, q.scene.hdr, X + (size_t)(q.row_base + k) * PRDPT_BATCH_MAX_PARAMS,
                q.d);
     for (int tile = first; tile < last; ++tile) {
-      render_tile<false, ROT, CHUNKED>(S, sph, sph_mat, q.scene.nodes, q.scene.tris, q.scene.tri_slot, k,
+      render_tile<false, ROT>(S, sph, sph_mat, q.scene.nodes, q.scene.tris, q.scene.tri_slot, k,
                          tile, kTagPath, q.k0, q.k1, q.ref,
                          nullptr, partial + (size_t)q.partial_base + (size_t)k * q.n_tiles + tile,
-                         nullptr, stack, wsum, 1, my_paths, &s_job, &s_leaf);
+                         nullptr, stack, wsum, 1, &s_job, &s_leaf, &s_pix);
       __syncthreads();
     }
   }
@@ -1498,9 +1510,9 @@ int render_grid_limit(int rot, int n_sph) {
   if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
   const size_t lds = (size_t)sphere_lds_bytes(n_sph);
   const hipError_t e = rot ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                                 &per_cu, render_loss_kernel<false, true, false>, kBlock, lds)
+                                 &per_cu, render_loss_kernel<false, true>, kBlock, lds)
                            : hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                                 &per_cu, render_loss_kernel<false, false, false>, kBlock, lds);
+                                 &per_cu, render_loss_kernel<false, false>, kBlock, lds);
   if (e != hipSuccess) return 0;
   slot = std::max(1, n_cu * std::max(1, per_cu));
   return slot;
@@ -1531,37 +1543,26 @@ void quad_frame_host(const float* q, float* n, float* nu) {
 hipError_t launch_render(hipStream_t st, const DevScene& sc, int W, int H, const float* X, int nk,
                          int d, int tag, uint64_t seed, const float* ref, float* img,
                          float* partial, unsigned long long* counters, int* work,
-                         const int* order, float* cost, int crn, int rot, int n_sph,
-                         int spp, float* pbuf, int pbuf_blocks) {
+                         const int* order, float* cost, int crn, int rot, int n_sph) {
   const int n_tiles = render_tiles(W, H);
-  const int n_items = n_tiles * nk;
+  const long long n_items = (long long)n_tiles * nk;
+  if (n_items >= (1ll << 31)) return hipErrorInvalidValue;  // the work counter is an int
   const int limit = render_grid_limit(rot, n_sph);
-  if (limit <= 0 || pbuf_blocks <= 0) return hipErrorInvalidDevice;
+  if (limit <= 0) return hipErrorInvalidDevice;
   const size_t lds = (size_t)sphere_lds_bytes(n_sph);
-  const int blocks = std::min(std::min(n_items, limit), pbuf_blocks);
+  const int blocks = (int)std::min<long long>(n_items, limit);
   hipLaunchKernelGGL(reset_work_kernel, dim3(1), dim3(64), 0, st, work);
   const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
-#define PRDPT_RENDER(C, R, K)                                                                    \
-  hipLaunchKernelGGL((render_loss_kernel<C, R, K>), dim3(blocks), dim3(kBlock), lds, st, sc, X, d,  \
-                     tag, k0, k1, ref, img, partial, counters, n_tiles, n_items, work, order, cost,  \
-                     crn, pbuf)
-  const bool chunked = spp > kSampleChunk;
+#define PRDPT_RENDER(C, R)                                                                       \
+  hipLaunchKernelGGL((render_loss_kernel<C, R>), dim3(blocks), dim3(kBlock), lds, st, sc, X, d,  \
+                     tag, k0, k1, ref, img, partial, counters, n_tiles, (int)n_items, work, order, \
+                     cost, crn)
   if (counters) {
-    if (rot) {
-      if (chunked) PRDPT_RENDER(true, true, true);
-      else PRDPT_RENDER(true, true, false);
-    } else {
-      if (chunked) PRDPT_RENDER(true, false, true);
-      else PRDPT_RENDER(true, false, false);
-    }
+    if (rot) PRDPT_RENDER(true, true);
+    else PRDPT_RENDER(true, false);
   } else {
-    if (rot) {
-      if (chunked) PRDPT_RENDER(false, true, true);
-      else PRDPT_RENDER(false, true, false);
-    } else {
-      if (chunked) PRDPT_RENDER(false, false, true);
-      else PRDPT_RENDER(false, false, false);
-    }
+    if (rot) PRDPT_RENDER(false, true);
+    else PRDPT_RENDER(false, false);
   }
 #undef PRDPT_RENDER
   return hipGetLastError();
@@ -1591,23 +1592,17 @@ hipError_t launch_combine(hipStream_t st, int rows, int d, int independent, cons
 // content (totals are read from the device-side meta), so it can be captured
 // once in a graph and replayed for every batch.
 hipError_t launch_batch(hipStream_t st, const BatchReq* reqs, BatchMeta* meta, int render_blocks,
-                        int rot, int max_sph, int max_spp, float* tau, double* c, float* X,
-                        float* partial, double* losses, double* grads, double* loss, float* pbuf) {
+                        int rot, int max_sph, float* tau, double* c, float* X,
+                        float* partial, double* losses, double* grads, double* loss) {
   const size_t lds = (size_t)sphere_lds_bytes(max_sph);
   hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, st, meta);
   hipLaunchKernelGGL(batch_tau_kernel, dim3(64), dim3(64), 0, st, reqs, meta, tau, c, X);
-#define PRDPT_BATCH_RENDER(R, K)                                                                \
-  hipLaunchKernelGGL((batch_render_kernel<R, K>), dim3(render_blocks), dim3(kBlock), lds, st, reqs, \
-                     meta, X, partial, pbuf)
-  const bool chunked = max_spp > kSampleChunk;
-  if (rot) {
-    if (chunked) PRDPT_BATCH_RENDER(true, true);
-    else PRDPT_BATCH_RENDER(true, false);
-  } else {
-    if (chunked) PRDPT_BATCH_RENDER(false, true);
-    else PRDPT_BATCH_RENDER(false, false);
-  }
-#undef PRDPT_BATCH_RENDER
+  if (rot)
+    hipLaunchKernelGGL((batch_render_kernel<true>), dim3(render_blocks), dim3(kBlock), lds, st, reqs,
+                       meta, X, partial);
+  else
+    hipLaunchKernelGGL((batch_render_kernel<false>), dim3(render_blocks), dim3(kBlock), lds, st, reqs,
+                       meta, X, partial);
   hipLaunchKernelGGL(batch_loss_kernel, dim3(1024), dim3(64), 0, st, reqs, meta, partial, losses);
   hipLaunchKernelGGL(batch_combine_kernel, dim3(256), dim3(64), 0, st, reqs, meta, c, losses,
                      grads, loss);

@@ -20,7 +20,7 @@ constexpr int kMaxDepth4 = (kMaxInnerDepth + 1) / 2;
 // small per-lane private array that only unusually deep descents reach.
 constexpr int kStackBound = 3 * kMaxDepth4 + 1;
 #ifndef PRDPT_STACK_LDS
-#define PRDPT_STACK_LDS 26
+#define PRDPT_STACK_LDS 23
 #endif
 constexpr int kStackEntries = PRDPT_STACK_LDS;
 constexpr int kStackOverflow = kStackBound - kStackEntries;
@@ -92,13 +92,6 @@ struct SceneHdr : SceneLds {
   int32_t bind_index[PRDPT_MAX_PARAMS];      // instance index for meshes
   int32_t bind_comp[PRDPT_MAX_PARAMS];
 };
-
-// Paths of a tile are rendered in chunks of kSampleChunk samples per pixel;
-// each render work-group keeps the radiance of its chunk's paths in its own
-// region of kPathBufFloats floats ([sample][pixel][rgb]) until the pixels add
-// them up in sample order.
-constexpr int kSampleChunk = 64;
-constexpr int kPathBufFloats = 64 * kSampleChunk * 3;
 
 // Dynamic LDS of a render work-group: n_sph spheres (centre, radius) and their
 // materials.
