@@ -73,11 +73,14 @@ extern "C" {
 #define PRDPT_EST_INDEPENDENT 0x100
 /* Flag or-ed into an independent mode (PRDPT_EST_INDEPENDENT must be set):
  * stratified draws, the alternative to antithetic pairs that Sec. 3.2
- * mentions.  The first uniform of draw i of the N draws is moved into stratum
- * i, (i + u) / N (binary32, kept below 1), which stratifies the radius of the
- * IS and IS_PERDIM samplers and the first Box-Muller radius of GAUSS; weights
- * and renders are those of the independent draws.  Accepted by the
- * single-request calls; the batched and served forms reject it. */
+ * mentions.  Only the first uniform of draw i of the N draws is moved into
+ * stratum i, (i + u) / N (binary32, kept below 1).  For d = 1 that stratifies
+ * the IS radius (the whole draw up to its sign); for IS with d > 1 it is one
+ * of the (d + 1) / 2 log-uniform terms of the squared radius and the
+ * direction is not stratified; for IS_PERDIM it is axis 0's radius; for GAUSS
+ * the first Box-Muller radius.  Weights and renders are those of the
+ * independent draws.  Accepted by the single-request calls; the batched and
+ * served forms reject it. */
 #define PRDPT_EST_STRATIFIED 0x200
 
 /* ---- scene description ---------------------------------------------------- */
@@ -161,8 +164,8 @@ const char* prdpt_last_error(void);
  * sum of resident scene footprints in bytes (0 = unbounded): scene creation
  * beyond it fails with PRDPT_E_ADMISSION.  Scratch that the context allocates
  * on first use and keeps until it is destroyed is not counted: per-estimate
- * arrays (O(N d + N tiles)) and a path buffer of 48 KB per resident render
- * work-group (~200 MB on a 256-CU device, allocated with 50 % slack).
+ * arrays of O(N d + N tiles) elements (N tiles: 4 bytes per perturbation and
+ * 8x8 pixel tile), allocated with 50 % slack.
  */
 int prdpt_ctx_create(int device, void* stream, size_t hbm_budget, prdpt_ctx** out);
 /* Synchronise and release the context's own memory (scenes must be destroyed first). */
@@ -173,10 +176,13 @@ int prdpt_ctx_set_stream(prdpt_ctx* ctx, void* stream);
 int prdpt_ctx_resident_bytes(prdpt_ctx* ctx, size_t* bytes);
 
 /*
- * Validate and copy a scene, build its BVHs on the host (binned SAH, 4-wide
- * 128-byte nodes, 48-byte triangles and a 4-byte id-to-position entry per
- * triangle), upload them, and return a handle that stays resident in HBM until
- * prdpt_scene_destroy.  *footprint_bytes (nullable)
+ * The scene handle stands for the function P of Alg. 1 (Sec. 3.4): the scene
+ * whose image the renderer computes for parameters theta, the pixel integral of
+ * Sec. 2.1 (Eq. 1-3), here with the parameter bindings that map theta onto the
+ * scene.  Validate and copy a scene, build its BVHs on the host (binned SAH,
+ * 4-wide 128-byte nodes, 48-byte triangles and a 4-byte id-to-position entry
+ * per triangle), upload them, and return a handle that stays resident in HBM
+ * until prdpt_scene_destroy.  *footprint_bytes (nullable)
  * receives the device bytes held.  Errors: PRDPT_E_ARG (null), PRDPT_E_SCENE
  * (limits, indices, material rules), PRDPT_E_ADMISSION, PRDPT_E_NOMEM.
  */
@@ -252,7 +258,8 @@ int prdpt_grad_estimate_async(prdpt_scene* scene, const float* ref_dev, const fl
  * with rows = P pairs, or, with PRDPT_EST_INDEPENDENT in est,
  *     grad_dev[j] = scale * (1/N) sum_i c_dev[i][j] losses_dev[i]
  * with rows = N draws; scale = *scale_dev (device double, NULL means 1).  All
- * pointers device.
+ * pointers device.  1 <= d <= PRDPT_MAX_PARAMS, 1 <= rows <= 2^20, else
+ * PRDPT_E_ARG.
  */
 int prdpt_combine_async(prdpt_ctx* ctx, int rows, int d, const double* c_dev,
                         const double* losses_dev, const double* scale_dev, double* grad_dev,
@@ -353,16 +360,36 @@ int prdpt_server_add_job(prdpt_server* sv, const prdpt_scene_desc* desc, const f
 /* Queue one gradient estimate of job `job_id` (theta, sigma: host float[d], copied). */
 int prdpt_server_submit(prdpt_server* sv, int job_id, const float* theta, const float* sigma, int N,
                         uint64_t seed, int est, int64_t* ticket);
+/* As prdpt_server_submit, with a deadline timeout_s seconds after submission
+ * (0: none; negative or non-finite: PRDPT_E_ARG).  A request still queued or
+ * running when its deadline passes completes at once with PRDPT_E_TIMEOUT (a
+ * running one's result is dropped when its epoch ends); the other requests,
+ * of its epoch too, are not affected. */
+int prdpt_server_submit_deadline(prdpt_server* sv, int job_id, const float* theta,
+                                 const float* sigma, int N, uint64_t seed, int est,
+                                 double timeout_s, int64_t* ticket);
 /* Cancel a queued request (it completes with PRDPT_E_CANCELLED unless already running). */
 int prdpt_server_cancel(prdpt_server* sv, int64_t ticket);
 /* Take up to max completion records, waiting up to timeout_ms for the first. */
 int prdpt_server_poll(prdpt_server* sv, prdpt_completion* out, int max, int timeout_ms, int* n_out);
 int prdpt_server_get_stats(prdpt_server* sv, prdpt_server_stats* stats);
-/* Finish all queued and running requests, then release everything. */
+/* Finish all queued and running requests (queued requests that can no longer
+ * start complete with PRDPT_E_CANCELLED), then release everything.  A job
+ * whose upload fails (device memory, the context's budget, HIP) fails its
+ * requests with that status instead of holding the queue. */
 int prdpt_server_stop(prdpt_server* sv);
 
 /* Wait for all work enqueued on the context's stream. */
 int prdpt_ctx_synchronize(prdpt_ctx* ctx);
+
+/*
+ * Failure injection for tests of the error paths (process-wide): with
+ * after >= 0 the next `after` device or pinned host allocations of the library
+ * succeed and every later one fails, so the call that needs it returns
+ * PRDPT_E_NOMEM (the server fails that request) and frees what it took;
+ * after < 0 turns injection off.  Always PRDPT_OK.
+ */
+int prdpt_debug_fail_allocations(int64_t after);
 
 /*
  * Measurement hooks.  With timing enabled the context records a pair of HIP
@@ -381,7 +408,9 @@ int prdpt_ctx_read_timing(prdpt_ctx* ctx, double* total_ms, int64_t* launches);
  * iterations of the ray loop executed per wavefront (summed over wavefronts;
  * lane work / (64 x iterations) is each loop's SIMD efficiency), counts[7]
  * lanes idle in ray-loop iterations because their tile has no path left for
- * them (summed over iterations).  counts: host uint64_t[8].  Synchronous.
+ * them (summed over iterations), counts[8] traversal-stack pushes that went to
+ * the private part beyond the LDS entries, counts[9] the most stack entries
+ * one ray held at once.  counts: host uint64_t[10].  Synchronous.
  */
 int prdpt_traversal_counts(prdpt_scene* scene, const float* theta, const float* sigma, int N,
                            uint64_t seed, int est, uint64_t* counts);

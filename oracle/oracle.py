@@ -25,6 +25,15 @@ TAG_TAU, TAG_PATH, TAG_REF = 1, 2, 3
 _lib = None
 
 
+def use_library(path):
+    """Load the oracle from another build of oracle.c (e.g. the host-tuned one
+    the benchmark times); only before the oracle has been used."""
+    global LIB_PATH
+    if _lib is not None and path != LIB_PATH:
+        raise RuntimeError("the oracle library is already loaded")
+    LIB_PATH = path
+
+
 def lib():
     global _lib
     if _lib is None:

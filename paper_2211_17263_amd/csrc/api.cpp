@@ -1,6 +1,7 @@
 // C ABI of the estimator: contexts, resident scenes and the estimator calls.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -22,6 +23,33 @@ int prdpt::fail(int code, const std::string& msg) {
 }
 
 namespace {
+// allocation-failure injection: < 0 off; otherwise the number of allocations
+// still allowed to succeed before every later one fails
+std::atomic<int64_t> g_alloc_budget{-1};
+
+bool alloc_allowed() {
+  int64_t left = g_alloc_budget.load();
+  while (left >= 0) {
+    if (left == 0) return false;
+    if (g_alloc_budget.compare_exchange_weak(left, left - 1)) return true;
+  }
+  return true;
+}
+}  // namespace
+
+hipError_t prdpt::dev_malloc(void** p, size_t bytes) {
+  *p = nullptr;
+  if (!alloc_allowed()) return hipErrorOutOfMemory;
+  return hipMalloc(p, bytes);
+}
+
+hipError_t prdpt::pinned_malloc(void** p, size_t bytes) {
+  *p = nullptr;
+  if (!alloc_allowed()) return hipErrorOutOfMemory;
+  return hipHostMalloc(p, bytes, hipHostMallocDefault);
+}
+
+namespace {
 
 template <class T>
 int ensure(prdpt_ctx* ctx, DevBuf<T>& b, size_t n) {
@@ -34,7 +62,7 @@ int ensure(prdpt_ctx* ctx, DevBuf<T>& b, size_t n) {
     b.n = 0;
   }
   size_t want = n + n / 2;
-  if (hipMalloc(&b.p, want * sizeof(T)) != hipSuccess) {
+  if (dev_malloc((void**)&b.p, want * sizeof(T)) != hipSuccess) {
     b.p = nullptr;
     return fail(PRDPT_E_NOMEM, "device allocation of scratch failed");
   }
@@ -86,6 +114,9 @@ int check_request(const prdpt_scene* s, const float* theta, const float* sigma, 
   if (!theta || !sigma) return fail(PRDPT_E_ARG, "theta/sigma is null");
   if (N < 2 || (N & 1)) return fail(PRDPT_E_ARG, "N must be even and >= 2");
   if (N > (1 << 20)) return fail(PRDPT_E_ARG, "N too large");
+  // (perturbation, tile) work items are counted in 32 bits
+  if ((long long)N * render_tiles(s->hdr.W, s->hdr.H) >= (1ll << 31))
+    return fail(PRDPT_E_ARG, "N x pixel tiles must stay below 2^31");
   if (host_vectors) {
     for (int j = 0; j < s->hdr.n_param; ++j) {
       if (!std::isfinite(theta[j])) return fail(PRDPT_E_ARG, "theta must be finite");
@@ -158,7 +189,7 @@ int ensure_pinned(prdpt_ctx* ctx, T*& p, size_t& cap, size_t n) {
     p = nullptr;
     cap = 0;
   }
-  if (hipHostMalloc((void**)&p, n * sizeof(T), hipHostMallocDefault) != hipSuccess) {
+  if (pinned_malloc((void**)&p, n * sizeof(T)) != hipSuccess) {
     p = nullptr;
     return fail(PRDPT_E_NOMEM, "pinned host allocation failed");
   }
@@ -177,6 +208,11 @@ int upload_vectors(prdpt_ctx* ctx, const float* theta, const float* sigma, int d
 extern "C" {
 
 const char* prdpt_last_error(void) { return g_err.c_str(); }
+
+int prdpt_debug_fail_allocations(int64_t after) {
+  g_alloc_budget.store(after < 0 ? -1 : after);
+  return PRDPT_OK;
+}
 
 int prdpt_ctx_create(int device, void* stream, size_t hbm_budget, prdpt_ctx** out) {
   if (!out) return fail(PRDPT_E_ARG, "out is null");
@@ -458,12 +494,12 @@ int prdpt::upload_scene(prdpt_ctx* ctx, const HostScene& hs, prdpt_scene** out) 
     if (s->d_tile_order) hipFree(s->d_tile_order);
     delete s;
   };
-  bool ok = hipMalloc(&s->d_hdr, sizeof(SceneHdr)) == hipSuccess;
-  ok = ok && hipMalloc(&s->d_nodes, std::max<size_t>(1, nodes.size()) * sizeof(Node)) == hipSuccess;
-  ok = ok && hipMalloc(&s->d_tris, std::max<size_t>(1, tris.size()) * sizeof(Tri)) == hipSuccess;
-  ok = ok && hipMalloc(&s->d_tri_slot, std::max<size_t>(1, tris.size()) * sizeof(int32_t)) == hipSuccess;
-  ok = ok && hipMalloc(&s->d_tile_cost, s->n_tiles * sizeof(float)) == hipSuccess;
-  ok = ok && hipMalloc(&s->d_tile_order, s->n_tiles * sizeof(int)) == hipSuccess;
+  bool ok = dev_malloc((void**)&s->d_hdr, sizeof(SceneHdr)) == hipSuccess;
+  ok = ok && dev_malloc((void**)&s->d_nodes, std::max<size_t>(1, nodes.size()) * sizeof(Node)) == hipSuccess;
+  ok = ok && dev_malloc((void**)&s->d_tris, std::max<size_t>(1, tris.size()) * sizeof(Tri)) == hipSuccess;
+  ok = ok && dev_malloc((void**)&s->d_tri_slot, std::max<size_t>(1, tris.size()) * sizeof(int32_t)) == hipSuccess;
+  ok = ok && dev_malloc((void**)&s->d_tile_cost, s->n_tiles * sizeof(float)) == hipSuccess;
+  ok = ok && dev_malloc((void**)&s->d_tile_order, s->n_tiles * sizeof(int)) == hipSuccess;
   if (!ok) {
     release();
     return fail(PRDPT_E_NOMEM, "device allocation of the scene failed");
@@ -668,7 +704,8 @@ int prdpt_combine_async(prdpt_ctx* ctx, int rows, int d, const double* c_dev,
                         const double* losses_dev, const double* scale_dev, double* grad_dev,
                         int est) {
   if (!ctx || !c_dev || !losses_dev || !grad_dev) return fail(PRDPT_E_ARG, "null argument");
-  if (rows < 1 || d < 1 || d > 64) return fail(PRDPT_E_ARG, "bad row count or d");
+  if (rows < 1 || rows > (1 << 20) || d < 1 || d > PRDPT_MAX_PARAMS)
+    return fail(PRDPT_E_ARG, "rows must be in 1..2^20 and d in 1..PRDPT_MAX_PARAMS");
   if (int rc = check_est(est)) return rc;
   std::lock_guard<std::mutex> g(ctx->mu);
   HIP_TRY(hipSetDevice(ctx->device));
@@ -716,19 +753,19 @@ int prdpt_traversal_counts(prdpt_scene* s, const float* theta, const float* sigm
   std::lock_guard<std::mutex> g(ctx->mu);
   HIP_TRY(hipSetDevice(ctx->device));
   if (int rc = prepare(ctx, N, d, render_tiles(h.W, h.H))) return rc;
-  if (int rc = ensure(ctx, ctx->counters, 8)) return rc;
+  if (int rc = ensure(ctx, ctx->counters, 10)) return rc;
   if (int rc = upload_vectors(ctx, theta, sigma, d)) return rc;
-  HIP_TRY(hipMemsetAsync(ctx->counters.p, 0, 8 * sizeof(unsigned long long), ctx->stream));
+  HIP_TRY(hipMemsetAsync(ctx->counters.p, 0, 10 * sizeof(unsigned long long), ctx->stream));
   HIP_TRY(launch_tau(ctx->stream, est, d, rows, seed, ctx->sigma.p, ctx->theta.p, chi_mean(d),
                      std::sqrt(2.0 * M_PI), ctx->tau.p, ctx->c.p, ctx->X.p));
   HIP_TRY(launch_render(ctx->stream, s->dev(), h.W, h.H, ctx->X.p, N, d, kTagPath, seed, nullptr,
                         nullptr, nullptr, ctx->counters.p, ctx->work.p, s->d_tile_order,
                         nullptr, (est & PRDPT_EST_INDEPENDENT) ? 0 : 1, s->hdr.has_rot,
                         s->hdr.n_sph));
-  unsigned long long host[8];
+  unsigned long long host[10];
   HIP_TRY(hipMemcpyAsync(host, ctx->counters.p, sizeof(host), hipMemcpyDeviceToHost, ctx->stream));
   HIP_TRY(hipStreamSynchronize(ctx->stream));
-  for (int i = 0; i < 8; ++i) counts[i] = host[i];
+  for (int i = 0; i < 10; ++i) counts[i] = host[i];
   return PRDPT_OK;
 }
 

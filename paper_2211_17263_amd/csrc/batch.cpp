@@ -41,7 +41,7 @@ int grow_dev(T*& p, size_t& cap_field_unused, size_t n) {
     HIP_TRY(hipFree(p));
     p = nullptr;
   }
-  if (hipMalloc(&p, std::max<size_t>(1, n) * sizeof(T)) != hipSuccess) {
+  if (dev_malloc((void**)&p, std::max<size_t>(1, n) * sizeof(T)) != hipSuccess) {
     p = nullptr;
     return fail(PRDPT_E_NOMEM, "device allocation for the batch failed");
   }
@@ -54,7 +54,7 @@ int grow_host(T*& p, size_t n) {
     HIP_TRY(hipHostFree(p));
     p = nullptr;
   }
-  if (hipHostMalloc(&p, std::max<size_t>(1, n) * sizeof(T), hipHostMallocDefault) != hipSuccess) {
+  if (pinned_malloc((void**)&p, std::max<size_t>(1, n) * sizeof(T)) != hipSuccess) {
     p = nullptr;
     return fail(PRDPT_E_NOMEM, "pinned host allocation for the batch failed");
   }

@@ -70,9 +70,11 @@ constexpr double kCostNode = PRDPT_SAH_NODE;
 constexpr double kCostTri = PRDPT_SAH_TRI;
 
 // largest triangle count a subtree whose root inner node sits at depth D can
-// hold within the depth bound (two leaves of kLeafMax at depth kMaxInnerDepth)
+// hold within the depth bound (two leaves of kLeafMax at depth kMaxInnerDepth);
+// below the bound (the children of a leaf) nothing fits
 inline long long capacity(int D) {
   const int levels = kMaxInnerDepth - D + 1;
+  if (levels < 0) return 0;
   return levels >= 40 ? (1LL << 50) : (long long)kLeafMax << levels;
 }
 

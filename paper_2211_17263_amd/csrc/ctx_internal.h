@@ -43,6 +43,10 @@ hipError_t launch_copy(hipStream_t st, const void* src, void* dst, size_t n16);
 
 // records `msg` as the calling thread's last error and returns `code`
 int fail(int code, const std::string& msg);
+// every device and pinned host allocation of the library goes through these
+// two (prdpt_debug_fail_allocations makes them fail on request)
+hipError_t dev_malloc(void** p, size_t bytes);
+hipError_t pinned_malloc(void** p, size_t bytes);
 
 // Mean of the chi distribution with d degrees of freedom (the IS weight constant):
 // C_1 = sqrt(2/pi), C_{k+1} = k / C_k.

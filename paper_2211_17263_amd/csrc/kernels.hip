@@ -232,6 +232,8 @@ struct Counters {
   uint32_t nodes, tris, rays, paths;
   uint32_t wave_node_iters, wave_tri_iters, wave_outer_iters;
   uint32_t idle_lane_iters;  // ray-loop iterations x lanes with no path of the tile left
+  uint32_t overflow_pushes;  // stack pushes into the private part
+  uint32_t deepest;          // most stack entries in use at once
 };
 
 __device__ __forceinline__ bool first_active_lane() {
@@ -465,6 +467,13 @@ __device__ bool continue_trace(const SceneLds& S, const Node* __restrict__ nodes
   int node = -1;   // inner node being visited, -1: none
   int leaf = 0;    // pending leaf (encoded < 0), 0: none
   int iters = 0;
+  auto push_entry = [&](int e) {
+    push(stack, stride, ovf, sp, e);
+    if (COUNT) {
+      if (sp > kStackEntries) cnt.overflow_pushes++;
+      cnt.deepest = max(cnt.deepest, (uint32_t)sp);
+    }
+  };
   const int entered = __popcll(__ballot(1));
   while (true) {
     // ---- node loop: descend until enough lanes hold a leaf
@@ -521,34 +530,34 @@ __device__ bool continue_trace(const SceneLds& S, const Node* __restrict__ nodes
         }
         if (t2 < inf) {
           if (r2 >= 0) {
-            if (next >= 0) push(stack, stride, ovf, sp, next);
+            if (next >= 0) push_entry(next);
             next = r2;
           } else {
-            if (near_leaf != 0) push(stack, stride, ovf, sp, near_leaf);
+            if (near_leaf != 0) push_entry(near_leaf);
             near_leaf = r2;
           }
         }
         if (t1 < inf) {
           if (r1 >= 0) {
-            if (next >= 0) push(stack, stride, ovf, sp, next);
+            if (next >= 0) push_entry(next);
             next = r1;
           } else {
-            if (near_leaf != 0) push(stack, stride, ovf, sp, near_leaf);
+            if (near_leaf != 0) push_entry(near_leaf);
             near_leaf = r1;
           }
         }
         if (t0 < inf) {
           if (r0 >= 0) {
-            if (next >= 0) push(stack, stride, ovf, sp, next);
+            if (next >= 0) push_entry(next);
             next = r0;
           } else {
-            if (near_leaf != 0) push(stack, stride, ovf, sp, near_leaf);
+            if (near_leaf != 0) push_entry(near_leaf);
             near_leaf = r0;
           }
         }
         if (near_leaf != 0) {
           if (leaf == 0) leaf = near_leaf;
-          else push(stack, stride, ovf, sp, near_leaf);
+          else push_entry(near_leaf);
         }
         node = next;
       }
@@ -636,7 +645,7 @@ __device__ bool continue_trace(const SceneLds& S, const Node* __restrict__ nodes
     // the lanes that entered are still tracing: the current node goes back on
     // the stack
     if (iters >= budget || __popcll(__ballot(1)) * 100 <= entered * PRDPT_TRACE_QUORUM) {
-      if (node >= 0) push(stack, stride, ovf, sp, node);
+      if (node >= 0) push_entry(node);
       tr.sp = sp;
       tr.inst = inst;
       return false;
@@ -765,7 +774,7 @@ __device__ __forceinline__ void render_tile(const SceneLds& S, const float* __re
   const int n_lights = S.n_pl + S.n_area;
   int* stk = stack + t;
   int ovf[kStackOverflow];  // stack entries beyond the LDS part (deep descents only)
-  Counters cnt{0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
+  Counters cnt{0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
 
   // path state
   V3 o = mk(0.0f, 0.0f, 0.0f), dir = o, p = o, n = o;
@@ -1079,6 +1088,8 @@ __device__ __forceinline__ void render_tile(const SceneLds& S, const float* __re
     atomicAdd(&counters[5], (unsigned long long)cnt.wave_tri_iters);
     atomicAdd(&counters[6], (unsigned long long)cnt.wave_outer_iters);
     atomicAdd(&counters[7], (unsigned long long)cnt.idle_lane_iters);
+    atomicAdd(&counters[8], (unsigned long long)cnt.overflow_pushes);
+    atomicMax(&counters[9], (unsigned long long)cnt.deepest);
   }
   if (partial_slot) {
     // fixed-order butterfly within the wave, then the waves in order

@@ -10,9 +10,13 @@
 // streams, so requests that arrive while an epoch runs are admitted as soon as
 // a slot and memory free up and their work overlaps the running epoch on the
 // device.  Each result is the same as the request alone (the batch path is
-// bit-identical to the single-request path).
+// bit-identical to the single-request path).  A request may carry a deadline:
+// once it has passed, the request completes with PRDPT_E_TIMEOUT whether it is
+// still queued or already running (its result is then dropped when its epoch
+// ends); the other requests of its epoch are not affected.
 #include <atomic>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -49,6 +53,7 @@ struct Pending {
   int N = 0, est = 0;
   uint64_t seed = 0;
   double t_submit = 0.0;
+  double deadline = 0.0;  // steady-clock seconds; 0: none
 };
 
 struct Slot {
@@ -57,6 +62,7 @@ struct Slot {
   hipEvent_t done = nullptr;
   double t_start = 0.0;
   std::vector<Pending> items;
+  std::vector<char> expired;  // items already completed with PRDPT_E_TIMEOUT
   std::vector<prdpt_request> reqs;
   std::vector<std::vector<double>> grads;
   std::vector<double> loss;
@@ -118,7 +124,11 @@ void evict(prdpt_server* sv, Job& j) {
   sv->stats.evictions++;
 }
 
+// admit(): the job cannot be made resident before a running epoch frees memory
+constexpr int kWaitForMemory = 1;
+
 // Make job `ji` resident within the budget; jobs in `protect` are not evicted.
+// Returns PRDPT_OK, kWaitForMemory, or a (terminal) error status.
 int admit(prdpt_server* sv, int ji, const std::vector<char>& protect) {
   Job& j = *sv->jobs[ji];
   if (j.scene) return PRDPT_OK;
@@ -132,11 +142,11 @@ int admit(prdpt_server* sv, int ji, const std::vector<char>& protect) {
       if (!c.scene || c.in_flight || protect[k]) continue;
       if (victim < 0 || c.last_used < sv->jobs[victim]->last_used) victim = (int)k;
     }
-    if (victim < 0) return PRDPT_E_ADMISSION;  // wait for running epochs to finish
+    if (victim < 0) return kWaitForMemory;  // wait for running epochs to finish
     evict(sv, *sv->jobs[victim]);
   }
   if (int rc = upload_scene(sv->ctx, j.host, &j.scene)) return rc;
-  if (hipMalloc(&j.d_ref, ref_bytes) != hipSuccess ||
+  if (dev_malloc((void**)&j.d_ref, ref_bytes) != hipSuccess ||
       hipMemcpy(j.d_ref, j.ref_host.data(), ref_bytes, hipMemcpyHostToDevice) != hipSuccess) {
     prdpt_scene_destroy(j.scene);
     j.scene = nullptr;
@@ -157,6 +167,7 @@ void retire(prdpt_server* sv, Slot& s) {
     const Pending& p = s.items[i];
     Job& j = *sv->jobs[p.job];
     j.in_flight--;
+    if (s.expired[i]) continue;  // completed with PRDPT_E_TIMEOUT while it ran
     const int d = j.host.hdr.n_param;
     complete(sv, p, s.reqs[i].status, s.t_start, s.grads[i].data(), d, s.loss[i]);
   }
@@ -186,16 +197,19 @@ bool launch_epoch(prdpt_server* sv, Slot& s) {
       keep.push_back(p);
       continue;
     }
+    const char was_protected = protect[p.job];
     protect[p.job] = 1;
     const int rc = admit(sv, p.job, protect);
-    if (rc == PRDPT_E_ADMISSION && sv->cfg.hbm_budget &&
-        sv->jobs[p.job]->host.footprint + sv->jobs[p.job]->ref_host.size() * 4 > sv->cfg.hbm_budget) {
-      complete(sv, p, PRDPT_E_ADMISSION, 0.0, nullptr, 0, 0.0);  // can never fit
+    if (rc == kWaitForMemory) {
+      protect[p.job] = was_protected;
+      keep.push_back(p);  // admitted in a later epoch, when memory frees up
       continue;
     }
     if (rc != PRDPT_OK) {
-      protect[p.job] = 0;
-      keep.push_back(p);  // admitted in a later epoch, when memory frees up
+      // the job can never fit the budget, or its upload failed (the context's
+      // own budget, device memory, HIP): the request fails, the others go on
+      protect[p.job] = was_protected;
+      complete(sv, p, rc, 0.0, nullptr, 0, 0.0);
       continue;
     }
     s.items.push_back(p);
@@ -204,6 +218,7 @@ bool launch_epoch(prdpt_server* sv, Slot& s) {
   for (auto it = keep.rbegin(); it != keep.rend(); ++it) sv->pending.push_front(*it);
   if (s.items.empty()) return false;
   const size_t n = s.items.size();
+  s.expired.assign(n, 0);
   s.reqs.assign(n, prdpt_request{});
   s.grads.assign(n, std::vector<double>(PRDPT_BATCH_MAX_PARAMS, 0.0));
   s.loss.assign(n, 0.0);
@@ -246,10 +261,39 @@ bool launch_epoch(prdpt_server* sv, Slot& s) {
   return true;
 }
 
+// Requests whose deadline has passed complete with PRDPT_E_TIMEOUT: queued
+// ones leave the queue, running ones are marked so that their epoch drops the
+// result (server lock held).  Returns true if any request expired.
+bool expire(prdpt_server* sv) {
+  const double t = now_s();
+  bool any = false;
+  for (auto it = sv->pending.begin(); it != sv->pending.end();) {
+    if (it->deadline > 0.0 && t > it->deadline) {
+      complete(sv, *it, PRDPT_E_TIMEOUT, 0.0, nullptr, 0, 0.0);
+      it = sv->pending.erase(it);
+      any = true;
+    } else {
+      ++it;
+    }
+  }
+  for (Slot& s : sv->slots) {
+    if (!s.busy) continue;
+    for (size_t i = 0; i < s.items.size(); ++i) {
+      if (!s.expired[i] && s.items[i].deadline > 0.0 && t > s.items[i].deadline) {
+        complete(sv, s.items[i], PRDPT_E_TIMEOUT, s.t_start, nullptr, 0, 0.0);
+        s.expired[i] = 1;
+        any = true;
+      }
+    }
+  }
+  return any;
+}
+
 void server_loop(prdpt_server* sv) {
   hipSetDevice(sv->ctx->device);
   std::unique_lock<std::mutex> lk(sv->mu);
   while (true) {
+    if (expire(sv)) sv->cv_done.notify_all();
     bool any_busy = false;
     for (Slot& s : sv->slots) {
       if (!s.busy) continue;
@@ -271,8 +315,19 @@ void server_loop(prdpt_server* sv) {
     any_busy = any_busy || launched;
     for (Slot& s : sv->slots) any_busy = any_busy || s.busy;
     if (sv->stop && !any_busy && sv->pending.empty()) break;
-    if (any_busy) {
-      // poll the running epochs; new submissions wake us immediately
+    if (!any_busy && !sv->pending.empty()) {
+      // nothing runs and nothing queued could start (no memory can free up):
+      // on stop the queue is cancelled, otherwise wait for a change instead of
+      // retrying at once
+      if (sv->stop) {
+        for (const Pending& p : sv->pending) complete(sv, p, PRDPT_E_CANCELLED, 0.0, nullptr, 0, 0.0);
+        sv->pending.clear();
+        sv->cv_done.notify_all();
+        continue;
+      }
+      sv->cv_work.wait_for(lk, std::chrono::milliseconds(1));
+    } else if (any_busy || !sv->pending.empty()) {
+      // poll the running epochs and the deadlines; new submissions wake us
       sv->cv_work.wait_for(lk, std::chrono::microseconds(200));
     } else {
       sv->cv_work.wait(lk, [&] { return sv->stop || !sv->pending.empty(); });
@@ -313,7 +368,15 @@ int prdpt_server_add_job(prdpt_server* sv, const prdpt_scene_desc* desc, const f
 
 int prdpt_server_submit(prdpt_server* sv, int job_id, const float* theta, const float* sigma, int N,
                         uint64_t seed, int est, int64_t* ticket) {
+  return prdpt_server_submit_deadline(sv, job_id, theta, sigma, N, seed, est, 0.0, ticket);
+}
+
+int prdpt_server_submit_deadline(prdpt_server* sv, int job_id, const float* theta,
+                                 const float* sigma, int N, uint64_t seed, int est,
+                                 double timeout_s, int64_t* ticket) {
   if (!sv || !theta || !sigma || !ticket) return fail(PRDPT_E_ARG, "null argument");
+  if (!(timeout_s >= 0.0) || !std::isfinite(timeout_s))
+    return fail(PRDPT_E_ARG, "timeout must be finite and >= 0");
   Pending p;
   {
     std::lock_guard<std::mutex> g(sv->mu);
@@ -334,6 +397,7 @@ int prdpt_server_submit(prdpt_server* sv, int job_id, const float* theta, const 
     p.seed = seed;
     p.ticket = sv->next_ticket++;
     p.t_submit = now_s();
+    p.deadline = timeout_s > 0.0 ? p.t_submit + timeout_s : 0.0;
     sv->pending.push_back(p);
     sv->stats.submitted++;
     *ticket = p.ticket;

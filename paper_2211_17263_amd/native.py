@@ -33,6 +33,7 @@ EXPORTS = [
     "prdpt_copy_probe", "prdpt_batch_estimate", "prdpt_batch_config", "prdpt_batch_autotune",
     "prdpt_server_start", "prdpt_server_add_job", "prdpt_server_submit", "prdpt_server_cancel",
     "prdpt_server_poll", "prdpt_server_get_stats", "prdpt_server_stop",
+    "prdpt_server_submit_deadline", "prdpt_debug_fail_allocations",
 ]
 
 
@@ -130,6 +131,9 @@ def load():
     L.prdpt_server_start.argtypes = [vp, C.POINTER(ServerConfig), pvp]
     L.prdpt_server_add_job.argtypes = [vp, C.POINTER(SceneDesc), vp, C.POINTER(C.c_int)]
     L.prdpt_server_submit.argtypes = [vp, i32, vp, vp, i32, u64, i32, C.POINTER(C.c_int64)]
+    L.prdpt_server_submit_deadline.argtypes = [vp, i32, vp, vp, i32, u64, i32, C.c_double,
+                                               C.POINTER(C.c_int64)]
+    L.prdpt_debug_fail_allocations.argtypes = [C.c_int64]
     L.prdpt_server_cancel.argtypes = [vp, C.c_int64]
     L.prdpt_server_poll.argtypes = [vp, C.POINTER(Completion), i32, i32, C.POINTER(C.c_int)]
     L.prdpt_server_get_stats.argtypes = [vp, C.POINTER(ServerStats)]
@@ -330,6 +334,11 @@ def prdpt_grad_estimate_async(scene, ref, theta, sigma, N, seed, est, grad, loss
         _dev(c, torch.float64) if c is not None else None))
 
 
+def prdpt_debug_fail_allocations(after):
+    """Let `after` more library allocations succeed, then fail them (< 0: off)."""
+    _check(load().prdpt_debug_fail_allocations(int(after)))
+
+
 def prdpt_ctx_set_timing(ctx, enable):
     _check(load().prdpt_ctx_set_timing(ctx.h, 1 if enable else 0))
 
@@ -343,15 +352,17 @@ def prdpt_ctx_read_timing(ctx):
 
 def prdpt_traversal_counts(scene, theta, sigma, N, seed, est):
     """Work counts of one estimate's render: per-lane nodes, tris, rays, paths,
-    wave-level iterations of the node, triangle and ray loops, and lanes idle in
-    ray-loop iterations because their pixel is done."""
+    wave-level iterations of the node, triangle and ray loops, lanes idle in
+    ray-loop iterations because their pixel is done, stack pushes into the
+    private part and the deepest stack."""
     th, tp = _host(theta, np.float32)
     sg, sp = _host(sigma, np.float32)
-    out = np.zeros(8, np.uint64)
+    out = np.zeros(10, np.uint64)
     _check(load().prdpt_traversal_counts(scene.h, tp, sp, int(N), int(seed), int(est),
                                          out.ctypes.data_as(C.c_void_p)))
     return dict(zip(("nodes", "tris", "rays", "paths", "wave_node_iters", "wave_tri_iters",
-                     "wave_ray_iters", "idle_lane_iters"), (int(x) for x in out)))
+                     "wave_ray_iters", "idle_lane_iters", "overflow_pushes", "deepest_stack"),
+                    (int(x) for x in out)))
 
 
 def prdpt_copy_probe(ctx, src, dst, iters=10):
@@ -469,14 +480,20 @@ class Server:
         self.d[jid.value] = scene.d
         return jid.value
 
-    def submit(self, job, theta, sigma, N, seed, est):
+    def submit(self, job, theta, sigma, N, seed, est, timeout_s=None):
+        """Queue a request; with timeout_s it calls prdpt_server_submit_deadline."""
         th, tp = _host(theta, np.float32)
         sg, sp = _host(sigma, np.float32)
         if th.size != self.d[job] or sg.size != self.d[job]:
             raise ValueError("theta/sigma length must equal the job's parameter count")
         t = C.c_int64()
-        _check(load().prdpt_server_submit(self.h, int(job), tp, sp, int(N), int(seed), int(est),
-                                          C.byref(t)))
+        if timeout_s is None:
+            _check(load().prdpt_server_submit(self.h, int(job), tp, sp, int(N), int(seed),
+                                              int(est), C.byref(t)))
+        else:
+            _check(load().prdpt_server_submit_deadline(self.h, int(job), tp, sp, int(N),
+                                                       int(seed), int(est), float(timeout_s),
+                                                       C.byref(t)))
         return t.value
 
     def cancel(self, ticket):

@@ -577,3 +577,25 @@ def lens_scene(ior=1.5, radius=0.5):
     m = s.material(DIELECTRIC, ior=ior)
     s.sphere((0.0, 0.0, 0.0), radius, m)
     return s
+
+
+def deep_stack_scene(seed=6, n_tris=524288, width=48, height=40, spp=2, bounces=1):
+    """Many long, thin triangles overlapping across the whole view in a slab
+    (z in [-0.5, 0.5]): their BVH is deep and a ray meets most boxes, so
+    traversal keeps up to three siblings per level on its stack.  A diffuse
+    floor below and a point light; the parameters translate the mesh in x, y."""
+    rng = np.random.default_rng(seed)
+    s = _new_scene("deep-stack", width, height, spp, bounces, eye=(0.0, 0.0, 3.0), look=(0, 0, 0))
+    floor = s.material(DIFFUSE, (0.7, 0.7, 0.7))
+    m = s.material(DIFFUSE, (0.6, 0.4, 0.3))
+    s.quad((-10.0, -10.0, -1.0), (20.0, 0.0, 0.0), (0.0, 20.0, 0.0), floor)
+    z = rng.uniform(-0.5, 0.5, n_tris)
+    x, y = rng.uniform(-1, 1, n_tris), rng.uniform(-1, 1, n_tris)
+    dx, dy = rng.uniform(-1, 1, n_tris), rng.uniform(-1, 1, n_tris)
+    v = np.stack([np.stack([x - dx, y - dy, z], 1), np.stack([x + dx, y + dy, z + 0.001], 1),
+                  np.stack([x + 0.002, y, z], 1)], 1).astype(np.float32)
+    s.mesh(v.reshape(-1, 3), np.arange(3 * n_tris, dtype=np.int32).reshape(-1, 3), m)
+    s.plight((0.5, 0.8, 2.5), (6.0, 6.0, 6.0))
+    s.bind(BIND_MESH, 0, 0)
+    s.bind(BIND_MESH, 0, 1)
+    return s

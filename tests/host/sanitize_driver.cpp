@@ -1,0 +1,254 @@
+// Host-side checks of the library under AddressSanitizer and
+// UndefinedBehaviorSanitizer (built by tests/test_host_sanitizers.py; runs
+// without a GPU).  Exercises scene validation and the BVH builder on random,
+// degenerate and deep triangle sets, checks the built trees' invariants (every
+// triangle in exactly one leaf, padded leaf boxes containing their triangles,
+// 4-wide depth within the traversal stack bound), every entry point's argument
+// checks, the host optimiser step, and context creation without a device.
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <random>
+#include <vector>
+
+#include "ctx_internal.h"
+
+using namespace prdpt;
+
+static int g_failures = 0;
+#define CHECK(c)                                                             \
+  do {                                                                       \
+    if (!(c)) {                                                              \
+      std::fprintf(stderr, "CHECK failed at line %d: %s\n", __LINE__, #c);   \
+      ++g_failures;                                                          \
+    }                                                                        \
+  } while (0)
+
+struct SceneArrays {
+  std::vector<int32_t> mat_type{0};
+  std::vector<float> mat_rgb{0.5f, 0.5f, 0.5f};
+  std::vector<float> mat_ior{1.0f};
+  std::vector<float> tris;
+  std::vector<int32_t> mesh_off{0, 0};
+  std::vector<int32_t> mesh_mat{0};
+  std::vector<float> mesh_xlate{0.0f, 0.0f, 0.0f};
+  std::vector<int32_t> bindings{2, 0, 0};
+  prdpt_scene_desc desc() {
+    prdpt_scene_desc d{};
+    float eye[3] = {0, 0, 5}, fwd[3] = {0, 0, -1}, right[3] = {0.4f, 0, 0}, up[3] = {0, 0.4f, 0};
+    for (int i = 0; i < 3; ++i) {
+      d.eye[i] = eye[i];
+      d.fwd[i] = fwd[i];
+      d.right[i] = right[i];
+      d.up[i] = up[i];
+    }
+    d.width = 16;
+    d.height = 12;
+    d.spp = 1;
+    d.max_bounces = 1;
+    d.n_materials = 1;
+    d.mat_type = mat_type.data();
+    d.mat_rgb = mat_rgb.data();
+    d.mat_ior = mat_ior.data();
+    mesh_off[1] = (int32_t)(tris.size() / 9);
+    d.n_meshes = 1;
+    d.mesh_offset = mesh_off.data();
+    d.mesh_mat = mesh_mat.data();
+    d.mesh_translation = mesh_xlate.data();
+    d.n_triangles = (int32_t)(tris.size() / 9);
+    d.triangles = tris.data();
+    d.n_params = 1;
+    d.bindings = bindings.data();
+    return d;
+  }
+};
+
+// Walks the 4-wide tree: every triangle reached exactly once, each leaf box
+// holds its triangles' vertices, depth within kMaxDepth4.  Returns the depth.
+static int check_tree(const HostScene& hs, int n_tris) {
+  std::vector<int> seen(hs.tris.size(), 0);
+  int max_depth = 0;
+  struct Item { int node, depth; };
+  std::vector<Item> todo;
+  for (int i = 0; i < PRDPT_MAX_INSTANCES; ++i)
+    if (hs.hdr.inst_root[i] >= 0 && i < hs.hdr.n_inst) todo.push_back({hs.hdr.inst_root[i], 1});
+  while (!todo.empty()) {
+    Item it = todo.back();
+    todo.pop_back();
+    CHECK(it.node >= 0 && it.node < (int)hs.nodes.size());
+    if (it.node < 0 || it.node >= (int)hs.nodes.size()) continue;
+    max_depth = std::max(max_depth, it.depth);
+    const Node& nd = hs.nodes[it.node];
+    for (int c = 0; c < 4; ++c) {
+      const int32_t r = nd.ref[c];
+      if (r == kEmptyChild) {
+        CHECK(nd.lox[c] > nd.hix[c]);  // inverted box: never hit
+        continue;
+      }
+      if (r >= 0) {
+        CHECK(r > it.node);  // depth-first layout: a subtree follows its node
+        todo.push_back({r, it.depth + 1});
+        continue;
+      }
+      const int code = ~r, first = code >> 3, count = (code & 7) + 1;
+      CHECK(count <= kLeafMax);
+      CHECK(first >= 0 && first + count <= (int)hs.tris.size());
+      for (int t = first; t < first + count && t < (int)hs.tris.size(); ++t) {
+        seen[t]++;
+        const Tri& tr = hs.tris[t];
+        const float v[3][3] = {{tr.v0x, tr.v0y, tr.v0z},
+                               {tr.v0x + tr.e1x, tr.v0y + tr.e1y, tr.v0z + tr.e1z},
+                               {tr.v0x + tr.e2x, tr.v0y + tr.e2y, tr.v0z + tr.e2z}};
+        for (int k = 0; k < 3; ++k) {
+          CHECK(nd.lox[c] <= v[k][0] && v[k][0] <= nd.hix[c]);
+          CHECK(nd.loy[c] <= v[k][1] && v[k][1] <= nd.hiy[c]);
+          CHECK(nd.loz[c] <= v[k][2] && v[k][2] <= nd.hiz[c]);
+        }
+      }
+    }
+  }
+  CHECK((int)hs.tris.size() == n_tris);
+  for (size_t t = 0; t < seen.size(); ++t) CHECK(seen[t] == 1);
+  CHECK(max_depth <= kMaxDepth4);
+  return max_depth;
+}
+
+static void random_soup(SceneArrays& a, int n, float extent, float size, unsigned seed) {
+  std::mt19937 rng(seed);
+  std::uniform_real_distribution<float> u(-1.0f, 1.0f);
+  a.tris.clear();
+  for (int i = 0; i < n; ++i) {
+    const float c[3] = {u(rng) * extent, u(rng) * extent, u(rng) * extent};
+    for (int k = 0; k < 3; ++k)
+      for (int ax = 0; ax < 3; ++ax) a.tris.push_back(c[ax] + u(rng) * size);
+  }
+}
+
+int main(int argc, char** argv) {
+  // ---- the GPU tests' deep-stack scene (raw float32 [n][9] triangles): its
+  // tree must stay within the stack bound while exceeding the LDS part
+  if (argc > 1) {
+    FILE* f = std::fopen(argv[1], "rb");
+    CHECK(f != nullptr);
+    if (f) {
+      SceneArrays a;
+      float buf[9];
+      while (std::fread(buf, sizeof(float), 9, f) == 9) a.tris.insert(a.tris.end(), buf, buf + 9);
+      std::fclose(f);
+      prdpt_scene_desc d = a.desc();
+      HostScene hs;
+      CHECK(build_host_scene(&d, hs) == PRDPT_OK);
+      const int depth = check_tree(hs, (int)(a.tris.size() / 9));
+      std::printf("file depth4=%d stack_bound=%d lds_entries=%d\n", depth, 3 * depth + 1,
+                  kStackEntries);
+    }
+  }
+  // ---- BVH builds and invariants
+  const int sizes[] = {1, 2, 3, 4, 5, 17, 33, 1000, 20000};
+  for (int n : sizes) {
+    SceneArrays a;
+    random_soup(a, n, 1.0f, 0.05f, 100u + n);
+    prdpt_scene_desc d = a.desc();
+    HostScene hs;
+    CHECK(build_host_scene(&d, hs) == PRDPT_OK);
+    const int depth = check_tree(hs, n);
+    std::printf("soup n=%d nodes=%zu depth4=%d\n", n, hs.nodes.size(), depth);
+  }
+  {  // every triangle identical: no split separates them
+    SceneArrays a;
+    for (int i = 0; i < 300; ++i)
+      for (float v : {0.f, 0.f, 0.f, 1.f, 0.f, 0.f, 0.f, 1.f, 0.f}) a.tris.push_back(v);
+    prdpt_scene_desc d = a.desc();
+    HostScene hs;
+    CHECK(build_host_scene(&d, hs) == PRDPT_OK);
+    std::printf("identical depth4=%d\n", check_tree(hs, 300));
+  }
+  {  // zero-area and huge triangles
+    SceneArrays a;
+    random_soup(a, 500, 1e6f, 0.0f, 7u);
+    prdpt_scene_desc d = a.desc();
+    HostScene hs;
+    CHECK(build_host_scene(&d, hs) == PRDPT_OK);
+    std::printf("degenerate depth4=%d\n", check_tree(hs, 500));
+  }
+  {  // a deep tree of long, thin, overlapping triangles across the view: a
+     // ray meets most boxes, so traversal keeps up to three siblings per level
+    SceneArrays a;
+    std::mt19937 rng(3);
+    std::uniform_real_distribution<float> u(-1.0f, 1.0f);
+    const int n = 65536;
+    for (int i = 0; i < n; ++i) {
+      const float z = u(rng) * 0.5f, x = u(rng), y = u(rng), dx = u(rng), dy = u(rng);
+      const float tri[9] = {x - dx, y - dy, z, x + dx, y + dy, z + 0.001f, x + 0.002f, y, z};
+      for (float v : tri) a.tris.push_back(v);
+    }
+    prdpt_scene_desc d = a.desc();
+    HostScene hs;
+    CHECK(build_host_scene(&d, hs) == PRDPT_OK);
+    const int depth = check_tree(hs, n);
+    std::printf("deep depth4=%d stack_bound=%d lds_entries=%d private_entries=%d\n", depth,
+                3 * depth + 1, kStackEntries, kStackOverflow);
+    CHECK(3 * depth + 1 <= kStackBound);
+  }
+  // ---- validation failures
+  {
+    SceneArrays a;
+    random_soup(a, 10, 1.0f, 0.1f, 9u);
+    prdpt_scene_desc d = a.desc();
+    HostScene hs;
+    prdpt_scene_desc bad = d;
+    bad.width = 0;
+    CHECK(build_host_scene(&bad, hs) == PRDPT_E_SCENE);
+    bad = d;
+    bad.n_params = 0;
+    CHECK(build_host_scene(&bad, hs) == PRDPT_E_SCENE);
+    bad = d;
+    bad.triangles = nullptr;
+    CHECK(build_host_scene(&bad, hs) == PRDPT_E_SCENE);
+    std::vector<int32_t> bad_bind{2, 5, 0};  // mesh index out of range
+    bad = d;
+    bad.bindings = bad_bind.data();
+    CHECK(build_host_scene(&bad, hs) == PRDPT_E_SCENE);
+    std::vector<int32_t> bad_mat{7};
+    bad = d;
+    bad.mesh_mat = bad_mat.data();
+    CHECK(build_host_scene(&bad, hs) == PRDPT_E_SCENE);
+    CHECK(build_host_scene(nullptr, hs) == PRDPT_E_ARG);
+  }
+  // ---- entry points reject null arguments before touching a device
+  CHECK(prdpt_ctx_create(0, nullptr, 0, nullptr) == PRDPT_E_ARG);
+  CHECK(prdpt_ctx_destroy(nullptr) == PRDPT_E_ARG);
+  CHECK(prdpt_scene_create(nullptr, nullptr, nullptr, nullptr) == PRDPT_E_ARG);
+  CHECK(prdpt_scene_destroy(nullptr) == PRDPT_E_ARG);
+  CHECK(prdpt_grad_estimate(nullptr, nullptr, nullptr, nullptr, 4, 1, 0, nullptr, nullptr,
+                            nullptr) == PRDPT_E_ARG);
+  CHECK(prdpt_grad_estimate_async(nullptr, nullptr, nullptr, nullptr, 4, 1, 0, nullptr, nullptr,
+                                  nullptr, nullptr) == PRDPT_E_ARG);
+  CHECK(prdpt_combine_async(nullptr, 1, 1, nullptr, nullptr, nullptr, nullptr, 0) == PRDPT_E_ARG);
+  CHECK(prdpt_batch_estimate(nullptr, nullptr, 0) == PRDPT_E_ARG);
+  CHECK(prdpt_server_start(nullptr, nullptr, nullptr) == PRDPT_E_ARG);
+  CHECK(prdpt_server_submit_deadline(nullptr, 0, nullptr, nullptr, 4, 1, 0, 1.0, nullptr) ==
+        PRDPT_E_ARG);
+  CHECK(prdpt_debug_fail_allocations(-1) == PRDPT_OK);
+  // ---- host optimiser step
+  {
+    double theta[3] = {1.0, -2.0, 0.5}, g[3] = {0.1, -0.2, 0.0}, m[3] = {0, 0, 0}, v[3] = {0, 0, 0};
+    CHECK(prdpt_adam_step(3, theta, g, m, v, 1, 0.01, 0.9, 0.999, 1e-8) == PRDPT_OK);
+    CHECK(std::fabs(theta[0] - (1.0 - 0.01)) < 1e-9 && std::fabs(theta[1] - (-2.0 + 0.01)) < 1e-9);
+    CHECK(prdpt_adam_step(3, nullptr, g, m, v, 1, 0.01, 0.9, 0.999, 1e-8) == PRDPT_E_ARG);
+    CHECK(prdpt_sigma_schedule(1.0, 0.05, 0, 200) == 1.0);
+    CHECK(std::fabs(prdpt_sigma_schedule(1.0, 0.05, 199, 200) - 0.05) < 1e-15);
+  }
+  // ---- a context on a missing device fails cleanly
+  {
+    prdpt_ctx* ctx = nullptr;
+    const int rc = prdpt_ctx_create(999, nullptr, 0, &ctx);
+    CHECK(rc != PRDPT_OK && ctx == nullptr);
+  }
+  if (g_failures) {
+    std::fprintf(stderr, "%d checks failed\n", g_failures);
+    return 1;
+  }
+  std::printf("host checks OK\n");
+  return 0;
+}

@@ -185,3 +185,41 @@ def test_autotune_writes_and_reads_cache(setup, tmp_path):
     assert (b2, t2) == (b, t) and ms2 == pytest.approx(ms, rel=1e-6)
     NV.prdpt_batch_estimate(ctx, reqs)
     assert all(r.status == 0 for r in reqs)
+
+
+def test_batch_large_scene_against_oracle():
+    # a batched request on a scene of the batched workload's largest size
+    # (512x512, about 120k triangles) beside a small one: losses and gradient
+    # against the oracle's estimate
+    import torch
+    from paper_2211_17263_amd import native as NV
+    rng = np.random.default_rng(61)
+    cases = []
+    for side, n_tris, N, est, d in ((512, 120000, 4, O.IS, 6), (64, 2000, 8, O.GAUSS, 3)):
+        sc, fields = S.random_job_scene(rng, side, n_tris, 4, 2)
+        for idx in rng.permutation(len(fields))[:d]:
+            sc.bind(*fields[idx])
+        cases.append((sc, N, est, d))
+    ctx = NV.Context(0)
+    try:
+        reqs, want = [], []
+        for k, (sc, N, est, d) in enumerate(cases):
+            say("batch-large-oracle", sc.width, sc.n_tris, N)
+            th_ref = np.zeros(d, np.float32)
+            th0 = np.full(d, 0.1, np.float32)
+            sg = np.full(d, 0.3, np.float32)
+            osc = O.OracleScene(sc)
+            ref = osc.reference(th_ref, seed=5 + k)
+            gs = NV.prdpt_scene_create(ctx, sc)
+            reqs.append((gs, NV.BatchRequest(gs, torch.from_numpy(ref).cuda(), th0, sg, N, 70 + k,
+                                             est)))
+            want.append((osc.grad_estimate(ref, th0, sg, N, 70 + k, est), sg, N, est))
+        NV.prdpt_batch_estimate(ctx, [q for _, q in reqs])
+        for (gs, q), (o, sg, N, est) in zip(reqs, want):
+            assert q.status == 0
+            _, c = O.draw_tau(est, sg, N // 2, q.seed)
+            PT.assert_losses_match(q.losses[:N], o["losses"], "batch-large")
+            PT.assert_grad_match(q.grad[: gs.d], o["grad"], c, o["losses"], "batch-large")
+            gs.destroy()
+    finally:
+        ctx.close()

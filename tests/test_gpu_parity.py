@@ -196,13 +196,13 @@ def test_ragged_tiny_and_degenerate(ctx):
     _full_parity(ctx, pr2, 10, "one-pixel")
 
 
-def test_more_samples_than_one_chunk(ctx):
-    # spp above the per-work-group path buffer's chunk (64 samples): the tile's
-    # paths run in two chunks, each pixel adding its samples in order
+def test_more_samples_than_one_wave(ctx):
+    # more samples per pixel (80) than lanes in a wave: the tile's paths are
+    # 80 x 64 jobs, several of the same pixel finishing in one iteration
     sc = S.toy_scene(width=21, height=13, spp=80, bounces=1)
     pr = dict(scene=sc, theta_ref=np.zeros(2, np.float32), theta0=np.array([0.3, -0.2], np.float32),
               sigma=np.full(2, 0.3, np.float32), N=4, est=O.IS)
-    _full_parity(ctx, pr, 19, "two-chunks")
+    _full_parity(ctx, pr, 19, "spp-80")
 
 
 def test_exact_ties_take_the_smaller_id(ctx):
@@ -428,9 +428,38 @@ def test_admission_budget():
 
 
 def test_cornell_full_size(ctx):
-    # the full global-illumination workload: 256x256, 16 spp, 4 bounces, N = 16, IS
+    # the full global-illumination workload: 256x256, 16 spp, 4 bounces, N = 16,
+    # IS; all 16 images pixel by pixel, the losses and the gradient
     pr = S.cornell_problem(seed=2)
-    _full_parity(ctx, pr, 2024, "cornell-full", check_images=False)
+    _full_parity(ctx, pr, 2024, "cornell-full")
+
+
+def test_caustic_full_size_estimate(ctx):
+    # one whole estimate of the caustic workload (512x512, 64 spp, 8 bounces,
+    # 50k occluders, N = 32, IS, sigma 1.0 of step 0) against the oracle's:
+    # every per-image loss and the gradient
+    pr = S.caustic_problem(seed=3)
+    _full_parity(ctx, pr, 4242, "caustic-full-estimate", check_images=False)
+
+
+def test_deep_stack_uses_private_part(ctx):
+    # long thin triangles overlapping across the view: a ray's traversal
+    # stack outgrows its LDS part into the private entries (host tests show
+    # this tree's bound is above the LDS part and within the private one);
+    # the estimate still equals the oracle's
+    from paper_2211_17263_amd import native as NV
+    sc = S.deep_stack_scene()
+    pr = dict(scene=sc, theta_ref=np.array([0.05, -0.03], np.float32),
+              theta0=np.array([-0.04, 0.06], np.float32), sigma=np.full(2, 0.05, np.float32),
+              N=4, est=O.IS)
+    gs = gpu_scene(ctx, sc)
+    try:
+        say("deep-stack counts", sc.n_tris)
+        c = NV.prdpt_traversal_counts(gs, pr["theta0"], pr["sigma"], 4, 3, O.IS)
+    finally:
+        gs.destroy()
+    assert c["deepest_stack"] > 23 and c["overflow_pushes"] > 0, c
+    _full_parity(ctx, pr, 3, "deep-stack")
 
 
 @pytest.mark.parametrize("step", [0, 100, 199])

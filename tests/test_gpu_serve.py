@@ -103,3 +103,37 @@ def test_admission_refusal_and_cancel():
     assert res[tickets[-1]]["status"] == NV.PRDPT_E_CANCELLED
     assert all(res[t]["status"] == 0 for t in tickets[:-1])
     ctx.close()
+
+
+def test_served_results_against_oracle():
+    # completions of the server on small jobs equal the oracle's estimates
+    # within the parity bar (not only the HIP single-request path)
+    from oracle import oracle as O
+    from paper_2211_17263_amd import native as NV
+    from tests import parity as PT
+    jobs = S.batch_jobs(seed=77, n_jobs=3, max_side=64, max_tris=5000)
+    say("serve-oracle", [(j["scene"].width, j["scene"].n_tris, j["N"]) for j in jobs])
+    ctx = NV.Context(0)
+    orcs = [O.OracleScene(j["scene"]) for j in jobs]
+    refs = [o.reference(j["theta_ref"], seed=4) for o, j in zip(orcs, jobs)]
+    sv = NV.Server(ctx, max_batch=4)
+    try:
+        ids = [sv.add_job(j["scene"], r) for j, r in zip(jobs, refs)]
+        subs = []
+        for i in range(6):
+            k = i % len(jobs)
+            t = sv.submit(ids[k], jobs[k]["theta0"], jobs[k]["sigma"], jobs[k]["N"], 900 + i,
+                          jobs[k]["est"])
+            subs.append((t, k, 900 + i))
+        res = drain(sv, len(subs))
+    finally:
+        sv.stop()
+    for t, k, seed in subs:
+        j = jobs[k]
+        c = res[t]
+        assert c["status"] == 0
+        o = orcs[k].grad_estimate(refs[k], j["theta0"], j["sigma"], j["N"], seed, j["est"])
+        _, w = O.draw_tau(j["est"], j["sigma"], j["N"] // 2, seed)
+        PT.assert_grad_match(c["grad"], o["grad"], w, o["losses"], "served")
+        assert abs(c["loss"] - o["loss"]) <= PT.LOSS_REL * abs(o["loss"])
+    ctx.close()

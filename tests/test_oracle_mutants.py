@@ -48,3 +48,28 @@ def test_pin_catches_mutant(name, tmp_path):
                         pin], cwd=ROOT, env=env, capture_output=True, text=True, timeout=300)
     assert r.returncode == 1, f"pin {pin} did not fail on mutant {name}:\n{r.stdout[-2000:]}"
     assert "failed" in r.stdout
+
+
+def test_host_tuned_build_is_bit_identical(tmp_path):
+    # the benchmark times a -march=native build; its results must be the
+    # tests' bit for bit
+    from oracle import build as OB
+    lib = OB.build(native=True, out=str(tmp_path / "liboracle_native.so"))
+    probe = (
+        "import hashlib, numpy as np\n"
+        "from oracle import oracle as O\n"
+        "from paper_2211_17263_amd import scenes as S\n"
+        "pr = S.caustic_problem(seed=3, width=48, height=40, spp=2, n_occluders=3000)\n"
+        "osc = O.OracleScene(pr['scene'])\n"
+        "ref = osc.reference(pr['theta_ref'], seed=1)\n"
+        "r = osc.grad_estimate(ref, pr['theta0'], pr['sigma'], 4, 3, pr['est'])\n"
+        "print(hashlib.sha256(r['grad'].tobytes() + r['losses'].tobytes()).hexdigest())\n")
+    outs = []
+    for path in (None, lib):
+        env = dict(os.environ)
+        if path:
+            env["PRDPT_ORACLE_LIB"] = path
+        r = subprocess.run([sys.executable, "-c", probe], cwd=ROOT, env=env, capture_output=True,
+                           text=True, timeout=300, check=True)
+        outs.append(r.stdout.strip())
+    assert outs[0] == outs[1] and len(outs[0]) == 64
