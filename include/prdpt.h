@@ -252,6 +252,32 @@ int prdpt_grad_estimate_async(prdpt_scene* scene, const float* ref_dev, const fl
                               double* c_dev);
 
 /*
+ * Allocation-free form of prdpt_grad_estimate_async, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same arguments, results and stream order;
+ * the call allocates nothing (no hipMalloc, hipFree or allocating library
+ * routine) and records no timing events.  Its scratch lives in a fixed device
+ * array of PRDPT_NOALLOC_SCRATCH_BYTES that the library reserves on every
+ * device it runs on (looked up when a context is created there) and keeps
+ * until the process ends.  A request needs, each rounded up to 256 bytes:
+ * N d floats (parameter rows), R d floats (draws) and, if c_dev is NULL, R d
+ * doubles (weights), with R = N/2 (R = N with PRDPT_EST_INDEPENDENT); N x
+ * tiles floats (tile losses; tiles = ceil(W/8) ceil(H/8)); N doubles if
+ * losses_dev is NULL; one int.  Larger requests fail with PRDPT_E_ARG before
+ * anything is enqueued.  All calls on one device share that array and each
+ * call leaves its contents behind (the work counter is cleared by a kernel at
+ * the start of every call): calls that overlap on one device, from different
+ * streams or contexts, race and give wrong results, so they must be ordered
+ * (the same stream, or events).  PRDPT_E_HIP if the array could not be looked
+ * up on the context's device.
+ */
+#define PRDPT_NOALLOC_SCRATCH_BYTES (16u << 20)
+int prdpt_grad_estimate_noalloc(prdpt_scene* scene, const float* ref_dev, const float* theta_dev,
+                                const float* sigma_dev, int N, uint64_t seed, int est,
+                                double* grad_dev, double* loss_dev, double* losses_dev,
+                                double* c_dev);
+
+/*
  * Gradient combination alone (Eq. 10), stream-ordered, for the weights of an
  * estimate made with estimator flags `est`:
  *     grad_dev[j] = scale * (1/P) sum_p c_dev[p][j] (losses_dev[2p] - losses_dev[2p+1])

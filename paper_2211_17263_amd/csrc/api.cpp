@@ -83,11 +83,12 @@ hipEvent_t take_event(prdpt_ctx* ctx) {
 
 // launch the fused render kernel, bracketed by timing events when enabled
 hipError_t timed_render(prdpt_ctx* ctx, const prdpt_scene* s, const float* X, int nk, int d, int tag,
-                        uint64_t seed, const float* ref, float* img, float* partial, int crn) {
+                        uint64_t seed, const float* ref, float* img, float* partial, int crn,
+                        int* work, bool allow_timing = true) {
   const DevScene sc = s->dev();
   const int W = s->hdr.W, H = s->hdr.H;
   hipEvent_t a = nullptr, b = nullptr;
-  if (ctx->timing) {
+  if (ctx->timing && allow_timing) {
     a = take_event(ctx);
     b = take_event(ctx);
     if (a && b) {
@@ -96,7 +97,7 @@ hipError_t timed_render(prdpt_ctx* ctx, const prdpt_scene* s, const float* X, in
     }
   }
   hipError_t e = launch_render(ctx->stream, sc, W, H, X, nk, d, tag, seed, ref, img, partial, nullptr,
-                               ctx->work.p, s->d_tile_order, s->d_tile_cost, crn, s->hdr.has_rot,
+                               work, s->d_tile_order, s->d_tile_cost, crn, s->hdr.has_rot,
                                s->hdr.n_sph);
   if (e != hipSuccess) return e;
   if (a && b) {
@@ -156,27 +157,50 @@ int prepare(prdpt_ctx* ctx, int N, int d, int n_tiles) {
   return PRDPT_OK;
 }
 
+// device arrays of one estimate: parameter rows, draws, weights, per-tile
+// partial losses, per-image losses and the render's work counter
+struct EstimateBufs {
+  float* X;
+  float* tau;
+  double* c;
+  float* partial;
+  double* losses;
+  int* work;
+};
+
 // enqueue tau + fused render/loss + losses + combine on the context stream
-int enqueue_estimate(prdpt_scene* s, const float* ref, const float* theta_dev,
-                     const float* sigma_dev, int N, uint64_t seed, int est, double* grad_dev,
-                     double* loss_dev, double* losses_dev, double* c_dev) {
+// into the given buffers (c_dev / losses_dev, when not null, replace b.c /
+// b.losses); allow_timing = false records no timing events
+int enqueue_into(prdpt_scene* s, const float* ref, const float* theta_dev, const float* sigma_dev,
+                 int N, uint64_t seed, int est, double* grad_dev, double* loss_dev,
+                 double* losses_dev, double* c_dev, const EstimateBufs& b, bool allow_timing) {
   prdpt_ctx* ctx = s->ctx;
   const SceneHdr& h = s->hdr;
   const int d = h.n_param;
   const int indep = (est & PRDPT_EST_INDEPENDENT) != 0;
   const int rows = n_draws(est, N);
   const int n_tiles = render_tiles(h.W, h.H);
-  int rc = prepare(ctx, N, d, n_tiles);
-  if (rc) return rc;
-  double* c = c_dev ? c_dev : ctx->c.p;
-  double* L = losses_dev ? losses_dev : ctx->losses.p;
+  double* c = c_dev ? c_dev : b.c;
+  double* L = losses_dev ? losses_dev : b.losses;
   HIP_TRY(launch_tau(ctx->stream, est, d, rows, seed, sigma_dev, theta_dev, chi_mean(d),
-                     std::sqrt(2.0 * M_PI), ctx->tau.p, c, ctx->X.p));
-  HIP_TRY(timed_render(ctx, s, ctx->X.p, N, d, kTagPath, seed, ref, nullptr, ctx->partial.p,
-                       indep ? 0 : 1));
-  HIP_TRY(launch_losses(ctx->stream, ctx->partial.p, n_tiles, N, h.W * h.H, L));
+                     std::sqrt(2.0 * M_PI), b.tau, c, b.X));
+  HIP_TRY(timed_render(ctx, s, b.X, N, d, kTagPath, seed, ref, nullptr, b.partial, indep ? 0 : 1,
+                       b.work, allow_timing));
+  HIP_TRY(launch_losses(ctx->stream, b.partial, n_tiles, N, h.W * h.H, L));
   HIP_TRY(launch_combine(ctx->stream, rows, d, indep, c, L, nullptr, grad_dev, loss_dev));
   return PRDPT_OK;
+}
+
+// the same on the context's own scratch (allocated or grown on demand)
+int enqueue_estimate(prdpt_scene* s, const float* ref, const float* theta_dev,
+                     const float* sigma_dev, int N, uint64_t seed, int est, double* grad_dev,
+                     double* loss_dev, double* losses_dev, double* c_dev) {
+  prdpt_ctx* ctx = s->ctx;
+  const SceneHdr& h = s->hdr;
+  if (int rc = prepare(ctx, N, h.n_param, render_tiles(h.W, h.H))) return rc;
+  const EstimateBufs b{ctx->X.p, ctx->tau.p, ctx->c.p, ctx->partial.p, ctx->losses.p, ctx->work.p};
+  return enqueue_into(s, ref, theta_dev, sigma_dev, N, seed, est, grad_dev, loss_dev, losses_dev,
+                      c_dev, b, true);
 }
 
 // pinned host staging of at least n elements (hipHostMalloc; grows only)
@@ -225,6 +249,10 @@ int prdpt_ctx_create(int device, void* stream, size_t hbm_budget, prdpt_ctx** ou
   ctx->device = device;
   ctx->budget = hbm_budget;
   ctx->stream = (hipStream_t)stream;  // NULL: the device's null stream
+  // this device's copy of the allocation-free estimate's scratch array (a
+  // failed lookup only disables that entry point)
+  ctx->scratch_status = noalloc_scratch(device, &ctx->scratch);
+  if (ctx->scratch_status != hipSuccess) ctx->scratch = nullptr;
   *out = ctx;
   return PRDPT_OK;
 }
@@ -698,6 +726,49 @@ int prdpt_grad_estimate_async(prdpt_scene* s, const float* ref_dev, const float*
   HIP_TRY(hipSetDevice(ctx->device));
   return enqueue_estimate(s, ref_dev, theta_dev, sigma_dev, N, seed, est, grad_dev, loss_dev,
                           losses_dev, c_dev);
+}
+
+int prdpt_grad_estimate_noalloc(prdpt_scene* s, const float* ref_dev, const float* theta_dev,
+                                const float* sigma_dev, int N, uint64_t seed, int est,
+                                double* grad_dev, double* loss_dev, double* losses_dev,
+                                double* c_dev) {
+  if (int rc = check_request(s, theta_dev, sigma_dev, N, false)) return rc;
+  if (int rc = check_est(est)) return rc;
+  if (!ref_dev || !grad_dev || !loss_dev) return fail(PRDPT_E_ARG, "null device pointer");
+  prdpt_ctx* ctx = s->ctx;
+  const SceneHdr& h = s->hdr;
+  const size_t d = (size_t)h.n_param, rows = (size_t)n_draws(est, N);
+  const size_t n_tiles = (size_t)render_tiles(h.W, h.H);
+  // the estimate's arrays, each at a 256-byte boundary of the scratch array
+  size_t used = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = used;
+    used += (bytes + 255) & ~(size_t)255;
+    return at;
+  };
+  const size_t oX = take((size_t)N * d * sizeof(float));
+  const size_t otau = take(rows * d * sizeof(float));
+  const size_t oc = c_dev ? 0 : take(rows * d * sizeof(double));
+  const size_t opart = take((size_t)N * n_tiles * sizeof(float));
+  const size_t oL = losses_dev ? 0 : take((size_t)N * sizeof(double));
+  const size_t owork = take(sizeof(int));
+  if (used > (size_t)PRDPT_NOALLOC_SCRATCH_BYTES)
+    return fail(PRDPT_E_ARG, "the request needs " + std::to_string(used) +
+                                 " bytes of scratch, more than the allocation-free estimate's " +
+                                 std::to_string((size_t)PRDPT_NOALLOC_SCRATCH_BYTES));
+  std::lock_guard<std::mutex> g(ctx->mu);
+  HIP_TRY(hipSetDevice(ctx->device));
+  if (!ctx->scratch)
+    return fail(PRDPT_E_HIP, std::string("scratch array unavailable: ") +
+                                 hipGetErrorString(ctx->scratch_status));
+  char* base = static_cast<char*>(ctx->scratch);
+  const EstimateBufs b{reinterpret_cast<float*>(base + oX), reinterpret_cast<float*>(base + otau),
+                       c_dev ? nullptr : reinterpret_cast<double*>(base + oc),
+                       reinterpret_cast<float*>(base + opart),
+                       losses_dev ? nullptr : reinterpret_cast<double*>(base + oL),
+                       reinterpret_cast<int*>(base + owork)};
+  return enqueue_into(s, ref_dev, theta_dev, sigma_dev, N, seed, est, grad_dev, loss_dev,
+                      losses_dev, c_dev, b, false);
 }
 
 int prdpt_combine_async(prdpt_ctx* ctx, int rows, int d, const double* c_dev,

@@ -40,6 +40,10 @@ hipError_t launch_batch(hipStream_t st, const BatchReq* reqs, BatchMeta* meta, i
                         int rot, int max_sph, float* tau, double* c, float* X,
                         float* partial, double* losses, double* grads, double* loss);
 hipError_t launch_copy(hipStream_t st, const void* src, void* dst, size_t n16);
+// device address of the current device's copy of the allocation-free
+// estimate's scratch array (PRDPT_NOALLOC_SCRATCH_BYTES), looked up once per
+// device; `device` must be current
+hipError_t noalloc_scratch(int device, void** out);
 
 // records `msg` as the calling thread's last error and returns `code`
 int fail(int code, const std::string& msg);
@@ -125,6 +129,9 @@ struct prdpt_ctx {
   prdpt::DevBuf<double> c, losses, grad, loss;
   prdpt::DevBuf<unsigned long long> counters;
   prdpt::DevBuf<int> work;  // work counter of the persistent render kernel
+  // this device's scratch array of prdpt_grad_estimate_noalloc (null: lookup failed)
+  void* scratch = nullptr;
+  hipError_t scratch_status = hipSuccess;
   // the synchronous estimate's inputs [theta | sigma] and outputs
   // [grad | loss | losses], each moved by one copy through pinned host memory
   prdpt::DevBuf<float> vin;

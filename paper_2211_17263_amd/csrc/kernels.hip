@@ -18,6 +18,7 @@
 #include <algorithm>
 #include <cstddef>
 #include <cstdint>
+#include <mutex>
 
 #include "prdpt_internal.h"
 
@@ -1492,11 +1493,35 @@ __global__ __launch_bounds__(256) void copy_kernel(const float4* __restrict__ sr
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
 }
 
+// Scratch of the allocation-free estimate (prdpt_grad_estimate_noalloc): one
+// fixed array that every device the library runs on holds until the process
+// ends.  Host code never passes this name to a kernel (on the host it is a
+// stand-in, not a device address); it uses the address noalloc_scratch looked
+// up for the device.
+static __device__ __align__(256) unsigned char scratch[PRDPT_NOALLOC_SCRATCH_BYTES];
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
 // launchers (host)
 // ---------------------------------------------------------------------------
+hipError_t noalloc_scratch(int device, void** out) {
+  static std::mutex mu;
+  static void* addr[64] = {};
+  if (!out) return hipErrorInvalidValue;
+  *out = nullptr;
+  if (device < 0 || device >= 64) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> g(mu);
+  if (!addr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[device] = p;
+  }
+  *out = addr[device];
+  return hipSuccess;
+}
+
 int render_tiles(int W, int H) { return ((W + kTileW - 1) / kTileW) * ((H + kTileH - 1) / kTileH); }
 
 hipError_t launch_tau(hipStream_t st, int est, int d, int P, uint64_t seed, const float* sigma,

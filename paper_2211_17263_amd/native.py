@@ -34,6 +34,7 @@ EXPORTS = [
     "prdpt_server_start", "prdpt_server_add_job", "prdpt_server_submit", "prdpt_server_cancel",
     "prdpt_server_poll", "prdpt_server_get_stats", "prdpt_server_stop",
     "prdpt_server_submit_deadline", "prdpt_debug_fail_allocations",
+    "prdpt_grad_estimate_noalloc",
 ]
 
 
@@ -114,6 +115,7 @@ def load():
     L.prdpt_smoothed_loss.argtypes = [vp, vp, vp, vp, i32, u64, vp]
     L.prdpt_grad_estimate.argtypes = [vp, vp, vp, vp, i32, u64, i32, vp, vp, vp]
     L.prdpt_grad_estimate_async.argtypes = [vp, vp, vp, vp, i32, u64, i32, vp, vp, vp, vp]
+    L.prdpt_grad_estimate_noalloc.argtypes = [vp, vp, vp, vp, i32, u64, i32, vp, vp, vp, vp]
     L.prdpt_combine_async.argtypes = [vp, i32, i32, vp, vp, vp, vp, i32]
     L.prdpt_ctx_set_timing.argtypes = [vp, i32]
     L.prdpt_ctx_read_timing.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
@@ -328,6 +330,16 @@ def prdpt_grad_estimate_async(scene, ref, theta, sigma, N, seed, est, grad, loss
                               c=None):
     import torch
     _check(load().prdpt_grad_estimate_async(
+        scene.h, _dev(ref, torch.float32), _dev(theta, torch.float32), _dev(sigma, torch.float32),
+        int(N), int(seed), int(est), _dev(grad, torch.float64), _dev(loss, torch.float64),
+        _dev(losses, torch.float64) if losses is not None else None,
+        _dev(c, torch.float64) if c is not None else None))
+
+
+def prdpt_grad_estimate_noalloc(scene, ref, theta, sigma, N, seed, est, grad, loss, losses=None,
+                                c=None):
+    import torch
+    _check(load().prdpt_grad_estimate_noalloc(
         scene.h, _dev(ref, torch.float32), _dev(theta, torch.float32), _dev(sigma, torch.float32),
         int(N), int(seed), int(est), _dev(grad, torch.float64), _dev(loss, torch.float64),
         _dev(losses, torch.float64) if losses is not None else None,
