@@ -5,16 +5,22 @@ One step = one pass of the whole hot path over one batch of synthetic input:
 draw the antithetic perturbations, path-trace every perturbed scene, reduce each
 image's squared error against the reference, combine the losses with the kernel
 weights in binary64, then the host-side bandwidth schedule and Adam step.  The
-default workload is the global-illumination scene (256x256, 16 spp, 4 bounces,
-6 parameters, N = 16 importance-sampled perturbations).
+default workload is the caustic scene (512x512, 64 spp, 8 bounces, a glass
+sphere focusing an area light past a 50000-triangle occluder, 3 parameters,
+N = 32 importance-sampled perturbations, bandwidth annealed 1.0 -> 0.05); the
+global-illumination scene (256x256, 16 spp, 4 bounces, 6 parameters, N = 16)
+runs beside it under "extra_workloads".
 
 Prints one JSON line.  `value` is gradient estimates per second over the timed
-steps; `roofline` describes the fused render kernel (algorithmic node/triangle/
-reference bytes per launch over its event-timed duration, against 8 TB/s HBM),
-`roofline_alu` the same kernel's algorithmic binary32 arithmetic against the
-157.3 TFLOP/s vector peak, and `valu` its measured VALU issue utilisation;
-`cpu_baseline` is the CPU oracle timed on this host's cores on a bounded sample
-(a subset of the antithetic pairs of one estimate) of the same workload.
+steps, `latency_ms` the per-step distribution (p10/p50/p90/p99); `roofline`
+describes the fused render kernel: algorithmic node/triangle/reference bytes
+per launch over its event-timed duration against 8 TB/s, with the measured
+DRAM rate and the copy probe's achievable rate beside it (`cache_served` when
+the algorithmic rate exceeds what DRAM can deliver); `roofline_alu` is the same
+kernel's algorithmic binary32 arithmetic against the 157.3 TFLOP/s vector peak
+and `valu` its measured VALU issue utilisation; `cpu_baseline` is the CPU
+oracle timed on this host's cores on a bounded sample (antithetic pairs of the
+first timed estimate), and `parity` compares those renders with the GPU's.
 """
 import argparse
 import hashlib
@@ -119,7 +125,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="cornell",
+    ap.add_argument("--workload", default="caustic",
                     choices=["cornell", "toy", "caustic", "batch", "serve", "inverse", "ablation",
                              "highd"])
     ap.add_argument("--serve-seconds", type=float, default=20.0,
@@ -127,8 +133,11 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=200.0,
                     help="serve workload: offered Poisson arrival rate (requests/s)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline leg")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="caustic: skip the short global-illumination run beside the headline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
-                    help="CPU-oracle baseline: run whole estimates until this much time passed")
+                    help="CPU-oracle baseline: render antithetic pairs of the first timed "
+                         "estimate until this much time passed")
     ap.add_argument("--seed", type=int, default=1000)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run the streaming-copy probe (1 GiB, 20 copies) and print its rate")
@@ -159,10 +168,29 @@ def main():
     if args.workload == "ablation":
         return bench_ablation(args, NV)
 
-    pr, desc, sigma0, sigma_end = workload(args.workload)
+    out = bench_estimator(args, NV, args.workload, cpu=not args.no_cpu)
+    if args.workload == "caustic" and not args.no_extra:
+        # the global-illumination workload beside the headline (short, no CPU leg)
+        sub = argparse.Namespace(**vars(args))
+        sub.steps, sub.warmup = 20, 5
+        gi = bench_estimator(sub, NV, "cornell", cpu=False)
+        out["extra_workloads"] = {"cornell": {k: gi[k] for k in (
+            "value", "unit", "ms_per_step", "latency_ms", "config", "paths_per_s", "kernel",
+            "roofline", "roofline_alu", "simd_efficiency")}}
+    print(json.dumps(out), flush=True)
+
+
+def bench_estimator(args, NV, name, cpu=True):
+    """W warm-up and K timed steps of one estimator workload: per step the
+    bandwidth of the annealing schedule, one prdpt_grad_estimate (perturbation
+    draw, fused render + loss, losses, binary64 combine; inputs resident on the
+    device, theta/sigma up and the gradient down through pinned memory) and
+    the host Adam step.  Then the work of the timed launches (counting kernel),
+    the roofline figures, and, with cpu, the oracle leg (timing + parity)."""
+    import torch
+    pr, desc, sigma0, sigma_end = workload(name)
     scene = pr["scene"]
     N, est, d = pr["N"], pr["est"], scene.d
-    P = N // 2
     H, W, spp = scene.height, scene.width, scene.spp
     total_steps = args.warmup + args.steps
 
@@ -170,7 +198,7 @@ def main():
     t_build = time.perf_counter()
     sc = NV.prdpt_scene_create(ctx, scene)
     t_build = time.perf_counter() - t_build
-    log(f"workload {args.workload}: {W}x{H} spp={spp} N={N} d={d}, scene built in {t_build:.2f} s")
+    log(f"workload {name}: {W}x{H} spp={spp} N={N} d={d}, scene built in {t_build:.2f} s")
     ref = NV.prdpt_render_reference(sc, pr["theta_ref"], args.seed + 7)
 
     theta = pr["theta0"].astype(np.float64)
@@ -189,7 +217,7 @@ def main():
         r = NV.prdpt_grad_estimate(sc, ref, th32, s, N, seed, est)
         NV.prdpt_adam_step(theta, r["grad"], m, v, t + 1, lr)
         lat.append(time.perf_counter() - t0)
-        trajectory.append((th32, s, seed))
+        trajectory.append((th32, s, seed, r))
         return r
 
     for t in range(args.warmup):
@@ -212,20 +240,24 @@ def main():
 
     # algorithmic work of the timed launches, replayed with the counting kernel
     # (at most 8 evenly spaced timed steps; the per-estimate mean stands for all)
-    cnt = {"nodes": 0, "tris": 0, "rays": 0, "paths": 0, "wave_node_iters": 0,
-           "wave_tri_iters": 0, "wave_ray_iters": 0, "idle_lane_iters": 0}
+    keys = ("nodes", "tris", "rays", "paths", "wave_node_iters", "wave_tri_iters",
+            "wave_ray_iters", "idle_lane_iters", "overflow_pushes")
+    cnt = {k: 0 for k in keys}
+    deepest = 0
     counted = sorted(set(np.linspace(0, len(trajectory) - 1, min(8, len(trajectory))).round().astype(int)))
     for i in counted:
-        th32, s, seed = trajectory[i]
+        th32, s, seed, _ = trajectory[i]
         c = NV.prdpt_traversal_counts(sc, th32, s, N, seed, est)
-        for k in cnt:
+        for k in keys:
             cnt[k] += c[k]
+        deepest = max(deepest, c["deepest_stack"])
     K = args.steps
-    per = {k: cnt[k] / len(counted) for k in cnt}
+    per = {k: cnt[k] / len(counted) for k in keys}
     alg_bytes = per["nodes"] * NODE_BYTES + per["tris"] * TRI_BYTES + N * H * W * REF_BYTES_PER_PIXEL
     kernel_avg_s = (kernel_ms / launches) / 1e3 if launches else float("nan")
     achieved = alg_bytes / kernel_avg_s / 1e9
     paths_per_est = N * H * W * spp
+    lat_ms = 1e3 * np.asarray(lat)
 
     out = {
         "metric": "gradient estimates/sec and paths/sec at 1e-4 rel. error; p50/p99 request latency",
@@ -240,18 +272,26 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": args.workload, "scene": desc, "width": W, "height": H, "spp": spp,
+        "config": {"workload": name, "scene": desc, "width": W, "height": H, "spp": spp,
                    "max_bounces": scene.max_bounces, "params": d, "N": N,
-                   "estimator": ["gauss", "is", "is_perdim"][est], "triangles": scene.n_tris},
+                   "estimator": ["gauss", "is", "is_perdim"][est], "triangles": scene.n_tris,
+                   "sigma": f"{float(sigma0[0]):g} -> {float(sigma_end[0]):g} linearly over the "
+                            f"{total_steps} steps" if float(sigma0[0]) != float(sigma_end[0])
+                            else f"{float(sigma0[0]):g}"},
         "paths_per_s": paths_per_est * K / elapsed,
         "rays_per_s": per["rays"] * K / elapsed,
-        "latency_ms": {"p50": 1e3 * float(np.percentile(lat, 50)),
-                       "p99": 1e3 * float(np.percentile(lat, 99))},
+        "latency_ms": {"p10": float(np.percentile(lat_ms, 10)),
+                       "p50": float(np.percentile(lat_ms, 50)),
+                       "p90": float(np.percentile(lat_ms, 90)),
+                       "p99": float(np.percentile(lat_ms, 99)),
+                       "mean": float(lat_ms.mean())},
         "kernel": {"name": "render_loss_kernel", "avg_ms": 1e3 * kernel_avg_s, "launches": launches,
                    "share_of_step": (kernel_ms / 1e3) / elapsed},
         "work_per_estimate": {"nodes": per["nodes"], "triangles": per["tris"], "rays": per["rays"],
-                              "paths": per["paths"], "counted_steps": len(counted)},
-        "step_ms_by_sigma": {f"{float(trajectory[i][1][0]):.4g}": 1e3 * lat[i] for i in
+                              "paths": per["paths"], "counted_steps": len(counted),
+                              "stack_pushes_beyond_lds": per["overflow_pushes"],
+                              "deepest_stack": deepest},
+        "step_ms_by_sigma": {f"{float(trajectory[i][1][0]):.4g}": float(lat_ms[i]) for i in
                              sorted({0, len(lat) // 2, len(lat) - 1})},
         "simd_efficiency": {
             "node_loop": per["nodes"] / max(64 * per["wave_node_iters"], 1),
@@ -259,23 +299,31 @@ def main():
             "ray_loop": per["rays"] / max(64 * per["wave_ray_iters"], 1),
             "ray_loop_lanes_idle_done": per["idle_lane_iters"] / max(64 * per["wave_ray_iters"], 1)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_profile(args.workload)},
-        "valu": valu_from_profile(args.workload, kernel_avg_s),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_profile(name),
+                     "achieved_is": "algorithmic bytes (128 B per node visit, 48 B per triangle "
+                                    "test, 12 B per reference pixel read) per launch over the "
+                                    "event-timed launch"},
+        "valu": valu_from_profile(name, kernel_avg_s),
         "roofline_alu": alu_roofline(per, kernel_avg_s),
         "scene_build_s": t_build,
         "final_loss": last["loss"],
     }
-
+    rf = out["roofline"]
     achievable = copy_rate(ctx, NV, 256 << 20, 10)
-    out["roofline"]["achievable_copy_GBps"] = achievable
-    out["roofline"]["frac_of_achievable"] = achieved / achievable
-    if not args.no_cpu:
+    rf["achievable_copy_GBps"] = achievable
+    rf["frac_of_achievable"] = achieved / achievable
+    # above the copy probe's rate the gather is served from L2 / Infinity Cache
+    rf["cache_served"] = bool(achieved > achievable)
+    if rf["traffic"] is not None:
+        rf["dram_GBps"] = rf["traffic"] / kernel_avg_s / 1e9
+        rf["dram_frac"] = rf["dram_GBps"] / HBM_PEAK_GBS
+    rf["fp32_frac"] = out["roofline_alu"]["frac"]
+    if cpu:
         log("CPU oracle baseline leg")
-        out["cpu_baseline"], out["parity"] = cpu_leg(sc, pr, sigma0, args, NV)
-
+        out["cpu_baseline"], out["parity"] = cpu_leg(sc, pr, ref, trajectory[0], args, NV)
     sc.destroy()
     ctx.close()
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def bench_inverse(args, NV):
@@ -705,42 +753,61 @@ def copy_rate(ctx, NV, nbytes, iters):
     return 2 * nbytes / (ms / 1e3) / 1e9
 
 
-def cpu_leg(sc, pr, sigma0, args, NV):
-    """CPU oracle timed on a bounded sample of the same workload: whole estimates
-    (all antithetic pairs) with consecutive seeds until about --cpu-seconds of
-    work are done; then the GPU per-image losses are checked against the oracle's
-    on the first of those estimates (same reference, parameters and seed)."""
+def cpu_leg(sc, pr, ref, first, args, NV):
+    """The CPU oracle on the host's cores, on a bounded sample of the same
+    workload: the antithetic pairs of the first timed estimate (same
+    parameters, bandwidth, seed and reference), rendered pair by pair until
+    about --cpu-seconds have passed (the whole estimate when it fits).  The
+    oracle is built for this host (-O3 -march=native; bit-identical to the
+    tests' build).  Parity on the same sample: every rendered oracle image
+    against the GPU's image of the same perturbation, pixel by pixel, its loss
+    against the GPU's per-image loss, and, when all pairs were rendered, the
+    gradient."""
     import torch
 
+    from oracle import build as OB
     from oracle import oracle as O
+    from tests import parity as PT
+    try:
+        O.use_library(OB.build(native=True))
+        build = "gcc -O3 -march=native (host-tuned)"
+    except Exception as e:  # noqa: BLE001 - the portable build gives the same results
+        log(f"host-tuned oracle build failed ({e}); timing the portable build")
+        build = "gcc -O3 (portable)"
     scene = pr["scene"]
     N, est = pr["N"], pr["est"]
+    P = N // 2
+    th32, sigma, seed, r = first
     cores = len(os.sched_getaffinity(0))
     osc = O.OracleScene(scene)
-    ref_o = osc.reference(pr["theta_ref"], seed=args.seed + 7, nthreads=cores)
-    theta = pr["theta0"].astype(np.float32)
-    first = None
-    reps = 0
-    t0 = time.perf_counter()
-    while True:
-        o = osc.grad_estimate(ref_o, theta, sigma0, N, args.seed + reps, est, nthreads=cores)
-        first = first or o
-        reps += 1
-        dt = time.perf_counter() - t0
-        if dt >= args.cpu_seconds or reps >= 64:
+    ref_h = ref.cpu().numpy()
+    imgs = NV.prdpt_render_perturbed(sc, th32, sigma, N, seed, est)[0].cpu().numpy()
+    tau, c = O.draw_tau(est, sigma, P, seed)
+    L = np.zeros(N)
+    worst_img = {"flips": 0, "rel_rmse": 0.0}
+    t_cpu = 0.0
+    done = 0
+    while done < P:
+        p = done
+        for mm in range(2):
+            X = (th32 + tau[p]) if mm == 0 else (th32 - tau[p])
+            t1 = time.perf_counter()
+            img = osc.render(X.astype(np.float32), tag=O.TAG_PATH, pair=p, seed=seed, nthreads=cores)
+            t_cpu += time.perf_counter() - t1
+            L[2 * p + mm] = O.mse(img, ref_h)
+            st = PT.image_stats(imgs[2 * p + mm], img)
+            worst_img["flips"] = max(worst_img["flips"], st["flips"])
+            worst_img["rel_rmse"] = max(worst_img["rel_rmse"], st["rel_rmse"])
+        done += 1
+        if t_cpu >= args.cpu_seconds:
             break
-    g = NV.prdpt_grad_estimate(sc, torch.from_numpy(ref_o).cuda(), theta, sigma0, N, args.seed, est)
-    rel = np.abs(g["losses"] - first["losses"]) / np.abs(first["losses"])
-    _, c = O.draw_tau(est, sigma0, N // 2, args.seed)
-    S = (np.abs(c) * (first["losses"][0::2] + first["losses"][1::2])[:, None]).mean(axis=0)
-    gerr = np.abs(g["grad"] - first["grad"]) / S
-    paths = N * scene.width * scene.height * scene.spp
-    # about 4096 evenly spread pixels of one render on one thread: the
-    # single-thread rate beside the all-core one
+    renders = 2 * done
+    paths = renders * scene.width * scene.height * scene.spp
+    # one thread: about 4096 evenly spread pixels of the first render
     npix = scene.width * scene.height
     pix = np.arange(0, npix, max(1, npix // 4096), dtype=np.int32)
     t1 = time.perf_counter()
-    osc.render_pixels(theta, pix, seed=args.seed, nthreads=1)
+    osc.render_pixels((th32 + tau[0]).astype(np.float32), pix, seed=seed, pair=0, nthreads=1)
     single = time.perf_counter() - t1
     model = ""
     try:
@@ -748,19 +815,26 @@ def cpu_leg(sc, pr, sigma0, args, NV):
             model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
     except OSError:
         pass
-    base = {"value": reps / dt, "unit": "gradient estimates/s", "cores": cores, "kind": "oracle",
-            "sample": f"{reps} whole estimate(s) ({reps * N} renders, {reps * paths} paths) "
-                      f"in {dt:.1f} s",
-            "paths_per_s": reps * paths / dt, "cpu_model": model,
+    base = {"value": (renders / N) / t_cpu, "unit": "gradient estimates/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"{renders} of the {N} renders of the first timed estimate "
+                      f"({done} antithetic pair(s), {paths} paths) in {t_cpu:.1f} s on {cores} "
+                      f"threads; estimates/s = renders per second / N",
+            "paths_per_s": paths / t_cpu, "cpu_model": model, "build": build,
             "single_thread_paths_per_s": pix.size * scene.spp / single}
-    sig = np.abs(first["grad"]) >= 0.1 * S          # components well above the cancellation scale
-    grel = np.abs(g["grad"] - first["grad"])[sig] / np.abs(first["grad"])[sig]
-    parity = {"checked_renders": N, "max_rel_loss_err": float(rel.max()),
-              "max_grad_err_over_scale": float(gerr.max()),
-              "max_rel_grad_err_significant": float(grel.max()) if grel.size else None,
-              "significant_components": int(sig.sum()),
-              "q_hat_gpu": float(g["loss"]), "q_hat_oracle": float(first["loss"]),
-              "pass_1e-4": bool(rel.max() <= 1e-4 and gerr.max() <= 1e-4)}
+    rel = np.abs(r["losses"][:renders] - L[:renders]) / np.abs(L[:renders])
+    parity = {"checked_renders": renders, "of_renders": N, "pixels_per_render": npix,
+              "max_flip_pixels": int(worst_img["flips"]), "max_image_rel_rmse": worst_img["rel_rmse"],
+              "max_rel_loss_err": float(rel.max()),
+              "pass_1e-4": bool(worst_img["flips"] == 0 and worst_img["rel_rmse"] <= PT.REL_RMSE
+                                and rel.max() <= PT.LOSS_REL)}
+    if done == P:
+        g_orc, q_orc = O.combine(c, L)
+        S = PT.grad_scale(c, L)
+        gerr = np.abs(r["grad"] - g_orc) / S
+        parity.update({"max_grad_err_over_scale": float(gerr.max()),
+                       "q_hat_gpu": float(r["loss"]), "q_hat_oracle": float(q_orc)})
+        parity["pass_1e-4"] = bool(parity["pass_1e-4"] and gerr.max() <= PT.GRAD_REL)
     return base, parity
 
 
