@@ -366,10 +366,18 @@ int prdpt::build_host_scene(const prdpt_scene_desc* D, HostScene& hs) {
     h.mat_type[i] = D->mat_type[i];
     for (int c = 0; c < 3; ++c) h.mat_rgb[i][c] = D->mat_rgb[3 * i + c];
     h.mat_ior[i] = D->mat_ior[i];
-    if (h.mat_type[i] == PRDPT_MAT_DIELECTRIC && !(h.mat_ior[i] > 0.0f)) {
-      return fail(PRDPT_E_SCENE, "dielectric ior must be > 0");
+    if (h.mat_type[i] == PRDPT_MAT_DIELECTRIC) {
+      if (!(h.mat_ior[i] > 0.0f) || !std::isfinite(h.mat_ior[i]))
+        return fail(PRDPT_E_SCENE, "dielectric ior must be finite and > 0");
+      // a dielectric has no colour: its first channel carries 1/ior, the
+      // index ratio of a ray entering the body (colour bindings of a
+      // dielectric are refused below)
+      h.mat_rgb[i][0] = 1.0f / h.mat_ior[i];
     }
   }
+  // multiplying by the inverse of a power-of-two size is exact
+  h.inv_w = (h.W & (h.W - 1)) == 0 ? 1.0f / (float)h.W : 0.0f;
+  h.inv_h = (h.H & (h.H - 1)) == 0 ? 1.0f / (float)h.H : 0.0f;
   for (int i = 0; i < h.n_sph; ++i) {
     for (int c = 0; c < 4; ++c) h.sph[i][c] = D->spheres[4 * i + c];
     h.sph_mat[i] = D->sphere_mat[i];
@@ -378,6 +386,9 @@ int prdpt::build_host_scene(const prdpt_scene_desc* D, HostScene& hs) {
   for (int i = 0; i < h.n_quad; ++i) {
     for (int c = 0; c < 9; ++c) h.quad[i][c] = D->quads[9 * i + c];
     quad_frame_host(h.quad[i], h.quad_n[i], h.quad_nu[i]);
+    if (!(h.quad_n[i][3] > 0.0f) || !std::isfinite(h.quad_n[i][3]))
+      return fail(PRDPT_E_SCENE, "quad edges must span a parallelogram");
+    h.quad_lo[i] = quad_neg_limit_host(h.quad_n[i][3]);
     h.quad_mat[i] = D->quad_mat[i];
     if (h.mat_type[h.quad_mat[i]] == PRDPT_MAT_EMISSIVE) h.area_quad[h.n_area++] = i;
   }

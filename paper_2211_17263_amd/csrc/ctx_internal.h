@@ -27,6 +27,8 @@ void euler_rotation_host(const float* ang, float* R);
 // normal and squared length, unit normal and area of a quad [origin, edge1,
 // edge2] (the kernels' operation order)
 void quad_frame_host(const float* q, float* n, float* nu);
+// largest x whose correctly rounded x / nn is below 0 (nn > 0 finite)
+float quad_neg_limit_host(float nn);
 // tiles by descending measured render time (no-op for more than 4096 tiles)
 hipError_t launch_tile_order(hipStream_t st, const float* cost, int* order, int n_tiles);
 hipError_t launch_losses(hipStream_t st, const float* partial, int n_tiles, int N, int npix,

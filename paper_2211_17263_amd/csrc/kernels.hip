@@ -18,6 +18,7 @@
 #include <algorithm>
 #include <cstddef>
 #include <cstdint>
+#include <cstring>
 #include <mutex>
 
 #include "prdpt_internal.h"
@@ -146,9 +147,15 @@ __device__ __forceinline__ bool hit_sphere(V3 o, V3 d, const float* sp, float tm
   return true;
 }
 
-// qn: the quad's edge1 x edge2 and its squared length (per-scene constants)
-__device__ __forceinline__ bool hit_quad(V3 o, V3 d, const float* qd, const float* qn, float tmax,
-                                         float* tout) {
+// qn: the quad's edge1 x edge2 and its squared length nn; qlo: the largest x
+// whose correctly rounded quotient x / nn is below 0 (per-scene constants).
+// A parallelogram coordinate is a numerator X over nn, and the hit needs its
+// rounded quotient in [0, 1]; rounding is monotone, 1 is representable and
+// nn (1 + 2^-24) lies below the float after nn, so round(X / nn) > 1 exactly
+// when X > nn, and round(X / nn) < 0 exactly when X <= qlo: the two tests
+// decide as the divisions would, without dividing.
+__device__ __forceinline__ bool hit_quad(V3 o, V3 d, const float* qd, const float* qn, float qlo,
+                                         float tmax, float* tout) {
   const V3 qo = ld3(qd), e1 = ld3(qd + 3), e2 = ld3(qd + 6);
   const V3 n = ld3(qn);
   const float den = dot(n, d);
@@ -157,10 +164,10 @@ __device__ __forceinline__ bool hit_quad(V3 o, V3 d, const float* qd, const floa
   if (!(t > 0.0f && t < tmax)) return false;
   const V3 pd = sub(at(o, d, t), qo);
   const float nn = qn[3];
-  const float al = dot(cross(pd, e2), n) / nn;
-  if (al < 0.0f || al > 1.0f) return false;
-  const float be = dot(cross(e1, pd), n) / nn;
-  if (be < 0.0f || be > 1.0f) return false;
+  const float al = dot(cross(pd, e2), n);
+  if (al <= qlo || al > nn) return false;
+  const float be = dot(cross(e1, pd), n);
+  if (be <= qlo || be > nn) return false;
   *tout = t;
   return true;
 }
@@ -435,7 +442,7 @@ __device__ __forceinline__ bool begin_trace(const SceneLds& S, const float* __re
   for (int i = 0; i < S.n_quad; ++i) {
     if (any && S.mat_type[S.quad_mat[i]] == PRDPT_MAT_EMISSIVE) continue;
     float t;
-    if (hit_quad(o, d, S.quad[i], S.quad_n[i], tmax, &t)) {
+    if (hit_quad(o, d, S.quad[i], S.quad_n[i], S.quad_lo[i], tmax, &t)) {
       if (any) {
         h.id = S.n_sph + i;
         return true;
@@ -669,8 +676,9 @@ __device__ __forceinline__ void basis(V3 n, V3* b1, V3* b2) {
   *b2 = mk(b, sign + n.y * n.y * a, -n.y);
 }
 
-__device__ __forceinline__ float fresnel_dielectric(float cosi, float ei, float et) {
-  const float eta = ei / et;
+// eta = ei / et (rounded), passed in: the interface is air against the body,
+// so it is either 1/ior or ior, both per-material constants
+__device__ __forceinline__ float fresnel_dielectric(float cosi, float ei, float et, float eta) {
   const float sin2t = (eta * eta) * (1.0f - cosi * cosi);
   if (sin2t >= 1.0f) return 1.0f;
   const float cost = sqrtf(1.0f - sin2t);
@@ -773,6 +781,9 @@ __device__ __forceinline__ void render_tile(const SceneLds& S, const float* __re
   const int pair = crn ? k >> 1 : k;
   const int spp = S.spp;
   const int n_lights = S.n_pl + S.n_area;
+  const float inv_w = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(S.inv_w)));
+  const float inv_h = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(S.inv_h)));
+  const bool pow2_w = inv_w != 0.0f, pow2_h = inv_h != 0.0f;
   int* stk = stack + t;
   int ovf[kStackOverflow];  // stack entries beyond the LDS part (deep descents only)
   Counters cnt{0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
@@ -871,20 +882,21 @@ __device__ __forceinline__ void render_tile(const SceneLds& S, const float* __re
               V3 nn = ng;
               float cosi = -dot(dir, nn);
               float ei = 1.0f, et = ior;
+              float eta = S.mat_rgb[mat][0];  // 1 / ior: entering the body
               if (cosi < 0.0f) {
                 nn = neg(nn);
                 cosi = -cosi;
                 ei = ior;
                 et = 1.0f;
+                eta = ior;  // ior / 1: leaving it
               }
-              const float F = fresnel_dielectric(cosi, ei, et);
+              const float F = fresnel_dielectric(cosi, ei, et, eta);
               V3 nd, side;
               if (unit_open(w.z) < F) {
                 const float dn = dot(dir, nn);
                 nd = mk(dir.x - nn.x * (2.0f * dn), dir.y - nn.y * (2.0f * dn), dir.z - nn.z * (2.0f * dn));
                 side = nn;
               } else {
-                const float eta = ei / et;
                 const float sin2t = (eta * eta) * (1.0f - cosi * cosi);
                 const float cost = sqrtf(1.0f - sin2t);
                 const float kk = eta * cosi - cost;
@@ -1029,8 +1041,10 @@ __device__ __forceinline__ void render_tile(const SceneLds& S, const float* __re
           jyo = unit_open(wj.y);
         }
         const float px = (float)(tx0 + qx) + jxo, py = (float)(ty0 + qy) + jyo;
-        const float sx = 2.0f * (px / (float)S.W) - 1.0f;
-        const float sy = 1.0f - 2.0f * (py / (float)S.H);
+        // dividing by a power of two is exact, and so is multiplying by its
+        // inverse (a wave-uniform choice)
+        const float sx = 2.0f * (pow2_w ? px * inv_w : px / (float)S.W) - 1.0f;
+        const float sy = 1.0f - 2.0f * (pow2_h ? py * inv_h : py / (float)S.H);
         o = ld3(S.eye);
         dir = unit(mk(S.fwd[0] + S.right[0] * sx + S.up[0] * sy,
                       S.fwd[1] + S.right[1] * sx + S.up[1] * sy,
@@ -1560,6 +1574,33 @@ void euler_rotation_host(const float* ang, float* R) { euler_rotation(ang, R); }
 // normal with the area, in the operation order of the intersection and the
 // shading: cross product, squared length, its sqrt, one reciprocal, three
 // products.
+// Largest binary32 x whose correctly rounded quotient x / nn is below 0, for
+// nn > 0 finite: round(x / nn) < 0 exactly when x < -nn 2^-150 (half the
+// smallest subnormal; the tie rounds to -0), so this is minus the smallest
+// float above nn 2^-150.  Computed on the bit pattern (no floating-point
+// operation, so no dependence on the host's subnormal modes).
+float quad_neg_limit_host(float nn) {
+  uint32_t b;
+  std::memcpy(&b, &nn, 4);
+  const uint32_t eb = (b >> 23) & 0xffu, m = b & 0x7fffffu;
+  uint32_t y;  // bits of the smallest float above nn 2^-150
+  if (eb > 150) {
+    y = ((eb - 150) << 23 | m) + 1;  // nn 2^-150 is itself a normal float
+  } else if (eb == 0) {
+    y = 1;  // subnormal nn: nn 2^-150 is below the smallest subnormal
+  } else {
+    // nn 2^-150 = (2^23 + m) 2^(eb - 300), in units of the smallest subnormal
+    // 2^-149: (2^23 + m) 2^(eb - 151), below one unit shifted out
+    const int sh = 151 - (int)eb;
+    const uint32_t q = sh >= 32 ? 0u : ((0x800000u | m) >> sh);
+    y = q + 1;
+  }
+  y |= 0x80000000u;
+  float out;
+  std::memcpy(&out, &y, 4);
+  return out;
+}
+
 void quad_frame_host(const float* q, float* n, float* nu) {
   const float ax = q[3], ay = q[4], az = q[5], bx = q[6], by = q[7], bz = q[8];
   const float nx = ay * bz - az * by, ny = az * bx - ax * bz, nz = ax * by - ay * bx;

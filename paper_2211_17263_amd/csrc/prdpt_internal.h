@@ -65,13 +65,15 @@ struct SceneLds {
   int32_t W, H, spp, B, pixel_center;
   int32_t n_mat, n_sph, n_quad, n_inst, n_pl, n_param, n_area, n_tri;
   int32_t tri_id_base;                       // n_sph + n_quad
+  float inv_w, inv_h;                        // 1/W, 1/H when W, H are powers of two, else 0
   int32_t mat_type[PRDPT_MAX_MATERIALS];
-  float mat_rgb[PRDPT_MAX_MATERIALS][3];
+  float mat_rgb[PRDPT_MAX_MATERIALS][3];     // a dielectric's [0] holds 1/ior (rounded)
   float mat_ior[PRDPT_MAX_MATERIALS];
   float quad[PRDPT_MAX_QUADS][9];
   int32_t quad_mat[PRDPT_MAX_QUADS];
   int32_t area_quad[PRDPT_MAX_QUADS];        // emissive quads in index order
-  float quad_n[PRDPT_MAX_QUADS][4];          // edge1 x edge2 and its squared length
+  float quad_n[PRDPT_MAX_QUADS][4];          // edge1 x edge2 and its squared length nn
+  float quad_lo[PRDPT_MAX_QUADS];            // largest x whose rounded x / nn is below 0
   float quad_nu[PRDPT_MAX_QUADS][4];         // unit normal and area (edges are never bound)
   int32_t inst_root[PRDPT_MAX_INSTANCES];    // root node of each instance BVH (-1: empty)
   float inst_xlate[PRDPT_MAX_INSTANCES][3];

@@ -7,6 +7,7 @@
 // checks, the host optimiser step, and context creation without a device.
 #include <cmath>
 #include <cstdio>
+#include <cstring>
 #include <cstdlib>
 #include <random>
 #include <vector>
@@ -189,6 +190,44 @@ int main(int argc, char** argv) {
     std::printf("deep depth4=%d stack_bound=%d lds_entries=%d private_entries=%d\n", depth,
                 3 * depth + 1, kStackEntries, kStackOverflow);
     CHECK(3 * depth + 1 <= kStackBound);
+  }
+  // ---- the division-free quad coordinate test decides as the division does:
+  // (x <= lo || x > nn) == (round(x / nn) < 0 || round(x / nn) > 1)
+  {
+    std::mt19937 rng(11);
+    std::uniform_real_distribution<float> ue(-140.0f, 120.0f);
+    long long checked = 0, mismatches = 0;
+    auto agree = [&](float x, float nn, float lo) {
+      const float q = x / nn;
+      const bool div = q < 0.0f || q > 1.0f;
+      const bool cmp = x <= lo || x > nn;
+      ++checked;
+      if (div != cmp) ++mismatches;
+    };
+    auto step = [](float v, int k) {
+      while (k > 0) { v = std::nextafter(v, INFINITY); --k; }
+      while (k < 0) { v = std::nextafter(v, -INFINITY); ++k; }
+      return v;
+    };
+    std::vector<float> nns = {1.0f, 2.0f, 1.5f, 3.99f, 160000.0f, 3.0e38f, 1e-30f, 1.2e-38f,
+                              0.0625f, 1.0000001f, 1.9999999f};
+    for (int i = 0; i < 3000; ++i) nns.push_back(std::ldexp(1.0f + (float)(rng() % 1000) / 1000.0f,
+                                                            (int)ue(rng)));
+    for (float nn : nns) {
+      if (!(nn > 0.0f) || !std::isfinite(nn)) continue;
+      const float lo = quad_neg_limit_host(nn);
+      for (float c : {0.0f, -0.0f, lo, nn, -nn, std::ldexp(nn, -150), -std::ldexp(nn, -150),
+                      1.0f, -1.0f})
+        for (int k = -40; k <= 40; ++k) agree(step(c, k), nn, lo);
+      for (int k = 0; k < 200; ++k) {
+        uint32_t b = (uint32_t)rng();
+        float x;
+        std::memcpy(&x, &b, 4);
+        agree(x, nn, lo);
+      }
+    }
+    std::printf("quad limits: %lld cases, %lld mismatches\n", checked, mismatches);
+    CHECK(mismatches == 0);
   }
   // ---- validation failures
   {
