@@ -1117,3 +1117,385 @@ void orc_adam_step(int d, double* theta, const double* g, double* m, double* v, 
     theta[j] -= lr * mh / (sqrt(vh) + eps);
   }
 }
+
+/* ========================================================================= */
+/* Eq. 9: the smoothed gradient through a differentiable renderer            */
+/* ========================================================================= */
+/* For scenes of one diffuse sphere (the parameters move its centre) over one
+ * diffuse quad (the ground) lit by one point light, rendered with direct
+ * light only.  The pixel value is the box-filtered integral of the point
+ * radiance f(x; theta) over the pixel (Sec. 2.1, Eq. 1-3); its derivative
+ * (Reynolds transport in the image plane) is
+ *     dI/dtheta = int_pixel df/dtheta dx  +  sum over moving edges of
+ *                 int_edge (f_inside - f_outside) (v . n_out) dl,
+ * the interior term from the shading of the sphere (the hit point and normal
+ * move with the centre; the ground's shading does not depend on theta), and
+ * edge terms on the two discontinuities that move: the sphere's silhouette
+ * and the boundary of its shadow on the ground.  Both edges are closed curves
+ * traced by a circle of tangent points on the sphere (seen from the eye, and
+ * from the light); they are sampled uniformly in the circle's angle (edge
+ * sampling), each sample adding to the pixel it falls in.  The estimator of
+ * Eq. 9 with perturbations drawn from the kernel (the kernel weight then
+ * drops, as for Eq. 7) is
+ *     g = (1/N) sum_k dL/dtheta (theta + tau_k),
+ *     dL/dtheta = 2/(3HW) sum_px,c (I_k - R) dI_k/dtheta,
+ * with I_k the rendered image and dI_k/dtheta from samples independent of
+ * it (interior jitter from stream tag 6, edge angles from tag 7), so that the
+ * product estimates the gradient of the loss of the expected image.
+ * Per-sample arithmetic is binary32 in a fixed order; sums are binary64. */
+
+#define ORC_TAG_DIFF 6
+#define ORC_TAG_EDGE 7
+#define DP_SILHOUETTE 1
+#define DP_SHADOW 2
+
+/* the scene checks of the differentiable renderer; 0 if supported */
+static int dp_supported(const orc_scene* s) {
+  if (s->n_sph != 1 || s->n_quad != 1 || s->n_mesh != 0 || s->n_tri != 0 || s->n_pl != 1) return -1;
+  if (s->B != 0) return -1;
+  if (s->mat_type[s->sph_mat[0]] != ORC_DIFFUSE || s->mat_type[s->quad_mat[0]] != ORC_DIFFUSE) return -1;
+  if (s->n_param < 1 || s->n_param > 3) return -1;
+  for (int j = 0; j < s->n_param; ++j)
+    if (s->binding[3 * j] != ORC_BIND_SPHERE || s->binding[3 * j + 1] != 0) return -1;
+  return 0;
+}
+
+/* image position (pixel units, x right, y down) of world point X, and the
+ * rows of its Jacobian d(px, py)/dX */
+static void dp_project(const orc_scene* s, v3 X, float* px, float* py, v3* jx, v3* jy) {
+  v3 e = vld(s->eye), f = vld(s->fwd), r = vld(s->right), u = vld(s->up);
+  v3 D = vsub(X, e);
+  float lam = vdot(D, f), a = vdot(D, r), b = vdot(D, u);
+  float rr = vdot(r, r), uu = vdot(u, u);
+  float sx = a / (lam * rr), sy = b / (lam * uu);
+  float hw = 0.5f * (float)s->W, hh = 0.5f * (float)s->H;
+  *px = (sx + 1.0f) * hw;
+  *py = (1.0f - sy) * hh;
+  /* d sx / dX = (r lam - f a) / (lam^2 rr), d sy / dX = (u lam - f b) / (lam^2 uu) */
+  float l2r = (lam * lam) * rr, l2u = (lam * lam) * uu;
+  v3 gx = V((r.x * lam - f.x * a) / l2r, (r.y * lam - f.y * a) / l2r, (r.z * lam - f.z * a) / l2r);
+  v3 gy = V((u.x * lam - f.x * b) / l2u, (u.y * lam - f.y * b) / l2u, (u.z * lam - f.z * b) / l2u);
+  *jx = vscale(gx, hw);
+  *jy = vscale(gy, -hh);
+}
+
+/* direct radiance (rgb) leaving a diffuse point p with unit normal n toward
+ * the viewer, lit by the point light, without a shadow test */
+static void dp_shade(const orc_scene* s, const kstate* k, int mat, v3 p, v3 n, float out[3]) {
+  const float* lp = k->pl;
+  v3 toL = vsub(vld(lp), p);
+  float dist2 = vdot(toL, toL);
+  float dist = sqrtf(dist2);
+  v3 wi = vscale(toL, 1.0f / dist);
+  float cx = vdot(n, wi);
+  for (int c = 0; c < 3; ++c)
+    out[c] = cx > 0.0f ? (k->rgb[3 * mat + c] * INV_PI_F) * ((lp[3 + c] * cx) / dist2) : 0.0f;
+}
+
+/* the ground's unit normal, oriented toward the light */
+static v3 dp_ground_normal(const kstate* k) {
+  v3 n = vnorm(vcross(vld(k->quad + 3), vld(k->quad + 6)));
+  if (vdot(n, vsub(vld(k->pl), vld(k->quad))) < 0.0f) n = vneg(n);
+  return n;
+}
+
+/* radiance seen along a ray that leaves the sphere's silhouette tangentially:
+ * the ground behind it (shadowed by the sphere or not), or the environment */
+static void dp_behind(const orc_scene* s, const kstate* k, v3 o, v3 d, float out[3]) {
+  float t;
+  if (!quad_test(o, d, k->quad, INFINITY, &t)) {
+    for (int c = 0; c < 3; ++c) out[c] = s->env[c];
+    return;
+  }
+  v3 g = vray(o, d, t);
+  v3 n = dp_ground_normal(k);
+  v3 toL = vsub(vld(k->pl), g);
+  float dist = sqrtf(vdot(toL, toL));
+  v3 wi = vscale(toL, 1.0f / dist);
+  float ts;
+  if (sphere_test(spawn(g, n), wi, k->sph, dist * 0.9999f, &ts)) {
+    out[0] = out[1] = out[2] = 0.0f;
+    return;
+  }
+  dp_shade(s, k, s->quad_mat[0], g, n, out);
+}
+
+/* One silhouette sample at angle fraction `frac` of a turn: its pixel, the
+ * radiance step inside minus outside, the normal speed of the edge in pixels
+ * per unit move of each centre axis, and the edge length per radian (pixels).
+ * Returns 0 if the sample falls outside the image. */
+static int dp_silhouette(const orc_scene* s, const kstate* k, float frac, int* pix, float df[3],
+                         float vn[3], float* dl) {
+  v3 e = vld(s->eye), c = vld(k->sph);
+  float rho = k->sph[3];
+  v3 a = vsub(e, c);
+  float kk = (rho * rho) / vdot(a, a);
+  v3 cs = V(c.x + a.x * kk, c.y + a.y * kk, c.z + a.z * kk);
+  float rs = rho * sqrtf(1.0f - kk);
+  v3 b1, b2;
+  onb(vnorm(a), &b1, &b2);
+  float sn, cn;
+  orc_sincos_2pi(frac, &sn, &cn);
+  v3 p = V(cs.x + (b1.x * cn + b2.x * sn) * rs, cs.y + (b1.y * cn + b2.y * sn) * rs,
+           cs.z + (b1.z * cn + b2.z * sn) * rs);
+  v3 dp = V((b2.x * cn - b1.x * sn) * rs, (b2.y * cn - b1.y * sn) * rs, (b2.z * cn - b1.z * sn) * rs);
+  float px, py;
+  v3 jx, jy;
+  dp_project(s, p, &px, &py, &jx, &jy);
+  if (!(px >= 0.0f && px < (float)s->W && py >= 0.0f && py < (float)s->H)) return 0;
+  *pix = (int)py * s->W + (int)px;
+  float dx = vdot(jx, dp), dy = vdot(jy, dp);
+  *dl = sqrtf(dx * dx + dy * dy);
+  v3 n = vscale(vsub(p, c), 1.0f / rho);
+  float fin[3], fout[3];
+  dp_shade(s, k, s->sph_mat[0], p, n, fin);
+  v3 dir = vnorm(vsub(p, e));
+  dp_behind(s, k, e, dir, fout);
+  for (int ch = 0; ch < 3; ++ch) df[ch] = fin[ch] - fout[ch];
+  /* tangency h = |c - e|^2 - ((c - e) . w)^2 - rho^2 of the camera ray w:
+   * dh/dc = 2 m with m = c - p = -rho n; along the image, dh/dx =
+   * -2 q (m . dd/dx) / |d| with q = (c - e) . w and d the unnormalised ray
+   * (the camera's fwd + sx right + sy up) of the image point */
+  v3 f = vld(s->fwd), r = vld(s->right), u = vld(s->up);
+  v3 pe = vsub(p, e);
+  float lam = vdot(pe, f);
+  float dlen = sqrtf(vdot(pe, pe)) / lam;
+  float q = vdot(vsub(c, e), dir);
+  v3 m = vscale(n, -rho);
+  float gxx = ((-2.0f * q) / dlen) * (vdot(m, r) * (2.0f / (float)s->W));
+  float gyy = ((-2.0f * q) / dlen) * (vdot(m, u) * (-2.0f / (float)s->H));
+  float gn = sqrtf(gxx * gxx + gyy * gyy);
+  /* outward normal speed of the edge: -(dh/dc) / |dh/dx| = 2 rho n / |dh/dx| */
+  vn[0] = (2.0f * rho * n.x) / gn;
+  vn[1] = (2.0f * rho * n.y) / gn;
+  vn[2] = (2.0f * rho * n.z) / gn;
+  return 1;
+}
+
+/* One sample of the shadow boundary: the ray from the light tangent to the
+ * sphere at angle fraction `frac`, continued to the ground point g; its pixel
+ * (if g is on the ground, in front of the camera, inside the image and not
+ * hidden by the sphere), the lit radiance at g (the step across the edge),
+ * the normal speed of the edge toward the shadow, and the length per radian. */
+static int dp_shadow(const orc_scene* s, const kstate* k, float frac, int* pix, float df[3],
+                     float vn[3], float* dl) {
+  v3 e = vld(s->eye), c = vld(k->sph), L = vld(k->pl);
+  float rho = k->sph[3];
+  v3 a = vsub(L, c);
+  float kk = (rho * rho) / vdot(a, a);
+  v3 cs = V(c.x + a.x * kk, c.y + a.y * kk, c.z + a.z * kk);
+  float rs = rho * sqrtf(1.0f - kk);
+  v3 b1, b2;
+  onb(vnorm(a), &b1, &b2);
+  float sn, cn;
+  orc_sincos_2pi(frac, &sn, &cn);
+  v3 t = V(cs.x + (b1.x * cn + b2.x * sn) * rs, cs.y + (b1.y * cn + b2.y * sn) * rs,
+           cs.z + (b1.z * cn + b2.z * sn) * rs);
+  v3 dt = V((b2.x * cn - b1.x * sn) * rs, (b2.y * cn - b1.y * sn) * rs, (b2.z * cn - b1.z * sn) * rs);
+  v3 np = dp_ground_normal(k);
+  v3 q0 = vld(k->quad);
+  v3 tl = vsub(t, L);
+  float den = vdot(tl, np);
+  if (!(den < 0.0f)) return 0;
+  float lam = vdot(vsub(q0, L), np) / den;
+  if (!(lam > 1.0f)) return 0;
+  v3 g = vray(L, tl, lam);
+  /* on the ground quad */
+  v3 e1 = vld(k->quad + 3), e2 = vld(k->quad + 6), nq = vcross(e1, e2);
+  float nn = vdot(nq, nq);
+  v3 gd = vsub(g, q0);
+  float al = vdot(vcross(gd, e2), nq) / nn, be = vdot(vcross(e1, gd), nq) / nn;
+  if (al < 0.0f || al > 1.0f || be < 0.0f || be > 1.0f) return 0;
+  /* seen by the camera: in front of it, inside the image, not behind the sphere */
+  v3 f = vld(s->fwd), r = vld(s->right), u = vld(s->up);
+  v3 ge = vsub(g, e);
+  float lc = vdot(ge, f);
+  if (!(lc > 0.0f)) return 0;
+  float px, py;
+  v3 jx, jy;
+  dp_project(s, g, &px, &py, &jx, &jy);
+  if (!(px >= 0.0f && px < (float)s->W && py >= 0.0f && py < (float)s->H)) return 0;
+  float gdist = sqrtf(vdot(ge, ge));
+  v3 wc = vscale(ge, 1.0f / gdist);
+  float tsp;
+  if (sphere_test(e, wc, k->sph, gdist * 0.9999f, &tsp)) return 0;
+  *pix = (int)py * s->W + (int)px;
+  /* d g / d angle: the ray parameter lam changes with t */
+  float dlam = -lam * (vdot(dt, np) / den);
+  v3 dg = V(dt.x * lam + tl.x * dlam, dt.y * lam + tl.y * dlam, dt.z * lam + tl.z * dlam);
+  float dx = vdot(jx, dg), dy = vdot(jy, dg);
+  *dl = sqrtf(dx * dx + dy * dy);
+  dp_shade(s, k, s->quad_mat[0], g, np, df);
+  /* tangency of the light ray: h = |c - L|^2 - ((c - L) . w)^2 - rho^2 with w
+   * the unit direction from L to g; dh/dc = 2 m_s, m_s = (c - L) - q_s w;
+   * along the image, dh/dx = -2 q_s (m_s . dg/dx) / |g - L| with
+   * dg/dx = lc [dd/dx - ((dd/dx . np) / (d . np)) d], d = (g - e) / lc */
+  v3 lg = vsub(g, L);
+  float lgd = sqrtf(vdot(lg, lg));
+  v3 w = vscale(lg, 1.0f / lgd);
+  v3 cl = vsub(c, L);
+  float qs = vdot(cl, w);
+  v3 ms = V(cl.x - w.x * qs, cl.y - w.y * qs, cl.z - w.z * qs);
+  v3 d = vscale(ge, 1.0f / lc);
+  float dn = vdot(d, np);
+  v3 ddx = vscale(r, 2.0f / (float)s->W), ddy = vscale(u, -2.0f / (float)s->H);
+  float ax = vdot(ddx, np) / dn, ay = vdot(ddy, np) / dn;
+  v3 dgx = V((ddx.x - d.x * ax) * lc, (ddx.y - d.y * ax) * lc, (ddx.z - d.z * ax) * lc);
+  v3 dgy = V((ddy.x - d.x * ay) * lc, (ddy.y - d.y * ay) * lc, (ddy.z - d.z * ay) * lc);
+  float gxx = ((-2.0f * qs) * vdot(ms, dgx)) / lgd;
+  float gyy = ((-2.0f * qs) * vdot(ms, dgy)) / lgd;
+  float gn = sqrtf(gxx * gxx + gyy * gyy);
+  /* the lit side's outward normal points into the shadow, where h < 0:
+   * speed (dh/dc) / |dh/dx| = 2 m_s / |dh/dx| */
+  vn[0] = (2.0f * ms.x) / gn;
+  vn[1] = (2.0f * ms.y) / gn;
+  vn[2] = (2.0f * ms.z) / gn;
+  return 1;
+}
+
+/* Interior derivative sample at image point (px, py): df/dc (rgb x centre
+ * axis) if the camera ray meets the sphere first, else 0 (the ground's
+ * shading does not depend on the sphere away from the shadow's edge). */
+static void dp_interior(const orc_scene* s, const kstate* k, float px, float py, float out[3][3]) {
+  for (int c = 0; c < 3; ++c)
+    for (int j = 0; j < 3; ++j) out[c][j] = 0.0f;
+  float sx = 2.0f * (px / (float)s->W) - 1.0f;
+  float sy = 1.0f - 2.0f * (py / (float)s->H);
+  v3 e = vld(s->eye);
+  v3 d = vnorm(V(s->fwd[0] + s->right[0] * sx + s->up[0] * sy,
+                 s->fwd[1] + s->right[1] * sx + s->up[1] * sy,
+                 s->fwd[2] + s->right[2] * sx + s->up[2] * sy));
+  float ts, tg;
+  if (!sphere_test(e, d, k->sph, INFINITY, &ts)) return;
+  if (quad_test(e, d, k->quad, ts, &tg)) return;  /* the ground is nearer */
+  v3 c = vld(k->sph);
+  float rho = k->sph[3];
+  v3 p = vray(e, d, ts);
+  v3 n = vscale(vsub(p, c), 1.0f / rho);
+  v3 v = vsub(vld(k->pl), p);
+  float nv = vdot(n, v);
+  if (!(nv > 0.0f)) return;
+  float r2 = vdot(v, v), rr = sqrtf(r2), r3 = r2 * rr;
+  float dn = vdot(d, n);
+  const int mat = s->sph_mat[0];
+  for (int j = 0; j < 3; ++j) {
+    /* the hit moves along the ray: dt/dc_j = n_j / (d . n) */
+    float nj = j == 0 ? n.x : j == 1 ? n.y : n.z;
+    float dtj = nj / dn;
+    v3 dpj = vscale(d, dtj);
+    v3 ej = V(j == 0 ? 1.0f : 0.0f, j == 1 ? 1.0f : 0.0f, j == 2 ? 1.0f : 0.0f);
+    v3 dnj = vscale(vsub(dpj, ej), 1.0f / rho);
+    /* d/dc_j of (n . v) / |v|^3 with dv = -dp */
+    float dnv = vdot(dnj, v) - vdot(n, dpj);
+    float dvv = -vdot(v, dpj);
+    float dg = dnv / r3 - ((3.0f * nv) * dvv) / (r2 * r3);
+    for (int ch = 0; ch < 3; ++ch)
+      out[ch][j] = (k->rgb[3 * mat + ch] * INV_PI_F) * (k->pl[3 + ch] * dg);
+  }
+}
+
+/* dI/dtheta of one render (params X, stream pair `pair`): out[H][W][3][d]
+ * (binary64), the terms selected by mask (1 interior, 2 silhouette, 4 shadow);
+ * spp interior samples per pixel, edge_samples samples per edge. */
+int orc_dp_image_derivative(const orc_scene* s, const float* X, int pair, uint64_t seed,
+                            int edge_samples, int mask, int nthreads, double* out) {
+  if (dp_supported(s) || edge_samples < 1) return -1;
+  const int d = s->n_param, W = s->W, H = s->H;
+  kstate k;
+  kstate_init(s, X, &k);
+  uint32_t key[2];
+  seed_key(seed, key);
+  set_threads(nthreads);
+  memset(out, 0, sizeof(double) * (size_t)W * H * 3 * d);
+  if (mask & 1) {
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int pix = 0; pix < W * H; ++pix) {
+      double acc[3][3] = {{0}};
+      for (int smp = 0; smp < s->spp; ++smp) {
+        float jx = 0.5f, jy = 0.5f;
+        if (!s->pixel_center) {
+          uint32_t w[4];
+          philox_path(key, pix, smp, pair, ORC_TAG_DIFF, 0, 0, w);
+          jx = orc_u01(w[0]);
+          jy = orc_u01(w[1]);
+        }
+        float px = (float)(pix % W) + jx, py = (float)(pix / W) + jy;
+        float g[3][3];
+        dp_interior(s, &k, px, py, g);
+        for (int c = 0; c < 3; ++c)
+          for (int j = 0; j < 3; ++j) acc[c][j] += (double)g[c][j];
+      }
+      for (int c = 0; c < 3; ++c)
+        for (int j = 0; j < d; ++j) {
+          int ax = s->binding[3 * j + 2];
+          out[((size_t)pix * 3 + c) * d + j] = acc[c][ax] / (double)s->spp;
+        }
+    }
+  }
+  for (int edge = 0; edge < 2; ++edge) {
+    if (!(mask & (edge == 0 ? 2 : 4))) continue;
+    for (int m = 0; m < edge_samples; ++m) {
+      uint32_t ctr[4] = {(uint32_t)m, (uint32_t)edge, (uint32_t)pair,
+                         (uint32_t)ORC_TAG_EDGE << 24};
+      uint32_t w[4];
+      orc_philox4x32_10(ctr, key, w);
+      float frac = ((float)m + orc_u01(w[0])) / (float)edge_samples;
+      int pix;
+      float df[3], vn[3], dl;
+      int ok = edge == 0 ? dp_silhouette(s, &k, frac, &pix, df, vn, &dl)
+                         : dp_shadow(s, &k, frac, &pix, df, vn, &dl);
+      if (!ok) continue;
+      /* the sample stands for 2 pi / M radians of the edge */
+      double wgt = (2.0 * ORC_PI / (double)edge_samples) * (double)dl;
+      for (int c = 0; c < 3; ++c)
+        for (int j = 0; j < d; ++j) {
+          int ax = s->binding[3 * j + 2];
+          out[((size_t)pix * 3 + c) * d + j] += wgt * (double)df[c] * (double)vn[ax];
+        }
+    }
+  }
+  kstate_free(&k);
+  return 0;
+}
+
+/* Eq. 9 estimate: tau_k from the kernel (antithetic GAUSS pairs), renders
+ * I_k at theta +- tau_p (path stream of pair p), dI_k/dtheta with the
+ * derivative streams of pair p, and
+ *     g = (1/N) sum_k 2/(3HW) sum (I_k - R) dI_k/dtheta,  Q = mean L_k. */
+int orc_dp_grad_estimate(const orc_scene* s, const float* ref, const float* theta,
+                         const float* sigma, int N, uint64_t seed, int edge_samples, int nthreads,
+                         double* grad, double* loss, double* losses) {
+  if (check_args(s, sigma, N) || dp_supported(s) || edge_samples < 1) return -1;
+  const int d = s->n_param, P = N / 2;
+  const size_t npix = (size_t)s->W * s->H;
+  float* tau = (float*)malloc(sizeof(float) * (size_t)(P * d));
+  double* c = (double*)malloc(sizeof(double) * (size_t)(P * d));
+  float* img = (float*)malloc(sizeof(float) * 3 * npix);
+  double* dimg = (double*)malloc(sizeof(double) * 3 * npix * (size_t)d);
+  double* L = (double*)malloc(sizeof(double) * (size_t)N);
+  orc_draw_tau(ORC_EST_GAUSS, d, P, seed, sigma, tau, c);
+  for (int j = 0; j < d; ++j) grad[j] = 0.0;
+  float X[ORC_MAX_PARAMS];
+  for (int p = 0; p < P; ++p)
+    for (int mm = 0; mm < 2; ++mm) {
+      for (int j = 0; j < d; ++j)
+        X[j] = mm == 0 ? theta[j] + tau[p * d + j] : theta[j] - tau[p * d + j];
+      orc_render(s, X, ORC_TAG_PATH, p, seed, nthreads, img);
+      L[2 * p + mm] = orc_mse(img, ref, (int)npix);
+      orc_dp_image_derivative(s, X, p, seed, edge_samples, 7, nthreads, dimg);
+      const double scale = 2.0 / (3.0 * (double)npix);
+      for (int j = 0; j < d; ++j) {
+        double acc = 0.0;
+        for (size_t i = 0; i < 3 * npix; ++i)
+          acc += ((double)img[i] - (double)ref[i]) * dimg[i * d + j];
+        grad[j] += scale * acc;
+      }
+    }
+  double q = 0.0;
+  for (int i = 0; i < N; ++i) q += L[i];
+  for (int j = 0; j < d; ++j) grad[j] /= (double)N;
+  if (loss) *loss = q / (double)N;
+  if (losses) memcpy(losses, L, sizeof(double) * (size_t)N);
+  free(tau); free(c); free(img); free(dimg); free(L);
+  return 0;
+}

@@ -104,6 +104,19 @@ void orc_cosine_direction(const float n[3], float u1, float u2, float out[3]);
 void orc_dielectric_scatter(const float d[3], const float ng[3], float ior, float u,
                             float out[3], float side[3]);
 
+/* Eq. 9 through a differentiable direct-light renderer (scenes of one
+ * diffuse sphere, bound by its centre, over one diffuse quad under one point
+ * light, no bounces): the derivative image dI/dtheta [H][W][3][d] of one
+ * render (mask: 1 interior, 2 silhouette edge, 4 shadow edge; spp interior
+ * samples per pixel, edge_samples per edge), and the estimate
+ * g = (1/N) sum_k 2/(3HW) sum (I_k - R) dI_k/dtheta over antithetic GAUSS
+ * perturbations.  Return -1 on unsupported scenes or arguments. */
+int orc_dp_image_derivative(const orc_scene* s, const float* X, int pair, uint64_t seed,
+                            int edge_samples, int mask, int nthreads, double* out);
+int orc_dp_grad_estimate(const orc_scene* s, const float* ref, const float* theta,
+                         const float* sigma, int N, uint64_t seed, int edge_samples, int nthreads,
+                         double* grad, double* loss, double* losses);
+
 /* optimiser helpers (host-side step of the optimisation loop) */
 double orc_sigma_schedule(double sigma0, double sigma_end, int t, int T);
 void orc_adam_step(int d, double* theta, const double* g, double* m, double* v, int t,

@@ -102,6 +102,10 @@ def _declare(L):
     L.orc_fresnel.restype = C.c_float
     L.orc_cosine_direction.argtypes = [_f32p, C.c_float, C.c_float, _f32p]
     L.orc_dielectric_scatter.argtypes = [_f32p, _f32p, C.c_float, C.c_float, _f32p, _f32p]
+    L.orc_dp_image_derivative.argtypes = [C.c_void_p, _f32p, C.c_int, C.c_uint64, C.c_int, C.c_int,
+                                          C.c_int, _f64p]
+    L.orc_dp_grad_estimate.argtypes = [C.c_void_p, _f32p, _f32p, _f32p, C.c_int, C.c_uint64,
+                                       C.c_int, C.c_int, _f64p, C.POINTER(C.c_double), _f64p]
     L.orc_sigma_schedule.argtypes = [C.c_double, C.c_double, C.c_int, C.c_int]
     L.orc_sigma_schedule.restype = C.c_double
     L.orc_adam_step.argtypes = [C.c_int, _f64p, _f64p, _f64p, _f64p, C.c_int, C.c_double,
@@ -286,6 +290,27 @@ class OracleScene:
         if rc:
             raise ValueError("invalid estimator arguments")
         return q.value
+
+    def dp_image_derivative(self, X, pair=0, seed=0, edge_samples=4096, mask=7, nthreads=0):
+        """dI/dtheta [H, W, 3, d] of one render (Eq. 9's differentiable renderer)."""
+        out = np.zeros((self.H, self.W, 3, self.d), np.float64)
+        rc = lib().orc_dp_image_derivative(self.h, _f32(X, self.d), int(pair), int(seed),
+                                           int(edge_samples), int(mask), nthreads, out)
+        if rc:
+            raise ValueError("scene or arguments not supported by the differentiable renderer")
+        return out
+
+    def dp_grad_estimate(self, ref, theta, sigma, N, seed, edge_samples=4096, nthreads=0):
+        """Eq. 9 estimate: dict(grad, loss, losses)."""
+        d = self.d
+        g = np.zeros(d, np.float64)
+        q = C.c_double()
+        L = np.zeros(N, np.float64)
+        rc = lib().orc_dp_grad_estimate(self.h, _f32(ref), _f32(theta, d), _f32(sigma, d), int(N),
+                                        int(seed), int(edge_samples), nthreads, g, C.byref(q), L)
+        if rc:
+            raise ValueError("scene or arguments not supported by the differentiable renderer")
+        return dict(grad=g, loss=q.value, losses=L)
 
     def render_perturbed(self, theta, sigma, N, seed, mode, nthreads=0):
         imgs = np.zeros((N, self.H, self.W, 3), np.float32)

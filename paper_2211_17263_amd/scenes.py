@@ -599,3 +599,24 @@ def deep_stack_scene(seed=6, n_tris=524288, width=48, height=40, spp=2, bounces=
     s.bind(BIND_MESH, 0, 0)
     s.bind(BIND_MESH, 0, 1)
     return s
+
+
+def dp_scene(width=32, height=32, spp=1, eye=(0.0, 0.0, 5.0), look=(0.0, 0.0, 0.0), fov=40.0,
+             sphere=(0.0, 0.0, 0.5), radius=0.5, albedo=(0.8, 0.3, 0.2), light=(1.5, 1.5, 3.0),
+             ground=((-10.0, -10.0, 0.0), (20.0, 0.0, 0.0), (0.0, 20.0, 0.0)), env=(0.0, 0.0, 0.0),
+             pixel_center=0):
+    """The toy workload's kind of scene for the differentiable renderer: one
+    diffuse sphere whose centre (x, y) are the parameters, one diffuse ground
+    quad, one point light, direct light only; camera, sphere colour, light,
+    ground placement and environment are arguments (the renderer's tests use
+    them to isolate its interior, silhouette and shadow terms)."""
+    s = _new_scene("dp", width, height, spp, 0, eye=eye, look=look, up=(0, 1, 0), fov=fov,
+                   pixel_center=pixel_center, env=np.asarray(env, np.float32))
+    g = s.material(DIFFUSE, (0.8, 0.8, 0.8))
+    m = s.material(DIFFUSE, albedo)
+    sph = s.sphere(sphere, radius, m)
+    s.quad(ground[0], ground[1], ground[2], g)
+    s.plight(light, (10.0, 10.0, 10.0))
+    s.bind(BIND_SPHERE, sph, 0)
+    s.bind(BIND_SPHERE, sph, 1)
+    return s

@@ -1,8 +1,10 @@
 """The renderer pins must catch plausible mistakes.  Each case below builds a
 copy of the oracle with one deliberate error (a dropped cosine, a wrong area
 factor, a wrong disc radius or height of the cosine-weighted bounce, an
-inverted index ratio or a flipped sign in the refracted direction), loads it in
-a child process and checks that the pin aimed at that step fails there.  The
+inverted index ratio or a flipped sign in the refracted direction; in the
+differentiable renderer of Eq. 9 a wrong sign of the hit point's motion, of an
+edge's speed, a wrong edge length or speed), loads it in a child process and
+checks that the pin aimed at that step fails there.  The
 broken copies live in a temporary directory and are never used elsewhere."""
 import os
 import subprocess
@@ -29,6 +31,16 @@ MUTANTS = {
                              "tests/test_oracle_scatter.py::test_refraction_obeys_snell"),
     "refract_sign": ("float kk = rel * cosi - cost;", "float kk = rel * cosi + cost;",
                      "tests/test_oracle_scatter.py::test_ball_lens_paraxial_focus"),
+    # the differentiable renderer of Eq. 9
+    "dp_interior_hit_motion": ("float dtj = nj / dn;", "float dtj = -nj / dn;",
+                               "tests/test_oracle_eq9.py::test_interior_term_matches_central_differences"),
+    "dp_silhouette_speed_sign": ("vn[0] = (2.0f * rho * n.x) / gn;", "vn[0] = (-2.0f * rho * n.x) / gn;",
+                                 "tests/test_oracle_eq9.py::test_silhouette_term_matches_coverage_differences"),
+    "dp_silhouette_length": ("float dx = vdot(jx, dp), dy = vdot(jy, dp);",
+                             "float dx = vdot(jx, dp), dy = 0.0f * vdot(jy, dp);",
+                             "tests/test_oracle_eq9.py::test_silhouette_term_matches_coverage_differences"),
+    "dp_shadow_speed": ("vn[1] = (2.0f * ms.y) / gn;", "vn[1] = (ms.y) / gn;",
+                        "tests/test_oracle_eq9.py::test_shadow_term_matches_lit_radiance_differences"),
 }
 
 
