@@ -127,7 +127,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="caustic",
                     choices=["cornell", "toy", "caustic", "batch", "serve", "inverse", "ablation",
-                             "highd"])
+                             "highd", "eq9"])
     ap.add_argument("--serve-seconds", type=float, default=20.0,
                     help="serve workload: length of each arrival phase")
     ap.add_argument("--serve-rate", type=float, default=200.0,
@@ -165,6 +165,9 @@ def main():
         return bench_inverse(args, NV)
     if args.workload == "highd":
         return bench_highd(args, NV)
+    if args.workload == "eq9":
+        print(json.dumps(eq9_vs_eq10(args, NV, cpu=not args.no_cpu)), flush=True)
+        return
     if args.workload == "ablation":
         return bench_ablation(args, NV)
 
@@ -177,7 +180,62 @@ def main():
         out["extra_workloads"] = {"cornell": {k: gi[k] for k in (
             "value", "unit", "ms_per_step", "latency_ms", "config", "paths_per_s", "kernel",
             "roofline", "roofline_alu", "simd_efficiency")}}
+        out["extra_workloads"]["toy_eq9_vs_eq10"] = eq9_vs_eq10(args, NV, cpu=not args.no_cpu)
     print(json.dumps(out), flush=True)
+
+
+def eq9_vs_eq10(args, NV, cpu=True, steps=200, edge_samples=4096):
+    """The toy workload (64x64, 1 spp, N = 4, sigma 0.5, direct light) with both
+    estimators of Sec. 3.1: Eq. 10 (kernel derivative times the renderer,
+    prdpt_grad_estimate, GAUSS) and Eq. 9 (the kernel-smoothed gradient of the
+    differentiable renderer, prdpt_grad_estimate_dp): estimates per second over
+    `steps` calls each, the per-estimate variance of the gradient at theta_0
+    (same seeds), and, with cpu, one Eq. 9 estimate against the oracle's."""
+    import torch
+    from paper_2211_17263_amd import scenes as S
+    pr = S.toy_problem(seed=1)
+    sc_desc = S.dp_scene(width=64, height=64, spp=1)
+    ctx = NV.Context(0)
+    sc = NV.prdpt_scene_create(ctx, sc_desc)
+    ref = NV.prdpt_render_reference(sc, pr["theta_ref"], args.seed + 7)
+    th, sg, N = pr["theta0"], pr["sigma"], pr["N"]
+    res = {"config": {"workload": "toy", "width": 64, "height": 64, "spp": 1, "N": N,
+                      "sigma": float(sg[0]), "edge_samples_per_edge": edge_samples}}
+    for name, fn in (("eq10", lambda seed: NV.prdpt_grad_estimate(sc, ref, th, sg, N, seed,
+                                                                  NV.PRDPT_EST_GAUSS)),
+                     ("eq9", lambda seed: NV.prdpt_grad_estimate_dp(sc, ref, th, sg, N, seed,
+                                                                    edge_samples))):
+        for t in range(5):
+            fn(args.seed + t)
+        torch.cuda.synchronize()
+        grads = []
+        t0 = time.perf_counter()
+        for t in range(steps):
+            grads.append(fn(args.seed + 100 + t)["grad"])
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        g = np.asarray(grads)
+        res[name] = {"estimates_per_s": steps / el, "ms_per_estimate": 1e3 * el / steps,
+                     "grad_mean": g.mean(0).tolist(), "grad_var_sum": float(g.var(0, ddof=1).sum())}
+    res["eq9_over_eq10_time"] = res["eq9"]["ms_per_estimate"] / res["eq10"]["ms_per_estimate"]
+    res["eq9_over_eq10_variance"] = res["eq9"]["grad_var_sum"] / res["eq10"]["grad_var_sum"]
+    if cpu:
+        from oracle import oracle as O
+        from tests import parity as PT
+        osc = O.OracleScene(sc_desc)
+        ref_h = ref.cpu().numpy()
+        r = NV.prdpt_grad_estimate_dp(sc, ref, th, sg, N, args.seed, edge_samples)
+        t0 = time.perf_counter()
+        o = osc.dp_grad_estimate(ref_h, th, sg, N, args.seed, edge_samples=edge_samples)
+        res["eq9_oracle_s_per_estimate"] = time.perf_counter() - t0
+        rel = np.abs(r["losses"] - o["losses"]) / np.abs(o["losses"])
+        grel = np.abs(r["grad"] - o["grad"]) / np.maximum(np.abs(o["grad"]), 1e-12)
+        res["eq9_parity"] = {"max_rel_loss_err": float(rel.max()), "grad_gpu": r["grad"].tolist(),
+                             "grad_oracle": o["grad"].tolist(), "max_rel_grad_err": float(grel.max()),
+                             "pass_1e-4": bool(rel.max() <= PT.LOSS_REL and grel.max() <= 1e-4)}
+    sc.destroy()
+    ctx.close()
+    return res
 
 
 def bench_estimator(args, NV, name, cpu=True):

@@ -238,6 +238,27 @@ int prdpt_grad_estimate(prdpt_scene* scene, const float* ref, const float* theta
                         double* loss_out, double* losses_out);
 
 /*
+ * The smoothed gradient through a differentiable renderer (Sec. 3.1, Eq. 9):
+ *     grad = (1/N) sum_k dL/dtheta (theta + tau_k),
+ *     dL/dtheta = 2/(3 H W) sum over pixels and RGB of (I_k - R) dI_k/dtheta,
+ * with tau_k drawn from the kernel (GAUSS antithetic pairs; the kernel weight
+ * then drops, as for Eq. 7), I_k the rendered image of perturbation k and
+ * dI_k/dtheta from samples independent of it: per pixel, spp interior samples
+ * of the shading derivative (stream tag 6), plus edge_samples samples on each
+ * of the two edges that move with the parameters, the sphere's silhouette and
+ * its shadow's boundary on the ground (stream tag 7, Reynolds transport of
+ * the pixel integral).  Supported scenes (else PRDPT_E_SCENE): one diffuse
+ * sphere whose centre components are the parameters (d <= 3), one diffuse
+ * quad (the ground; the light and the sphere above its plane, the eye too),
+ * one point light, no meshes, max_bounces = 0.  ref: device float[H][W][3];
+ * grad_out host double[d]; loss_out (nullable) the mean of the N losses;
+ * losses_out (nullable) host double[N].  Synchronous.
+ */
+int prdpt_grad_estimate_dp(prdpt_scene* scene, const float* ref, const float* theta,
+                           const float* sigma, int N, uint64_t seed, int edge_samples,
+                           double* grad_out, double* loss_out, double* losses_out);
+
+/*
  * Stream-ordered form of prdpt_grad_estimate for callers that keep everything
  * on the device (the torch binding): theta_dev/sigma_dev device float[d];
  * grad_dev device double[d]; loss_dev device double[1]; losses_dev (nullable)

@@ -272,6 +272,7 @@ int prdpt_ctx_destroy(prdpt_ctx* ctx) {
   hipSetDevice(ctx->device);
   hipStreamSynchronize(ctx->stream);
   void* bufs[] = {ctx->X.p, ctx->tau.p, ctx->partial.p, ctx->theta.p, ctx->sigma.p,
+                  ctx->images.p, ctx->dp_partial.p,
                   ctx->c.p, ctx->losses.p, ctx->grad.p, ctx->loss.p, ctx->counters.p, ctx->work.p,
                   ctx->vin.p, ctx->vout.p};
   for (void* b : bufs)
@@ -703,6 +704,55 @@ int prdpt_grad_estimate(prdpt_scene* s, const float* ref, const float* theta, co
   std::memcpy(grad_out, ctx->h_vout, sizeof(double) * d);
   if (loss_out) *loss_out = ctx->h_vout[d];
   if (losses_out) std::memcpy(losses_out, ctx->h_vout + d + 1, sizeof(double) * N);
+  return PRDPT_OK;
+}
+
+int prdpt_grad_estimate_dp(prdpt_scene* s, const float* ref, const float* theta, const float* sigma,
+                           int N, uint64_t seed, int edge_samples, double* grad_out,
+                           double* loss_out, double* losses_out) {
+  if (int rc = check_request(s, theta, sigma, N, true)) return rc;
+  if (!ref || !grad_out) return fail(PRDPT_E_ARG, "ref/grad_out is null");
+  if (edge_samples < 1 || edge_samples > (1 << 24))
+    return fail(PRDPT_E_ARG, "edge_samples must be in 1..2^24");
+  const SceneHdr& h = s->hdr;
+  // the differentiable renderer: one diffuse sphere whose centre is bound,
+  // one diffuse quad (the ground), one point light, no meshes, no bounces
+  bool ok = h.n_sph == 1 && h.n_quad == 1 && h.n_inst == 0 && h.n_tri == 0 && h.n_pl == 1 &&
+            h.B == 0 && h.mat_type[h.sph_mat[0]] == PRDPT_MAT_DIFFUSE &&
+            h.mat_type[h.quad_mat[0]] == PRDPT_MAT_DIFFUSE && h.n_param >= 1 && h.n_param <= 3;
+  for (int j = 0; ok && j < h.n_param; ++j)
+    ok = h.bind_kind[j] == PRDPT_BIND_SPHERE && h.bind_index[j] == 0;
+  if (!ok)
+    return fail(PRDPT_E_SCENE, "Eq. 9 needs one diffuse sphere (its centre bound) over one diffuse "
+                               "quad under one point light, direct light only");
+  prdpt_ctx* ctx = s->ctx;
+  const int d = h.n_param, P = N / 2;
+  const size_t npix = (size_t)h.W * h.H;
+  const int bi = dp_interior_blocks(h.W, h.H), be = dp_edge_blocks(edge_samples);
+  std::lock_guard<std::mutex> g(ctx->mu);
+  HIP_TRY(hipSetDevice(ctx->device));
+  if (int rc = prepare(ctx, N, d, render_tiles(h.W, h.H))) return rc;
+  if (int rc = ensure(ctx, ctx->images, (size_t)N * npix * 3)) return rc;
+  if (int rc = ensure(ctx, ctx->dp_partial, (size_t)N * (bi + be) * 3)) return rc;
+  if (int rc = upload_vectors(ctx, theta, sigma, d)) return rc;
+  HIP_TRY(launch_tau(ctx->stream, PRDPT_EST_GAUSS, d, P, seed, ctx->sigma.p, ctx->theta.p,
+                     chi_mean(d), std::sqrt(2.0 * M_PI), ctx->tau.p, ctx->c.p, ctx->X.p));
+  HIP_TRY(timed_render(ctx, s, ctx->X.p, N, d, kTagPath, seed, ref, ctx->images.p, ctx->partial.p, 1,
+                       ctx->work.p));
+  HIP_TRY(launch_losses(ctx->stream, ctx->partial.p, render_tiles(h.W, h.H), N, (int)npix,
+                        ctx->losses.p));
+  double* pin = ctx->dp_partial.p;
+  double* pedge = pin + (size_t)N * bi * 3;
+  HIP_TRY(launch_dp(ctx->stream, s->d_hdr, h.W, h.H, ctx->X.p, N, d, seed, ctx->images.p, ref,
+                    edge_samples, pin, pedge, ctx->losses.p, ctx->grad.p, ctx->loss.p));
+  HIP_TRY(hipMemcpyAsync(grad_out, ctx->grad.p, sizeof(double) * d, hipMemcpyDeviceToHost, ctx->stream));
+  double q = 0.0;
+  HIP_TRY(hipMemcpyAsync(&q, ctx->loss.p, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  if (losses_out)
+    HIP_TRY(hipMemcpyAsync(losses_out, ctx->losses.p, sizeof(double) * N, hipMemcpyDeviceToHost,
+                           ctx->stream));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  if (loss_out) *loss_out = q;
   return PRDPT_OK;
 }
 

@@ -42,6 +42,14 @@ hipError_t launch_batch(hipStream_t st, const BatchReq* reqs, BatchMeta* meta, i
                         int rot, int max_sph, float* tau, double* c, float* X,
                         float* partial, double* losses, double* grads, double* loss);
 hipError_t launch_copy(hipStream_t st, const void* src, void* dst, size_t n16);
+// Eq. 9: interior and edge derivative terms of N renders weighted by their
+// (I - R), reduced to the gradient and the mean loss; pin/pedge hold
+// N x dp_interior_blocks / dp_edge_blocks rows of 3 doubles
+int dp_interior_blocks(int W, int H);
+int dp_edge_blocks(int M);
+hipError_t launch_dp(hipStream_t st, const SceneHdr* hdr, int W, int H, const float* X, int N, int d,
+                     uint64_t seed, const float* img, const float* ref, int M, double* pin,
+                     double* pedge, const double* losses, double* grad, double* loss);
 // device address of the current device's copy of the allocation-free
 // estimate's scratch array (PRDPT_NOALLOC_SCRATCH_BYTES), looked up once per
 // device; `device` must be current
@@ -128,6 +136,8 @@ struct prdpt_ctx {
   int n_scenes = 0;
   std::mutex mu;
   prdpt::DevBuf<float> X, tau, partial, theta, sigma;
+  prdpt::DevBuf<float> images;          // Eq. 9: the N rendered images
+  prdpt::DevBuf<double> dp_partial;     // Eq. 9: per-block derivative terms
   prdpt::DevBuf<double> c, losses, grad, loss;
   prdpt::DevBuf<unsigned long long> counters;
   prdpt::DevBuf<int> work;  // work counter of the persistent render kernel

@@ -1507,6 +1507,367 @@ __global__ __launch_bounds__(256) void copy_kernel(const float4* __restrict__ sr
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
 }
 
+// ---------------------------------------------------------------------------
+// Eq. 9: the kernel-smoothed gradient of a differentiable renderer, for
+// scenes of one diffuse sphere (its centre bound) over one diffuse ground quad
+// under one point light, direct light only.  The pixel derivative is the
+// interior term (the sphere's shading moves with its centre) plus samples on
+// the two moving edges, the silhouette and the shadow boundary, each the image
+// of a circle of tangent points; every term is weighted here by the pixel's
+// (I - R) and summed, giving the loss gradient of one render.
+// ---------------------------------------------------------------------------
+constexpr int kTagDiff = 6, kTagEdge = 7;
+
+// one render's sphere (centre, radius), its parameter rows applied
+struct DpState {
+  V3 c;
+  float rho;
+  const SceneHdr* g;
+};
+
+__device__ __forceinline__ DpState dp_state(const SceneHdr* __restrict__ g, const float* __restrict__ X,
+                                            int d) {
+  float c3[3] = {g->sph[0][0], g->sph[0][1], g->sph[0][2]};
+  for (int j = 0; j < d; ++j) {
+    const int ax = g->bind_comp[j];
+    c3[ax] = g->sph[0][ax] + X[j];
+  }
+  return DpState{mk(c3[0], c3[1], c3[2]), g->sph[0][3], g};
+}
+
+// pixel position of world point P and the rows of d(px, py)/dP
+__device__ __forceinline__ void dp_project(const SceneHdr* __restrict__ g, V3 P, float* px, float* py,
+                                           V3* jx, V3* jy) {
+  const V3 e = ld3(g->eye), f = ld3(g->fwd), r = ld3(g->right), u = ld3(g->up);
+  const V3 D = sub(P, e);
+  const float lam = dot(D, f), a = dot(D, r), b = dot(D, u);
+  const float rr = dot(r, r), uu = dot(u, u);
+  const float sx = a / (lam * rr), sy = b / (lam * uu);
+  const float hw = 0.5f * (float)g->W, hh = 0.5f * (float)g->H;
+  *px = (sx + 1.0f) * hw;
+  *py = (1.0f - sy) * hh;
+  const float l2r = (lam * lam) * rr, l2u = (lam * lam) * uu;
+  const V3 gx = mk((r.x * lam - f.x * a) / l2r, (r.y * lam - f.y * a) / l2r, (r.z * lam - f.z * a) / l2r);
+  const V3 gy = mk((u.x * lam - f.x * b) / l2u, (u.y * lam - f.y * b) / l2u, (u.z * lam - f.z * b) / l2u);
+  *jx = scale(gx, hw);
+  *jy = scale(gy, -hh);
+}
+
+// direct radiance of a diffuse point under the point light, no shadow test
+__device__ __forceinline__ void dp_shade(const SceneHdr* __restrict__ g, int mat, V3 p, V3 n, float out[3]) {
+  const float* lp = g->pl[0];
+  const V3 toL = sub(ld3(lp), p);
+  const float dist2 = dot(toL, toL);
+  const float dist = sqrtf(dist2);
+  const V3 wi = scale(toL, 1.0f / dist);
+  const float cx = dot(n, wi);
+  for (int c = 0; c < 3; ++c)
+    out[c] = cx > 0.0f ? (g->mat_rgb[mat][c] * kInvPi) * ((lp[3 + c] * cx) / dist2) : 0.0f;
+}
+
+__device__ __forceinline__ V3 dp_ground_normal(const SceneHdr* __restrict__ g) {
+  V3 n = unit(cross(ld3(g->quad[0] + 3), ld3(g->quad[0] + 6)));
+  if (dot(n, sub(ld3(g->pl[0]), ld3(g->quad[0]))) < 0.0f) n = neg(n);
+  return n;
+}
+
+__device__ __forceinline__ float dp_sphere4(const DpState& st, float* sp) {
+  sp[0] = st.c.x;
+  sp[1] = st.c.y;
+  sp[2] = st.c.z;
+  sp[3] = st.rho;
+  return st.rho;
+}
+
+// radiance behind the silhouette: the ground (shadowed or not) or the environment
+__device__ __forceinline__ void dp_behind(const DpState& st, V3 o, V3 d, float out[3]) {
+  const SceneHdr* g = st.g;
+  float t;
+  if (!hit_quad(o, d, g->quad[0], g->quad_n[0], g->quad_lo[0], __builtin_huge_valf(), &t)) {
+    for (int c = 0; c < 3; ++c) out[c] = g->env[c];
+    return;
+  }
+  const V3 p = at(o, d, t);
+  const V3 n = dp_ground_normal(g);
+  const V3 toL = sub(ld3(g->pl[0]), p);
+  const float dist = sqrtf(dot(toL, toL));
+  const V3 wi = scale(toL, 1.0f / dist);
+  float sp[4], ts;
+  dp_sphere4(st, sp);
+  if (hit_sphere(offset_origin(p, n), wi, sp, dist * 0.9999f, &ts)) {
+    out[0] = out[1] = out[2] = 0.0f;
+    return;
+  }
+  dp_shade(g, g->quad_mat[0], p, n, out);
+}
+
+// a point of the circle of tangent points seen from `from`, at angle
+// fraction frac, and its derivative per radian
+__device__ __forceinline__ void dp_tangent_circle(const DpState& st, V3 from, float frac, V3* p, V3* dp) {
+  const V3 a = sub(from, st.c);
+  const float kk = (st.rho * st.rho) / dot(a, a);
+  const V3 cs = mk(st.c.x + a.x * kk, st.c.y + a.y * kk, st.c.z + a.z * kk);
+  const float rs = st.rho * sqrtf(1.0f - kk);
+  V3 b1, b2;
+  basis(unit(a), &b1, &b2);
+  float sn, cn;
+  sincos_turn(frac, &sn, &cn);
+  *p = mk(cs.x + (b1.x * cn + b2.x * sn) * rs, cs.y + (b1.y * cn + b2.y * sn) * rs,
+          cs.z + (b1.z * cn + b2.z * sn) * rs);
+  *dp = mk((b2.x * cn - b1.x * sn) * rs, (b2.y * cn - b1.y * sn) * rs, (b2.z * cn - b1.z * sn) * rs);
+}
+
+// silhouette sample: pixel, radiance step inside - outside, outward normal
+// speed per centre axis (pixels per unit), edge length per radian (pixels)
+__device__ bool dp_silhouette(const DpState& st, float frac, int* pix, float df[3], float vn[3], float* dl) {
+  const SceneHdr* g = st.g;
+  const V3 e = ld3(g->eye);
+  V3 p, dp;
+  dp_tangent_circle(st, e, frac, &p, &dp);
+  float px, py;
+  V3 jx, jy;
+  dp_project(g, p, &px, &py, &jx, &jy);
+  if (!(px >= 0.0f && px < (float)g->W && py >= 0.0f && py < (float)g->H)) return false;
+  *pix = (int)py * g->W + (int)px;
+  const float dx = dot(jx, dp), dy = dot(jy, dp);
+  *dl = sqrtf(dx * dx + dy * dy);
+  const V3 n = scale(sub(p, st.c), 1.0f / st.rho);
+  float fin[3], fout[3];
+  dp_shade(g, g->sph_mat[0], p, n, fin);
+  const V3 dir = unit(sub(p, e));
+  dp_behind(st, e, dir, fout);
+  for (int c = 0; c < 3; ++c) df[c] = fin[c] - fout[c];
+  const V3 f = ld3(g->fwd), r = ld3(g->right), u = ld3(g->up);
+  const V3 pe = sub(p, e);
+  const float lam = dot(pe, f);
+  const float dlen = sqrtf(dot(pe, pe)) / lam;
+  const float q = dot(sub(st.c, e), dir);
+  const V3 m = scale(n, -st.rho);
+  const float gxx = ((-2.0f * q) / dlen) * (dot(m, r) * (2.0f / (float)g->W));
+  const float gyy = ((-2.0f * q) / dlen) * (dot(m, u) * (-2.0f / (float)g->H));
+  const float gn = sqrtf(gxx * gxx + gyy * gyy);
+  vn[0] = (2.0f * st.rho * n.x) / gn;
+  vn[1] = (2.0f * st.rho * n.y) / gn;
+  vn[2] = (2.0f * st.rho * n.z) / gn;
+  return true;
+}
+
+// shadow-boundary sample (see dp_silhouette); the step is the lit radiance
+__device__ bool dp_shadow(const DpState& st, float frac, int* pix, float df[3], float vn[3], float* dl) {
+  const SceneHdr* g = st.g;
+  const V3 e = ld3(g->eye), L = ld3(g->pl[0]);
+  V3 t, dt;
+  dp_tangent_circle(st, L, frac, &t, &dt);
+  const V3 np = dp_ground_normal(g);
+  const V3 q0 = ld3(g->quad[0]);
+  const V3 tl = sub(t, L);
+  const float den = dot(tl, np);
+  if (!(den < 0.0f)) return false;
+  const float lam = dot(sub(q0, L), np) / den;
+  if (!(lam > 1.0f)) return false;
+  const V3 gp = at(L, tl, lam);
+  // on the ground quad (the same decision as dividing by nn)
+  const V3 e1 = ld3(g->quad[0] + 3), e2 = ld3(g->quad[0] + 6), nq = ld3(g->quad_n[0]);
+  const float nn = g->quad_n[0][3], lo = g->quad_lo[0];
+  const V3 gd = sub(gp, q0);
+  const float al = dot(cross(gd, e2), nq), be = dot(cross(e1, gd), nq);
+  if (al <= lo || al > nn || be <= lo || be > nn) return false;
+  const V3 f = ld3(g->fwd), r = ld3(g->right), u = ld3(g->up);
+  const V3 ge = sub(gp, e);
+  const float lc = dot(ge, f);
+  if (!(lc > 0.0f)) return false;
+  float px, py;
+  V3 jx, jy;
+  dp_project(g, gp, &px, &py, &jx, &jy);
+  if (!(px >= 0.0f && px < (float)g->W && py >= 0.0f && py < (float)g->H)) return false;
+  const float gdist = sqrtf(dot(ge, ge));
+  const V3 wc = scale(ge, 1.0f / gdist);
+  float sp[4], tsp;
+  dp_sphere4(st, sp);
+  if (hit_sphere(e, wc, sp, gdist * 0.9999f, &tsp)) return false;
+  *pix = (int)py * g->W + (int)px;
+  const float dlam = -lam * (dot(dt, np) / den);
+  const V3 dg = mk(dt.x * lam + tl.x * dlam, dt.y * lam + tl.y * dlam, dt.z * lam + tl.z * dlam);
+  const float dx = dot(jx, dg), dy = dot(jy, dg);
+  *dl = sqrtf(dx * dx + dy * dy);
+  dp_shade(g, g->quad_mat[0], gp, np, df);
+  const V3 lg = sub(gp, L);
+  const float lgd = sqrtf(dot(lg, lg));
+  const V3 w = scale(lg, 1.0f / lgd);
+  const V3 cl = sub(st.c, L);
+  const float qs = dot(cl, w);
+  const V3 ms = mk(cl.x - w.x * qs, cl.y - w.y * qs, cl.z - w.z * qs);
+  const V3 dd = scale(ge, 1.0f / lc);
+  const float dn = dot(dd, np);
+  const V3 ddx = scale(r, 2.0f / (float)g->W), ddy = scale(u, -2.0f / (float)g->H);
+  const float ax = dot(ddx, np) / dn, ay = dot(ddy, np) / dn;
+  const V3 dgx = mk((ddx.x - dd.x * ax) * lc, (ddx.y - dd.y * ax) * lc, (ddx.z - dd.z * ax) * lc);
+  const V3 dgy = mk((ddy.x - dd.x * ay) * lc, (ddy.y - dd.y * ay) * lc, (ddy.z - dd.z * ay) * lc);
+  const float gxx = ((-2.0f * qs) * dot(ms, dgx)) / lgd;
+  const float gyy = ((-2.0f * qs) * dot(ms, dgy)) / lgd;
+  const float gn = sqrtf(gxx * gxx + gyy * gyy);
+  vn[0] = (2.0f * ms.x) / gn;
+  vn[1] = (2.0f * ms.y) / gn;
+  vn[2] = (2.0f * ms.z) / gn;
+  return true;
+}
+
+// interior derivative sample at image point (px, py): df/dc (rgb x axis)
+__device__ void dp_interior(const DpState& st, float px, float py, float out[3][3]) {
+  const SceneHdr* g = st.g;
+  for (int c = 0; c < 3; ++c)
+    for (int j = 0; j < 3; ++j) out[c][j] = 0.0f;
+  const float sx = 2.0f * (px / (float)g->W) - 1.0f;
+  const float sy = 1.0f - 2.0f * (py / (float)g->H);
+  const V3 e = ld3(g->eye);
+  const V3 d = unit(mk(g->fwd[0] + g->right[0] * sx + g->up[0] * sy, g->fwd[1] + g->right[1] * sx + g->up[1] * sy,
+                       g->fwd[2] + g->right[2] * sx + g->up[2] * sy));
+  float sp[4], ts, tg;
+  dp_sphere4(st, sp);
+  if (!hit_sphere(e, d, sp, __builtin_huge_valf(), &ts)) return;
+  if (hit_quad(e, d, g->quad[0], g->quad_n[0], g->quad_lo[0], ts, &tg)) return;
+  const float rho = st.rho;
+  const V3 p = at(e, d, ts);
+  const V3 n = scale(sub(p, st.c), 1.0f / rho);
+  const V3 v = sub(ld3(g->pl[0]), p);
+  const float nv = dot(n, v);
+  if (!(nv > 0.0f)) return;
+  const float r2 = dot(v, v), rr = sqrtf(r2), r3 = r2 * rr;
+  const float dn = dot(d, n);
+  const int mat = g->sph_mat[0];
+  for (int j = 0; j < 3; ++j) {
+    const float nj = j == 0 ? n.x : j == 1 ? n.y : n.z;
+    const float dtj = nj / dn;
+    const V3 dpj = scale(d, dtj);
+    const V3 ej = mk(j == 0 ? 1.0f : 0.0f, j == 1 ? 1.0f : 0.0f, j == 2 ? 1.0f : 0.0f);
+    const V3 dnj = scale(sub(dpj, ej), 1.0f / rho);
+    const float dnv = dot(dnj, v) - dot(n, dpj);
+    const float dvv = -dot(v, dpj);
+    const float dg = dnv / r3 - ((3.0f * nv) * dvv) / (r2 * r3);
+    for (int ch = 0; ch < 3; ++ch) out[ch][j] = (g->mat_rgb[mat][ch] * kInvPi) * (g->pl[0][3 + ch] * dg);
+  }
+}
+
+// block sum of d binary64 values in a fixed order (wave butterfly, then waves)
+template <int BS>
+__device__ __forceinline__ void dp_block_store(double (&acc)[3], int d, double* __restrict__ out) {
+  __shared__ double wsum[BS / 64][3];
+  for (int j = 0; j < 3; ++j) {
+    double v = acc[j];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6][j] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < (unsigned)d) {
+    double s = 0.0;
+    for (int w = 0; w < BS / 64; ++w) s += wsum[w][threadIdx.x];
+    out[threadIdx.x] = s;
+  }
+}
+
+constexpr int kDpBlock = 256;
+
+// interior term of render k: one thread per pixel, spp derivative samples;
+// partial[k][block][j] = sum over the block's pixels of sum_c (I - R)_c mean_s df_c/dc_ax(j)
+__global__ __launch_bounds__(kDpBlock) void dp_interior_kernel(const SceneHdr* __restrict__ g,
+                                                               const float* __restrict__ X, int d,
+                                                               uint32_t k0, uint32_t k1,
+                                                               const float* __restrict__ img,
+                                                               const float* __restrict__ ref,
+                                                               int blocks_per_image,
+                                                               double* __restrict__ partial) {
+  const int k = blockIdx.x / blocks_per_image, blk = blockIdx.x - k * blocks_per_image;
+  const int W = g->W, H = g->H, npix = W * H;
+  const int pix = blk * kDpBlock + threadIdx.x;
+  const DpState st = dp_state(g, X + (size_t)k * d, d);
+  const int pair = k >> 1;
+  double acc[3] = {0.0, 0.0, 0.0};
+  if (pix < npix) {
+    double s[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+    for (int smp = 0; smp < g->spp; ++smp) {
+      float jx = 0.5f, jy = 0.5f;
+      if (!g->pixel_center) {
+        const uint4 w = path_words(k0, k1, pix, smp, pair, kTagDiff, 0, 0);
+        jx = unit_open(w.x);
+        jy = unit_open(w.y);
+      }
+      float o[3][3];
+      dp_interior(st, (float)(pix % W) + jx, (float)(pix / W) + jy, o);
+      for (int c = 0; c < 3; ++c)
+        for (int j = 0; j < 3; ++j) s[c][j] += (double)o[c][j];
+    }
+    const float* I = img + ((size_t)k * npix + pix) * 3;
+    const float* R = ref + (size_t)pix * 3;
+    for (int j = 0; j < d; ++j) {
+      const int ax = g->bind_comp[j];
+      for (int c = 0; c < 3; ++c) acc[j] += ((double)I[c] - (double)R[c]) * (s[c][ax] / (double)g->spp);
+    }
+  }
+  dp_block_store<kDpBlock>(acc, d, partial + (size_t)blockIdx.x * 3);
+}
+
+// edge terms of render k: one thread per edge sample (silhouette samples then
+// shadow samples, M each), weighted by the sample pixel's (I - R)
+__global__ __launch_bounds__(kDpBlock) void dp_edge_kernel(const SceneHdr* __restrict__ g,
+                                                           const float* __restrict__ X, int d,
+                                                           uint32_t k0, uint32_t k1,
+                                                           const float* __restrict__ img,
+                                                           const float* __restrict__ ref, int M,
+                                                           int blocks_per_image,
+                                                           double* __restrict__ partial) {
+  const int k = blockIdx.x / blocks_per_image, blk = blockIdx.x - k * blocks_per_image;
+  const int i = blk * kDpBlock + threadIdx.x;
+  const DpState st = dp_state(g, X + (size_t)k * d, d);
+  double acc[3] = {0.0, 0.0, 0.0};
+  if (i < 2 * M) {
+    const int edge = i >= M ? 1 : 0, m = i - edge * M;
+    const uint4 w = philox10(make_uint4((uint32_t)m, (uint32_t)edge, (uint32_t)(k >> 1),
+                                        (uint32_t)kTagEdge << 24), k0, k1);
+    const float frac = ((float)m + unit_open(w.x)) / (float)M;
+    int pix;
+    float df[3], vn[3], dl;
+    const bool ok = edge == 0 ? dp_silhouette(st, frac, &pix, df, vn, &dl)
+                              : dp_shadow(st, frac, &pix, df, vn, &dl);
+    if (ok) {
+      const double wgt = (2.0 * 3.14159265358979323846 / (double)M) * (double)dl;
+      const size_t npix = (size_t)g->W * g->H;
+      const float* I = img + ((size_t)k * npix + pix) * 3;
+      const float* R = ref + (size_t)pix * 3;
+      for (int j = 0; j < d; ++j) {
+        const int ax = g->bind_comp[j];
+        for (int c = 0; c < 3; ++c)
+          acc[j] += ((double)I[c] - (double)R[c]) * (wgt * (double)df[c] * (double)vn[ax]);
+      }
+    }
+  }
+  dp_block_store<kDpBlock>(acc, d, partial + (size_t)blockIdx.x * 3);
+}
+
+// g_j = 2/(3HW) (1/N) sum over renders of their interior and edge partials
+// (each render's partials in block order), and Q = mean loss
+__global__ void dp_combine_kernel(int N, int d, int interior_blocks, int edge_blocks,
+                                  const double* __restrict__ pin, const double* __restrict__ pedge,
+                                  double inv_den, const double* __restrict__ losses,
+                                  double* __restrict__ grad, double* __restrict__ loss) {
+  const int j = threadIdx.x;
+  if (j < d) {
+    double acc = 0.0;
+    for (int k = 0; k < N; ++k) {
+      double gk = 0.0;
+      for (int b = 0; b < interior_blocks; ++b) gk += pin[((size_t)k * interior_blocks + b) * 3 + j];
+      for (int b = 0; b < edge_blocks; ++b) gk += pedge[((size_t)k * edge_blocks + b) * 3 + j];
+      acc += (2.0 * inv_den) * gk;
+    }
+    grad[j] = acc / (double)N;
+  }
+  if (j == 0) {
+    double s = 0.0;
+    for (int k = 0; k < N; ++k) s += losses[k];
+    *loss = s / (double)N;
+  }
+}
+
 // Scratch of the allocation-free estimate (prdpt_grad_estimate_noalloc): one
 // fixed array that every device the library runs on holds until the process
 // ends.  Host code never passes this name to a kernel (on the host it is a
@@ -1683,6 +2044,23 @@ hipError_t launch_batch(hipStream_t st, const BatchReq* reqs, BatchMeta* meta, i
   hipLaunchKernelGGL(batch_loss_kernel, dim3(1024), dim3(64), 0, st, reqs, meta, partial, losses);
   hipLaunchKernelGGL(batch_combine_kernel, dim3(256), dim3(64), 0, st, reqs, meta, c, losses,
                      grads, loss);
+  return hipGetLastError();
+}
+
+int dp_interior_blocks(int W, int H) { return (W * H + kDpBlock - 1) / kDpBlock; }
+int dp_edge_blocks(int M) { return (2 * M + kDpBlock - 1) / kDpBlock; }
+
+hipError_t launch_dp(hipStream_t st, const SceneHdr* hdr, int W, int H, const float* X, int N, int d,
+                     uint64_t seed, const float* img, const float* ref, int M, double* pin,
+                     double* pedge, const double* losses, double* grad, double* loss) {
+  const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+  const int bi = dp_interior_blocks(W, H), be = dp_edge_blocks(M);
+  hipLaunchKernelGGL(dp_interior_kernel, dim3(N * bi), dim3(kDpBlock), 0, st, hdr, X, d, k0, k1, img,
+                     ref, bi, pin);
+  hipLaunchKernelGGL(dp_edge_kernel, dim3(N * be), dim3(kDpBlock), 0, st, hdr, X, d, k0, k1, img, ref,
+                     M, be, pedge);
+  hipLaunchKernelGGL(dp_combine_kernel, dim3(1), dim3(64), 0, st, N, d, bi, be, pin, pedge,
+                     1.0 / (3.0 * (double)W * (double)H), losses, grad, loss);
   return hipGetLastError();
 }
 

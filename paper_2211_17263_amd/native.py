@@ -34,7 +34,7 @@ EXPORTS = [
     "prdpt_server_start", "prdpt_server_add_job", "prdpt_server_submit", "prdpt_server_cancel",
     "prdpt_server_poll", "prdpt_server_get_stats", "prdpt_server_stop",
     "prdpt_server_submit_deadline", "prdpt_debug_fail_allocations",
-    "prdpt_grad_estimate_noalloc",
+    "prdpt_grad_estimate_noalloc", "prdpt_grad_estimate_dp",
 ]
 
 
@@ -114,6 +114,7 @@ def load():
     L.prdpt_render_reference.argtypes = [vp, vp, u64, vp]
     L.prdpt_smoothed_loss.argtypes = [vp, vp, vp, vp, i32, u64, vp]
     L.prdpt_grad_estimate.argtypes = [vp, vp, vp, vp, i32, u64, i32, vp, vp, vp]
+    L.prdpt_grad_estimate_dp.argtypes = [vp, vp, vp, vp, i32, u64, i32, vp, vp, vp]
     L.prdpt_grad_estimate_async.argtypes = [vp, vp, vp, vp, i32, u64, i32, vp, vp, vp, vp]
     L.prdpt_grad_estimate_noalloc.argtypes = [vp, vp, vp, vp, i32, u64, i32, vp, vp, vp, vp]
     L.prdpt_combine_async.argtypes = [vp, i32, i32, vp, vp, vp, vp, i32]
@@ -323,6 +324,23 @@ def prdpt_grad_estimate(scene, ref, theta, sigma, N, seed, est):
     _check(load().prdpt_grad_estimate(scene.h, _dev(ref, torch.float32), tp, sp, int(N), int(seed),
                                       int(est), g.ctypes.data_as(C.c_void_p), C.byref(q),
                                       L.ctypes.data_as(C.c_void_p)))
+    return dict(grad=g, loss=q.value, losses=L)
+
+
+def prdpt_grad_estimate_dp(scene, ref, theta, sigma, N, seed, edge_samples=4096):
+    """Eq. 9 estimate: dict(grad=float64[d], loss=mean loss, losses=float64[N])."""
+    import torch
+    th, tp = _host(theta, np.float32)
+    sg, sp = _host(sigma, np.float32)
+    if th.size != scene.d or sg.size != scene.d:
+        raise ValueError("theta/sigma length must equal the scene's parameter count")
+    g = np.zeros(scene.d, np.float64)
+    q = C.c_double()
+    L = np.zeros(max(int(N), 1), np.float64)
+    _check(load().prdpt_grad_estimate_dp(scene.h, _dev(ref, torch.float32), tp, sp, int(N),
+                                         int(seed), int(edge_samples),
+                                         g.ctypes.data_as(C.c_void_p), C.byref(q),
+                                         L.ctypes.data_as(C.c_void_p)))
     return dict(grad=g, loss=q.value, losses=L)
 
 
