@@ -117,3 +117,34 @@ def test_many_objects_optimisation():
     finally:
         sc.destroy()
         ctx.close()
+
+
+def test_resumed_run_is_bit_identical(tmp_path):
+    # an interrupted run resumed from its checkpoint ends where the
+    # uninterrupted one does, bit for bit (same estimates, same Adam steps)
+    import torch
+    from paper_2211_17263_amd import native as NV
+    from paper_2211_17263_amd import optimize as OP
+    pr = S.toy_problem(seed=2)
+    say("resume")
+    ref = torch.from_numpy(O.OracleScene(pr["scene"]).reference(pr["theta_ref"], seed=4)).cuda()
+    ctx = NV.Context(0)
+    sc = NV.prdpt_scene_create(ctx, pr["scene"])
+    try:
+        kw = dict(sigma_min=0.05, warm_start=0.3, est=NV.PRDPT_EST_IS, seed=300)
+        full = OP.optimize(sc, ref, pr["theta0"], 0.5, 12, 0.03, 4, **kw)
+        path = str(tmp_path / "run.npz")
+        first = OP.optimize(sc, ref, pr["theta0"], 0.5, 12, 0.03, 4, checkpoint_path=path,
+                            checkpoint_every=2, stop_after=5, **kw)
+        assert OP.load_state(path).t == 5
+        rest = OP.optimize(sc, ref, None, None, None, None, None,
+                           resume=OP.load_state(path))
+        assert len(first.theta) + len(rest.theta) == 12
+        both = first.theta + rest.theta
+        for a, b in zip(full.theta, both):
+            assert np.array_equal(a, b)
+        assert np.array_equal(full.final_theta, rest.final_theta)
+        assert np.array_equal(full.state.m, rest.state.m) and np.array_equal(full.state.v, rest.state.v)
+    finally:
+        sc.destroy()
+        ctx.close()

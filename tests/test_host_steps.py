@@ -45,3 +45,23 @@ def test_warm_started_schedule():
     assert OP.sigma_at(0.5, 0.01, steps - 1, steps)[0] == np.float32(0.01)
     assert OP.sigma_at(1.0, 0.05, 0, 200, warm_start=0.0)[0] == np.float32(1.0)
     assert OP.sigma_at(1.0, 0.05, 199, 200, warm_start=0.0)[0] == np.float32(0.05)
+
+
+def test_driver_checkpoint_round_trip(tmp_path):
+    # the checkpoint holds the parameters, Adam's moments, the next iteration
+    # and the run's settings bit for bit, in a file that loads without pickle
+    import numpy as np
+    from paper_2211_17263_amd import optimize as OP
+    rng = np.random.default_rng(3)
+    st = OP.DriverState(theta=rng.normal(size=5), m=rng.normal(size=5), v=rng.random(5), t=17,
+                        steps=200, sigma0=np.array([1.0, 0.5, 0.25, 0.125, 0.0625]),
+                        sigma_min=0.05, warm_start=0.5, lr=0.01, N=32, est=1, seed=2**40 + 7)
+    path = str(tmp_path / "ckpt.npz")
+    OP.save_state(path, st)
+    back = OP.load_state(path)
+    for f in ("theta", "m", "v", "sigma0"):
+        assert np.array_equal(getattr(back, f).view(np.uint64), getattr(st, f).view(np.uint64))
+    for f in ("t", "steps", "sigma_min", "warm_start", "lr", "N", "est", "seed"):
+        assert getattr(back, f) == getattr(st, f)
+    with np.load(path, allow_pickle=False) as z:
+        assert all(z[k].dtype != object for k in z.files)
