@@ -343,18 +343,6 @@ __device__ __forceinline__ void push(int* __restrict__ lds, int stride, int* __r
   ++sp;
 }
 
-__device__ __forceinline__ int pop(const int* __restrict__ lds, int stride,
-                                   const int* __restrict__ ovf, int& sp) {
-  --sp;
-  // the LDS read is always in bounds; the private entry replaces it when the
-  // top lies beyond the LDS part
-  int e = lds[min(sp, kStackEntries - 1) * stride];
-  // (volatile: keeps this a private-memory load of its own rather than one
-  // generic load whose address selects between LDS and private memory)
-  if (sp >= kStackEntries) e = *(const volatile int*)&ovf[sp - kStackEntries];
-  return e;
-}
-
 // orders two (distance, reference) pairs by distance
 __device__ __forceinline__ void order2(float& ta, int& ra, float& tb, int& rb) {
   const bool sw = tb < ta;
@@ -486,9 +474,18 @@ __device__ bool continue_trace(const SceneLds& S, const Node* __restrict__ nodes
   while (true) {
     // ---- node loop: descend until enough lanes hold a leaf
     while (true) {
-      if (node < 0 && leaf == 0) {
-        if (sp > 0) {
-          const int e = pop(stack, stride, ovf, sp);
+      {
+        // pop into an empty hand; the LDS read is done by every lane (in
+        // bounds) and the private part is read where the top lies beyond the
+        // LDS part (in bounds too; the entry is used only where wanted)
+        const bool want = node < 0 && leaf == 0 && sp > 0;
+        const int top = sp - 1;
+        int e = stack[max(min(top, kStackEntries - 1), 0) * stride];
+        if (__ballot(sp > kStackEntries) != 0ull) {
+          if (sp > kStackEntries) e = *(const volatile int*)&ovf[top - kStackEntries];
+        }
+        if (want) {
+          sp = top;
           if (e < 0) leaf = e;
           else node = e;
         }
@@ -496,7 +493,7 @@ __device__ bool continue_trace(const SceneLds& S, const Node* __restrict__ nodes
       const bool ready = leaf != 0 || (node < 0 && sp == 0);
       if (__ballot(!ready) == 0ull) break;
 #if PRDPT_LEAF_QUORUM < 100
-      if (__popcll(__ballot(leaf != 0)) * 100 >= __popcll(__ballot(1)) * PRDPT_LEAF_QUORUM) break;
+      if (__popcll(__ballot(leaf < 0)) * 100 >= __popcll(__ballot(1)) * PRDPT_LEAF_QUORUM) break;
 #endif
       ++iters;
       if (node >= 0) {
@@ -532,6 +529,35 @@ __device__ bool continue_trace(const SceneLds& S, const Node* __restrict__ nodes
         // leaf becomes the pending leaf if none is; the others are pushed so
         // that nearer ones are popped first
         int next = -1, near_leaf = 0;
+        if (__ballot(sp > kStackEntries - 4) == 0ull) {
+          // a visit pushes at most four entries, and here all of them land in
+          // the LDS part: each child writes the entry it displaces (the
+          // previous nearest child of its kind) into the free slot above the
+          // top and the slot is kept only when that entry exists, with no
+          // branches
+          bool has_next = false, has_leaf = false;
+          // (bitwise operators on the flags keep them lane masks)
+          auto place = [&](float tc, int rc) {
+            const bool hit = tc < inf, is_inner = rc >= 0;
+            const bool inner = hit & is_inner, lf = hit & !is_inner;
+            stack[sp * stride] = inner ? next : near_leaf;
+            sp += (int)((inner & has_next) | (lf & has_leaf));
+            next = inner ? rc : next;
+            near_leaf = lf ? rc : near_leaf;
+            has_next = has_next | inner;
+            has_leaf = has_leaf | lf;
+          };
+          place(t3, r3);
+          place(t2, r2);
+          place(t1, r1);
+          place(t0, r0);
+          stack[sp * stride] = near_leaf;
+          sp += (int)(has_leaf & (leaf != 0));
+          leaf = leaf == 0 ? near_leaf : leaf;
+          node = next;
+          if (COUNT) cnt.deepest = max(cnt.deepest, (uint32_t)sp);
+          continue;
+        }
         if (t3 < inf) {
           if (r3 >= 0) next = r3;
           else near_leaf = r3;
