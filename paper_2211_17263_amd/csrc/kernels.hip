@@ -217,10 +217,12 @@ __device__ __forceinline__ unsigned long long hit_key(float t, int id) {
 }
 
 // LDS of the leaf phase: the wave's pending (lane, triangle) pairs in lane
-// order, as the owning lane of each, and each lane's best hit as a key.
+// order, as the owning lane of each, and each lane's best hit as a key.  The
+// owner table has kLeafMax spare entries: a lane with pairs stores kLeafMax
+// entries whatever its count.
 struct LeafLds {
   unsigned long long key[kBlock];
-  uint8_t owner[kBlock * kLeafMax];
+  uint8_t owner[kBlock * kLeafMax + kLeafMax];
 };
 static_assert(kBlock == 64, "the leaf phase spreads pairs over one wave");
 static_assert(sizeof(uint8_t) * kBlock * kLeafMax >= sizeof(uint32_t) * kBlock,
@@ -618,9 +620,14 @@ __device__ bool continue_trace(const SceneLds& S, const Node* __restrict__ nodes
       if (n_own > 0) {
         if (!any && h.id >= 0) mine = hit_key(h.t, h.id);
         lf->key[lane] = mine;
+        // pair excl + j of this lane, j < n_own, is owned by it.  The lanes
+        // with pairs have increasing excl, so no two of them store to one
+        // entry in the same store; storing from the last j down, an entry
+        // past this lane's count that belongs to a later lane is stored again
+        // by that lane (with a smaller j) afterwards, and the entries past the
+        // last pair are never read
 #pragma unroll
-        for (int j = 0; j < kLeafMax; ++j)
-          if (j < n_own) lf->owner[excl + j] = (uint8_t)lane;
+        for (int j = kLeafMax - 1; j >= 0; --j) lf->owner[excl + j] = (uint8_t)lane;
       }
       // pair p of this lane is triangle first + p - excl
       const int tri_base = first - excl;
