@@ -8,8 +8,11 @@ weights in binary64, then the host-side bandwidth schedule and Adam step.  The
 default workload is the caustic scene (512x512, 64 spp, 8 bounces, a glass
 sphere focusing an area light past a 50000-triangle occluder, 3 parameters,
 N = 32 importance-sampled perturbations, bandwidth annealed 1.0 -> 0.05); the
-global-illumination scene (256x256, 16 spp, 4 bounces, 6 parameters, N = 16)
-runs beside it under "extra_workloads".
+global-illumination scene (256x256, 16 spp, 4 bounces, 6 parameters, N = 16),
+Eq. 9 against Eq. 10 on the toy scene, the batched form (64 uneven jobs in one
+persistent graph launch against the plain per-request loop) and the served
+form (Poisson arrivals from 256 jobs against a plain FIFO, with p50/p99
+latency) run beside it under "extra_workloads".
 
 Prints one JSON line.  `value` is gradient estimates per second over the timed
 steps, `latency_ms` the per-step distribution (p10/p50/p90/p99); `roofline`
@@ -158,9 +161,11 @@ def main():
         return
 
     if args.workload == "batch":
-        return bench_batch(args, NV)
+        print(json.dumps(bench_batch(args, NV)), flush=True)
+        return
     if args.workload == "serve":
-        return bench_serve(args, NV)
+        print(json.dumps(bench_serve(args, NV)), flush=True)
+        return
     if args.workload == "inverse":
         return bench_inverse(args, NV)
     if args.workload == "highd":
@@ -181,6 +186,17 @@ def main():
             "value", "unit", "ms_per_step", "latency_ms", "config", "paths_per_s", "kernel",
             "roofline", "roofline_alu", "simd_efficiency")}}
         out["extra_workloads"]["toy_eq9_vs_eq10"] = eq9_vs_eq10(args, NV, cpu=not args.no_cpu)
+        # the batched and served forms against the plain per-request estimator
+        # (short runs: two timed batched and two plain passes over the 64 jobs;
+        # four 5 s arrival phases of the server)
+        sub = argparse.Namespace(**vars(args))
+        sub.steps, sub.warmup, sub.serve_seconds = 8, 1, 5.0
+        for key, fn in (("batch", bench_batch), ("serve", bench_serve)):
+            try:
+                out["extra_workloads"][key] = fn(sub, NV)
+            except Exception as e:  # noqa: BLE001 - the headline line must still print
+                log(f"{key} workload failed: {e!r}")
+                out["extra_workloads"][key] = {"error": repr(e)}
     print(json.dumps(out), flush=True)
 
 
@@ -668,7 +684,7 @@ def bench_batch(args, NV):
     for sc in scs:
         sc.destroy()
     ctx.close()
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def scene_roofline(NV, ctx, sc, ref, job, seed, K=5):
@@ -797,8 +813,12 @@ def bench_serve(args, NV):
            "config": {"workload": "serve", "jobs": len(jobs), "offered_rate": args.serve_rate,
                       "hbm_budget": budget, "max_batch": 64, "epochs_in_flight": 2},
            "latency_s": {"p50": s["latency_p50_s"], "p99": s["latency_p99_s"]},
+           "plain_per_request": {"value": res["plain"]["throughput_req_s"],
+                                 "latency_s": {"p50": res["plain"]["latency_p50_s"],
+                                               "p99": res["plain"]["latency_p99_s"]}},
+           "speedup_vs_plain": s["throughput_req_s"] / max(res["plain"]["throughput_req_s"], 1e-9),
            "phases": res}
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def copy_rate(ctx, NV, nbytes, iters):

@@ -85,3 +85,55 @@ def test_autograd_against_oracle_finite_differences():
     tol = 4.0 * np.sqrt(se_g ** 2 + se_fd ** 2)
     assert np.all(np.abs(g - fd) <= tol), (g, fd, se_g, se_fd)
     assert abs(fd[0]) > 10 * se_fd[0]      # the comparison has power
+
+
+def test_autograd_against_oracle_fd_on_batch_sized_scene():
+    """The same check on a scene of the batched workload's small end: 64x64,
+    one sample per pixel, two bounces, a 2000-triangle mesh (a random triangle
+    cloud plus an icosphere), an area light, a sphere; theta = the sphere's x
+    and the icosphere's x; importance-sampled perturbations in the forward."""
+    import torch
+    from paper_2211_17263_amd import native as NV
+    from paper_2211_17263_amd.autograd import smoothed_loss
+    rng = np.random.default_rng(21)
+    sc_desc, fields = S.random_job_scene(rng, 64, 2000, 1, 2)
+    for f in (fields[0], fields[9]):     # sphere centre x, icosphere translation x
+        sc_desc.bind(*f)
+    theta0 = np.array([0.25, -0.2], np.float32)
+    sigma = np.array([0.3, 0.3], np.float32)
+    say("autograd-fd", "64x64 2000 tris B=2")
+    osc = O.OracleScene(sc_desc)
+    ref = osc.reference(np.zeros(2, np.float32), seed=5)
+    Ng, seed_g = 2 * 20000, 4321
+    ctx = NV.Context(0)
+    sc = NV.prdpt_scene_create(ctx, sc_desc)
+    try:
+        ref_d = torch.from_numpy(ref).cuda()
+        theta = torch.tensor(theta0, device="cuda", requires_grad=True)
+        q = smoothed_loss(theta, sc, ref_d, sigma, Ng, seed_g, NV.PRDPT_EST_IS)
+        q.backward()
+        g = theta.grad.double().cpu().numpy()
+        r = NV.prdpt_grad_estimate(sc, ref_d, theta0, sigma, Ng, seed_g, NV.PRDPT_EST_IS)
+    finally:
+        sc.destroy()
+        ctx.close()
+    assert np.array_equal(g, r["grad"].astype(np.float32).astype(np.float64))
+    _, c = O.draw_tau(O.IS, sigma, Ng // 2, seed_g)
+    terms = c * (r["losses"][0::2] - r["losses"][1::2])[:, None]
+    se_g = terms.std(axis=0, ddof=1) / math.sqrt(terms.shape[0])
+    # the oracle's smoothed loss: central differences, common random numbers
+    No, seed_o, h = 2 * 4000, 99, 1e-3
+    fd = np.zeros(2)
+    se_fd = np.zeros(2)
+    for j in range(2):
+        e = np.zeros(2, np.float32)
+        e[j] = h
+        up = osc.grad_estimate(ref, theta0 + e, sigma, No, seed_o, O.GAUSS)["losses"]
+        dn = osc.grad_estimate(ref, theta0 - e, sigma, No, seed_o, O.GAUSS)["losses"]
+        hh = ((theta0 + e)[j].astype(np.float64) - (theta0 - e)[j].astype(np.float64))
+        per_pair = ((up[0::2] + up[1::2]) - (dn[0::2] + dn[1::2])) / (2.0 * hh)
+        fd[j] = per_pair.mean()
+        se_fd[j] = per_pair.std(ddof=1) / math.sqrt(per_pair.size)
+    tol = 4.0 * np.sqrt(se_g ** 2 + se_fd ** 2)
+    assert np.all(np.abs(g - fd) <= tol), (g, fd, se_g, se_fd)
+    assert np.all(np.abs(fd) > 6 * se_fd), (fd, se_fd)   # the comparison has power
