@@ -732,8 +732,17 @@ constexpr float kInvPi = 0.318309886183790671538f;
 // ---------------------------------------------------------------------------
 // kernels
 // ---------------------------------------------------------------------------
+// Five one-wave work-groups per SIMD (20 per CU): at most 96 VGPRs per lane
+// (512 / 5, in granules of 8) and at most 8192 bytes of LDS per work-group
+// (160 KB / 20), which the render kernels meet with the 15-entry LDS part of
+// the traversal stack and scenes of at most one sphere (more spheres lower
+// the resident count, which the launch reads from the occupancy calculator).
+// The fifth wave hides more of each wave's dependent-instruction latency: four
+// waves per SIMD (128 VGPRs, 23 LDS stack entries) took 3 % longer on both
+// workloads, although the register allocator now spills a few values outside
+// the traversal loops.
 #ifndef PRDPT_MIN_WAVES_PER_EU
-#define PRDPT_MIN_WAVES_PER_EU 4
+#define PRDPT_MIN_WAVES_PER_EU 5
 #endif
 
 // Load the scene constants and the spheres into LDS and apply perturbation k's

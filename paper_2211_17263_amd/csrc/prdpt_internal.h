@@ -19,8 +19,11 @@ constexpr int kMaxDepth4 = (kMaxInnerDepth + 1) / 2;
 // node adds one entry for itself.  kStackEntries live in LDS, the rest in a
 // small per-lane private array that only unusually deep descents reach.
 constexpr int kStackBound = 3 * kMaxDepth4 + 1;
+// 15 LDS entries keep a render work-group within 8192 bytes of LDS, so that
+// five fit a SIMD; deeper entries (a descent past 15 pending entries) go to
+// the private part.
 #ifndef PRDPT_STACK_LDS
-#define PRDPT_STACK_LDS 23
+#define PRDPT_STACK_LDS 15
 #endif
 constexpr int kStackEntries = PRDPT_STACK_LDS;
 constexpr int kStackOverflow = kStackBound - kStackEntries;
