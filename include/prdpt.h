@@ -165,7 +165,11 @@ const char* prdpt_last_error(void);
  * beyond it fails with PRDPT_E_ADMISSION.  Scratch that the context allocates
  * on first use and keeps until it is destroyed is not counted: per-estimate
  * arrays of O(N d + N tiles) elements (N tiles: 4 bytes per perturbation and
- * 8x8 pixel tile), allocated with 50 % slack.
+ * pixel tile), allocated with 50 % slack.  A scene renders in tiles of 8x8
+ * pixels, or of 4x4 pixels when its image has fewer than 2048 8x8 tiles and
+ * at least 16 samples per pixel (more, smaller work items for the persistent
+ * render kernel); the choice depends on the scene alone, so every entry point
+ * and the batched and served forms render a scene the same way.
  */
 int prdpt_ctx_create(int device, void* stream, size_t hbm_budget, prdpt_ctx** out);
 /* Synchronise and release the context's own memory (scenes must be destroyed first). */
@@ -283,7 +287,8 @@ int prdpt_grad_estimate_async(prdpt_scene* scene, const float* ref_dev, const fl
  * until the process ends.  A request needs, each rounded up to 256 bytes:
  * N d floats (parameter rows), R d floats (draws) and, if c_dev is NULL, R d
  * doubles (weights), with R = N/2 (R = N with PRDPT_EST_INDEPENDENT); N x
- * tiles floats (tile losses; tiles = ceil(W/8) ceil(H/8)); N doubles if
+ * tiles floats (tile losses; tiles = ceil(W/t) ceil(H/t) for the scene's tile
+ * size t, 8 or 4, see prdpt_ctx_create); N doubles if
  * losses_dev is NULL; one int.  Larger requests fail with PRDPT_E_ARG before
  * anything is enqueued.  All calls on one device share that array and each
  * call leaves its contents behind (the work counter is cleared by a kernel at
@@ -347,7 +352,8 @@ int prdpt_batch_estimate(prdpt_ctx* ctx, prdpt_request* reqs, int n);
 
 /*
  * Launch configuration of the batched form: persistent work-groups per compute
- * unit, pixel tiles (8x8) per work item, and whether to replay a captured
+ * unit, pixel tiles (of the scene's tile size) per work item, and whether to
+ * replay a captured
  * graph (1) or launch the kernels directly (0).
  */
 int prdpt_batch_config(prdpt_ctx* ctx, int blocks_per_cu, int tiles_per_item, int use_graph);
@@ -471,6 +477,22 @@ int prdpt_traversal_counts(prdpt_scene* scene, const float* theta, const float* 
  */
 int prdpt_copy_probe(prdpt_ctx* ctx, const void* src, void* dst, size_t bytes, int iters,
                      double* ms_per_copy);
+
+/*
+ * Self-test of the render kernel's arithmetic.  The renderer behind the
+ * estimator (Sec. 3.1's black box, made reproducible) rounds every division
+ * and square root on its geometric chain correctly, like the reference CPU
+ * implementation; the kernel forms 1/x and sqrt(x) from the hardware
+ * reciprocal and square root with fused-residual corrections instead of the
+ * compiler's longer correctly rounded sequences.  This runs all 2^32
+ * binary32 inputs through the three forms (the reciprocal on its domain:
+ * +-0, +-inf, NaN and normal |x| <= 2^126; the square root core on its
+ * domain: |x| >= 2^-104, +-0, +inf, NaN; the square root for every input)
+ * and compares each result with the correctly rounded operation (NaN equals
+ * NaN).  mismatches: host uint64_t[3], the three counts in that order (all
+ * zero when the forms are exact).  Synchronous; a few milliseconds.
+ */
+int prdpt_selftest_math(prdpt_ctx* ctx, uint64_t* mismatches);
 
 /*
  * Host-side step of the optimisation loop around the estimator (Sec. 3.3-3.4):

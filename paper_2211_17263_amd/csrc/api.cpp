@@ -96,7 +96,8 @@ hipError_t timed_render(prdpt_ctx* ctx, const prdpt_scene* s, const float* X, in
       if (e != hipSuccess) return e;
     }
   }
-  hipError_t e = launch_render(ctx->stream, sc, W, H, X, nk, d, tag, seed, ref, img, partial, nullptr,
+  hipError_t e = launch_render(ctx->stream, sc, W, H, s->hdr.tile_log2, X, nk, d, tag, seed, ref, img,
+                               partial, nullptr,
                                work, s->d_tile_order, s->d_tile_cost, crn, s->hdr.has_rot,
                                s->hdr.n_sph);
   if (e != hipSuccess) return e;
@@ -116,7 +117,7 @@ int check_request(const prdpt_scene* s, const float* theta, const float* sigma, 
   if (N < 2 || (N & 1)) return fail(PRDPT_E_ARG, "N must be even and >= 2");
   if (N > (1 << 20)) return fail(PRDPT_E_ARG, "N too large");
   // (perturbation, tile) work items are counted in 32 bits
-  if ((long long)N * render_tiles(s->hdr.W, s->hdr.H) >= (1ll << 31))
+  if ((long long)N * render_tiles(s->hdr.W, s->hdr.H, s->hdr.tile_log2) >= (1ll << 31))
     return fail(PRDPT_E_ARG, "N x pixel tiles must stay below 2^31");
   if (host_vectors) {
     for (int j = 0; j < s->hdr.n_param; ++j) {
@@ -179,7 +180,7 @@ int enqueue_into(prdpt_scene* s, const float* ref, const float* theta_dev, const
   const int d = h.n_param;
   const int indep = (est & PRDPT_EST_INDEPENDENT) != 0;
   const int rows = n_draws(est, N);
-  const int n_tiles = render_tiles(h.W, h.H);
+  const int n_tiles = render_tiles(h.W, h.H, h.tile_log2);
   double* c = c_dev ? c_dev : b.c;
   double* L = losses_dev ? losses_dev : b.losses;
   HIP_TRY(launch_tau(ctx->stream, est, d, rows, seed, sigma_dev, theta_dev, chi_mean(d),
@@ -197,7 +198,7 @@ int enqueue_estimate(prdpt_scene* s, const float* ref, const float* theta_dev,
                      double* loss_dev, double* losses_dev, double* c_dev) {
   prdpt_ctx* ctx = s->ctx;
   const SceneHdr& h = s->hdr;
-  if (int rc = prepare(ctx, N, h.n_param, render_tiles(h.W, h.H))) return rc;
+  if (int rc = prepare(ctx, N, h.n_param, render_tiles(h.W, h.H, h.tile_log2))) return rc;
   const EstimateBufs b{ctx->X.p, ctx->tau.p, ctx->c.p, ctx->partial.p, ctx->losses.p, ctx->work.p};
   return enqueue_into(s, ref, theta_dev, sigma_dev, N, seed, est, grad_dev, loss_dev, losses_dev,
                       c_dev, b, true);
@@ -379,6 +380,7 @@ int prdpt::build_host_scene(const prdpt_scene_desc* D, HostScene& hs) {
   // multiplying by the inverse of a power-of-two size is exact
   h.inv_w = (h.W & (h.W - 1)) == 0 ? 1.0f / (float)h.W : 0.0f;
   h.inv_h = (h.H & (h.H - 1)) == 0 ? 1.0f / (float)h.H : 0.0f;
+  h.tile_log2 = render_tile_log2(h.W, h.H, h.spp);
   for (int i = 0; i < h.n_sph; ++i) {
     for (int c = 0; c < 4; ++c) h.sph[i][c] = D->spheres[4 * i + c];
     h.sph_mat[i] = D->sphere_mat[i];
@@ -498,7 +500,7 @@ int prdpt::build_host_scene(const prdpt_scene_desc* D, HostScene& hs) {
   }
   hs.footprint = sizeof(SceneHdr) + nodes.size() * sizeof(Node) + tris.size() * sizeof(Tri) +
                  tris.size() * sizeof(int32_t) +
-                 (size_t)render_tiles(h.W, h.H) * (sizeof(float) + sizeof(int));
+                 (size_t)render_tiles(h.W, h.H, h.tile_log2) * (sizeof(float) + sizeof(int));
   return PRDPT_OK;
 }
 
@@ -524,7 +526,7 @@ int prdpt::upload_scene(prdpt_ctx* ctx, const HostScene& hs, prdpt_scene** out) 
     delete s;
     return fail(PRDPT_E_HIP, "hipSetDevice failed");
   }
-  s->n_tiles = render_tiles(h.W, h.H);
+  s->n_tiles = render_tiles(h.W, h.H, h.tile_log2);
   auto release = [&]() {
     if (s->d_hdr) hipFree(s->d_hdr);
     if (s->d_nodes) hipFree(s->d_nodes);
@@ -641,11 +643,11 @@ int prdpt_render_perturbed(prdpt_scene* s, const float* theta, const float* sigm
   const int d = h.n_param, rows = n_draws(est, N);
   std::lock_guard<std::mutex> g(ctx->mu);
   HIP_TRY(hipSetDevice(ctx->device));
-  if (int rc = prepare(ctx, N, d, render_tiles(h.W, h.H))) return rc;
+  if (int rc = prepare(ctx, N, d, render_tiles(h.W, h.H, h.tile_log2))) return rc;
   if (int rc = upload_vectors(ctx, theta, sigma, d)) return rc;
   HIP_TRY(launch_tau(ctx->stream, est, d, rows, seed, ctx->sigma.p, ctx->theta.p, chi_mean(d),
                      std::sqrt(2.0 * M_PI), ctx->tau.p, ctx->c.p, ctx->X.p));
-  HIP_TRY(launch_render(ctx->stream, s->dev(), h.W, h.H, ctx->X.p, N, d, kTagPath, seed, nullptr,
+  HIP_TRY(launch_render(ctx->stream, s->dev(), h.W, h.H, h.tile_log2, ctx->X.p, N, d, kTagPath, seed, nullptr,
                         images_out, nullptr, nullptr, ctx->work.p, s->d_tile_order,
                         s->d_tile_cost, (est & PRDPT_EST_INDEPENDENT) ? 0 : 1, h.has_rot,
                         h.n_sph));
@@ -663,9 +665,9 @@ int prdpt_render_reference(prdpt_scene* s, const float* X, uint64_t seed, float*
   const int d = h.n_param;
   std::lock_guard<std::mutex> g(ctx->mu);
   HIP_TRY(hipSetDevice(ctx->device));
-  if (int rc = prepare(ctx, 2, d, render_tiles(h.W, h.H))) return rc;
+  if (int rc = prepare(ctx, 2, d, render_tiles(h.W, h.H, h.tile_log2))) return rc;
   HIP_TRY(hipMemcpyAsync(ctx->X.p, X, sizeof(float) * d, hipMemcpyHostToDevice, ctx->stream));
-  HIP_TRY(launch_render(ctx->stream, s->dev(), h.W, h.H, ctx->X.p, 1, d, kTagRef, seed, nullptr,
+  HIP_TRY(launch_render(ctx->stream, s->dev(), h.W, h.H, h.tile_log2, ctx->X.p, 1, d, kTagRef, seed, nullptr,
                         image_out, nullptr, nullptr, ctx->work.p, s->d_tile_order,
                         s->d_tile_cost, 1, h.has_rot, h.n_sph));
   HIP_TRY(hipStreamSynchronize(ctx->stream));
@@ -682,7 +684,7 @@ int prdpt_grad_estimate(prdpt_scene* s, const float* ref, const float* theta, co
   const int d = s->hdr.n_param;
   std::lock_guard<std::mutex> g(ctx->mu);
   HIP_TRY(hipSetDevice(ctx->device));
-  if (int rc = prepare(ctx, N, d, render_tiles(s->hdr.W, s->hdr.H))) return rc;
+  if (int rc = prepare(ctx, N, d, render_tiles(s->hdr.W, s->hdr.H, s->hdr.tile_log2))) return rc;
   // one pinned upload of [theta | sigma], one pinned download of
   // [grad | loss | losses]
   const size_t n_in = 2 * (size_t)d, n_out = (size_t)d + 1 + (size_t)N;
@@ -731,7 +733,7 @@ int prdpt_grad_estimate_dp(prdpt_scene* s, const float* ref, const float* theta,
   const int bi = dp_interior_blocks(h.W, h.H), be = dp_edge_blocks(edge_samples);
   std::lock_guard<std::mutex> g(ctx->mu);
   HIP_TRY(hipSetDevice(ctx->device));
-  if (int rc = prepare(ctx, N, d, render_tiles(h.W, h.H))) return rc;
+  if (int rc = prepare(ctx, N, d, render_tiles(h.W, h.H, h.tile_log2))) return rc;
   if (int rc = ensure(ctx, ctx->images, (size_t)N * npix * 3)) return rc;
   if (int rc = ensure(ctx, ctx->dp_partial, (size_t)N * (bi + be) * 3)) return rc;
   if (int rc = upload_vectors(ctx, theta, sigma, d)) return rc;
@@ -739,7 +741,7 @@ int prdpt_grad_estimate_dp(prdpt_scene* s, const float* ref, const float* theta,
                      chi_mean(d), std::sqrt(2.0 * M_PI), ctx->tau.p, ctx->c.p, ctx->X.p));
   HIP_TRY(timed_render(ctx, s, ctx->X.p, N, d, kTagPath, seed, ref, ctx->images.p, ctx->partial.p, 1,
                        ctx->work.p));
-  HIP_TRY(launch_losses(ctx->stream, ctx->partial.p, render_tiles(h.W, h.H), N, (int)npix,
+  HIP_TRY(launch_losses(ctx->stream, ctx->partial.p, render_tiles(h.W, h.H, h.tile_log2), N, (int)npix,
                         ctx->losses.p));
   double* pin = ctx->dp_partial.p;
   double* pedge = pin + (size_t)N * bi * 3;
@@ -765,7 +767,7 @@ int prdpt_smoothed_loss(prdpt_scene* s, const float* ref, const float* theta, co
   const int d = s->hdr.n_param;
   std::lock_guard<std::mutex> g(ctx->mu);
   HIP_TRY(hipSetDevice(ctx->device));
-  if (int rc = prepare(ctx, N, d, render_tiles(s->hdr.W, s->hdr.H))) return rc;
+  if (int rc = prepare(ctx, N, d, render_tiles(s->hdr.W, s->hdr.H, s->hdr.tile_log2))) return rc;
   if (int rc = upload_vectors(ctx, theta, sigma, d)) return rc;
   if (int rc = enqueue_estimate(s, ref, ctx->theta.p, ctx->sigma.p, N, seed, PRDPT_EST_GAUSS,
                                 ctx->grad.p, ctx->loss.p, nullptr, nullptr))
@@ -799,7 +801,7 @@ int prdpt_grad_estimate_noalloc(prdpt_scene* s, const float* ref_dev, const floa
   prdpt_ctx* ctx = s->ctx;
   const SceneHdr& h = s->hdr;
   const size_t d = (size_t)h.n_param, rows = (size_t)n_draws(est, N);
-  const size_t n_tiles = (size_t)render_tiles(h.W, h.H);
+  const size_t n_tiles = (size_t)render_tiles(h.W, h.H, h.tile_log2);
   // the estimate's arrays, each at a 256-byte boundary of the scratch array
   size_t used = 0;
   auto take = [&](size_t bytes) {
@@ -884,13 +886,13 @@ int prdpt_traversal_counts(prdpt_scene* s, const float* theta, const float* sigm
   const int d = h.n_param, rows = n_draws(est, N);
   std::lock_guard<std::mutex> g(ctx->mu);
   HIP_TRY(hipSetDevice(ctx->device));
-  if (int rc = prepare(ctx, N, d, render_tiles(h.W, h.H))) return rc;
+  if (int rc = prepare(ctx, N, d, render_tiles(h.W, h.H, h.tile_log2))) return rc;
   if (int rc = ensure(ctx, ctx->counters, 10)) return rc;
   if (int rc = upload_vectors(ctx, theta, sigma, d)) return rc;
   HIP_TRY(hipMemsetAsync(ctx->counters.p, 0, 10 * sizeof(unsigned long long), ctx->stream));
   HIP_TRY(launch_tau(ctx->stream, est, d, rows, seed, ctx->sigma.p, ctx->theta.p, chi_mean(d),
                      std::sqrt(2.0 * M_PI), ctx->tau.p, ctx->c.p, ctx->X.p));
-  HIP_TRY(launch_render(ctx->stream, s->dev(), h.W, h.H, ctx->X.p, N, d, kTagPath, seed, nullptr,
+  HIP_TRY(launch_render(ctx->stream, s->dev(), h.W, h.H, h.tile_log2, ctx->X.p, N, d, kTagPath, seed, nullptr,
                         nullptr, nullptr, ctx->counters.p, ctx->work.p, s->d_tile_order,
                         nullptr, (est & PRDPT_EST_INDEPENDENT) ? 0 : 1, s->hdr.has_rot,
                         s->hdr.n_sph));
@@ -921,6 +923,24 @@ int prdpt_copy_probe(prdpt_ctx* ctx, const void* src, void* dst, size_t bytes, i
   hipEventDestroy(a);
   hipEventDestroy(b);
   *ms_per_copy = (double)ms / iters;
+  return PRDPT_OK;
+}
+
+int prdpt_selftest_math(prdpt_ctx* ctx, uint64_t* mismatches) {
+  if (!ctx || !mismatches) return fail(PRDPT_E_ARG, "bad self-test arguments");
+  std::lock_guard<std::mutex> g(ctx->mu);
+  HIP_TRY(hipSetDevice(ctx->device));
+  unsigned long long* d = nullptr;
+  if (dev_malloc((void**)&d, 3 * sizeof(unsigned long long)) != hipSuccess)
+    return fail(PRDPT_E_NOMEM, "self-test counters");
+  hipError_t e = hipMemsetAsync(d, 0, 3 * sizeof(unsigned long long), ctx->stream);
+  if (e == hipSuccess) e = launch_math_selftest(ctx->stream, d);
+  unsigned long long h[3] = {0, 0, 0};
+  if (e == hipSuccess) e = hipMemcpyAsync(h, d, sizeof h, hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  (void)hipFree(d);
+  if (e != hipSuccess) return fail(PRDPT_E_HIP, hipGetErrorString(e));
+  for (int i = 0; i < 3; ++i) mismatches[i] = h[i];
   return PRDPT_OK;
 }
 

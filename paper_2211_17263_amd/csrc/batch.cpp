@@ -167,7 +167,7 @@ int batch_enqueue(prdpt_ctx* ctx, BatchState& b, prdpt_request* reqs, int n, std
   const int tpi = b.tiles_per_item;
   for (int i : ok) {
     const SceneHdr& h = reqs[i].scene->hdr;
-    const int nt = render_tiles(h.W, h.H);
+    const int nt = render_tiles(h.W, h.H, h.tile_log2);
     pairs += reqs[i].N / 2;
     rows += reqs[i].N;
     partial += (size_t)reqs[i].N * nt;
@@ -188,7 +188,7 @@ int batch_enqueue(prdpt_ctx* ctx, BatchState& b, prdpt_request* reqs, int n, std
     t.H = h.H;
     t.N = r.N;
     t.d = h.n_param;
-    t.n_tiles = render_tiles(h.W, h.H);
+    t.n_tiles = render_tiles(h.W, h.H, h.tile_log2);
     t.items_per_row = (t.n_tiles + tpi - 1) / tpi;
     t.est = r.est;
     t.k0 = (uint32_t)r.seed;

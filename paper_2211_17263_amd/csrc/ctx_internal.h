@@ -13,15 +13,19 @@
 namespace prdpt {
 BvhOut build_bvh(const float* tri9, const int32_t* tri_mat, const int32_t* list, int n,
                  int32_t id_base, std::vector<Node>& nodes, std::vector<Tri>& tris);
-int render_tiles(int W, int H);
+// render tiles of an image with tiles of 2^tile_log2 square pixels, and the
+// tile size the library chooses for an image (scene constant tile_log2)
+int render_tiles(int W, int H, int tile_log2);
+int render_tile_log2(int W, int H, int spp);
 hipError_t launch_tau(hipStream_t st, int est, int d, int P, uint64_t seed, const float* sigma,
                       const float* theta, double cd, double sqrt2pi, float* tau, double* c, float* X);
-hipError_t launch_render(hipStream_t st, const DevScene& sc, int W, int H, const float* X, int nk,
+hipError_t launch_render(hipStream_t st, const DevScene& sc, int W, int H, int tile_log2,
+                         const float* X, int nk,
                          int d, int tag, uint64_t seed, const float* ref, float* img,
                          float* partial, unsigned long long* counters, int* work,
                          const int* order, float* cost, int crn, int rot, int n_sph);
 // resident render work-groups for a variant and sphere count (the grid bound)
-int render_grid_limit(int rot, int n_sph);
+int render_grid_limit(int rot, int n_sph, int tile_log2);
 // Rz(c) Ry(b) Rx(a) of the angles (a, b, c), row-major (the kernels' own formula)
 void euler_rotation_host(const float* ang, float* R);
 // normal and squared length, unit normal and area of a quad [origin, edge1,
@@ -42,6 +46,9 @@ hipError_t launch_batch(hipStream_t st, const BatchReq* reqs, BatchMeta* meta, i
                         int rot, int max_sph, float* tau, double* c, float* X,
                         float* partial, double* losses, double* grads, double* loss);
 hipError_t launch_copy(hipStream_t st, const void* src, void* dst, size_t n16);
+// exhaustive check of the render kernel's fast correctly rounded reciprocal
+// and square root (exact_math.h): adds the mismatch counts to bad[0..2]
+hipError_t launch_math_selftest(hipStream_t st, unsigned long long* bad);
 // Eq. 9: interior and edge derivative terms of N renders weighted by their
 // (I - R), reduced to the gradient and the mean loss; pin/pedge hold
 // N x dp_interior_blocks / dp_edge_blocks rows of 3 doubles

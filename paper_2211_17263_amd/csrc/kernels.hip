@@ -21,6 +21,7 @@
 #include <cstring>
 #include <mutex>
 
+#include "exact_math.h"
 #include "prdpt_internal.h"
 
 namespace prdpt {
@@ -114,9 +115,12 @@ __device__ __forceinline__ float dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y 
 __device__ __forceinline__ V3 cross(V3 a, V3 b) {
   return mk(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
 }
+// a / |a|: the correctly rounded root of the squared length, its correctly
+// rounded reciprocal (the root of a non-negative float is +0, a normal number
+// below 2^64, +inf or NaN: recip_nr's domain) and three products
 __device__ __forceinline__ V3 unit(V3 a) {
-  const float len = sqrtf(dot(a, a));
-  const float inv = 1.0f / len;
+  const float len = sqrt_cr(dot(a, a));
+  const float inv = recip_nr(len);
   return scale(a, inv);
 }
 __device__ __forceinline__ V3 at(V3 o, V3 d, float t) {
@@ -135,7 +139,7 @@ __device__ __forceinline__ bool hit_sphere(V3 o, V3 d, const float* sp, float tm
   const float cc = dot(oc, oc) - r * r;
   const float disc = b * b - a * cc;
   if (disc < 0.0f) return false;
-  const float sq = sqrtf(disc);
+  const float sq = sqrt_cr(disc);
   const float q = (b >= 0.0f) ? -(b + sq) : -(b - sq);
   if (q == 0.0f) return false;
   const float t0 = q / a, t1 = cc / q;
@@ -195,7 +199,7 @@ __device__ __forceinline__ bool hit_tri(V3 o, V3 d, V3 v0, V3 e1, V3 e2, float t
   return hit;
 }
 
-constexpr int kTileW = 8, kTileH = 8, kBlock = kTileW * kTileH;  // one wave per 8x8 tile
+constexpr int kBlock = 64;  // one wave per render tile (8x8 or 4x4 pixels)
 
 struct Hit {
   float t;
@@ -703,7 +707,9 @@ __device__ __forceinline__ V3 offset_origin(V3 p, V3 n) {
 // orthonormal basis around a unit vector (Duff et al., JCGT 2017)
 __device__ __forceinline__ void basis(V3 n, V3* b1, V3* b2) {
   const float sign = copysignf(1.0f, n.z);
-  const float a = -1.0f / (sign + n.z);
+  // -1 / (sign + n.z), correctly rounded: for a unit n, |sign + n.z| lies in
+  // [1, 2] (or is NaN), recip_nr's domain, and negation is exact
+  const float a = -recip_nr(sign + n.z);
   const float b = n.x * n.y * a;
   *b1 = mk(1.0f + sign * n.x * n.x * a, sign * b, -sign * n.x);
   *b2 = mk(b, sign + n.y * n.y * a, -n.y);
@@ -714,7 +720,8 @@ __device__ __forceinline__ void basis(V3 n, V3* b1, V3* b2) {
 __device__ __forceinline__ float fresnel_dielectric(float cosi, float ei, float et, float eta) {
   const float sin2t = (eta * eta) * (1.0f - cosi * cosi);
   if (sin2t >= 1.0f) return 1.0f;
-  const float cost = sqrtf(1.0f - sin2t);
+  // sin2t is a float below 1, so 1 - sin2t >= 2^-24: sqrt_nr's domain
+  const float cost = sqrt_nr(1.0f - sin2t);
   const float rs = (ei * cosi - et * cost) / (ei * cosi + et * cost);
   const float rp = (et * cosi - ei * cost) / (et * cosi + ei * cost);
   return 0.5f * (rs * rs + rp * rp);
@@ -795,7 +802,10 @@ __device__ __forceinline__ void load_state(SceneLds& S, float* __restrict__ sph,
 // and the sum, are reproducible, and nothing per path goes to device memory.
 // Per sample the radiance terms are added in the same order as a recursive
 // implementation (vertex by vertex; point lights, then area lights).
-template <bool COUNT, bool ROT>
+// LG: the tile size as a compile-time log2 (2 or 3), or 0 to read it from the
+// scene (the batched kernel and the counting copy); both decode tiles and
+// jobs with the same integer arithmetic, so they render a tile identically.
+template <bool COUNT, bool ROT, int LG>
 __device__ __forceinline__ void render_tile(const SceneLds& S, const float* __restrict__ sph,
                                             const int* __restrict__ sph_mat,
                                             const Node* __restrict__ nodes,
@@ -808,16 +818,21 @@ __device__ __forceinline__ void render_tile(const SceneLds& S, const float* __re
                                             int* __restrict__ stack, float* __restrict__ wsum,
                                             int crn, volatile int* __restrict__ next_job,
                                             LeafLds* __restrict__ lf, PixLds* __restrict__ pix_sum) {
-  const int tiles_x = (S.W + kTileW - 1) / kTileW;
+  // the tile: ts x ts pixels (ts = 8, or 4 for images of few tiles and many
+  // samples per pixel), tiles in row-major order
+  const int lg = LG ? LG : S.tile_log2, ts = 1 << lg;
+  const int tiles_x = (S.W + ts - 1) >> lg;
   const int t = threadIdx.x;
-  const int tx0 = (tile % tiles_x) * kTileW, ty0 = (tile / tiles_x) * kTileH;
-  const int lx = t & 7, ly = t >> 3;  // lane t sums and writes pixel (lx, ly) of the tile
+  const int tx0 = (tile % tiles_x) << lg, ty0 = (tile / tiles_x) << lg;
+  // lane t sums and writes pixel slot t = (lx, ly) of the tile
+  const int lx = t & (ts - 1), ly = t >> lg;
   const int x = tx0 + lx, y = ty0 + ly;
-  const bool valid = x < S.W && y < S.H;
+  const bool valid = ly < ts && x < S.W && y < S.H;
   const int pix = y * S.W + x;
   // the tile's valid pixels (tw x th) and its jobs: pixel q, sample c + j / nv
-  const int tw = min(kTileW, S.W - tx0), th = min(kTileH, S.H - ty0);
+  const int tw = min(ts, S.W - tx0), th = min(ts, S.H - ty0);
   const int nv = tw * th;
+  const bool full = nv == ts * ts;  // wave-uniform
   // path streams: the two renders of an antithetic pair share stream k / 2
   // (common random numbers); independent renders (crn = 0) use stream k
   const int pair = crn ? k >> 1 : k;
@@ -839,15 +854,15 @@ __device__ __forceinline__ void render_tile(const SceneLds& S, const float* __re
   int v = 0, mat = 0, light = -1;          // light >= 0: next-event stage of a diffuse vertex
   uint4 w = make_uint4(0u, 0u, 0u, 0u);
 
-  // the path in flight: sample jslot >> 6 of the tile pixel (jslot & 7,
-  // (jslot >> 3) & 7), whose sum is pix_sum entry jslot & 63; -1 when the lane
-  // has none
+  // the path in flight: sample jslot >> 6 of the tile pixel in slot
+  // jslot & 63 = x + ts y, whose sum is pix_sum entry jslot & 63; -1 when the
+  // lane has none
   int jslot = -1;
   bool tracing = false;   // a query is in flight (possibly suspended)
   bool answered = false;  // the last query's result (tr.h) is still to be used
   Trav tr;
   // image pixel index and sample of the path in flight
-  auto path_pix = [&]() { return (ty0 + ((jslot >> 3) & 7)) * S.W + tx0 + (jslot & 7); };
+  auto path_pix = [&]() { return (ty0 + ((jslot & 63) >> lg)) * S.W + tx0 + (jslot & (ts - 1)); };
   auto path_smp = [&]() { return jslot >> 6; };
   const int n_jobs = nv * spp;
   uint32_t* const claim = reinterpret_cast<uint32_t*>(lf->owner);
@@ -940,7 +955,8 @@ __device__ __forceinline__ void render_tile(const SceneLds& S, const float* __re
                 side = nn;
               } else {
                 const float sin2t = (eta * eta) * (1.0f - cosi * cosi);
-                const float cost = sqrtf(1.0f - sin2t);
+                // refraction only when F < 1, i.e. sin2t < 1: 1 - sin2t >= 2^-24
+                const float cost = sqrt_nr(1.0f - sin2t);
                 const float kk = eta * cosi - cost;
                 nd = mk(dir.x * eta + nn.x * kk, dir.y * eta + nn.y * kk, dir.z * eta + nn.z * kk);
                 side = neg(nn);
@@ -964,8 +980,8 @@ __device__ __forceinline__ void render_tile(const SceneLds& S, const float* __re
               const float* lp = S.pl[light];
               const V3 toL = sub(ld3(lp), p);
               const float dist2 = dot(toL, toL);
-              const float dist = sqrtf(dist2);
-              const V3 wi = scale(toL, 1.0f / dist);
+              const float dist = sqrt_cr(dist2);
+              const V3 wi = scale(toL, recip_nr(dist));  // dist: a root, as in unit()
               const float cx = dot(n, wi);
               if (!(cx > 0.0f)) continue;
               c0 = b0 * f0 * ((lp[3] * cx) / dist2);
@@ -996,8 +1012,8 @@ __device__ __forceinline__ void render_tile(const SceneLds& S, const float* __re
             const float area = S.quad_nu[qi][3];
             const V3 toL = sub(yl, p);
             const float dist2 = dot(toL, toL);
-            const float dist = sqrtf(dist2);
-            const V3 wi = scale(toL, 1.0f / dist);
+            const float dist = sqrt_cr(dist2);
+            const V3 wi = scale(toL, recip_nr(dist));  // dist: a root, as in unit()
             const float cx = dot(n, wi);
             const float cl = -dot(nlu, wi);
             if (!(cx > 0.0f && cl > 0.0f)) continue;
@@ -1018,10 +1034,11 @@ __device__ __forceinline__ void render_tile(const SceneLds& S, const float* __re
               end_path = true;
             } else {
               const float u1 = unit_open(w.z), u2 = unit_open(w.w);
-              const float r = sqrtf(u1);
+              // u1 and 1 - u1 lie in [2^-24, 1]: sqrt_nr's domain
+              const float r = sqrt_nr(u1);
               float sn, cs;
               sincos_turn(u2, &sn, &cs);
-              const float lx2 = r * cs, ly2 = r * sn, lz2 = sqrtf(1.0f - u1);
+              const float lx2 = r * cs, ly2 = r * sn, lz2 = sqrt_nr(1.0f - u1);
               V3 e1, e2;
               basis(n, &e1, &e2);
               dir = unit(mk(e1.x * lx2 + e2.x * ly2 + n.x * lz2, e1.y * lx2 + e2.y * ly2 + n.y * lz2,
@@ -1069,11 +1086,11 @@ __device__ __forceinline__ void render_tile(const SceneLds& S, const float* __re
         const int j = base + rank;
         if (rank == 0) *next_job = base + __popcll(m);
         if (j >= n_jobs) break;  // this lane is done with the tile
-        const int q = nv == kBlock ? (j & (kBlock - 1)) : j % nv;
-        const int sj = nv == kBlock ? (j >> 6) : j / nv;
-        const int qx = tw == kTileW ? (q & (kTileW - 1)) : q % tw;
-        const int qy = tw == kTileW ? (q >> 3) : q / tw;
-        jslot = sj * kBlock + qx + kTileW * qy;
+        const int q = full ? (j & (nv - 1)) : j % nv;
+        const int sj = full ? (j >> (2 * lg)) : j / nv;
+        const int qx = tw == ts ? (q & (ts - 1)) : q % tw;
+        const int qy = tw == ts ? (q >> lg) : q / tw;
+        jslot = sj * kBlock + qx + (qy << lg);
         // camera ray of the path
         if (COUNT) cnt.paths++;
         float jxo = 0.5f, jyo = 0.5f;
@@ -1174,7 +1191,7 @@ __device__ __forceinline__ void render_tile(const SceneLds& S, const float* __re
 // tiles by cost for the next launch puts the cheapest tiles last and shortens
 // the tail where few work-groups are still busy.  Outputs do not depend on
 // the order.
-template <bool COUNT, bool ROT>
+template <bool COUNT, bool ROT, int LG>
 __global__ __launch_bounds__(kBlock, PRDPT_MIN_WAVES_PER_EU) void render_loss_kernel(
     DevScene scene, const float* __restrict__ X, int d, int tag, uint32_t k0, uint32_t k1,
     const float* __restrict__ ref, float* __restrict__ img, float* __restrict__ partial,
@@ -1205,7 +1222,7 @@ __global__ __launch_bounds__(kBlock, PRDPT_MIN_WAVES_PER_EU) void render_loss_ke
     }
     unsigned long long t0 = 0;
     if (cost && threadIdx.x == 0) t0 = wall_clock64();
-    render_tile<COUNT, ROT>(S, sph, sph_mat, scene.nodes, scene.tris, scene.tri_slot, k, tile,
+    render_tile<COUNT, ROT, LG>(S, sph, sph_mat, scene.nodes, scene.tris, scene.tri_slot, k, tile,
                        tag, k0, k1, ref, img,
                        partial ? partial + (size_t)k * n_tiles + tile : nullptr, counters, stack,
                        wsum, crn, &s_job, &s_leaf, &s_pix);
@@ -1506,7 +1523,7 @@ __global__ __launch_bounds__(kBlock, PRDPT_MIN_WAVES_PER_EU) void batch_render_k
     load_state(S, sph, sph_mat, q.scene.hdr, X + (size_t)(q.row_base + k) * PRDPT_BATCH_MAX_PARAMS,
                q.d);
     for (int tile = first; tile < last; ++tile) {
-      render_tile<false, ROT>(S, sph, sph_mat, q.scene.nodes, q.scene.tris, q.scene.tri_slot, k,
+      render_tile<false, ROT, 0>(S, sph, sph_mat, q.scene.nodes, q.scene.tris, q.scene.tri_slot, k,
                          tile, kTagPath, q.k0, q.k1, q.ref,
                          nullptr, partial + (size_t)q.partial_base + (size_t)k * q.n_tiles + tile,
                          nullptr, stack, wsum, 1, &s_job, &s_leaf, &s_pix);
@@ -1543,6 +1560,33 @@ __global__ void batch_combine_kernel(const BatchReq* __restrict__ reqs,
 
 // Plain streaming copy (16-byte loads and stores, grid-stride): the reference
 // for achievable HBM bandwidth and for scaling the memory counters.
+// Every binary32 x in [base, base + n) (as bit patterns): each fast
+// correctly rounded operation of exact_math.h against the compiler's correctly
+// rounded one, on the inputs of its stated domain; a NaN equals any NaN.
+// bad[0..2]: recip_nr, sqrt_nr, sqrt_cr mismatches.
+__device__ __forceinline__ bool same_value(float a, float b) {
+  return (a != a && b != b) || __float_as_uint(a) == __float_as_uint(b);
+}
+__global__ __launch_bounds__(256) void math_selftest_kernel(uint32_t base, uint32_t n,
+                                                            unsigned long long* __restrict__ bad) {
+  uint32_t c0 = 0, c1 = 0, c2 = 0;
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const float x = __uint_as_float(base + i);
+    const float ax = fabsf(x);
+    const float q = 1.0f / x, r = sqrtf(x);
+    const bool rdom = ax <= 0x1p126f ? (ax >= 0x1p-126f || ax == 0.0f) : !(ax < __builtin_huge_valf());
+    c0 += rdom && !same_value(recip_nr(x), q);
+    const bool sdom = !(ax > 0.0f && ax < 0x1p-104f);
+    c1 += sdom && !same_value(sqrt_nr(x), r);
+    c2 += !same_value(sqrt_cr(x), r);
+    if (i > 0xffffffffu - stride) break;  // the next index would wrap
+  }
+  if (c0) atomicAdd(&bad[0], (unsigned long long)c0);
+  if (c1) atomicAdd(&bad[1], (unsigned long long)c1);
+  if (c2) atomicAdd(&bad[2], (unsigned long long)c2);
+}
+
 __global__ __launch_bounds__(256) void copy_kernel(const float4* __restrict__ src,
                                                    float4* __restrict__ dst, size_t n) {
   const size_t stride = (size_t)gridDim.x * blockDim.x;
@@ -1939,7 +1983,17 @@ hipError_t noalloc_scratch(int device, void** out) {
   return hipSuccess;
 }
 
-int render_tiles(int W, int H) { return ((W + kTileW - 1) / kTileW) * ((H + kTileH - 1) / kTileH); }
+int render_tiles(int W, int H, int tile_log2) {
+  const int ts = 1 << tile_log2;
+  return ((W + ts - 1) / ts) * ((H + ts - 1) / ts);
+}
+
+int render_tile_log2(int W, int H, int spp) {
+  // 4x4 tiles quadruple the work items of images under 2048 8x8 tiles, which
+  // otherwise leave the persistent grid with a few items per work-group and a
+  // long tail; 16 samples per pixel still give each item 256 paths
+  return (render_tiles(W, H, 3) < 2048 && spp >= 16) ? 2 : 3;
+}
 
 hipError_t launch_tau(hipStream_t st, int est, int d, int P, uint64_t seed, const float* sigma,
                       const float* theta, double cd, double sqrt2pi, float* tau, double* c, float* X) {
@@ -1951,21 +2005,30 @@ hipError_t launch_tau(hipStream_t st, int est, int d, int P, uint64_t seed, cons
 
 // resident work-groups of the render kernel on the current device for the
 // variant and the dynamic LDS of n_sph spheres (cached)
-int render_grid_limit(int rot, int n_sph) {
-  static int cached[64][2][PRDPT_MAX_SPHERES + 1];
+int render_grid_limit(int rot, int n_sph, int tile_log2) {
+  static int cached[64][2][2][PRDPT_MAX_SPHERES + 1];
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
   if (n_sph < 0 || n_sph > PRDPT_MAX_SPHERES) return 0;
   rot = rot ? 1 : 0;
-  int& slot = cached[dev][rot][n_sph];
+  const int small = tile_log2 == 2 ? 1 : 0;
+  int& slot = cached[dev][rot][small][n_sph];
   if (slot > 0) return slot;
   int n_cu = 0, per_cu = 0;
   if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
   const size_t lds = (size_t)sphere_lds_bytes(n_sph);
-  const hipError_t e = rot ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                                 &per_cu, render_loss_kernel<false, true>, kBlock, lds)
-                           : hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                                 &per_cu, render_loss_kernel<false, false>, kBlock, lds);
+  hipError_t e;
+  if (rot) {
+    e = small ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, render_loss_kernel<false, true, 2>,
+                                                             kBlock, lds)
+              : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, render_loss_kernel<false, true, 3>,
+                                                             kBlock, lds);
+  } else {
+    e = small ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, render_loss_kernel<false, false, 2>,
+                                                             kBlock, lds)
+              : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, render_loss_kernel<false, false, 3>,
+                                                             kBlock, lds);
+  }
   if (e != hipSuccess) return 0;
   slot = std::max(1, n_cu * std::max(1, per_cu));
   return slot;
@@ -2020,29 +2083,35 @@ void quad_frame_host(const float* q, float* n, float* nu) {
   nu[3] = area;
 }
 
-hipError_t launch_render(hipStream_t st, const DevScene& sc, int W, int H, const float* X, int nk,
+hipError_t launch_render(hipStream_t st, const DevScene& sc, int W, int H, int tile_log2,
+                         const float* X, int nk,
                          int d, int tag, uint64_t seed, const float* ref, float* img,
                          float* partial, unsigned long long* counters, int* work,
                          const int* order, float* cost, int crn, int rot, int n_sph) {
-  const int n_tiles = render_tiles(W, H);
+  const int n_tiles = render_tiles(W, H, tile_log2);
   const long long n_items = (long long)n_tiles * nk;
   if (n_items >= (1ll << 31)) return hipErrorInvalidValue;  // the work counter is an int
-  const int limit = render_grid_limit(rot, n_sph);
+  const int limit = render_grid_limit(rot, n_sph, tile_log2);
   if (limit <= 0) return hipErrorInvalidDevice;
   const size_t lds = (size_t)sphere_lds_bytes(n_sph);
   const int blocks = (int)std::min<long long>(n_items, limit);
   hipLaunchKernelGGL(reset_work_kernel, dim3(1), dim3(64), 0, st, work);
   const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
-#define PRDPT_RENDER(C, R)                                                                       \
-  hipLaunchKernelGGL((render_loss_kernel<C, R>), dim3(blocks), dim3(kBlock), lds, st, sc, X, d,  \
-                     tag, k0, k1, ref, img, partial, counters, n_tiles, (int)n_items, work, order, \
+#define PRDPT_RENDER(C, R, L)                                                                      \
+  hipLaunchKernelGGL((render_loss_kernel<C, R, L>), dim3(blocks), dim3(kBlock), lds, st, sc, X, d,  \
+                     tag, k0, k1, ref, img, partial, counters, n_tiles, (int)n_items, work, order,    \
                      cost, crn)
+  // the counting copy reads the tile size from the scene; the timed kernels
+  // have it as a constant
   if (counters) {
-    if (rot) PRDPT_RENDER(true, true);
-    else PRDPT_RENDER(true, false);
+    if (rot) PRDPT_RENDER(true, true, 0);
+    else PRDPT_RENDER(true, false, 0);
+  } else if (tile_log2 == 2) {
+    if (rot) PRDPT_RENDER(false, true, 2);
+    else PRDPT_RENDER(false, false, 2);
   } else {
-    if (rot) PRDPT_RENDER(false, true);
-    else PRDPT_RENDER(false, false);
+    if (rot) PRDPT_RENDER(false, true, 3);
+    else PRDPT_RENDER(false, false, 3);
   }
 #undef PRDPT_RENDER
   return hipGetLastError();
@@ -2103,6 +2172,14 @@ hipError_t launch_dp(hipStream_t st, const SceneHdr* hdr, int W, int H, const fl
                      M, be, pedge);
   hipLaunchKernelGGL(dp_combine_kernel, dim3(1), dim3(64), 0, st, N, d, bi, be, pin, pedge,
                      1.0 / (3.0 * (double)W * (double)H), losses, grad, loss);
+  return hipGetLastError();
+}
+
+hipError_t launch_math_selftest(hipStream_t st, unsigned long long* bad) {
+  // all 2^32 bit patterns in two halves (the index range of one launch is 32-bit)
+  hipLaunchKernelGGL(math_selftest_kernel, dim3(8192), dim3(256), 0, st, 0u, 0x80000000u, bad);
+  hipLaunchKernelGGL(math_selftest_kernel, dim3(8192), dim3(256), 0, st, 0x80000000u, 0x80000000u,
+                     bad);
   return hipGetLastError();
 }
 

@@ -69,6 +69,7 @@ struct SceneLds {
   int32_t n_mat, n_sph, n_quad, n_inst, n_pl, n_param, n_area, n_tri;
   int32_t tri_id_base;                       // n_sph + n_quad
   float inv_w, inv_h;                        // 1/W, 1/H when W, H are powers of two, else 0
+  int32_t tile_log2;                         // render tiles of 2^tile_log2 square pixels (3 or 2)
   int32_t mat_type[PRDPT_MAX_MATERIALS];
   float mat_rgb[PRDPT_MAX_MATERIALS][3];     // a dielectric's [0] holds 1/ior (rounded)
   float mat_ior[PRDPT_MAX_MATERIALS];

@@ -30,7 +30,8 @@ EXPORTS = [
     "prdpt_render_reference", "prdpt_smoothed_loss", "prdpt_grad_estimate",
     "prdpt_grad_estimate_async", "prdpt_combine_async", "prdpt_ctx_set_timing",
     "prdpt_ctx_read_timing", "prdpt_traversal_counts", "prdpt_sigma_schedule", "prdpt_adam_step",
-    "prdpt_copy_probe", "prdpt_batch_estimate", "prdpt_batch_config", "prdpt_batch_autotune",
+    "prdpt_copy_probe", "prdpt_selftest_math", "prdpt_batch_estimate", "prdpt_batch_config",
+    "prdpt_batch_autotune",
     "prdpt_server_start", "prdpt_server_add_job", "prdpt_server_submit", "prdpt_server_cancel",
     "prdpt_server_poll", "prdpt_server_get_stats", "prdpt_server_stop",
     "prdpt_server_submit_deadline", "prdpt_debug_fail_allocations",
@@ -126,6 +127,7 @@ def load():
     L.prdpt_adam_step.argtypes = [i32, dp, dp, dp, dp, i32, C.c_double, C.c_double, C.c_double,
                                   C.c_double]
     L.prdpt_copy_probe.argtypes = [vp, vp, vp, sz, i32, C.POINTER(C.c_double)]
+    L.prdpt_selftest_math.argtypes = [vp, C.POINTER(C.c_uint64)]
     L.prdpt_batch_estimate.argtypes = [vp, C.POINTER(Request), i32]
     L.prdpt_batch_config.argtypes = [vp, i32, i32, i32]
     L.prdpt_batch_autotune.argtypes = [vp, C.POINTER(Request), i32, C.c_char_p,
@@ -403,6 +405,15 @@ def prdpt_copy_probe(ctx, src, dst, iters=10):
     ms = C.c_double()
     _check(load().prdpt_copy_probe(ctx.h, _dev(src), _dev(dst), nbytes, int(iters), C.byref(ms)))
     return ms.value
+
+
+def prdpt_selftest_math(ctx):
+    """Mismatch counts of the render kernel's fast correctly rounded
+    reciprocal and square root over every binary32 input of their domains:
+    (reciprocal, square-root core, square root)."""
+    out = (C.c_uint64 * 3)()
+    _check(load().prdpt_selftest_math(ctx.h, out))
+    return tuple(int(v) for v in out)
 
 
 def prdpt_sigma_schedule(sigma0, sigma_end, t, T):
