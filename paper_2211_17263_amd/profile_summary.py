@@ -6,7 +6,9 @@ kernel-trace mode: per-kernel call count and mean/min/max duration from a
 counters mode: issue-level counters of one kernel (mean per dispatch over the
 last dispatches with the largest grid) from any number of ``--pmc`` runs, and
 the VALU issue utilisation they imply: wave-level VALU instructions x 4 cycles
-(a wave64 instruction occupies a 16-lane SIMD for 4 cycles) over the SIMD-cycles
+(a wave64 instruction occupies a 16-lane SIMD for 4 cycles; some instructions
+issue faster, so the ratio can exceed 1 when the pipes are saturated) over the
+SIMD-cycles
 of the dispatch (GRBM_GUI_ACTIVE, summed over the 8 XCDs, over 8, times 1024
 SIMDs).
 
