@@ -126,12 +126,14 @@ def kernel_trace(a):
             def grid(r):
                 return int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"])
             g = max(grid(r) for r in rows)
-            big = sorted((r for r in rows if grid(r) == g), key=lambda r: int(r["Start_Timestamp"]))
+            big = sorted((r for r in rows if a.any_grid or grid(r) == g),
+                         key=lambda r: int(r["Start_Timestamp"]))
             if a.last:
                 big = big[-a.last:]
             ms = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6 for r in big]
             which = f"the last {a.last} " if a.last else ""
-            out += ["", f"`{a.kernel}`, {which}dispatches with the largest grid ({g} work-items): "
+            sel = "" if a.any_grid else f" with the largest grid ({g} work-items)"
+            out += ["", f"`{a.kernel}`, {which}dispatches{sel}: "
                     f"{len(ms)}, mean {statistics.mean(ms):.3f} ms, min {min(ms):.3f} ms, "
                     f"max {max(ms):.3f} ms"]
     out += ["", *a.note]
@@ -173,6 +175,8 @@ def main():
                    help="also summarise this kernel's largest-grid dispatches")
     k.add_argument("--last", type=int, default=0,
                    help="only the last N of those dispatches (the timed ones)")
+    k.add_argument("--any-grid", action="store_true",
+                   help="take the kernel's dispatches of every grid size, not only the largest")
     k.add_argument("--out", required=True)
     a = ap.parse_args()
     {"traffic": traffic, "counters": counters, "trace": kernel_trace}[a.mode](a)
