@@ -197,8 +197,10 @@ def test_ragged_tiny_and_degenerate(ctx):
 
 
 def test_more_samples_than_one_wave(ctx):
-    # more samples per pixel (80) than lanes in a wave: the tile's paths are
-    # 80 x 64 jobs, several of the same pixel finishing in one iteration
+    # more samples per pixel (80) than lanes in a wave, several paths of the
+    # same pixel finishing in one iteration; a small image with at least 16
+    # samples per pixel renders in 4x4 tiles, here with ragged edges
+    # (21 x 13: 80 x 16 jobs per full tile)
     sc = S.toy_scene(width=21, height=13, spp=80, bounces=1)
     pr = dict(scene=sc, theta_ref=np.zeros(2, np.float32), theta0=np.array([0.3, -0.2], np.float32),
               sigma=np.full(2, 0.3, np.float32), N=4, est=O.IS)
