@@ -1082,8 +1082,12 @@ __device__ __forceinline__ void render_tile(const SceneLds& S, const float* __re
         const unsigned long long m = __ballot(1);
         const int rank = (int)__builtin_amdgcn_mbcnt_hi(
             (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-        const int base = *next_job;
+        // one read of the wave's job counter, broadcast, then the update: the
+        // update depends on the value read, so no lane can see it early,
+        // however the compiler lays out the branch
+        const int base = __builtin_amdgcn_readfirstlane(*next_job);
         const int j = base + rank;
+        __builtin_amdgcn_wave_barrier();
         if (rank == 0) *next_job = base + __popcll(m);
         if (j >= n_jobs) break;  // this lane is done with the tile
         const int q = full ? (j & (nv - 1)) : j % nv;
