@@ -629,9 +629,16 @@ __device__ bool continue_trace(const SceneLds& S, const Node* __restrict__ nodes
         // entry in the same store; storing from the last j down, an entry
         // past this lane's count that belongs to a later lane is stored again
         // by that lane (with a smaller j) afterwards, and the entries past the
-        // last pair are never read
+        // last pair are never read.  The result rests on the order of the
+        // stores, which a single-lane view of the code does not see (four
+        // stores to distinct bytes), so a wave barrier, which memory
+        // operations may not cross, separates them: the compiler can neither
+        // reorder nor merge them
 #pragma unroll
-        for (int j = kLeafMax - 1; j >= 0; --j) lf->owner[excl + j] = (uint8_t)lane;
+        for (int j = kLeafMax - 1; j >= 0; --j) {
+          lf->owner[excl + j] = (uint8_t)lane;
+          __builtin_amdgcn_wave_barrier();
+        }
       }
       // pair p of this lane is triangle first + p - excl
       const int tri_base = first - excl;
