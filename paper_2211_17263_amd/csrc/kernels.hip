@@ -299,8 +299,9 @@ __device__ __forceinline__ float safe_inv(float x) {
 //
 // Traversal is "while-while" with postponed leaves: the node loop visits inner
 // nodes, and a hit leaf child becomes the lane's pending leaf (or is pushed if
-// one is already pending); lanes holding a leaf keep descending speculatively.
-// The wave leaves the node loop once every lane holds a leaf or has no work
+// one is already pending); lanes holding a leaf keep descending speculatively,
+// into the nearest inner child and into inner nodes popped from the stack
+// (they stop at a leaf on top).  The wave leaves the node loop once every lane holds a leaf or has no work
 // left, or once at least PRDPT_LEAF_QUORUM percent of its active lanes hold
 // one.  The leaf phase then lists the (lane, triangle) pairs of all pending
 // leaves and deals them out to every active lane, a pair per lane per round:
@@ -483,13 +484,15 @@ __device__ bool continue_trace(const SceneLds& S, const Node* __restrict__ nodes
       {
         // pop into an empty hand; the LDS read is done by every lane (in
         // bounds) and the private part is read where the top lies beyond the
-        // LDS part (in bounds too; the entry is used only where wanted)
-        const bool want = node < 0 && leaf == 0 && sp > 0;
+        // LDS part (in bounds too; the entry is used only where wanted).  A
+        // lane holding a pending leaf still pops an inner node from the top
+        // (speculative descent), but leaves a leaf entry in place
         const int top = sp - 1;
         int e = stack[max(min(top, kStackEntries - 1), 0) * stride];
         if (__ballot(sp > kStackEntries) != 0ull) {
           if (sp > kStackEntries) e = *(const volatile int*)&ovf[top - kStackEntries];
         }
+        const bool want = node < 0 && sp > 0 && (leaf == 0 || e >= 0);
         if (want) {
           sp = top;
           if (e < 0) leaf = e;
@@ -537,30 +540,24 @@ __device__ bool continue_trace(const SceneLds& S, const Node* __restrict__ nodes
         int next = -1, near_leaf = 0;
         if (__ballot(sp > kStackEntries - 4) == 0ull) {
           // a visit pushes at most four entries, and here all of them land in
-          // the LDS part: each child writes the entry it displaces (the
-          // previous nearest child of its kind) into the free slot above the
-          // top and the slot is kept only when that entry exists, with no
-          // branches
-          bool has_next = false, has_leaf = false;
+          // the LDS part.  The h hit children are t0..t(h-1) (misses sort
+          // last); children 1..h-1 go on the stack, nearest on top, and the
+          // nearest child is visited next when inner, or becomes the pending
+          // leaf, or, when a leaf is already pending, goes on top of them
+          // (a leaf on top stops the speculative pops until the leaf phase).
+          // The stores of kept children are the only branches
+          const int h = (int)(t0 < inf) + (int)(t1 < inf) + (int)(t2 < inf) + (int)(t3 < inf);
+          const int b = sp + h - 4;  // child i is stored at slot b + 3 - i when i < h
+          if (h > 3) stack[b * stride] = r3;
+          if (h > 2) stack[(b + 1) * stride] = r2;
+          if (h > 1) stack[(b + 2) * stride] = r1;
+          sp += max(h - 1, 0);
           // (bitwise operators on the flags keep them lane masks)
-          auto place = [&](float tc, int rc) {
-            const bool hit = tc < inf, is_inner = rc >= 0;
-            const bool inner = hit & is_inner, lf = hit & !is_inner;
-            stack[sp * stride] = inner ? next : near_leaf;
-            sp += (int)((inner & has_next) | (lf & has_leaf));
-            next = inner ? rc : next;
-            near_leaf = lf ? rc : near_leaf;
-            has_next = has_next | inner;
-            has_leaf = has_leaf | lf;
-          };
-          place(t3, r3);
-          place(t2, r2);
-          place(t1, r1);
-          place(t0, r0);
-          stack[sp * stride] = near_leaf;
-          sp += (int)(has_leaf & (leaf != 0));
-          leaf = leaf == 0 ? near_leaf : leaf;
-          node = next;
+          const bool hit0 = h > 0, inner0 = r0 >= 0;
+          stack[sp * stride] = r0;  // a free slot, kept only for a second leaf
+          sp += (int)(hit0 & !inner0 & (leaf != 0));
+          leaf = (hit0 & !inner0 & (leaf == 0)) ? r0 : leaf;
+          node = (hit0 & inner0) ? r0 : -1;
           if (COUNT) cnt.deepest = max(cnt.deepest, (uint32_t)sp);
           continue;
         }

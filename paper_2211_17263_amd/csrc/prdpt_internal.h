@@ -15,8 +15,10 @@ constexpr int kMaxInnerDepth = 25;  // depth bound of the binary tree the builde
 constexpr int kMaxDepth4 = (kMaxInnerDepth + 1) / 2;
 // Traversal stack entries per ray: every node on the current path keeps at
 // most three of its children on the stack and the last one visited at most
-// four (all four children leaves while a leaf is already pending); a suspended
-// node adds one entry for itself.  kStackEntries live in LDS, the rest in a
+// four (its nearest child a leaf while a leaf is already pending: that leaf
+// goes on top, and a lane holding a leaf pops no leaf, so the lane descends
+// no further until the leaf phase); a suspended node adds one entry for
+// itself.  kStackEntries live in LDS, the rest in a
 // small per-lane private array that only unusually deep descents reach.
 constexpr int kStackBound = 3 * kMaxDepth4 + 1;
 // 15 LDS entries keep a render work-group within 8192 bytes of LDS, so that
