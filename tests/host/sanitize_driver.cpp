@@ -5,6 +5,7 @@
 // triangle in exactly one leaf, padded leaf boxes containing their triangles,
 // 4-wide depth within the traversal stack bound), every entry point's argument
 // checks, the host optimiser step, and context creation without a device.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -125,6 +126,146 @@ static void random_soup(SceneArrays& a, int n, float extent, float size, unsigne
   }
 }
 
+// One lane of the render kernel's node loop, replayed on the host to check the
+// traversal stack bound.  Every box the ray meets is kept (no distance
+// culling: the most entries), and the decisions the other lanes of a wave
+// make are drawn at random: whether a visit takes the branch-free placement
+// (only possible while this lane is four entries or more from the LDS part's
+// end) or the branchy one, when the wave turns to the leaf phase (which
+// clears the pending leaf), and when it suspends the query (the node being
+// visited goes back on the stack).  The placement and pop rules are the
+// kernel's: the nearest hit child visited next when inner, else made the
+// pending leaf or pushed on top; a lane holding a leaf pops inner entries
+// only.  Returns the deepest stack; *overflow is set when a push would pass
+// kStackBound.
+static int emulate_lane(const HostScene& hs, const float o[3], const float d[3], std::mt19937& rng,
+                        bool* overflow) {
+  const float inf = INFINITY;
+  float inv[3], oi[3];
+  for (int a = 0; a < 3; ++a) {
+    const float x = std::fabs(d[a]) < 1e-20f ? std::copysign(1e-20f, d[a]) : d[a];
+    inv[a] = 1.0f / x;
+    oi[a] = -o[a] * inv[a];
+  }
+  std::vector<int> st(kStackBound + 4, 0);
+  int sp = 0, node = -1, leaf = 0, deepest = 0;
+  auto push = [&](int e) {
+    if (sp >= kStackBound) {
+      *overflow = true;
+      return;
+    }
+    st[sp++] = e;
+    deepest = std::max(deepest, sp);
+  };
+  push(hs.hdr.inst_root[0]);
+  for (long long it = 0; it < 50000000LL; ++it) {
+    const int e = sp > 0 ? st[sp - 1] : 0;
+    if (node < 0 && sp > 0 && (leaf == 0 || e >= 0)) {
+      --sp;
+      if (e < 0) leaf = e;
+      else node = e;
+    }
+    if (node < 0 && leaf == 0 && sp == 0) break;
+    const bool ready = leaf != 0 || (node < 0 && sp == 0);
+    if (rng() % (ready ? 3 : 5) == 0) {  // the wave breaks (all ready, or the leaf quorum)
+      leaf = 0;  // the leaf phase
+      if (node >= 0 && rng() % 6 == 0) {  // suspended: resumes with an empty hand
+        push(node);
+        node = -1;
+      }
+      continue;
+    }
+    if (node < 0) continue;
+    const Node& nd = hs.nodes[node];
+    float t[4];
+    int r[4];
+    for (int c = 0; c < 4; ++c) {
+      const float lo[3] = {nd.lox[c], nd.loy[c], nd.loz[c]}, hi[3] = {nd.hix[c], nd.hiy[c], nd.hiz[c]};
+      float tmin = 0.0f, tmax = inf;
+      for (int a = 0; a < 3; ++a) {
+        const float t0 = lo[a] * inv[a] + oi[a], t1 = hi[a] * inv[a] + oi[a];
+        tmin = std::max(tmin, std::min(t0, t1));
+        tmax = std::min(tmax, std::max(t0, t1));
+      }
+      t[c] = (lo[0] <= hi[0] && tmin <= tmax) ? tmin : inf;
+      r[c] = nd.ref[c];
+    }
+    auto order2 = [&](int a, int b) {
+      if (t[b] < t[a]) {
+        std::swap(t[a], t[b]);
+        std::swap(r[a], r[b]);
+      }
+    };
+    order2(0, 1);
+    order2(2, 3);
+    order2(0, 2);
+    order2(1, 3);
+    order2(1, 2);
+    node = -1;
+    if (sp <= kStackEntries - 4 && rng() % 4 != 0) {  // branch-free placement
+      const int h = (t[0] < inf) + (t[1] < inf) + (t[2] < inf) + (t[3] < inf);
+      for (int i = h - 1; i >= 1; --i) push(r[i]);
+      if (h > 0) {
+        if (r[0] >= 0) node = r[0];
+        else if (leaf == 0) leaf = r[0];
+        else push(r[0]);
+      }
+    } else {  // branchy placement: nearest inner child next, nearest leaf pending
+      int next = -1, near_leaf = 0;
+      for (int i = 3; i >= 0; --i) {
+        if (!(t[i] < inf)) continue;
+        if (r[i] >= 0) {
+          if (next >= 0) push(next);
+          next = r[i];
+        } else {
+          if (near_leaf != 0) push(near_leaf);
+          near_leaf = r[i];
+        }
+      }
+      if (near_leaf != 0) {
+        if (leaf == 0) leaf = near_leaf;
+        else push(near_leaf);
+      }
+      node = next;
+    }
+  }
+  return deepest;
+}
+
+// Deepest emulated stack over `rays` rays aimed from around the tree's bounds
+// at points inside them.
+static int emulate_rays(const HostScene& hs, int rays, unsigned seed) {
+  float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  const Node& root = hs.nodes[hs.hdr.inst_root[0]];
+  for (int c = 0; c < 4; ++c) {
+    if (root.ref[c] == kEmptyChild) continue;
+    const float l[3] = {root.lox[c], root.loy[c], root.loz[c]}, h[3] = {root.hix[c], root.hiy[c], root.hiz[c]};
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = std::min(lo[a], l[a]);
+      hi[a] = std::max(hi[a], h[a]);
+    }
+  }
+  std::mt19937 rng(seed);
+  std::uniform_real_distribution<float> u(0.0f, 1.0f);
+  int deepest = 0;
+  bool overflow = false;
+  for (int i = 0; i < rays; ++i) {
+    float o[3], d[3], len = 0.0f;
+    for (int a = 0; a < 3; ++a) {
+      const float ext = hi[a] - lo[a];
+      o[a] = lo[a] - 0.5f * ext + 2.0f * ext * u(rng);
+      d[a] = lo[a] + ext * u(rng) - o[a];
+      len += d[a] * d[a];
+    }
+    if (!(len > 0.0f)) continue;
+    for (int a = 0; a < 3; ++a) d[a] /= std::sqrt(len);
+    deepest = std::max(deepest, emulate_lane(hs, o, d, rng, &overflow));
+  }
+  CHECK(!overflow);
+  CHECK(deepest <= kStackBound);
+  return deepest;
+}
+
 int main(int argc, char** argv) {
   // ---- the GPU tests' deep-stack scene (raw float32 [n][9] triangles): its
   // tree must stay within the stack bound while exceeding the LDS part
@@ -142,6 +283,7 @@ int main(int argc, char** argv) {
       const int depth = check_tree(hs, (int)(a.tris.size() / 9));
       std::printf("file depth4=%d stack_bound=%d lds_entries=%d\n", depth, 3 * depth + 1,
                   kStackEntries);
+      std::printf("file emulated deepest stack=%d\n", emulate_rays(hs, 24, 5u));
     }
   }
   // ---- BVH builds and invariants
@@ -153,7 +295,8 @@ int main(int argc, char** argv) {
     HostScene hs;
     CHECK(build_host_scene(&d, hs) == PRDPT_OK);
     const int depth = check_tree(hs, n);
-    std::printf("soup n=%d nodes=%zu depth4=%d\n", n, hs.nodes.size(), depth);
+    std::printf("soup n=%d nodes=%zu depth4=%d emulated deepest stack=%d\n", n, hs.nodes.size(),
+                depth, emulate_rays(hs, n >= 1000 ? 64 : 16, 17u + n));
   }
   {  // every triangle identical: no split separates them
     SceneArrays a;
@@ -189,6 +332,7 @@ int main(int argc, char** argv) {
     const int depth = check_tree(hs, n);
     std::printf("deep depth4=%d stack_bound=%d lds_entries=%d private_entries=%d\n", depth,
                 3 * depth + 1, kStackEntries, kStackOverflow);
+    std::printf("deep emulated deepest stack=%d\n", emulate_rays(hs, 64, 9u));
     CHECK(3 * depth + 1 <= kStackBound);
   }
   // ---- the division-free quad coordinate test decides as the division does:

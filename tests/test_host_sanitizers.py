@@ -59,3 +59,10 @@ def test_host_code_under_sanitizers(tmp_path):
     m = re.search(r"file depth4=(\d+) stack_bound=(\d+) lds_entries=(\d+)", r.stdout)
     depth, bound, lds = (int(g) for g in m.groups())
     assert lds < bound <= 3 * 13 + 1, r.stdout
+    # one lane of the node loop replayed on the host (no distance culling,
+    # random wave decisions): within the bound, and past the LDS part on the
+    # deep-stack scene as on the GPU
+    emu = [int(v) for v in re.findall(r"emulated deepest stack=(\d+)", r.stdout)]
+    assert emu and max(emu) <= bound, r.stdout
+    m = re.search(r"file emulated deepest stack=(\d+)", r.stdout)
+    assert lds < int(m.group(1)) <= bound, r.stdout
