@@ -238,6 +238,13 @@ struct PixLds {
   float rgb[3][kBlock];
 };
 static_assert(kLeafMax <= 7, "leaf counts are added up from three ballots");
+// static LDS of a render work-group: 20 of them (five waves per SIMD) fit a
+// CU only within 6 allocation units, with room for one sphere
+constexpr size_t kRenderStaticLds = sizeof(SceneLds) + sizeof(int) * kStackEntries * kBlock +
+                                    sizeof(float) * (kBlock / 64) + 2 * sizeof(int) +
+                                    sizeof(LeafLds) + sizeof(PixLds);
+static_assert(kRenderStaticLds + 20 <= 6 * kLdsAllocUnit,
+              "the render work-group's LDS must stay within six allocation units");
 
 // Work counters of the instrumented kernel copy: lane-level work (nodes,
 // triangles, rays, paths) and wave-level loop iterations (counted once per wave
@@ -2038,6 +2045,21 @@ int render_grid_limit(int rot, int n_sph, int tile_log2) {
                                                              kBlock, lds);
   }
   if (e != hipSuccess) return 0;
+  // the occupancy calculator assumes a finer LDS allocation than the
+  // hardware's 1280-byte units; a grid above the resident count would leave
+  // work-groups waiting for others to exit
+  hipFuncAttributes fa{};
+  int lds_cu = 0;
+  const void* fn = rot ? (small ? reinterpret_cast<const void*>(render_loss_kernel<false, true, 2>)
+                                : reinterpret_cast<const void*>(render_loss_kernel<false, true, 3>))
+                       : (small ? reinterpret_cast<const void*>(render_loss_kernel<false, false, 2>)
+                                : reinterpret_cast<const void*>(render_loss_kernel<false, false, 3>));
+  if (hipFuncGetAttributes(&fa, fn) == hipSuccess &&
+      hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) ==
+          hipSuccess && lds_cu > 0) {
+    const size_t units = (fa.sharedSizeBytes + lds + kLdsAllocUnit - 1) / kLdsAllocUnit;
+    per_cu = std::min(per_cu, (int)((size_t)lds_cu / (units * kLdsAllocUnit)));
+  }
   slot = std::max(1, n_cu * std::max(1, per_cu));
   return slot;
 }

@@ -21,12 +21,16 @@ constexpr int kMaxDepth4 = (kMaxInnerDepth + 1) / 2;
 // itself.  kStackEntries live in LDS, the rest in a
 // small per-lane private array that only unusually deep descents reach.
 constexpr int kStackBound = 3 * kMaxDepth4 + 1;
-// 15 LDS entries keep a render work-group within 8192 bytes of LDS, so that
-// five fit a SIMD; deeper entries (a descent past 15 pending entries) go to
-// the private part.
+// 13 LDS entries keep a render work-group (with one sphere) within 7680
+// bytes of LDS: gfx950 hands out a CU's 160 KB of LDS in units of 1280 bytes
+// (measured: 21 work-groups of 7680 bytes are resident on a CU at once, 18
+// of 7696 to 8960 bytes), so 20 work-groups, five waves per SIMD, fit; deeper
+// entries (a descent past 13 pending entries) go to the private part.
 #ifndef PRDPT_STACK_LDS
-#define PRDPT_STACK_LDS 15
+#define PRDPT_STACK_LDS 13
 #endif
+// LDS allocation unit of a work-group on gfx950 (bytes)
+constexpr int kLdsAllocUnit = 1280;
 constexpr int kStackEntries = PRDPT_STACK_LDS;
 constexpr int kStackOverflow = kStackBound - kStackEntries;
 // child reference of an empty slot of a 4-wide node
