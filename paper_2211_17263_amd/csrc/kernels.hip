@@ -486,7 +486,13 @@ __device__ bool continue_trace(const SceneLds& S, const Node* __restrict__ nodes
   };
   const int entered = __popcll(__ballot(1));
   while (true) {
-    // ---- node loop: descend until enough lanes hold a leaf
+    // ---- node loop: descend until enough lanes hold a leaf.  The wave
+    // raises its issue priority here: a node visit's loads depend on the
+    // previous visit's result, so a wave whose node data has arrived issues
+    // ahead of the shading and leaf-phase work of the other waves on the SIMD
+    // and has its next loads in flight sooner (the execution of each wave,
+    // and so every result, is unchanged)
+    __builtin_amdgcn_s_setprio(1);
     while (true) {
       {
         // pop into an empty hand; the LDS read is done by every lane (in
@@ -606,6 +612,7 @@ __device__ bool continue_trace(const SceneLds& S, const Node* __restrict__ nodes
         node = next;
       }
     }
+    __builtin_amdgcn_s_setprio(0);
     // ---- leaf phase: the pending leaves' (lane, triangle) pairs, spread over
     // the active lanes in lane order; each owner keeps the least hit key of its
     // pairs (the same hit as testing them one by one with keep_closer)
