@@ -758,10 +758,11 @@ constexpr float kInvPi = 0.318309886183790671538f;
 // kernels
 // ---------------------------------------------------------------------------
 // Five one-wave work-groups per SIMD (20 per CU): at most 96 VGPRs per lane
-// (512 / 5, in granules of 8) and at most 8192 bytes of LDS per work-group
-// (160 KB / 20), which the render kernels meet with the 15-entry LDS part of
-// the traversal stack and scenes of at most one sphere (more spheres lower
-// the resident count, which the launch reads from the occupancy calculator).
+// (512 / 5, in granules of 8) and at most six 1280-byte LDS allocation units
+// (7680 bytes) per work-group, which the render kernels meet with the
+// 13-entry LDS part of the traversal stack and scenes of at most one sphere
+// (more spheres lower the resident count, which the launch computes from the
+// occupancy calculator and the LDS units).
 // The fifth wave hides more of each wave's dependent-instruction latency: four
 // waves per SIMD (128 VGPRs, 23 LDS stack entries) took 3 % longer on both
 // workloads, although the register allocator now spills a few values outside
