@@ -352,9 +352,12 @@ int prdpt_batch_estimate(prdpt_ctx* ctx, prdpt_request* reqs, int n);
 
 /*
  * Launch configuration of the batched form: persistent work-groups per compute
- * unit, pixel tiles (of the scene's tile size) per work item, and whether to
- * replay a captured
- * graph (1) or launch the kernels directly (0).
+ * unit (0, the default: as many as the compute units hold at once for the
+ * batch's largest sphere count), pixel tiles (of the scene's tile size) per
+ * work item, and whether to replay a captured graph (1) or launch the kernels
+ * directly (0).  The served form takes the context's configuration.
+ * Returns PRDPT_E_ARG for blocks_per_cu outside 0..64 or tiles_per_item
+ * outside 1..4096.
  */
 int prdpt_batch_config(prdpt_ctx* ctx, int blocks_per_cu, int tiles_per_item, int use_graph);
 

@@ -216,13 +216,15 @@ int batch_enqueue(prdpt_ctx* ctx, BatchState& b, prdpt_request* reqs, int n, std
   m.total_items = item_base;
   m.total_rows = row_base;
   m.tiles_per_item = tpi;
-  const int render_blocks = std::max(1, b.n_cu * b.blocks_per_cu);
   int rot = 0;  // the render variant that applies instance rotations
   int max_sph = 0;
   for (int i : ok) {
     rot |= reqs[i].scene->hdr.has_rot;
     max_sph = std::max(max_sph, reqs[i].scene->hdr.n_sph);
   }
+  // blocks_per_cu 0: every work-group the CUs hold at once
+  const int render_blocks = b.blocks_per_cu > 0 ? std::max(1, b.n_cu * b.blocks_per_cu)
+                                                : std::max(1, batch_grid_limit(rot, max_sph));
   // order after earlier work on the context stream (e.g. reference uploads)
   HIP_TRY(hipEventRecord(b.ready, ctx->stream));
   HIP_TRY(hipStreamWaitEvent(b.stream, b.ready, 0));
@@ -378,8 +380,8 @@ int prdpt_batch_estimate(prdpt_ctx* ctx, prdpt_request* reqs, int n) {
 
 int prdpt_batch_config(prdpt_ctx* ctx, int blocks_per_cu, int tiles_per_item, int use_graph) {
   if (!ctx) return fail(PRDPT_E_ARG, "ctx is null");
-  if (blocks_per_cu < 1 || blocks_per_cu > 64 || tiles_per_item < 1 || tiles_per_item > 4096)
-    return fail(PRDPT_E_ARG, "blocks_per_cu in 1..64, tiles_per_item in 1..4096");
+  if (blocks_per_cu < 0 || blocks_per_cu > 64 || tiles_per_item < 1 || tiles_per_item > 4096)
+    return fail(PRDPT_E_ARG, "blocks_per_cu in 0..64, tiles_per_item in 1..4096");
   std::lock_guard<std::mutex> g(ctx->mu);
   BatchState& b = ctx->batch;
   if (b.exec && (b.blocks_per_cu != blocks_per_cu || b.tiles_per_item != tiles_per_item)) {

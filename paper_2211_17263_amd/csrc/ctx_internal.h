@@ -26,6 +26,7 @@ hipError_t launch_render(hipStream_t st, const DevScene& sc, int W, int H, int t
                          const int* order, float* cost, int crn, int rot, int n_sph);
 // resident render work-groups for a variant and sphere count (the grid bound)
 int render_grid_limit(int rot, int n_sph, int tile_log2);
+int batch_grid_limit(int rot, int max_sph);
 // Rz(c) Ry(b) Rx(a) of the angles (a, b, c), row-major (the kernels' own formula)
 void euler_rotation_host(const float* ang, float* R);
 // normal and squared length, unit normal and area of a quad [origin, edge1,
@@ -88,7 +89,7 @@ struct BatchState {
   hipStream_t stream = nullptr;  // own non-blocking stream (capturable)
   hipEvent_t ready = nullptr;    // orders the batch stream after the context stream
   int n_cu = 0;
-  int blocks_per_cu = 16, tiles_per_item = 1, use_graph = 1;
+  int blocks_per_cu = 0, tiles_per_item = 1, use_graph = 1;  // 0: as many as are resident
   size_t cap_req = 0, cap_pairs = 0, cap_rows = 0, cap_partial = 0;
   BatchReq* d_reqs = nullptr;
   BatchMeta* d_meta = nullptr;

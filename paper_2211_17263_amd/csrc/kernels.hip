@@ -2026,6 +2026,25 @@ hipError_t launch_tau(hipStream_t st, int est, int d, int P, uint64_t seed, cons
   return hipGetLastError();
 }
 
+// Work-groups of a kernel resident at once on a CU of device dev with
+// dyn_lds bytes of dynamic LDS: the occupancy calculator's count, capped by
+// the count the hardware's 1280-byte LDS allocation units allow (the
+// calculator assumes a finer allocation; a persistent grid above the resident
+// count leaves work-groups waiting for others to exit).  0 on error.
+static int resident_per_cu(int dev, const void* fn, size_t dyn_lds) {
+  int per_cu = 0, lds_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kBlock, dyn_lds) != hipSuccess)
+    return 0;
+  hipFuncAttributes fa{};
+  if (hipFuncGetAttributes(&fa, fn) == hipSuccess &&
+      hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) ==
+          hipSuccess && lds_cu > 0) {
+    const size_t units = (fa.sharedSizeBytes + dyn_lds + kLdsAllocUnit - 1) / kLdsAllocUnit;
+    per_cu = std::min(per_cu, (int)((size_t)lds_cu / (units * kLdsAllocUnit)));
+  }
+  return std::max(1, per_cu);
+}
+
 // resident work-groups of the render kernel on the current device for the
 // variant and the dynamic LDS of n_sph spheres (cached)
 int render_grid_limit(int rot, int n_sph, int tile_log2) {
@@ -2037,38 +2056,35 @@ int render_grid_limit(int rot, int n_sph, int tile_log2) {
   const int small = tile_log2 == 2 ? 1 : 0;
   int& slot = cached[dev][rot][small][n_sph];
   if (slot > 0) return slot;
-  int n_cu = 0, per_cu = 0;
+  int n_cu = 0;
   if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  const size_t lds = (size_t)sphere_lds_bytes(n_sph);
-  hipError_t e;
-  if (rot) {
-    e = small ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, render_loss_kernel<false, true, 2>,
-                                                             kBlock, lds)
-              : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, render_loss_kernel<false, true, 3>,
-                                                             kBlock, lds);
-  } else {
-    e = small ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, render_loss_kernel<false, false, 2>,
-                                                             kBlock, lds)
-              : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, render_loss_kernel<false, false, 3>,
-                                                             kBlock, lds);
-  }
-  if (e != hipSuccess) return 0;
-  // the occupancy calculator assumes a finer LDS allocation than the
-  // hardware's 1280-byte units; a grid above the resident count would leave
-  // work-groups waiting for others to exit
-  hipFuncAttributes fa{};
-  int lds_cu = 0;
   const void* fn = rot ? (small ? reinterpret_cast<const void*>(render_loss_kernel<false, true, 2>)
                                 : reinterpret_cast<const void*>(render_loss_kernel<false, true, 3>))
                        : (small ? reinterpret_cast<const void*>(render_loss_kernel<false, false, 2>)
                                 : reinterpret_cast<const void*>(render_loss_kernel<false, false, 3>));
-  if (hipFuncGetAttributes(&fa, fn) == hipSuccess &&
-      hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) ==
-          hipSuccess && lds_cu > 0) {
-    const size_t units = (fa.sharedSizeBytes + lds + kLdsAllocUnit - 1) / kLdsAllocUnit;
-    per_cu = std::min(per_cu, (int)((size_t)lds_cu / (units * kLdsAllocUnit)));
-  }
-  slot = std::max(1, n_cu * std::max(1, per_cu));
+  const int per_cu = resident_per_cu(dev, fn, (size_t)sphere_lds_bytes(n_sph));
+  if (per_cu < 1) return 0;
+  slot = n_cu * per_cu;
+  return slot;
+}
+
+// resident work-groups of the batched render kernel on the current device
+// with the dynamic LDS of max_sph spheres (cached)
+int batch_grid_limit(int rot, int max_sph) {
+  static int cached[64][2][PRDPT_MAX_SPHERES + 1];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+  if (max_sph < 0 || max_sph > PRDPT_MAX_SPHERES) return 0;
+  rot = rot ? 1 : 0;
+  int& slot = cached[dev][rot][max_sph];
+  if (slot > 0) return slot;
+  int n_cu = 0;
+  if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  const void* fn = rot ? reinterpret_cast<const void*>(batch_render_kernel<true>)
+                       : reinterpret_cast<const void*>(batch_render_kernel<false>);
+  const int per_cu = resident_per_cu(dev, fn, (size_t)sphere_lds_bytes(max_sph));
+  if (per_cu < 1) return 0;
+  slot = n_cu * per_cu;
   return slot;
 }
 

@@ -51,13 +51,15 @@ def _batch(NV, ctx, jobs, scenes, refs, idx, seeds):
     return reqs
 
 
-@pytest.mark.parametrize("use_graph", [True, False])
-def test_batch_equals_alone_bitwise(setup, use_graph):
+@pytest.mark.parametrize("use_graph,bpc,tpi", [(True, 4, 2), (False, 4, 2), (True, 0, 1)])
+def test_batch_equals_alone_bitwise(setup, use_graph, bpc, tpi):
+    # bpc 0: the default, as many work-groups as the compute units hold at once
     import torch
     from paper_2211_17263_amd import native as NV
     ctx, jobs, scenes, refs = setup
-    say("batch-vs-alone", "graph" if use_graph else "direct", [j["scene"].width for j in jobs])
-    NV.prdpt_batch_config(ctx, 4, 2, use_graph)
+    say("batch-vs-alone", "graph" if use_graph else "direct", bpc, tpi,
+        [j["scene"].width for j in jobs])
+    NV.prdpt_batch_config(ctx, bpc, tpi, use_graph)
     rng = np.random.default_rng(0)
     for rep in range(3):   # graph replays with eager single-request work in between
         idx = list(range(len(jobs))) if rep == 0 else sorted(rng.choice(len(jobs), 6, replace=False))
