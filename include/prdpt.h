@@ -98,7 +98,7 @@ extern "C" {
 
 /* Limits of one scene. */
 #define PRDPT_MAX_PARAMS 256
-#define PRDPT_BATCH_MAX_PARAMS 32 /* d limit of the batched and served forms */
+#define PRDPT_BATCH_MAX_PARAMS PRDPT_MAX_PARAMS /* d limit of the batched and served forms */
 #define PRDPT_MAX_MATERIALS 32
 #define PRDPT_MAX_SPHERES 128
 #define PRDPT_MAX_QUADS 16
@@ -325,8 +325,8 @@ int prdpt_combine_async(prdpt_ctx* ctx, int rows, int d, const double* c_dev,
  * perturbation, run of pixel tiles) items from a device counter, one loss and
  * one combine launch, captured once in a HIP graph and replayed per batch.
  * Every result equals prdpt_grad_estimate of that request alone, bit for bit.
- * A request's scene may have at most PRDPT_BATCH_MAX_PARAMS parameters (larger
- * d: PRDPT_E_ARG for that request; use the single-request calls).
+ * A request's scene may have up to PRDPT_BATCH_MAX_PARAMS (= PRDPT_MAX_PARAMS)
+ * parameters, as for the single-request calls.
  */
 typedef struct {
   prdpt_scene* scene;      /* resident scene of the batch's context */
@@ -409,8 +409,8 @@ typedef struct {
 int prdpt_server_start(prdpt_ctx* ctx, const prdpt_server_config* cfg, prdpt_server** out);
 /* Register a job: the description is validated and its BVHs built now (host);
  * ref_host is host float[H][W][3], copied.  *job_id receives the job's id.
- * A job's scene has at most PRDPT_BATCH_MAX_PARAMS parameters (else
- * PRDPT_E_SCENE). */
+ * A job's scene has up to PRDPT_BATCH_MAX_PARAMS (= PRDPT_MAX_PARAMS)
+ * parameters. */
 int prdpt_server_add_job(prdpt_server* sv, const prdpt_scene_desc* desc, const float* ref_host,
                          int* job_id);
 /* Queue one gradient estimate of job `job_id` (theta, sigma: host float[d], copied). */

@@ -21,6 +21,8 @@ PRDPT_E_SCENE, PRDPT_E_CANCELLED, PRDPT_E_TIMEOUT = -5, -6, -7
 PRDPT_EST_GAUSS, PRDPT_EST_IS, PRDPT_EST_IS_PERDIM = 0, 1, 2
 PRDPT_EST_INDEPENDENT = 0x100   # or-ed into a mode: no antithetic partners (noAT)
 PRDPT_EST_STRATIFIED = 0x200    # or-ed into an independent mode: stratified first uniforms
+PRDPT_MAX_PARAMS = 256
+PRDPT_BATCH_MAX_PARAMS = PRDPT_MAX_PARAMS  # d limit of the batched and served forms
 
 # every symbol declared in include/prdpt.h
 EXPORTS = [
@@ -76,7 +78,7 @@ class ServerConfig(C.Structure):
 
 class Completion(C.Structure):
     _fields_ = [("ticket", C.c_int64), ("job", C.c_int32), ("status", C.c_int32),
-                ("loss", C.c_double), ("grad", C.c_double * 32), ("t_submit", C.c_double),
+                ("loss", C.c_double), ("grad", C.c_double * PRDPT_BATCH_MAX_PARAMS), ("t_submit", C.c_double),
                 ("t_start", C.c_double), ("t_done", C.c_double)]
 
 

@@ -143,16 +143,19 @@ def test_batch_isolates_invalid_requests(setup):
     bad_sigma = NV.BatchRequest(scenes[2], refs[2], jobs[2]["theta0"], np.zeros_like(jobs[2]["sigma"]),
                                 jobs[2]["N"], 5, jobs[2]["est"])
     bad_est = NV.BatchRequest(scenes[3], refs[3], jobs[3]["theta0"], jobs[3]["sigma"], jobs[3]["N"], 5, 9)
-    # more parameters than the batched form takes (d = 150)
+    # a wide request (d = 150, 75 spheres) in the same batch is valid
     srt = S.sort_problem(width=16, height=16, spp=1)
     wide_sc = NV.prdpt_scene_create(ctx, srt["scene"])
-    wide = NV.BatchRequest(wide_sc, refs[0], srt["theta0"], srt["sigma"], 4, 5, 1)
+    wide_ref = NV.prdpt_render_reference(wide_sc, srt["theta_ref"], 1)
+    wide = NV.BatchRequest(wide_sc, wide_ref, srt["theta0"], srt["sigma"], 4, 5, 1)
     NV.prdpt_batch_estimate(ctx, [odd, good, bad_sigma, bad_est, wide])
-    wide_sc.destroy()
     assert [r.status for r in (odd, good, bad_sigma, bad_est, wide)] == [
-        NV.PRDPT_E_ARG, 0, NV.PRDPT_E_ARG, NV.PRDPT_E_ARG, NV.PRDPT_E_ARG]
+        NV.PRDPT_E_ARG, 0, NV.PRDPT_E_ARG, NV.PRDPT_E_ARG, 0]
     a = _alone(NV, scenes[0], refs[0], jobs[0], 5)
     assert np.array_equal(good.grad[: scenes[0].d], a["grad"])
+    w = NV.prdpt_grad_estimate(wide_sc, wide_ref, srt["theta0"], srt["sigma"], 4, 5, 1)
+    assert np.array_equal(wide.grad[:150], w["grad"]) and wide.loss[0] == w["loss"]
+    wide_sc.destroy()
 
 
 def test_batch_against_oracle(setup):

@@ -91,15 +91,6 @@ def test_admission_refusal_and_cancel():
     finally:
         sv.stop()
     assert res[t_refused]["status"] == NV.PRDPT_E_ADMISSION
-    # served jobs take at most PRDPT_BATCH_MAX_PARAMS parameters
-    sv2 = NV.Server(ctx)
-    try:
-        srt = S.sort_problem(width=16, height=16, spp=1)
-        with pytest.raises(NV.PrdptError) as e:
-            sv2.add_job(srt["scene"], np.zeros((16, 16, 3), np.float32))
-        assert e.value.code == NV.PRDPT_E_SCENE
-    finally:
-        sv2.stop()
     assert res[tickets[-1]]["status"] == NV.PRDPT_E_CANCELLED
     assert all(res[t]["status"] == 0 for t in tickets[:-1])
     ctx.close()
@@ -137,3 +128,37 @@ def test_served_results_against_oracle():
         PT.assert_grad_match(c["grad"], o["grad"], w, o["losses"], "served")
         assert abs(c["loss"] - o["loss"]) <= PT.LOSS_REL * abs(o["loss"])
     ctx.close()
+
+
+def test_high_dimensional_job_batched_and_served():
+    # the 150-parameter object-sorting scene (75 spheres: a larger dynamic LDS
+    # and fewer resident work-groups) through the batched and the served
+    # forms: both equal the single-request estimate bit for bit
+    import torch
+    from paper_2211_17263_amd import native as NV
+    pr = S.sort_problem(width=24, height=16, spp=1)
+    d = pr["scene"].d
+    say("serve-150d", d)
+    assert d == 150
+    ctx = NV.Context(0)
+    sc = NV.prdpt_scene_create(ctx, pr["scene"])
+    try:
+        ref = NV.prdpt_render_reference(sc, pr["theta_ref"], 2)
+        a = NV.prdpt_grad_estimate(sc, ref, pr["theta0"], pr["sigma"], 8, 77, pr["est"])
+        torch.cuda.synchronize()
+        q = NV.BatchRequest(sc, ref, pr["theta0"], pr["sigma"], 8, 77, pr["est"])
+        NV.prdpt_batch_estimate(ctx, [q])
+        assert q.status == 0
+        assert np.array_equal(q.grad[:d], a["grad"]) and q.loss[0] == a["loss"]
+        sv = NV.Server(ctx)
+        try:
+            j = sv.add_job(pr["scene"], ref.cpu().numpy())
+            t = sv.submit(j, pr["theta0"], pr["sigma"], 8, 77, pr["est"])
+            c = drain(sv, 1)[t]
+        finally:
+            sv.stop()
+        assert c["status"] == 0
+        assert np.array_equal(c["grad"], a["grad"]) and c["loss"] == a["loss"]
+    finally:
+        sc.destroy()
+        ctx.close()
