@@ -308,9 +308,9 @@ __device__ __forceinline__ float safe_inv(float x) {
 // nodes, and a hit leaf child becomes the lane's pending leaf (or is pushed if
 // one is already pending); lanes holding a leaf keep descending speculatively,
 // into the nearest inner child and into inner nodes popped from the stack
-// (they stop at a leaf on top).  The wave leaves the node loop once every lane holds a leaf or has no work
-// left, or once at least PRDPT_LEAF_QUORUM percent of its active lanes hold
-// one.  The leaf phase then lists the (lane, triangle) pairs of all pending
+// (they stop at a leaf on top).  The wave leaves the node loop once every lane
+// holds a leaf or has no work left, or once at least PRDPT_LEAF_QUORUM percent
+// of its active lanes hold one.  The leaf phase then lists the (lane, triangle) pairs of all pending
 // leaves and deals them out to every active lane, a pair per lane per round:
 // the lane fetches the owner's ray with cross-lane permutes, tests the
 // triangle and folds the hit into the owner's best-hit key in LDS with an
