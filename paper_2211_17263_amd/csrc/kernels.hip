@@ -1959,18 +1959,21 @@ __global__ void dp_combine_kernel(int N, int d, int interior_blocks, int edge_bl
                                   const double* __restrict__ pin, const double* __restrict__ pedge,
                                   double inv_den, const double* __restrict__ losses,
                                   double* __restrict__ grad, double* __restrict__ loss) {
-  const int j = threadIdx.x;
-  if (j < d) {
-    double acc = 0.0;
+  // one wave: lane l sums the block partials l, l + 64, ... of every image
+  // (interior, then edge), then a fixed-order butterfly adds the lanes, so the
+  // result is reproducible; the images' weights are all 2 / den
+  const int l = threadIdx.x;
+  for (int j = 0; j < d; ++j) {
+    double part = 0.0;
     for (int k = 0; k < N; ++k) {
-      double gk = 0.0;
-      for (int b = 0; b < interior_blocks; ++b) gk += pin[((size_t)k * interior_blocks + b) * 3 + j];
-      for (int b = 0; b < edge_blocks; ++b) gk += pedge[((size_t)k * edge_blocks + b) * 3 + j];
-      acc += (2.0 * inv_den) * gk;
+      for (int b = l; b < interior_blocks; b += 64) part += pin[((size_t)k * interior_blocks + b) * 3 + j];
+      for (int b = l; b < edge_blocks; b += 64) part += pedge[((size_t)k * edge_blocks + b) * 3 + j];
     }
-    grad[j] = acc / (double)N;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off, 64);
+    if (l == 0) grad[j] = ((2.0 * inv_den) * part) / (double)N;
   }
-  if (j == 0) {
+  if (l == 0) {
     double s = 0.0;
     for (int k = 0; k < N; ++k) s += losses[k];
     *loss = s / (double)N;
