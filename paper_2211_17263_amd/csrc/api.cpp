@@ -106,7 +106,12 @@ hipError_t timed_render(prdpt_ctx* ctx, const prdpt_scene* s, const float* X, in
     if (e != hipSuccess) return e;
     ctx->pending.emplace_back(a, b);
   }
-  // the next render of this scene takes its costliest tiles first
+  // the next render of this scene takes its costliest tiles first; when every
+  // work item of a launch like this one is resident at once, the order cannot
+  // matter and the sort (a launch of its own) is skipped
+  if ((long long)nk * s->n_tiles <=
+      (long long)render_grid_limit(s->hdr.has_rot, s->hdr.n_sph, s->hdr.tile_log2))
+    return hipSuccess;
   return launch_tile_order(ctx->stream, s->d_tile_cost, s->d_tile_order, s->n_tiles);
 }
 
